@@ -1,0 +1,93 @@
+"""Pins for the oracle's local Schwarz part (Sec. 3: overlapping subdomains,
+R_p on the interior nodes of bar-Omega_p, A_p = R_p A R_p^T, eq. (asm) local
+term), checked by counting, brute force and dense library inverses."""
+import numpy as np
+
+from oracle import fem, schwarz
+from paper_2606_20496_amd import meshgen as mg
+
+
+def test_small_cube_restriction_sizes():
+    # 8 subdomains of 4^3 elements, one layer of overlap, Dirichlet on x = 0:
+    # a subdomain touching x = 0 keeps 4 x 5 x 5 = 100 interior vertices, the
+    # others 5 x 5 x 5 = 125 (counting the vertex planes of the extended block).
+    m = mg.small_cube()
+    sets = schwarz.overlapping_subdomains(m.e2v, m.part, m.n_part, 1)
+    R = schwarz.restriction_sets(m.e2v, sets, m.dirichlet)
+    assert sorted(len(r) for r in R) == [100] * 4 + [125] * 4
+    assert sum(len(r) for r in R) == 900
+    assert all(len(s) == 125 for s in sets)   # 5^3 elements after one layer (clipped)
+
+
+def test_coverage_of_free_vertices():
+    m = mg.box_mesh(10, 3, block=3, boxes=(2, 2, 2))
+    sets = schwarz.overlapping_subdomains(m.e2v, m.part, m.n_part, 1)
+    R = schwarz.restriction_sets(m.e2v, sets, m.dirichlet)
+    cover = np.zeros(m.n_vert, int)
+    for r in R:
+        cover[r] += 1
+    free = ~m.dirichlet.astype(bool)
+    assert cover[free].min() >= 1 and cover[free].max() <= 8
+    assert cover[~free].max() == 0
+
+
+def _brute_force_sets(e2v, part, n_part, layers, dirichlet):
+    # Pure-Python sets, straight from the definitions.
+    E = len(e2v)
+    ev = [set(map(int, row)) for row in e2v]
+    out_R = []
+    for p in range(n_part):
+        S = {e for e in range(E) if part[e] == p}
+        for _ in range(layers):
+            verts = set().union(*(ev[e] for e in S))
+            S = S | {e for e in range(E) if ev[e] & verts}
+        verts = set().union(*(ev[e] for e in S))
+        R = sorted(v for v in verts if not dirichlet[v]
+                   and all(e in S for e in range(E) if v in ev[e]))
+        out_R.append((S, R))
+    return out_R
+
+
+def test_overlap_matches_brute_force():
+    for layers in (1, 2):
+        m = mg.box_mesh((5, 4, 3), 7, block=2, boxes=(2, 2, 2), faces=("y1",))
+        sets = schwarz.overlapping_subdomains(m.e2v, m.part, m.n_part, layers)
+        R = schwarz.restriction_sets(m.e2v, sets, m.dirichlet)
+        bf = _brute_force_sets(m.e2v, m.part, m.n_part, layers, m.dirichlet)
+        for p in range(m.n_part):
+            assert set(sets[p].tolist()) == bf[p][0]
+            assert R[p].tolist() == bf[p][1]
+
+
+def test_single_subdomain_is_exact_inverse():
+    m = mg.box_mesh(5, 4, block=5, boxes=(1, 1, 1))
+    assert m.n_part == 1
+    A, Ae, Afull, free, fidx = fem.stiffness(m.xyz, m.e2v, m.dirichlet)
+    sets = schwarz.overlapping_subdomains(m.e2v, m.part, m.n_part, 1)
+    R = schwarz.restriction_sets(m.e2v, sets, m.dirichlet)
+    loc = schwarz.LocalSolves(A, [fidx[r] for r in R])
+    r = np.random.default_rng(0).standard_normal(A.shape[0])
+    z = loc.apply(r)
+    assert np.abs(z - np.linalg.solve(A.toarray(), r)).max() < 1e-12 * np.abs(z).max()
+
+
+def test_local_part_against_dense_inverses():
+    m = mg.box_mesh(6, 5, block=3, boxes=(2, 2, 2), faces=("z0",))
+    A, Ae, Afull, free, fidx = fem.stiffness(m.xyz, m.e2v, m.dirichlet)
+    sets = schwarz.overlapping_subdomains(m.e2v, m.part, m.n_part, 1)
+    R = [fidx[r] for r in schwarz.restriction_sets(m.e2v, sets, m.dirichlet)]
+    loc = schwarz.LocalSolves(A, R)
+    Ad = A.toarray()
+    n = Ad.shape[0]
+    Mdense = np.zeros((n, n))
+    for Rp in R:
+        Rm = np.zeros((len(Rp), n))
+        Rm[np.arange(len(Rp)), Rp] = 1.0
+        Mdense += Rm.T @ np.linalg.inv(Rm @ Ad @ Rm.T) @ Rm
+    rng = np.random.default_rng(1)
+    for _ in range(3):
+        r = rng.standard_normal(n)
+        assert np.abs(loc.apply(r) - Mdense @ r).max() < 1e-12 * np.abs(Mdense @ r).max()
+    # symmetric positive definite (overlap covers every free vertex)
+    assert np.abs(Mdense - Mdense.T).max() < 1e-12 * np.abs(Mdense).max()
+    assert np.linalg.eigvalsh(Mdense)[0] > 0
