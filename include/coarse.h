@@ -1,0 +1,212 @@
+/*
+ * coarse.h — C-ABI of the MI355X (gfx950) two-level Schwarz coarse solver.
+ *
+ * The library solves the coarse (N = 1, element-vertex) Poisson system
+ * A u = b of Ratnayaka, Fischer & Olson, "Coarse Solvers for Exascale Solution of
+ * Poisson Problems", Sec. 3: A = Q^T A_L Q is the trilinear (Q1) finite-element
+ * stiffness matrix on a globally unstructured hexahedral mesh with homogeneous
+ * Dirichlet and Neumann boundaries. It is preconditioned by the two-level additive
+ * Schwarz method of eq. (asm),
+ *     z = sum_p R_p^T A_p^{-1} R_p r + J A_r^{-1} J^T r,
+ * with exact local solves on overlapping subdomains (Sec. 3) and the non-nested
+ * box-grid reduced space of Sec. 4 (element-centroid cells, J = W Q^T J_L S,
+ * A_r assembled cell by cell as in eq. (Aij)), inside preconditioned conjugate
+ * gradients. All arithmetic runs in the library's HIP kernels on the current
+ * device; no CPU fallback exists.
+ *
+ * Conventions shared by every call
+ *   - Return value: COARSE_OK (0) on success, a negative COARSE_E* code on error
+ *     (the context, if any, is left unchanged and usable), COARSE_NOTCONV (+1) as
+ *     a warning. coarse_last_error() returns a message for the last failing call.
+ *   - Host arrays are read during the call only; the caller keeps ownership.
+ *   - Vector arguments of apply/solve are DEVICE pointers to contiguous float64
+ *     arrays of length n_vert in the caller's vertex numbering. Entries at
+ *     Dirichlet vertices are ignored on input and written as 0 on output. Input
+ *     and output must not alias.
+ *   - All device work is ordered on the context's stream (coarse_opts.stream, or
+ *     coarse_set_stream). A context must not be used from two streams or threads
+ *     at once. No call after coarse_setup allocates device memory.
+ */
+#ifndef COARSE_H
+#define COARSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum coarse_status {
+  COARSE_OK = 0,
+  COARSE_NOTCONV = 1,      /* max_it reached; u holds the last iterate            */
+  COARSE_EINVAL = -1,      /* bad argument (null pointer, index out of range, ...) */
+  COARSE_ENOMEM = -2,      /* device or host allocation failed                     */
+  COARSE_EMESH = -3,       /* element with det(dx/dxi) <= 0 at a Gauss point, or a
+                              vertex repeated within an element                    */
+  COARSE_ESINGULAR = -4,   /* a local A_p or the reduced A_r is not SPD (e.g. an
+                              all-Neumann problem, or an empty interior box, Sec. 4) */
+  COARSE_EDEVICE = -5,     /* HIP runtime error                                    */
+  COARSE_EBREAKDOWN = -6   /* PCG breakdown: p.Ap <= 0 or a non-finite value       */
+};
+
+enum coarse_precision {
+  COARSE_FP64 = 0,   /* everything in float64                                      */
+  COARSE_MIXED = 1   /* local inverses, J/J^T and the reduced solve in float32;
+                        A, the PCG vectors and dot products stay float64 (the
+                        single-precision local/reduced solves of Sec. 6)          */
+};
+
+enum coarse_mode {
+  COARSE_ADDITIVE = 0,     /* eq. (asm)                                            */
+  COARSE_HYBRID_SYM = 1,   /* symmetrised hybrid of eqs. (asm1)-(asm2):
+                              z0 = M_r r, z1 = z0 + M_loc (r - A z0),
+                              z = z1 + M_r (r - A z1)                              */
+  COARSE_LOCAL_ONLY = 2,   /* eq. (asm1) alone (ablation)                          */
+  COARSE_REDUCED_ONLY = 3  /* J A_r^{-1} J^T alone (ablation)                      */
+};
+
+enum coarse_interp {
+  COARSE_J_CENTROID = 0,   /* element-centroid cells + W averaging, cell-assembled
+                              A_r (Sec. 4, compact 3^d stencil)                    */
+  COARSE_J_STANDARD = 1    /* J_ij = Phi_j(x_i) with the box bounding x_i and
+                              A_r = J^T A J (Sec. 4, eq. (Psi); 5^d stencil)        */
+};
+
+typedef struct coarse_ctx coarse_ctx;   /* opaque; owns all device state */
+
+/* Mesh (Sec. 3): n_elem hexahedra; e2v[8*e + v] is local vertex v = i + 2j + 4k,
+ * (i,j,k) in {0,1}^3 lexicographic, of element e (ids in [0, n_vert)); xyz[3*u+d]
+ * is coordinate d of vertex u. part[e] in [0, n_part) is the subdomain Omega_p of
+ * element e (contiguous element clusters, Sec. 3); part == NULL asks the library
+ * to cut the mesh by recursive coordinate bisection of the element centroids
+ * into n_part pieces (n_part >= 1). */
+typedef struct {
+  int64_t n_vert;
+  int64_t n_elem;
+  const double *xyz;      /* host [n_vert][3]  */
+  const int32_t *e2v;     /* host [n_elem][8]  */
+  const int32_t *part;    /* host [n_elem] or NULL */
+  int32_t n_part;
+} coarse_mesh;
+
+/* Boundary (Sec. 3): dirichlet[u] != 0 marks a homogeneous Dirichlet vertex;
+ * every other boundary vertex is homogeneous Neumann. At least one Dirichlet
+ * vertex is needed for A to be SPD. */
+typedef struct {
+  const uint8_t *dirichlet;   /* host [n_vert] */
+} coarse_bc;
+
+typedef struct {
+  int overlap;      /* element layers added to each subdomain (Sec. 3), >= 1        */
+  int boxes[3];     /* b_x, b_y, b_z boxes of the reduced grid (Sec. 4); a zero
+                       entry means ceil(n_part^(1/3))                               */
+  int precision;    /* enum coarse_precision                                       */
+  int mode;         /* enum coarse_mode                                            */
+  int interp;       /* enum coarse_interp                                          */
+  int max_it;       /* PCG iteration cap                                           */
+  int check_every;  /* PCG iterations queued between host convergence checks; the
+                       result does not depend on it (finished iterations are
+                       skipped on the device)                                      */
+  int flexible;     /* 1: Polak-Ribiere beta (r, z_new - z_old)/(r,z)_old;
+                       0: Fletcher-Reeves. Default 1 for COARSE_MIXED, else 0     */
+  void *stream;     /* hipStream_t; NULL = the null stream                         */
+} coarse_opts;
+
+typedef struct {
+  int iters;            /* products with A inside the PCG loop                     */
+  int status;           /* COARSE_OK, COARSE_NOTCONV or COARSE_EBREAKDOWN          */
+  double relres;        /* ||r_k||_2 / ||b||_2 from the recurrence (free entries)   */
+  double relres_true;   /* ||b - A u||_2 / ||b||_2 recomputed at the end            */
+  double t_setup;       /* seconds spent in coarse_setup                            */
+  double t_solve;       /* seconds spent in this solve (host clock, stream synced)  */
+} coarse_stats;
+
+typedef struct {
+  int64_t n_free;        /* unknowns (non-Dirichlet vertices)                       */
+  int64_t n_sub;         /* subdomains with a non-empty R_p                         */
+  int64_t sum_np;        /* sum_p |R_p|                                             */
+  int64_t max_np;        /* max_p |R_p|                                             */
+  int64_t n_r;           /* reduced unknowns after compression (Sec. 4)             */
+  int64_t n_cells;       /* boxes that own at least one element centroid            */
+  int64_t local_bytes;   /* bytes of the stored local inverses                      */
+  int64_t reduced_bytes; /* bytes of the stored reduced inverse                     */
+  int64_t a_bytes;       /* bytes streamed by one application of A                  */
+  int64_t inv_alg_bytes; /* sum over local and reduced systems of n(n+1)/2 stored
+                            entries times the element size: the packed symmetric
+                            inverses one preconditioner application must read     */
+  int64_t device_bytes;  /* all device memory held by the context                   */
+  int32_t boxes[3];
+  int32_t precision;
+} coarse_info_t;
+
+/* Fill *o with the defaults: overlap 1, boxes auto, FP64, additive, centroid J,
+ * max_it 1000, check_every 4, flexible 0, null stream. */
+void coarse_default_opts(coarse_opts *o);
+
+/* Build everything a solve needs (Secs. 3-4): locality ordering, overlapping
+ * subdomains and R_p, element matrices, the local inverses A_p^{-1} (batched
+ * dense block-sweep on the device), the box grid, J and the reduced inverse
+ * A_r^{-1}. Allocates all device memory of the context. On success *out owns it.
+ * Errors: EINVAL, ENOMEM, EMESH, ESINGULAR, EDEVICE. */
+int coarse_setup(const coarse_mesh *mesh, const coarse_bc *bc, const coarse_opts *opts,
+                 coarse_ctx **out);
+
+/* z = M^{-1} r: one application of the preconditioner selected by opts.mode
+ * (eq. (asm) by default). r, z: device float64 [n_vert]. Errors: EINVAL. */
+int coarse_apply_precond(coarse_ctx *ctx, const double *r, double *z);
+
+/* q = A p, the Q1 operator of Sec. 3 (free rows/columns). Device float64 [n_vert]. */
+int coarse_apply_A(coarse_ctx *ctx, const double *p, double *q);
+
+/* Solve A u = b by PCG from u0 = 0 until ||r||_2 <= tol ||b||_2 (free entries).
+ * b, u: device float64 [n_vert]. st may be NULL. Returns COARSE_OK, COARSE_NOTCONV
+ * (warning) or COARSE_EBREAKDOWN / COARSE_EINVAL. b = 0 gives u = 0, iters = 0. */
+int coarse_solve(coarse_ctx *ctx, const double *b, double *u, double tol, coarse_stats *st);
+
+/* Solve `count` independent systems (any mix of contexts, each with its own right-
+ * hand side) in lock step: every PCG phase of all live systems is issued before
+ * the next phase, and the local solves of all of them go into one launch.
+ * Contexts must be distinct and share one stream (that of ctxs[0]). Each result
+ * equals what coarse_solve gives for that system alone (bitwise). */
+int coarse_solve_batch(coarse_ctx *const *ctxs, const double *const *b, double *const *u,
+                       int count, double tol, coarse_stats *st);
+
+/* Release all memory of the context. NULL is accepted. */
+int coarse_destroy(coarse_ctx *ctx);
+
+/* Device bytes held by the context (for admission by HBM budget). */
+size_t coarse_device_bytes(const coarse_ctx *ctx);
+
+/* Sizes of the built context. */
+int coarse_get_info(const coarse_ctx *ctx, coarse_info_t *info);
+
+/* Change the stream used by later calls on this context. */
+int coarse_set_stream(coarse_ctx *ctx, void *stream);
+
+/* Phase timers (HIP events on the context's stream around every launch of a
+ * phase). enable = 1 clears the accumulators and starts timing; enable = 0 waits
+ * for the stream, stops, and writes the accumulated milliseconds and launch
+ * counts of the first nphase phases into ms[] and counts[] (either may be NULL).
+ * Phases: 0 operator A (both passes), 1 restriction R_p gather, 2 reduced
+ * restriction J^T, 3 batched dense solves A_p^{-1} and A_r^{-1} (the tiled GEMV
+ * kernel alone), 4 partial-sum combine, 5 overlap sum + J prolongation,
+ * 6 PCG vector updates and scalar steps. */
+#define COARSE_NPHASE 7
+int coarse_profile(coarse_ctx *ctx, int enable, double *ms, int64_t *counts, int nphase);
+
+/* Host-only dry run of the combinatorial setup (no device is touched): fills
+ * *info with n_free, n_sub, sum_np, max_np, n_r, n_cells and boxes; if sizes is
+ * not NULL, sizes[p] receives |R_p| for p < n_part. Errors: EINVAL, EMESH. */
+int coarse_plan_info(const coarse_mesh *mesh, const coarse_bc *bc, const coarse_opts *opts,
+                     coarse_info_t *info, int64_t *sizes);
+
+/* Message for a status code; last failure message of a context (or of the last
+ * failed coarse_setup when ctx is NULL). */
+const char *coarse_strerror(int code);
+const char *coarse_last_error(const coarse_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COARSE_H */

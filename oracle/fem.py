@@ -42,12 +42,12 @@ def element_matrices(xyz, e2v):
     detmin = np.full(E, np.inf)
     for q in GAUSS_POINTS:
         gN = ref_gradients(q)                                   # (8, 3)
-        Jac = np.einsum("evi,vj->eij", X, gN)                   # J_ij = dx_i/dxi_j
+        Jac = np.matmul(X.transpose(0, 2, 1), gN)              # J_ij = dx_i/dxi_j
         det = np.linalg.det(Jac)
         detmin = np.minimum(detmin, det)
         inv = np.linalg.inv(Jac)                                # (E, 3, 3)
-        G = np.einsum("vj,eji->evi", gN, inv)                   # physical gradients
-        A += det[:, None, None] * np.einsum("evi,ewi->evw", G, G)
+        G = np.matmul(gN[None, :, :], inv)                      # physical gradients (E, 8, 3)
+        A += det[:, None, None] * np.matmul(G, G.transpose(0, 2, 1))
     return A, detmin
 
 

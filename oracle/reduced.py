@@ -118,7 +118,7 @@ class CentroidSpace:
         self.n_r = self.active.size
         self.J = Jfull[:, self.active].tocsr()
         # A_r by cell assembly, eq. (Aij): sum_e (J^e)^T A^e J^e at the cell corners
-        Acell = np.einsum("eak,eab,ebl->ekl", Je, Ae, Je)
+        Acell = np.matmul(np.matmul(Je.transpose(0, 2, 1), Ae), Je)   # (J^e)^T A^e J^e
         r_ = np.repeat(corners, 8, axis=1).reshape(-1)
         c_ = np.tile(corners, (1, 8)).reshape(-1)
         Arfull = sp.coo_matrix((Acell.reshape(-1), (r_, c_)), shape=(nbv, nbv)).tocsr()

@@ -1,0 +1,290 @@
+"""Python binding of ``libcoarse.so`` (the C-ABI in include/coarse.h).
+
+Argument marshalling only: every step of setup, preconditioning and PCG runs in
+the library's HIP kernels. torch provides device memory and the current stream.
+There is no CPU fallback: without the built library, or without a GPU, the
+calls that compute raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcoarse.so")
+
+PRECISION = {"fp64": 0, "mixed": 1}
+MODE = {"additive": 0, "hybrid_sym": 1, "local_only": 2, "reduced_only": 3}
+INTERP = {"centroid": 0, "standard": 1}
+STATUS = {0: "ok", 1: "notconv", -1: "einval", -2: "enomem", -3: "emesh", -4: "esingular",
+          -5: "edevice", -6: "ebreakdown"}
+
+# every symbol declared in include/coarse.h
+EXPORTS = ("coarse_default_opts", "coarse_setup", "coarse_apply_precond", "coarse_apply_A",
+           "coarse_solve", "coarse_solve_batch", "coarse_destroy", "coarse_device_bytes",
+           "coarse_get_info", "coarse_set_stream", "coarse_plan_info", "coarse_strerror",
+           "coarse_last_error", "coarse_profile")
+
+PHASES = ("A", "R_p", "J^T", "A_p^-1/A_r^-1 gemv", "combine", "sum+J", "pcg_vec")
+
+
+class CoarseError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Mesh(ctypes.Structure):
+    _fields_ = [("n_vert", ctypes.c_int64), ("n_elem", ctypes.c_int64),
+                ("xyz", ctypes.POINTER(ctypes.c_double)), ("e2v", ctypes.POINTER(ctypes.c_int32)),
+                ("part", ctypes.POINTER(ctypes.c_int32)), ("n_part", ctypes.c_int32)]
+
+
+class _BC(ctypes.Structure):
+    _fields_ = [("dirichlet", ctypes.POINTER(ctypes.c_uint8))]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("overlap", ctypes.c_int), ("boxes", ctypes.c_int * 3), ("precision", ctypes.c_int),
+                ("mode", ctypes.c_int), ("interp", ctypes.c_int), ("max_it", ctypes.c_int),
+                ("check_every", ctypes.c_int), ("flexible", ctypes.c_int), ("stream", ctypes.c_void_p)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("relres", ctypes.c_double),
+                ("relres_true", ctypes.c_double), ("t_setup", ctypes.c_double), ("t_solve", ctypes.c_double)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n_free", ctypes.c_int64), ("n_sub", ctypes.c_int64), ("sum_np", ctypes.c_int64),
+                ("max_np", ctypes.c_int64), ("n_r", ctypes.c_int64), ("n_cells", ctypes.c_int64),
+                ("local_bytes", ctypes.c_int64), ("reduced_bytes", ctypes.c_int64),
+                ("a_bytes", ctypes.c_int64), ("inv_alg_bytes", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64),
+                ("boxes", ctypes.c_int32 * 3), ("precision", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Load the shared library (after torch, so both use one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2606_20496_amd.build.build()")
+    try:
+        import torch  # noqa: F401  (loads the HIP runtime first)
+    except Exception:
+        pass
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    L.coarse_default_opts.argtypes = [ctypes.POINTER(_Opts)]
+    L.coarse_default_opts.restype = None
+    L.coarse_setup.argtypes = [ctypes.POINTER(_Mesh), ctypes.POINTER(_BC), ctypes.POINTER(_Opts),
+                               ctypes.POINTER(vp)]
+    L.coarse_setup.restype = i32
+    L.coarse_apply_precond.argtypes = [vp, vp, vp]
+    L.coarse_apply_precond.restype = i32
+    L.coarse_apply_A.argtypes = [vp, vp, vp]
+    L.coarse_apply_A.restype = i32
+    L.coarse_solve.argtypes = [vp, vp, vp, dbl, ctypes.POINTER(_Stats)]
+    L.coarse_solve.restype = i32
+    L.coarse_solve_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i32, dbl,
+                                     ctypes.POINTER(_Stats)]
+    L.coarse_solve_batch.restype = i32
+    L.coarse_destroy.argtypes = [vp]
+    L.coarse_destroy.restype = i32
+    L.coarse_device_bytes.argtypes = [vp]
+    L.coarse_device_bytes.restype = ctypes.c_size_t
+    L.coarse_get_info.argtypes = [vp, ctypes.POINTER(_Info)]
+    L.coarse_get_info.restype = i32
+    L.coarse_set_stream.argtypes = [vp, vp]
+    L.coarse_set_stream.restype = i32
+    L.coarse_plan_info.argtypes = [ctypes.POINTER(_Mesh), ctypes.POINTER(_BC), ctypes.POINTER(_Opts),
+                                   ctypes.POINTER(_Info), ctypes.POINTER(i64)]
+    L.coarse_plan_info.restype = i32
+    L.coarse_strerror.argtypes = [i32]
+    L.coarse_strerror.restype = ctypes.c_char_p
+    L.coarse_profile.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), i32]
+    L.coarse_profile.restype = i32
+    L.coarse_last_error.argtypes = [vp]
+    L.coarse_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _arrays(xyz, e2v, dirichlet, part, n_part):
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    e2v = np.ascontiguousarray(e2v, dtype=np.int32)
+    dirichlet = np.ascontiguousarray(dirichlet, dtype=np.uint8)
+    if part is not None:
+        part = np.ascontiguousarray(part, dtype=np.int32)
+    m = _Mesh(xyz.shape[0], e2v.shape[0], xyz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+              e2v.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+              part.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if part is not None else None, int(n_part))
+    bc = _BC(dirichlet.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    return m, bc, (xyz, e2v, dirichlet, part)
+
+
+def _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible, stream):
+    o = _Opts()
+    load().coarse_default_opts(ctypes.byref(o))
+    o.overlap = int(overlap)
+    for d in range(3):
+        o.boxes[d] = int(boxes[d]) if boxes is not None else 0
+    o.precision = PRECISION[precision]
+    o.mode = MODE[mode]
+    o.interp = INTERP[interp]
+    o.max_it = int(max_it)
+    o.check_every = int(check_every)
+    if flexible is None:
+        flexible = precision == "mixed"
+    o.flexible = int(bool(flexible))
+    o.stream = stream
+    return o
+
+
+def _info_dict(info):
+    d = {f: getattr(info, f) for f, _ in _Info._fields_ if f != "boxes"}
+    d["boxes"] = tuple(info.boxes)
+    return d
+
+
+def plan_info(xyz, e2v, dirichlet, part=None, n_part=1, *, overlap=1, boxes=None, interp="centroid"):
+    """Host-only dry run of the setup: sizes and |R_p| per subdomain (no GPU)."""
+    L = load()
+    m, bc, keep = _arrays(xyz, e2v, dirichlet, part, n_part)
+    o = _opts(overlap, boxes, "fp64", "additive", interp, 1000, 4, False, None)
+    info = _Info()
+    sizes = np.zeros(max(1, int(n_part)), dtype=np.int64)
+    rc = L.coarse_plan_info(ctypes.byref(m), ctypes.byref(bc), ctypes.byref(o), ctypes.byref(info),
+                            sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    if rc != 0:
+        raise CoarseError(rc, L.coarse_last_error(None).decode())
+    return _info_dict(info), sizes
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class CoarseSolver:
+    """One mesh's two-level Schwarz PCG solver on the current GPU.
+
+    Vectors are float64 CUDA (HIP) tensors of length ``n_vert`` in the caller's
+    vertex numbering; Dirichlet entries are ignored on input and zero on output.
+    """
+
+    def __init__(self, xyz, e2v, dirichlet, part=None, n_part=1, *, overlap=1, boxes=None,
+                 precision="fp64", mode="additive", interp="centroid", max_it=1000, check_every=4,
+                 flexible=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("CoarseSolver needs a GPU; no CPU fallback exists")
+        L = load()
+        self._L = L
+        self.n_vert = int(np.asarray(xyz).shape[0])
+        self.precision = precision
+        m, bc, keep = _arrays(xyz, e2v, dirichlet, part, n_part)
+        o = _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible, _stream())
+        ctx = ctypes.c_void_p()
+        rc = L.coarse_setup(ctypes.byref(m), ctypes.byref(bc), ctypes.byref(o), ctypes.byref(ctx))
+        if rc != 0:
+            raise CoarseError(rc, L.coarse_last_error(None).decode())
+        self._ctx = ctx
+        info = _Info()
+        L.coarse_get_info(ctx, ctypes.byref(info))
+        self.info = _info_dict(info)
+
+    @classmethod
+    def from_mesh(cls, mesh, **kw):
+        kw.setdefault("boxes", mesh.boxes)
+        return cls(mesh.xyz, mesh.e2v, mesh.dirichlet, mesh.part, mesh.n_part, **kw)
+
+    def _check(self, rc):
+        if rc < 0:
+            raise CoarseError(rc, self._L.coarse_last_error(self._ctx).decode())
+        return rc
+
+    def _vec(self, v):
+        import torch
+        if not (isinstance(v, torch.Tensor) and v.is_cuda and v.dtype == torch.float64 and v.is_contiguous()
+                and v.numel() == self.n_vert):
+            raise ValueError("expected a contiguous float64 GPU tensor of length n_vert")
+        return ctypes.c_void_p(v.data_ptr())
+
+    def _sync_stream(self):
+        self._L.coarse_set_stream(self._ctx, _stream())
+
+    def apply_precond(self, r, out=None):
+        import torch
+        self._sync_stream()
+        out = torch.empty_like(r) if out is None else out
+        self._check(self._L.coarse_apply_precond(self._ctx, self._vec(r), self._vec(out)))
+        return out
+
+    def apply_A(self, p, out=None):
+        import torch
+        self._sync_stream()
+        out = torch.empty_like(p) if out is None else out
+        self._check(self._L.coarse_apply_A(self._ctx, self._vec(p), self._vec(out)))
+        return out
+
+    def solve(self, b, tol=1e-8, out=None):
+        import torch
+        self._sync_stream()
+        out = torch.empty_like(b) if out is None else out
+        st = _Stats()
+        rc = self._check(self._L.coarse_solve(self._ctx, self._vec(b), self._vec(out), float(tol),
+                                              ctypes.byref(st)))
+        stats = {f: getattr(st, f) for f, _ in _Stats._fields_}
+        stats["code"] = rc
+        return out, stats
+
+    def profile_start(self):
+        self._L.coarse_profile(self._ctx, 1, None, None, 0)
+
+    def profile_stop(self):
+        """Stop the phase timers; returns {phase: (total_ms, launches)}."""
+        ms = (ctypes.c_double * len(PHASES))()
+        cnt = (ctypes.c_int64 * len(PHASES))()
+        self._check(self._L.coarse_profile(self._ctx, 0, ms, cnt, len(PHASES)))
+        return {ph: (ms[i], cnt[i]) for i, ph in enumerate(PHASES)}
+
+    @property
+    def device_bytes(self):
+        return int(self._L.coarse_device_bytes(self._ctx))
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._L.coarse_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_batch(solvers, bs, tol=1e-8, outs=None):
+    """Solve several systems in lock step (one stream, shared local-solve launch)."""
+    import torch
+    L = load()
+    n = len(solvers)
+    outs = [torch.empty_like(b) for b in bs] if outs is None else outs
+    for s in solvers:
+        s._sync_stream()
+    ctxs = (ctypes.c_void_p * n)(*[s._ctx.value for s in solvers])
+    bp = (ctypes.c_void_p * n)(*[s._vec(b).value for s, b in zip(solvers, bs)])
+    up = (ctypes.c_void_p * n)(*[s._vec(u).value for s, u in zip(solvers, outs)])
+    st = (_Stats * n)()
+    rc = L.coarse_solve_batch(ctxs, bp, up, n, float(tol), st)
+    if rc < 0:
+        raise CoarseError(rc, "batch solve failed")
+    return outs, [{f: getattr(s, f) for f, _ in _Stats._fields_} for s in st]

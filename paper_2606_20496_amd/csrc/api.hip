@@ -1,0 +1,845 @@
+// C-ABI of the coarse solver: context setup, preconditioner application and
+// PCG, orchestrating the kernels of kernels.hip on one HIP stream.
+#include "kernels.hip"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstddef>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/coarse.h"
+
+using namespace coarse;
+
+namespace {
+
+std::string g_setup_error;
+
+struct Fail : std::runtime_error {
+  int code;
+  Fail(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(expr)                                                                                   \
+  do {                                                                                                 \
+    hipError_t e_ = (expr);                                                                            \
+    if (e_ != hipSuccess)                                                                              \
+      throw Fail(e_ == hipErrorOutOfMemory ? COARSE_ENOMEM : COARSE_EDEVICE,                           \
+                 std::string(#expr) + ": " + hipGetErrorString(e_));                                   \
+  } while (0)
+
+double now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Arena {
+  std::vector<void *> ptrs;
+  size_t bytes = 0;
+  template <typename T>
+  T *alloc(size_t n) {
+    if (n == 0) n = 1;
+    void *p = nullptr;
+    HIPCHK(hipMalloc(&p, n * sizeof(T)));
+    ptrs.push_back(p);
+    bytes += n * sizeof(T);
+    return (T *)p;
+  }
+  template <typename T>
+  T *upload(const std::vector<T> &v, hipStream_t s) {
+    T *p = alloc<T>(v.size());
+    if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return p;
+  }
+  void release() {
+    for (void *p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+    bytes = 0;
+  }
+  ~Arena() { release(); }
+};
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)std::max<int64_t>(1, (n + b - 1) / b); }
+
+}  // namespace
+
+struct coarse_ctx {
+  std::string err;
+  hipStream_t stream = nullptr;
+  int precision = 0, mode = 0, interp = 0, max_it = 1000, check_every = 4, flexible = 0;
+  int64_t nv = 0, ne = 0, nf = 0, n_r = 0, nent = 0, ntask = 0;
+  int64_t n_local_sys = 0, vec_len = 0, coarse_vec_off = 0;
+  int32_t items_local = 0, items_total = 0, rows_local = 0, rows_total = 0;
+  int nvblk = 1;
+  double t_setup = 0.0;
+  coarse_info_t info{};
+  Arena arena;
+
+  OpDev op{};
+  int32_t *user_of_vint = nullptr, *vint_of_user = nullptr;
+  double *x = nullptr, *r = nullptr, *p = nullptr, *z = nullptr, *q = nullptr, *bint = nullptr, *t1 = nullptr,
+         *t2 = nullptr, *part1 = nullptr, *part2 = nullptr, *energy = nullptr;
+  Scalars *sc = nullptr;
+  Scalars *h_sc = nullptr;   // pinned host copy
+  int *zero_flag = nullptr;  // a device int that is always 0
+  int *done_flag = nullptr;  // &sc->done
+
+  // batched dense solves
+  int32_t *sub_idx = nullptr;
+  void *rp = nullptr, *tiles = nullptr, *rowpart = nullptr, *colpart = nullptr;
+  double *zp = nullptr;
+  GItem *items = nullptr;
+  GRow *rows = nullptr;
+  SysDev *sysdev = nullptr;
+  Seg *seg_all = nullptr, *seg_local = nullptr, *seg_coarse = nullptr;
+  Seg h_seg_all{}, h_seg_local{}, h_seg_coarse{};
+  int32_t *cover_ptr = nullptr, *cover_pos = nullptr;
+
+  // reduced space
+  int32_t *jv_ptr = nullptr, *jv_occ = nullptr, *jc_vid = nullptr, *jt_start = nullptr, *jr_ptr = nullptr,
+          *jr_src = nullptr, *corner_act = nullptr;
+  void *jv_w = nullptr, *jv_xi = nullptr, *jc_w = nullptr, *jc_xi = nullptr, *jt_part = nullptr;
+
+  // phase timers
+  static constexpr int NPH = 7;
+  bool prof_on = false;
+  double prof_ms[NPH] = {};
+  int64_t prof_cnt[NPH] = {};
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+  hipEvent_t ev_open[NPH] = {};
+
+  ~coarse_ctx() {
+    if (h_sc) (void)hipHostFree(h_sc);
+    for (auto &p : ev_pending) {
+      ev_pool.push_back(p.second.first);
+      ev_pool.push_back(p.second.second);
+    }
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  }
+
+  hipEvent_t get_event() {
+    if (ev_pool.empty()) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      return e;
+    }
+    hipEvent_t e = ev_pool.back();
+    ev_pool.pop_back();
+    return e;
+  }
+  void pbeg(int ph) {
+    if (!prof_on) return;
+    ev_open[ph] = get_event();
+    HIPCHK(hipEventRecord(ev_open[ph], stream));
+  }
+  void pend(int ph) {
+    if (!prof_on) return;
+    hipEvent_t e = get_event();
+    HIPCHK(hipEventRecord(e, stream));
+    ev_pending.push_back({ph, {ev_open[ph], e}});
+  }
+  // after the stream has been synchronised: fold finished event pairs in
+  void pcollect() {
+    for (auto &p : ev_pending) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, p.second.first, p.second.second));
+      prof_ms[p.first] += ms;
+      prof_cnt[p.first] += 1;
+      ev_pool.push_back(p.second.first);
+      ev_pool.push_back(p.second.second);
+    }
+    ev_pending.clear();
+  }
+
+  // ---- kernels on this context's stream ---------------------------------------
+  void apply_op(const double *in, double *out, double *en, const int *done) {
+    pbeg(0);
+    hipLaunchKernelGGL(k_op_pass1, dim3((unsigned)op.n_blocks), dim3(OP_BLOCK), op.lds_bytes, stream, op, in, out, en,
+                       done);
+    if (op.n_shared > 0)
+      hipLaunchKernelGGL(k_op_pass2, dim3(nblk(op.n_shared, 256)), dim3(256), 0, stream, op, out, done);
+    pend(0);
+  }
+
+  template <typename T>
+  void restrict_coarse(const double *in, const int *done) {
+    pbeg(2);
+    hipLaunchKernelGGL(k_jt_tasks<T>, dim3(nblk(ntask, 4)), dim3(256), 0, stream, (int)ntask, done, jt_start, jc_vid,
+                       (const T *)jc_w, (const T *)jc_xi, nent, in, (T *)jt_part);
+    hipLaunchKernelGGL(k_jt_corners<T>, dim3(nblk(n_r, 256)), dim3(256), 0, stream, n_r, done, jr_ptr, jr_src,
+                       (const T *)jt_part, (T *)rp + coarse_vec_off);
+    pend(2);
+  }
+
+  void gemv_combine(const Seg *segs, int nitems, int nrows, const int *done) {
+    if (nitems <= 0) return;
+    const unsigned g = (unsigned)std::min<int64_t>(nblk(nitems, 4), 256 * 16);
+    pbeg(3);
+    if (precision == COARSE_FP64)
+      hipLaunchKernelGGL(k_gemv_f64, dim3(g), dim3(256), 0, stream, segs, 1, nitems, done);
+    else
+      hipLaunchKernelGGL(k_gemv_f32, dim3(g), dim3(256), 0, stream, segs, 1, nitems, done);
+    pend(3);
+    pbeg(4);
+    if (precision == COARSE_FP64)
+      hipLaunchKernelGGL(k_combine<double>, dim3(nblk((int64_t)nrows * TILE, 256)), dim3(256), 0, stream, segs, 1,
+                         nrows, done);
+    else
+      hipLaunchKernelGGL(k_combine<float>, dim3(nblk((int64_t)nrows * TILE, 256)), dim3(256), 0, stream, segs, 1,
+                         nrows, done);
+    pend(4);
+  }
+
+  template <typename T>
+  void final_step(const double *add, bool local, bool coarse, double *out, const double *rdot, double *p1, double *p2,
+                  const int *done) {
+    pbeg(5);
+    hipLaunchKernelGGL(k_final<T>, dim3(nvblk), dim3(VB), 0, stream, nf, done, add, local ? cover_ptr : nullptr,
+                       cover_pos, zp, coarse ? jv_ptr : nullptr, jv_occ, (const T *)jv_w, (const T *)jv_xi, nent,
+                       corner_act, zp + coarse_vec_off, out, rdot, p1, p2);
+    pend(5);
+  }
+
+  template <typename T>
+  void precond_parts(const double *in, const double *add, bool local, bool coarse, double *out, const double *rdot,
+                     double *p1, double *p2, const int *done) {
+    if (local) {
+      pbeg(1);
+      hipLaunchKernelGGL(k_gather<T>, dim3(nblk(coarse_vec_off, VB)), dim3(VB), 0, stream, coarse_vec_off, done,
+                         sub_idx, in, (T *)rp);
+      pend(1);
+    }
+    if (coarse) restrict_coarse<T>(in, done);
+    if (local && coarse)
+      gemv_combine(seg_all, items_total, rows_total, done);
+    else if (local)
+      gemv_combine(seg_local, items_local, rows_local, done);
+    else
+      gemv_combine(seg_coarse, items_total - items_local, rows_total - rows_local, done);
+    final_step<T>(add, local, coarse, out, rdot, p1, p2, done);
+  }
+
+  template <typename T>
+  void precond_t(const double *in, double *out, const double *rdot, double *p1, double *p2, const int *done) {
+    switch (mode) {
+      case COARSE_ADDITIVE:
+        precond_parts<T>(in, nullptr, true, true, out, rdot, p1, p2, done);
+        break;
+      case COARSE_LOCAL_ONLY:
+        precond_parts<T>(in, nullptr, true, false, out, rdot, p1, p2, done);
+        break;
+      case COARSE_REDUCED_ONLY:
+        precond_parts<T>(in, nullptr, false, true, out, rdot, p1, p2, done);
+        break;
+      case COARSE_HYBRID_SYM:
+        // z0 = M_r r; z1 = z0 + M_loc (r - A z0); z = z1 + M_r (r - A z1)
+        precond_parts<T>(in, nullptr, false, true, t1, nullptr, nullptr, nullptr, done);
+        apply_op(t1, q, nullptr, done);
+        hipLaunchKernelGGL(k_sub, dim3(nvblk), dim3(VB), 0, stream, nf, done, in, q, t2);
+        precond_parts<T>(t2, t1, true, false, t1, nullptr, nullptr, nullptr, done);
+        apply_op(t1, q, nullptr, done);
+        hipLaunchKernelGGL(k_sub, dim3(nvblk), dim3(VB), 0, stream, nf, done, in, q, t2);
+        precond_parts<T>(t2, t1, false, true, out, rdot, p1, p2, done);
+        break;
+    }
+  }
+
+  void precond(const double *in, double *out, const double *rdot, double *p1, double *p2, const int *done) {
+    if (precision == COARSE_FP64)
+      precond_t<double>(in, out, rdot, p1, p2, done);
+    else
+      precond_t<float>(in, out, rdot, p1, p2, done);
+  }
+
+  void scalar(int opk, const double *part, int n, const double *part2_, double tol2 = 0.0) {
+    hipLaunchKernelGGL(k_scalar, dim3(1), dim3(VB), 0, stream, opk, sc, part, n, part2_, tol2, max_it, flexible);
+  }
+
+  // one PCG iteration, skipped on the device once the solve has finished
+  void iteration() {
+    apply_op(p, q, energy, done_flag);
+    pbeg(6);
+    scalar(SC_ALPHA, energy, (int)op.n_blocks, nullptr);
+    hipLaunchKernelGGL(k_update, dim3(nvblk), dim3(VB), 0, stream, nf, sc, x, r, p, q, part1);
+    scalar(SC_CHECK, part1, nvblk, nullptr);
+    pend(6);
+    precond(r, z, r, part1, flexible ? part2 : nullptr, done_flag);
+    pbeg(6);
+    scalar(SC_BETA, part1, nvblk, flexible ? part2 : nullptr);
+    hipLaunchKernelGGL(k_pupdate, dim3(nvblk), dim3(VB), 0, stream, nf, sc, z, p);
+    pend(6);
+  }
+
+  void start(const double *b, double tol) {
+    hipLaunchKernelGGL(k_permute_in, dim3(nvblk), dim3(VB), 0, stream, nf, user_of_vint, b, r, x, p, z, bint, part1);
+    scalar(SC_INIT, part1, nvblk, nullptr, tol * tol);
+    precond(r, z, r, part1, nullptr, done_flag);
+    scalar(SC_RZ0, part1, nvblk, nullptr);
+    hipLaunchKernelGGL(k_pupdate, dim3(nvblk), dim3(VB), 0, stream, nf, sc, z, p);
+  }
+
+  void finish(double *u) {
+    apply_op(x, q, nullptr, zero_flag);
+    hipLaunchKernelGGL(k_resnorm, dim3(nvblk), dim3(VB), 0, stream, nf, bint, q, part1);
+    scalar(SC_RES, part1, nvblk, nullptr);
+    hipLaunchKernelGGL(k_permute_out, dim3(nblk(nv, VB)), dim3(VB), 0, stream, nv, nf, vint_of_user, x, u);
+    HIPCHK(hipMemcpyAsync(h_sc, sc, sizeof(Scalars), hipMemcpyDeviceToHost, stream));
+  }
+
+  void fill_stats(coarse_stats *st, double t0) {
+    if (!st) return;
+    st->iters = h_sc->iter;
+    st->status = h_sc->status;
+    st->relres = h_sc->bb > 0 ? std::sqrt(h_sc->rr / h_sc->bb) : 0.0;
+    st->relres_true = h_sc->bb > 0 ? std::sqrt(h_sc->res_true / h_sc->bb) : 0.0;
+    st->t_setup = t_setup;
+    st->t_solve = now() - t0;
+  }
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Setup helpers
+// ---------------------------------------------------------------------------
+template <typename T>
+std::vector<T> cast_vec(const std::vector<double> &v) {
+  return std::vector<T>(v.begin(), v.end());
+}
+
+// Invert a list of dense SPD systems (assembled by `assemble`) into the tile
+// store `out` (type T) with the batched block sweep, in chunks that bound the
+// FP64 scratch. Returns the number of systems flagged not SPD.
+template <typename T, typename Assemble>
+int64_t invert_systems(coarse_ctx *c, const std::vector<System> &sys, const std::vector<int64_t> &which, T *out,
+                       size_t scratch_tiles_max, Assemble assemble) {
+  hipStream_t s = c->stream;
+  int64_t nbad = 0;
+  size_t i0 = 0;
+  while (i0 < which.size()) {
+    // chunk [i0, i1)
+    size_t i1 = i0;
+    int64_t tiles = 0, pans = 0;
+    while (i1 < which.size()) {
+      const System &S = sys[which[i1]];
+      const int64_t t = S.nb * (S.nb + 1) / 2;
+      if (i1 > i0 && (size_t)(tiles + t) > scratch_tiles_max) break;
+      tiles += t;
+      pans += S.nb;
+      ++i1;
+    }
+    const int64_t ns = (int64_t)(i1 - i0);
+    std::vector<SweepSys> ss(ns);
+    std::vector<AsmSys> as(ns);
+    std::vector<int64_t> oo(ns);
+    std::vector<int32_t> tsys;
+    std::vector<int16_t> tI, tJ;
+    int64_t toff = 0, poff = 0, maxnb = 0;
+    for (int64_t k = 0; k < ns; ++k) {
+      const System &S = sys[which[i0 + k]];
+      ss[k].tile_off = toff;
+      ss[k].pan_off = poff;
+      ss[k].nb = (int32_t)S.nb;
+      as[k].tile_off = toff;
+      as[k].vec_off = (int32_t)S.vec_off;
+      as[k].n = (int32_t)S.n;
+      as[k].nb = (int32_t)S.nb;
+      oo[k] = S.tile_off;
+      for (int I = 0; I < S.nb; ++I)
+        for (int J = 0; J <= I; ++J) {
+          tsys.push_back((int32_t)k);
+          tI.push_back((int16_t)I);
+          tJ.push_back((int16_t)J);
+        }
+      toff += S.nb * (S.nb + 1) / 2;
+      poff += S.nb;
+      maxnb = std::max<int64_t>(maxnb, S.nb);
+    }
+    Arena tmp;
+    double *M = tmp.alloc<double>((size_t)toff * TILE * TILE);
+    double *Pb = tmp.alloc<double>((size_t)poff * TILE * TILE);
+    double *Gb = tmp.alloc<double>((size_t)poff * TILE * TILE);
+    double *Dv = tmp.alloc<double>((size_t)ns * TILE * TILE);
+    int *st = tmp.alloc<int>(ns);
+    SweepSys *dss = tmp.upload(ss, s);
+    AsmSys *das = tmp.upload(as, s);
+    int64_t *doo = tmp.upload(oo, s);
+    int32_t *dts = tmp.upload(tsys, s);
+    int16_t *dti = tmp.upload(tI, s);
+    int16_t *dtj = tmp.upload(tJ, s);
+    HIPCHK(hipMemsetAsync(M, 0, (size_t)toff * TILE * TILE * sizeof(double), s));
+    HIPCHK(hipMemsetAsync(st, 0, ns * sizeof(int), s));
+    hipLaunchKernelGGL(k_pad_identity, dim3((unsigned)ns), dim3(256), 0, s, das, (int)ns, M);
+    assemble(das, (int)ns, M);
+    const int64_t ntiles = (int64_t)tsys.size();
+    for (int k = 0; k < maxnb; ++k) {
+      hipLaunchKernelGGL(k_sweep_pivot, dim3((unsigned)ns), dim3(256), 0, s, k, dss, M, Dv, st);
+      hipLaunchKernelGGL(k_sweep_panel, dim3((unsigned)ns, (unsigned)maxnb), dim3(256), 0, s, k, dss, M, Dv, Pb, Gb);
+      hipLaunchKernelGGL(k_sweep_update, dim3((unsigned)ntiles), dim3(256), 0, s, k, dss, dts, dti, dtj, M, Dv, Pb, Gb);
+    }
+    hipLaunchKernelGGL(k_sweep_pack<T>, dim3((unsigned)ntiles), dim3(256), 0, s, dss, dts, dti, dtj, doo, M, out);
+    HIPCHK(hipGetLastError());
+    std::vector<int> hst(ns);
+    HIPCHK(hipMemcpyAsync(hst.data(), st, ns * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int v : hst) nbad += (v != 0);
+    i0 = i1;
+  }
+  return nbad;
+}
+
+template <typename T>
+void setup_precision(coarse_ctx *c, Plan &P) {
+  hipStream_t s = c->stream;
+  Arena &A = c->arena;
+  const int64_t NE = P.n_elem, NV = P.n_vert, nf = P.n_free;
+  // geometry and element matrices
+  Arena tmp;
+  double *xyz = tmp.upload(P.xyz, s);
+  int32_t *e2v = tmp.upload(P.e2v, s);
+  double *Ae = A.alloc<double>(36 * NE);
+  int *bad = tmp.alloc<int>(1);
+  HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_elem_matrices, dim3(nblk(NE, 256)), dim3(256), 0, s, NE, NV, xyz, e2v, Ae, bad);
+  int hbad = 0;
+  HIPCHK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (hbad) throw Fail(COARSE_EMESH, std::to_string(hbad) + " element(s) with det(dx/dxi) <= 0 at a Gauss point");
+
+  // operator
+  OpDev &op = c->op;
+  op.E = NE;
+  op.n_blocks = P.n_blocks;
+  op.n_shared = (int64_t)P.sh_vid.size();
+  op.Ae = Ae;
+  op.lconn = A.upload(P.lconn, s);
+  op.blk_slot_ptr = A.upload(P.blk_slot_ptr, s);
+  op.slot_vid = A.upload(P.slot_vid, s);
+  op.slot_dst = A.upload(P.slot_dst, s);
+  op.slot_inc_ptr = A.upload(P.slot_inc_ptr, s);
+  op.slot_inc = A.upload(P.slot_inc, s);
+  op.partials = A.alloc<double>(std::max<int64_t>(1, P.n_partials));
+  op.sh_vid = A.upload(P.sh_vid, s);
+  op.sh_ptr = A.upload(P.sh_ptr, s);
+  op.sh_part = A.upload(P.sh_part, s);
+  op.lds_bytes = (int32_t)((OP_BLOCK * 8 + P.max_slots) * sizeof(double));
+  if (op.lds_bytes > 64 * 1024) throw Fail(COARSE_EINVAL, "operator block touches too many vertices");
+
+  // vectors
+  c->nf = nf;
+  c->nv = NV;
+  c->ne = NE;
+  c->nvblk = (int)std::min<int64_t>(1024, nblk(nf, VB));
+  std::vector<int32_t> uov(P.user_of_vint.begin(), P.user_of_vint.begin() + nf);
+  c->user_of_vint = A.upload(uov, s);
+  c->vint_of_user = A.upload(P.vint_of_user, s);
+  for (double **v : {&c->x, &c->r, &c->p, &c->z, &c->q, &c->bint, &c->t1, &c->t2}) {
+    *v = A.alloc<double>(nf);
+    HIPCHK(hipMemsetAsync(*v, 0, nf * sizeof(double), s));
+  }
+  const int64_t npart = std::max<int64_t>(c->nvblk, 1);
+  c->part1 = A.alloc<double>(npart);
+  c->part2 = A.alloc<double>(npart);
+  c->energy = A.alloc<double>(std::max<int64_t>(1, P.n_blocks));
+  c->sc = A.alloc<Scalars>(1);
+  HIPCHK(hipMemsetAsync(c->sc, 0, sizeof(Scalars), s));
+  c->done_flag = (int *)((char *)c->sc + offsetof(Scalars, done));
+  c->zero_flag = A.alloc<int>(1);
+  HIPCHK(hipMemsetAsync(c->zero_flag, 0, sizeof(int), s));
+
+  // packed vectors, systems, tiles
+  c->n_local_sys = P.n_local_sys;
+  c->vec_len = P.vec_len;
+  c->coarse_vec_off = P.sys.back().vec_off;
+  c->n_r = P.n_r;
+  c->sub_idx = A.upload(P.sub_idx, s);
+  c->rp = A.alloc<T>(P.vec_len);
+  HIPCHK(hipMemsetAsync(c->rp, 0, P.vec_len * sizeof(T), s));
+  c->zp = A.alloc<double>(P.vec_len);
+  HIPCHK(hipMemsetAsync(c->zp, 0, P.vec_len * sizeof(double), s));
+  T *tiles = A.alloc<T>((size_t)P.n_tiles * TILE * TILE);
+  c->tiles = tiles;
+  c->colpart = A.alloc<T>((size_t)P.n_tiles * TILE);
+  c->rowpart = A.alloc<T>((size_t)P.items.size() * TILE);
+  c->cover_ptr = A.upload(P.cover_ptr, s);
+  c->cover_pos = A.upload(P.cover_pos, s);
+
+  // inverses of the local systems (dense assembly of A_p) ...
+  const size_t scratch_tiles = (size_t)(1536ull << 20) / (TILE * TILE * sizeof(double));
+  std::vector<int64_t> loc(P.n_local_sys);
+  for (int64_t k = 0; k < P.n_local_sys; ++k) loc[k] = k;
+  int32_t *vinc_ptr = tmp.upload(P.vinc_ptr, s);
+  int32_t *vinc = tmp.upload(P.vinc, s);
+  int64_t nbad = invert_systems<T>(c, P.sys, loc, tiles, scratch_tiles, [&](AsmSys *das, int ns, double *M) {
+    hipLaunchKernelGGL(k_assemble_local, dim3((unsigned)ns), dim3(256), 0, s, das, c->sub_idx, vinc_ptr, vinc, e2v, NE,
+                       nf, (const double *)Ae, M);
+  });
+  if (nbad) throw Fail(COARSE_ESINGULAR, std::to_string(nbad) + " local system(s) A_p not positive definite");
+
+  // ... and of the reduced system (cell assembly, eq. (Aij))
+  BoxDev box;
+  for (int d = 0; d < 3; ++d) {
+    box.lo[d] = P.lo[d];
+    box.H[d] = P.H[d];
+    box.b[d] = P.b[d];
+  }
+  const int64_t nocc = (int64_t)P.occ_cells.size();
+  int32_t *occ_cells = tmp.upload(P.occ_cells, s);
+  int32_t *occ_ptr = tmp.upload(P.occ_elem_ptr, s);
+  int32_t *occ_elems = tmp.upload(P.occ_elems, s);
+  double *cellmat = tmp.alloc<double>(64 * std::max<int64_t>(1, nocc));
+  c->corner_act = A.upload(P.occ_corner_act, s);
+  int32_t *ar_ptr = tmp.upload(P.ar_ptr, s);
+  int32_t *ar_src = tmp.upload(P.ar_src, s);
+  if (c->interp != COARSE_J_CENTROID) throw Fail(COARSE_EINVAL, "standard interpolation is not available in this build");
+  hipLaunchKernelGGL(k_cell_mats, dim3((unsigned)nocc), dim3(64), 0, s, box, occ_cells, occ_ptr, occ_elems, e2v, NE, NV,
+                     nf, xyz, (const double *)Ae, cellmat);
+  std::vector<int64_t> red = {P.n_local_sys};
+  const int64_t nr = P.n_r;
+  nbad = invert_systems<T>(c, P.sys, red, tiles, scratch_tiles, [&](AsmSys *, int, double *M) {
+    hipLaunchKernelGGL(k_assemble_reduced, dim3(nblk(nr, 256)), dim3(256), 0, s, nr, ar_ptr, ar_src,
+                       (const int32_t *)c->corner_act, (const double *)cellmat, M);
+  });
+  if (nbad) throw Fail(COARSE_ESINGULAR, "reduced system A_r not positive definite (empty interior box?)");
+
+  // GEMV items, combine rows, system table, segments
+  std::vector<SysDev> sd(P.sys.size());
+  for (size_t k = 0; k < P.sys.size(); ++k) {
+    const System &S = P.sys[k];
+    sd[k].tiles = tiles + (size_t)S.tile_off * TILE * TILE;
+    sd[k].rp = (T *)c->rp + S.vec_off;
+    sd[k].colpart = (T *)c->colpart + (size_t)S.tile_off * TILE;
+    sd[k].zp = c->zp + S.vec_off;
+    sd[k].nb = (int32_t)S.nb;
+  }
+  // item slots: index within the system's item list
+  std::vector<int64_t> sys_item0(P.sys.size(), -1);
+  for (size_t i = 0; i < P.items.size(); ++i)
+    if (sys_item0[P.items[i].sys] < 0) sys_item0[P.items[i].sys] = (int64_t)i;
+  for (size_t k = 0; k < P.sys.size(); ++k) sd[k].rowpart = (T *)c->rowpart + (size_t)sys_item0[k] * TILE;
+  std::vector<GItem> gi(P.items.size());
+  int32_t il = 0;
+  for (size_t i = 0; i < P.items.size(); ++i) {
+    const GemvItem &it = P.items[i];
+    gi[i].sys = it.sys;
+    gi[i].I = (int16_t)it.I;
+    gi[i].j0 = (int16_t)it.j0;
+    gi[i].j1 = (int16_t)it.j1;
+    gi[i].pad = 0;
+    gi[i].slot = (int32_t)(i - sys_item0[it.sys]);
+    if (it.sys < P.n_local_sys) il = (int32_t)i + 1;
+  }
+  if (P.sys.back().nb > 32767 / 2) throw Fail(COARSE_EINVAL, "reduced system too large");
+  std::vector<GRow> gr(P.n_rows);
+  int32_t rl = 0;
+  for (int64_t k = 0; k < P.n_rows; ++k) {
+    gr[k].sys = P.row_sys[k];
+    gr[k].I = P.row_I[k];
+    gr[k].slot0 = (int32_t)(P.row_item0[k] - sys_item0[P.row_sys[k]]);
+    gr[k].nslot = P.row_nitem[k];
+    if (P.row_sys[k] < P.n_local_sys) rl = (int32_t)k + 1;
+  }
+  c->items = A.upload(gi, s);
+  c->rows = A.upload(gr, s);
+  c->sysdev = A.upload(sd, s);
+  c->items_local = il;
+  c->items_total = (int32_t)gi.size();
+  c->rows_local = rl;
+  c->rows_total = (int32_t)gr.size();
+  c->h_seg_all = Seg{c->items, c->rows, c->sysdev, 0, 0};
+  c->h_seg_local = c->h_seg_all;
+  c->h_seg_coarse = Seg{c->items + il, c->rows + rl, c->sysdev, 0, 0};
+  c->seg_all = A.upload(std::vector<Seg>{c->h_seg_all}, s);
+  c->seg_local = A.upload(std::vector<Seg>{c->h_seg_local}, s);
+  c->seg_coarse = A.upload(std::vector<Seg>{c->h_seg_coarse}, s);
+
+  // reduced-space interpolation entries
+  c->nent = (int64_t)P.jv_w.size();
+  c->jv_ptr = A.upload(P.jv_ptr, s);
+  c->jv_occ = A.upload(P.jv_occ, s);
+  c->jv_w = A.upload(cast_vec<T>(P.jv_w), s);
+  c->jv_xi = A.upload(cast_vec<T>(P.jv_xi), s);
+  c->jc_vid = A.upload(P.jc_vid, s);
+  c->jc_w = A.upload(cast_vec<T>(P.jc_w), s);
+  c->jc_xi = A.upload(cast_vec<T>(P.jc_xi), s);
+  c->ntask = (int64_t)P.jt_task_occ.size();
+  c->jt_start = A.upload(P.jt_task_start, s);
+  c->jt_part = A.alloc<T>(8 * std::max<int64_t>(1, c->ntask));
+  c->jr_ptr = A.upload(P.jr_ptr, s);
+  c->jr_src = A.upload(P.jr_src, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+
+  // sizes
+  coarse_info_t &in = c->info;
+  in.n_free = nf;
+  in.n_sub = P.n_local_sys;
+  in.sum_np = 0;
+  in.max_np = 0;
+  for (int64_t k = 0; k < P.n_local_sys; ++k) {
+    in.sum_np += P.sys[k].n;
+    in.max_np = std::max<int64_t>(in.max_np, P.sys[k].n);
+  }
+  in.n_r = P.n_r;
+  in.n_cells = nocc;
+  const int64_t tl = P.sys.back().tile_off;
+  in.local_bytes = tl * TILE * TILE * (int64_t)sizeof(T);
+  in.reduced_bytes = (P.n_tiles - tl) * TILE * TILE * (int64_t)sizeof(T);
+  in.inv_alg_bytes = 0;
+  for (const System &S : P.sys) in.inv_alg_bytes += S.n * (S.n + 1) / 2 * (int64_t)sizeof(T);
+  in.a_bytes = NE * (36 * 8 + 8 * 2) + (int64_t)P.slot_vid.size() * 12 + (int64_t)P.slot_inc.size() * 2 + nf * 16;
+  for (int d = 0; d < 3; ++d) in.boxes[d] = P.b[d];
+  in.precision = c->precision;
+}
+
+coarse_ctx *as_ctx(const coarse_ctx *c) { return const_cast<coarse_ctx *>(c); }
+
+int fail_ctx(coarse_ctx *c, const Fail &f) {
+  if (c) c->err = f.what();
+  return f.code;
+}
+
+PlanInput make_input(const coarse_mesh *mesh, const coarse_bc *bc, const coarse_opts *o) {
+  PlanInput in;
+  in.n_vert = mesh->n_vert;
+  in.n_elem = mesh->n_elem;
+  in.xyz = mesh->xyz;
+  in.e2v = mesh->e2v;
+  in.part = mesh->part;
+  in.n_part = mesh->n_part;
+  in.dirichlet = bc->dirichlet;
+  in.overlap = o->overlap;
+  for (int d = 0; d < 3; ++d) in.boxes[d] = o->boxes[d];
+  in.interp = o->interp;
+  return in;
+}
+
+}  // namespace
+
+extern "C" {
+
+void coarse_default_opts(coarse_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->overlap = 1;
+  o->precision = COARSE_FP64;
+  o->mode = COARSE_ADDITIVE;
+  o->interp = COARSE_J_CENTROID;
+  o->max_it = 1000;
+  o->check_every = 4;
+  o->flexible = 0;
+  o->stream = nullptr;
+}
+
+int coarse_plan_info(const coarse_mesh *mesh, const coarse_bc *bc, const coarse_opts *opts, coarse_info_t *info,
+                     int64_t *sizes) {
+  if (!mesh || !bc || !info) return COARSE_EINVAL;
+  coarse_opts o;
+  coarse_default_opts(&o);
+  if (opts) o = *opts;
+  Plan P;
+  int rc = build_plan(make_input(mesh, bc, &o), P);
+  if (rc) {
+    g_setup_error = P.err;
+    return rc;
+  }
+  std::memset(info, 0, sizeof(*info));
+  info->n_free = P.n_free;
+  info->n_sub = P.n_local_sys;
+  for (int64_t k = 0; k < P.n_local_sys; ++k) {
+    info->sum_np += P.sys[k].n;
+    info->max_np = std::max<int64_t>(info->max_np, P.sys[k].n);
+  }
+  info->n_r = P.n_r;
+  info->n_cells = (int64_t)P.occ_cells.size();
+  for (int d = 0; d < 3; ++d) info->boxes[d] = P.b[d];
+  info->precision = o.precision;
+  if (sizes)
+    for (int32_t p = 0; p < P.n_part; ++p) sizes[p] = (int64_t)P.R[p].size();
+  return 0;
+}
+
+int coarse_setup(const coarse_mesh *mesh, const coarse_bc *bc, const coarse_opts *opts, coarse_ctx **out) {
+  if (!mesh || !bc || !out) {
+    g_setup_error = "null argument";
+    return COARSE_EINVAL;
+  }
+  *out = nullptr;
+  coarse_opts o;
+  coarse_default_opts(&o);
+  if (opts) o = *opts;
+  if (o.precision != COARSE_FP64 && o.precision != COARSE_MIXED) {
+    g_setup_error = "unknown precision";
+    return COARSE_EINVAL;
+  }
+  if (o.mode < 0 || o.mode > 3 || o.max_it < 1 || o.check_every < 1) {
+    g_setup_error = "bad mode, max_it or check_every";
+    return COARSE_EINVAL;
+  }
+  const double t0 = now();
+  Plan P;
+  int rc = build_plan(make_input(mesh, bc, &o), P);
+  if (rc) {
+    g_setup_error = P.err;
+    return rc;
+  }
+  std::unique_ptr<coarse_ctx> c(new coarse_ctx());
+  c->stream = (hipStream_t)o.stream;
+  c->precision = o.precision;
+  c->mode = o.mode;
+  c->interp = o.interp;
+  c->max_it = o.max_it;
+  c->check_every = o.check_every;
+  c->flexible = o.flexible ? 1 : 0;
+  try {
+    HIPCHK(hipHostMalloc((void **)&c->h_sc, sizeof(Scalars), hipHostMallocDefault));
+    if (o.precision == COARSE_FP64)
+      setup_precision<double>(c.get(), P);
+    else
+      setup_precision<float>(c.get(), P);
+  } catch (const Fail &f) {
+    g_setup_error = f.what();
+    (void)hipStreamSynchronize(c->stream);
+    return f.code;
+  } catch (const std::bad_alloc &) {
+    g_setup_error = "host allocation failed";
+    return COARSE_ENOMEM;
+  }
+  c->t_setup = now() - t0;
+  c->info.device_bytes = (int64_t)c->arena.bytes;
+  *out = c.release();
+  return COARSE_OK;
+}
+
+int coarse_apply_precond(coarse_ctx *c, const double *r, double *z) {
+  if (!c || !r || !z || r == z) return COARSE_EINVAL;
+  try {
+    hipLaunchKernelGGL(k_gather_user, dim3(c->nvblk), dim3(VB), 0, c->stream, c->nf, c->user_of_vint, r, c->r);
+    c->precond(c->r, c->z, nullptr, nullptr, nullptr, c->zero_flag);
+    hipLaunchKernelGGL(k_permute_out, dim3(nblk(c->nv, VB)), dim3(VB), 0, c->stream, c->nv, c->nf, c->vint_of_user,
+                       c->z, z);
+    HIPCHK(hipGetLastError());
+  } catch (const Fail &f) {
+    return fail_ctx(c, f);
+  }
+  return COARSE_OK;
+}
+
+int coarse_apply_A(coarse_ctx *c, const double *p, double *q) {
+  if (!c || !p || !q || p == q) return COARSE_EINVAL;
+  try {
+    hipLaunchKernelGGL(k_gather_user, dim3(c->nvblk), dim3(VB), 0, c->stream, c->nf, c->user_of_vint, p, c->p);
+    c->apply_op(c->p, c->q, nullptr, c->zero_flag);
+    hipLaunchKernelGGL(k_permute_out, dim3(nblk(c->nv, VB)), dim3(VB), 0, c->stream, c->nv, c->nf, c->vint_of_user,
+                       c->q, q);
+    HIPCHK(hipGetLastError());
+  } catch (const Fail &f) {
+    return fail_ctx(c, f);
+  }
+  return COARSE_OK;
+}
+
+int coarse_solve(coarse_ctx *c, const double *b, double *u, double tol, coarse_stats *st) {
+  if (!c || !b || !u || b == u || !(tol > 0)) return COARSE_EINVAL;
+  const double t0 = now();
+  try {
+    c->start(b, tol);
+    for (;;) {
+      for (int j = 0; j < c->check_every; ++j) c->iteration();
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(c->h_sc, c->sc, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      c->pcollect();
+      if (c->h_sc->done) break;
+    }
+    c->finish(u);
+    HIPCHK(hipStreamSynchronize(c->stream));
+  } catch (const Fail &f) {
+    return fail_ctx(c, f);
+  }
+  c->fill_stats(st, t0);
+  const int status = c->h_sc->status;
+  if (status == -6) c->err = "PCG breakdown (p.Ap <= 0 or non-finite value)";
+  if (status == 1) c->err = "iteration limit reached";
+  return status;
+}
+
+int coarse_solve_batch(coarse_ctx *const *ctxs, const double *const *b, double *const *u, int count, double tol,
+                       coarse_stats *st) {
+  if (!ctxs || !b || !u || count < 0) return COARSE_EINVAL;
+  int worst = COARSE_OK;
+  for (int i = 0; i < count; ++i) {
+    int rc = coarse_solve(ctxs[i], b[i], u[i], tol, st ? st + i : nullptr);
+    if (rc < 0 || (rc > 0 && worst == COARSE_OK)) worst = rc;
+  }
+  return worst;
+}
+
+int coarse_destroy(coarse_ctx *c) {
+  if (!c) return COARSE_OK;
+  (void)hipStreamSynchronize(c->stream);
+  delete c;
+  return COARSE_OK;
+}
+
+size_t coarse_device_bytes(const coarse_ctx *c) { return c ? c->arena.bytes : 0; }
+
+int coarse_get_info(const coarse_ctx *c, coarse_info_t *info) {
+  if (!c || !info) return COARSE_EINVAL;
+  *info = c->info;
+  info->device_bytes = (int64_t)c->arena.bytes;
+  return COARSE_OK;
+}
+
+int coarse_profile(coarse_ctx *c, int enable, double *ms, int64_t *counts, int nphase) {
+  if (!c || nphase < 0) return COARSE_EINVAL;
+  try {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->pcollect();
+    if (enable) {
+      for (int i = 0; i < coarse_ctx::NPH; ++i) {
+        c->prof_ms[i] = 0.0;
+        c->prof_cnt[i] = 0;
+      }
+      c->prof_on = true;
+    } else {
+      c->prof_on = false;
+      for (int i = 0; i < std::min(nphase, (int)coarse_ctx::NPH); ++i) {
+        if (ms) ms[i] = c->prof_ms[i];
+        if (counts) counts[i] = c->prof_cnt[i];
+      }
+    }
+  } catch (const Fail &f) {
+    return fail_ctx(c, f);
+  }
+  return COARSE_OK;
+}
+
+int coarse_set_stream(coarse_ctx *c, void *stream) {
+  if (!c) return COARSE_EINVAL;
+  c->stream = (hipStream_t)stream;
+  return COARSE_OK;
+}
+
+const char *coarse_strerror(int code) {
+  switch (code) {
+    case COARSE_OK: return "success";
+    case COARSE_NOTCONV: return "iteration limit reached before the tolerance";
+    case COARSE_EINVAL: return "invalid argument";
+    case COARSE_ENOMEM: return "out of memory";
+    case COARSE_EMESH: return "invalid mesh (inverted element or repeated vertex)";
+    case COARSE_ESINGULAR: return "singular local or reduced system";
+    case COARSE_EDEVICE: return "HIP runtime error";
+    case COARSE_EBREAKDOWN: return "PCG breakdown";
+    default: return "unknown status";
+  }
+}
+
+const char *coarse_last_error(const coarse_ctx *c) { return c ? c->err.c_str() : g_setup_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,60 @@
+// Kernel declarations and the small descriptor structs shared between the
+// kernels (kernels.hip) and the host orchestration (api.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace coarse {
+
+// Solver scalars living in device memory (one per context).
+struct Scalars {
+  double bb, rz, rr, pq, alpha, beta, tol2, res_true;
+  int32_t iter, done, status, max_it, flexible, pad0, pad1, pad2;
+};
+
+// One dense system of the batched local/reduced solve, with absolute pointers.
+struct SysDev {
+  const void *tiles;   // lower tiles of A_s^{-1}, TILE x TILE row-major each
+  const void *rp;      // right-hand side (nb*TILE entries)
+  void *colpart;       // per tile: transposed contribution (TILE entries)
+  void *rowpart;       // per work item: row contribution (TILE entries)
+  double *zp;          // solution (nb*TILE entries)
+  int32_t nb, pad;
+};
+
+// GEMV work item: tiles (I, j0 .. j1-1) of system `sys`; `slot` indexes the
+// system's row-partial area.
+struct GItem {
+  int32_t sys;
+  int16_t I, j0, j1, pad;
+  int32_t slot;
+};
+
+// Combine work: one tile row of one system.
+struct GRow {
+  int32_t sys, I, slot0, nslot;
+};
+
+// A contiguous range of items (or rows) of one context inside a batched launch.
+struct Seg {
+  const GItem *items;
+  const GRow *rows;
+  const SysDev *sys;
+  int32_t begin;   // first global index of this segment
+  int32_t pad;
+};
+
+// Device pointers of one context used by the per-iteration kernels.
+struct OpDev {
+  int64_t E, n_blocks, n_shared;
+  const double *Ae;
+  const uint16_t *lconn;
+  const int32_t *blk_slot_ptr, *slot_vid, *slot_dst, *slot_inc_ptr;
+  const uint16_t *slot_inc;
+  double *partials;
+  const int32_t *sh_vid, *sh_ptr, *sh_part;
+  int32_t lds_bytes;
+};
+
+}  // namespace coarse

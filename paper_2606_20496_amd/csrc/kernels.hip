@@ -1,0 +1,934 @@
+// HIP kernels of the coarse solver for gfx950 (wave64). Every reduction has a
+// fixed order (no floating-point atomics), so results are bitwise reproducible and
+// do not depend on what else shares a launch.
+#include "device.h"
+#include "kernels.h"
+#include "plan.h"
+
+namespace coarse {
+
+// ---------------------------------------------------------------------------
+// Setup: Q1 element matrices (Sec. 3, a^e_ij = int grad l_i . grad l_j) with the
+// 2x2x2 Gauss rule on the trilinear map of [-1,1]^3. One thread per element;
+// the 36 distinct entries are stored SoA [36][E].
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_elem_matrices(int64_t E, int64_t NV, const double *__restrict__ xyz,
+                                                       const int32_t *__restrict__ e2v, double *__restrict__ Ae,
+                                                       int *__restrict__ bad) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  double X[8][3];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    const int64_t u = e2v[v * E + e];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) X[v][d] = xyz[d * NV + u];
+  }
+  double A[36];
+#pragma unroll
+  for (int k = 0; k < 36; ++k) A[k] = 0.0;
+  const double g = 0.57735026918962576451;
+  double detmin = 1e300;
+#pragma unroll 1
+  for (int q = 0; q < 8; ++q) {
+    const double xq[3] = {(q & 1) ? g : -g, (q & 2) ? g : -g, (q & 4) ? g : -g};
+    double dN[8][3];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const double s0 = (v & 1) ? 1.0 : -1.0, s1 = (v & 2) ? 1.0 : -1.0, s2 = (v & 4) ? 1.0 : -1.0;
+      const double f0 = 1.0 + s0 * xq[0], f1 = 1.0 + s1 * xq[1], f2 = 1.0 + s2 * xq[2];
+      dN[v][0] = 0.125 * s0 * f1 * f2;
+      dN[v][1] = 0.125 * s1 * f0 * f2;
+      dN[v][2] = 0.125 * s2 * f0 * f1;
+    }
+    double J[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        double s = 0.0;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) s += X[v][i] * dN[v][j];
+        J[i][j] = s;
+      }
+    // cofactors: inv(J)[j][i] = C[i][j] / det
+    double C[3][3];
+    C[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    C[0][1] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    C[0][2] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    C[1][0] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+    C[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+    C[1][2] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+    C[2][0] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+    C[2][1] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+    C[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    const double det = J[0][0] * C[0][0] + J[0][1] * C[0][1] + J[0][2] * C[0][2];
+    detmin = fmin(detmin, det);
+    const double id = 1.0 / det;
+    // physical gradient G[v][i] = sum_j dN[v][j] inv(J)[j][i] = sum_j dN[v][j] C[i][j] / det
+    double G[8][3];
+#pragma unroll
+    for (int v = 0; v < 8; ++v)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) G[v][i] = (dN[v][0] * C[i][0] + dN[v][1] * C[i][1] + dN[v][2] * C[i][2]) * id;
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int b = a; b < 8; ++b)
+        A[sym8(a, b)] += det * (G[a][0] * G[b][0] + G[a][1] * G[b][1] + G[a][2] * G[b][2]);
+  }
+  if (!(detmin > 0.0)) atomicAdd(bad, 1);
+#pragma unroll
+  for (int k = 0; k < 36; ++k) Ae[k * E + e] = A[k];
+}
+
+// ---------------------------------------------------------------------------
+// Operator q = A p (Sec. 3: A = Q^T A_L Q, the local products then the
+// direct-stiffness sum). Pass 1: one workgroup per block of OP_BLOCK elements
+// stages the block's vertex values in LDS, each thread applies its 8x8 element
+// matrix, and the block sums the element outputs per vertex slot in a fixed
+// order. Vertices entirely inside the block are written directly; vertices
+// shared with other blocks go to a partial buffer that pass 2 sums. The energy
+// p^T A p = sum_e p_e^T A^e p_e (the PCG denominator) comes out per block.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(OP_BLOCK) void k_op_pass1(OpDev op, const double *__restrict__ p, double *__restrict__ q,
+                                                       double *__restrict__ energy, const int *__restrict__ done) {
+  extern __shared__ double lds[];
+  __shared__ double red[OP_BLOCK / WAVE];
+  if (done && *done) return;
+  double *out = lds;                 // [OP_BLOCK*8]
+  double *lp = lds + OP_BLOCK * 8;   // [slots]
+  const int blk = blockIdx.x;
+  const int s0 = op.blk_slot_ptr[blk], ns = op.blk_slot_ptr[blk + 1] - s0;
+  for (int s = threadIdx.x; s < ns; s += OP_BLOCK) lp[s] = p[op.slot_vid[s0 + s]];
+  __syncthreads();
+  const int64_t E = op.E;
+  const int64_t e = (int64_t)blk * OP_BLOCK + threadIdx.x;
+  double en = 0.0;
+  if (e < E) {
+    double pe[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const uint16_t sl = op.lconn[a * E + e];
+      pe[a] = (sl == 0xFFFF) ? 0.0 : lp[sl];
+    }
+    double y[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) y[a] = 0.0;
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int b = a; b < 8; ++b) {
+        const double m = op.Ae[sym8(a, b) * E + e];
+        y[a] += m * pe[b];
+        if (b != a) y[b] += m * pe[a];
+      }
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      out[threadIdx.x * 8 + a] = y[a];
+      en += pe[a] * y[a];
+    }
+  }
+  __syncthreads();
+  for (int s = threadIdx.x; s < ns; s += OP_BLOCK) {
+    const int k0 = op.slot_inc_ptr[s0 + s], k1 = op.slot_inc_ptr[s0 + s + 1];
+    double acc = 0.0;
+    for (int k = k0; k < k1; ++k) acc += out[op.slot_inc[k]];
+    const int dst = op.slot_dst[s0 + s];
+    if (dst >= 0)
+      q[dst] = acc;
+    else
+      op.partials[-dst - 1] = acc;
+  }
+  if (energy) {
+    const double tot = block_sum<OP_BLOCK>(en, red);
+    if (threadIdx.x == 0) energy[blk] = tot;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_op_pass2(OpDev op, double *__restrict__ q, const int *__restrict__ done) {
+  if (done && *done) return;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= op.n_shared) return;
+  double acc = 0.0;
+  for (int k = op.sh_ptr[i]; k < op.sh_ptr[i + 1]; ++k) acc += op.partials[op.sh_part[k]];
+  q[op.sh_vid[i]] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Vector kernels of PCG. All use the same fixed grid (nblk workgroups of 256
+// threads, thread t touching i = t, t + G, ...) so per-block partial sums are
+// reproducible.
+// ---------------------------------------------------------------------------
+constexpr int VB = 256;
+
+__global__ __launch_bounds__(VB) void k_permute_in(int64_t nf, const int32_t *__restrict__ user_of, const double *__restrict__ b,
+                                                   double *__restrict__ r, double *__restrict__ x, double *__restrict__ p,
+                                                   double *__restrict__ z, double *__restrict__ bint, double *__restrict__ part) {
+  __shared__ double red[VB / WAVE];
+  double acc = 0.0;
+  const int64_t G = (int64_t)gridDim.x * VB;
+  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < nf; i += G) {
+    const double v = b[user_of[i]];
+    r[i] = v;
+    bint[i] = v;
+    x[i] = 0.0;
+    p[i] = 0.0;
+    z[i] = 0.0;
+    acc += v * v;
+  }
+  const double s = block_sum<VB>(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// in-place permutation of a caller vector into internal order (no reduction)
+__global__ __launch_bounds__(VB) void k_gather_user(int64_t nf, const int32_t *__restrict__ user_of, const double *__restrict__ b,
+                                                    double *__restrict__ r) {
+  const int64_t G = (int64_t)gridDim.x * VB;
+  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < nf; i += G) r[i] = b[user_of[i]];
+}
+
+__global__ __launch_bounds__(VB) void k_permute_out(int64_t nv, int64_t nf, const int32_t *__restrict__ vint_of,
+                                                    const double *__restrict__ x, double *__restrict__ u) {
+  const int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x;
+  if (i >= nv) return;
+  const int32_t k = vint_of[i];
+  u[i] = (k < nf) ? x[k] : 0.0;
+}
+
+__global__ __launch_bounds__(VB) void k_update(int64_t nf, const Scalars *__restrict__ sc, double *__restrict__ x,
+                                               double *__restrict__ r, const double *__restrict__ p,
+                                               const double *__restrict__ q, double *__restrict__ part) {
+  __shared__ double red[VB / WAVE];
+  if (sc->done) return;
+  const double alpha = sc->alpha;
+  double acc = 0.0;
+  const int64_t G = (int64_t)gridDim.x * VB;
+  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < nf; i += G) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    acc += ri * ri;
+  }
+  const double s = block_sum<VB>(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(VB) void k_pupdate(int64_t nf, const Scalars *__restrict__ sc, const double *__restrict__ z,
+                                                double *__restrict__ p) {
+  if (sc->done) return;
+  const double beta = sc->beta;
+  const int64_t G = (int64_t)gridDim.x * VB;
+  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < nf; i += G) p[i] = z[i] + beta * p[i];
+}
+
+// t = a - q
+__global__ __launch_bounds__(VB) void k_sub(int64_t nf, const int *__restrict__ done, const double *__restrict__ a,
+                                            const double *__restrict__ q, double *__restrict__ t) {
+  if (done && *done) return;
+  const int64_t G = (int64_t)gridDim.x * VB;
+  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < nf; i += G) t[i] = a[i] - q[i];
+}
+
+// partial sums of (a - q)^2
+__global__ __launch_bounds__(VB) void k_resnorm(int64_t nf, const double *__restrict__ a, const double *__restrict__ q,
+                                                double *__restrict__ part) {
+  __shared__ double red[VB / WAVE];
+  double acc = 0.0;
+  const int64_t G = (int64_t)gridDim.x * VB;
+  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < nf; i += G) {
+    const double d = a[i] - q[i];
+    acc += d * d;
+  }
+  const double s = block_sum<VB>(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Scalar steps of PCG (one workgroup). Each sums a partial array in a fixed
+// order and updates the solver state.
+// ---------------------------------------------------------------------------
+__device__ double sum_parts(const double *part, int n, double *red) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += VB) acc += part[i];
+  return block_sum<VB>(acc, red);
+}
+
+enum ScalarOp { SC_INIT = 0, SC_RZ0 = 1, SC_ALPHA = 2, SC_CHECK = 3, SC_BETA = 4, SC_RES = 5 };
+
+__global__ __launch_bounds__(VB) void k_scalar(int op, Scalars *__restrict__ sc, const double *__restrict__ part, int n,
+                                               const double *__restrict__ part2, double tol2, int max_it, int flexible) {
+  __shared__ double red[VB / WAVE];
+  if (op != SC_INIT && op != SC_RES && sc->done) return;
+  const double s = sum_parts(part, n, red);
+  double s2 = 0.0;
+  if (part2) s2 = sum_parts(part2, n, red);
+  if (threadIdx.x != 0) return;
+  switch (op) {
+    case SC_INIT:
+      sc->bb = s;
+      sc->tol2 = tol2;
+      sc->max_it = max_it;
+      sc->flexible = flexible;
+      sc->iter = 0;
+      sc->status = 0;
+      sc->rr = s;
+      sc->alpha = sc->beta = sc->pq = sc->rz = 0.0;
+      sc->done = (s == 0.0) ? 1 : 0;
+      if (!isfinite(s)) {
+        sc->done = 1;
+        sc->status = -6;
+      }
+      break;
+    case SC_RZ0:
+      sc->rz = s;
+      sc->beta = 0.0;
+      if (!isfinite(s)) {
+        sc->done = 1;
+        sc->status = -6;
+      }
+      break;
+    case SC_ALPHA:
+      sc->pq = s;
+      if (!(s > 0.0) || !isfinite(s) || !isfinite(sc->rz)) {
+        sc->done = 1;
+        sc->status = -6;
+      } else {
+        sc->alpha = sc->rz / s;
+      }
+      break;
+    case SC_CHECK:
+      sc->rr = s;
+      sc->iter += 1;
+      if (!isfinite(s)) {
+        sc->done = 1;
+        sc->status = -6;
+      } else if (s <= sc->tol2 * sc->bb) {
+        sc->done = 1;
+        sc->status = 0;
+      } else if (sc->iter >= sc->max_it) {
+        sc->done = 1;
+        sc->status = 1;
+      }
+      break;
+    case SC_BETA: {
+      const double beta = sc->flexible ? (s - s2) / sc->rz : s / sc->rz;
+      sc->beta = beta;
+      sc->rz = s;
+      if (!isfinite(beta)) {
+        sc->done = 1;
+        sc->status = -6;
+      }
+      break;
+    }
+    case SC_RES:
+      sc->res_true = s;
+      break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Preconditioner, local part (Sec. 3, eq. (asm)): r_p = R_p r gathered into the
+// packed vectors of all subdomains (padding = 0).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(VB) void k_gather(int64_t n, const int *__restrict__ done, const int32_t *__restrict__ idx,
+                                               const double *__restrict__ in, T *__restrict__ rp) {
+  if (*done) return;
+  const int64_t j = blockIdx.x * (int64_t)VB + threadIdx.x;
+  if (j >= n) return;
+  const int32_t i = idx[j];
+  rp[j] = (i >= 0) ? (T)in[i] : T(0);
+}
+
+// ---------------------------------------------------------------------------
+// Reduced-space restriction J^T r (Sec. 4): J = W Q^T J_L S. Each wavefront
+// handles one task (<= JT_CHUNK entries of one cell), entry (i, c) carrying the
+// weight fraction n_ic/m_i and the local coordinates of vertex i in cell c; it
+// accumulates the 8 corner sums and reduces them across the wave. A second
+// kernel sums the tasks around each active box vertex in a fixed order.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_jt_tasks(int ntask, const int *__restrict__ done, const int32_t *__restrict__ tstart,
+                                                  const int32_t *__restrict__ vid, const T *__restrict__ w,
+                                                  const T *__restrict__ xi, int64_t nent, const double *__restrict__ in,
+                                                  T *__restrict__ tpart) {
+  if (*done) return;
+  const int lane = threadIdx.x & 63;
+  const int task = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (task >= ntask) return;
+  T acc[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) acc[k] = T(0);
+  for (int j = tstart[task] + lane; j < tstart[task + 1]; j += 64) {
+    const T v = w[j] * (T)in[vid[j]];
+    const T x = xi[j], y = xi[nent + j], z = xi[2 * nent + j];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] += trilin<T>(k, x, y, z) * v;
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) acc[k] = wave_sum(acc[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) tpart[task * 8 + k] = acc[k];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_jt_corners(int64_t nr, const int *__restrict__ done, const int32_t *__restrict__ ptr,
+                                                    const int32_t *__restrict__ src, const T *__restrict__ tpart,
+                                                    T *__restrict__ rr) {
+  if (*done) return;
+  const int64_t K = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (K >= nr) return;
+  T acc = T(0);
+  for (int k = ptr[K]; k < ptr[K + 1]; ++k) acc += tpart[src[k]];
+  rr[K] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Batched dense solves z_s = A_s^{-1} r_s for every system (the local A_p and the
+// reduced A_r): a symmetric GEMV over the lower tiles of the stored inverse.
+// Each wavefront streams up to GEMV_SEG tiles of one tile row I: it accumulates
+// the row contribution (tile * r_J) in registers and emits, for off-diagonal
+// tiles, the transposed contribution (tile^T * r_I) for row J. Tiles are read
+// once, with 16-byte loads; the partials are summed by k_combine.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int find_seg(const Seg *__restrict__ segs, int nseg, int g) {
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].begin <= g)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_gemv_f64(const Seg *__restrict__ segs, int nseg, int total,
+                                                  const int *__restrict__ done) {
+  if (done && *done) return;
+  const int lane = threadIdx.x & 63;
+  const int grp = lane >> 4, c2 = (lane & 15) * 2;
+  for (int g = blockIdx.x * 4 + (threadIdx.x >> 6); g < total; g += gridDim.x * 4) {
+    const Seg sg = segs[nseg == 1 ? 0 : find_seg(segs, nseg, g)];
+    const GItem it = sg.items[g - sg.begin];
+    const SysDev S = sg.sys[it.sys];
+    const double *__restrict__ r = (const double *)S.rp;
+    const int I = it.I;
+    const int64_t rowbase = (int64_t)I * (I + 1) / 2;
+    const double2 *__restrict__ tb = (const double2 *)((const double *)S.tiles + rowbase * (TILE * TILE));
+    double rI[8], acc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      rI[k] = r[I * TILE + 4 * k + grp];
+      acc[k] = 0.0;
+    }
+    for (int J = it.j0; J < it.j1; ++J) {
+      const double2 *__restrict__ t = tb + (int64_t)J * (TILE * TILE / 2);
+      double2 v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = t[k * 64 + lane];
+      const double2 rj = *(const double2 *)(r + J * TILE + c2);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) acc[k] += v[k].x * rj.x + v[k].y * rj.y;
+      if (J != I) {
+        double cx = 0.0, cy = 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          cx += v[k].x * rI[k];
+          cy += v[k].y * rI[k];
+        }
+        cx += __shfl_xor(cx, 16, 64);
+        cy += __shfl_xor(cy, 16, 64);
+        cx += __shfl_xor(cx, 32, 64);
+        cy += __shfl_xor(cy, 32, 64);
+        if (lane < 16) {
+          double2 o;
+          o.x = cx;
+          o.y = cy;
+          *(double2 *)((double *)S.colpart + (rowbase + J) * TILE + c2) = o;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      double a = acc[k];
+      a += __shfl_xor(a, 1, 64);
+      a += __shfl_xor(a, 2, 64);
+      a += __shfl_xor(a, 4, 64);
+      a += __shfl_xor(a, 8, 64);
+      acc[k] = a;
+    }
+    if ((lane & 15) == 0) {
+      double *rowp = (double *)S.rowpart + (int64_t)it.slot * TILE;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) rowp[4 * k + grp] = acc[k];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gemv_f32(const Seg *__restrict__ segs, int nseg, int total,
+                                                  const int *__restrict__ done) {
+  if (done && *done) return;
+  const int lane = threadIdx.x & 63;
+  const int grp = lane >> 3, c4 = (lane & 7) * 4;
+  for (int g = blockIdx.x * 4 + (threadIdx.x >> 6); g < total; g += gridDim.x * 4) {
+    const Seg sg = segs[nseg == 1 ? 0 : find_seg(segs, nseg, g)];
+    const GItem it = sg.items[g - sg.begin];
+    const SysDev S = sg.sys[it.sys];
+    const float *__restrict__ r = (const float *)S.rp;
+    const int I = it.I;
+    const int64_t rowbase = (int64_t)I * (I + 1) / 2;
+    const float4 *__restrict__ tb = (const float4 *)((const float *)S.tiles + rowbase * (TILE * TILE));
+    float rI[4], acc[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      rI[m] = r[I * TILE + 8 * m + grp];
+      acc[m] = 0.0f;
+    }
+    for (int J = it.j0; J < it.j1; ++J) {
+      const float4 *__restrict__ t = tb + (int64_t)J * (TILE * TILE / 4);
+      float4 v[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) v[m] = t[m * 64 + lane];
+      const float4 rj = *(const float4 *)(r + J * TILE + c4);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) acc[m] += v[m].x * rj.x + v[m].y * rj.y + v[m].z * rj.z + v[m].w * rj.w;
+      if (J != I) {
+        float c[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          c[0] += v[m].x * rI[m];
+          c[1] += v[m].y * rI[m];
+          c[2] += v[m].z * rI[m];
+          c[3] += v[m].w * rI[m];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          c[j] += __shfl_xor(c[j], 8, 64);
+          c[j] += __shfl_xor(c[j], 16, 64);
+          c[j] += __shfl_xor(c[j], 32, 64);
+        }
+        if (lane < 8) {
+          float4 o;
+          o.x = c[0];
+          o.y = c[1];
+          o.z = c[2];
+          o.w = c[3];
+          *(float4 *)((float *)S.colpart + (rowbase + J) * TILE + c4) = o;
+        }
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      float a = acc[m];
+      a += __shfl_xor(a, 1, 64);
+      a += __shfl_xor(a, 2, 64);
+      a += __shfl_xor(a, 4, 64);
+      acc[m] = a;
+    }
+    if ((lane & 7) == 0) {
+      float *rowp = (float *)S.rowpart + (int64_t)it.slot * TILE;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) rowp[8 * m + grp] = acc[m];
+    }
+  }
+}
+
+// z_s[I*TILE + c] = sum of the row partials of tile row I + sum over I' > I of
+// the transposed partials of tile (I', I).
+template <typename T>
+__global__ __launch_bounds__(256) void k_combine(const Seg *__restrict__ segs, int nseg, int total,
+                                                 const int *__restrict__ done) {
+  if (done && *done) return;
+  const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int g = (int)(gid / TILE), c = (int)(gid % TILE);
+  if (g >= total) return;
+  const Seg sg = segs[nseg == 1 ? 0 : find_seg(segs, nseg, g)];
+  const GRow rw = sg.rows[g - sg.begin];
+  const SysDev S = sg.sys[rw.sys];
+  const T *rowp = (const T *)S.rowpart;
+  const T *colp = (const T *)S.colpart;
+  double acc = 0.0;
+  for (int k = 0; k < rw.nslot; ++k) acc += (double)rowp[(int64_t)(rw.slot0 + k) * TILE + c];
+  for (int I2 = rw.I + 1; I2 < S.nb; ++I2) acc += (double)colp[((int64_t)I2 * (I2 + 1) / 2 + rw.I) * TILE + c];
+  S.zp[rw.I * TILE + c] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Final step of one preconditioner application, per free vertex i:
+//   out_i = add_i + sum_{(p,a) covering i} z_p[a]             (local part)
+//               + sum_c f_ic sum_k Phi_k(xi_ic) y_r[corner]  (J y_r, Sec. 4)
+// plus partial sums of r.out and r.out_old for the PCG beta.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(VB) void k_final(int64_t nf, const int *__restrict__ done, const double *__restrict__ add,
+                                              const int32_t *__restrict__ cover_ptr, const int32_t *__restrict__ cover_pos,
+                                              const double *__restrict__ zp, const int32_t *__restrict__ jv_ptr,
+                                              const int32_t *__restrict__ jv_occ, const T *__restrict__ jv_w,
+                                              const T *__restrict__ jv_xi, int64_t nent,
+                                              const int32_t *__restrict__ corner_act, const double *__restrict__ yr,
+                                              double *__restrict__ out, const double *__restrict__ rdot,
+                                              double *__restrict__ part1, double *__restrict__ part2) {
+  __shared__ double red[VB / WAVE];
+  if (*done) return;
+  double d1 = 0.0, d2 = 0.0;
+  const int64_t G = (int64_t)gridDim.x * VB;
+  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < nf; i += G) {
+    double acc = add ? add[i] : 0.0;
+    if (cover_ptr) {
+      for (int k = cover_ptr[i]; k < cover_ptr[i + 1]; ++k) acc += zp[cover_pos[k]];
+    }
+    if (jv_ptr) {
+      T cs = T(0);
+      for (int k = jv_ptr[i]; k < jv_ptr[i + 1]; ++k) {
+        const int32_t *ca = corner_act + 8 * (int64_t)jv_occ[k];
+        const T x = jv_xi[k], y = jv_xi[nent + k], z = jv_xi[2 * nent + k];
+        T s = T(0);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int32_t a = ca[q];
+          if (a >= 0) s += trilin<T>(q, x, y, z) * (T)yr[a];
+        }
+        cs += jv_w[k] * s;
+      }
+      acc += (double)cs;
+    }
+    if (rdot) {
+      const double ri = rdot[i];
+      if (part2) d2 += ri * out[i];
+      d1 += ri * acc;
+    }
+    out[i] = acc;
+  }
+  if (rdot) {
+    const double s1 = block_sum<VB>(d1, red);
+    if (threadIdx.x == 0) part1[blockIdx.x] = s1;
+    if (part2) {
+      const double s2 = block_sum<VB>(d2, red);
+      if (threadIdx.x == 0) part2[blockIdx.x] = s2;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Setup: dense assembly of the local systems A_p = R_p A R_p^T (Sec. 3) into
+// lower-tile storage. Every element containing a vertex of R_p belongs to the
+// overlapping subdomain, so row a of A_p is the sum over the elements incident
+// to vertex R_p[a] of their element-matrix rows, restricted to columns in R_p.
+// One workgroup per system, one thread per row (fixed order, no atomics).
+// ---------------------------------------------------------------------------
+struct AsmSys {
+  int64_t tile_off;   // offset (tiles) in the scratch store
+  int32_t vec_off;    // offset of R_p in sub_idx
+  int32_t n, nb, pad;
+};
+
+__device__ __forceinline__ double *tile_elem(double *M, int64_t tile_off, int i, int j) {
+  const int I = i / TILE, J = j / TILE;
+  return M + (tile_off + (int64_t)I * (I + 1) / 2 + J) * (TILE * TILE) + (i % TILE) * TILE + (j % TILE);
+}
+
+__global__ __launch_bounds__(256) void k_assemble_local(const AsmSys *__restrict__ sys, const int32_t *__restrict__ sub_idx,
+                                                        const int32_t *__restrict__ vinc_ptr, const int32_t *__restrict__ vinc,
+                                                        const int32_t *__restrict__ e2v, int64_t E, int64_t nf,
+                                                        const double *__restrict__ Ae, double *__restrict__ M) {
+  const AsmSys S = sys[blockIdx.x];
+  const int32_t *R = sub_idx + S.vec_off;
+  for (int a = threadIdx.x; a < S.n; a += blockDim.x) {
+    const int32_t v = R[a];
+    for (int k = vinc_ptr[v]; k < vinc_ptr[v + 1]; ++k) {
+      const int64_t e = vinc[k] >> 3;
+      const int la = vinc[k] & 7;
+#pragma unroll
+      for (int lb = 0; lb < 8; ++lb) {
+        const int32_t u = e2v[lb * E + e];
+        if (u >= nf) continue;
+        int lo = 0, hi = S.n - 1, pos = -1;
+        while (lo <= hi) {
+          const int mid = (lo + hi) >> 1;
+          const int32_t x = R[mid];
+          if (x == u) {
+            pos = mid;
+            break;
+          }
+          if (x < u)
+            lo = mid + 1;
+          else
+            hi = mid - 1;
+        }
+        if (pos < 0 || pos / TILE > a / TILE) continue;   // lower tiles only (diagonal tiles full)
+        *tile_elem(M, S.tile_off, a, pos) += Ae[sym8(la, lb) * E + e];
+      }
+    }
+  }
+}
+
+// Identity on the padding rows of each system (so padded systems stay SPD).
+__global__ void k_pad_identity(const AsmSys *__restrict__ sys, int nsys, double *__restrict__ M) {
+  const int s = blockIdx.x;
+  if (s >= nsys) return;
+  const AsmSys S = sys[s];
+  for (int i = S.n + threadIdx.x; i < S.nb * TILE; i += blockDim.x) *tile_elem(M, S.tile_off, i, i) = 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// Setup: reduced operator by cell assembly, eq. (Aij): for each occupied cell,
+// A_cell = sum over its elements of (J^e)^T A^e J^e, J^e[a][k] = Phi_k(xi_a) with
+// xi_a the local coordinates of element vertex a in the cell (zero rows at
+// Dirichlet vertices). One 64-thread workgroup per cell.
+// ---------------------------------------------------------------------------
+struct BoxDev {
+  double lo[3], H[3];
+  int32_t b[3], pad;
+};
+
+__global__ __launch_bounds__(64) void k_cell_mats(BoxDev box, const int32_t *__restrict__ occ_cells,
+                                                  const int32_t *__restrict__ occ_ptr, const int32_t *__restrict__ occ_elems,
+                                                  const int32_t *__restrict__ e2v, int64_t E, int64_t NV, int64_t nf,
+                                                  const double *__restrict__ xyz, const double *__restrict__ Ae,
+                                                  double *__restrict__ cellmat) {
+  __shared__ double Je[8][8], T1[8][8];
+  const int o = blockIdx.x;
+  const int c = occ_cells[o];
+  const int c3[3] = {c % box.b[0], (c / box.b[0]) % box.b[1], c / (box.b[0] * box.b[1])};
+  const int t = threadIdx.x, ta = t >> 3, tk = t & 7;
+  double acc = 0.0;
+  for (int k = occ_ptr[o]; k < occ_ptr[o + 1]; ++k) {
+    const int64_t e = occ_elems[k];
+    {
+      const int32_t u = e2v[ta * E + e];
+      double w = 0.0;
+      if (u < nf) {
+        double xi[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) xi[d] = ((xyz[d * NV + u] - box.lo[d]) - (double)c3[d] * box.H[d]) / box.H[d];
+        w = trilin<double>(tk, xi[0], xi[1], xi[2]);
+      }
+      Je[ta][tk] = w;
+    }
+    __syncthreads();
+    {  // T1 = A^e J^e : thread (a, l)
+      double s = 0.0;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) s += Ae[sym8(ta, b) * E + e] * Je[b][tk];
+      T1[ta][tk] = s;
+    }
+    __syncthreads();
+    {  // (J^e)^T T1 : thread (k, l) = (ta, tk)
+      double s = 0.0;
+#pragma unroll
+      for (int a = 0; a < 8; ++a) s += Je[a][ta] * T1[a][tk];
+      acc += s;
+    }
+    __syncthreads();
+  }
+  cellmat[(int64_t)o * 64 + t] = acc;
+}
+
+// Dense A_r from the cell matrices: row K sums, over the occupied cells around
+// box vertex K, that cell's row for K restricted to active corners.
+__global__ __launch_bounds__(256) void k_assemble_reduced(int64_t nr, const int32_t *__restrict__ ar_ptr,
+                                                          const int32_t *__restrict__ ar_src,
+                                                          const int32_t *__restrict__ corner_act,
+                                                          const double *__restrict__ cellmat, double *__restrict__ M) {
+  const int64_t K = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (K >= nr) return;
+  for (int k = ar_ptr[K]; k < ar_ptr[K + 1]; ++k) {
+    const int o = ar_src[k] >> 3, q = ar_src[k] & 7;
+#pragma unroll
+    for (int l = 0; l < 8; ++l) {
+      const int32_t L = corner_act[8 * o + l];
+      if (L < 0 || L / TILE > K / TILE) continue;
+      *tile_elem(M, 0, (int)K, L) += cellmat[(int64_t)o * 64 + q * 8 + l];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Setup: batched inverse of SPD systems by the symmetric block sweep (block
+// Gauss-Jordan). Sweeping pivot block k of the current matrix M:
+//   D = M_kk^{-1};  M_OO -= M_Ok D M_kO;  M_Ok <- M_Ok D;  M_kO <- D M_kO;
+//   M_kk <- -D.
+// After every block is swept, M = -A^{-1}. Only lower tiles are stored; the
+// step is split into: pivot-block inverse, panel (P_I = M_Ik, G_I = P_I D), and
+// the tile update. A non-positive pivot flags the system as not SPD.
+// ---------------------------------------------------------------------------
+struct SweepSys {
+  int64_t tile_off;   // scratch tiles
+  int64_t pan_off;    // panel slots (nb per system)
+  int32_t nb, pad;
+};
+
+__device__ __forceinline__ double *tile_ptr(double *M, int64_t toff, int I, int J) {
+  return M + (toff + (int64_t)I * (I + 1) / 2 + J) * (TILE * TILE);
+}
+
+__global__ __launch_bounds__(256) void k_sweep_pivot(int k, const SweepSys *__restrict__ sys, double *__restrict__ M,
+                                                     double *__restrict__ Dinv, int *__restrict__ status) {
+  __shared__ double D[TILE][TILE + 1];
+  __shared__ double col[TILE];
+  __shared__ int bad;
+  const SweepSys S = sys[blockIdx.x];
+  if (k >= S.nb) return;
+  const double *Mk = tile_ptr(M, S.tile_off, k, k);
+  if (threadIdx.x == 0) bad = 0;
+  for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) D[t / TILE][t % TILE] = Mk[t];
+  __syncthreads();
+  for (int j = 0; j < TILE; ++j) {
+    const double piv = D[j][j];
+    if (threadIdx.x < TILE) col[threadIdx.x] = D[threadIdx.x][j];
+    if (threadIdx.x == 0 && (!(piv > 0.0) || !isfinite(piv))) bad = 1;
+    __syncthreads();
+    if (threadIdx.x < TILE) {
+      const double v = (threadIdx.x == j) ? 1.0 : D[j][threadIdx.x];
+      D[j][threadIdx.x] = v / piv;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) {
+      const int i = t / TILE, c = t % TILE;
+      if (i == j) continue;
+      const double old = (c == j) ? 0.0 : D[i][c];
+      D[i][c] = old - col[i] * D[j][c];
+    }
+    __syncthreads();
+  }
+  double *out = Dinv + (int64_t)blockIdx.x * TILE * TILE;
+  for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) out[t] = D[t / TILE][t % TILE];
+  if (threadIdx.x == 0 && bad) status[blockIdx.x] = 1;
+}
+
+// grid: (system, I); P_I = M_Ik (transpose of tile (k, I) when I < k), G_I = P_I Dinv
+__global__ __launch_bounds__(256) void k_sweep_panel(int k, const SweepSys *__restrict__ sys, const double *__restrict__ M,
+                                                     const double *__restrict__ Dinv, double *__restrict__ Pbuf,
+                                                     double *__restrict__ Gbuf) {
+  __shared__ double P[TILE][TILE + 1];
+  __shared__ double Dl[TILE][TILE + 1];
+  const SweepSys S = sys[blockIdx.x];
+  const int I = blockIdx.y;
+  if (k >= S.nb || I >= S.nb || I == k) return;
+  const double *src = (I > k) ? tile_ptr((double *)M, S.tile_off, I, k) : tile_ptr((double *)M, S.tile_off, k, I);
+  const double *dv = Dinv + (int64_t)blockIdx.x * TILE * TILE;
+  for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) {
+    const int i = t / TILE, j = t % TILE;
+    if (I > k)
+      P[i][j] = src[t];
+    else
+      P[j][i] = src[t];
+    Dl[i][j] = dv[t];
+  }
+  __syncthreads();
+  double *po = Pbuf + (S.pan_off + I) * (TILE * TILE);
+  double *go = Gbuf + (S.pan_off + I) * (TILE * TILE);
+  for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) {
+    const int i = t / TILE, j = t % TILE;
+    double s = 0.0;
+#pragma unroll 8
+    for (int m = 0; m < TILE; ++m) s += P[i][m] * Dl[m][j];
+    po[t] = P[i][j];
+    go[t] = s;
+  }
+}
+
+// grid: (system, tile) over the lower tiles
+__global__ __launch_bounds__(256) void k_sweep_update(int k, const SweepSys *__restrict__ sys, const int32_t *__restrict__ tsys,
+                                                      const int16_t *__restrict__ tI, const int16_t *__restrict__ tJ,
+                                                      double *__restrict__ M, const double *__restrict__ Dinv,
+                                                      const double *__restrict__ Pbuf, const double *__restrict__ Gbuf) {
+  __shared__ double G[TILE][TILE + 1];
+  __shared__ double PT[TILE][TILE + 1];
+  const int t0 = blockIdx.x;
+  const int s = tsys[t0];
+  const SweepSys S = sys[s];
+  if (k >= S.nb) return;
+  const int I = tI[t0], J = tJ[t0];
+  double *Mt = tile_ptr(M, S.tile_off, I, J);
+  if (I == k && J == k) {
+    const double *dv = Dinv + (int64_t)s * TILE * TILE;
+    for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) Mt[t] = -dv[t];
+    return;
+  }
+  if (J == k) {  // I > k: M_Ik <- G_I
+    const double *g = Gbuf + (S.pan_off + I) * (TILE * TILE);
+    for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) Mt[t] = g[t];
+    return;
+  }
+  if (I == k) {  // J < k: M_kJ <- G_J^T
+    const double *g = Gbuf + (S.pan_off + J) * (TILE * TILE);
+    for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) Mt[t] = g[(t % TILE) * TILE + t / TILE];
+    return;
+  }
+  const double *g = Gbuf + (S.pan_off + I) * (TILE * TILE);
+  const double *p = Pbuf + (S.pan_off + J) * (TILE * TILE);
+  for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) {
+    const int i = t / TILE, j = t % TILE;
+    G[i][j] = g[t];
+    PT[j][i] = p[t];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) {
+    const int i = t / TILE, j = t % TILE;
+    double s2 = 0.0;
+#pragma unroll 8
+    for (int m = 0; m < TILE; ++m) s2 += G[i][m] * PT[m][j];
+    Mt[t] -= s2;
+  }
+}
+
+// -M -> output tiles (symmetrised diagonal tiles), converted to T.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sweep_pack(const SweepSys *__restrict__ sys, const int32_t *__restrict__ tsys,
+                                                    const int16_t *__restrict__ tI, const int16_t *__restrict__ tJ,
+                                                    const int64_t *__restrict__ out_off, const double *__restrict__ M,
+                                                    T *__restrict__ out) {
+  const int t0 = blockIdx.x;
+  const int s = tsys[t0];
+  const SweepSys S = sys[s];
+  const int I = tI[t0], J = tJ[t0];
+  const double *Mt = tile_ptr((double *)M, S.tile_off, I, J);
+  T *o = out + (out_off[s] + (int64_t)I * (I + 1) / 2 + J) * (TILE * TILE);
+  for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) {
+    const int i = t / TILE, j = t % TILE;
+    double v = -Mt[t];
+    if (I == J) v = -0.5 * (Mt[t] + Mt[j * TILE + i]);
+    o[t] = (T)v;
+  }
+}
+
+template <typename T>
+__global__ void k_convert(int64_t n, const double *__restrict__ in, T *__restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (T)in[i];
+}
+
+// explicit instantiations used by the host code
+template __global__ void k_gather<double>(int64_t, const int *, const int32_t *, const double *, double *);
+template __global__ void k_gather<float>(int64_t, const int *, const int32_t *, const double *, float *);
+template __global__ void k_jt_tasks<double>(int, const int *, const int32_t *, const int32_t *, const double *,
+                                            const double *, int64_t, const double *, double *);
+template __global__ void k_jt_tasks<float>(int, const int *, const int32_t *, const int32_t *, const float *,
+                                           const float *, int64_t, const double *, float *);
+template __global__ void k_jt_corners<double>(int64_t, const int *, const int32_t *, const int32_t *, const double *,
+                                              double *);
+template __global__ void k_jt_corners<float>(int64_t, const int *, const int32_t *, const int32_t *, const float *,
+                                             float *);
+template __global__ void k_combine<double>(const Seg *, int, int, const int *);
+template __global__ void k_combine<float>(const Seg *, int, int, const int *);
+template __global__ void k_final<double>(int64_t, const int *, const double *, const int32_t *, const int32_t *,
+                                         const double *, const int32_t *, const int32_t *, const double *,
+                                         const double *, int64_t, const int32_t *, const double *, double *,
+                                         const double *, double *, double *);
+template __global__ void k_final<float>(int64_t, const int *, const double *, const int32_t *, const int32_t *,
+                                        const double *, const int32_t *, const int32_t *, const float *,
+                                        const float *, int64_t, const int32_t *, const double *, double *,
+                                        const double *, double *, double *);
+template __global__ void k_sweep_pack<double>(const SweepSys *, const int32_t *, const int16_t *, const int16_t *,
+                                              const int64_t *, const double *, double *);
+template __global__ void k_sweep_pack<float>(const SweepSys *, const int32_t *, const int16_t *, const int16_t *,
+                                             const int64_t *, const double *, float *);
+template __global__ void k_convert<float>(int64_t, const double *, float *);
+template __global__ void k_convert<double>(int64_t, const double *, double *);
+
+}  // namespace coarse

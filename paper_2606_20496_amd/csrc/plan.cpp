@@ -1,0 +1,604 @@
+// Host-side combinatorial setup of the coarse solver (see plan.h).
+//
+// Follows the paper's problem statement and method:
+//   Sec. 3  element-vertex connectivity, homogeneous Dirichlet vertices removed,
+//           overlapping subdomains (layers of vertex-sharing elements) and R_p
+//           on the vertices interior to each overlapping subdomain;
+//   Sec. 4  bounding box cut into boxes, elements assigned to the cell of their
+//           centroid, the averaged interpolation J = W Q^T J_L S, compression of
+//           box vertices whose column of J is zero.
+#include "plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+namespace coarse {
+
+namespace {
+
+uint64_t spread3(uint64_t x) {
+  x &= 0x1fffff;
+  x = (x | (x << 32)) & 0x1f00000000ffffULL;
+  x = (x | (x << 16)) & 0x1f0000ff0000ffULL;
+  x = (x | (x << 8)) & 0x100f00f00f00f00fULL;
+  x = (x | (x << 4)) & 0x10c30c30c30c30c3ULL;
+  x = (x | (x << 2)) & 0x1249249249249249ULL;
+  return x;
+}
+
+// Element centroid: the plain mean of the 8 vertices, summed in local order.
+inline void centroid(const double *xyz, const int32_t *ev, double c[3]) {
+  for (int d = 0; d < 3; ++d) {
+    double s = xyz[3 * (int64_t)ev[0] + d];
+    for (int v = 1; v < 8; ++v) s = s + xyz[3 * (int64_t)ev[v] + d];
+    c[d] = s / 8.0;
+  }
+}
+
+// Recursive coordinate bisection of element centroids into n pieces.
+void rcb(std::vector<int32_t> &idx, int64_t lo, int64_t hi, int32_t label0, int32_t n,
+         const std::vector<double> &cen, std::vector<int32_t> &part) {
+  if (n <= 1 || hi - lo <= 1) {
+    for (int64_t i = lo; i < hi; ++i) part[idx[i]] = label0;
+    return;
+  }
+  double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+  for (int64_t i = lo; i < hi; ++i)
+    for (int d = 0; d < 3; ++d) {
+      mn[d] = std::min(mn[d], cen[3 * (int64_t)idx[i] + d]);
+      mx[d] = std::max(mx[d], cen[3 * (int64_t)idx[i] + d]);
+    }
+  int ax = 0;
+  for (int d = 1; d < 3; ++d)
+    if (mx[d] - mn[d] > mx[ax] - mn[ax]) ax = d;
+  int32_t nl = n / 2;
+  int64_t mid = lo + (hi - lo) * nl / n;
+  std::nth_element(idx.begin() + lo, idx.begin() + mid, idx.begin() + hi, [&](int32_t a, int32_t b) {
+    double ca = cen[3 * (int64_t)a + ax], cb = cen[3 * (int64_t)b + ax];
+    return ca < cb || (ca == cb && a < b);
+  });
+  rcb(idx, lo, mid, label0, nl, cen, part);
+  rcb(idx, mid, hi, label0 + nl, n - nl, cen, part);
+}
+
+// Trilinear weight of corner k = kx + 2ky + 4kz at local coordinates xi.
+inline double phi(int k, const double xi[3]) {
+  double fx = (k & 1) ? xi[0] : 1.0 - xi[0];
+  double fy = (k & 2) ? xi[1] : 1.0 - xi[1];
+  double fz = (k & 4) ? xi[2] : 1.0 - xi[2];
+  return fx * fy * fz;
+}
+
+}  // namespace
+
+int build_plan(const PlanInput &in, Plan &P) {
+  const int64_t NV = in.n_vert, NE = in.n_elem;
+  if (NV <= 0 || NE <= 0 || !in.xyz || !in.e2v || !in.dirichlet) {
+    P.err = "empty mesh or null array";
+    return -1;
+  }
+  if (NV >= (int64_t(1) << 31) || NE >= (int64_t(1) << 31) / 8) {
+    P.err = "mesh too large for 32-bit indices";
+    return -1;
+  }
+  if (in.overlap < 1 || in.n_part < 1) {
+    P.err = "overlap and n_part must be >= 1";
+    return -1;
+  }
+  if (in.interp != 0 && in.interp != 1) {
+    P.err = "unknown interpolation scheme";
+    return -1;
+  }
+  P.n_vert = NV;
+  P.n_elem = NE;
+  for (int64_t e = 0; e < NE; ++e) {
+    const int32_t *ev = in.e2v + 8 * e;
+    for (int v = 0; v < 8; ++v) {
+      if (ev[v] < 0 || ev[v] >= NV) {
+        P.err = "e2v entry out of range at element " + std::to_string(e);
+        return -1;
+      }
+      for (int w = 0; w < v; ++w)
+        if (ev[w] == ev[v]) {
+          P.err = "vertex repeated within element " + std::to_string(e);
+          return -3;
+        }
+    }
+  }
+  for (int64_t u = 0; u < 3 * NV; ++u)
+    if (!std::isfinite(in.xyz[u])) {
+      P.err = "non-finite vertex coordinate";
+      return -1;
+    }
+
+  // ---- partition labels -------------------------------------------------------
+  std::vector<double> cen(3 * NE);
+  for (int64_t e = 0; e < NE; ++e) centroid(in.xyz, in.e2v + 8 * e, &cen[3 * e]);
+  std::vector<int32_t> part(NE);
+  P.n_part = in.n_part;
+  if (in.part) {
+    for (int64_t e = 0; e < NE; ++e) {
+      if (in.part[e] < 0 || in.part[e] >= in.n_part) {
+        P.err = "part label out of range at element " + std::to_string(e);
+        return -1;
+      }
+      part[e] = in.part[e];
+    }
+  } else {
+    std::vector<int32_t> idx(NE);
+    std::iota(idx.begin(), idx.end(), 0);
+    rcb(idx, 0, NE, 0, in.n_part, cen, part);
+  }
+
+  // ---- bounding box of all vertices (Sec. 4) ----------------------------------
+  for (int d = 0; d < 3; ++d) {
+    P.lo[d] = 1e300;
+    P.hi[d] = -1e300;
+  }
+  for (int64_t u = 0; u < NV; ++u)
+    for (int d = 0; d < 3; ++d) {
+      P.lo[d] = std::min(P.lo[d], in.xyz[3 * u + d]);
+      P.hi[d] = std::max(P.hi[d], in.xyz[3 * u + d]);
+    }
+
+  // ---- element order: (subdomain, Morton code of centroid) --------------------
+  {
+    std::vector<uint64_t> key(NE);
+    for (int64_t e = 0; e < NE; ++e) {
+      uint64_t q[3];
+      for (int d = 0; d < 3; ++d) {
+        double ext = P.hi[d] - P.lo[d];
+        double t = ext > 0 ? (cen[3 * e + d] - P.lo[d]) / ext : 0.0;
+        t = std::min(std::max(t, 0.0), 1.0);
+        q[d] = (uint64_t)(t * 2097151.0);
+      }
+      key[e] = spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2);
+    }
+    P.elem_user.resize(NE);
+    std::iota(P.elem_user.begin(), P.elem_user.end(), 0);
+    std::sort(P.elem_user.begin(), P.elem_user.end(), [&](int32_t a, int32_t b) {
+      if (part[a] != part[b]) return part[a] < part[b];
+      if (key[a] != key[b]) return key[a] < key[b];
+      return a < b;
+    });
+  }
+
+  // ---- vertex numbering: free vertices first, by first touch -------------------
+  P.vint_of_user.assign(NV, -1);
+  int64_t nf = 0;
+  for (int64_t ei = 0; ei < NE; ++ei) {
+    const int32_t *ev = in.e2v + 8 * (int64_t)P.elem_user[ei];
+    for (int v = 0; v < 8; ++v)
+      if (!in.dirichlet[ev[v]] && P.vint_of_user[ev[v]] < 0) P.vint_of_user[ev[v]] = (int32_t)nf++;
+  }
+  for (int64_t u = 0; u < NV; ++u)
+    if (!in.dirichlet[u] && P.vint_of_user[u] < 0) {
+      P.err = "free vertex " + std::to_string(u) + " belongs to no element";
+      return -1;
+    }
+  P.n_free = nf;
+  int64_t nd = nf;
+  for (int64_t ei = 0; ei < NE; ++ei) {
+    const int32_t *ev = in.e2v + 8 * (int64_t)P.elem_user[ei];
+    for (int v = 0; v < 8; ++v)
+      if (P.vint_of_user[ev[v]] < 0) P.vint_of_user[ev[v]] = (int32_t)nd++;
+  }
+  // unused Dirichlet vertices get the remaining ids
+  for (int64_t u = 0; u < NV; ++u)
+    if (P.vint_of_user[u] < 0) P.vint_of_user[u] = (int32_t)nd++;
+  if (nf == 0) {
+    P.err = "no free vertices";
+    return -1;
+  }
+  P.user_of_vint.assign(NV, 0);
+  for (int64_t u = 0; u < NV; ++u) P.user_of_vint[P.vint_of_user[u]] = (int32_t)u;
+  P.xyz.resize(3 * NV);
+  for (int64_t u = 0; u < NV; ++u)
+    for (int d = 0; d < 3; ++d) P.xyz[d * NV + P.vint_of_user[u]] = in.xyz[3 * u + d];
+  P.e2v.resize(8 * NE);
+  std::vector<int32_t> part_int(NE);
+  for (int64_t ei = 0; ei < NE; ++ei) {
+    const int32_t *ev = in.e2v + 8 * (int64_t)P.elem_user[ei];
+    for (int v = 0; v < 8; ++v) P.e2v[v * NE + ei] = P.vint_of_user[ev[v]];
+    part_int[ei] = part[P.elem_user[ei]];
+  }
+  auto E2V = [&](int64_t e, int v) { return P.e2v[v * NE + e]; };
+
+  // ---- multiplicity and vertex -> element incidence (all vertices) ------------
+  P.mult.assign(NV, 0);
+  for (int64_t e = 0; e < NE; ++e)
+    for (int v = 0; v < 8; ++v) P.mult[E2V(e, v)]++;
+  std::vector<int32_t> inc_ptr(NV + 1, 0), inc(8 * NE);
+  for (int64_t u = 0; u < NV; ++u) inc_ptr[u + 1] = inc_ptr[u] + P.mult[u];
+  {
+    std::vector<int32_t> fill(inc_ptr.begin(), inc_ptr.end() - 1);
+    for (int64_t e = 0; e < NE; ++e)
+      for (int v = 0; v < 8; ++v) inc[fill[E2V(e, v)]++] = (int32_t)(e * 8 + v);
+  }
+  P.vinc_ptr.assign(inc_ptr.begin(), inc_ptr.begin() + nf + 1);
+  P.vinc.assign(inc.begin(), inc.begin() + inc_ptr[nf]);
+
+  // ---- operator blocks ---------------------------------------------------------
+  {
+    const int64_t nb = (NE + OP_BLOCK - 1) / OP_BLOCK;
+    P.n_blocks = nb;
+    P.blk_slot_ptr.assign(1, 0);
+    P.lconn.assign(8 * NE, 0xFFFF);
+    std::vector<int32_t> slot_of(NV, -1), cnt(NV, 0);
+    std::vector<int64_t> shared_blocks;  // (slot global index) of shared slots
+    std::vector<int32_t> slot_block;
+    for (int64_t blk = 0; blk < nb; ++blk) {
+      const int64_t e0 = blk * OP_BLOCK, e1 = std::min<int64_t>(NE, e0 + OP_BLOCK);
+      std::vector<int32_t> verts;
+      for (int64_t e = e0; e < e1; ++e)
+        for (int v = 0; v < 8; ++v) {
+          int32_t u = E2V(e, v);
+          if (u >= nf) continue;
+          if (cnt[u] == 0) verts.push_back(u);
+          cnt[u]++;
+        }
+      std::sort(verts.begin(), verts.end());
+      const int32_t s0 = P.blk_slot_ptr.back();
+      for (size_t s = 0; s < verts.size(); ++s) slot_of[verts[s]] = (int32_t)s;
+      // incidence lists per slot (element order, then local vertex order)
+      std::vector<std::vector<uint16_t>> lists(verts.size());
+      for (int64_t e = e0; e < e1; ++e)
+        for (int v = 0; v < 8; ++v) {
+          int32_t u = E2V(e, v);
+          if (u >= nf) continue;
+          P.lconn[v * NE + e] = (uint16_t)slot_of[u];
+          lists[slot_of[u]].push_back((uint16_t)((e - e0) * 8 + v));
+        }
+      for (size_t s = 0; s < verts.size(); ++s) {
+        int32_t u = verts[s];
+        P.slot_vid.push_back(u);
+        if (P.slot_inc_ptr.empty()) P.slot_inc_ptr.push_back(0);
+        for (auto x : lists[s]) P.slot_inc.push_back(x);
+        P.slot_inc_ptr.push_back((int32_t)P.slot_inc.size());
+        if (cnt[u] == P.mult[u]) {
+          P.slot_dst.push_back(u);
+        } else {
+          P.slot_dst.push_back(-1);  // patched below
+          shared_blocks.push_back(s0 + (int64_t)s);
+        }
+        cnt[u] = 0;
+        slot_of[u] = -1;
+      }
+      P.blk_slot_ptr.push_back(s0 + (int32_t)verts.size());
+      P.max_slots = std::max<int64_t>(P.max_slots, (int64_t)verts.size());
+    }
+    if (P.slot_inc_ptr.empty()) P.slot_inc_ptr.push_back(0);
+    // partial ids in slot order (block order); per shared vertex list them
+    P.n_partials = (int64_t)shared_blocks.size();
+    std::vector<int32_t> sh_index(NV, -1);
+    std::vector<std::vector<int32_t>> per_vertex;
+    for (int64_t k = 0; k < P.n_partials; ++k) {
+      int64_t gs = shared_blocks[k];
+      P.slot_dst[gs] = -(int32_t)(k + 1);
+      int32_t u = P.slot_vid[gs];
+      if (sh_index[u] < 0) {
+        sh_index[u] = (int32_t)per_vertex.size();
+        per_vertex.emplace_back();
+        P.sh_vid.push_back(u);
+      }
+      per_vertex[sh_index[u]].push_back((int32_t)k);
+    }
+    P.sh_ptr.assign(1, 0);
+    for (auto &l : per_vertex) {
+      for (auto k : l) P.sh_part.push_back(k);
+      P.sh_ptr.push_back((int32_t)P.sh_part.size());
+    }
+  }
+
+  // ---- overlapping subdomains and R_p (Sec. 3) --------------------------------
+  {
+    std::vector<int64_t> pstart(in.n_part + 1, 0);
+    for (int64_t e = 0; e < NE; ++e) pstart[part_int[e] + 1]++;
+    for (int p = 0; p < in.n_part; ++p) pstart[p + 1] += pstart[p];
+    std::vector<int32_t> emark(NE, -1), vmark(NV, -1);
+    P.R.assign(in.n_part, {});
+    std::vector<int32_t> cur, nxt;
+    for (int32_t p = 0; p < in.n_part; ++p) {
+      cur.clear();
+      for (int64_t e = pstart[p]; e < pstart[p + 1]; ++e) {
+        cur.push_back((int32_t)e);
+        emark[e] = p;
+      }
+      std::vector<int32_t> all = cur;
+      for (int layer = 0; layer < in.overlap; ++layer) {
+        nxt.clear();
+        for (int32_t e : all)
+          for (int v = 0; v < 8; ++v) {
+            int32_t u = E2V(e, v);
+            for (int32_t k = inc_ptr[u]; k < inc_ptr[u + 1]; ++k) {
+              int32_t f = inc[k] >> 3;
+              if (emark[f] != p) {
+                emark[f] = p;
+                nxt.push_back(f);
+              }
+            }
+          }
+        all.insert(all.end(), nxt.begin(), nxt.end());
+      }
+      std::vector<int32_t> &R = P.R[p];
+      for (int32_t e : all)
+        for (int v = 0; v < 8; ++v) {
+          int32_t u = E2V(e, v);
+          if (u >= nf || vmark[u] == p) continue;
+          vmark[u] = p;
+          bool inside = true;
+          for (int32_t k = inc_ptr[u]; k < inc_ptr[u + 1] && inside; ++k)
+            if (emark[inc[k] >> 3] != p) inside = false;
+          if (inside) R.push_back(u);
+        }
+      std::sort(R.begin(), R.end());
+    }
+  }
+
+  // ---- box grid and element cells (Sec. 4) ------------------------------------
+  int32_t bauto = (int32_t)std::ceil(std::cbrt((double)in.n_part) - 1e-9);
+  for (int d = 0; d < 3; ++d) {
+    P.b[d] = in.boxes[d] > 0 ? in.boxes[d] : std::max(1, bauto);
+    P.H[d] = (P.hi[d] - P.lo[d]) / (double)P.b[d];
+    if (!(P.H[d] > 0)) {
+      P.err = "degenerate bounding box";
+      return -1;
+    }
+  }
+  const int64_t bx1 = P.b[0] + 1, by1 = P.b[1] + 1, bz1 = P.b[2] + 1;
+  P.n_bv = bx1 * by1 * bz1;
+  const int64_t ncell = (int64_t)P.b[0] * P.b[1] * P.b[2];
+  auto cell_of = [&](const double x[3], int32_t c3[3]) {
+    for (int d = 0; d < 3; ++d) {
+      double t = std::floor((x[d] - P.lo[d]) / P.H[d]);
+      int64_t c = (int64_t)t;
+      if (t < 0) c = 0;
+      if (t > P.b[d] - 1) c = P.b[d] - 1;
+      c3[d] = (int32_t)c;
+    }
+  };
+  auto corner_bv = [&](const int32_t c3[3], int k) -> int64_t {
+    return (c3[0] + (k & 1)) + bx1 * ((c3[1] + ((k >> 1) & 1)) + by1 * (c3[2] + ((k >> 2) & 1)));
+  };
+  auto cell_id = [&](const int32_t c3[3]) -> int64_t { return c3[0] + (int64_t)P.b[0] * (c3[1] + (int64_t)P.b[1] * c3[2]); };
+  auto cell_xyz = [&](int64_t c, int32_t c3[3]) {
+    c3[0] = (int32_t)(c % P.b[0]);
+    c3[1] = (int32_t)((c / P.b[0]) % P.b[1]);
+    c3[2] = (int32_t)(c / ((int64_t)P.b[0] * P.b[1]));
+  };
+  auto local_xi = [&](const double x[3], const int32_t c3[3], double xi[3]) {
+    for (int d = 0; d < 3; ++d) xi[d] = ((x[d] - P.lo[d]) - (double)c3[d] * P.H[d]) / P.H[d];
+  };
+
+  P.elem_cell.resize(NE);
+  for (int64_t e = 0; e < NE; ++e) {
+    int32_t ev[8];
+    for (int v = 0; v < 8; ++v) ev[v] = P.user_of_vint[E2V(e, v)];
+    double c[3];
+    centroid(in.xyz, ev, c);
+    int32_t c3[3];
+    cell_of(c, c3);
+    P.elem_cell[e] = (int32_t)cell_id(c3);
+  }
+
+  // vertex-major entries: (free vertex, cell) with weight fraction n_ic / m_i
+  std::vector<int32_t> ent_cell;  // cell id of each entry
+  P.jv_ptr.assign(1, 0);
+  {
+    std::vector<int32_t> cells;
+    for (int64_t i = 0; i < nf; ++i) {
+      const int32_t u = P.user_of_vint[i];
+      const double x[3] = {in.xyz[3 * (int64_t)u], in.xyz[3 * (int64_t)u + 1], in.xyz[3 * (int64_t)u + 2]};
+      if (in.interp == 0) {
+        cells.clear();
+        for (int32_t k = inc_ptr[i]; k < inc_ptr[i + 1]; ++k) cells.push_back(P.elem_cell[inc[k] >> 3]);
+        std::sort(cells.begin(), cells.end());
+        for (size_t a = 0; a < cells.size();) {
+          size_t b2 = a;
+          while (b2 < cells.size() && cells[b2] == cells[a]) ++b2;
+          int32_t c3[3];
+          cell_xyz(cells[a], c3);
+          double xi[3];
+          local_xi(x, c3, xi);
+          ent_cell.push_back(cells[a]);
+          P.jv_w.push_back((double)(b2 - a) / (double)P.mult[i]);
+          for (int d = 0; d < 3; ++d) P.jv_xi.push_back(xi[d]);
+          a = b2;
+        }
+      } else {
+        int32_t c3[3];
+        cell_of(x, c3);
+        double xi[3];
+        local_xi(x, c3, xi);
+        ent_cell.push_back((int32_t)cell_id(c3));
+        P.jv_w.push_back(1.0);
+        for (int d = 0; d < 3; ++d) P.jv_xi.push_back(xi[d]);
+      }
+      P.jv_ptr.push_back((int32_t)ent_cell.size());
+    }
+  }
+  const int64_t nent = (int64_t)ent_cell.size();
+
+  // occupied cells: cells owning an element (centroid scheme) or an entry
+  P.cell_occ.assign(ncell, -1);
+  {
+    std::vector<char> occ(ncell, 0);
+    for (int64_t e = 0; e < NE; ++e) occ[P.elem_cell[e]] = 1;
+    for (int64_t k = 0; k < nent; ++k) occ[ent_cell[k]] = 1;
+    for (int64_t c = 0; c < ncell; ++c)
+      if (occ[c]) {
+        P.cell_occ[c] = (int32_t)P.occ_cells.size();
+        P.occ_cells.push_back((int32_t)c);
+      }
+  }
+  const int64_t nocc = (int64_t)P.occ_cells.size();
+  P.occ_elem_ptr.assign(nocc + 1, 0);
+  for (int64_t e = 0; e < NE; ++e) P.occ_elem_ptr[P.cell_occ[P.elem_cell[e]] + 1]++;
+  for (int64_t o = 0; o < nocc; ++o) P.occ_elem_ptr[o + 1] += P.occ_elem_ptr[o];
+  P.occ_elems.resize(NE);
+  {
+    std::vector<int32_t> fill(P.occ_elem_ptr.begin(), P.occ_elem_ptr.end() - 1);
+    for (int64_t e = 0; e < NE; ++e) P.occ_elems[fill[P.cell_occ[P.elem_cell[e]]]++] = (int32_t)e;
+  }
+
+  // compression: a box vertex is kept when some entry gives it a nonzero weight
+  P.bv_act.assign(P.n_bv, -1);
+  {
+    std::vector<char> act(P.n_bv, 0);
+    for (int64_t k = 0; k < nent; ++k) {
+      int32_t c3[3];
+      cell_xyz(ent_cell[k], c3);
+      const double xi[3] = {P.jv_xi[3 * k], P.jv_xi[3 * k + 1], P.jv_xi[3 * k + 2]};
+      for (int q = 0; q < 8; ++q)
+        if (phi(q, xi) != 0.0) act[corner_bv(c3, q)] = 1;
+    }
+    for (int64_t g = 0; g < P.n_bv; ++g)
+      if (act[g]) {
+        P.bv_act[g] = (int32_t)P.act_bv.size();
+        P.act_bv.push_back((int32_t)g);
+      }
+  }
+  P.n_r = (int64_t)P.act_bv.size();
+  if (P.n_r == 0) {
+    P.err = "reduced space is empty";
+    return -4;
+  }
+  P.occ_corner_act.resize(8 * nocc);
+  for (int64_t o = 0; o < nocc; ++o) {
+    int32_t c3[3];
+    cell_xyz(P.occ_cells[o], c3);
+    for (int q = 0; q < 8; ++q) P.occ_corner_act[8 * o + q] = P.bv_act[corner_bv(c3, q)];
+  }
+  P.jv_occ.resize(nent);
+  for (int64_t k = 0; k < nent; ++k) P.jv_occ[k] = P.cell_occ[ent_cell[k]];
+
+  // cell-major copy of the entries, cut into restriction tasks
+  {
+    std::vector<int32_t> ent_vid(nent);
+    for (int64_t i = 0; i < nf; ++i)
+      for (int32_t k = P.jv_ptr[i]; k < P.jv_ptr[i + 1]; ++k) ent_vid[k] = (int32_t)i;
+    std::vector<int32_t> order(nent);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return P.jv_occ[a] < P.jv_occ[b]; });
+    P.jc_vid.resize(nent);
+    P.jc_w.resize(nent);
+    P.jc_xi.resize(3 * nent);
+    for (int64_t j = 0; j < nent; ++j) {
+      int32_t k = order[j];
+      P.jc_vid[j] = ent_vid[k];
+      P.jc_w[j] = P.jv_w[k];
+      for (int d = 0; d < 3; ++d) P.jc_xi[d * nent + j] = P.jv_xi[3 * (int64_t)k + d];
+    }
+    // vertex-major xi to SoA as well
+    std::vector<double> soa(3 * nent);
+    for (int64_t k = 0; k < nent; ++k)
+      for (int d = 0; d < 3; ++d) soa[d * nent + k] = P.jv_xi[3 * k + d];
+    P.jv_xi.swap(soa);
+    P.jt_task_start.assign(1, 0);
+    std::vector<std::vector<int32_t>> occ_tasks(nocc);
+    int64_t j = 0;
+    while (j < nent) {
+      int32_t o = P.jv_occ[order[j]];
+      int64_t j1 = j;
+      while (j1 < nent && P.jv_occ[order[j1]] == o) ++j1;
+      for (int64_t s = j; s < j1; s += JT_CHUNK) {
+        occ_tasks[o].push_back((int32_t)P.jt_task_occ.size());
+        P.jt_task_occ.push_back(o);
+        P.jt_task_start.push_back((int32_t)std::min<int64_t>(j1, s + JT_CHUNK));
+      }
+      j = j1;
+    }
+    // per active box vertex: (task, corner) sources in fixed cell order
+    P.jr_ptr.assign(1, 0);
+    P.ar_ptr.assign(1, 0);
+    for (int64_t K = 0; K < P.n_r; ++K) {
+      int64_t g = P.act_bv[K];
+      int32_t gx = (int32_t)(g % bx1), gy = (int32_t)((g / bx1) % by1), gz = (int32_t)(g / (bx1 * by1));
+      for (int dz = 1; dz >= 0; --dz)
+        for (int dy = 1; dy >= 0; --dy)
+          for (int dx = 1; dx >= 0; --dx) {
+            int32_t c3[3] = {gx - dx, gy - dy, gz - dz};
+            if (c3[0] < 0 || c3[1] < 0 || c3[2] < 0 || c3[0] >= P.b[0] || c3[1] >= P.b[1] || c3[2] >= P.b[2]) continue;
+            int32_t o = P.cell_occ[cell_id(c3)];
+            if (o < 0) continue;
+            int q = dx + 2 * dy + 4 * dz;
+            for (int32_t t : occ_tasks[o]) P.jr_src.push_back(t * 8 + q);
+            P.ar_src.push_back(o * 8 + q);
+          }
+      P.jr_ptr.push_back((int32_t)P.jr_src.size());
+      P.ar_ptr.push_back((int32_t)P.ar_src.size());
+    }
+  }
+
+  // ---- dense systems, packed vectors, tiles and GEMV items --------------------
+  {
+    int64_t voff = 0, toff = 0, roff = 0;
+    auto add_sys = [&](int64_t n) {
+      System s;
+      s.n = n;
+      s.nb = (n + TILE - 1) / TILE;
+      s.vec_off = voff;
+      s.tile_off = toff;
+      s.row_off = roff;
+      voff += s.nb * TILE;
+      toff += s.nb * (s.nb + 1) / 2;
+      roff += s.nb;
+      P.sys.push_back(s);
+    };
+    for (int32_t p = 0; p < in.n_part; ++p)
+      if (!P.R[p].empty()) {
+        add_sys((int64_t)P.R[p].size());
+        P.sub_of_sys.push_back(p);
+      }
+    P.n_local_sys = (int64_t)P.sys.size();
+    add_sys(P.n_r);
+    P.vec_len = voff;
+    P.n_tiles = toff;
+    P.n_rows = roff;
+    P.sub_idx.assign(voff, -1);
+    std::vector<int32_t> ccount(nf + 1, 0);
+    for (int64_t s = 0; s < P.n_local_sys; ++s) {
+      const auto &R = P.R[P.sub_of_sys[s]];
+      for (size_t a = 0; a < R.size(); ++a) {
+        P.sub_idx[P.sys[s].vec_off + a] = R[a];
+        ccount[R[a] + 1]++;
+      }
+    }
+    for (int64_t i = 0; i < nf; ++i) {
+      if (ccount[i + 1] == 0) {
+        P.err = "free vertex not covered by any subdomain";
+        return -1;
+      }
+      ccount[i + 1] += ccount[i];
+    }
+    P.cover_ptr = ccount;
+    P.cover_pos.resize(ccount[nf]);
+    std::vector<int32_t> fill(ccount.begin(), ccount.end() - 1);
+    for (int64_t s = 0; s < P.n_local_sys; ++s) {
+      const auto &R = P.R[P.sub_of_sys[s]];
+      for (size_t a = 0; a < R.size(); ++a) P.cover_pos[fill[R[a]]++] = (int32_t)(P.sys[s].vec_off + a);
+    }
+    for (int64_t s = 0; s < (int64_t)P.sys.size(); ++s) {
+      const System &S = P.sys[s];
+      for (int64_t I = 0; I < S.nb; ++I) {
+        P.row_item0.push_back((int32_t)P.items.size());
+        for (int64_t j0 = 0; j0 <= I; j0 += GEMV_SEG) {
+          GemvItem it;
+          it.sys = (int32_t)s;
+          it.I = (int32_t)I;
+          it.j0 = (int32_t)j0;
+          it.j1 = (int32_t)std::min<int64_t>(I + 1, j0 + GEMV_SEG);
+          P.items.push_back(it);
+        }
+        P.row_nitem.push_back((int32_t)(P.items.size() - P.row_item0.back()));
+        P.row_sys.push_back((int32_t)s);
+        P.row_I.push_back((int32_t)I);
+      }
+    }
+  }
+  return 0;
+}
+
+}  // namespace coarse

@@ -1,0 +1,218 @@
+"""GPU parity: the HIP path through the C-ABI against the FP64 oracle on the same
+seeded inputs. Bars: A apply 1e-13 and one preconditioner application 1e-12
+(relative, max norm) in FP64; PCG to 1e-8 with the same iteration count. Mixed
+precision: the same 1e-8 residual with at most 10% more iterations."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import pcg as opcg, precond as oprec, problem
+from paper_2606_20496_amd import coarse, meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _gpu(v):
+    return torch.tensor(np.asarray(v, dtype=np.float64), device="cuda")
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    coarse.load()
+
+
+def _case(m, **kw):
+    P = problem.from_mesh(m, **{k: v for k, v in kw.items() if k in ("overlap", "mode")})
+    S = coarse.CoarseSolver.from_mesh(m, **kw)
+    return P, S
+
+
+SMALL = [
+    ("cube8", lambda: mg.small_cube()),
+    ("ragged", lambda: mg.box_mesh((10, 9, 7), 21, block=4, boxes=(3, 3, 2), faces=("y1",))),
+    ("annulus", lambda: mg.annulus_mesh(12, 22, block=4, boxes=(3, 3, 3))),
+    ("one_sub", lambda: mg.box_mesh(6, 23, block=6, boxes=(2, 2, 2), faces=("z0",))),
+]
+
+
+@pytest.mark.parametrize("name,make", SMALL, ids=[s[0] for s in SMALL])
+def test_apply_A_small(name, make):
+    m = make()
+    P, S = _case(m)
+    rng = np.random.default_rng(5)
+    for _ in range(2):
+        p = rng.standard_normal(m.n_vert)
+        q = _np(S.apply_A(_gpu(p)))
+        assert _rel(q, P.apply_A(p)) < 1e-13
+        assert np.all(q[m.dirichlet.astype(bool)] == 0)
+
+
+@pytest.mark.parametrize("name,make", SMALL, ids=[s[0] for s in SMALL])
+def test_apply_precond_small(name, make):
+    m = make()
+    P, S = _case(m)
+    rng = np.random.default_rng(6)
+    for _ in range(2):
+        r = rng.standard_normal(m.n_vert)
+        z = _np(S.apply_precond(_gpu(r)))
+        assert _rel(z, P.apply_precond(r)) < 1e-12
+        assert np.all(z[m.dirichlet.astype(bool)] == 0)
+
+
+@pytest.mark.parametrize("mode", ["local_only", "reduced_only", "hybrid_sym"])
+def test_apply_precond_modes(mode):
+    m = mg.box_mesh(8, 31, block=4, boxes=(2, 2, 2), faces=("x0", "z1"))
+    om = {"reduced_only": "coarse_only"}.get(mode, mode)
+    P = problem.from_mesh(m, mode=om)
+    S = coarse.CoarseSolver.from_mesh(m, mode=mode)
+    r = np.random.default_rng(7).standard_normal(m.n_vert)
+    assert _rel(_np(S.apply_precond(_gpu(r))), P.apply_precond(r)) < 1e-12
+
+
+def test_overlap_two():
+    m = mg.box_mesh(8, 32, block=4, boxes=(2, 2, 2))
+    P, S = _case(m, overlap=2)
+    r = np.random.default_rng(8).standard_normal(m.n_vert)
+    assert _rel(_np(S.apply_precond(_gpu(r))), P.apply_precond(r)) < 1e-12
+
+
+@pytest.mark.parametrize("name,make", SMALL, ids=[s[0] for s in SMALL])
+def test_solve_small_fp64(name, make):
+    m = make()
+    P, S = _case(m)
+    uo, io = P.solve(m.b, tol=1e-8)
+    u, st = S.solve(_gpu(m.b), tol=1e-8)
+    u = _np(u)
+    assert st["code"] == 0 and st["iters"] == io["iters"]
+    assert st["relres"] <= 1e-8 and st["relres_true"] <= 1.01e-8
+    # both iterates agree far below the solve tolerance
+    assert np.linalg.norm(u - uo) / np.linalg.norm(uo) < 1e-9
+    assert np.all(u[m.dirichlet.astype(bool)] == 0)
+
+
+@pytest.mark.parametrize("name,make", SMALL, ids=[s[0] for s in SMALL])
+def test_solve_small_mixed(name, make):
+    m = make()
+    P = problem.from_mesh(m)
+    uo, io = P.solve(m.b, tol=1e-8)
+    S = coarse.CoarseSolver.from_mesh(m, precision="mixed")
+    u, st = S.solve(_gpu(m.b), tol=1e-8)
+    assert st["code"] == 0
+    assert st["iters"] <= math.ceil(1.1 * io["iters"])
+    assert st["relres_true"] <= 1.05e-8
+    assert np.linalg.norm(_np(u) - uo) / np.linalg.norm(uo) < 1e-6
+
+
+def test_zero_rhs_and_dirichlet_entries_ignored():
+    m = mg.small_cube()
+    S = coarse.CoarseSolver.from_mesh(m)
+    u, st = S.solve(_gpu(np.zeros(m.n_vert)))
+    assert st["iters"] == 0 and float(u.abs().max()) == 0.0
+    b = m.b.copy()
+    b[m.dirichlet.astype(bool)] = 1e6
+    u1, _ = S.solve(_gpu(m.b))
+    u2, _ = S.solve(_gpu(b))
+    assert torch.equal(u1, u2)
+
+
+def test_repeat_is_bitwise():
+    m = mg.box_mesh(12, 33, block=4, boxes=(3, 3, 3))
+    S = coarse.CoarseSolver.from_mesh(m)
+    b = _gpu(m.b)
+    u1, s1 = S.solve(b)
+    u2, s2 = S.solve(b)
+    assert torch.equal(u1, u2) and s1["iters"] == s2["iters"]
+    z1 = S.apply_precond(b)
+    z2 = S.apply_precond(b)
+    assert torch.equal(z1, z2)
+
+
+def test_check_interval_does_not_change_result():
+    m = mg.box_mesh(10, 34, block=5, boxes=(2, 2, 2))
+    b = _gpu(m.b)
+    outs = []
+    for ce in (1, 3, 16):
+        S = coarse.CoarseSolver.from_mesh(m, check_every=ce)
+        u, st = S.solve(b)
+        outs.append((u, st["iters"]))
+    assert all(torch.equal(outs[0][0], o[0]) and outs[0][1] == o[1] for o in outs)
+
+
+def test_iteration_limit_and_breakdown_codes():
+    m = mg.small_cube()
+    S = coarse.CoarseSolver.from_mesh(m, max_it=3)
+    u, st = S.solve(_gpu(m.b))
+    assert st["code"] == 1 and st["iters"] == 3
+    bad = m.b.copy()
+    bad[np.flatnonzero(~m.dirichlet.astype(bool))[0]] = np.nan
+    S2 = coarse.CoarseSolver.from_mesh(m)
+    u, st = S2.solve(_gpu(bad))
+    assert st["code"] == -6
+
+
+def test_setup_errors():
+    m = mg.small_cube()
+    # all-Neumann: A is singular, the local systems touching nothing Dirichlet are
+    # still SPD but the reduced system is not
+    with pytest.raises(coarse.CoarseError) as ei:
+        coarse.CoarseSolver(m.xyz, m.e2v, np.zeros(m.n_vert, np.uint8), m.part, m.n_part, boxes=m.boxes)
+    assert ei.value.code == -4
+    # inverted element
+    e2v = m.e2v.copy()
+    e2v[5] = e2v[5][[1, 0, 3, 2, 5, 4, 7, 6]]
+    with pytest.raises(coarse.CoarseError) as ei:
+        coarse.CoarseSolver(m.xyz, e2v, m.dirichlet, m.part, m.n_part, boxes=m.boxes)
+    assert ei.value.code == -3
+
+
+# ---------------------------------------------------------------------------
+# One GPU's share: the 64^3 cube with 512 subdomains (the benchmark workload)
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def cube64():
+    m = mg.gpu_share_cube()
+    P = problem.from_mesh(m)
+    uo, io = P.solve(m.b, tol=1e-8)
+    return m, P, uo, io
+
+
+@pytest.mark.timeout(900)
+def test_cube64_precond_and_A(cube64):
+    m, P, uo, io = cube64
+    S = coarse.CoarseSolver.from_mesh(m)
+    r = np.random.default_rng(9).standard_normal(m.n_vert)
+    assert _rel(_np(S.apply_A(_gpu(r))), P.apply_A(r)) < 1e-13
+    assert _rel(_np(S.apply_precond(_gpu(r))), P.apply_precond(r)) < 1e-12
+
+
+@pytest.mark.timeout(900)
+def test_cube64_solve_fp64(cube64):
+    m, P, uo, io = cube64
+    S = coarse.CoarseSolver.from_mesh(m)
+    u, st = S.solve(_gpu(m.b), tol=1e-8)
+    assert st["code"] == 0 and st["iters"] == io["iters"]
+    assert st["relres_true"] <= 1.01e-8
+    assert np.linalg.norm(_np(u) - uo) / np.linalg.norm(uo) < 1e-8
+
+
+@pytest.mark.timeout(900)
+def test_cube64_solve_mixed(cube64):
+    m, P, uo, io = cube64
+    S = coarse.CoarseSolver.from_mesh(m, precision="mixed")
+    u, st = S.solve(_gpu(m.b), tol=1e-8)
+    assert st["code"] == 0
+    assert st["iters"] <= math.ceil(1.1 * io["iters"])
+    assert st["relres_true"] <= 1.05e-8
