@@ -91,6 +91,8 @@ def main():
     ap.add_argument("--n", type=int, default=64, help="cube edge in elements (64 = one GPU's share)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="first run a plain 1 GiB device copy (known bytes) to scale HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -104,6 +106,13 @@ def main():
         print("no GPU available", file=sys.stderr)
         sys.exit(1)
     coarse.load()
+    if args.copy_calib:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     mesh = mg.gpu_share_cube(n=args.n)
 
     fp64 = run_form(torch, coarse, mesh, "fp64", args.steps, args.warmup, args.tol)

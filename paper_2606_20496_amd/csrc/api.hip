@@ -366,6 +366,7 @@ int64_t invert_systems(coarse_ctx *c, const std::vector<System> &sys, const std:
     double *Gb = tmp.alloc<double>((size_t)poff * TILE * TILE);
     double *Dv = tmp.alloc<double>((size_t)ns * TILE * TILE);
     int *st = tmp.alloc<int>(ns);
+    double *diag0 = tmp.alloc<double>((size_t)poff * TILE);
     SweepSys *dss = tmp.upload(ss, s);
     AsmSys *das = tmp.upload(as, s);
     int64_t *doo = tmp.upload(oo, s);
@@ -377,8 +378,9 @@ int64_t invert_systems(coarse_ctx *c, const std::vector<System> &sys, const std:
     hipLaunchKernelGGL(k_pad_identity, dim3((unsigned)ns), dim3(256), 0, s, das, (int)ns, M);
     assemble(das, (int)ns, M);
     const int64_t ntiles = (int64_t)tsys.size();
+    hipLaunchKernelGGL(k_save_diag, dim3((unsigned)ns), dim3(256), 0, s, dss, (const double *)M, diag0);
     for (int k = 0; k < maxnb; ++k) {
-      hipLaunchKernelGGL(k_sweep_pivot, dim3((unsigned)ns), dim3(256), 0, s, k, dss, M, Dv, st);
+      hipLaunchKernelGGL(k_sweep_pivot, dim3((unsigned)ns), dim3(256), 0, s, k, dss, M, Dv, (const double *)diag0, st);
       hipLaunchKernelGGL(k_sweep_panel, dim3((unsigned)ns, (unsigned)maxnb), dim3(256), 0, s, k, dss, M, Dv, Pb, Gb);
       hipLaunchKernelGGL(k_sweep_update, dim3((unsigned)ntiles), dim3(256), 0, s, k, dss, dts, dti, dtj, M, Dv, Pb, Gb);
     }

@@ -766,8 +766,26 @@ __device__ __forceinline__ double *tile_ptr(double *M, int64_t toff, int I, int 
   return M + (toff + (int64_t)I * (I + 1) / 2 + J) * (TILE * TILE);
 }
 
+// Save the diagonal of the assembled systems (the reference for the relative
+// pivot test below).
+__global__ __launch_bounds__(256) void k_save_diag(const SweepSys *__restrict__ sys, const double *__restrict__ M,
+                                                   double *__restrict__ diag0) {
+  const SweepSys S = sys[blockIdx.x];
+  for (int i = threadIdx.x; i < S.nb * TILE; i += blockDim.x) {
+    const int I = i / TILE;
+    diag0[S.pan_off * TILE + i] = M[(S.tile_off + (int64_t)I * (I + 1) / 2 + I) * (TILE * TILE) + (i % TILE) * (TILE + 1)];
+  }
+}
+
+// A pivot is the diagonal of a Schur complement of the SPD system; it must stay
+// positive, and a pivot below PIVOT_RTOL times the original diagonal entry marks
+// the system as numerically singular (e.g. the constant null space of an
+// all-Neumann reduced operator).
+constexpr double PIVOT_RTOL = 1e-13;
+
 __global__ __launch_bounds__(256) void k_sweep_pivot(int k, const SweepSys *__restrict__ sys, double *__restrict__ M,
-                                                     double *__restrict__ Dinv, int *__restrict__ status) {
+                                                     double *__restrict__ Dinv, const double *__restrict__ diag0,
+                                                     int *__restrict__ status) {
   __shared__ double D[TILE][TILE + 1];
   __shared__ double col[TILE];
   __shared__ int bad;
@@ -780,7 +798,9 @@ __global__ __launch_bounds__(256) void k_sweep_pivot(int k, const SweepSys *__re
   for (int j = 0; j < TILE; ++j) {
     const double piv = D[j][j];
     if (threadIdx.x < TILE) col[threadIdx.x] = D[threadIdx.x][j];
-    if (threadIdx.x == 0 && (!(piv > 0.0) || !isfinite(piv))) bad = 1;
+    if (threadIdx.x == 0 &&
+        (!(piv > PIVOT_RTOL * diag0[S.pan_off * TILE + (int64_t)k * TILE + j]) || !isfinite(piv)))
+      bad = 1;
     __syncthreads();
     if (threadIdx.x < TILE) {
       const double v = (threadIdx.x == j) ? 1.0 : D[j][threadIdx.x];

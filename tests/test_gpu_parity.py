@@ -159,8 +159,11 @@ def test_iteration_limit_and_breakdown_codes():
     bad = m.b.copy()
     bad[np.flatnonzero(~m.dirichlet.astype(bool))[0]] = np.nan
     S2 = coarse.CoarseSolver.from_mesh(m)
-    u, st = S2.solve(_gpu(bad))
-    assert st["code"] == -6
+    with pytest.raises(coarse.CoarseError) as ei:
+        S2.solve(_gpu(bad))
+    assert ei.value.code == -6
+    u, st = S2.solve(_gpu(m.b))          # the context stays usable
+    assert st["code"] == 0
 
 
 def test_setup_errors():
