@@ -185,13 +185,15 @@ int coarse_get_info(const coarse_ctx *ctx, coarse_info_t *info);
 int coarse_set_stream(coarse_ctx *ctx, void *stream);
 
 /* Phase timers (HIP events on the context's stream around every launch of a
- * phase). enable = 1 clears the accumulators and starts timing; enable = 0 waits
- * for the stream, stops, and writes the accumulated milliseconds and launch
- * counts of the first nphase phases into ms[] and counts[] (either may be NULL).
- * Phases: 0 operator A (both passes), 1 restriction R_p gather, 2 reduced
- * restriction J^T, 3 batched dense solves A_p^{-1} and A_r^{-1} (the tiled GEMV
- * kernel alone), 4 partial-sum combine, 5 overlap sum + J prolongation,
- * 6 PCG vector updates and scalar steps. */
+ * phase). enable != 0 is a bit mask of the phases to time (bit i = phase i;
+ * 0x7F = all): it clears the accumulators and starts timing. enable = 0 waits for
+ * the stream, stops, and writes the accumulated milliseconds and launch counts of
+ * the first nphase phases into ms[] and counts[] (either may be NULL).
+ * Phases: 0 operator A (with the search-direction update), 1 restriction R_p
+ * gather (with the first stage of J^T in the additive mode), 2 reduced
+ * restriction J^T (corner sums), 3 batched dense solves A_p^{-1} and A_r^{-1} (the
+ * tiled GEMV kernel alone), 4 partial-sum combine, 5 overlap sum + J
+ * prolongation (with (r, z)), 6 PCG vector update. */
 #define COARSE_NPHASE 7
 int coarse_profile(coarse_ctx *ctx, int enable, double *ms, int64_t *counts, int nphase);
 

@@ -27,7 +27,7 @@ EXPORTS = ("coarse_default_opts", "coarse_setup", "coarse_apply_precond", "coars
            "coarse_get_info", "coarse_set_stream", "coarse_plan_info", "coarse_strerror",
            "coarse_last_error", "coarse_profile")
 
-PHASES = ("A", "R_p", "J^T", "A_p^-1/A_r^-1 gemv", "combine", "sum+J", "pcg_vec")
+PHASES = ("A+p", "R_p+J^T", "J^T corners", "A_p^-1/A_r^-1 gemv", "combine", "sum+J", "x,r update")
 
 
 class CoarseError(RuntimeError):
@@ -246,8 +246,9 @@ class CoarseSolver:
         stats["code"] = rc
         return out, stats
 
-    def profile_start(self):
-        self._L.coarse_profile(self._ctx, 1, None, None, 0)
+    def profile_start(self, mask=0x7F):
+        """Time the phases whose bits are set in ``mask`` (bit i = PHASES[i])."""
+        self._check(self._L.coarse_profile(self._ctx, int(mask), None, None, 0))
 
     def profile_stop(self):
         """Stop the phase timers; returns {phase: (total_ms, launches)}."""

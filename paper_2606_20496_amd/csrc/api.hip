@@ -81,8 +81,10 @@ struct coarse_ctx {
 
   OpDev op{};
   int32_t *user_of_vint = nullptr, *vint_of_user = nullptr;
-  double *x = nullptr, *r = nullptr, *p = nullptr, *z = nullptr, *q = nullptr, *bint = nullptr, *t1 = nullptr,
-         *t2 = nullptr, *part1 = nullptr, *part2 = nullptr, *energy = nullptr;
+  double *x = nullptr, *r = nullptr, *p = nullptr, *pb = nullptr, *z = nullptr, *q = nullptr, *bint = nullptr,
+         *t1 = nullptr, *t2 = nullptr, *part1 = nullptr, *part2 = nullptr, *energy = nullptr;
+  double *prr = nullptr;     // partial sums of ||r||^2 (and of ||b||^2 at the start)
+  int last_iters = 0;        // iterations of the previous solve (first batch size)
   Scalars *sc = nullptr;
   Scalars *h_sc = nullptr;   // pinned host copy
   int *zero_flag = nullptr;  // a device int that is always 0
@@ -106,7 +108,7 @@ struct coarse_ctx {
 
   // phase timers
   static constexpr int NPH = 7;
-  bool prof_on = false;
+  int prof_mask = 0;
   double prof_ms[NPH] = {};
   int64_t prof_cnt[NPH] = {};
   std::vector<hipEvent_t> ev_pool;
@@ -133,12 +135,12 @@ struct coarse_ctx {
     return e;
   }
   void pbeg(int ph) {
-    if (!prof_on) return;
+    if (!((prof_mask >> ph) & 1)) return;
     ev_open[ph] = get_event();
     HIPCHK(hipEventRecord(ev_open[ph], stream));
   }
   void pend(int ph) {
-    if (!prof_on) return;
+    if (!((prof_mask >> ph) & 1)) return;
     hipEvent_t e = get_event();
     HIPCHK(hipEventRecord(e, stream));
     ev_pending.push_back({ph, {ev_open[ph], e}});
@@ -171,9 +173,14 @@ struct coarse_ctx {
     pbeg(2);
     hipLaunchKernelGGL(k_jt_tasks<T>, dim3(nblk(ntask, 4)), dim3(256), 0, stream, (int)ntask, done, jt_start, jc_vid,
                        (const T *)jc_w, (const T *)jc_xi, nent, in, (T *)jt_part);
+    corners<T>(done);
+    pend(2);
+  }
+
+  template <typename T>
+  void corners(const int *done) {
     hipLaunchKernelGGL(k_jt_corners<T>, dim3(nblk(n_r, 256)), dim3(256), 0, stream, n_r, done, jr_ptr, jr_src,
                        (const T *)jt_part, (T *)rp + coarse_vec_off);
-    pend(2);
   }
 
   void gemv_combine(const Seg *segs, int nitems, int nrows, const int *done) {
@@ -195,105 +202,119 @@ struct coarse_ctx {
     pend(4);
   }
 
+  // scal: count the iteration in the solver state (PCG); start: first application
   template <typename T>
   void final_step(const double *add, bool local, bool coarse, double *out, const double *rdot, double *p1, double *p2,
-                  const int *done) {
+                  const int *done, bool scal, int start) {
     pbeg(5);
     hipLaunchKernelGGL(k_final<T>, dim3(nvblk), dim3(VB), 0, stream, nf, done, add, local ? cover_ptr : nullptr,
                        cover_pos, zp, coarse ? jv_ptr : nullptr, jv_occ, (const T *)jv_w, (const T *)jv_xi, nent,
-                       corner_act, zp + coarse_vec_off, out, rdot, p1, p2);
+                       corner_act, zp + coarse_vec_off, out, rdot, p1, p2, scal ? sc : nullptr, start);
     pend(5);
   }
 
+  // chk != nullptr: the convergence test of PCG runs first, from these partials
   template <typename T>
   void precond_parts(const double *in, const double *add, bool local, bool coarse, double *out, const double *rdot,
-                     double *p1, double *p2, const int *done) {
-    if (local) {
+                     double *p1, double *p2, const int *done, bool scal, int start, const double *chk) {
+    if (local && coarse) {
+      // convergence test, R_p gather and the first stage of J^T in one launch
       pbeg(1);
-      hipLaunchKernelGGL(k_gather<T>, dim3(nblk(coarse_vec_off, VB)), dim3(VB), 0, stream, coarse_vec_off, done,
-                         sub_idx, in, (T *)rp);
+      const int ng = (int)nblk(coarse_vec_off, 256);
+      const int nt = (int)nblk(ntask, 4);
+      hipLaunchKernelGGL(k_pre<T>, dim3(ng + nt), dim3(256), 0, stream, ng, coarse_vec_off, done, sub_idx, in, (T *)rp,
+                         (int)ntask, jt_start, jc_vid, (const T *)jc_w, (const T *)jc_xi, nent, (T *)jt_part,
+                         chk ? sc : nullptr, chk, nvblk, start);
       pend(1);
+      pbeg(2);
+      corners<T>(done);
+      pend(2);
+    } else {
+      if (chk) hipLaunchKernelGGL(k_check, dim3(1), dim3(256), 0, stream, sc, chk, nvblk, start);
+      if (local) {
+        pbeg(1);
+        hipLaunchKernelGGL(k_gather<T>, dim3(nblk(coarse_vec_off, VB)), dim3(VB), 0, stream, coarse_vec_off, done,
+                           sub_idx, in, (T *)rp);
+        pend(1);
+      }
+      if (coarse) restrict_coarse<T>(in, done);
     }
-    if (coarse) restrict_coarse<T>(in, done);
     if (local && coarse)
       gemv_combine(seg_all, items_total, rows_total, done);
     else if (local)
       gemv_combine(seg_local, items_local, rows_local, done);
     else
       gemv_combine(seg_coarse, items_total - items_local, rows_total - rows_local, done);
-    final_step<T>(add, local, coarse, out, rdot, p1, p2, done);
+    final_step<T>(add, local, coarse, out, rdot, p1, p2, done, scal, start);
   }
 
   template <typename T>
-  void precond_t(const double *in, double *out, const double *rdot, double *p1, double *p2, const int *done) {
+  void precond_t(const double *in, double *out, const double *rdot, double *p1, double *p2, const int *done, bool scal,
+                 int start, const double *chk) {
     switch (mode) {
       case COARSE_ADDITIVE:
-        precond_parts<T>(in, nullptr, true, true, out, rdot, p1, p2, done);
+        precond_parts<T>(in, nullptr, true, true, out, rdot, p1, p2, done, scal, start, chk);
         break;
       case COARSE_LOCAL_ONLY:
-        precond_parts<T>(in, nullptr, true, false, out, rdot, p1, p2, done);
+        precond_parts<T>(in, nullptr, true, false, out, rdot, p1, p2, done, scal, start, chk);
         break;
       case COARSE_REDUCED_ONLY:
-        precond_parts<T>(in, nullptr, false, true, out, rdot, p1, p2, done);
+        precond_parts<T>(in, nullptr, false, true, out, rdot, p1, p2, done, scal, start, chk);
         break;
       case COARSE_HYBRID_SYM:
         // z0 = M_r r; z1 = z0 + M_loc (r - A z0); z = z1 + M_r (r - A z1)
-        precond_parts<T>(in, nullptr, false, true, t1, nullptr, nullptr, nullptr, done);
+        precond_parts<T>(in, nullptr, false, true, t1, nullptr, nullptr, nullptr, done, false, 0, chk);
         apply_op(t1, q, nullptr, done);
         hipLaunchKernelGGL(k_sub, dim3(nvblk), dim3(VB), 0, stream, nf, done, in, q, t2);
-        precond_parts<T>(t2, t1, true, false, t1, nullptr, nullptr, nullptr, done);
+        precond_parts<T>(t2, t1, true, false, t1, nullptr, nullptr, nullptr, done, false, 0, nullptr);
         apply_op(t1, q, nullptr, done);
         hipLaunchKernelGGL(k_sub, dim3(nvblk), dim3(VB), 0, stream, nf, done, in, q, t2);
-        precond_parts<T>(t2, t1, false, true, out, rdot, p1, p2, done);
+        precond_parts<T>(t2, t1, false, true, out, rdot, p1, p2, done, scal, start, nullptr);
         break;
     }
   }
 
-  void precond(const double *in, double *out, const double *rdot, double *p1, double *p2, const int *done) {
+  void precond(const double *in, double *out, const double *rdot, double *p1, double *p2, const int *done,
+               bool scal = false, int start = 0, const double *chk = nullptr) {
     if (precision == COARSE_FP64)
-      precond_t<double>(in, out, rdot, p1, p2, done);
+      precond_t<double>(in, out, rdot, p1, p2, done, scal, start, chk);
     else
-      precond_t<float>(in, out, rdot, p1, p2, done);
+      precond_t<float>(in, out, rdot, p1, p2, done, scal, start, chk);
   }
 
-  void scalar(int opk, const double *part, int n, const double *part2_, double tol2 = 0.0) {
-    hipLaunchKernelGGL(k_scalar, dim3(1), dim3(VB), 0, stream, opk, sc, part, n, part2_, tol2, max_it, flexible);
-  }
-
-  // one PCG iteration, skipped on the device once the solve has finished
+  // One PCG iteration k (skipped on the device once the solve has finished):
+  //   beta, p_k = z_k + beta p_{k-1}, q = A p_k     (operator kernel)
+  //   alpha, x += alpha p_k, r -= alpha q, ||r||^2  (update kernel)
+  //   stop?, z = M r, (r, z)                        (preconditioner kernels)
   void iteration() {
-    apply_op(p, q, energy, done_flag);
+    pbeg(0);
+    hipLaunchKernelGGL(k_op_fused, dim3((unsigned)op.n_blocks), dim3(OP_BLOCK), op.lds_bytes, stream, op,
+                       (const double *)z, p, pb, q, energy, sc, (const double *)part1, (const double *)part2, nvblk);
+    pend(0);
     pbeg(6);
-    scalar(SC_ALPHA, energy, (int)op.n_blocks, nullptr);
-    hipLaunchKernelGGL(k_update, dim3(nvblk), dim3(VB), 0, stream, nf, sc, x, r, p, q, part1);
-    scalar(SC_CHECK, part1, nvblk, nullptr);
+    hipLaunchKernelGGL(k_update_fused, dim3(nvblk), dim3(VB), 0, stream, nf, op, sc, x, r, (const double *)p,
+                       (const double *)pb, (const double *)q, (const double *)energy, (int)op.n_blocks, prr);
     pend(6);
-    precond(r, z, r, part1, flexible ? part2 : nullptr, done_flag);
-    pbeg(6);
-    scalar(SC_BETA, part1, nvblk, flexible ? part2 : nullptr);
-    hipLaunchKernelGGL(k_pupdate, dim3(nvblk), dim3(VB), 0, stream, nf, sc, z, p);
-    pend(6);
+    precond(r, z, r, part1, flexible ? part2 : nullptr, done_flag, true, 0, prr);
   }
 
   void start(const double *b, double tol) {
-    hipLaunchKernelGGL(k_permute_in, dim3(nvblk), dim3(VB), 0, stream, nf, user_of_vint, b, r, x, p, z, bint, part1);
-    scalar(SC_INIT, part1, nvblk, nullptr, tol * tol);
-    precond(r, z, r, part1, nullptr, done_flag);
-    scalar(SC_RZ0, part1, nvblk, nullptr);
-    hipLaunchKernelGGL(k_pupdate, dim3(nvblk), dim3(VB), 0, stream, nf, sc, z, p);
+    hipLaunchKernelGGL(k_start, dim3(nvblk), dim3(VB), 0, stream, nf, user_of_vint, b, r, x, p, pb, z, bint, prr, sc,
+                       tol * tol, max_it, flexible);
+    precond(r, z, r, part1, flexible ? part2 : nullptr, done_flag, true, 1, prr);
   }
 
   void finish(double *u) {
     apply_op(x, q, nullptr, zero_flag);
     hipLaunchKernelGGL(k_resnorm, dim3(nvblk), dim3(VB), 0, stream, nf, bint, q, part1);
-    scalar(SC_RES, part1, nvblk, nullptr);
+    hipLaunchKernelGGL(k_res_total, dim3(1), dim3(VB), 0, stream, sc, (const double *)part1, nvblk);
     hipLaunchKernelGGL(k_permute_out, dim3(nblk(nv, VB)), dim3(VB), 0, stream, nv, nf, vint_of_user, x, u);
     HIPCHK(hipMemcpyAsync(h_sc, sc, sizeof(Scalars), hipMemcpyDeviceToHost, stream));
   }
 
   void fill_stats(coarse_stats *st, double t0) {
     if (!st) return;
-    st->iters = h_sc->iter;
+    st->iters = h_sc->iters;
     st->status = h_sc->status;
     st->relres = h_sc->bb > 0 ? std::sqrt(h_sc->rr / h_sc->bb) : 0.0;
     st->relres_true = h_sc->bb > 0 ? std::sqrt(h_sc->res_true / h_sc->bb) : 0.0;
@@ -429,6 +450,8 @@ void setup_precision(coarse_ctx *c, Plan &P) {
   op.sh_vid = A.upload(P.sh_vid, s);
   op.sh_ptr = A.upload(P.sh_ptr, s);
   op.sh_part = A.upload(P.sh_part, s);
+  op.slot_pw = A.upload(P.slot_pw, s);
+  op.sh_idx = A.upload(P.sh_idx, s);
   op.lds_bytes = (int32_t)((OP_BLOCK * 8 + P.max_slots) * sizeof(double));
   if (op.lds_bytes > 64 * 1024) throw Fail(COARSE_EINVAL, "operator block touches too many vertices");
 
@@ -440,7 +463,7 @@ void setup_precision(coarse_ctx *c, Plan &P) {
   std::vector<int32_t> uov(P.user_of_vint.begin(), P.user_of_vint.begin() + nf);
   c->user_of_vint = A.upload(uov, s);
   c->vint_of_user = A.upload(P.vint_of_user, s);
-  for (double **v : {&c->x, &c->r, &c->p, &c->z, &c->q, &c->bint, &c->t1, &c->t2}) {
+  for (double **v : {&c->x, &c->r, &c->p, &c->pb, &c->z, &c->q, &c->bint, &c->t1, &c->t2}) {
     *v = A.alloc<double>(nf);
     HIPCHK(hipMemsetAsync(*v, 0, nf * sizeof(double), s));
   }
@@ -451,6 +474,7 @@ void setup_precision(coarse_ctx *c, Plan &P) {
   c->sc = A.alloc<Scalars>(1);
   HIPCHK(hipMemsetAsync(c->sc, 0, sizeof(Scalars), s));
   c->done_flag = (int *)((char *)c->sc + offsetof(Scalars, done));
+  c->prr = A.alloc<double>(npart);
   c->zero_flag = A.alloc<int>(1);
   HIPCHK(hipMemsetAsync(c->zero_flag, 0, sizeof(int), s));
 
@@ -751,8 +775,10 @@ int coarse_solve(coarse_ctx *c, const double *b, double *u, double tol, coarse_s
   const double t0 = now();
   try {
     c->start(b, tol);
+    int batch = std::max(c->check_every, c->last_iters);
     for (;;) {
-      for (int j = 0; j < c->check_every; ++j) c->iteration();
+      for (int j = 0; j < batch; ++j) c->iteration();
+      batch = c->check_every;
       HIPCHK(hipGetLastError());
       HIPCHK(hipMemcpyAsync(c->h_sc, c->sc, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
       HIPCHK(hipStreamSynchronize(c->stream));
@@ -765,6 +791,7 @@ int coarse_solve(coarse_ctx *c, const double *b, double *u, double tol, coarse_s
     return fail_ctx(c, f);
   }
   c->fill_stats(st, t0);
+  c->last_iters = c->h_sc->iters;
   const int status = c->h_sc->status;
   if (status == -6) c->err = "PCG breakdown (p.Ap <= 0 or non-finite value)";
   if (status == 1) c->err = "iteration limit reached";
@@ -808,9 +835,9 @@ int coarse_profile(coarse_ctx *c, int enable, double *ms, int64_t *counts, int n
         c->prof_ms[i] = 0.0;
         c->prof_cnt[i] = 0;
       }
-      c->prof_on = true;
+      c->prof_mask = enable & ((1 << coarse_ctx::NPH) - 1);
     } else {
-      c->prof_on = false;
+      c->prof_mask = 0;
       for (int i = 0; i < std::min(nphase, (int)coarse_ctx::NPH); ++i) {
         if (ms) ms[i] = c->prof_ms[i];
         if (counts) counts[i] = c->prof_cnt[i];

@@ -9,8 +9,10 @@ namespace coarse {
 
 // Solver scalars living in device memory (one per context).
 struct Scalars {
-  double bb, rz, rr, pq, alpha, beta, tol2, res_true;
-  int32_t iter, done, status, max_it, flexible, pad0, pad1, pad2;
+  double bb, rho[2], rr, pq, alpha, beta, tol2, res_true;
+  int32_t iter;    // completed iterations (parity of the double buffers)
+  int32_t iters;   // iterations reported when the solve ended
+  int32_t done, status, max_it, flexible, pad0, pad1;
 };
 
 // One dense system of the batched local/reduced solve, with absolute pointers.
@@ -54,6 +56,8 @@ struct OpDev {
   const uint16_t *slot_inc;
   double *partials;
   const int32_t *sh_vid, *sh_ptr, *sh_part;
+  const uint8_t *slot_pw;     // 1: this slot's block writes the vertex's search direction
+  const int32_t *sh_idx;      // free vertex -> index into sh_ptr, or -1 (owned by one block)
   int32_t lds_bytes;
 };
 

@@ -244,86 +244,296 @@ __global__ __launch_bounds__(VB) void k_resnorm(int64_t nf, const double *__rest
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// ---------------------------------------------------------------------------
-// Scalar steps of PCG (one workgroup). Each sums a partial array in a fixed
-// order and updates the solver state.
-// ---------------------------------------------------------------------------
-__device__ double sum_parts(const double *part, int n, double *red) {
+// ||b - A u||^2 from the partials of k_resnorm (one workgroup).
+__global__ __launch_bounds__(VB) void k_res_total(Scalars *__restrict__ sc, const double *__restrict__ part, int n) {
+  __shared__ double red[VB / WAVE];
   double acc = 0.0;
   for (int i = threadIdx.x; i < n; i += VB) acc += part[i];
-  return block_sum<VB>(acc, red);
+  const double s = block_sum<VB>(acc, red);
+  if (threadIdx.x == 0) sc->res_true = s;
 }
 
-enum ScalarOp { SC_INIT = 0, SC_RZ0 = 1, SC_ALPHA = 2, SC_CHECK = 3, SC_BETA = 4, SC_RES = 5 };
 
-__global__ __launch_bounds__(VB) void k_scalar(int op, Scalars *__restrict__ sc, const double *__restrict__ part, int n,
-                                               const double *__restrict__ part2, double tol2, int max_it, int flexible) {
+// ---------------------------------------------------------------------------
+// Fused PCG kernels. A scalar that needs a sum over workgroups of the previous
+// kernel (p.Ap, ||r||^2, (r, z)) is formed by every workgroup of the consuming
+// kernel from the at most 1024 partials, in the same fixed order, so all
+// workgroups agree without any cross-workgroup synchronisation; workgroup 0
+// records it in the solver state. Values that a kernel both reads and records
+// (rho) are double-buffered by iteration parity.
+// ---------------------------------------------------------------------------
+// Sum of part[0..n) in a fixed order, returned to every thread (NT threads).
+template <int NT>
+__device__ __forceinline__ double block_total(const double *__restrict__ part, int n, double *red) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += NT) acc += part[i];
+  acc = wave_sum(acc);
+  const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+  __syncthreads();
+  if (l == 0) red[w] = acc;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < NT / WAVE; ++i) s += red[i];
+  return s;
+}
+
+// r = b (internal order), x = 0, both search-direction buffers and z = 0, and
+// the partial sums of ||b||^2; workgroup 0 resets the solver state.
+__global__ __launch_bounds__(VB) void k_start(int64_t nf, const int32_t *__restrict__ user_of, const double *__restrict__ b,
+                                              double *__restrict__ r, double *__restrict__ x, double *__restrict__ pa,
+                                              double *__restrict__ pb, double *__restrict__ z, double *__restrict__ bint,
+                                              double *__restrict__ part, Scalars *__restrict__ sc, double tol2, int max_it,
+                                              int flexible) {
   __shared__ double red[VB / WAVE];
-  if (op != SC_INIT && op != SC_RES && sc->done) return;
-  const double s = sum_parts(part, n, red);
-  double s2 = 0.0;
-  if (part2) s2 = sum_parts(part2, n, red);
-  if (threadIdx.x != 0) return;
-  switch (op) {
-    case SC_INIT:
-      sc->bb = s;
+  double acc = 0.0;
+  const int64_t G = (int64_t)gridDim.x * VB;
+  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < nf; i += G) {
+    const double v = b[user_of[i]];
+    r[i] = v;
+    bint[i] = v;
+    x[i] = 0.0;
+    pa[i] = 0.0;
+    pb[i] = 0.0;
+    z[i] = 0.0;
+    acc += v * v;
+  }
+  const double s = block_sum<VB>(acc, red);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s;
+    if (blockIdx.x == 0) {
       sc->tol2 = tol2;
       sc->max_it = max_it;
       sc->flexible = flexible;
       sc->iter = 0;
+      sc->iters = 0;
       sc->status = 0;
-      sc->rr = s;
-      sc->alpha = sc->beta = sc->pq = sc->rz = 0.0;
-      sc->done = (s == 0.0) ? 1 : 0;
-      if (!isfinite(s)) {
-        sc->done = 1;
-        sc->status = -6;
-      }
-      break;
-    case SC_RZ0:
-      sc->rz = s;
-      sc->beta = 0.0;
-      if (!isfinite(s)) {
-        sc->done = 1;
-        sc->status = -6;
-      }
-      break;
-    case SC_ALPHA:
-      sc->pq = s;
-      if (!(s > 0.0) || !isfinite(s) || !isfinite(sc->rz)) {
-        sc->done = 1;
-        sc->status = -6;
-      } else {
-        sc->alpha = sc->rz / s;
-      }
-      break;
-    case SC_CHECK:
-      sc->rr = s;
-      sc->iter += 1;
-      if (!isfinite(s)) {
-        sc->done = 1;
-        sc->status = -6;
-      } else if (s <= sc->tol2 * sc->bb) {
-        sc->done = 1;
-        sc->status = 0;
-      } else if (sc->iter >= sc->max_it) {
-        sc->done = 1;
-        sc->status = 1;
-      }
-      break;
-    case SC_BETA: {
-      const double beta = sc->flexible ? (s - s2) / sc->rz : s / sc->rz;
-      sc->beta = beta;
-      sc->rz = s;
-      if (!isfinite(beta)) {
-        sc->done = 1;
-        sc->status = -6;
-      }
-      break;
+      sc->done = 0;
+      sc->rho[0] = sc->rho[1] = sc->alpha = sc->beta = sc->pq = 0.0;
     }
-    case SC_RES:
-      sc->res_true = s;
-      break;
+  }
+}
+
+// Operator with the direction update folded in: beta_{k-1} = rho_k / rho_{k-1}
+// (or the Polak-Ribiere form) from the partials of the last preconditioner
+// application, p_k = z_k + beta_{k-1} p_{k-1} formed while the block's vertex
+// values are staged (p_0 = z_0), written once per vertex by its designated block,
+// then q = A p_k as in k_op_pass1 with per-workgroup partials of p.Ap.
+__global__ __launch_bounds__(OP_BLOCK) void k_op_fused(OpDev op, const double *__restrict__ z, double *__restrict__ pa,
+                                                       double *__restrict__ pb, double *__restrict__ q,
+                                                       double *__restrict__ energy, Scalars *__restrict__ sc,
+                                                       const double *__restrict__ rz1, const double *__restrict__ rz2,
+                                                       int nrz) {
+  extern __shared__ double lds[];
+  __shared__ double red[OP_BLOCK / WAVE];
+  if (sc->done) return;
+  const int it = sc->iter;
+  const double rho = block_total<OP_BLOCK>(rz1, nrz, red);
+  double beta = 0.0;
+  if (it > 0) {
+    const double num = sc->flexible ? rho - block_total<OP_BLOCK>(rz2, nrz, red) : rho;
+    beta = num / sc->rho[(it - 1) & 1];
+  }
+  if (!isfinite(rho) || !isfinite(beta)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->done = 1;
+      sc->status = -6;
+      sc->iters = it;
+    }
+    return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->rho[it & 1] = rho;
+    sc->beta = beta;
+  }
+  double *pcur = (it & 1) ? pb : pa;
+  const double *pprev = (it & 1) ? pa : pb;
+  double *out = lds;
+  double *lp = lds + OP_BLOCK * 8;
+  const int blk = blockIdx.x;
+  const int s0 = op.blk_slot_ptr[blk], ns = op.blk_slot_ptr[blk + 1] - s0;
+  for (int s = threadIdx.x; s < ns; s += OP_BLOCK) {
+    const int32_t v = op.slot_vid[s0 + s];
+    const double pv = z[v] + beta * pprev[v];
+    lp[s] = pv;
+    if (op.slot_pw[s0 + s]) pcur[v] = pv;
+  }
+  __syncthreads();
+  const int64_t E = op.E;
+  const int64_t e = (int64_t)blk * OP_BLOCK + threadIdx.x;
+  double en = 0.0;
+  if (e < E) {
+    double pe[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const uint16_t sl = op.lconn[a * E + e];
+      pe[a] = (sl == 0xFFFF) ? 0.0 : lp[sl];
+    }
+    double y[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) y[a] = 0.0;
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int b = a; b < 8; ++b) {
+        const double m = op.Ae[sym8(a, b) * E + e];
+        y[a] += m * pe[b];
+        if (b != a) y[b] += m * pe[a];
+      }
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      out[threadIdx.x * 8 + a] = y[a];
+      en += pe[a] * y[a];
+    }
+  }
+  __syncthreads();
+  for (int s = threadIdx.x; s < ns; s += OP_BLOCK) {
+    const int k0 = op.slot_inc_ptr[s0 + s], k1 = op.slot_inc_ptr[s0 + s + 1];
+    double acc = 0.0;
+    for (int k = k0; k < k1; ++k) acc += out[op.slot_inc[k]];
+    const int dst = op.slot_dst[s0 + s];
+    if (dst >= 0)
+      q[dst] = acc;
+    else
+      op.partials[-dst - 1] = acc;
+  }
+  const double tot = block_sum<OP_BLOCK>(en, red);
+  if (threadIdx.x == 0) energy[blk] = tot;
+}
+
+// alpha = rho / p.Ap (from the operator's partials), x += alpha p,
+// r -= alpha q (q of vertices shared between operator blocks is summed here from
+// the operator's partials), and partials of ||r||^2.
+__global__ __launch_bounds__(VB) void k_update_fused(int64_t nf, OpDev op, Scalars *__restrict__ sc, double *__restrict__ x,
+                                                     double *__restrict__ r, const double *__restrict__ pa,
+                                                     const double *__restrict__ pb, const double *__restrict__ q,
+                                                     const double *__restrict__ energy, int nen,
+                                                     double *__restrict__ part) {
+  __shared__ double red[VB / WAVE];
+  if (sc->done) return;
+  const int it = sc->iter;
+  const double pq = block_total<VB>(energy, nen, red);
+  const double rho = sc->rho[it & 1];
+  if (!(pq > 0.0) || !isfinite(pq)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->pq = pq;
+      sc->done = 1;
+      sc->status = -6;
+      sc->iters = it;
+    }
+    return;
+  }
+  const double alpha = rho / pq;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->pq = pq;
+    sc->alpha = alpha;
+  }
+  const double *p = (it & 1) ? pb : pa;
+  double acc = 0.0;
+  const int64_t G = (int64_t)gridDim.x * VB;
+  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < nf; i += G) {
+    const int32_t sh = op.sh_idx[i];
+    double qi;
+    if (sh < 0) {
+      qi = q[i];
+    } else {
+      qi = 0.0;
+      for (int k = op.sh_ptr[sh]; k < op.sh_ptr[sh + 1]; ++k) qi += op.partials[op.sh_part[k]];
+    }
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * qi;
+    r[i] = ri;
+    acc += ri * ri;
+  }
+  const double s = block_sum<VB>(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// Convergence test at the start of a preconditioner application inside PCG.
+// start = 1: the partials are those of ||b||^2 (b = 0 ends the solve at once);
+// otherwise of ||r_{k+1}||^2, tested against tol^2 ||b||^2 and the iteration cap.
+// Returns true when the solve is over (every workgroup reaches the same answer).
+__device__ bool pcg_check(Scalars *__restrict__ sc, const double *__restrict__ part, int n, int start, double *red) {
+  const double s = block_total<256>(part, n, red);
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  if (start) {
+    const bool stop = !(s > 0.0) || !isfinite(s);
+    if (lead) {
+      sc->bb = s;
+      sc->rr = s;
+      if (stop) {
+        sc->done = 1;
+        sc->status = isfinite(s) ? 0 : -6;
+        sc->iters = 0;
+      }
+    }
+    return stop;
+  }
+  const int nit = sc->iter + 1;
+  int status = 2;
+  if (!isfinite(s))
+    status = -6;
+  else if (s <= sc->tol2 * sc->bb)
+    status = 0;
+  else if (nit >= sc->max_it)
+    status = 1;
+  if (lead) {
+    sc->rr = s;
+    if (status != 2) {
+      sc->done = 1;
+      sc->status = status;
+      sc->iters = nit;
+    }
+  }
+  return status != 2;
+}
+
+// The convergence test alone (used when the first kernel of a preconditioner
+// variant cannot carry it).
+__global__ __launch_bounds__(256) void k_check(Scalars *__restrict__ sc, const double *__restrict__ part, int n,
+                                               int start) {
+  __shared__ double red[256 / WAVE];
+  if (sc->done) return;
+  (void)pcg_check(sc, part, n, start, red);
+}
+
+// Restriction R_p r into the packed local vectors (workgroups [0, ng)) and the
+// first stage of J^T r (the remaining workgroups, one task per wavefront).
+template <typename T>
+__global__ __launch_bounds__(256) void k_pre(int ng, int64_t n, const int *__restrict__ done, const int32_t *__restrict__ idx,
+                                             const double *__restrict__ in, T *__restrict__ rp, int ntask,
+                                             const int32_t *__restrict__ tstart, const int32_t *__restrict__ vid,
+                                             const T *__restrict__ w, const T *__restrict__ xi, int64_t nent,
+                                             T *__restrict__ tpart, Scalars *__restrict__ sc,
+                                             const double *__restrict__ chk, int nchk, int start) {
+  __shared__ double red[256 / WAVE];
+  if (*done) return;
+  if (sc && pcg_check(sc, chk, nchk, start, red)) return;
+  if ((int)blockIdx.x < ng) {
+    const int64_t j = blockIdx.x * (int64_t)256 + threadIdx.x;
+    if (j < n) {
+      const int32_t i = idx[j];
+      rp[j] = (i >= 0) ? (T)in[i] : T(0);
+    }
+    return;
+  }
+  const int lane = threadIdx.x & 63;
+  const int task = (blockIdx.x - ng) * 4 + (threadIdx.x >> 6);
+  if (task >= ntask) return;
+  T acc[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) acc[k] = T(0);
+  for (int j = tstart[task] + lane; j < tstart[task + 1]; j += 64) {
+    const T v = w[j] * (T)in[vid[j]];
+    const T x = xi[j], y = xi[nent + j], z = xi[2 * nent + j];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] += trilin<T>(k, x, y, z) * v;
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) acc[k] = wave_sum(acc[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) tpart[task * 8 + k] = acc[k];
   }
 }
 
@@ -406,6 +616,30 @@ __device__ __forceinline__ int find_seg(const Seg *__restrict__ segs, int nseg, 
   return lo;
 }
 
+// Streaming (non-temporal) 16-byte loads: the stored inverses are read once per
+// application and should not displace the small vectors from the caches.
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ double2 ldnt(const double2 *p) {
+  const nt_d2 v = __builtin_nontemporal_load((const nt_d2 *)p);
+  double2 o;
+  o.x = v.x;
+  o.y = v.y;
+  return o;
+}
+__device__ __forceinline__ float4 ldnt(const float4 *p) {
+  const nt_f4 v = __builtin_nontemporal_load((const nt_f4 *)p);
+  float4 o;
+  o.x = v.x;
+  o.y = v.y;
+  o.z = v.z;
+  o.w = v.w;
+  return o;
+}
+
+// FP64: a wavefront covers a 32x32 tile with 8 loads of 16 bytes per lane; lane l
+// holds rows 4k + l/16 (k < 8), columns 2(l%16) and 2(l%16)+1. The next tile is
+// loaded while the current one is used.
 __global__ __launch_bounds__(256) void k_gemv_f64(const Seg *__restrict__ segs, int nseg, int total,
                                                   const int *__restrict__ done) {
   if (done && *done) return;
@@ -418,7 +652,10 @@ __global__ __launch_bounds__(256) void k_gemv_f64(const Seg *__restrict__ segs, 
     const double *__restrict__ r = (const double *)S.rp;
     const int I = it.I;
     const int64_t rowbase = (int64_t)I * (I + 1) / 2;
-    const double2 *__restrict__ tb = (const double2 *)((const double *)S.tiles + rowbase * (TILE * TILE));
+    const double2 *__restrict__ t = (const double2 *)((const double *)S.tiles + (rowbase + it.j0) * (TILE * TILE));
+    double2 v[8], w[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = ldnt(t + k * 64 + lane);
     double rI[8], acc[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -426,10 +663,12 @@ __global__ __launch_bounds__(256) void k_gemv_f64(const Seg *__restrict__ segs, 
       acc[k] = 0.0;
     }
     for (int J = it.j0; J < it.j1; ++J) {
-      const double2 *__restrict__ t = tb + (int64_t)J * (TILE * TILE / 2);
-      double2 v[8];
+      const bool more = J + 1 < it.j1;
+      t += TILE * TILE / 2;
+      if (more) {
 #pragma unroll
-      for (int k = 0; k < 8; ++k) v[k] = t[k * 64 + lane];
+        for (int k = 0; k < 8; ++k) w[k] = ldnt(t + k * 64 + lane);
+      }
       const double2 rj = *(const double2 *)(r + J * TILE + c2);
 #pragma unroll
       for (int k = 0; k < 8; ++k) acc[k] += v[k].x * rj.x + v[k].y * rj.y;
@@ -451,6 +690,10 @@ __global__ __launch_bounds__(256) void k_gemv_f64(const Seg *__restrict__ segs, 
           *(double2 *)((double *)S.colpart + (rowbase + J) * TILE + c2) = o;
         }
       }
+      if (more) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = w[k];
+      }
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -469,6 +712,8 @@ __global__ __launch_bounds__(256) void k_gemv_f64(const Seg *__restrict__ segs, 
   }
 }
 
+// FP32: 4 loads of 16 bytes per lane per tile; lane l holds rows 8m + l/8 (m < 4),
+// columns 4(l%8) .. 4(l%8)+3.
 __global__ __launch_bounds__(256) void k_gemv_f32(const Seg *__restrict__ segs, int nseg, int total,
                                                   const int *__restrict__ done) {
   if (done && *done) return;
@@ -481,7 +726,10 @@ __global__ __launch_bounds__(256) void k_gemv_f32(const Seg *__restrict__ segs, 
     const float *__restrict__ r = (const float *)S.rp;
     const int I = it.I;
     const int64_t rowbase = (int64_t)I * (I + 1) / 2;
-    const float4 *__restrict__ tb = (const float4 *)((const float *)S.tiles + rowbase * (TILE * TILE));
+    const float4 *__restrict__ t = (const float4 *)((const float *)S.tiles + (rowbase + it.j0) * (TILE * TILE));
+    float4 v[4], w[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v[m] = ldnt(t + m * 64 + lane);
     float rI[4], acc[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
@@ -489,10 +737,12 @@ __global__ __launch_bounds__(256) void k_gemv_f32(const Seg *__restrict__ segs, 
       acc[m] = 0.0f;
     }
     for (int J = it.j0; J < it.j1; ++J) {
-      const float4 *__restrict__ t = tb + (int64_t)J * (TILE * TILE / 4);
-      float4 v[4];
+      const bool more = J + 1 < it.j1;
+      t += TILE * TILE / 4;
+      if (more) {
 #pragma unroll
-      for (int m = 0; m < 4; ++m) v[m] = t[m * 64 + lane];
+        for (int m = 0; m < 4; ++m) w[m] = ldnt(t + m * 64 + lane);
+      }
       const float4 rj = *(const float4 *)(r + J * TILE + c4);
 #pragma unroll
       for (int m = 0; m < 4; ++m) acc[m] += v[m].x * rj.x + v[m].y * rj.y + v[m].z * rj.z + v[m].w * rj.w;
@@ -519,6 +769,10 @@ __global__ __launch_bounds__(256) void k_gemv_f32(const Seg *__restrict__ segs, 
           o.w = c[3];
           *(float4 *)((float *)S.colpart + (rowbase + J) * TILE + c4) = o;
         }
+      }
+      if (more) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) v[m] = w[m];
       }
     }
 #pragma unroll
@@ -571,7 +825,8 @@ __global__ __launch_bounds__(VB) void k_final(int64_t nf, const int *__restrict_
                                               const T *__restrict__ jv_xi, int64_t nent,
                                               const int32_t *__restrict__ corner_act, const double *__restrict__ yr,
                                               double *__restrict__ out, const double *__restrict__ rdot,
-                                              double *__restrict__ part1, double *__restrict__ part2) {
+                                              double *__restrict__ part1, double *__restrict__ part2,
+                                              Scalars *__restrict__ sc, int start) {
   __shared__ double red[VB / WAVE];
   if (*done) return;
   double d1 = 0.0, d2 = 0.0;
@@ -610,6 +865,8 @@ __global__ __launch_bounds__(VB) void k_final(int64_t nf, const int *__restrict_
       const double s2 = block_sum<VB>(d2, red);
       if (threadIdx.x == 0) part2[blockIdx.x] = s2;
     }
+    // one completed iteration (not for the first application)
+    if (sc && !start && blockIdx.x == 0 && threadIdx.x == 0) sc->iter = sc->iter + 1;
   }
 }
 
@@ -936,14 +1193,6 @@ template __global__ void k_jt_corners<float>(int64_t, const int *, const int32_t
                                              float *);
 template __global__ void k_combine<double>(const Seg *, int, int, const int *);
 template __global__ void k_combine<float>(const Seg *, int, int, const int *);
-template __global__ void k_final<double>(int64_t, const int *, const double *, const int32_t *, const int32_t *,
-                                         const double *, const int32_t *, const int32_t *, const double *,
-                                         const double *, int64_t, const int32_t *, const double *, double *,
-                                         const double *, double *, double *);
-template __global__ void k_final<float>(int64_t, const int *, const double *, const int32_t *, const int32_t *,
-                                        const double *, const int32_t *, const int32_t *, const float *,
-                                        const float *, int64_t, const int32_t *, const double *, double *,
-                                        const double *, double *, double *);
 template __global__ void k_sweep_pack<double>(const SweepSys *, const int32_t *, const int16_t *, const int16_t *,
                                               const int64_t *, const double *, double *);
 template __global__ void k_sweep_pack<float>(const SweepSys *, const int32_t *, const int16_t *, const int16_t *,

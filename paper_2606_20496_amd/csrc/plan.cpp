@@ -290,6 +290,18 @@ int build_plan(const PlanInput &in, Plan &P) {
       for (auto k : l) P.sh_part.push_back(k);
       P.sh_ptr.push_back((int32_t)P.sh_part.size());
     }
+    // one writer per vertex: the owning block, or the first block sharing it
+    P.slot_pw.assign(P.slot_vid.size(), 0);
+    std::vector<char> seen(nf, 0);
+    for (size_t gs = 0; gs < P.slot_vid.size(); ++gs) {
+      const int32_t u = P.slot_vid[gs];
+      if (!seen[u]) {
+        seen[u] = 1;
+        P.slot_pw[gs] = 1;
+      }
+    }
+    P.sh_idx.assign(nf, -1);
+    for (size_t k = 0; k < P.sh_vid.size(); ++k) P.sh_idx[P.sh_vid[k]] = (int32_t)k;
   }
 
   // ---- overlapping subdomains and R_p (Sec. 3) --------------------------------

@@ -69,6 +69,8 @@ struct Plan {
   std::vector<int32_t> sh_vid;         // shared vertices
   std::vector<int32_t> sh_ptr;         // [n_shared+1] into partial ids (block order)
   std::vector<int32_t> sh_part;
+  std::vector<uint8_t> slot_pw;        // 1: the slot's block writes the vertex (first block touching it)
+  std::vector<int32_t> sh_idx;         // [n_free] index into sh_ptr or -1
 
   // free vertex -> incident (element, local vertex) pairs, element order
   std::vector<int32_t> vinc_ptr;       // [n_free+1]

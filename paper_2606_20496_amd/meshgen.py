@@ -272,6 +272,21 @@ def serving_arrivals(rate, count=4096, seed=59999, reuse=0.3):
     return t, mesh_id, rhs_seed
 
 
+def rhs_bumps(mesh: Mesh, seed: int, bumps: int = 20, noise: float = 1e-3) -> np.ndarray:
+    """A fresh RHS of ``bumps`` Gaussian bumps (width 0.05, centres uniform in the
+    bounding box, amplitudes N(0,1)) plus N(0, noise^2) values (0 on Dirichlet)."""
+    rng = np.random.default_rng(seed)
+    lo, hi = mesh.xyz.min(0), mesh.xyz.max(0)
+    centres = lo + (hi - lo) * rng.random((bumps, 3))
+    amps = rng.standard_normal(bumps)
+    b = np.zeros(mesh.n_vert)
+    for c, a in zip(centres, amps):
+        b += a * np.exp(-((mesh.xyz - c) ** 2).sum(1) / (2.0 * 0.05 ** 2))
+    b += noise * rng.standard_normal(mesh.n_vert)
+    b[mesh.dirichlet.astype(bool)] = 0.0
+    return b
+
+
 def rhs_normal(mesh: Mesh, seed: int) -> np.ndarray:
     """A fresh i.i.d. N(0,1) RHS for ``mesh`` (0 on Dirichlet vertices)."""
     b = np.random.default_rng(seed).standard_normal(mesh.n_vert)
