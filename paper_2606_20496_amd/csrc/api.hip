@@ -105,6 +105,9 @@ struct coarse_ctx {
   int32_t *jv_ptr = nullptr, *jv_occ = nullptr, *jc_vid = nullptr, *jt_start = nullptr, *jr_ptr = nullptr,
           *jr_src = nullptr, *corner_act = nullptr;
   void *jv_w = nullptr, *jv_xi = nullptr, *jc_w = nullptr, *jc_xi = nullptr, *jt_part = nullptr;
+  int32_t *jv_base = nullptr, *act_bv = nullptr;
+  double *yfull = nullptr;   // reduced solution on all (b+1)^3 box vertices (0 where inactive)
+  int bx1 = 1, bxy1 = 1;
 
   // phase timers
   static constexpr int NPH = 7;
@@ -179,7 +182,7 @@ struct coarse_ctx {
 
   template <typename T>
   void corners(const int *done) {
-    hipLaunchKernelGGL(k_jt_corners<T>, dim3(nblk(n_r, 256)), dim3(256), 0, stream, n_r, done, jr_ptr, jr_src,
+    hipLaunchKernelGGL(k_jt_corners<T>, dim3(nblk(n_r, 4)), dim3(256), 0, stream, n_r, done, jr_ptr, jr_src,
                        (const T *)jt_part, (T *)rp + coarse_vec_off);
   }
 
@@ -208,8 +211,8 @@ struct coarse_ctx {
                   const int *done, bool scal, int start) {
     pbeg(5);
     hipLaunchKernelGGL(k_final<T>, dim3(nvblk), dim3(VB), 0, stream, nf, done, add, local ? cover_ptr : nullptr,
-                       cover_pos, zp, coarse ? jv_ptr : nullptr, jv_occ, (const T *)jv_w, (const T *)jv_xi, nent,
-                       corner_act, zp + coarse_vec_off, out, rdot, p1, p2, scal ? sc : nullptr, start);
+                       cover_pos, zp, coarse ? jv_ptr : nullptr, jv_base, (const T *)jv_w, (const T *)jv_xi, nent, bx1,
+                       bxy1, (const double *)yfull, out, rdot, p1, p2, scal ? sc : nullptr, start);
     pend(5);
   }
 
@@ -449,9 +452,8 @@ void setup_precision(coarse_ctx *c, Plan &P) {
   op.partials = A.alloc<double>(std::max<int64_t>(1, P.n_partials));
   op.sh_vid = A.upload(P.sh_vid, s);
   op.sh_ptr = A.upload(P.sh_ptr, s);
-  op.sh_part = A.upload(P.sh_part, s);
   op.slot_pw = A.upload(P.slot_pw, s);
-  op.sh_idx = A.upload(P.sh_idx, s);
+  op.vq = (const int2 *)A.upload(P.vq, s);
   op.lds_bytes = (int32_t)((OP_BLOCK * 8 + P.max_slots) * sizeof(double));
   if (op.lds_bytes > 64 * 1024) throw Fail(COARSE_EINVAL, "operator block touches too many vertices");
 
@@ -533,6 +535,13 @@ void setup_precision(coarse_ctx *c, Plan &P) {
   });
   if (nbad) throw Fail(COARSE_ESINGULAR, "reduced system A_r not positive definite (empty interior box?)");
 
+  // reduced solution on the full box-vertex grid (inactive vertices stay 0)
+  c->yfull = A.alloc<double>(P.n_bv);
+  HIPCHK(hipMemsetAsync(c->yfull, 0, P.n_bv * sizeof(double), s));
+  c->act_bv = A.upload(P.act_bv, s);
+  c->bx1 = P.b[0] + 1;
+  c->bxy1 = (P.b[0] + 1) * (P.b[1] + 1);
+
   // GEMV items, combine rows, system table, segments
   std::vector<SysDev> sd(P.sys.size());
   for (size_t k = 0; k < P.sys.size(); ++k) {
@@ -542,6 +551,10 @@ void setup_precision(coarse_ctx *c, Plan &P) {
     sd[k].colpart = (T *)c->colpart + (size_t)S.tile_off * TILE;
     sd[k].zp = c->zp + S.vec_off;
     sd[k].nb = (int32_t)S.nb;
+    sd[k].n = (int32_t)S.n;
+    const bool red_sys = (int64_t)k == P.n_local_sys;
+    sd[k].yfull = red_sys ? c->yfull : nullptr;
+    sd[k].act_bv = red_sys ? c->act_bv : nullptr;
   }
   // item slots: index within the system's item list
   std::vector<int64_t> sys_item0(P.sys.size(), -1);
@@ -587,7 +600,7 @@ void setup_precision(coarse_ctx *c, Plan &P) {
   // reduced-space interpolation entries
   c->nent = (int64_t)P.jv_w.size();
   c->jv_ptr = A.upload(P.jv_ptr, s);
-  c->jv_occ = A.upload(P.jv_occ, s);
+  c->jv_base = A.upload(P.jv_base, s);
   c->jv_w = A.upload(cast_vec<T>(P.jv_w), s);
   c->jv_xi = A.upload(cast_vec<T>(P.jv_xi), s);
   c->jc_vid = A.upload(P.jc_vid, s);

@@ -22,7 +22,9 @@ struct SysDev {
   void *colpart;       // per tile: transposed contribution (TILE entries)
   void *rowpart;       // per work item: row contribution (TILE entries)
   double *zp;          // solution (nb*TILE entries)
-  int32_t nb, pad;
+  double *yfull;       // reduced system only: solution scattered to all box vertices
+  const int32_t *act_bv;   // reduced system only: active index -> box vertex
+  int32_t nb, n;
 };
 
 // GEMV work item: tiles (I, j0 .. j1-1) of system `sys`; `slot` indexes the
@@ -55,9 +57,9 @@ struct OpDev {
   const int32_t *blk_slot_ptr, *slot_vid, *slot_dst, *slot_inc_ptr;
   const uint16_t *slot_inc;
   double *partials;
-  const int32_t *sh_vid, *sh_ptr, *sh_part;
+  const int32_t *sh_vid, *sh_ptr;
   const uint8_t *slot_pw;     // 1: this slot's block writes the vertex's search direction
-  const int32_t *sh_idx;      // free vertex -> index into sh_ptr, or -1 (owned by one block)
+  const int2 *vq;             // free vertex -> (first partial, count); count 0: owned by one block
   int32_t lds_bytes;
 };
 

@@ -151,7 +151,7 @@ __global__ __launch_bounds__(256) void k_op_pass2(OpDev op, double *__restrict__
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= op.n_shared) return;
   double acc = 0.0;
-  for (int k = op.sh_ptr[i]; k < op.sh_ptr[i + 1]; ++k) acc += op.partials[op.sh_part[k]];
+  for (int k = op.sh_ptr[i]; k < op.sh_ptr[i + 1]; ++k) acc += op.partials[k];
   q[op.sh_vid[i]] = acc;
 }
 
@@ -432,13 +432,21 @@ __global__ __launch_bounds__(VB) void k_update_fused(int64_t nf, OpDev op, Scala
   double acc = 0.0;
   const int64_t G = (int64_t)gridDim.x * VB;
   for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < nf; i += G) {
-    const int32_t sh = op.sh_idx[i];
+    const int2 vq = op.vq[i];
     double qi;
-    if (sh < 0) {
+    if (vq.y == 0) {
       qi = q[i];
     } else {
+      // the partials of a shared vertex are contiguous: issue the loads together
       qi = 0.0;
-      for (int k = op.sh_ptr[sh]; k < op.sh_ptr[sh + 1]; ++k) qi += op.partials[op.sh_part[k]];
+      for (int k0 = 0; k0 < vq.y; k0 += 8) {
+        double pv[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) pv[k] = (k0 + k < vq.y) ? op.partials[vq.x + k0 + k] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (k0 + k < vq.y) qi += pv[k];
+      }
     }
     x[i] += alpha * p[i];
     const double ri = r[i] - alpha * qi;
@@ -499,6 +507,45 @@ __global__ __launch_bounds__(256) void k_check(Scalars *__restrict__ sc, const d
 
 // Restriction R_p r into the packed local vectors (workgroups [0, ng)) and the
 // first stage of J^T r (the remaining workgroups, one task per wavefront).
+// One restriction task (a wavefront): the 8 corner sums of at most JT_CHUNK
+// entries (i, c) of one cell, weight w_ic = n_ic/m_i times the trilinear
+// weights at the local coordinates of vertex i, applied to in[i]. Each lane takes
+// at most JT_CHUNK/64 entries, loaded together.
+template <typename T>
+__device__ __forceinline__ void jt_task(int task, const int32_t *__restrict__ tstart, const int32_t *__restrict__ vid,
+                                        const T *__restrict__ w, const T *__restrict__ xi, int64_t nent,
+                                        const double *__restrict__ in, T *__restrict__ tpart) {
+  constexpr int PER = JT_CHUNK / 64;
+  const int lane = threadIdx.x & 63;
+  const int j0 = tstart[task], j1 = tstart[task + 1];
+  int jj[PER];
+  T v[PER], x[PER], y[PER], z[PER];
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int j = j0 + lane + 64 * m;
+    jj[m] = (j < j1) ? vid[j] : -1;
+    v[m] = (j < j1) ? w[j] : T(0);
+    x[m] = (j < j1) ? xi[j] : T(0);
+    y[m] = (j < j1) ? xi[nent + j] : T(0);
+    z[m] = (j < j1) ? xi[2 * nent + j] : T(0);
+  }
+#pragma unroll
+  for (int m = 0; m < PER; ++m) v[m] = (jj[m] >= 0) ? v[m] * (T)in[jj[m]] : T(0);
+  T acc[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    acc[k] = T(0);
+#pragma unroll
+    for (int m = 0; m < PER; ++m) acc[k] += trilin<T>(k, x[m], y[m], z[m]) * v[m];
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) acc[k] = wave_sum(acc[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) tpart[task * 8 + k] = acc[k];
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_pre(int ng, int64_t n, const int *__restrict__ done, const int32_t *__restrict__ idx,
                                              const double *__restrict__ in, T *__restrict__ rp, int ntask,
@@ -517,24 +564,9 @@ __global__ __launch_bounds__(256) void k_pre(int ng, int64_t n, const int *__res
     }
     return;
   }
-  const int lane = threadIdx.x & 63;
   const int task = (blockIdx.x - ng) * 4 + (threadIdx.x >> 6);
   if (task >= ntask) return;
-  T acc[8];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) acc[k] = T(0);
-  for (int j = tstart[task] + lane; j < tstart[task + 1]; j += 64) {
-    const T v = w[j] * (T)in[vid[j]];
-    const T x = xi[j], y = xi[nent + j], z = xi[2 * nent + j];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) acc[k] += trilin<T>(k, x, y, z) * v;
-  }
-#pragma unroll
-  for (int k = 0; k < 8; ++k) acc[k] = wave_sum(acc[k]);
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) tpart[task * 8 + k] = acc[k];
-  }
+  jt_task<T>(task, tstart, vid, w, xi, nent, in, tpart);
 }
 
 // ---------------------------------------------------------------------------
@@ -564,36 +596,25 @@ __global__ __launch_bounds__(256) void k_jt_tasks(int ntask, const int *__restri
                                                   const T *__restrict__ xi, int64_t nent, const double *__restrict__ in,
                                                   T *__restrict__ tpart) {
   if (*done) return;
-  const int lane = threadIdx.x & 63;
   const int task = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (task >= ntask) return;
-  T acc[8];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) acc[k] = T(0);
-  for (int j = tstart[task] + lane; j < tstart[task + 1]; j += 64) {
-    const T v = w[j] * (T)in[vid[j]];
-    const T x = xi[j], y = xi[nent + j], z = xi[2 * nent + j];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) acc[k] += trilin<T>(k, x, y, z) * v;
-  }
-#pragma unroll
-  for (int k = 0; k < 8; ++k) acc[k] = wave_sum(acc[k]);
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) tpart[task * 8 + k] = acc[k];
-  }
+  jt_task<T>(task, tstart, vid, w, xi, nent, in, tpart);
 }
 
+// Second stage of J^T: one wavefront per active box vertex sums the task
+// partials of the occupied cells around it (lane-strided, then across the wave).
 template <typename T>
 __global__ __launch_bounds__(256) void k_jt_corners(int64_t nr, const int *__restrict__ done, const int32_t *__restrict__ ptr,
                                                     const int32_t *__restrict__ src, const T *__restrict__ tpart,
                                                     T *__restrict__ rr) {
   if (*done) return;
-  const int64_t K = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t K = blockIdx.x * (int64_t)4 + (threadIdx.x >> 6);
   if (K >= nr) return;
   T acc = T(0);
-  for (int k = ptr[K]; k < ptr[K + 1]; ++k) acc += tpart[src[k]];
-  rr[K] = acc;
+  for (int k = ptr[K] + lane; k < ptr[K + 1]; k += 64) acc += tpart[src[k]];
+  acc = wave_sum(acc);
+  if (lane == 0) rr[K] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -807,8 +828,22 @@ __global__ __launch_bounds__(256) void k_combine(const Seg *__restrict__ segs, i
   const T *colp = (const T *)S.colpart;
   double acc = 0.0;
   for (int k = 0; k < rw.nslot; ++k) acc += (double)rowp[(int64_t)(rw.slot0 + k) * TILE + c];
-  for (int I2 = rw.I + 1; I2 < S.nb; ++I2) acc += (double)colp[((int64_t)I2 * (I2 + 1) / 2 + rw.I) * TILE + c];
+  // column partials of tiles (I2, I), I2 > I: loads issued four at a time, summed in order
+  for (int I2 = rw.I + 1; I2 < S.nb; I2 += 4) {
+    T v[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      v[m] = (I2 + m < S.nb) ? colp[((int64_t)(I2 + m) * (I2 + m + 1) / 2 + rw.I) * TILE + c] : T(0);
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      if (I2 + m < S.nb) acc += (double)v[m];
+  }
   S.zp[rw.I * TILE + c] = acc;
+  // the reduced solution is also scattered onto the full box-vertex grid
+  if (S.yfull) {
+    const int K = rw.I * TILE + c;
+    if (K < S.n) S.yfull[S.act_bv[K]] = acc;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -821,12 +856,11 @@ template <typename T>
 __global__ __launch_bounds__(VB) void k_final(int64_t nf, const int *__restrict__ done, const double *__restrict__ add,
                                               const int32_t *__restrict__ cover_ptr, const int32_t *__restrict__ cover_pos,
                                               const double *__restrict__ zp, const int32_t *__restrict__ jv_ptr,
-                                              const int32_t *__restrict__ jv_occ, const T *__restrict__ jv_w,
-                                              const T *__restrict__ jv_xi, int64_t nent,
-                                              const int32_t *__restrict__ corner_act, const double *__restrict__ yr,
-                                              double *__restrict__ out, const double *__restrict__ rdot,
-                                              double *__restrict__ part1, double *__restrict__ part2,
-                                              Scalars *__restrict__ sc, int start) {
+                                              const int32_t *__restrict__ jv_base, const T *__restrict__ jv_w,
+                                              const T *__restrict__ jv_xi, int64_t nent, int bx1, int bxy1,
+                                              const double *__restrict__ yfull, double *__restrict__ out,
+                                              const double *__restrict__ rdot, double *__restrict__ part1,
+                                              double *__restrict__ part2, Scalars *__restrict__ sc, int start) {
   __shared__ double red[VB / WAVE];
   if (*done) return;
   double d1 = 0.0, d2 = 0.0;
@@ -834,19 +868,33 @@ __global__ __launch_bounds__(VB) void k_final(int64_t nf, const int *__restrict_
   for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < nf; i += G) {
     double acc = add ? add[i] : 0.0;
     if (cover_ptr) {
-      for (int k = cover_ptr[i]; k < cover_ptr[i + 1]; ++k) acc += zp[cover_pos[k]];
+      // local solutions covering vertex i, loads issued eight at a time, summed in order
+      const int c0 = cover_ptr[i], c1 = cover_ptr[i + 1];
+      for (int k0 = c0; k0 < c1; k0 += 8) {
+        int pos[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) pos[m] = (k0 + m < c1) ? cover_pos[k0 + m] : -1;
+        double v[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v[m] = (pos[m] >= 0) ? zp[pos[m]] : 0.0;
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+          if (pos[m] >= 0) acc += v[m];
+      }
     }
     if (jv_ptr) {
+      // J y_r: the corners of the entry's cell are box vertices base + {0,1} +
+      // bx1 {0,1} + bxy1 {0,1} of the full grid (inactive ones hold 0)
       T cs = T(0);
       for (int k = jv_ptr[i]; k < jv_ptr[i + 1]; ++k) {
-        const int32_t *ca = corner_act + 8 * (int64_t)jv_occ[k];
+        const int b0 = jv_base[k];
         const T x = jv_xi[k], y = jv_xi[nent + k], z = jv_xi[2 * nent + k];
+        double yc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) yc[q] = yfull[b0 + (q & 1) + ((q >> 1) & 1) * bx1 + ((q >> 2) & 1) * bxy1];
         T s = T(0);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int32_t a = ca[q];
-          if (a >= 0) s += trilin<T>(q, x, y, z) * (T)yr[a];
-        }
+        for (int q = 0; q < 8; ++q) s += trilin<T>(q, x, y, z) * (T)yc[q];
         cs += jv_w[k] * s;
       }
       acc += (double)cs;

@@ -270,26 +270,32 @@ int build_plan(const PlanInput &in, Plan &P) {
       P.max_slots = std::max<int64_t>(P.max_slots, (int64_t)verts.size());
     }
     if (P.slot_inc_ptr.empty()) P.slot_inc_ptr.push_back(0);
-    // partial ids in slot order (block order); per shared vertex list them
+    // partial ids grouped by vertex (vertices in order of first appearance, each
+    // vertex's partials contiguous and in block order), so the sum over a shared
+    // vertex reads one contiguous range
     P.n_partials = (int64_t)shared_blocks.size();
     std::vector<int32_t> sh_index(NV, -1);
-    std::vector<std::vector<int32_t>> per_vertex;
+    std::vector<int32_t> count;
     for (int64_t k = 0; k < P.n_partials; ++k) {
-      int64_t gs = shared_blocks[k];
-      P.slot_dst[gs] = -(int32_t)(k + 1);
-      int32_t u = P.slot_vid[gs];
+      const int32_t u = P.slot_vid[shared_blocks[k]];
       if (sh_index[u] < 0) {
-        sh_index[u] = (int32_t)per_vertex.size();
-        per_vertex.emplace_back();
+        sh_index[u] = (int32_t)count.size();
+        count.push_back(0);
         P.sh_vid.push_back(u);
       }
-      per_vertex[sh_index[u]].push_back((int32_t)k);
+      count[sh_index[u]]++;
     }
-    P.sh_ptr.assign(1, 0);
-    for (auto &l : per_vertex) {
-      for (auto k : l) P.sh_part.push_back(k);
-      P.sh_ptr.push_back((int32_t)P.sh_part.size());
+    P.sh_ptr.assign(count.size() + 1, 0);
+    for (size_t j = 0; j < count.size(); ++j) P.sh_ptr[j + 1] = P.sh_ptr[j] + count[j];
+    {
+      std::vector<int32_t> fill(P.sh_ptr.begin(), P.sh_ptr.end() - 1);
+      for (int64_t k = 0; k < P.n_partials; ++k) {
+        const int64_t gs = shared_blocks[k];
+        const int32_t pid = fill[sh_index[P.slot_vid[gs]]]++;
+        P.slot_dst[gs] = -(pid + 1);
+      }
     }
+    P.sh_part.clear();
     // one writer per vertex: the owning block, or the first block sharing it
     P.slot_pw.assign(P.slot_vid.size(), 0);
     std::vector<char> seen(nf, 0);
@@ -300,8 +306,12 @@ int build_plan(const PlanInput &in, Plan &P) {
         P.slot_pw[gs] = 1;
       }
     }
-    P.sh_idx.assign(nf, -1);
-    for (size_t k = 0; k < P.sh_vid.size(); ++k) P.sh_idx[P.sh_vid[k]] = (int32_t)k;
+    // per free vertex: (first partial, count), count 0 = owned by one block
+    P.vq.assign(2 * nf, 0);
+    for (size_t j = 0; j < P.sh_vid.size(); ++j) {
+      P.vq[2 * P.sh_vid[j]] = P.sh_ptr[j];
+      P.vq[2 * P.sh_vid[j] + 1] = P.sh_ptr[j + 1] - P.sh_ptr[j];
+    }
   }
 
   // ---- overlapping subdomains and R_p (Sec. 3) --------------------------------
@@ -485,6 +495,12 @@ int build_plan(const PlanInput &in, Plan &P) {
   }
   P.jv_occ.resize(nent);
   for (int64_t k = 0; k < nent; ++k) P.jv_occ[k] = P.cell_occ[ent_cell[k]];
+  P.jv_base.resize(nent);
+  for (int64_t k = 0; k < nent; ++k) {
+    int32_t c3[3];
+    cell_xyz(ent_cell[k], c3);
+    P.jv_base[k] = (int32_t)corner_bv(c3, 0);
+  }
 
   // cell-major copy of the entries, cut into restriction tasks
   {

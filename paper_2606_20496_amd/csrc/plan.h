@@ -14,7 +14,7 @@ constexpr int TILE = 32;
 // Elements per workgroup of the operator kernel.
 constexpr int OP_BLOCK = 256;
 // Tiles per GEMV work item (one wavefront streams at most this many tiles).
-constexpr int GEMV_SEG = 8;
+constexpr int GEMV_SEG = 4;
 // Reduced-space entries per restriction task (one wavefront).
 constexpr int JT_CHUNK = 256;
 
@@ -67,10 +67,10 @@ struct Plan {
   std::vector<uint16_t> lconn;         // SoA [8][E]: slot of local vertex a (0xFFFF = Dirichlet)
   int64_t n_partials = 0;
   std::vector<int32_t> sh_vid;         // shared vertices
-  std::vector<int32_t> sh_ptr;         // [n_shared+1] into partial ids (block order)
-  std::vector<int32_t> sh_part;
+  std::vector<int32_t> sh_ptr;         // [n_shared+1] partial ids of shared vertex j: [sh_ptr[j], sh_ptr[j+1])
+  std::vector<int32_t> sh_part;        // unused (partials are contiguous per vertex)
   std::vector<uint8_t> slot_pw;        // 1: the slot's block writes the vertex (first block touching it)
-  std::vector<int32_t> sh_idx;         // [n_free] index into sh_ptr or -1
+  std::vector<int32_t> vq;             // [n_free][2]: first partial and count (0 = owned)
 
   // free vertex -> incident (element, local vertex) pairs, element order
   std::vector<int32_t> vinc_ptr;       // [n_free+1]
@@ -109,6 +109,7 @@ struct Plan {
   // vertex-major interpolation entries (prolongation J)
   std::vector<int32_t> jv_ptr;           // [n_free+1]
   std::vector<int32_t> jv_occ;           // occupied-cell index of the entry
+  std::vector<int32_t> jv_base;          // box-vertex id of the entry's cell corner 0
   std::vector<double> jv_w;              // weight fraction n_ic/m_i
   std::vector<double> jv_xi;             // [3][n_entries] local coordinates
   // cell-major entries (restriction J^T)
