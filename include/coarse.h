@@ -172,6 +172,30 @@ int coarse_solve(coarse_ctx *ctx, const double *b, double *u, double tol, coarse
 int coarse_solve_batch(coarse_ctx *const *ctxs, const double *const *b, double *const *u,
                        int count, double tol, coarse_stats *st);
 
+/* Continuous batching (lock-step solves). A batch advances every live solve by
+ * whole PCG iterations: each solve's own kernels run on one of a few internal
+ * side streams, and the dense local and reduced solves of all live solves run as
+ * ONE GEMV launch (and one partial-sum launch) per iteration. Solves join with
+ * coarse_batch_submit and leave when coarse_batch_step reports them finished, so
+ * requests that arrive while others are running are admitted between steps.
+ * Results are bitwise identical to coarse_solve of the same context and RHS.
+ * Contexts must use the additive preconditioner and share one precision; while
+ * in a batch a context must not be used otherwise. `stream` orders the batch
+ * against the caller (inputs must be ready on it before submit); use_graph = 1
+ * captures one lock step as a HIP graph and replays it (needs a non-null stream;
+ * the graph is rebuilt when the set of live solves changes). */
+typedef struct coarse_batch coarse_batch;
+int coarse_batch_create(void *stream, int use_graph, coarse_batch **out);
+/* Start the solve of ctx for right-hand side b into u (device, as in
+ * coarse_solve); tag is returned by coarse_batch_step when it finishes. */
+int coarse_batch_submit(coarse_batch *bt, coarse_ctx *ctx, const double *b, double *u, double tol, int64_t tag);
+/* Advance all live solves by `iters` lock steps, then retire the finished ones:
+ * their u is written (stream-ordered before later work on `stream`), and up to
+ * cap of them are reported in tags[] / stats[] (*n_done of them). */
+int coarse_batch_step(coarse_batch *bt, int iters, int64_t *tags, coarse_stats *stats, int cap, int *n_done);
+int coarse_batch_live(const coarse_batch *bt);
+int coarse_batch_destroy(coarse_batch *bt);
+
 /* Release all memory of the context. NULL is accepted. */
 int coarse_destroy(coarse_ctx *ctx);
 

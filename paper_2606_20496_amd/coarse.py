@@ -25,7 +25,8 @@ STATUS = {0: "ok", 1: "notconv", -1: "einval", -2: "enomem", -3: "emesh", -4: "e
 EXPORTS = ("coarse_default_opts", "coarse_setup", "coarse_apply_precond", "coarse_apply_A",
            "coarse_solve", "coarse_solve_batch", "coarse_destroy", "coarse_device_bytes",
            "coarse_get_info", "coarse_set_stream", "coarse_plan_info", "coarse_strerror",
-           "coarse_last_error", "coarse_profile")
+           "coarse_last_error", "coarse_profile", "coarse_batch_create", "coarse_batch_submit",
+           "coarse_batch_step", "coarse_batch_live", "coarse_batch_destroy")
 
 PHASES = ("A+p", "R_p+J^T", "J^T corners", "A_p^-1/A_r^-1 gemv", "combine", "sum+J", "x,r update")
 
@@ -111,6 +112,16 @@ def load():
     L.coarse_strerror.restype = ctypes.c_char_p
     L.coarse_profile.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), i32]
     L.coarse_profile.restype = i32
+    L.coarse_batch_create.argtypes = [vp, i32, ctypes.POINTER(vp)]
+    L.coarse_batch_create.restype = i32
+    L.coarse_batch_submit.argtypes = [vp, vp, vp, vp, dbl, i64]
+    L.coarse_batch_submit.restype = i32
+    L.coarse_batch_step.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(_Stats), i32, ctypes.POINTER(i32)]
+    L.coarse_batch_step.restype = i32
+    L.coarse_batch_live.argtypes = [vp]
+    L.coarse_batch_live.restype = i32
+    L.coarse_batch_destroy.argtypes = [vp]
+    L.coarse_batch_destroy.restype = i32
     L.coarse_last_error.argtypes = [vp]
     L.coarse_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -289,3 +300,65 @@ def solve_batch(solvers, bs, tol=1e-8, outs=None):
     if rc < 0:
         raise CoarseError(rc, "batch solve failed")
     return outs, [{f: getattr(s, f) for f, _ in _Stats._fields_} for s in st]
+
+
+class Batch:
+    """Lock-step batch of independent solves (continuous batching): solves join with
+    :meth:`submit` and leave when :meth:`step` reports them finished. All dense local
+    and reduced solves of the live solves run in one GEMV launch per iteration.
+
+    ``stream``: a ``torch.cuda.Stream`` ordering the batch against the caller (the
+    right-hand sides must be ready on it); ``use_graph`` replays one captured lock
+    step as a HIP graph (needs a non-default stream)."""
+
+    def __init__(self, stream=None, use_graph=False):
+        import torch
+        L = load()
+        self._L = L
+        self.stream = stream
+        handle = ctypes.c_void_p(stream.cuda_stream) if stream is not None else ctypes.c_void_p(
+            torch.cuda.current_stream().cuda_stream)
+        bt = ctypes.c_void_p()
+        rc = L.coarse_batch_create(handle, int(bool(use_graph)), ctypes.byref(bt))
+        if rc != 0:
+            raise CoarseError(rc, L.coarse_last_error(None).decode())
+        self._bt = bt
+        self._keep = {}
+
+    def submit(self, solver, b, u, tag, tol=1e-8):
+        rc = self._L.coarse_batch_submit(self._bt, solver._ctx, solver._vec(b), solver._vec(u), float(tol), int(tag))
+        if rc != 0:
+            raise CoarseError(rc, "batch submit failed")
+        self._keep[int(tag)] = (solver, b, u)
+
+    def step(self, iters=1, cap=4096):
+        """Advance every live solve by ``iters`` iterations; returns [(tag, stats)] of
+        the solves that finished."""
+        tags = (ctypes.c_int64 * cap)()
+        st = (_Stats * cap)()
+        nd = ctypes.c_int(0)
+        rc = self._L.coarse_batch_step(self._bt, int(iters), tags, st, int(cap), ctypes.byref(nd))
+        if rc != 0:
+            raise CoarseError(rc, "batch step failed")
+        out = []
+        for k in range(nd.value):
+            d = {f: getattr(st[k], f) for f, _ in _Stats._fields_}
+            d["code"] = d["status"]
+            out.append((int(tags[k]), d))
+            self._keep.pop(int(tags[k]), None)
+        return out
+
+    @property
+    def live(self):
+        return int(self._L.coarse_batch_live(self._bt))
+
+    def close(self):
+        if getattr(self, "_bt", None):
+            self._L.coarse_batch_destroy(self._bt)
+            self._bt = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -290,6 +290,11 @@ struct coarse_ctx {
   //   alpha, x += alpha p_k, r -= alpha q, ||r||^2  (update kernel)
   //   stop?, z = M r, (r, z)                        (preconditioner kernels)
   void iteration() {
+    op_update();
+    precond(r, z, r, part1, flexible ? part2 : nullptr, done_flag, true, 0, prr);
+  }
+
+  void op_update() {
     pbeg(0);
     hipLaunchKernelGGL(k_op_fused, dim3((unsigned)op.n_blocks), dim3(OP_BLOCK), op.lds_bytes, stream, op,
                        (const double *)z, p, pb, q, energy, sc, (const double *)part1, (const double *)part2, nvblk);
@@ -298,7 +303,32 @@ struct coarse_ctx {
     hipLaunchKernelGGL(k_update_fused, dim3(nvblk), dim3(VB), 0, stream, nf, op, sc, x, r, (const double *)p,
                        (const double *)pb, (const double *)q, (const double *)energy, (int)op.n_blocks, prr);
     pend(6);
-    precond(r, z, r, part1, flexible ? part2 : nullptr, done_flag, true, 0, prr);
+  }
+
+  // The additive iteration split around the dense solves, for lock-step batches:
+  // front = operator, update, convergence test, R_p and J^T; back = overlap sum and
+  // prolongation. The batched GEMV + combine of all live solves goes in between.
+  template <typename T>
+  void front_t() {
+    op_update();
+    const int ng = (int)nblk(coarse_vec_off, 256);
+    const int nt = (int)nblk(ntask, 4);
+    hipLaunchKernelGGL(k_pre<T>, dim3(ng + nt), dim3(256), 0, stream, ng, coarse_vec_off, done_flag, sub_idx, r,
+                       (T *)rp, (int)ntask, jt_start, jc_vid, (const T *)jc_w, (const T *)jc_xi, nent, (T *)jt_part, sc,
+                       (const double *)prr, nvblk, 0);
+    corners<T>(done_flag);
+  }
+  void front() {
+    if (precision == COARSE_FP64)
+      front_t<double>();
+    else
+      front_t<float>();
+  }
+  void back() {
+    if (precision == COARSE_FP64)
+      final_step<double>(nullptr, true, true, z, r, part1, flexible ? part2 : nullptr, done_flag, true, 0);
+    else
+      final_step<float>(nullptr, true, true, z, r, part1, flexible ? part2 : nullptr, done_flag, true, 0);
   }
 
   void start(const double *b, double tol) {
@@ -590,9 +620,9 @@ void setup_precision(coarse_ctx *c, Plan &P) {
   c->items_total = (int32_t)gi.size();
   c->rows_local = rl;
   c->rows_total = (int32_t)gr.size();
-  c->h_seg_all = Seg{c->items, c->rows, c->sysdev, 0, 0};
+  c->h_seg_all = Seg{c->items, c->rows, c->sysdev, nullptr, 0, 0};
   c->h_seg_local = c->h_seg_all;
-  c->h_seg_coarse = Seg{c->items + il, c->rows + rl, c->sysdev, 0, 0};
+  c->h_seg_coarse = Seg{c->items + il, c->rows + rl, c->sysdev, nullptr, 0, 0};
   c->seg_all = A.upload(std::vector<Seg>{c->h_seg_all}, s);
   c->seg_local = A.upload(std::vector<Seg>{c->h_seg_local}, s);
   c->seg_coarse = A.upload(std::vector<Seg>{c->h_seg_coarse}, s);
@@ -659,6 +689,192 @@ PlanInput make_input(const coarse_mesh *mesh, const coarse_bc *bc, const coarse_
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// Lock-step batch of independent solves (continuous batching). Every live solve
+// advances one PCG iteration per lock step: its own kernels (operator, update,
+// convergence test, R_p, J^T, then the overlap sum and prolongation) run on one of
+// a few side streams, and the dense local and reduced solves of all live solves
+// go into ONE GEMV launch and ONE combine launch on the main stream. Solves join
+// and leave only between steps. A solve's arithmetic never depends on the others,
+// so its result is bitwise the same alone or in any mix.
+// ---------------------------------------------------------------------------
+struct coarse_batch {
+  static constexpr int NS = 4;
+  std::string err;
+  hipStream_t main = nullptr;
+  hipStream_t side[NS] = {};
+  hipEvent_t ev_fork = nullptr, ev_mid = nullptr, ev_join[NS] = {};
+  struct Entry {
+    coarse_ctx *c;
+    const double *b;
+    double *u;
+    int64_t tag;
+    double t0;
+    hipStream_t saved_stream;
+  };
+  std::vector<Entry> live;
+  int precision = -1;
+  bool dirty = true, use_graph = false;
+  Seg *d_seg = nullptr;      // [2][cap]: item segments, then row segments
+  Seg *h_seg = nullptr;      // pinned staging
+  int cap = 0, n_items = 0, n_rows = 0;
+  hipGraphExec_t gexec = nullptr;
+
+  void init(hipStream_t s, bool graph) {
+    main = s;
+    use_graph = graph && s != nullptr;   // the null stream cannot be captured
+    for (int k = 0; k < NS; ++k) {
+      HIPCHK(hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&ev_join[k], hipEventDisableTiming));
+    }
+    HIPCHK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ev_mid, hipEventDisableTiming));
+  }
+
+  ~coarse_batch() {
+    if (main) (void)hipStreamSynchronize(main);
+    for (auto &e : live) {
+      (void)hipStreamSynchronize(e.c->stream);
+      e.c->stream = e.saved_stream;
+    }
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (d_seg) (void)hipFree(d_seg);
+    if (h_seg) (void)hipHostFree(h_seg);
+    for (int k = 0; k < NS; ++k) {
+      if (side[k]) (void)hipStreamDestroy(side[k]);
+      if (ev_join[k]) (void)hipEventDestroy(ev_join[k]);
+    }
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_mid) (void)hipEventDestroy(ev_mid);
+  }
+
+  void fork_sides(hipEvent_t ev) {
+    HIPCHK(hipEventRecord(ev, main));
+    for (int k = 0; k < NS; ++k) HIPCHK(hipStreamWaitEvent(side[k], ev, 0));
+  }
+  void join_sides() {
+    for (int k = 0; k < NS; ++k) {
+      HIPCHK(hipEventRecord(ev_join[k], side[k]));
+      HIPCHK(hipStreamWaitEvent(main, ev_join[k], 0));
+    }
+  }
+
+  int submit(coarse_ctx *c, const double *b, double *u, double tol, int64_t tag) {
+    if (c->mode != COARSE_ADDITIVE) {
+      err = "batched solves use the additive preconditioner";
+      return COARSE_EINVAL;
+    }
+    if (precision >= 0 && c->precision != precision) {
+      err = "all solves of a batch share one precision";
+      return COARSE_EINVAL;
+    }
+    for (auto &e : live)
+      if (e.c == c) {
+        err = "context already in the batch";
+        return COARSE_EINVAL;
+      }
+    precision = c->precision;
+    c->prof_mask = 0;   // no per-phase events inside lock steps (they may be captured)
+    Entry e{c, b, u, tag, now(), c->stream};
+    c->stream = side[live.size() % NS];
+    fork_sides(ev_fork);   // inputs written on the main stream are visible
+    c->start(b, 1.0 * tol);
+    live.push_back(e);
+    dirty = true;
+    return COARSE_OK;
+  }
+
+  void rebuild_segments() {
+    const int n = (int)live.size();
+    if (n > cap) {
+      if (d_seg) HIPCHK(hipFree(d_seg));
+      if (h_seg) HIPCHK(hipHostFree(h_seg));
+      d_seg = nullptr;
+      h_seg = nullptr;
+      cap = std::max(2 * n, 16);
+      HIPCHK(hipMalloc(&d_seg, 2 * cap * sizeof(Seg)));
+      HIPCHK(hipHostMalloc((void **)&h_seg, 2 * cap * sizeof(Seg), hipHostMallocDefault));
+    }
+    n_items = n_rows = 0;
+    for (int k = 0; k < n; ++k) {
+      coarse_ctx *c = live[k].c;
+      h_seg[k] = Seg{c->items, c->rows, c->sysdev, c->done_flag, n_items, 0};
+      h_seg[cap + k] = Seg{c->items, c->rows, c->sysdev, c->done_flag, n_rows, 0};
+      n_items += c->items_total;
+      n_rows += c->rows_total;
+    }
+    HIPCHK(hipMemcpyAsync(d_seg, h_seg, 2 * cap * sizeof(Seg), hipMemcpyHostToDevice, main));
+    if (gexec) {
+      HIPCHK(hipGraphExecDestroy(gexec));
+      gexec = nullptr;
+    }
+    dirty = false;
+  }
+
+  // one lock step of every live solve
+  void lock_step() {
+    const int n = (int)live.size();
+    fork_sides(ev_fork);
+    for (auto &e : live) e.c->front();
+    join_sides();
+    const unsigned g = (unsigned)std::min<int64_t>(nblk(n_items, 4), 256 * 16);
+    if (precision == COARSE_FP64) {
+      hipLaunchKernelGGL(k_gemv_f64, dim3(g), dim3(256), 0, main, (const Seg *)d_seg, n, n_items, (const int *)nullptr);
+      hipLaunchKernelGGL(k_combine<double>, dim3(nblk((int64_t)n_rows * TILE, 256)), dim3(256), 0, main,
+                         (const Seg *)(d_seg + cap), n, n_rows, (const int *)nullptr);
+    } else {
+      hipLaunchKernelGGL(k_gemv_f32, dim3(g), dim3(256), 0, main, (const Seg *)d_seg, n, n_items, (const int *)nullptr);
+      hipLaunchKernelGGL(k_combine<float>, dim3(nblk((int64_t)n_rows * TILE, 256)), dim3(256), 0, main,
+                         (const Seg *)(d_seg + cap), n, n_rows, (const int *)nullptr);
+    }
+    fork_sides(ev_mid);
+    for (auto &e : live) e.c->back();
+    join_sides();
+  }
+
+  int step(int iters, int64_t *tags, coarse_stats *stats, int capn, int *n_done) {
+    *n_done = 0;
+    if (live.empty()) return COARSE_OK;
+    if (dirty) rebuild_segments();
+    if (use_graph) {
+      if (!gexec) {
+        hipGraph_t graph;
+        HIPCHK(hipStreamBeginCapture(main, hipStreamCaptureModeRelaxed));
+        lock_step();
+        HIPCHK(hipStreamEndCapture(main, &graph));
+        HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+        HIPCHK(hipGraphDestroy(graph));
+      }
+      for (int i = 0; i < iters; ++i) HIPCHK(hipGraphLaunch(gexec, main));
+    } else {
+      for (int i = 0; i < iters; ++i) lock_step();
+    }
+    HIPCHK(hipGetLastError());
+    for (auto &e : live) HIPCHK(hipMemcpyAsync(e.c->h_sc, e.c->sc, sizeof(Scalars), hipMemcpyDeviceToHost, main));
+    HIPCHK(hipStreamSynchronize(main));
+    std::vector<Entry> keep;
+    std::vector<Entry> fin;
+    for (auto &e : live) (e.c->h_sc->done ? fin : keep).push_back(e);
+    if (fin.empty()) return COARSE_OK;
+    for (auto &e : fin) e.c->finish(e.u);
+    for (auto &e : fin) {
+      HIPCHK(hipStreamSynchronize(e.c->stream));
+      e.c->last_iters = e.c->h_sc->iters;
+      if (*n_done < capn) {
+        if (tags) tags[*n_done] = e.tag;
+        if (stats) e.c->fill_stats(&stats[*n_done], e.t0);
+        ++*n_done;
+      }
+      e.c->stream = e.saved_stream;
+    }
+    // finished solves' outputs were written on side streams: order them before main
+    join_sides();
+    live.swap(keep);
+    dirty = true;
+    return COARSE_OK;
+  }
+};
 
 extern "C" {
 
@@ -814,12 +1030,77 @@ int coarse_solve(coarse_ctx *c, const double *b, double *u, double tol, coarse_s
 int coarse_solve_batch(coarse_ctx *const *ctxs, const double *const *b, double *const *u, int count, double tol,
                        coarse_stats *st) {
   if (!ctxs || !b || !u || count < 0) return COARSE_EINVAL;
+  if (count == 0) return COARSE_OK;
+  for (int i = 0; i < count; ++i)
+    for (int j = 0; j < i; ++j)
+      if (ctxs[i] == ctxs[j] || !ctxs[i]) return COARSE_EINVAL;
+  coarse_batch *bt = nullptr;
+  int rc = coarse_batch_create(ctxs[0]->stream, 0, &bt);
+  if (rc) return rc;
   int worst = COARSE_OK;
-  for (int i = 0; i < count; ++i) {
-    int rc = coarse_solve(ctxs[i], b[i], u[i], tol, st ? st + i : nullptr);
-    if (rc < 0 || (rc > 0 && worst == COARSE_OK)) worst = rc;
+  for (int i = 0; i < count && worst >= 0; ++i) {
+    rc = coarse_batch_submit(bt, ctxs[i], b[i], u[i], tol, i);
+    if (rc < 0) worst = rc;
   }
+  std::vector<int64_t> tags(count);
+  std::vector<coarse_stats> sts(count);
+  while (worst >= 0 && coarse_batch_live(bt) > 0) {
+    int nd = 0;
+    rc = coarse_batch_step(bt, ctxs[0]->check_every, tags.data(), sts.data(), count, &nd);
+    if (rc < 0) {
+      worst = rc;
+      break;
+    }
+    for (int k = 0; k < nd; ++k) {
+      if (st) st[tags[k]] = sts[k];
+      const int s = sts[k].status;
+      if (s < 0 || (s > 0 && worst == COARSE_OK)) worst = s;
+    }
+  }
+  coarse_batch_destroy(bt);
   return worst;
+}
+
+int coarse_batch_create(void *stream, int use_graph, coarse_batch **out) {
+  if (!out) return COARSE_EINVAL;
+  *out = nullptr;
+  std::unique_ptr<coarse_batch> bt(new coarse_batch());
+  try {
+    bt->init((hipStream_t)stream, use_graph != 0);
+  } catch (const Fail &f) {
+    g_setup_error = f.what();
+    return f.code;
+  }
+  *out = bt.release();
+  return COARSE_OK;
+}
+
+int coarse_batch_submit(coarse_batch *bt, coarse_ctx *c, const double *b, double *u, double tol, int64_t tag) {
+  if (!bt || !c || !b || !u || b == u || !(tol > 0)) return COARSE_EINVAL;
+  try {
+    return bt->submit(c, b, u, tol, tag);
+  } catch (const Fail &f) {
+    bt->err = f.what();
+    return f.code;
+  }
+}
+
+int coarse_batch_step(coarse_batch *bt, int iters, int64_t *tags, coarse_stats *stats, int cap, int *n_done) {
+  if (!bt || iters < 1 || !n_done || cap < 0) return COARSE_EINVAL;
+  try {
+    return bt->step(iters, tags, stats, cap, n_done);
+  } catch (const Fail &f) {
+    bt->err = f.what();
+    return f.code;
+  }
+}
+
+int coarse_batch_live(const coarse_batch *bt) { return bt ? (int)bt->live.size() : 0; }
+
+int coarse_batch_destroy(coarse_batch *bt) {
+  if (!bt) return COARSE_OK;
+  delete bt;
+  return COARSE_OK;
 }
 
 int coarse_destroy(coarse_ctx *c) {

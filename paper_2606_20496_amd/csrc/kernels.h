@@ -45,7 +45,8 @@ struct Seg {
   const GItem *items;
   const GRow *rows;
   const SysDev *sys;
-  int32_t begin;   // first global index of this segment
+  const int *done;   // the owning solve's finished flag (batched launches), or null
+  int32_t begin;     // first global index of this segment
   int32_t pad;
 };
 

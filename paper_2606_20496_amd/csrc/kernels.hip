@@ -668,6 +668,7 @@ __global__ __launch_bounds__(256) void k_gemv_f64(const Seg *__restrict__ segs, 
   const int grp = lane >> 4, c2 = (lane & 15) * 2;
   for (int g = blockIdx.x * 4 + (threadIdx.x >> 6); g < total; g += gridDim.x * 4) {
     const Seg sg = segs[nseg == 1 ? 0 : find_seg(segs, nseg, g)];
+    if (sg.done && *sg.done) continue;
     const GItem it = sg.items[g - sg.begin];
     const SysDev S = sg.sys[it.sys];
     const double *__restrict__ r = (const double *)S.rp;
@@ -742,6 +743,7 @@ __global__ __launch_bounds__(256) void k_gemv_f32(const Seg *__restrict__ segs, 
   const int grp = lane >> 3, c4 = (lane & 7) * 4;
   for (int g = blockIdx.x * 4 + (threadIdx.x >> 6); g < total; g += gridDim.x * 4) {
     const Seg sg = segs[nseg == 1 ? 0 : find_seg(segs, nseg, g)];
+    if (sg.done && *sg.done) continue;
     const GItem it = sg.items[g - sg.begin];
     const SysDev S = sg.sys[it.sys];
     const float *__restrict__ r = (const float *)S.rp;
@@ -822,6 +824,7 @@ __global__ __launch_bounds__(256) void k_combine(const Seg *__restrict__ segs, i
   const int g = (int)(gid / TILE), c = (int)(gid % TILE);
   if (g >= total) return;
   const Seg sg = segs[nseg == 1 ? 0 : find_seg(segs, nseg, g)];
+  if (sg.done && *sg.done) return;
   const GRow rw = sg.rows[g - sg.begin];
   const SysDev S = sg.sys[rw.sys];
   const T *rowp = (const T *)S.rowpart;

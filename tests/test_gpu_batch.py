@@ -1,0 +1,96 @@
+"""Lock-step batches of independent solves: every result is bitwise the same
+alone and in the mix (FP64 and mixed precision), with solves joining while
+others run, and with the lock step replayed from a captured HIP graph. A few
+batch members are also checked against the oracle."""
+import numpy as np
+import pytest
+
+from oracle import problem
+from paper_2606_20496_amd import coarse, meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    coarse.load()
+
+
+def _meshes(count=8):
+    # the batch workload's generator, first `count` meshes capped at n <= 24
+    ms = mg.batch_meshes(count=count, nmax=24)
+    return ms
+
+
+def _alone(ms, precision):
+    out = []
+    for m in ms:
+        S = coarse.CoarseSolver.from_mesh(m, precision=precision)
+        u, st = S.solve(torch.tensor(m.b, device="cuda"))
+        out.append((u, st["iters"]))
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_equals_alone(precision, graph):
+    ms = _meshes()
+    ref = _alone(ms, precision)
+    stream = torch.cuda.Stream()
+    solvers = [coarse.CoarseSolver.from_mesh(m, precision=precision) for m in ms]
+    bs = [torch.tensor(m.b, device="cuda") for m in ms]
+    us = [torch.zeros_like(b) for b in bs]
+    torch.cuda.synchronize()
+    bt = coarse.Batch(stream=stream, use_graph=graph)
+    done = {}
+    # half now, the rest joins while the first half is running
+    for k in range(4):
+        bt.submit(solvers[k], bs[k], us[k], tag=k)
+    for tag, st in bt.step(3):
+        done[tag] = st
+    for k in range(4, len(ms)):
+        bt.submit(solvers[k], bs[k], us[k], tag=k)
+    guard = 0
+    while bt.live > 0:
+        for tag, st in bt.step(2):
+            done[tag] = st
+        guard += 1
+        assert guard < 500
+    stream.synchronize()
+    assert sorted(done) == list(range(len(ms)))
+    for k in range(len(ms)):
+        assert done[k]["code"] == 0
+        assert done[k]["iters"] == ref[k][1]
+        assert torch.equal(us[k], ref[k][0]), k
+    bt.close()
+
+
+def test_solve_batch_api_matches_oracle():
+    ms = _meshes(4)
+    solvers = [coarse.CoarseSolver.from_mesh(m) for m in ms]
+    bs = [torch.tensor(m.b, device="cuda") for m in ms]
+    us, sts = coarse.solve_batch(solvers, bs)
+    for m, u, st in zip(ms, us, sts):
+        P = problem.from_mesh(m)
+        uo, io = P.solve(m.b)
+        assert st["iters"] == io["iters"]
+        assert np.linalg.norm(u.cpu().numpy() - uo) / np.linalg.norm(uo) < 1e-9
+
+
+def test_batch_rejects_mixed_precisions():
+    ms = _meshes(2)
+    a = coarse.CoarseSolver.from_mesh(ms[0], precision="fp64")
+    b = coarse.CoarseSolver.from_mesh(ms[1], precision="mixed")
+    bt = coarse.Batch()
+    u0 = torch.zeros(ms[0].n_vert, dtype=torch.float64, device="cuda")
+    u1 = torch.zeros(ms[1].n_vert, dtype=torch.float64, device="cuda")
+    bt.submit(a, torch.tensor(ms[0].b, device="cuda"), u0, tag=0)
+    with pytest.raises(coarse.CoarseError):
+        bt.submit(b, torch.tensor(ms[1].b, device="cuda"), u1, tag=1)
+    while bt.live:
+        bt.step(4)
+    bt.close()
