@@ -30,6 +30,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 
 
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def _pct(a, q):
     return float(np.percentile(np.asarray(a), q)) if len(a) else float("nan")
 
@@ -76,6 +80,49 @@ def run_form(torch, coarse, mesh, rhs, precision, steps, warmup, tol):
     }
 
 
+def run_batch_workload(torch, coarse, mg, tol, reps=3):
+    """64 independent meshes (n log-uniform in [6, 48], blocks of 4/6/8 elements)
+    solved together in lock step (one GEMV launch for all their local and reduced
+    solves per iteration, HIP-graph replay), versus one at a time."""
+    meshes = mg.batch_meshes(count=64)
+    out = {"meshes": len(meshes), "elements": int(sum(m.n_elem for m in meshes))}
+    for prec in ("mixed", "fp64"):
+        t0 = time.perf_counter()
+        solvers = [coarse.CoarseSolver.from_mesh(m, precision=prec) for m in meshes]
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            bs = [torch.tensor(m.b, device="cuda") for m in meshes]
+            us = [torch.empty_like(b) for b in bs]
+        stream.synchronize()
+        bt = coarse.Batch(stream=stream, use_graph=True)
+        best = None
+        for rep in range(reps + 1):
+            t1 = time.perf_counter()
+            for k, S in enumerate(solvers):
+                bt.submit(S, bs[k], us[k], tag=k, tol=tol)
+            n = 0
+            while bt.live:
+                n += len(bt.step(2))
+            stream.synchronize()
+            dt = time.perf_counter() - t1
+            if rep > 0:
+                best = dt if best is None else min(best, dt)
+        bt.close()
+        t1 = time.perf_counter()
+        for k, S in enumerate(solvers):
+            S.solve(bs[k], tol, out=us[k])
+        torch.cuda.synchronize()
+        seq = time.perf_counter() - t1
+        for S in solvers:
+            S.close()
+        out[prec] = {"batched_solves_per_s": round(len(meshes) / best, 2),
+                     "one_at_a_time_solves_per_s": round(len(meshes) / seq, 2),
+                     "setup_s_total": round(t_setup, 3)}
+    return out
+
+
 def cpu_baseline(mesh, tol):
     """The FP64 oracle, as it stands, on the host cores: one full solve of the
     same workload (setup timed separately and excluded)."""
@@ -102,6 +149,8 @@ def main():
     ap.add_argument("--n", type=int, default=64, help="cube edge in elements (64 = one GPU's share)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--batch", action="store_true", help="also run the 64-mesh batched workload")
+    ap.add_argument("--serving", action="store_true", help="also run a short serving-loop workload")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 1 GiB device copy (known bytes) to scale HBM counters")
     args = ap.parse_args()
@@ -128,8 +177,13 @@ def main():
     nrhs = min(args.steps + args.warmup, 32)
     rhs = [torch.tensor(mesh.b if i == 0 else mg.rhs_bumps(mesh, 100 + i), device="cuda") for i in range(nrhs)]
 
+    _log("fp64 form")
     fp64 = run_form(torch, coarse, mesh, rhs, "fp64", args.steps, args.warmup, args.tol)
-    mixed = None if args.no_mixed else run_form(torch, coarse, mesh, rhs, "mixed", args.steps, args.warmup, args.tol)
+    _log(f"fp64: {fp64['solves_per_s']:.2f} solves/s")
+    mixed = None
+    if not args.no_mixed:
+        mixed = run_form(torch, coarse, mesh, rhs, "mixed", args.steps, args.warmup, args.tol)
+        _log(f"mixed: {mixed['solves_per_s']:.2f} solves/s")
 
     # roofline of the dominant kernel: the batched dense solve (tiled symmetric GEMV
     # over the stored local and reduced inverses), HBM-bound
@@ -143,8 +197,29 @@ def main():
             "alg_bytes_per_launch": alg_bytes}
     phases = {k: {"avg_us": round(1e3 * v[0] / max(v[1], 1), 2), "launches": v[1]} for k, v in fp64["phases"].items()}
 
+    batch = None
+    if args.batch:
+        _log("batch workload")
+        batch = run_batch_workload(torch, coarse, mg, args.tol)
+        _log(f"batch: {batch}")
+    serving = None
+    if args.serving:
+        from paper_2606_20496_amd import serve
+        _log("serving workload: generating requests")
+        reqs = serve.make_requests(200.0, 192, nmax=96)
+        _log("serving: continuous batching")
+        srv = serve.Server(64e9, precision="mixed", use_graph=True, step_iters=2)
+        rec, wall = srv.run(reqs)
+        srv.close()
+        serving = {"rate_per_s": 200.0, "requests": 192, "mixed_continuous_batching": serve.summarize(rec, wall)}
+        _log(f"serving: {serving}")
+        rec2, wall2 = serve.serve_sequential(reqs)
+        serving["fp64_one_at_a_time"] = serve.summarize(rec2, wall2)
+        _log(f"sequential: {serving['fp64_one_at_a_time']}")
+
     cpu = None
     if not args.no_cpu_baseline:
+        _log("cpu baseline (oracle)")
         cpu = cpu_baseline(mesh, args.tol)
 
     line = {
@@ -185,6 +260,10 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if batch is not None:
+        line["batch_workload"] = batch
+    if serving is not None:
+        line["serving_workload"] = serving
     print(json.dumps(line), flush=True)
 
 

@@ -227,8 +227,8 @@ int coarse_profile(coarse_ctx *ctx, int enable, double *ms, int64_t *counts, int
 int coarse_plan_info(const coarse_mesh *mesh, const coarse_bc *bc, const coarse_opts *opts,
                      coarse_info_t *info, int64_t *sizes);
 
-/* Message for a status code; last failure message of a context (or of the last
- * failed coarse_setup when ctx is NULL). */
+/* Message for a status code; last failure message of a context (or, when ctx
+ * is NULL, of the last failed coarse_setup on the calling host thread). */
 const char *coarse_strerror(int code);
 const char *coarse_last_error(const coarse_ctx *ctx);
 

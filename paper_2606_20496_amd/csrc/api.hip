@@ -18,7 +18,7 @@ using namespace coarse;
 
 namespace {
 
-std::string g_setup_error;
+thread_local std::string g_setup_error;   // setups may run on several host threads
 
 struct Fail : std::runtime_error {
   int code;
@@ -49,10 +49,14 @@ struct Arena {
     bytes += n * sizeof(T);
     return (T *)p;
   }
+  // The source may be a temporary: the copy is complete when this returns.
   template <typename T>
   T *upload(const std::vector<T> &v, hipStream_t s) {
     T *p = alloc<T>(v.size());
-    if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    if (!v.empty()) {
+      HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
     return p;
   }
   void release() {

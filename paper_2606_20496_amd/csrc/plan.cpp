@@ -10,7 +10,10 @@
 #include "plan.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 
@@ -71,9 +74,22 @@ inline double phi(int k, const double xi[3]) {
   return fx * fy * fz;
 }
 
+// Phase timings of the host setup on stderr when COARSE_TRACE is set.
+struct Trace {
+  bool on = std::getenv("COARSE_TRACE") != nullptr;
+  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+  void mark(const char *what) {
+    if (!on) return;
+    const auto n = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[coarse plan] %-28s %8.3f ms\n", what, std::chrono::duration<double, std::milli>(n - t).count());
+    t = n;
+  }
+};
+
 }  // namespace
 
 int build_plan(const PlanInput &in, Plan &P) {
+  Trace tr;
   const int64_t NV = in.n_vert, NE = in.n_elem;
   if (NV <= 0 || NE <= 0 || !in.xyz || !in.e2v || !in.dirichlet) {
     P.err = "empty mesh or null array";
@@ -113,6 +129,7 @@ int build_plan(const PlanInput &in, Plan &P) {
       return -1;
     }
 
+  tr.mark("validate");
   // ---- partition labels -------------------------------------------------------
   std::vector<double> cen(3 * NE);
   for (int64_t e = 0; e < NE; ++e) centroid(in.xyz, in.e2v + 8 * e, &cen[3 * e]);
@@ -132,6 +149,7 @@ int build_plan(const PlanInput &in, Plan &P) {
     rcb(idx, 0, NE, 0, in.n_part, cen, part);
   }
 
+  tr.mark("partition");
   // ---- bounding box of all vertices (Sec. 4) ----------------------------------
   for (int d = 0; d < 3; ++d) {
     P.lo[d] = 1e300;
@@ -143,6 +161,7 @@ int build_plan(const PlanInput &in, Plan &P) {
       P.hi[d] = std::max(P.hi[d], in.xyz[3 * u + d]);
     }
 
+  tr.mark("bounding box");
   // ---- element order: (subdomain, Morton code of centroid) --------------------
   {
     std::vector<uint64_t> key(NE);
@@ -165,6 +184,7 @@ int build_plan(const PlanInput &in, Plan &P) {
     });
   }
 
+  tr.mark("element order");
   // ---- vertex numbering: free vertices first, by first touch -------------------
   P.vint_of_user.assign(NV, -1);
   int64_t nf = 0;
@@ -206,6 +226,7 @@ int build_plan(const PlanInput &in, Plan &P) {
   }
   auto E2V = [&](int64_t e, int v) { return P.e2v[v * NE + e]; };
 
+  tr.mark("vertex numbering");
   // ---- multiplicity and vertex -> element incidence (all vertices) ------------
   P.mult.assign(NV, 0);
   for (int64_t e = 0; e < NE; ++e)
@@ -220,6 +241,7 @@ int build_plan(const PlanInput &in, Plan &P) {
   P.vinc_ptr.assign(inc_ptr.begin(), inc_ptr.begin() + nf + 1);
   P.vinc.assign(inc.begin(), inc.begin() + inc_ptr[nf]);
 
+  tr.mark("incidence");
   // ---- operator blocks ---------------------------------------------------------
   {
     const int64_t nb = (NE + OP_BLOCK - 1) / OP_BLOCK;
@@ -314,6 +336,7 @@ int build_plan(const PlanInput &in, Plan &P) {
     }
   }
 
+  tr.mark("operator blocks");
   // ---- overlapping subdomains and R_p (Sec. 3) --------------------------------
   {
     std::vector<int64_t> pstart(in.n_part + 1, 0);
@@ -359,6 +382,7 @@ int build_plan(const PlanInput &in, Plan &P) {
     }
   }
 
+  tr.mark("overlap and R_p");
   // ---- box grid and element cells (Sec. 4) ------------------------------------
   int32_t bauto = (int32_t)std::ceil(std::cbrt((double)in.n_part) - 1e-9);
   for (int d = 0; d < 3; ++d) {
@@ -560,6 +584,7 @@ int build_plan(const PlanInput &in, Plan &P) {
     }
   }
 
+  tr.mark("reduced space");
   // ---- dense systems, packed vectors, tiles and GEMV items --------------------
   {
     int64_t voff = 0, toff = 0, roff = 0;
@@ -626,6 +651,7 @@ int build_plan(const PlanInput &in, Plan &P) {
       }
     }
   }
+  tr.mark("systems and items");
   return 0;
 }
 

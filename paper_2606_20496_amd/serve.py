@@ -1,0 +1,265 @@
+"""Serving loop for coarse solves on one GPU: continuous batching with admission
+by HBM budget and a per-mesh context cache.
+
+Requests (arrival time, mesh key, mesh, right-hand side) are admitted as they
+arrive. A request whose mesh context is resident and idle joins the lock-step
+batch at the next step; a request for a new mesh first gets its context built
+by a setup worker thread (setups run on their own stream, overlapping the
+solves), if the resident contexts leave room in the HBM budget (idle contexts
+are evicted least-recently-used first; otherwise the setup waits). Finished
+solves retire after each step and free their mesh for the next request on it.
+Every solve's result is bitwise what a solo solve of the same context gives.
+
+The plain FP64 one-at-a-time path (:func:`serve_sequential`) processes the same
+request stream in arrival order with one solve at a time, for comparison.
+"""
+from __future__ import annotations
+
+import collections
+import concurrent.futures as cf
+import dataclasses
+import time
+
+import numpy as np
+
+from . import coarse
+
+
+@dataclasses.dataclass
+class Request:
+    t_arrive: float          # seconds after the start of the run
+    key: int                 # mesh identity (requests with the same key share a context)
+    mesh: object             # meshgen.Mesh (or any object with its fields)
+    b: np.ndarray            # right-hand side, one value per vertex
+    rid: int = 0
+
+
+@dataclasses.dataclass
+class Record:
+    rid: int
+    key: int
+    t_arrive: float
+    t_done: float
+    iters: int
+    relres_true: float
+    setup: bool              # this request's mesh was set up for it (cache miss)
+    status: int
+    u: object = None         # the solution (kept only when asked for)
+
+    @property
+    def latency(self):
+        return self.t_done - self.t_arrive
+
+
+def summarize(records, wall):
+    lat = np.array([r.latency for r in records])
+    return {
+        "requests": len(records), "wall_s": wall,
+        "solves_per_s": len(records) / wall if wall > 0 else float("nan"),
+        "p50_ms": 1e3 * float(np.percentile(lat, 50)) if len(lat) else float("nan"),
+        "p99_ms": 1e3 * float(np.percentile(lat, 99)) if len(lat) else float("nan"),
+        "mean_iters": float(np.mean([r.iters for r in records])) if records else float("nan"),
+        "max_relres_true": float(max((r.relres_true for r in records), default=0.0)),
+        "cache_misses": int(sum(r.setup for r in records)),
+        "failed": int(sum(r.status != 0 for r in records)),
+    }
+
+
+class Server:
+    def __init__(self, budget_bytes, precision="mixed", use_graph=True, step_iters=2, tol=1e-8,
+                 setup_workers=2, solver_kw=None, keep_outputs=False):
+        import torch
+        self.torch = torch
+        self.budget = int(budget_bytes)
+        self.precision = precision
+        self.step_iters = int(step_iters)
+        self.tol = tol
+        self.stream = torch.cuda.Stream()
+        self.batch = coarse.Batch(stream=self.stream, use_graph=use_graph)
+        self.pool = cf.ThreadPoolExecutor(max_workers=setup_workers)
+        self.solver_kw = dict(solver_kw or {})
+        self.cache = collections.OrderedDict()   # key -> CoarseSolver (LRU order)
+        self.busy = set()                        # keys with a live solve
+        self.setting_up = {}                     # key -> Future
+        self.pending = {}                        # key -> estimated bytes of a setup in flight
+        self.used = 0
+        self.keep_outputs = keep_outputs
+
+    def _setup(self, mesh):
+        torch = self.torch
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            S = coarse.CoarseSolver.from_mesh(mesh, precision=self.precision, **self.solver_kw)
+        s.synchronize()
+        S._setup_stream = s          # the context keeps using this stream handle between solves
+        return S
+
+    def _evict_for(self, need, keep=()):
+        """Evict idle contexts (least recently used first, never those in `keep`)
+        until `need` more bytes fit the budget; True if they do."""
+        for key in list(self.cache):
+            if self.used + need <= self.budget:
+                return True
+            if key in self.busy or key in keep:
+                continue
+            S = self.cache.pop(key)
+            self.used -= S.device_bytes
+            S.close()
+        return self.used + need <= self.budget
+
+    @staticmethod
+    def estimate_bytes(mesh, precision):
+        """Rough device footprint of a context before it exists: element data, the
+        stored inverses (packed symmetric, padded to 32) and vectors."""
+        E, n = mesh.n_elem, mesh.n_vert
+        vol = E / max(mesh.n_part, 1)
+        np_ = (vol ** (1 / 3) + 2) ** 3
+        nb = np.ceil(np_ / 32)
+        tiles = mesh.n_part * nb * (nb + 1) / 2
+        es = 8 if precision == "fp64" else 4
+        return int(E * 420 + n * 200 + tiles * 1024 * es * 1.1 + tiles * 32 * es)
+
+    def run(self, requests, t0=None):
+        torch = self.torch
+        reqs = collections.deque(sorted(requests, key=lambda r: r.t_arrive))
+        waiting = collections.deque()      # arrived, not yet in the batch
+        live = {}                          # rid -> (Request, u, missed)
+        missed = set()
+        records = []
+        t0 = time.perf_counter() if t0 is None else t0
+        now = lambda: time.perf_counter() - t0
+        while reqs or waiting or live or self.setting_up:
+            t = now()
+            while reqs and reqs[0].t_arrive <= t:
+                waiting.append(reqs.popleft())
+            # finished setups become resident
+            for key, fut in list(self.setting_up.items()):
+                if fut.done():
+                    S = fut.result()
+                    del self.setting_up[key]
+                    self.pending.pop(key, None)
+                    self.cache[key] = S
+                    self.used += S.device_bytes
+            # admit waiting requests: first those whose context is resident and idle
+            keep = collections.deque()
+            for rq in waiting:
+                if rq.key in self.cache and rq.key not in self.busy:
+                    S = self.cache[rq.key]
+                    self.cache.move_to_end(rq.key)
+                    with torch.cuda.stream(self.stream):
+                        b = torch.tensor(rq.b, device="cuda")
+                        u = torch.empty_like(b)
+                    self.batch.submit(S, b, u, tag=rq.rid, tol=self.tol)
+                    self.busy.add(rq.key)
+                    live[rq.rid] = (rq, u, b)
+                else:
+                    keep.append(rq)
+            waiting = keep
+            # then start setups for new meshes while the budget allows; contexts a
+            # waiting request needs are never evicted, and a setup that does not fit
+            # even with everything idle evicted runs only when nothing else does
+            needed = {rq.key for rq in waiting}
+            for rq in waiting:
+                if rq.key in self.cache or rq.key in self.setting_up:
+                    continue
+                need = self.estimate_bytes(rq.mesh, self.precision)
+                fits = self._evict_for(need + sum(self.pending.values()), keep=needed)
+                alone = not self.busy and not self.setting_up and not live
+                if fits or alone:
+                    self.setting_up[rq.key] = self.pool.submit(self._setup, rq.mesh)
+                    self.pending[rq.key] = need
+                    missed.add(rq.rid)
+            if live:
+                for tag, st in self.batch.step(self.step_iters):
+                    rq, u, b = live.pop(tag)
+                    self.busy.discard(rq.key)
+                    records.append(Record(rid=rq.rid, key=rq.key, t_arrive=rq.t_arrive, t_done=now(),
+                                          iters=st["iters"], relres_true=st["relres_true"],
+                                          setup=rq.rid in missed, status=st["status"],
+                                          u=u if self.keep_outputs else None))
+            else:
+                time.sleep(0.0005)
+        self.stream.synchronize()
+        return records, now()
+
+    def close(self):
+        self.pool.shutdown(wait=True)
+        self.batch.close()
+        for S in self.cache.values():
+            S.close()
+        self.cache.clear()
+
+
+def serve_sequential(requests, precision="fp64", tol=1e-8, solver_kw=None):
+    """The plain one-at-a-time path: arrival order, one solve at a time, contexts
+    cached by mesh key, setup in line."""
+    import torch
+    cache = {}
+    records = []
+    t0 = time.perf_counter()
+    for rq in sorted(requests, key=lambda r: r.t_arrive):
+        while time.perf_counter() - t0 < rq.t_arrive:
+            time.sleep(0.0002)
+        miss = rq.key not in cache
+        if miss:
+            cache[rq.key] = coarse.CoarseSolver.from_mesh(rq.mesh, precision=precision, **(solver_kw or {}))
+        S = cache[rq.key]
+        b = torch.tensor(rq.b, device="cuda")
+        u, st = S.solve(b, tol)
+        records.append(Record(rid=rq.rid, key=rq.key, t_arrive=rq.t_arrive, t_done=time.perf_counter() - t0,
+                              iters=st["iters"], relres_true=st["relres_true"], setup=miss,
+                              status=st["status"]))
+    wall = time.perf_counter() - t0
+    for S in cache.values():
+        S.close()
+    return records, wall
+
+
+def make_requests(rate, count, seed=59999, nmax=96, reuse=0.3):
+    """The serving workload: Poisson arrivals at `rate`, meshes drawn by
+    meshgen.serving_request_mesh (n log-uniform in [8, nmax], graded z), 30% of
+    requests reusing an earlier mesh with a new N(0,1) right-hand side."""
+    from . import meshgen as mg
+    t, mesh_id, rhs_seed = mg.serving_arrivals(rate, count=count, seed=seed, reuse=reuse)
+    meshes = {}
+    out = []
+    for q in range(count):
+        k = int(mesh_id[q])
+        if k not in meshes:
+            meshes[k] = mg.serving_request_mesh(k, nmax=nmax)
+        m = meshes[k]
+        out.append(Request(t_arrive=float(t[q]), key=k, mesh=m, b=mg.rhs_normal(m, int(rhs_seed[q])), rid=q))
+    return out
+
+
+def main():
+    import argparse
+    import json
+    import torch
+    ap = argparse.ArgumentParser(description="serving loop for coarse solves (continuous batching)")
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--count", type=int, default=256)
+    ap.add_argument("--nmax", type=int, default=96)
+    ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--precision", default="mixed")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--step-iters", type=int, default=2)
+    ap.add_argument("--sequential", action="store_true", help="also run the FP64 one-at-a-time path")
+    args = ap.parse_args()
+    coarse.load()
+    reqs = make_requests(args.rate, args.count, nmax=args.nmax)
+    torch.cuda.synchronize()
+    srv = Server(args.budget_gb * 1e9, precision=args.precision, use_graph=not args.no_graph,
+                 step_iters=args.step_iters)
+    rec, wall = srv.run(reqs)
+    srv.close()
+    out = {"rate": args.rate, "count": args.count, "nmax": args.nmax, "precision": args.precision,
+           "serving": summarize(rec, wall)}
+    if args.sequential:
+        rec2, wall2 = serve_sequential(reqs)
+        out["sequential_fp64"] = summarize(rec2, wall2)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

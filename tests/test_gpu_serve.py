@@ -1,0 +1,49 @@
+"""The serving loop: every request of a seeded arrival stream (new meshes and
+reused ones, admitted while others run) completes with the same result,
+bitwise, as a solo solve of its mesh and right-hand side, within the HBM
+budget's admission rules."""
+import pytest
+
+from paper_2606_20496_amd import coarse, serve
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    coarse.load()
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_serving_results_equal_solo(precision):
+    reqs = serve.make_requests(rate=400.0, count=24, nmax=20)
+    srv = serve.Server(budget_bytes=2e9, precision=precision, use_graph=True, step_iters=2, keep_outputs=True)
+    records, wall = srv.run(reqs)
+    srv.close()
+    assert len(records) == len(reqs)
+    bad = [(r.rid, r.key, r.status, r.iters, r.relres_true, r.setup) for r in records if r.status != 0]
+    assert not bad, bad
+    assert sum(r.setup for r in records) == len({r.key for r in reqs})
+    by_id = {r.rid: r for r in records}
+    solo = {}
+    for rq in reqs:
+        if rq.key not in solo:
+            solo[rq.key] = coarse.CoarseSolver.from_mesh(rq.mesh, precision=precision)
+        u, st = solo[rq.key].solve(torch.tensor(rq.b, device="cuda"))
+        rec = by_id[rq.rid]
+        assert rec.iters == st["iters"]
+        assert torch.equal(rec.u, u), rq.rid
+    s = serve.summarize(records, wall)
+    assert s["requests"] == 24 and s["failed"] == 0
+
+
+def test_tight_budget_still_serves_everything():
+    reqs = serve.make_requests(rate=1000.0, count=16, nmax=16)
+    srv = serve.Server(budget_bytes=1, precision="mixed", use_graph=False, step_iters=2)
+    records, wall = srv.run(reqs)
+    srv.close()
+    assert len(records) == 16 and all(r.status == 0 for r in records)
