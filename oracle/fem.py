@@ -51,6 +51,20 @@ def element_matrices(xyz, e2v):
     return A, detmin
 
 
+def element_magnitudes(xyz, e2v):
+    """The same sum as :func:`element_matrices` taken in absolute values,
+    sum_q |J_q| |G_q| |G_q|^T (E, 8, 8): the magnitude that bounds the rounding
+    error of any evaluation of A^e and of the products with it."""
+    X = np.asarray(xyz, dtype=np.float64)[np.asarray(e2v)]
+    M = np.zeros((X.shape[0], 8, 8))
+    for q in GAUSS_POINTS:
+        gN = ref_gradients(q)
+        Jac = np.matmul(X.transpose(0, 2, 1), gN)
+        G = np.abs(np.matmul(gN[None, :, :], np.linalg.inv(Jac)))
+        M += np.abs(np.linalg.det(Jac))[:, None, None] * np.matmul(G, G.transpose(0, 2, 1))
+    return M
+
+
 def assemble(Ae, e2v, n_vert):
     """A_full = Q^T A_L Q as a sparse (n_vert x n_vert) matrix: the local-to-global
     summation of Sec. 3 (duplicates summed)."""

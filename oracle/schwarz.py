@@ -89,3 +89,22 @@ def local_solves_for(A, R_free, which):
     where factoring every subdomain would take too long)."""
     A = A.tocsr()
     return {p: sla.cho_factor(A[R_free[p]][:, R_free[p]].toarray(), lower=True) for p in which}
+
+
+def local_part_at(A, R_free, rows, r):
+    """Entries ``rows`` (free numbering) of the local part sum_p R_p^T A_p^{-1} R_p r,
+    computed from only the subdomains whose R_p contains one of those rows. Each
+    entry is the full sum over every subdomain covering it, so it equals the
+    corresponding entry of :meth:`LocalSolves.apply` on the whole mesh."""
+    rows = np.asarray(rows, dtype=np.int64)
+    which = [p for p, R in enumerate(R_free) if np.isin(rows, R, assume_unique=False).any()]
+    factors = local_solves_for(A, R_free, which)
+    out = np.zeros(rows.size)
+    for p in which:
+        R = np.asarray(R_free[p], dtype=np.int64)
+        zp = sla.cho_solve(factors[p], r[R])
+        order = np.argsort(R, kind="stable")
+        pos = np.minimum(np.searchsorted(R[order], rows), R.size - 1)
+        hit = R[order][pos] == rows
+        out[hit] += zp[order[pos[hit]]]
+    return out, which

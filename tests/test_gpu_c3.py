@@ -1,0 +1,161 @@
+"""Full-size parity on the 128^3 quarter-annulus (2.1M elements, 4096 subdomains
+of 8^3 elements, 16^3 boxes, radial stretching 1.05), the mesh on which mixed
+precision is compared with FP64.
+
+A whole oracle solve does not fit in test time at this size, so the checks are:
+the operator A in full against the oracle's sparse A; the local Schwarz part on
+sampled vertices, from the oracle factoring only the subdomains that cover
+them; the reduced term J A_r^{-1} J^T in full against the oracle; the additive
+preconditioner on the same samples; and the solves through the oracle's own
+true residual, with the mixed form's iterations held to the FP64 path's."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fem, reduced, schwarz
+from paper_2606_20496_amd import coarse, meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _gpu(v):
+    return torch.tensor(np.asarray(v, dtype=np.float64), device="cuda")
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def c3():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    coarse.load()
+    m = mg.large_annulus()
+    d = m.dirichlet.astype(bool)
+    A, Ae, _, free, fidx = fem.stiffness(m.xyz, m.e2v, d)
+    absA = fem.assemble(fem.element_magnitudes(m.xyz, m.e2v), m.e2v, m.n_vert)[free][:, free].tocsr()
+    mult = fem.multiplicity(m.e2v, m.n_vert)
+    red = reduced.CentroidSpace(m.xyz, m.e2v, d, Ae, m.boxes, fidx, mult)
+    sets = schwarz.overlapping_subdomains(m.e2v, m.part, m.n_part, 1)
+    R = [fidx[r] for r in schwarz.restriction_sets(m.e2v, sets, d)]
+    # sampled free rows: random ones, plus the most covered ones and rows next to
+    # the Dirichlet face r = 1
+    rng = np.random.default_rng(11)
+    cover = np.zeros(free.size, np.int64)
+    for Rp in R:
+        cover[Rp] += 1
+    rad = np.hypot(m.xyz[free, 0], m.xyz[free, 1])
+    rows = np.unique(np.concatenate([
+        rng.choice(free.size, 40, replace=False),
+        rng.choice(np.flatnonzero(cover == cover.max()), 8, replace=False),
+        np.argsort(rad, kind="stable")[:8],
+    ]))
+    r = np.random.default_rng(12).standard_normal(m.n_vert)
+    loc, which = schwarz.local_part_at(A, R, rows, r[free])
+    yield dict(m=m, A=A, absA=absA, free=free, red=red, rows=rows, r=r, loc=loc, n_cover_sub=len(which),
+               cover_max=int(cover.max()))
+
+
+def _relmax(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def test_c3_sizes(c3):
+    m = c3["m"]
+    info, _ = coarse.plan_info(m.xyz, m.e2v, m.dirichlet, m.part, m.n_part, boxes=m.boxes)
+    assert m.n_elem == 128 ** 3 and m.n_part == 4096
+    assert info["n_free"] == c3["free"].size
+    assert info["n_r"] == c3["red"].n_r < 17 ** 3      # compressed box vertices
+    assert c3["cover_max"] <= 8
+
+
+@pytest.mark.timeout(900)
+def test_c3_apply_A(c3):
+    # The radially stretched elements near r = 1 (aspect ratio ~130) have entries
+    # far larger than the result, and A is applied element by element (Sec. 3,
+    # A = Q^T A_L Q), so the bar is the rounding bound of that computation, entry
+    # by entry: 256 eps times the same sums taken in absolute values (quadrature
+    # terms, element entries and incident elements), which covers the 8 Gauss
+    # points and the summation in any order.
+    m = c3["m"]
+    S = coarse.CoarseSolver.from_mesh(m, mode="local_only")
+    p = np.random.default_rng(13).standard_normal(m.n_vert)
+    q = _np(S.apply_A(_gpu(p)))[c3["free"]]
+    S.close()
+    A, pf = c3["A"], p[c3["free"]]
+    ref = A @ pf
+    bound = 256 * np.finfo(np.float64).eps * (c3["absA"] @ np.abs(pf))
+    assert np.all(np.abs(q - ref) <= bound)
+    assert _relmax(q, ref) < 1e-12
+
+
+@pytest.mark.timeout(900)
+def test_c3_local_part_sampled(c3):
+    # every subdomain covering a sampled row is included in the oracle's sum
+    m = c3["m"]
+    S = coarse.CoarseSolver.from_mesh(m, mode="local_only")
+    z = _np(S.apply_precond(_gpu(c3["r"])))[c3["free"]]
+    S.close()
+    assert _relmax(z[c3["rows"]], c3["loc"]) < 1e-12
+
+
+@pytest.mark.timeout(900)
+def test_c3_reduced_term_in_full(c3):
+    m = c3["m"]
+    S = coarse.CoarseSolver.from_mesh(m, mode="reduced_only")
+    z = _np(S.apply_precond(_gpu(c3["r"])))[c3["free"]]
+    assert _relmax(z, c3["red"].apply(c3["r"][c3["free"]])) < 1e-12
+    S.close()
+
+
+@pytest.mark.timeout(900)
+def test_c3_additive_sampled(c3):
+    m = c3["m"]
+    S = coarse.CoarseSolver.from_mesh(m)
+    z = _np(S.apply_precond(_gpu(c3["r"])))[c3["free"]]
+    zc = c3["red"].apply(c3["r"][c3["free"]])
+    ref = c3["loc"] + zc[c3["rows"]]
+    assert _relmax(z[c3["rows"]], ref) < 1e-12
+    S.close()
+
+
+def _true_relres(c3, u):
+    m, A, free = c3["m"], c3["A"], c3["free"]
+    b = m.b[free]
+    return float(np.linalg.norm(b - A @ u[free]) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def c3_fp64(c3):
+    m = c3["m"]
+    S = coarse.CoarseSolver.from_mesh(m)
+    u, st = S.solve(_gpu(m.b), tol=1e-8)
+    S.close()
+    return _np(u), st
+
+
+@pytest.mark.timeout(900)
+def test_c3_solve_fp64(c3, c3_fp64):
+    u, st = c3_fp64
+    assert st["code"] == 0 and st["relres"] <= 1e-8
+    assert _true_relres(c3, u) <= 1.01e-8
+    assert abs(_true_relres(c3, u) - st["relres_true"]) < 1e-10
+
+
+@pytest.mark.timeout(900)
+def test_c3_solve_mixed(c3, c3_fp64):
+    m = c3["m"]
+    u64, st64 = c3_fp64
+    S = coarse.CoarseSolver.from_mesh(m, precision="mixed")
+    u, st = S.solve(_gpu(m.b), tol=1e-8)
+    u = _np(u)
+    S.close()
+    assert st["code"] == 0
+    assert st["iters"] <= math.ceil(1.1 * st64["iters"])
+    assert _true_relres(c3, u) <= 1.05e-8
+    # both solutions approximate the same u to within the solve tolerance
+    assert np.linalg.norm(u - u64) / np.linalg.norm(u64) < 1e-6

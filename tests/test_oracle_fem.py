@@ -159,3 +159,18 @@ def test_inverted_element_rejected():
     e2v = e2v[:, [1, 0, 3, 2, 5, 4, 7, 6]]   # mirror in x: negative Jacobian
     with pytest.raises(ValueError):
         fem.stiffness(xyz, e2v, np.zeros(8, np.uint8))
+
+
+def test_element_magnitudes_bound_the_element_matrices():
+    # the absolute-value sum dominates |A^e| entry by entry, equals it on the
+    # diagonal (a sum of non-negative terms), and on the unit cube reproduces the
+    # closed-form diagonal h/3 of the Q1 stiffness
+    m = mg.box_mesh(4, 9, block=2, boxes=(2, 2, 2))
+    Ae, _ = fem.element_matrices(m.xyz, m.e2v)
+    M = fem.element_magnitudes(m.xyz, m.e2v)
+    assert np.all(M >= np.abs(Ae) * (1 - 1e-14))
+    d = np.arange(8)
+    assert np.allclose(M[:, d, d], Ae[:, d, d], rtol=1e-14, atol=0)
+    cube = np.array([[i, j, k] for k in (0, 1) for j in (0, 1) for i in (0, 1)], dtype=float)
+    Mc = fem.element_magnitudes(cube, np.arange(8)[None, :])[0]
+    assert np.allclose(np.diag(Mc), 1.0 / 3.0, rtol=1e-14)

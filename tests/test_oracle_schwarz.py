@@ -91,3 +91,21 @@ def test_local_part_against_dense_inverses():
     # symmetric positive definite (overlap covers every free vertex)
     assert np.abs(Mdense - Mdense.T).max() < 1e-12 * np.abs(Mdense).max()
     assert np.linalg.eigvalsh(Mdense)[0] > 0
+
+
+def test_sampled_local_part_against_dense_inverses():
+    # the sampled form used at full size: entries of sum_p R_p^T A_p^-1 R_p r from
+    # only the subdomains covering the sampled rows, against dense inverses
+    m = mg.box_mesh(9, 6, block=3, boxes=(3, 3, 3), faces=("x1",))
+    A, Ae, Afull, free, fidx = fem.stiffness(m.xyz, m.e2v, m.dirichlet)
+    sets = schwarz.overlapping_subdomains(m.e2v, m.part, m.n_part, 1)
+    R = [fidx[r] for r in schwarz.restriction_sets(m.e2v, sets, m.dirichlet)]
+    Ad = A.toarray()
+    r = np.random.default_rng(2).standard_normal(Ad.shape[0])
+    full = np.zeros(Ad.shape[0])
+    for Rp in R:
+        full[Rp] += np.linalg.solve(Ad[np.ix_(Rp, Rp)], r[Rp])
+    rows = np.random.default_rng(3).choice(Ad.shape[0], 17, replace=False)
+    got, which = schwarz.local_part_at(A, R, rows, r)
+    assert np.abs(got - full[rows]).max() < 1e-12 * np.abs(full).max()
+    assert 0 < len(which) < len(R)          # only the covering subdomains were factored
