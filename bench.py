@@ -227,18 +227,11 @@ def main():
         _log(f"batch: {batch}")
     serving = None
     if args.serving:
-        from paper_2606_20496_amd import serve
-        _log("serving workload: generating requests")
-        reqs = serve.make_requests(200.0, 192, nmax=96)
-        _log("serving: continuous batching")
-        srv = serve.Server(64e9, precision="mixed", use_graph=True, step_iters=2)
-        rec, wall = srv.run(reqs)
-        srv.close()
-        serving = {"rate_per_s": 200.0, "requests": 192, "mixed_continuous_batching": serve.summarize(rec, wall)}
-        _log(f"serving: {serving}")
-        rec2, wall2 = serve.serve_sequential(reqs)
-        serving["fp64_one_at_a_time"] = serve.summarize(rec2, wall2)
-        _log(f"sequential: {serving['fp64_one_at_a_time']}")
+        # the full-size serving workload once ended in a host segmentation fault
+        # whose cause has not been found; it stays switched off until it is
+        print("--serving is disabled: a full-size serving run crashed (host segmentation fault) "
+              "and the cause has not been found", file=sys.stderr)
+        sys.exit(2)
 
     cpu = None
     if not args.no_cpu_baseline:

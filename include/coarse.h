@@ -152,6 +152,27 @@ void coarse_default_opts(coarse_opts *o);
 int coarse_setup(const coarse_mesh *mesh, const coarse_bc *bc, const coarse_opts *opts,
                  coarse_ctx **out);
 
+/* coarse_setup in two halves, for callers that prepare new meshes while the GPU
+ * is busy with other work (a serving loop):
+ *   coarse_plan_create: the host half. Validates opts, orders the elements and
+ *     vertices, builds the overlapping subdomains and R_p (Sec. 3), the box grid,
+ *     the element cells and the weights of J (Sec. 4) and every work table. It
+ *     makes no HIP call and touches no device, so it may run on any host thread
+ *     while other threads use the GPU. The plan holds copies of all it needs: the
+ *     caller may free the mesh arrays on return. Errors: EINVAL, EMESH (mesh
+ *     topology), ENOMEM (host memory).
+ *   coarse_setup_from_plan: the device half, on `stream` (NULL = default stream;
+ *     opts.stream of the plan is not used): uploads the plan, forms the element
+ *     matrices, assembles and inverts every A_p and A_r. Errors as coarse_setup.
+ *     The plan is not modified and may be used again or destroyed afterwards.
+ *   coarse_plan_destroy: frees the plan (host memory only); NULL is accepted.
+ * coarse_setup(mesh, bc, opts, out) is these three calls with opts.stream. */
+typedef struct coarse_plan coarse_plan;
+int coarse_plan_create(const coarse_mesh *mesh, const coarse_bc *bc, const coarse_opts *opts,
+                       coarse_plan **out);
+int coarse_setup_from_plan(const coarse_plan *plan, void *stream, coarse_ctx **out);
+int coarse_plan_destroy(coarse_plan *plan);
+
 /* z = M^{-1} r: one application of the preconditioner selected by opts.mode
  * (eq. (asm) by default). r, z: device float64 [n_vert]. Errors: EINVAL. */
 int coarse_apply_precond(coarse_ctx *ctx, const double *r, double *z);

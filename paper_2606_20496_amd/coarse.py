@@ -26,7 +26,8 @@ EXPORTS = ("coarse_default_opts", "coarse_setup", "coarse_apply_precond", "coars
            "coarse_solve", "coarse_solve_batch", "coarse_destroy", "coarse_device_bytes",
            "coarse_get_info", "coarse_set_stream", "coarse_plan_info", "coarse_strerror",
            "coarse_last_error", "coarse_profile", "coarse_batch_create", "coarse_batch_submit",
-           "coarse_batch_step", "coarse_batch_live", "coarse_batch_destroy")
+           "coarse_batch_step", "coarse_batch_live", "coarse_batch_destroy", "coarse_plan_create",
+           "coarse_setup_from_plan", "coarse_plan_destroy")
 
 PHASES = ("A+p", "R_p+J^T", "J^T corners", "A_p^-1/A_r^-1 gemv", "combine", "sum+J", "x,r update")
 
@@ -122,6 +123,13 @@ def load():
     L.coarse_batch_live.restype = i32
     L.coarse_batch_destroy.argtypes = [vp]
     L.coarse_batch_destroy.restype = i32
+    L.coarse_plan_create.argtypes = [ctypes.POINTER(_Mesh), ctypes.POINTER(_BC), ctypes.POINTER(_Opts),
+                                     ctypes.POINTER(vp)]
+    L.coarse_plan_create.restype = i32
+    L.coarse_setup_from_plan.argtypes = [vp, vp, ctypes.POINTER(vp)]
+    L.coarse_setup_from_plan.restype = i32
+    L.coarse_plan_destroy.argtypes = [vp]
+    L.coarse_plan_destroy.restype = i32
     L.coarse_last_error.argtypes = [vp]
     L.coarse_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -184,6 +192,44 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+class Plan:
+    """The host half of a setup (coarse_plan_create): no GPU call, so it may be
+    built on a worker thread while the GPU serves other solves. Takes the same
+    arguments as :class:`CoarseSolver`; :meth:`CoarseSolver.from_plan` does the
+    device half."""
+
+    def __init__(self, xyz, e2v, dirichlet, part=None, n_part=1, *, overlap=1, boxes=None,
+                 precision="fp64", mode="additive", interp="centroid", max_it=1000, check_every=4,
+                 flexible=None):
+        L = load()
+        self._L = L
+        self.n_vert = int(np.asarray(xyz).shape[0])
+        self.precision = precision
+        m, bc, keep = _arrays(xyz, e2v, dirichlet, part, n_part)
+        o = _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible, None)
+        pl = ctypes.c_void_p()
+        rc = L.coarse_plan_create(ctypes.byref(m), ctypes.byref(bc), ctypes.byref(o), ctypes.byref(pl))
+        if rc != 0:
+            raise CoarseError(rc, L.coarse_last_error(None).decode())
+        self._plan = pl
+
+    @classmethod
+    def from_mesh(cls, mesh, **kw):
+        kw.setdefault("boxes", mesh.boxes)
+        return cls(mesh.xyz, mesh.e2v, mesh.dirichlet, mesh.part, mesh.n_part, **kw)
+
+    def close(self):
+        if getattr(self, "_plan", None):
+            self._L.coarse_plan_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class CoarseSolver:
     """One mesh's two-level Schwarz PCG solver on the current GPU.
 
@@ -216,6 +262,27 @@ class CoarseSolver:
     def from_mesh(cls, mesh, **kw):
         kw.setdefault("boxes", mesh.boxes)
         return cls(mesh.xyz, mesh.e2v, mesh.dirichlet, mesh.part, mesh.n_part, **kw)
+
+    @classmethod
+    def from_plan(cls, plan):
+        """The device half of a setup from a :class:`Plan`, on the current stream."""
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("CoarseSolver needs a GPU; no CPU fallback exists")
+        L = load()
+        self = cls.__new__(cls)
+        self._L = L
+        self.n_vert = plan.n_vert
+        self.precision = plan.precision
+        ctx = ctypes.c_void_p()
+        rc = L.coarse_setup_from_plan(plan._plan, _stream(), ctypes.byref(ctx))
+        if rc != 0:
+            raise CoarseError(rc, L.coarse_last_error(None).decode())
+        self._ctx = ctx
+        info = _Info()
+        L.coarse_get_info(ctx, ctypes.byref(info))
+        self.info = _info_dict(info)
+        return self
 
     def _check(self, rc):
         if rc < 0:

@@ -71,6 +71,14 @@ inline unsigned nblk(int64_t n, int b) { return (unsigned)std::max<int64_t>(1, (
 
 }  // namespace
 
+// Host half of a setup: everything the device half uploads, built without any
+// HIP call (so it may be built on any host thread).
+struct coarse_plan {
+  Plan P;
+  coarse_opts o;
+  double t_plan = 0.0;
+};
+
 struct coarse_ctx {
   std::string err;
   hipStream_t stream = nullptr;
@@ -454,7 +462,7 @@ int64_t invert_systems(coarse_ctx *c, const std::vector<System> &sys, const std:
 }
 
 template <typename T>
-void setup_precision(coarse_ctx *c, Plan &P) {
+void setup_precision(coarse_ctx *c, const Plan &P) {
   hipStream_t s = c->stream;
   Arena &A = c->arena;
   const int64_t NE = P.n_elem, NV = P.n_vert, nf = P.n_free;
@@ -923,7 +931,7 @@ int coarse_plan_info(const coarse_mesh *mesh, const coarse_bc *bc, const coarse_
   return 0;
 }
 
-int coarse_setup(const coarse_mesh *mesh, const coarse_bc *bc, const coarse_opts *opts, coarse_ctx **out) {
+int coarse_plan_create(const coarse_mesh *mesh, const coarse_bc *bc, const coarse_opts *opts, coarse_plan **out) {
   if (!mesh || !bc || !out) {
     g_setup_error = "null argument";
     return COARSE_EINVAL;
@@ -940,15 +948,50 @@ int coarse_setup(const coarse_mesh *mesh, const coarse_bc *bc, const coarse_opts
     g_setup_error = "bad mode, max_it or check_every";
     return COARSE_EINVAL;
   }
-  const double t0 = now();
-  Plan P;
-  int rc = build_plan(make_input(mesh, bc, &o), P);
-  if (rc) {
-    g_setup_error = P.err;
-    return rc;
+  try {
+    const double t0 = now();
+    std::unique_ptr<coarse_plan> pl(new coarse_plan());
+    pl->o = o;
+    int rc = build_plan(make_input(mesh, bc, &o), pl->P);
+    if (rc) {
+      g_setup_error = pl->P.err;
+      return rc;
+    }
+    pl->t_plan = now() - t0;
+    *out = pl.release();
+  } catch (const std::bad_alloc &) {
+    g_setup_error = "host allocation failed";
+    return COARSE_ENOMEM;
   }
+  return COARSE_OK;
+}
+
+int coarse_plan_destroy(coarse_plan *plan) {
+  delete plan;
+  return COARSE_OK;
+}
+
+int coarse_setup(const coarse_mesh *mesh, const coarse_bc *bc, const coarse_opts *opts, coarse_ctx **out) {
+  if (out) *out = nullptr;
+  coarse_plan *pl = nullptr;
+  int rc = coarse_plan_create(mesh, bc, opts, &pl);
+  if (rc) return rc;
+  rc = coarse_setup_from_plan(pl, pl->o.stream, out);
+  coarse_plan_destroy(pl);
+  return rc;
+}
+
+int coarse_setup_from_plan(const coarse_plan *plan, void *stream, coarse_ctx **out) {
+  if (!plan || !out) {
+    g_setup_error = "null argument";
+    return COARSE_EINVAL;
+  }
+  *out = nullptr;
+  const coarse_opts &o = plan->o;
+  const Plan &P = plan->P;
+  const double t0 = now() - plan->t_plan;
   std::unique_ptr<coarse_ctx> c(new coarse_ctx());
-  c->stream = (hipStream_t)o.stream;
+  c->stream = (hipStream_t)stream;
   c->precision = o.precision;
   c->mode = o.mode;
   c->interp = o.interp;

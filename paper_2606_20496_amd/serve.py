@@ -3,12 +3,16 @@ by HBM budget and a per-mesh context cache.
 
 Requests (arrival time, mesh key, mesh, right-hand side) are admitted as they
 arrive. A request whose mesh context is resident and idle joins the lock-step
-batch at the next step; a request for a new mesh first gets its context built
-by a setup worker thread (setups run on their own stream, overlapping the
-solves), if the resident contexts leave room in the HBM budget (idle contexts
-are evicted least-recently-used first; otherwise the setup waits). Finished
-solves retire after each step and free their mesh for the next request on it.
-Every solve's result is bitwise what a solo solve of the same context gives.
+batch at the next step. A request for a new mesh first gets its setup plan (the
+host half of the setup: orderings, subdomains, box grid, work tables) built by a
+worker thread, which makes no GPU call, while the GPU keeps serving; the device
+half (uploads, element matrices, inversions) then runs on the serving thread
+between lock steps, on its own stream, once the resident contexts leave room in
+the HBM budget (idle contexts are evicted least-recently-used first; otherwise
+the plan waits). All GPU calls of the loop come from the one serving thread.
+Finished solves retire after each step and free their mesh for the next request
+on it. Every solve's result is bitwise what a solo solve of the same context
+gives.
 
 The plain FP64 one-at-a-time path (:func:`serve_sequential`) processes the same
 request stream in arrival order with one solve at a time, for comparison.
@@ -67,7 +71,7 @@ def summarize(records, wall):
 
 class Server:
     def __init__(self, budget_bytes, precision="mixed", use_graph=True, step_iters=2, tol=1e-8,
-                 setup_workers=2, solver_kw=None, keep_outputs=False):
+                 plan_workers=2, solver_kw=None, keep_outputs=False):
         import torch
         self.torch = torch
         self.budget = int(budget_bytes)
@@ -75,23 +79,25 @@ class Server:
         self.step_iters = int(step_iters)
         self.tol = tol
         self.stream = torch.cuda.Stream()
+        self.setup_stream = torch.cuda.Stream()
         self.batch = coarse.Batch(stream=self.stream, use_graph=use_graph)
-        self.pool = cf.ThreadPoolExecutor(max_workers=setup_workers)
+        self.pool = cf.ThreadPoolExecutor(max_workers=plan_workers)
         self.solver_kw = dict(solver_kw or {})
         self.cache = collections.OrderedDict()   # key -> CoarseSolver (LRU order)
         self.busy = set()                        # keys with a live solve
-        self.setting_up = {}                     # key -> Future
-        self.pending = {}                        # key -> estimated bytes of a setup in flight
+        self.planning = {}                       # key -> Future of a Plan (host only)
+        self.ready = {}                          # key -> (Plan, estimated bytes)
+        self.max_plans = 2 * plan_workers        # plans held on the host at once
         self.used = 0
         self.keep_outputs = keep_outputs
 
-    def _setup(self, mesh):
-        torch = self.torch
-        s = torch.cuda.Stream()
-        with torch.cuda.stream(s):
-            S = coarse.CoarseSolver.from_mesh(mesh, precision=self.precision, **self.solver_kw)
-        s.synchronize()
-        S._setup_stream = s          # the context keeps using this stream handle between solves
+    def _plan(self, mesh):
+        return coarse.Plan.from_mesh(mesh, precision=self.precision, **self.solver_kw)
+
+    def _device_setup(self, plan):
+        with self.torch.cuda.stream(self.setup_stream):
+            S = coarse.CoarseSolver.from_plan(plan)
+        self.setup_stream.synchronize()
         return S
 
     def _evict_for(self, need, keep=()):
@@ -123,24 +129,21 @@ class Server:
         torch = self.torch
         reqs = collections.deque(sorted(requests, key=lambda r: r.t_arrive))
         waiting = collections.deque()      # arrived, not yet in the batch
-        live = {}                          # rid -> (Request, u, missed)
+        live = {}                          # rid -> (Request, u, b)
         missed = set()
         records = []
         t0 = time.perf_counter() if t0 is None else t0
         now = lambda: time.perf_counter() - t0
-        while reqs or waiting or live or self.setting_up:
+        while reqs or waiting or live or self.planning or self.ready:
             t = now()
             while reqs and reqs[0].t_arrive <= t:
                 waiting.append(reqs.popleft())
-            # finished setups become resident
-            for key, fut in list(self.setting_up.items()):
+            # plans finished on the worker threads
+            for key, fut in list(self.planning.items()):
                 if fut.done():
-                    S = fut.result()
-                    del self.setting_up[key]
-                    self.pending.pop(key, None)
-                    self.cache[key] = S
-                    self.used += S.device_bytes
-            # admit waiting requests: first those whose context is resident and idle
+                    del self.planning[key]
+                    self.ready[key] = fut.result()
+            # admit waiting requests whose context is resident and idle
             keep = collections.deque()
             for rq in waiting:
                 if rq.key in self.cache and rq.key not in self.busy:
@@ -155,20 +158,26 @@ class Server:
                 else:
                     keep.append(rq)
             waiting = keep
-            # then start setups for new meshes while the budget allows; contexts a
-            # waiting request needs are never evicted, and a setup that does not fit
-            # even with everything idle evicted runs only when nothing else does
+            # device halves of ready plans while the budget allows; contexts a
+            # waiting request needs are never evicted, and a context that does not
+            # fit even with everything idle evicted is built only when no solve runs
             needed = {rq.key for rq in waiting}
+            for key, (plan, need) in list(self.ready.items()):
+                if self._evict_for(need, keep=needed) or not live:
+                    S = self._device_setup(plan)
+                    plan.close()
+                    del self.ready[key]
+                    self.cache[key] = S
+                    self.used += S.device_bytes
+            # host plans for new meshes
             for rq in waiting:
-                if rq.key in self.cache or rq.key in self.setting_up:
+                if rq.key in self.cache or rq.key in self.planning or rq.key in self.ready:
                     continue
+                if len(self.planning) + len(self.ready) >= self.max_plans:
+                    break
                 need = self.estimate_bytes(rq.mesh, self.precision)
-                fits = self._evict_for(need + sum(self.pending.values()), keep=needed)
-                alone = not self.busy and not self.setting_up and not live
-                if fits or alone:
-                    self.setting_up[rq.key] = self.pool.submit(self._setup, rq.mesh)
-                    self.pending[rq.key] = need
-                    missed.add(rq.rid)
+                self.planning[rq.key] = self.pool.submit(lambda m=rq.mesh, n=need: (self._plan(m), n))
+                missed.add(rq.rid)
             if live:
                 for tag, st in self.batch.step(self.step_iters):
                     rq, u, b = live.pop(tag)
@@ -184,6 +193,9 @@ class Server:
 
     def close(self):
         self.pool.shutdown(wait=True)
+        for plan, _ in self.ready.values():
+            plan.close()
+        self.ready.clear()
         self.batch.close()
         for S in self.cache.values():
             S.close()

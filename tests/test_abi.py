@@ -96,3 +96,15 @@ def test_solver_refuses_without_gpu():
     m = mg.small_cube()
     with pytest.raises(RuntimeError):
         coarse.CoarseSolver.from_mesh(m)
+
+
+def test_plan_is_host_only():
+    # the host half of a setup runs without any GPU (this machine may have none)
+    m = mg.small_cube()
+    pl = coarse.Plan.from_mesh(m, precision="mixed")
+    assert pl._plan
+    pl.close()
+    pl.close()                      # idempotent
+    with pytest.raises(coarse.CoarseError) as ei:
+        coarse.Plan(m.xyz, m.e2v, m.dirichlet, m.part, m.n_part, boxes=m.boxes, max_it=0)
+    assert ei.value.code == -1

@@ -47,3 +47,22 @@ def test_tight_budget_still_serves_everything():
     records, wall = srv.run(reqs)
     srv.close()
     assert len(records) == 16 and all(r.status == 0 for r in records)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_setup_from_plan_equals_setup(precision):
+    # the two halves of a setup give the same context as the one-call setup,
+    # and a plan can serve more than one device setup
+    from paper_2606_20496_amd import meshgen as mg
+    m = mg.box_mesh(12, 41, block=4, boxes=(3, 3, 3), faces=("y0",))
+    b = torch.tensor(m.b, device="cuda")
+    S1 = coarse.CoarseSolver.from_mesh(m, precision=precision)
+    pl = coarse.Plan.from_mesh(m, precision=precision)
+    S2 = coarse.CoarseSolver.from_plan(pl)
+    S3 = coarse.CoarseSolver.from_plan(pl)
+    pl.close()
+    u1, s1 = S1.solve(b)
+    for S in (S2, S3):
+        u, st = S.solve(b)
+        assert st["iters"] == s1["iters"] and torch.equal(u, u1)
+        assert S.device_bytes == S1.device_bytes
