@@ -144,6 +144,72 @@ def run_batch_workload(torch, coarse, mg, tol, reps=3):
     return out
 
 
+def kernel_bytes(info, n_elem, precision):
+    """Algorithmic bytes per launch of the per-iteration kernels (what the method
+    must move with this storage; index tables of the blocking scheme excluded):
+    A+p  : A^e (36 unique FP64 = 288 B) + 8 u16 slots per element; z, p_old read,
+           p and q written per free vertex
+    R_p+J^T stage 1: per packed entry index + r value + r_p write; per J entry
+           vertex id, weight, 3 local coordinates and the r value
+    sum+J: per packed entry position + z_p; per free vertex cover pointer, r read,
+           z written, J pointer; per J entry base corner, weight, 3 coordinates
+    x,r update: x, r read and written, p, q read per free vertex."""
+    es = 8 if precision == "fp64" else 4
+    nf, snp, nj = info["n_free"], info["sum_np"], info["n_jent"]
+    return {
+        "A+p": n_elem * (288 + 16) + nf * 32,
+        "R_p+J^T": snp * (4 + 8 + es) + nj * (4 + es + 3 * es + 8),
+        "sum+J": snp * (4 + 8) + nf * (4 + 8 + 8 + 4) + nj * (4 + es + 3 * es),
+        "x,r update": nf * 48,
+    }
+
+
+def run_kernels_large(torch, coarse, mg, tol):
+    """The operator and interpolation kernels on the 128^3 quarter-annulus (2.1M
+    elements, 4096 subdomains), where launch latency is amortised: HIP-event
+    timings of every launch over one whole solve, against algorithmic bytes."""
+    mesh = mg.large_annulus()
+    out = {"workload": "annulus128: 128^3 quarter-annulus, radial ratio 1.05, 4096 subdomains of 8^3, "
+                       "16^3 boxes", "n_elem": mesh.n_elem}
+    b = torch.tensor(mesh.b, device="cuda")
+    u = torch.empty_like(b)
+    for prec in ("fp64", "mixed"):
+        t0 = time.perf_counter()
+        S = coarse.CoarseSolver.from_mesh(mesh, precision=prec)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        S.solve(b, tol, out=u)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, st = S.solve(b, tol, out=u)
+        torch.cuda.synchronize()
+        t_solve = time.perf_counter() - t1
+        S.profile_start(0x7F)
+        S.solve(b, tol, out=u)
+        ph = S.profile_stop()
+        info = dict(S.info)
+        S.close()
+        kb = kernel_bytes(info, mesh.n_elem, prec)
+        ks = {}
+        for name, (ms, cnt) in ph.items():
+            avg = ms / max(cnt, 1) * 1e3
+            e = {"avg_us": round(avg, 2), "launches": cnt}
+            if name in kb and avg > 0:
+                gbs = kb[name] / (avg * 1e-6) / 1e9
+                e.update(alg_bytes=kb[name], GBs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4))
+            ks[name] = e
+        gm = ph[coarse.PHASES[GEMV_PHASE]]
+        gavg = gm[0] / max(st["iters"], 1) * 1e3
+        ks[coarse.PHASES[GEMV_PHASE]].update(
+            alg_bytes=info["inv_alg_bytes"], avg_us_work=round(gavg, 2),
+            GBs=round(info["inv_alg_bytes"] / (gavg * 1e-6) / 1e9, 1),
+            frac=round(info["inv_alg_bytes"] / (gavg * 1e-6) / 1e9 / HBM_PEAK_GBS, 4))
+        out[prec] = {"iters": st["iters"], "relres_true": st["relres_true"], "solve_ms": round(1e3 * t_solve, 3),
+                     "solves_per_s": round(1.0 / t_solve, 3), "setup_s": round(t_setup, 3), "kernels": ks}
+        _log(f"annulus128 {prec}: {st['iters']} iters, {1e3 * t_solve:.2f} ms/solve")
+    return out
+
+
 def cpu_baseline(mesh, tol):
     """The FP64 oracle, as it stands, on the host cores: one full solve of the
     same workload (setup timed separately and excluded)."""
@@ -170,7 +236,8 @@ def main():
     ap.add_argument("--n", type=int, default=64, help="cube edge in elements (64 = one GPU's share)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--batch", action="store_true", help="also run the 64-mesh batched workload")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-mesh batched workload")
+    ap.add_argument("--no-large", action="store_true", help="skip the 128^3 annulus kernel measurements")
     ap.add_argument("--serving", action="store_true", help="also run a short serving-loop workload")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 1 GiB device copy (known bytes) to scale HBM counters")
@@ -221,10 +288,15 @@ def main():
     phases = {k: {"avg_us": round(1e3 * v[0] / max(v[1], 1), 2), "launches": v[1]} for k, v in fp64["phases"].items()}
 
     batch = None
-    if args.batch:
+    if not args.no_batch:
         _log("batch workload")
         batch = run_batch_workload(torch, coarse, mg, args.tol)
         _log(f"batch: {batch}")
+    large = None
+    if not args.no_large:
+        _log("annulus128 kernels")
+        large = run_kernels_large(torch, coarse, mg, args.tol)
+
     serving = None
     if args.serving:
         # the full-size serving workload once ended in a host segmentation fault
@@ -278,6 +350,8 @@ def main():
     }
     if batch is not None:
         line["batch_workload"] = batch
+    if large is not None:
+        line["large_workload"] = large
     if serving is not None:
         line["serving_workload"] = serving
     print(json.dumps(line), flush=True)

@@ -135,6 +135,8 @@ typedef struct {
   int64_t inv_alg_bytes; /* sum over local and reduced systems of n(n+1)/2 stored
                             entries times the element size: the packed symmetric
                             inverses one preconditioner application must read     */
+  int64_t n_jent;        /* entries of J: (free vertex, cell) pairs with a nonzero
+                            weight fraction (Sec. 4, J = W Q^T J_L S)              */
   int64_t device_bytes;  /* all device memory held by the context                   */
   int32_t boxes[3];
   int32_t precision;

@@ -51,17 +51,22 @@ def element_matrices(xyz, e2v):
     return A, detmin
 
 
-def element_magnitudes(xyz, e2v):
+def element_magnitudes(xyz, e2v, conditioned=False):
     """The same sum as :func:`element_matrices` taken in absolute values,
     sum_q |J_q| |G_q| |G_q|^T (E, 8, 8): the magnitude that bounds the rounding
-    error of any evaluation of A^e and of the products with it."""
+    error of the products with A^e. With ``conditioned`` each quadrature term is
+    weighted by the 2-norm condition number of J_q, since the physical gradients
+    G_q = gN J_q^{-1} carry a relative rounding error of order cond(J_q) eps."""
     X = np.asarray(xyz, dtype=np.float64)[np.asarray(e2v)]
     M = np.zeros((X.shape[0], 8, 8))
     for q in GAUSS_POINTS:
         gN = ref_gradients(q)
         Jac = np.matmul(X.transpose(0, 2, 1), gN)
         G = np.abs(np.matmul(gN[None, :, :], np.linalg.inv(Jac)))
-        M += np.abs(np.linalg.det(Jac))[:, None, None] * np.matmul(G, G.transpose(0, 2, 1))
+        w = np.abs(np.linalg.det(Jac))
+        if conditioned:
+            w = w * np.linalg.cond(Jac)
+        M += w[:, None, None] * np.matmul(G, G.transpose(0, 2, 1))
     return M
 
 

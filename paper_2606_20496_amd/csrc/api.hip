@@ -673,6 +673,7 @@ void setup_precision(coarse_ctx *c, const Plan &P) {
   in.reduced_bytes = (P.n_tiles - tl) * TILE * TILE * (int64_t)sizeof(T);
   in.inv_alg_bytes = 0;
   for (const System &S : P.sys) in.inv_alg_bytes += S.n * (S.n + 1) / 2 * (int64_t)sizeof(T);
+  in.n_jent = (int64_t)P.jv_w.size();
   in.a_bytes = NE * (36 * 8 + 8 * 2) + (int64_t)P.slot_vid.size() * 12 + (int64_t)P.slot_inc.size() * 2 + nf * 16;
   for (int d = 0; d < 3; ++d) in.boxes[d] = P.b[d];
   in.precision = c->precision;
@@ -924,6 +925,7 @@ int coarse_plan_info(const coarse_mesh *mesh, const coarse_bc *bc, const coarse_
   }
   info->n_r = P.n_r;
   info->n_cells = (int64_t)P.occ_cells.size();
+  info->n_jent = (int64_t)P.jv_w.size();
   for (int d = 0; d < 3; ++d) info->boxes[d] = P.b[d];
   info->precision = o.precision;
   if (sizes)

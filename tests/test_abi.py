@@ -62,6 +62,11 @@ def test_plan_matches_oracle_reduced_space():
         info, _ = coarse.plan_info(m.xyz, m.e2v, m.dirichlet, m.part, m.n_part, boxes=m.boxes)
         assert info["n_r"] == S.n_r
         assert info["n_cells"] == len(np.unique(S.cells[:, 0] + 1000 * S.cells[:, 1] + 10 ** 6 * S.cells[:, 2]))
+        # J entries: distinct (free vertex, cell of an incident element) pairs
+        cid = S.cells[:, 0] + 1000 * S.cells[:, 1] + 10 ** 6 * S.cells[:, 2]
+        v = fidx[np.asarray(m.e2v)]
+        pairs = np.unique(np.stack([v.ravel(), np.repeat(cid, 8)], 1)[v.ravel() >= 0], axis=0)
+        assert info["n_jent"] == len(pairs)
 
 
 def test_plan_partition_by_bisection():

@@ -37,7 +37,8 @@ def c3():
     m = mg.large_annulus()
     d = m.dirichlet.astype(bool)
     A, Ae, _, free, fidx = fem.stiffness(m.xyz, m.e2v, d)
-    absA = fem.assemble(fem.element_magnitudes(m.xyz, m.e2v), m.e2v, m.n_vert)[free][:, free].tocsr()
+    absA = fem.assemble(fem.element_magnitudes(m.xyz, m.e2v, conditioned=True), m.e2v,
+                        m.n_vert)[free][:, free].tocsr()
     mult = fem.multiplicity(m.e2v, m.n_vert)
     red = reduced.CentroidSpace(m.xyz, m.e2v, d, Ae, m.boxes, fidx, mult)
     sets = schwarz.overlapping_subdomains(m.e2v, m.part, m.n_part, 1)
@@ -78,9 +79,8 @@ def test_c3_apply_A(c3):
     # The radially stretched elements near r = 1 (aspect ratio ~130) have entries
     # far larger than the result, and A is applied element by element (Sec. 3,
     # A = Q^T A_L Q), so the bar is the rounding bound of that computation, entry
-    # by entry: 256 eps times the same sums taken in absolute values (quadrature
-    # terms, element entries and incident elements), which covers the 8 Gauss
-    # points and the summation in any order.
+    # by entry: 64 eps times the same sums in absolute values, each quadrature
+    # term weighted by cond(J_q) (the gradients come from J_q^{-1}).
     m = c3["m"]
     S = coarse.CoarseSolver.from_mesh(m, mode="local_only")
     p = np.random.default_rng(13).standard_normal(m.n_vert)
@@ -88,8 +88,10 @@ def test_c3_apply_A(c3):
     S.close()
     A, pf = c3["A"], p[c3["free"]]
     ref = A @ pf
-    bound = 256 * np.finfo(np.float64).eps * (c3["absA"] @ np.abs(pf))
-    assert np.all(np.abs(q - ref) <= bound)
+    bound = 64 * np.finfo(np.float64).eps * (c3["absA"] @ np.abs(pf))
+    ratio = np.abs(q - ref) / bound
+    k = int(np.argmax(ratio))
+    assert ratio[k] <= 1.0, (float(ratio[k]), k, float(q[k]), float(ref[k]), float(bound[k]))
     assert _relmax(q, ref) < 1e-12
 
 

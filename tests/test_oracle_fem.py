@@ -174,3 +174,8 @@ def test_element_magnitudes_bound_the_element_matrices():
     cube = np.array([[i, j, k] for k in (0, 1) for j in (0, 1) for i in (0, 1)], dtype=float)
     Mc = fem.element_magnitudes(cube, np.arange(8)[None, :])[0]
     assert np.allclose(np.diag(Mc), 1.0 / 3.0, rtol=1e-14)
+    # the conditioned form: cond(J) = 1 on the unit cube, = 4 on a 1 x 1 x 1/4 box
+    assert np.allclose(fem.element_magnitudes(cube, np.arange(8)[None, :], conditioned=True)[0], Mc, rtol=1e-14)
+    flat = cube * np.array([1.0, 1.0, 0.25])
+    assert np.allclose(fem.element_magnitudes(flat, np.arange(8)[None, :], conditioned=True)[0],
+                       4.0 * fem.element_magnitudes(flat, np.arange(8)[None, :])[0], rtol=1e-13)
