@@ -192,6 +192,10 @@ struct coarse_ctx {
     pend(2);
   }
 
+  // workgroups of k_pre: the gather part and the J^T task part (each loops)
+  int pre_gather_blocks() const { return (int)std::min<int64_t>(nblk(coarse_vec_off, 256), 1024); }
+  int pre_task_blocks() const { return (int)std::min<int64_t>(nblk(ntask, 4), 512); }
+
   template <typename T>
   void corners(const int *done) {
     hipLaunchKernelGGL(k_jt_corners<T>, dim3(nblk(n_r, 4)), dim3(256), 0, stream, n_r, done, jr_ptr, jr_src,
@@ -222,7 +226,7 @@ struct coarse_ctx {
   void final_step(const double *add, bool local, bool coarse, double *out, const double *rdot, double *p1, double *p2,
                   const int *done, bool scal, int start) {
     pbeg(5);
-    hipLaunchKernelGGL(k_final<T>, dim3(nvblk), dim3(VB), 0, stream, nf, done, add, local ? cover_ptr : nullptr,
+    hipLaunchKernelGGL(k_final<T>, dim3(nvblk), dim3(VW), 0, stream, nf, done, add, local ? cover_ptr : nullptr,
                        cover_pos, zp, coarse ? jv_ptr : nullptr, jv_base, (const T *)jv_w, (const T *)jv_xi, nent, bx1,
                        bxy1, (const double *)yfull, out, rdot, p1, p2, scal ? sc : nullptr, start);
     pend(5);
@@ -235,8 +239,7 @@ struct coarse_ctx {
     if (local && coarse) {
       // convergence test, R_p gather and the first stage of J^T in one launch
       pbeg(1);
-      const int ng = (int)nblk(coarse_vec_off, 256);
-      const int nt = (int)nblk(ntask, 4);
+      const int ng = pre_gather_blocks(), nt = pre_task_blocks();
       hipLaunchKernelGGL(k_pre<T>, dim3(ng + nt), dim3(256), 0, stream, ng, coarse_vec_off, done, sub_idx, in, (T *)rp,
                          (int)ntask, jt_start, jc_vid, (const T *)jc_w, (const T *)jc_xi, nent, (T *)jt_part,
                          chk ? sc : nullptr, chk, nvblk, start);
@@ -312,7 +315,7 @@ struct coarse_ctx {
                        (const double *)z, p, pb, q, energy, sc, (const double *)part1, (const double *)part2, nvblk);
     pend(0);
     pbeg(6);
-    hipLaunchKernelGGL(k_update_fused, dim3(nvblk), dim3(VB), 0, stream, nf, op, sc, x, r, (const double *)p,
+    hipLaunchKernelGGL(k_update_fused, dim3(nvblk), dim3(VW), 0, stream, nf, op, sc, x, r, (const double *)p,
                        (const double *)pb, (const double *)q, (const double *)energy, (int)op.n_blocks, prr);
     pend(6);
   }
@@ -323,8 +326,7 @@ struct coarse_ctx {
   template <typename T>
   void front_t() {
     op_update();
-    const int ng = (int)nblk(coarse_vec_off, 256);
-    const int nt = (int)nblk(ntask, 4);
+    const int ng = pre_gather_blocks(), nt = pre_task_blocks();
     hipLaunchKernelGGL(k_pre<T>, dim3(ng + nt), dim3(256), 0, stream, ng, coarse_vec_off, done_flag, sub_idx, r,
                        (T *)rp, (int)ntask, jt_start, jc_vid, (const T *)jc_w, (const T *)jc_xi, nent, (T *)jt_part, sc,
                        (const double *)prr, nvblk, 0);

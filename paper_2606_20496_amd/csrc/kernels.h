@@ -54,7 +54,7 @@ struct Seg {
 struct OpDev {
   int64_t E, n_blocks, n_shared;
   const double *Ae;
-  const uint16_t *lconn;
+  const uint16_t *lconn;   // [E][8] block-local slots, one 16-byte load per element
   const int32_t *blk_slot_ptr, *slot_vid, *slot_dst, *slot_inc_ptr;
   const uint16_t *slot_inc;
   double *partials;

@@ -91,6 +91,72 @@ __global__ __launch_bounds__(256) void k_elem_matrices(int64_t E, int64_t NV, co
 // shared with other blocks go to a partial buffer that pass 2 sums. The energy
 // p^T A p = sum_e p_e^T A^e p_e (the PCG denominator) comes out per block.
 // ---------------------------------------------------------------------------
+// An element's 8 block-local slots (one 16-byte record) and its 36 unique matrix
+// entries do not depend on the vector: their loads are issued first and stay in
+// flight while the block stages its vertex values.
+__device__ __forceinline__ void elem_load(const OpDev &op, int64_t e, double m[36], uint4 &c) {
+  c = *(const uint4 *)(op.lconn + e * 8);
+#pragma unroll
+  for (int k = 0; k < 36; ++k) m[k] = op.Ae[k * op.E + e];
+}
+
+__device__ __forceinline__ unsigned slot_at(const uint4 &c, int a) {
+  const unsigned w = (a < 2) ? c.x : (a < 4) ? c.y : (a < 6) ? c.z : c.w;
+  return (a & 1) ? (w >> 16) : (w & 0xFFFFu);
+}
+
+// y = A^e p_e from the staged slot values (upper triangle row by row, mirrored)
+// into out[0..8); returns p_e . y.
+__device__ __forceinline__ double elem_apply(const double m[36], const uint4 &c, const double *lp, double *out) {
+  double pe[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const unsigned sl = slot_at(c, a);
+    pe[a] = (sl == 0xFFFFu) ? 0.0 : lp[sl];
+  }
+  double y[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) y[a] = 0.0;
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = a; b < 8; ++b) {
+      const double v = m[sym8(a, b)];
+      y[a] += v * pe[b];
+      if (b != a) y[b] += v * pe[a];
+    }
+  double en = 0.0;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    out[a] = y[a];
+    en += pe[a] * y[a];
+  }
+  return en;
+}
+
+// Per slot of the block, the element outputs of its incidences summed in list
+// order (the first 8 incidence loads issued together), written to q for a vertex
+// the block owns or to its partial otherwise.
+__device__ __forceinline__ void block_scatter(const OpDev &op, int s0, int ns, const double *out,
+                                              double *__restrict__ q) {
+  for (int s = threadIdx.x; s < ns; s += OP_BLOCK) {
+    const int k0 = op.slot_inc_ptr[s0 + s], k1 = op.slot_inc_ptr[s0 + s + 1];
+    const int dst = op.slot_dst[s0 + s];
+    unsigned li[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) li[k] = (k0 + k < k1) ? op.slot_inc[k0 + k] : 0u;
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (k0 + k < k1) acc += out[li[k]];
+    for (int k = k0 + 8; k < k1; ++k) acc += out[op.slot_inc[k]];
+    if (dst >= 0)
+      q[dst] = acc;
+    else
+      op.partials[-dst - 1] = acc;
+  }
+}
+
 __global__ __launch_bounds__(OP_BLOCK) void k_op_pass1(OpDev op, const double *__restrict__ p, double *__restrict__ q,
                                                        double *__restrict__ energy, const int *__restrict__ done) {
   extern __shared__ double lds[];
@@ -99,47 +165,17 @@ __global__ __launch_bounds__(OP_BLOCK) void k_op_pass1(OpDev op, const double *_
   double *out = lds;                 // [OP_BLOCK*8]
   double *lp = lds + OP_BLOCK * 8;   // [slots]
   const int blk = blockIdx.x;
+  const int64_t e = (int64_t)blk * OP_BLOCK + threadIdx.x;
+  double m[36];
+  uint4 c = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+  if (e < op.E) elem_load(op, e, m, c);
   const int s0 = op.blk_slot_ptr[blk], ns = op.blk_slot_ptr[blk + 1] - s0;
   for (int s = threadIdx.x; s < ns; s += OP_BLOCK) lp[s] = p[op.slot_vid[s0 + s]];
   __syncthreads();
-  const int64_t E = op.E;
-  const int64_t e = (int64_t)blk * OP_BLOCK + threadIdx.x;
   double en = 0.0;
-  if (e < E) {
-    double pe[8];
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      const uint16_t sl = op.lconn[a * E + e];
-      pe[a] = (sl == 0xFFFF) ? 0.0 : lp[sl];
-    }
-    double y[8];
-#pragma unroll
-    for (int a = 0; a < 8; ++a) y[a] = 0.0;
-#pragma unroll
-    for (int a = 0; a < 8; ++a)
-#pragma unroll
-      for (int b = a; b < 8; ++b) {
-        const double m = op.Ae[sym8(a, b) * E + e];
-        y[a] += m * pe[b];
-        if (b != a) y[b] += m * pe[a];
-      }
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      out[threadIdx.x * 8 + a] = y[a];
-      en += pe[a] * y[a];
-    }
-  }
+  if (e < op.E) en = elem_apply(m, c, lp, out + threadIdx.x * 8);
   __syncthreads();
-  for (int s = threadIdx.x; s < ns; s += OP_BLOCK) {
-    const int k0 = op.slot_inc_ptr[s0 + s], k1 = op.slot_inc_ptr[s0 + s + 1];
-    double acc = 0.0;
-    for (int k = k0; k < k1; ++k) acc += out[op.slot_inc[k]];
-    const int dst = op.slot_dst[s0 + s];
-    if (dst >= 0)
-      q[dst] = acc;
-    else
-      op.partials[-dst - 1] = acc;
-  }
+  block_scatter(op, s0, ns, out, q);
   if (energy) {
     const double tot = block_sum<OP_BLOCK>(en, red);
     if (threadIdx.x == 0) energy[blk] = tot;
@@ -161,6 +197,11 @@ __global__ __launch_bounds__(256) void k_op_pass2(OpDev op, double *__restrict__
 // reproducible.
 // ---------------------------------------------------------------------------
 constexpr int VB = 256;
+// The two per-vertex kernels of every iteration (update, final sum) run with
+// larger workgroups: their grid is capped at 1024 workgroups (the partial sums
+// that later kernels add up redundantly), so more threads per workgroup means
+// more loads in flight.
+constexpr int VW = 512;
 
 __global__ __launch_bounds__(VB) void k_permute_in(int64_t nf, const int32_t *__restrict__ user_of, const double *__restrict__ b,
                                                    double *__restrict__ r, double *__restrict__ x, double *__restrict__ p,
@@ -262,11 +303,20 @@ __global__ __launch_bounds__(VB) void k_res_total(Scalars *__restrict__ sc, cons
 // records it in the solver state. Values that a kernel both reads and records
 // (rho) are double-buffered by iteration parity.
 // ---------------------------------------------------------------------------
+constexpr int UV = 4;   // entries per thread and step in the restriction gather
+
 // Sum of part[0..n) in a fixed order, returned to every thread (NT threads).
 template <int NT>
 __device__ __forceinline__ double block_total(const double *__restrict__ part, int n, double *red) {
   double acc = 0.0;
-  for (int i = threadIdx.x; i < n; i += NT) acc += part[i];
+  for (int i0 = threadIdx.x; i0 < n; i0 += 4 * NT) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = (i0 + u * NT < n) ? part[i0 + u * NT] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i0 + u * NT < n) acc += v[u];
+  }
   acc = wave_sum(acc);
   const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
   __syncthreads();
@@ -327,6 +377,11 @@ __global__ __launch_bounds__(OP_BLOCK) void k_op_fused(OpDev op, const double *_
   extern __shared__ double lds[];
   __shared__ double red[OP_BLOCK / WAVE];
   if (sc->done) return;
+  const int blk = blockIdx.x;
+  const int64_t e = (int64_t)blk * OP_BLOCK + threadIdx.x;
+  double m[36];
+  uint4 c = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+  if (e < op.E) elem_load(op, e, m, c);
   const int it = sc->iter;
   const double rho = block_total<OP_BLOCK>(rz1, nrz, red);
   double beta = 0.0;
@@ -350,53 +405,30 @@ __global__ __launch_bounds__(OP_BLOCK) void k_op_fused(OpDev op, const double *_
   const double *pprev = (it & 1) ? pa : pb;
   double *out = lds;
   double *lp = lds + OP_BLOCK * 8;
-  const int blk = blockIdx.x;
   const int s0 = op.blk_slot_ptr[blk], ns = op.blk_slot_ptr[blk + 1] - s0;
-  for (int s = threadIdx.x; s < ns; s += OP_BLOCK) {
-    const int32_t v = op.slot_vid[s0 + s];
-    const double pv = z[v] + beta * pprev[v];
-    lp[s] = pv;
-    if (op.slot_pw[s0 + s]) pcur[v] = pv;
+  // two slots per thread and step, their loads issued together
+  for (int s = threadIdx.x; s < ns; s += 2 * OP_BLOCK) {
+    const int s1 = s + OP_BLOCK;
+    const bool two = s1 < ns;
+    const int32_t v0 = op.slot_vid[s0 + s];
+    const int32_t v1 = two ? op.slot_vid[s0 + s1] : v0;
+    const uint8_t w0 = op.slot_pw[s0 + s];
+    const uint8_t w1 = two ? op.slot_pw[s0 + s1] : 0;
+    const double z0 = z[v0], z1 = z[v1], q0 = pprev[v0], q1 = pprev[v1];
+    const double pv0 = z0 + beta * q0;
+    lp[s] = pv0;
+    if (w0) pcur[v0] = pv0;
+    if (two) {
+      const double pv1 = z1 + beta * q1;
+      lp[s1] = pv1;
+      if (w1) pcur[v1] = pv1;
+    }
   }
   __syncthreads();
-  const int64_t E = op.E;
-  const int64_t e = (int64_t)blk * OP_BLOCK + threadIdx.x;
   double en = 0.0;
-  if (e < E) {
-    double pe[8];
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      const uint16_t sl = op.lconn[a * E + e];
-      pe[a] = (sl == 0xFFFF) ? 0.0 : lp[sl];
-    }
-    double y[8];
-#pragma unroll
-    for (int a = 0; a < 8; ++a) y[a] = 0.0;
-#pragma unroll
-    for (int a = 0; a < 8; ++a)
-#pragma unroll
-      for (int b = a; b < 8; ++b) {
-        const double m = op.Ae[sym8(a, b) * E + e];
-        y[a] += m * pe[b];
-        if (b != a) y[b] += m * pe[a];
-      }
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      out[threadIdx.x * 8 + a] = y[a];
-      en += pe[a] * y[a];
-    }
-  }
+  if (e < op.E) en = elem_apply(m, c, lp, out + threadIdx.x * 8);
   __syncthreads();
-  for (int s = threadIdx.x; s < ns; s += OP_BLOCK) {
-    const int k0 = op.slot_inc_ptr[s0 + s], k1 = op.slot_inc_ptr[s0 + s + 1];
-    double acc = 0.0;
-    for (int k = k0; k < k1; ++k) acc += out[op.slot_inc[k]];
-    const int dst = op.slot_dst[s0 + s];
-    if (dst >= 0)
-      q[dst] = acc;
-    else
-      op.partials[-dst - 1] = acc;
-  }
+  block_scatter(op, s0, ns, out, q);
   const double tot = block_sum<OP_BLOCK>(en, red);
   if (threadIdx.x == 0) energy[blk] = tot;
 }
@@ -404,15 +436,15 @@ __global__ __launch_bounds__(OP_BLOCK) void k_op_fused(OpDev op, const double *_
 // alpha = rho / p.Ap (from the operator's partials), x += alpha p,
 // r -= alpha q (q of vertices shared between operator blocks is summed here from
 // the operator's partials), and partials of ||r||^2.
-__global__ __launch_bounds__(VB) void k_update_fused(int64_t nf, OpDev op, Scalars *__restrict__ sc, double *__restrict__ x,
+__global__ __launch_bounds__(VW) void k_update_fused(int64_t nf, OpDev op, Scalars *__restrict__ sc, double *__restrict__ x,
                                                      double *__restrict__ r, const double *__restrict__ pa,
                                                      const double *__restrict__ pb, const double *__restrict__ q,
                                                      const double *__restrict__ energy, int nen,
                                                      double *__restrict__ part) {
-  __shared__ double red[VB / WAVE];
+  __shared__ double red[VW / WAVE];
   if (sc->done) return;
   const int it = sc->iter;
-  const double pq = block_total<VB>(energy, nen, red);
+  const double pq = block_total<VW>(energy, nen, red);
   const double rho = sc->rho[it & 1];
   if (!(pq > 0.0) || !isfinite(pq)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -430,8 +462,8 @@ __global__ __launch_bounds__(VB) void k_update_fused(int64_t nf, OpDev op, Scala
   }
   const double *p = (it & 1) ? pb : pa;
   double acc = 0.0;
-  const int64_t G = (int64_t)gridDim.x * VB;
-  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < nf; i += G) {
+  const int64_t G = (int64_t)gridDim.x * VW;
+  for (int64_t i = blockIdx.x * (int64_t)VW + threadIdx.x; i < nf; i += G) {
     const int2 vq = op.vq[i];
     double qi;
     if (vq.y == 0) {
@@ -453,7 +485,7 @@ __global__ __launch_bounds__(VB) void k_update_fused(int64_t nf, OpDev op, Scala
     r[i] = ri;
     acc += ri * ri;
   }
-  const double s = block_sum<VB>(acc, red);
+  const double s = block_sum<VW>(acc, red);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
@@ -505,8 +537,9 @@ __global__ __launch_bounds__(256) void k_check(Scalars *__restrict__ sc, const d
   (void)pcg_check(sc, part, n, start, red);
 }
 
-// Restriction R_p r into the packed local vectors (workgroups [0, ng)) and the
-// first stage of J^T r (the remaining workgroups, one task per wavefront).
+// Restriction R_p r into the packed local vectors (workgroups [0, ng), grid-
+// stride) and the first stage of J^T r (the remaining workgroups, one task per
+// wavefront at a time).
 // One restriction task (a wavefront): the 8 corner sums of at most JT_CHUNK
 // entries (i, c) of one cell, weight w_ic = n_ic/m_i times the trilinear
 // weights at the local coordinates of vertex i, applied to in[i]. Each lane takes
@@ -557,16 +590,24 @@ __global__ __launch_bounds__(256) void k_pre(int ng, int64_t n, const int *__res
   if (*done) return;
   if (sc && pcg_check(sc, chk, nchk, start, red)) return;
   if ((int)blockIdx.x < ng) {
-    const int64_t j = blockIdx.x * (int64_t)256 + threadIdx.x;
-    if (j < n) {
-      const int32_t i = idx[j];
-      rp[j] = (i >= 0) ? (T)in[i] : T(0);
+    // UV entries per thread and step, index and value loads issued together
+    const int64_t G = (int64_t)ng * 256;
+    for (int64_t j0 = blockIdx.x * (int64_t)256 + threadIdx.x; j0 < n; j0 += G * UV) {
+      int32_t ii[UV];
+#pragma unroll
+      for (int u = 0; u < UV; ++u) ii[u] = (j0 + u * G < n) ? idx[j0 + u * G] : -1;
+      double vv[UV];
+#pragma unroll
+      for (int u = 0; u < UV; ++u) vv[u] = (ii[u] >= 0) ? in[ii[u]] : 0.0;
+#pragma unroll
+      for (int u = 0; u < UV; ++u)
+        if (j0 + u * G < n) rp[j0 + u * G] = (ii[u] >= 0) ? (T)vv[u] : T(0);
     }
     return;
   }
-  const int task = (blockIdx.x - ng) * 4 + (threadIdx.x >> 6);
-  if (task >= ntask) return;
-  jt_task<T>(task, tstart, vid, w, xi, nent, in, tpart);
+  const int nw = ((int)gridDim.x - ng) * 4;
+  for (int task = (blockIdx.x - ng) * 4 + (threadIdx.x >> 6); task < ntask; task += nw)
+    jt_task<T>(task, tstart, vid, w, xi, nent, in, tpart);
 }
 
 // ---------------------------------------------------------------------------
@@ -856,7 +897,7 @@ __global__ __launch_bounds__(256) void k_combine(const Seg *__restrict__ segs, i
 // plus partial sums of r.out and r.out_old for the PCG beta.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(VB) void k_final(int64_t nf, const int *__restrict__ done, const double *__restrict__ add,
+__global__ __launch_bounds__(VW) void k_final(int64_t nf, const int *__restrict__ done, const double *__restrict__ add,
                                               const int32_t *__restrict__ cover_ptr, const int32_t *__restrict__ cover_pos,
                                               const double *__restrict__ zp, const int32_t *__restrict__ jv_ptr,
                                               const int32_t *__restrict__ jv_base, const T *__restrict__ jv_w,
@@ -864,11 +905,11 @@ __global__ __launch_bounds__(VB) void k_final(int64_t nf, const int *__restrict_
                                               const double *__restrict__ yfull, double *__restrict__ out,
                                               const double *__restrict__ rdot, double *__restrict__ part1,
                                               double *__restrict__ part2, Scalars *__restrict__ sc, int start) {
-  __shared__ double red[VB / WAVE];
+  __shared__ double red[VW / WAVE];
   if (*done) return;
   double d1 = 0.0, d2 = 0.0;
-  const int64_t G = (int64_t)gridDim.x * VB;
-  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < nf; i += G) {
+  const int64_t G = (int64_t)gridDim.x * VW;
+  for (int64_t i = blockIdx.x * (int64_t)VW + threadIdx.x; i < nf; i += G) {
     double acc = add ? add[i] : 0.0;
     if (cover_ptr) {
       // local solutions covering vertex i, loads issued eight at a time, summed in order
@@ -895,10 +936,10 @@ __global__ __launch_bounds__(VB) void k_final(int64_t nf, const int *__restrict_
         double yc[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) yc[q] = yfull[b0 + (q & 1) + ((q >> 1) & 1) * bx1 + ((q >> 2) & 1) * bxy1];
-        T s = T(0);
+        T sv = T(0);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) s += trilin<T>(q, x, y, z) * (T)yc[q];
-        cs += jv_w[k] * s;
+        for (int q = 0; q < 8; ++q) sv += trilin<T>(q, x, y, z) * (T)yc[q];
+        cs += jv_w[k] * sv;
       }
       acc += (double)cs;
     }
@@ -910,10 +951,10 @@ __global__ __launch_bounds__(VB) void k_final(int64_t nf, const int *__restrict_
     out[i] = acc;
   }
   if (rdot) {
-    const double s1 = block_sum<VB>(d1, red);
+    const double s1 = block_sum<VW>(d1, red);
     if (threadIdx.x == 0) part1[blockIdx.x] = s1;
     if (part2) {
-      const double s2 = block_sum<VB>(d2, red);
+      const double s2 = block_sum<VW>(d2, red);
       if (threadIdx.x == 0) part2[blockIdx.x] = s2;
     }
     // one completed iteration (not for the first application)
@@ -1128,6 +1169,14 @@ __global__ __launch_bounds__(256) void k_sweep_pivot(int k, const SweepSys *__re
   if (threadIdx.x == 0 && bad) status[blockIdx.x] = 1;
 }
 
+// 32 x 32 x 32 tile products on the matrix cores: v_mfma_f64_16x16x4f64 takes a
+// 16 x 4 block of A (lane l holds A[l%16][l/16]) and a 4 x 16 block of B (lane l
+// holds B[l/16][l%16]) and accumulates into a 16 x 16 block of which lane l holds
+// rows l/16, l/16 + 4, l/16 + 8 and l/16 + 12 of column l%16. Each of the 4 waves of a workgroup
+// owns one 16 x 16 quadrant of the output tile; the K = 32 sum takes 8 steps in
+// increasing k.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
 // grid: (system, I); P_I = M_Ik (transpose of tile (k, I) when I < k), G_I = P_I Dinv
 __global__ __launch_bounds__(256) void k_sweep_panel(int k, const SweepSys *__restrict__ sys, const double *__restrict__ M,
                                                      const double *__restrict__ Dinv, double *__restrict__ Pbuf,
@@ -1150,14 +1199,15 @@ __global__ __launch_bounds__(256) void k_sweep_panel(int k, const SweepSys *__re
   __syncthreads();
   double *po = Pbuf + (S.pan_off + I) * (TILE * TILE);
   double *go = Gbuf + (S.pan_off + I) * (TILE * TILE);
-  for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) {
-    const int i = t / TILE, j = t % TILE;
-    double s = 0.0;
-#pragma unroll 8
-    for (int m = 0; m < TILE; ++m) s += P[i][m] * Dl[m][j];
-    po[t] = P[i][j];
-    go[t] = s;
-  }
+  for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) po[t] = P[t / TILE][t % TILE];
+  const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+  const int r0 = (w >> 1) * 16, c0 = (w & 1) * 16, cl = l % 16, kq = l / 16;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int st = 0; st < TILE / 4; ++st)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(P[r0 + cl][4 * st + kq], Dl[4 * st + kq][c0 + cl], acc, 0, 0, 0);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) go[(r0 + kq + 4 * r) * TILE + c0 + cl] = acc[r];
 }
 
 // grid: (system, tile) over the lower tiles
@@ -1166,7 +1216,7 @@ __global__ __launch_bounds__(256) void k_sweep_update(int k, const SweepSys *__r
                                                       double *__restrict__ M, const double *__restrict__ Dinv,
                                                       const double *__restrict__ Pbuf, const double *__restrict__ Gbuf) {
   __shared__ double G[TILE][TILE + 1];
-  __shared__ double PT[TILE][TILE + 1];
+  __shared__ double Pj[TILE][TILE + 1];
   const int t0 = blockIdx.x;
   const int s = tsys[t0];
   const SweepSys S = sys[s];
@@ -1188,21 +1238,24 @@ __global__ __launch_bounds__(256) void k_sweep_update(int k, const SweepSys *__r
     for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) Mt[t] = g[(t % TILE) * TILE + t / TILE];
     return;
   }
+  // M_IJ -= G_I P_J^T on the matrix cores (the accumulator starts from M_IJ)
   const double *g = Gbuf + (S.pan_off + I) * (TILE * TILE);
   const double *p = Pbuf + (S.pan_off + J) * (TILE * TILE);
   for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) {
     const int i = t / TILE, j = t % TILE;
-    G[i][j] = g[t];
-    PT[j][i] = p[t];
+    G[i][j] = -g[t];
+    Pj[i][j] = p[t];
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) {
-    const int i = t / TILE, j = t % TILE;
-    double s2 = 0.0;
-#pragma unroll 8
-    for (int m = 0; m < TILE; ++m) s2 += G[i][m] * PT[m][j];
-    Mt[t] -= s2;
-  }
+  const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+  const int r0 = (w >> 1) * 16, c0 = (w & 1) * 16, cl = l % 16, kq = l / 16;
+  double *mo = Mt + (r0 + kq) * TILE + c0 + cl;
+  v4d acc = {mo[0], mo[4 * TILE], mo[8 * TILE], mo[12 * TILE]};
+#pragma unroll
+  for (int st = 0; st < TILE / 4; ++st)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(G[r0 + cl][4 * st + kq], Pj[c0 + cl][4 * st + kq], acc, 0, 0, 0);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) mo[4 * r * TILE] = acc[r];
 }
 
 // -M -> output tiles (symmetrised diagonal tiles), converted to T.

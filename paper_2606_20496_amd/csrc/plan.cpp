@@ -270,7 +270,7 @@ int build_plan(const PlanInput &in, Plan &P) {
         for (int v = 0; v < 8; ++v) {
           int32_t u = E2V(e, v);
           if (u >= nf) continue;
-          P.lconn[v * NE + e] = (uint16_t)slot_of[u];
+          P.lconn[e * 8 + v] = (uint16_t)slot_of[u];
           lists[slot_of[u]].push_back((uint16_t)((e - e0) * 8 + v));
         }
       for (size_t s = 0; s < verts.size(); ++s) {

@@ -64,7 +64,7 @@ struct Plan {
   std::vector<int32_t> slot_dst;       // >=0: owned, write q[dst]; <0: partial -(k+1)
   std::vector<int32_t> slot_inc_ptr;   // [n_slots+1] into slot_inc
   std::vector<uint16_t> slot_inc;      // e_local*8 + a
-  std::vector<uint16_t> lconn;         // SoA [8][E]: slot of local vertex a (0xFFFF = Dirichlet)
+  std::vector<uint16_t> lconn;         // [E][8]: slot of local vertex a (0xFFFF = Dirichlet), 16 B per element
   int64_t n_partials = 0;
   std::vector<int32_t> sh_vid;         // shared vertices
   std::vector<int32_t> sh_ptr;         // [n_shared+1] partial ids of shared vertex j: [sh_ptr[j], sh_ptr[j+1])
