@@ -204,7 +204,9 @@ struct coarse_ctx {
 
   void gemv_combine(const Seg *segs, int nitems, int nrows, const int *done) {
     if (nitems <= 0) return;
-    const unsigned g = (unsigned)std::min<int64_t>(nblk(nitems, 4), 256 * 16);
+    // one wavefront per work item (the kernel also loops over a smaller grid, but
+    // one item per wavefront measured fastest on MI355X at every size tried)
+    const unsigned g = nblk(nitems, 4);
     pbeg(3);
     if (precision == COARSE_FP64)
       hipLaunchKernelGGL(k_gemv_f64, dim3(g), dim3(256), 0, stream, segs, 1, nitems, done);
@@ -472,7 +474,7 @@ void setup_precision(coarse_ctx *c, const Plan &P) {
   Arena tmp;
   double *xyz = tmp.upload(P.xyz, s);
   int32_t *e2v = tmp.upload(P.e2v, s);
-  double *Ae = A.alloc<double>(36 * NE);
+  double *Ae = A.alloc<double>(36 * (int64_t)nblk(NE, OP_BLOCK) * OP_BLOCK);   // blocked, see ae_at
   int *bad = tmp.alloc<int>(1);
   HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), s));
   hipLaunchKernelGGL(k_elem_matrices, dim3(nblk(NE, 256)), dim3(256), 0, s, NE, NV, xyz, e2v, Ae, bad);
@@ -833,7 +835,7 @@ struct coarse_batch {
     fork_sides(ev_fork);
     for (auto &e : live) e.c->front();
     join_sides();
-    const unsigned g = (unsigned)std::min<int64_t>(nblk(n_items, 4), 256 * 16);
+    const unsigned g = nblk(n_items, 4);
     if (precision == COARSE_FP64) {
       hipLaunchKernelGGL(k_gemv_f64, dim3(g), dim3(256), 0, main, (const Seg *)d_seg, n, n_items, (const int *)nullptr);
       hipLaunchKernelGGL(k_combine<double>, dim3(nblk((int64_t)n_rows * TILE, 256)), dim3(256), 0, main,

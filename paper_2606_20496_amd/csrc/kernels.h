@@ -5,7 +5,16 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "plan.h"
+
 namespace coarse {
+
+// Element matrices (36 unique FP64 entries of each symmetric 8x8 A^e) are stored
+// per operator block of OP_BLOCK elements: [block][36][OP_BLOCK], so the block
+// that applies them streams one contiguous 72 KB region.
+__host__ __device__ inline int64_t ae_at(int k, int64_t e) {
+  return ((e / OP_BLOCK) * 36 + k) * OP_BLOCK + (e % OP_BLOCK);
+}
 
 // Solver scalars living in device memory (one per context).
 struct Scalars {

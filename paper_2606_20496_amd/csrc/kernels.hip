@@ -10,7 +10,7 @@ namespace coarse {
 // ---------------------------------------------------------------------------
 // Setup: Q1 element matrices (Sec. 3, a^e_ij = int grad l_i . grad l_j) with the
 // 2x2x2 Gauss rule on the trilinear map of [-1,1]^3. One thread per element;
-// the 36 distinct entries are stored SoA [36][E].
+// the 36 distinct entries are stored per operator block (ae_at).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_elem_matrices(int64_t E, int64_t NV, const double *__restrict__ xyz,
                                                        const int32_t *__restrict__ e2v, double *__restrict__ Ae,
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void k_elem_matrices(int64_t E, int64_t NV, co
   }
   if (!(detmin > 0.0)) atomicAdd(bad, 1);
 #pragma unroll
-  for (int k = 0; k < 36; ++k) Ae[k * E + e] = A[k];
+  for (int k = 0; k < 36; ++k) Ae[ae_at(k, e)] = A[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256) void k_elem_matrices(int64_t E, int64_t NV, co
 __device__ __forceinline__ void elem_load(const OpDev &op, int64_t e, double m[36], uint4 &c) {
   c = *(const uint4 *)(op.lconn + e * 8);
 #pragma unroll
-  for (int k = 0; k < 36; ++k) m[k] = op.Ae[k * op.E + e];
+  for (int k = 0; k < 36; ++k) m[k] = op.Ae[ae_at(k, e)];
 }
 
 __device__ __forceinline__ unsigned slot_at(const uint4 &c, int a) {
@@ -1009,7 +1009,7 @@ __global__ __launch_bounds__(256) void k_assemble_local(const AsmSys *__restrict
             hi = mid - 1;
         }
         if (pos < 0 || pos / TILE > a / TILE) continue;   // lower tiles only (diagonal tiles full)
-        *tile_elem(M, S.tile_off, a, pos) += Ae[sym8(la, lb) * E + e];
+        *tile_elem(M, S.tile_off, a, pos) += Ae[ae_at(sym8(la, lb), e)];
       }
     }
   }
@@ -1062,7 +1062,7 @@ __global__ __launch_bounds__(64) void k_cell_mats(BoxDev box, const int32_t *__r
     {  // T1 = A^e J^e : thread (a, l)
       double s = 0.0;
 #pragma unroll
-      for (int b = 0; b < 8; ++b) s += Ae[sym8(ta, b) * E + e] * Je[b][tk];
+      for (int b = 0; b < 8; ++b) s += Ae[ae_at(sym8(ta, b), e)] * Je[b][tk];
       T1[ta][tk] = s;
     }
     __syncthreads();
