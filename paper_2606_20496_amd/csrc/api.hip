@@ -97,6 +97,7 @@ struct coarse_ctx {
          *t1 = nullptr, *t2 = nullptr, *part1 = nullptr, *part2 = nullptr, *energy = nullptr;
   double *prr = nullptr;     // partial sums of ||r||^2 (and of ||b||^2 at the start)
   int last_iters = 0;        // iterations of the previous solve (first batch size)
+  int gemv_tiles[COARSE_GEMV_BUCKETS] = {};   // work-item table this context was built with
   Scalars *sc = nullptr;
   Scalars *h_sc = nullptr;   // pinned host copy
   int *zero_flag = nullptr;  // a device int that is always 0
@@ -466,7 +467,7 @@ int64_t invert_systems(coarse_ctx *c, const std::vector<System> &sys, const std:
 }
 
 template <typename T>
-void setup_precision(coarse_ctx *c, const Plan &P) {
+void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
   hipStream_t s = c->stream;
   Arena &A = c->arena;
   const int64_t NE = P.n_elem, NV = P.n_vert, nf = P.n_free;
@@ -495,6 +496,7 @@ void setup_precision(coarse_ctx *c, const Plan &P) {
   op.slot_dst = A.upload(P.slot_dst, s);
   op.slot_inc_ptr = A.upload(P.slot_inc_ptr, s);
   op.slot_inc = A.upload(P.slot_inc, s);
+  op.slot_inc8 = A.upload(P.slot_inc8, s);
   op.partials = A.alloc<double>(std::max<int64_t>(1, P.n_partials));
   op.sh_vid = A.upload(P.sh_vid, s);
   op.sh_ptr = A.upload(P.sh_ptr, s);
@@ -539,7 +541,10 @@ void setup_precision(coarse_ctx *c, const Plan &P) {
   T *tiles = A.alloc<T>((size_t)P.n_tiles * TILE * TILE);
   c->tiles = tiles;
   c->colpart = A.alloc<T>((size_t)P.n_tiles * TILE);
-  c->rowpart = A.alloc<T>((size_t)P.items.size() * TILE);
+  GemvTable G;
+  build_gemv_items(P, gemv_tiles, coarse_gemv_bucket_max, COARSE_GEMV_BUCKETS, G);
+  for (int b = 0; b < COARSE_GEMV_BUCKETS; ++b) c->gemv_tiles[b] = gemv_tiles[b] >= 1 ? gemv_tiles[b] : GEMV_SEG;
+  c->rowpart = A.alloc<T>((size_t)G.items.size() * TILE);
   c->cover_ptr = A.upload(P.cover_ptr, s);
   c->cover_pos = A.upload(P.cover_pos, s);
 
@@ -604,13 +609,13 @@ void setup_precision(coarse_ctx *c, const Plan &P) {
   }
   // item slots: index within the system's item list
   std::vector<int64_t> sys_item0(P.sys.size(), -1);
-  for (size_t i = 0; i < P.items.size(); ++i)
-    if (sys_item0[P.items[i].sys] < 0) sys_item0[P.items[i].sys] = (int64_t)i;
+  for (size_t i = 0; i < G.items.size(); ++i)
+    if (sys_item0[G.items[i].sys] < 0) sys_item0[G.items[i].sys] = (int64_t)i;
   for (size_t k = 0; k < P.sys.size(); ++k) sd[k].rowpart = (T *)c->rowpart + (size_t)sys_item0[k] * TILE;
-  std::vector<GItem> gi(P.items.size());
+  std::vector<GItem> gi(G.items.size());
   int32_t il = 0;
-  for (size_t i = 0; i < P.items.size(); ++i) {
-    const GemvItem &it = P.items[i];
+  for (size_t i = 0; i < G.items.size(); ++i) {
+    const GemvItem &it = G.items[i];
     gi[i].sys = it.sys;
     gi[i].I = (int16_t)it.I;
     gi[i].j0 = (int16_t)it.j0;
@@ -623,11 +628,11 @@ void setup_precision(coarse_ctx *c, const Plan &P) {
   std::vector<GRow> gr(P.n_rows);
   int32_t rl = 0;
   for (int64_t k = 0; k < P.n_rows; ++k) {
-    gr[k].sys = P.row_sys[k];
-    gr[k].I = P.row_I[k];
-    gr[k].slot0 = (int32_t)(P.row_item0[k] - sys_item0[P.row_sys[k]]);
-    gr[k].nslot = P.row_nitem[k];
-    if (P.row_sys[k] < P.n_local_sys) rl = (int32_t)k + 1;
+    gr[k].sys = G.row_sys[k];
+    gr[k].I = G.row_I[k];
+    gr[k].slot0 = (int32_t)(G.row_item0[k] - sys_item0[G.row_sys[k]]);
+    gr[k].nslot = G.row_nitem[k];
+    if (G.row_sys[k] < P.n_local_sys) rl = (int32_t)k + 1;
   }
   c->items = A.upload(gi, s);
   c->rows = A.upload(gr, s);
@@ -681,6 +686,7 @@ void setup_precision(coarse_ctx *c, const Plan &P) {
   in.a_bytes = NE * (36 * 8 + 8 * 2) + (int64_t)P.slot_vid.size() * 12 + (int64_t)P.slot_inc.size() * 2 + nf * 16;
   for (int d = 0; d < 3; ++d) in.boxes[d] = P.b[d];
   in.precision = c->precision;
+  for (int b = 0; b < COARSE_GEMV_BUCKETS; ++b) in.gemv_tiles[b] = c->gemv_tiles[b];
 }
 
 coarse_ctx *as_ctx(const coarse_ctx *c) { return const_cast<coarse_ctx *>(c); }
@@ -972,6 +978,12 @@ int coarse_plan_create(const coarse_mesh *mesh, const coarse_bc *bc, const coars
   return COARSE_OK;
 }
 
+int coarse_plan_set_gemv_tiles(coarse_plan *plan, const int *tiles) {
+  if (!plan || !tiles) return COARSE_EINVAL;
+  for (int b = 0; b < COARSE_GEMV_BUCKETS; ++b) plan->o.gemv_tiles[b] = tiles[b];
+  return COARSE_OK;
+}
+
 int coarse_plan_destroy(coarse_plan *plan) {
   delete plan;
   return COARSE_OK;
@@ -1007,9 +1019,9 @@ int coarse_setup_from_plan(const coarse_plan *plan, void *stream, coarse_ctx **o
   try {
     HIPCHK(hipHostMalloc((void **)&c->h_sc, sizeof(Scalars), hipHostMallocDefault));
     if (o.precision == COARSE_FP64)
-      setup_precision<double>(c.get(), P);
+      setup_precision<double>(c.get(), P, o.gemv_tiles);
     else
-      setup_precision<float>(c.get(), P);
+      setup_precision<float>(c.get(), P, o.gemv_tiles);
   } catch (const Fail &f) {
     g_setup_error = f.what();
     (void)hipStreamSynchronize(c->stream);

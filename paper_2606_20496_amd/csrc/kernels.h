@@ -66,6 +66,7 @@ struct OpDev {
   const uint16_t *lconn;   // [E][8] block-local slots, one 16-byte load per element
   const int32_t *blk_slot_ptr, *slot_vid, *slot_dst, *slot_inc_ptr;
   const uint16_t *slot_inc;
+  const uint16_t *slot_inc8;  // per slot: the first 8 incidences as one 16-byte record
   double *partials;
   const int32_t *sh_vid, *sh_ptr;
   const uint8_t *slot_pw;     // 1: this slot's block writes the vertex's search direction

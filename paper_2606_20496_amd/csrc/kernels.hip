@@ -135,21 +135,24 @@ __device__ __forceinline__ double elem_apply(const double m[36], const uint4 &c,
 }
 
 // Per slot of the block, the element outputs of its incidences summed in list
-// order (the first 8 incidence loads issued together), written to q for a vertex
-// the block owns or to its partial otherwise.
+// order (one 16-byte record holds up to 8 of them), written to q for a vertex the
+// block owns or to its partial otherwise.
 __device__ __forceinline__ void block_scatter(const OpDev &op, int s0, int ns, const double *out,
                                               double *__restrict__ q) {
   for (int s = threadIdx.x; s < ns; s += OP_BLOCK) {
-    const int k0 = op.slot_inc_ptr[s0 + s], k1 = op.slot_inc_ptr[s0 + s + 1];
+    const uint4 rec = *(const uint4 *)(op.slot_inc8 + (int64_t)(s0 + s) * 8);
     const int dst = op.slot_dst[s0 + s];
-    unsigned li[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) li[k] = (k0 + k < k1) ? op.slot_inc[k0 + k] : 0u;
     double acc = 0.0;
+    if (slot_at(rec, 0) == 0xFFFEu) {
+      // more than 8 incidences: the CSR list
+      for (int k = op.slot_inc_ptr[s0 + s]; k < op.slot_inc_ptr[s0 + s + 1]; ++k) acc += out[op.slot_inc[k]];
+    } else {
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (k0 + k < k1) acc += out[li[k]];
-    for (int k = k0 + 8; k < k1; ++k) acc += out[op.slot_inc[k]];
+      for (int k = 0; k < 8; ++k) {
+        const unsigned li = slot_at(rec, k);
+        if (li != 0xFFFFu) acc += out[li];
+      }
+    }
     if (dst >= 0)
       q[dst] = acc;
     else

@@ -279,6 +279,11 @@ int build_plan(const PlanInput &in, Plan &P) {
         if (P.slot_inc_ptr.empty()) P.slot_inc_ptr.push_back(0);
         for (auto x : lists[s]) P.slot_inc.push_back(x);
         P.slot_inc_ptr.push_back((int32_t)P.slot_inc.size());
+        // the same list as one 16-byte record (0xFFFF ends it; 0xFFFE first: the
+        // list is longer than 8 and only the CSR form holds it)
+        for (int k = 0; k < 8; ++k)
+          P.slot_inc8.push_back(lists[s].size() > 8 ? (k == 0 ? 0xFFFE : 0xFFFF)
+                                                    : (k < (int)lists[s].size() ? lists[s][k] : 0xFFFF));
         if (cnt[u] == P.mult[u]) {
           P.slot_dst.push_back(u);
         } else {
@@ -633,26 +638,34 @@ int build_plan(const PlanInput &in, Plan &P) {
       const auto &R = P.R[P.sub_of_sys[s]];
       for (size_t a = 0; a < R.size(); ++a) P.cover_pos[fill[R[a]]++] = (int32_t)(P.sys[s].vec_off + a);
     }
-    for (int64_t s = 0; s < (int64_t)P.sys.size(); ++s) {
-      const System &S = P.sys[s];
-      for (int64_t I = 0; I < S.nb; ++I) {
-        P.row_item0.push_back((int32_t)P.items.size());
-        for (int64_t j0 = 0; j0 <= I; j0 += GEMV_SEG) {
-          GemvItem it;
-          it.sys = (int32_t)s;
-          it.I = (int32_t)I;
-          it.j0 = (int32_t)j0;
-          it.j1 = (int32_t)std::min<int64_t>(I + 1, j0 + GEMV_SEG);
-          P.items.push_back(it);
-        }
-        P.row_nitem.push_back((int32_t)(P.items.size() - P.row_item0.back()));
-        P.row_sys.push_back((int32_t)s);
-        P.row_I.push_back((int32_t)I);
-      }
-    }
   }
   tr.mark("systems and items");
   return 0;
+}
+
+void build_gemv_items(const Plan &P, const int *tiles_of_bucket, const int *bucket_max, int nbucket,
+                      GemvTable &out) {
+  out = GemvTable();
+  for (int64_t s = 0; s < (int64_t)P.sys.size(); ++s) {
+    const System &S = P.sys[s];
+    int b = 0;
+    while (b + 1 < nbucket && S.nb > bucket_max[b]) ++b;
+    const int64_t seg = (tiles_of_bucket && tiles_of_bucket[b] >= 1) ? tiles_of_bucket[b] : GEMV_SEG;
+    for (int64_t I = 0; I < S.nb; ++I) {
+      out.row_item0.push_back((int32_t)out.items.size());
+      for (int64_t j0 = 0; j0 <= I; j0 += seg) {
+        GemvItem it;
+        it.sys = (int32_t)s;
+        it.I = (int32_t)I;
+        it.j0 = (int32_t)j0;
+        it.j1 = (int32_t)std::min<int64_t>(I + 1, j0 + seg);
+        out.items.push_back(it);
+      }
+      out.row_nitem.push_back((int32_t)(out.items.size() - out.row_item0.back()));
+      out.row_sys.push_back((int32_t)s);
+      out.row_I.push_back((int32_t)I);
+    }
+  }
 }
 
 }  // namespace coarse

@@ -64,6 +64,7 @@ struct Plan {
   std::vector<int32_t> slot_dst;       // >=0: owned, write q[dst]; <0: partial -(k+1)
   std::vector<int32_t> slot_inc_ptr;   // [n_slots+1] into slot_inc
   std::vector<uint16_t> slot_inc;      // e_local*8 + a
+  std::vector<uint16_t> slot_inc8;      // [slots][8]: the incidence list as one record (see plan.cpp)
   std::vector<uint16_t> lconn;         // [E][8]: slot of local vertex a (0xFFFF = Dirichlet), 16 B per element
   int64_t n_partials = 0;
   std::vector<int32_t> sh_vid;         // shared vertices
@@ -86,10 +87,7 @@ struct Plan {
   std::vector<int32_t> sub_idx;          // [vec_len] internal vertex or -1 (padding / reduced)
   std::vector<int32_t> cover_ptr;        // [n_free+1]
   std::vector<int32_t> cover_pos;        // positions in the packed vectors
-  std::vector<GemvItem> items;
-  // row table: per (system, tile row): first item, item count, system id
-  std::vector<int32_t> row_item0, row_nitem, row_sys, row_I;
-  int64_t n_rows = 0;
+  int64_t n_rows = 0;                    // tile rows over all systems
   // local-system element lists for the dense assembly are implied by R (all
   // incident elements of a vertex in R_p lie in the overlapping subdomain)
 
@@ -127,5 +125,15 @@ struct Plan {
 
 // Build the plan; returns 0 or a negative coarse_status (message in plan.err).
 int build_plan(const PlanInput &in, Plan &plan);
+
+// GEMV work items and the row table for the systems of a plan: each tile row I of
+// a system with nb tile rows is cut into items of tiles_of_bucket[bucket(nb)]
+// tiles (bucket b: nb <= bucket_max[b]; a value < 1 means GEMV_SEG).
+struct GemvTable {
+  std::vector<GemvItem> items;
+  std::vector<int32_t> row_item0, row_nitem, row_sys, row_I;
+};
+void build_gemv_items(const Plan &P, const int *tiles_of_bucket, const int *bucket_max, int nbucket,
+                      GemvTable &out);
 
 }  // namespace coarse
