@@ -10,9 +10,11 @@ different seeded RHS per step, up to 32 distinct ones). Inputs are resident on
 the GPU before timing; the per-mesh setup (factorisations) is done
 once before the timed region and reported separately.
 
-Prints one JSON line (rank 0). The FP64 solve rate is `value`; the mixed
-precision form (FP32 local/reduced inverses and interpolation, FP64 residual,
-dots and outer iteration) is reported beside it.
+Prints one JSON line (rank 0). The FP64 solve rate is `value`. Two mixed forms
+are reported beside it: FP32 local/reduced inverses and interpolation, and the
+same with the inverses stored in FP16; both keep the operator, residual, dot
+products and outer iteration in FP64. Also reported: the 64-mesh batched
+workload, and the per-kernel figures on the 128^3 quarter-annulus.
 """
 from __future__ import annotations
 
@@ -101,13 +103,25 @@ def run_form(torch, coarse, mesh, rhs, precision, steps, warmup, tol):
     }
 
 
+def _form_summary(f, dtype):
+    if f is None:
+        return None
+    avg_ms = f["gemv"][0] / max(f["gemv_work_launches"], 1)
+    return {"value": round(f["solves_per_s"], 3), "unit": "solves/s", "dtype": dtype,
+            "ms_per_step": round(f["ms_per_solve"], 4), "p50_ms": round(f["p50_ms"], 4),
+            "p99_ms": round(f["p99_ms"], 4), "iters": f["iters"], "iters_range": [f["iters_min"], f["iters_max"]],
+            "relres_true_max": f["relres_true_max"], "setup_s": round(f["setup_s"], 3),
+            "gemv_avg_launch_us": round(avg_ms * 1e3, 2), "gemv_alg_bytes": f["info"]["inv_alg_bytes"],
+            "gemv_achieved_GBs": round(f["info"]["inv_alg_bytes"] / (avg_ms / 1e3) / 1e9, 1)}
+
+
 def run_batch_workload(torch, coarse, mg, tol, reps=3):
     """64 independent meshes (n log-uniform in [6, 48], blocks of 4/6/8 elements)
     solved together in lock step (one GEMV launch for all their local and reduced
     solves per iteration, HIP-graph replay), versus one at a time."""
     meshes = mg.batch_meshes(count=64)
     out = {"meshes": len(meshes), "elements": int(sum(m.n_elem for m in meshes))}
-    for prec in ("mixed", "fp64"):
+    for prec in ("mixed16", "mixed", "fp64"):
         t0 = time.perf_counter()
         solvers = [coarse.CoarseSolver.from_mesh(m, precision=prec) for m in meshes]
         torch.cuda.synchronize()
@@ -173,7 +187,7 @@ def run_kernels_large(torch, coarse, mg, tol):
                        "16^3 boxes", "n_elem": mesh.n_elem}
     b = torch.tensor(mesh.b, device="cuda")
     u = torch.empty_like(b)
-    for prec in ("fp64", "mixed"):
+    for prec in ("fp64", "mixed", "mixed16"):
         t0 = time.perf_counter()
         S = coarse.CoarseSolver.from_mesh(mesh, precision=prec)
         torch.cuda.synchronize()
@@ -210,6 +224,30 @@ def run_kernels_large(torch, coarse, mg, tol):
     return out
 
 
+def run_ablations(torch, coarse, mesh, b, tol, max_it=400):
+    """Iterations to the tolerance for the preconditioner's parts and variants on
+    the bench mesh (FP64): the additive two-level method, its local part alone,
+    its reduced part alone, the symmetrised coarse-local-coarse hybrid, and two
+    layers of overlap (the paper's study of the parts, Sec. 5)."""
+    out = {}
+    for name, kw in (("additive", {}), ("local_only", {"mode": "local_only"}),
+                     ("reduced_only", {"mode": "reduced_only"}), ("hybrid_sym", {"mode": "hybrid_sym"}),
+                     ("additive_overlap2", {"overlap": 2})):
+        S = coarse.CoarseSolver.from_mesh(mesh, max_it=max_it, **kw)
+        u = torch.empty_like(b)
+        t0 = time.perf_counter()
+        try:
+            _, st = S.solve(b, tol, out=u)
+            res = {"iters": st["iters"], "converged": st["code"] == 0, "relres": st["relres"]}
+        except coarse.CoarseError as err:
+            # the reduced part alone is singular on the full space: PCG breaks down
+            res = {"iters": None, "converged": False, "error": str(err)}
+        torch.cuda.synchronize()
+        out[name] = {**res, "ms": round(1e3 * (time.perf_counter() - t0), 3), "device_bytes": S.device_bytes}
+        S.close()
+    return out
+
+
 def cpu_baseline(mesh, tol):
     """The FP64 oracle, as it stands, on the host cores: one full solve of the
     same workload (setup timed separately and excluded)."""
@@ -238,6 +276,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-mesh batched workload")
     ap.add_argument("--no-large", action="store_true", help="skip the 128^3 annulus kernel measurements")
+    ap.add_argument("--no-ablations", action="store_true", help="skip the preconditioner-part study")
     ap.add_argument("--serving", action="store_true", help="also run a short serving-loop workload")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 1 GiB device copy (known bytes) to scale HBM counters")
@@ -268,10 +307,12 @@ def main():
     _log("fp64 form")
     fp64 = run_form(torch, coarse, mesh, rhs, "fp64", args.steps, args.warmup, args.tol)
     _log(f"fp64: {fp64['solves_per_s']:.2f} solves/s")
-    mixed = None
+    mixed = mixed16 = None
     if not args.no_mixed:
         mixed = run_form(torch, coarse, mesh, rhs, "mixed", args.steps, args.warmup, args.tol)
         _log(f"mixed: {mixed['solves_per_s']:.2f} solves/s")
+        mixed16 = run_form(torch, coarse, mesh, rhs, "mixed16", args.steps, args.warmup, args.tol)
+        _log(f"mixed16: {mixed16['solves_per_s']:.2f} solves/s")
 
     # roofline of the dominant kernel: the batched dense solve (tiled symmetric GEMV
     # over the stored local and reduced inverses), HBM-bound
@@ -292,6 +333,12 @@ def main():
         _log("batch workload")
         batch = run_batch_workload(torch, coarse, mg, args.tol)
         _log(f"batch: {batch}")
+    ablations = None
+    if not args.no_ablations:
+        _log("ablations")
+        ablations = run_ablations(torch, coarse, mesh, rhs[0], args.tol)
+        _log(f"ablations: { {k: v['iters'] for k, v in ablations.items()} }")
+
     large = None
     if not args.no_large:
         _log("annulus128 kernels")
@@ -334,16 +381,9 @@ def main():
         "iters_range": [fp64["iters_min"], fp64["iters_max"]],
         "relres_true_max": fp64["relres_true_max"],
         "setup_s": round(fp64["setup_s"], 3),
-        "mixed": None if mixed is None else {
-            "value": round(mixed["solves_per_s"], 3), "unit": "solves/s", "dtype": "f32 local/reduced, f64 outer",
-            "ms_per_step": round(mixed["ms_per_solve"], 4), "p50_ms": round(mixed["p50_ms"], 4),
-            "p99_ms": round(mixed["p99_ms"], 4), "iters": mixed["iters"],
-            "iters_range": [mixed["iters_min"], mixed["iters_max"]], "relres_true_max": mixed["relres_true_max"],
-            "setup_s": round(mixed["setup_s"], 3),
-            "gemv_avg_launch_us": round(mixed["gemv"][0] / max(mixed["gemv_work_launches"], 1) * 1e3, 2),
-            "gemv_alg_bytes": mixed["info"]["inv_alg_bytes"],
-            "gemv_achieved_GBs": round(mixed["info"]["inv_alg_bytes"] /
-                                       (mixed["gemv"][0] / max(mixed["gemv_work_launches"], 1) / 1e3) / 1e9, 1)},
+        "mixed": _form_summary(mixed, "f32 local/reduced inverses, f32 J, f64 operator/vectors/dots"),
+        "mixed16": _form_summary(mixed16, "f16 storage of the local/reduced inverses (power-of-two scale per "
+                                          "system), f32 arithmetic, f32 J, f64 operator/vectors/dots"),
         "phases_fp64": phases,
         "roofline": roof,
         "cpu_baseline": cpu,
@@ -352,6 +392,8 @@ def main():
         line["batch_workload"] = batch
     if large is not None:
         line["large_workload"] = large
+    if ablations is not None:
+        line["ablations"] = ablations
     if serving is not None:
         line["serving_workload"] = serving
     print(json.dumps(line), flush=True)

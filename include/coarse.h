@@ -52,9 +52,14 @@ enum coarse_status {
 
 enum coarse_precision {
   COARSE_FP64 = 0,   /* everything in float64                                      */
-  COARSE_MIXED = 1   /* local inverses, J/J^T and the reduced solve in float32;
+  COARSE_MIXED = 1,  /* local inverses, J/J^T and the reduced solve in float32;
                         A, the PCG vectors and dot products stay float64 (the
                         single-precision local/reduced solves of Sec. 6)          */
+  COARSE_MIXED_F16 = 2 /* as COARSE_MIXED, with the local and reduced inverses
+                        stored in float16 (each system's inverse divided by a
+                        power-of-two scale so no entry exceeds 2^14) and applied
+                        with float32 arithmetic: half the bytes of the dominant
+                        kernel, a less exact preconditioner                       */
 };
 
 enum coarse_mode {
@@ -97,6 +102,10 @@ typedef struct {
   const uint8_t *dirichlet;   /* host [n_vert] */
 } coarse_bc;
 
+/* Size buckets of the work-item table (upper bounds on nb; the last is open). */
+#define COARSE_GEMV_BUCKETS 8
+static const int coarse_gemv_bucket_max[COARSE_GEMV_BUCKETS] = {2, 4, 8, 12, 16, 24, 48, 1 << 30};
+
 typedef struct {
   int overlap;      /* element layers added to each subdomain (Sec. 3), >= 1        */
   int boxes[3];     /* b_x, b_y, b_z boxes of the reduced grid (Sec. 4); a zero
@@ -109,8 +118,15 @@ typedef struct {
                        result does not depend on it (finished iterations are
                        skipped on the device)                                      */
   int flexible;     /* 1: Polak-Ribiere beta (r, z_new - z_old)/(r,z)_old;
-                       0: Fletcher-Reeves. Default 1 for COARSE_MIXED, else 0     */
+                       0: Fletcher-Reeves. Default 1 for the mixed forms, else 0  */
   void *stream;     /* hipStream_t; NULL = the null stream                         */
+  int gemv_tiles[COARSE_GEMV_BUCKETS];
+                    /* tiles per work item of the batched dense solve, per size
+                       bucket of a system's tile count nb = ceil(n/32): bucket b
+                       holds nb <= coarse_gemv_bucket_max[b]. 0 = 4. Changes only
+                       the order of rounding inside a row sum and the speed; a
+                       context keeps its choice for life (results stay bitwise
+                       reproducible, alone or batched)                             */
 } coarse_opts;
 
 typedef struct {
@@ -140,6 +156,7 @@ typedef struct {
   int64_t device_bytes;  /* all device memory held by the context                   */
   int32_t boxes[3];
   int32_t precision;
+  int32_t gemv_tiles[COARSE_GEMV_BUCKETS];   /* work-item table the context uses     */
 } coarse_info_t;
 
 /* Fill *o with the defaults: overlap 1, boxes auto, FP64, additive, centroid J,
@@ -170,6 +187,9 @@ int coarse_setup(const coarse_mesh *mesh, const coarse_bc *bc, const coarse_opts
  *   coarse_plan_destroy: frees the plan (host memory only); NULL is accepted.
  * coarse_setup(mesh, bc, opts, out) is these three calls with opts.stream. */
 typedef struct coarse_plan coarse_plan;
+/* Replace the work-item table (opts.gemv_tiles) a plan hands to later device
+ * setups; for tuning the batched dense solve without rebuilding the plan. */
+int coarse_plan_set_gemv_tiles(coarse_plan *plan, const int *tiles);
 int coarse_plan_create(const coarse_mesh *mesh, const coarse_bc *bc, const coarse_opts *opts,
                        coarse_plan **out);
 int coarse_setup_from_plan(const coarse_plan *plan, void *stream, coarse_ctx **out);

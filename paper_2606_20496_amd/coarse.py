@@ -8,6 +8,7 @@ calls that compute raise.
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 
 import numpy as np
@@ -15,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcoarse.so")
 
-PRECISION = {"fp64": 0, "mixed": 1}
+PRECISION = {"fp64": 0, "mixed": 1, "mixed16": 2}
 MODE = {"additive": 0, "hybrid_sym": 1, "local_only": 2, "reduced_only": 3}
 INTERP = {"centroid": 0, "standard": 1}
 STATUS = {0: "ok", 1: "notconv", -1: "einval", -2: "enomem", -3: "emesh", -4: "esingular",
@@ -27,7 +28,7 @@ EXPORTS = ("coarse_default_opts", "coarse_setup", "coarse_apply_precond", "coars
            "coarse_get_info", "coarse_set_stream", "coarse_plan_info", "coarse_strerror",
            "coarse_last_error", "coarse_profile", "coarse_batch_create", "coarse_batch_submit",
            "coarse_batch_step", "coarse_batch_live", "coarse_batch_destroy", "coarse_plan_create",
-           "coarse_setup_from_plan", "coarse_plan_destroy")
+           "coarse_setup_from_plan", "coarse_plan_destroy", "coarse_plan_set_gemv_tiles")
 
 PHASES = ("A+p", "R_p+J^T", "J^T corners", "A_p^-1/A_r^-1 gemv", "combine", "sum+J", "x,r update")
 
@@ -48,10 +49,32 @@ class _BC(ctypes.Structure):
     _fields_ = [("dirichlet", ctypes.POINTER(ctypes.c_uint8))]
 
 
+# Size buckets of the GEMV work-item table (upper bounds on a system's tile
+# count nb = ceil(n/32), the last open), as in coarse.h.
+GEMV_BUCKETS = 8
+GEMV_BUCKET_MAX = (2, 4, 8, 12, 16, 24, 48, 1 << 30)
+TUNING_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "gemv_tuning.json")
+
+
+def gemv_table(precision="fp64"):
+    """Tiles per GEMV work item per size bucket for a precision: the table written
+    by the tuner (``python -m paper_2606_20496_amd.tune``) if one is present, else
+    4 everywhere."""
+    try:
+        with open(TUNING_PATH) as f:
+            t = json.load(f)[precision]["tiles_per_item"]
+        if len(t) == GEMV_BUCKETS and all(int(x) >= 1 for x in t):
+            return [int(x) for x in t]
+    except (OSError, ValueError, KeyError, TypeError):
+        pass
+    return [4] * GEMV_BUCKETS
+
+
 class _Opts(ctypes.Structure):
     _fields_ = [("overlap", ctypes.c_int), ("boxes", ctypes.c_int * 3), ("precision", ctypes.c_int),
                 ("mode", ctypes.c_int), ("interp", ctypes.c_int), ("max_it", ctypes.c_int),
-                ("check_every", ctypes.c_int), ("flexible", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("check_every", ctypes.c_int), ("flexible", ctypes.c_int), ("stream", ctypes.c_void_p),
+                ("gemv_tiles", ctypes.c_int * GEMV_BUCKETS)]
 
 
 class _Stats(ctypes.Structure):
@@ -65,7 +88,8 @@ class _Info(ctypes.Structure):
                 ("local_bytes", ctypes.c_int64), ("reduced_bytes", ctypes.c_int64),
                 ("a_bytes", ctypes.c_int64), ("inv_alg_bytes", ctypes.c_int64),
                 ("n_jent", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("boxes", ctypes.c_int32 * 3), ("precision", ctypes.c_int32)]
+                ("boxes", ctypes.c_int32 * 3), ("precision", ctypes.c_int32),
+                ("gemv_tiles", ctypes.c_int32 * GEMV_BUCKETS)]
 
 
 _lib = None
@@ -128,6 +152,8 @@ def load():
     L.coarse_plan_create.restype = i32
     L.coarse_setup_from_plan.argtypes = [vp, vp, ctypes.POINTER(vp)]
     L.coarse_setup_from_plan.restype = i32
+    L.coarse_plan_set_gemv_tiles.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+    L.coarse_plan_set_gemv_tiles.restype = i32
     L.coarse_plan_destroy.argtypes = [vp]
     L.coarse_plan_destroy.restype = i32
     L.coarse_last_error.argtypes = [vp]
@@ -149,7 +175,7 @@ def _arrays(xyz, e2v, dirichlet, part, n_part):
     return m, bc, (xyz, e2v, dirichlet, part)
 
 
-def _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible, stream):
+def _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible, stream, gemv_tiles=None):
     o = _Opts()
     load().coarse_default_opts(ctypes.byref(o))
     o.overlap = int(overlap)
@@ -161,15 +187,21 @@ def _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible
     o.max_it = int(max_it)
     o.check_every = int(check_every)
     if flexible is None:
-        flexible = precision == "mixed"
+        flexible = precision in ("mixed", "mixed16")
     o.flexible = int(bool(flexible))
     o.stream = stream
+    t = gemv_table(precision) if gemv_tiles is None else list(gemv_tiles)
+    if len(t) != GEMV_BUCKETS:
+        raise ValueError(f"gemv_tiles needs {GEMV_BUCKETS} entries")
+    for b in range(GEMV_BUCKETS):
+        o.gemv_tiles[b] = int(t[b])
     return o
 
 
 def _info_dict(info):
-    d = {f: getattr(info, f) for f, _ in _Info._fields_ if f != "boxes"}
+    d = {f: getattr(info, f) for f, _ in _Info._fields_ if f not in ("boxes", "gemv_tiles")}
     d["boxes"] = tuple(info.boxes)
+    d["gemv_tiles"] = tuple(info.gemv_tiles)
     return d
 
 
@@ -200,13 +232,13 @@ class Plan:
 
     def __init__(self, xyz, e2v, dirichlet, part=None, n_part=1, *, overlap=1, boxes=None,
                  precision="fp64", mode="additive", interp="centroid", max_it=1000, check_every=4,
-                 flexible=None):
+                 flexible=None, gemv_tiles=None):
         L = load()
         self._L = L
         self.n_vert = int(np.asarray(xyz).shape[0])
         self.precision = precision
         m, bc, keep = _arrays(xyz, e2v, dirichlet, part, n_part)
-        o = _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible, None)
+        o = _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible, None, gemv_tiles)
         pl = ctypes.c_void_p()
         rc = L.coarse_plan_create(ctypes.byref(m), ctypes.byref(bc), ctypes.byref(o), ctypes.byref(pl))
         if rc != 0:
@@ -217,6 +249,13 @@ class Plan:
     def from_mesh(cls, mesh, **kw):
         kw.setdefault("boxes", mesh.boxes)
         return cls(mesh.xyz, mesh.e2v, mesh.dirichlet, mesh.part, mesh.n_part, **kw)
+
+    def set_gemv_tiles(self, tiles):
+        """Work-item table (tiles per item, per size bucket) for later device setups."""
+        arr = (ctypes.c_int * GEMV_BUCKETS)(*[int(t) for t in tiles])
+        rc = self._L.coarse_plan_set_gemv_tiles(self._plan, arr)
+        if rc != 0:
+            raise CoarseError(rc, "bad work-item table")
 
     def close(self):
         if getattr(self, "_plan", None):
@@ -239,7 +278,7 @@ class CoarseSolver:
 
     def __init__(self, xyz, e2v, dirichlet, part=None, n_part=1, *, overlap=1, boxes=None,
                  precision="fp64", mode="additive", interp="centroid", max_it=1000, check_every=4,
-                 flexible=None):
+                 flexible=None, gemv_tiles=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("CoarseSolver needs a GPU; no CPU fallback exists")
@@ -248,7 +287,7 @@ class CoarseSolver:
         self.n_vert = int(np.asarray(xyz).shape[0])
         self.precision = precision
         m, bc, keep = _arrays(xyz, e2v, dirichlet, part, n_part)
-        o = _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible, _stream())
+        o = _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible, _stream(), gemv_tiles)
         ctx = ctypes.c_void_p()
         rc = L.coarse_setup(ctypes.byref(m), ctypes.byref(bc), ctypes.byref(o), ctypes.byref(ctx))
         if rc != 0:

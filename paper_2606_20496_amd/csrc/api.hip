@@ -10,6 +10,7 @@
 #include <memory>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/coarse.h"
@@ -211,6 +212,8 @@ struct coarse_ctx {
     pbeg(3);
     if (precision == COARSE_FP64)
       hipLaunchKernelGGL(k_gemv_f64, dim3(g), dim3(256), 0, stream, segs, 1, nitems, done);
+    else if (precision == COARSE_MIXED_F16)
+      hipLaunchKernelGGL(k_gemv_f16, dim3(g), dim3(256), 0, stream, segs, 1, nitems, done);
     else
       hipLaunchKernelGGL(k_gemv_f32, dim3(g), dim3(256), 0, stream, segs, 1, nitems, done);
     pend(3);
@@ -388,7 +391,7 @@ std::vector<T> cast_vec(const std::vector<double> &v) {
 // FP64 scratch. Returns the number of systems flagged not SPD.
 template <typename T, typename Assemble>
 int64_t invert_systems(coarse_ctx *c, const std::vector<System> &sys, const std::vector<int64_t> &which, T *out,
-                       size_t scratch_tiles_max, Assemble assemble) {
+                       size_t scratch_tiles_max, std::vector<float> &scales, Assemble assemble) {
   hipStream_t s = c->stream;
   int64_t nbad = 0;
   size_t i0 = 0;
@@ -455,18 +458,29 @@ int64_t invert_systems(coarse_ctx *c, const std::vector<System> &sys, const std:
       hipLaunchKernelGGL(k_sweep_panel, dim3((unsigned)ns, (unsigned)maxnb), dim3(256), 0, s, k, dss, M, Dv, Pb, Gb);
       hipLaunchKernelGGL(k_sweep_update, dim3((unsigned)ntiles), dim3(256), 0, s, k, dss, dts, dti, dtj, M, Dv, Pb, Gb);
     }
-    hipLaunchKernelGGL(k_sweep_pack<T>, dim3((unsigned)ntiles), dim3(256), 0, s, dss, dts, dti, dtj, doo, M, out);
+    // FP16 storage: a power-of-two scale per system keeps every entry in range
+    float *dscale = nullptr;
+    if (std::is_same<T, _Float16>::value) {
+      dscale = tmp.alloc<float>(ns);
+      hipLaunchKernelGGL(k_sys_scale, dim3((unsigned)ns), dim3(256), 0, s, dss, (const double *)M, dscale);
+    }
+    hipLaunchKernelGGL(k_sweep_pack<T>, dim3((unsigned)ntiles), dim3(256), 0, s, dss, dts, dti, dtj, doo, M,
+                       (const float *)dscale, out);
     HIPCHK(hipGetLastError());
     std::vector<int> hst(ns);
+    std::vector<float> hsc(ns, 1.0f);
     HIPCHK(hipMemcpyAsync(hst.data(), st, ns * sizeof(int), hipMemcpyDeviceToHost, s));
+    if (dscale) HIPCHK(hipMemcpyAsync(hsc.data(), dscale, ns * sizeof(float), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     for (int v : hst) nbad += (v != 0);
+    for (int64_t k = 0; k < ns; ++k) scales[which[i0 + k]] = hsc[k];
     i0 = i1;
   }
   return nbad;
 }
 
-template <typename T>
+// T: vectors, interpolation and partial sums; TT: the stored inverse tiles.
+template <typename T, typename TT>
 void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
   hipStream_t s = c->stream;
   Arena &A = c->arena;
@@ -538,7 +552,8 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
   HIPCHK(hipMemsetAsync(c->rp, 0, P.vec_len * sizeof(T), s));
   c->zp = A.alloc<double>(P.vec_len);
   HIPCHK(hipMemsetAsync(c->zp, 0, P.vec_len * sizeof(double), s));
-  T *tiles = A.alloc<T>((size_t)P.n_tiles * TILE * TILE);
+  TT *tiles = A.alloc<TT>((size_t)P.n_tiles * TILE * TILE);
+  std::vector<float> sys_scale(P.sys.size(), 1.0f);
   c->tiles = tiles;
   c->colpart = A.alloc<T>((size_t)P.n_tiles * TILE);
   GemvTable G;
@@ -554,7 +569,7 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
   for (int64_t k = 0; k < P.n_local_sys; ++k) loc[k] = k;
   int32_t *vinc_ptr = tmp.upload(P.vinc_ptr, s);
   int32_t *vinc = tmp.upload(P.vinc, s);
-  int64_t nbad = invert_systems<T>(c, P.sys, loc, tiles, scratch_tiles, [&](AsmSys *das, int ns, double *M) {
+  int64_t nbad = invert_systems<TT>(c, P.sys, loc, tiles, scratch_tiles, sys_scale, [&](AsmSys *das, int ns, double *M) {
     hipLaunchKernelGGL(k_assemble_local, dim3((unsigned)ns), dim3(256), 0, s, das, c->sub_idx, vinc_ptr, vinc, e2v, NE,
                        nf, (const double *)Ae, M);
   });
@@ -575,15 +590,58 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
   c->corner_act = A.upload(P.occ_corner_act, s);
   int32_t *ar_ptr = tmp.upload(P.ar_ptr, s);
   int32_t *ar_src = tmp.upload(P.ar_src, s);
-  if (c->interp != COARSE_J_CENTROID) throw Fail(COARSE_EINVAL, "standard interpolation is not available in this build");
-  hipLaunchKernelGGL(k_cell_mats, dim3((unsigned)nocc), dim3(64), 0, s, box, occ_cells, occ_ptr, occ_elems, e2v, NE, NV,
-                     nf, xyz, (const double *)Ae, cellmat);
   std::vector<int64_t> red = {P.n_local_sys};
   const int64_t nr = P.n_r;
-  nbad = invert_systems<T>(c, P.sys, red, tiles, scratch_tiles, [&](AsmSys *, int, double *M) {
-    hipLaunchKernelGGL(k_assemble_reduced, dim3(nblk(nr, 256)), dim3(256), 0, s, nr, ar_ptr, ar_src,
-                       (const int32_t *)c->corner_act, (const double *)cellmat, M);
-  });
+  if (c->interp == COARSE_J_CENTROID) {
+    hipLaunchKernelGGL(k_cell_mats, dim3((unsigned)nocc), dim3(64), 0, s, box, occ_cells, occ_ptr, occ_elems, e2v, NE,
+                       NV, nf, xyz, (const double *)Ae, cellmat);
+    nbad = invert_systems<TT>(c, P.sys, red, tiles, scratch_tiles, sys_scale, [&](AsmSys *, int, double *M) {
+      hipLaunchKernelGGL(k_assemble_reduced, dim3(nblk(nr, 256)), dim3(256), 0, s, nr, ar_ptr, ar_src,
+                         (const int32_t *)c->corner_act, (const double *)cellmat, M);
+    });
+  } else {
+    // Galerkin A_r = J^T A J by probes, in FP64 whatever the solve precision
+    const int64_t ne = (int64_t)P.jv_w.size();
+    int32_t *pjv_ptr = tmp.upload(P.jv_ptr, s);
+    int32_t *pjv_base = tmp.upload(P.jv_base, s);
+    double *pjv_xi = tmp.upload(P.jv_xi, s);
+    int32_t *pjc_vid = tmp.upload(P.jc_vid, s);
+    double *pjc_w = tmp.upload(P.jc_w, s);
+    double *pjc_xi = tmp.upload(P.jc_xi, s);
+    int32_t *pjt = tmp.upload(P.jt_task_start, s);
+    int32_t *pjr_ptr = tmp.upload(P.jr_ptr, s);
+    int32_t *pjr_src = tmp.upload(P.jr_src, s);
+    int32_t *pbv_act = tmp.upload(P.bv_act, s);
+    int32_t *pact_bv = tmp.upload(P.act_bv, s);
+    const int64_t ntask = (int64_t)P.jt_task_occ.size();
+    double *pv = tmp.alloc<double>(nf), *pq = tmp.alloc<double>(nf), *prr = tmp.alloc<double>(nr);
+    double *ptp = tmp.alloc<double>(8 * std::max<int64_t>(1, ntask));
+    ProbeDev pr{};
+    for (int d = 0; d < 3; ++d) {
+      pr.p[d] = P.probe_p[d];
+      pr.d[d] = P.probe_d[d];
+      pr.b[d] = P.b[d];
+    }
+    pr.bx1 = P.b[0] + 1;
+    pr.bxy1 = (P.b[0] + 1) * (P.b[1] + 1);
+    nbad = invert_systems<TT>(c, P.sys, red, tiles, scratch_tiles, sys_scale, [&](AsmSys *, int, double *M) {
+      for (pr.c[2] = 0; pr.c[2] < pr.p[2]; ++pr.c[2])
+        for (pr.c[1] = 0; pr.c[1] < pr.p[1]; ++pr.c[1])
+          for (pr.c[0] = 0; pr.c[0] < pr.p[0]; ++pr.c[0]) {
+            hipLaunchKernelGGL(k_probe_vec, dim3(nblk(nf, 256)), dim3(256), 0, s, nf, pr, (const int32_t *)pjv_ptr,
+                               (const int32_t *)pjv_base, (const double *)pjv_xi, ne, pv);
+            c->apply_op(pv, pq, nullptr, c->zero_flag);
+            hipLaunchKernelGGL(k_jt_tasks<double>, dim3(nblk(ntask, 4)), dim3(256), 0, s, (int)ntask,
+                               (const int *)c->zero_flag, (const int32_t *)pjt, (const int32_t *)pjc_vid,
+                               (const double *)pjc_w, (const double *)pjc_xi, ne, (const double *)pq, ptp);
+            hipLaunchKernelGGL(k_jt_corners<double>, dim3(nblk(nr, 4)), dim3(256), 0, s, nr,
+                               (const int *)c->zero_flag, (const int32_t *)pjr_ptr, (const int32_t *)pjr_src,
+                               (const double *)ptp, prr);
+            hipLaunchKernelGGL(k_probe_scatter, dim3(nblk(nr, 256)), dim3(256), 0, s, nr, pr,
+                               (const int32_t *)pact_bv, (const int32_t *)pbv_act, (const double *)prr, M);
+          }
+    });
+  }
   if (nbad) throw Fail(COARSE_ESINGULAR, "reduced system A_r not positive definite (empty interior box?)");
 
   // reduced solution on the full box-vertex grid (inactive vertices stay 0)
@@ -603,6 +661,8 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
     sd[k].zp = c->zp + S.vec_off;
     sd[k].nb = (int32_t)S.nb;
     sd[k].n = (int32_t)S.n;
+    sd[k].scale = sys_scale[k];
+    sd[k].pad = 0;
     const bool red_sys = (int64_t)k == P.n_local_sys;
     sd[k].yfull = red_sys ? c->yfull : nullptr;
     sd[k].act_bv = red_sys ? c->act_bv : nullptr;
@@ -678,10 +738,10 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
   in.n_r = P.n_r;
   in.n_cells = nocc;
   const int64_t tl = P.sys.back().tile_off;
-  in.local_bytes = tl * TILE * TILE * (int64_t)sizeof(T);
-  in.reduced_bytes = (P.n_tiles - tl) * TILE * TILE * (int64_t)sizeof(T);
+  in.local_bytes = tl * TILE * TILE * (int64_t)sizeof(TT);
+  in.reduced_bytes = (P.n_tiles - tl) * TILE * TILE * (int64_t)sizeof(TT);
   in.inv_alg_bytes = 0;
-  for (const System &S : P.sys) in.inv_alg_bytes += S.n * (S.n + 1) / 2 * (int64_t)sizeof(T);
+  for (const System &S : P.sys) in.inv_alg_bytes += S.n * (S.n + 1) / 2 * (int64_t)sizeof(TT);
   in.n_jent = (int64_t)P.jv_w.size();
   in.a_bytes = NE * (36 * 8 + 8 * 2) + (int64_t)P.slot_vid.size() * 12 + (int64_t)P.slot_inc.size() * 2 + nf * 16;
   for (int d = 0; d < 3; ++d) in.boxes[d] = P.b[d];
@@ -847,7 +907,10 @@ struct coarse_batch {
       hipLaunchKernelGGL(k_combine<double>, dim3(nblk((int64_t)n_rows * TILE, 256)), dim3(256), 0, main,
                          (const Seg *)(d_seg + cap), n, n_rows, (const int *)nullptr);
     } else {
-      hipLaunchKernelGGL(k_gemv_f32, dim3(g), dim3(256), 0, main, (const Seg *)d_seg, n, n_items, (const int *)nullptr);
+      if (precision == COARSE_MIXED_F16)
+        hipLaunchKernelGGL(k_gemv_f16, dim3(g), dim3(256), 0, main, (const Seg *)d_seg, n, n_items, (const int *)nullptr);
+      else
+        hipLaunchKernelGGL(k_gemv_f32, dim3(g), dim3(256), 0, main, (const Seg *)d_seg, n, n_items, (const int *)nullptr);
       hipLaunchKernelGGL(k_combine<float>, dim3(nblk((int64_t)n_rows * TILE, 256)), dim3(256), 0, main,
                          (const Seg *)(d_seg + cap), n, n_rows, (const int *)nullptr);
     }
@@ -952,7 +1015,7 @@ int coarse_plan_create(const coarse_mesh *mesh, const coarse_bc *bc, const coars
   coarse_opts o;
   coarse_default_opts(&o);
   if (opts) o = *opts;
-  if (o.precision != COARSE_FP64 && o.precision != COARSE_MIXED) {
+  if (o.precision != COARSE_FP64 && o.precision != COARSE_MIXED && o.precision != COARSE_MIXED_F16) {
     g_setup_error = "unknown precision";
     return COARSE_EINVAL;
   }
@@ -1019,9 +1082,11 @@ int coarse_setup_from_plan(const coarse_plan *plan, void *stream, coarse_ctx **o
   try {
     HIPCHK(hipHostMalloc((void **)&c->h_sc, sizeof(Scalars), hipHostMallocDefault));
     if (o.precision == COARSE_FP64)
-      setup_precision<double>(c.get(), P, o.gemv_tiles);
+      setup_precision<double, double>(c.get(), P, o.gemv_tiles);
+    else if (o.precision == COARSE_MIXED)
+      setup_precision<float, float>(c.get(), P, o.gemv_tiles);
     else
-      setup_precision<float>(c.get(), P, o.gemv_tiles);
+      setup_precision<float, _Float16>(c.get(), P, o.gemv_tiles);
   } catch (const Fail &f) {
     g_setup_error = f.what();
     (void)hipStreamSynchronize(c->stream);

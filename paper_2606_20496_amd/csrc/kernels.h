@@ -34,6 +34,8 @@ struct SysDev {
   double *yfull;       // reduced system only: solution scattered to all box vertices
   const int32_t *act_bv;   // reduced system only: active index -> box vertex
   int32_t nb, n;
+  float scale;             // FP16 tiles hold A_s^{-1} / scale (1 otherwise)
+  int32_t pad;
 };
 
 // GEMV work item: tiles (I, j0 .. j1-1) of system `sys`; `slot` indexes the

@@ -858,6 +858,94 @@ __global__ __launch_bounds__(256) void k_gemv_f32(const Seg *__restrict__ segs, 
   }
 }
 
+// FP16 tiles (the inverse divided by a power-of-two scale per system, so every
+// entry is at most 2^14), FP32 arithmetic: 2 loads of 16 bytes per lane per tile;
+// lane l holds rows 16m + l/4 (m < 2), columns 8(l%4) .. 8(l%4)+7. The row and
+// column sums are multiplied back by the scale when written.
+typedef _Float16 nt_h8 __attribute__((ext_vector_type(8)));
+__global__ __launch_bounds__(256) void k_gemv_f16(const Seg *__restrict__ segs, int nseg, int total,
+                                                  const int *__restrict__ done) {
+  if (done && *done) return;
+  const int lane = threadIdx.x & 63;
+  const int grp = lane >> 2, c8 = (lane & 3) * 8;
+  for (int g = blockIdx.x * 4 + (threadIdx.x >> 6); g < total; g += gridDim.x * 4) {
+    const Seg sg = segs[nseg == 1 ? 0 : find_seg(segs, nseg, g)];
+    if (sg.done && *sg.done) continue;
+    const GItem it = sg.items[g - sg.begin];
+    const SysDev S = sg.sys[it.sys];
+    const float *__restrict__ r = (const float *)S.rp;
+    const int I = it.I;
+    const int64_t rowbase = (int64_t)I * (I + 1) / 2;
+    const nt_h8 *__restrict__ t = (const nt_h8 *)((const _Float16 *)S.tiles + (rowbase + it.j0) * (TILE * TILE));
+    nt_h8 v[2], w[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) v[m] = __builtin_nontemporal_load(t + m * 64 + lane);
+    float rI[2], acc[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      rI[m] = r[I * TILE + 16 * m + grp];
+      acc[m] = 0.0f;
+    }
+    for (int J = it.j0; J < it.j1; ++J) {
+      const bool more = J + 1 < it.j1;
+      t += TILE * TILE / 8;
+      if (more) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m) w[m] = __builtin_nontemporal_load(t + m * 64 + lane);
+      }
+      const float4 ra = *(const float4 *)(r + J * TILE + c8);
+      const float4 rb = *(const float4 *)(r + J * TILE + c8 + 4);
+      const float rj[8] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w};
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[m] += (float)v[m][k] * rj[k];
+      if (J != I) {
+        float c[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) c[k] = (float)v[0][k] * rI[0] + (float)v[1][k] * rI[1];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          c[k] += __shfl_xor(c[k], 4, 64);
+          c[k] += __shfl_xor(c[k], 8, 64);
+          c[k] += __shfl_xor(c[k], 16, 64);
+          c[k] += __shfl_xor(c[k], 32, 64);
+        }
+        if (lane < 4) {
+          float4 o0, o1;
+          o0.x = c[0] * S.scale;
+          o0.y = c[1] * S.scale;
+          o0.z = c[2] * S.scale;
+          o0.w = c[3] * S.scale;
+          o1.x = c[4] * S.scale;
+          o1.y = c[5] * S.scale;
+          o1.z = c[6] * S.scale;
+          o1.w = c[7] * S.scale;
+          float *cp = (float *)S.colpart + (rowbase + J) * TILE + c8;
+          *(float4 *)cp = o0;
+          *(float4 *)(cp + 4) = o1;
+        }
+      }
+      if (more) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m) v[m] = w[m];
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      float a = acc[m];
+      a += __shfl_xor(a, 1, 64);
+      a += __shfl_xor(a, 2, 64);
+      acc[m] = a * S.scale;
+    }
+    if ((lane & 3) == 0) {
+      float *rowp = (float *)S.rowpart + (int64_t)it.slot * TILE;
+#pragma unroll
+      for (int m = 0; m < 2; ++m) rowp[16 * m + grp] = acc[m];
+    }
+  }
+}
+
 // z_s[I*TILE + c] = sum of the row partials of tile row I + sum over I' > I of
 // the transposed partials of tile (I', I).
 template <typename T>
@@ -1100,6 +1188,67 @@ __global__ __launch_bounds__(256) void k_assemble_reduced(int64_t nr, const int3
 }
 
 // ---------------------------------------------------------------------------
+// Setup, standard interpolation (Sec. 4, eq. (Psi)): the Galerkin reduced
+// operator A_r = J^T A J, one probe per class of box vertices congruent modulo
+// (px, py, pz). A probe is v = J sum_{L in class} e_L; then A v and J^T A v come
+// from the solve's own kernels, and entry K of the result is A_r[K, L] for the
+// one L of the class within reach of K (the classes are spaced so that no two of
+// them reach the same K).
+// ---------------------------------------------------------------------------
+struct ProbeDev {
+  int32_t p[3], d[3], c[3], b[3];
+  int32_t bx1, bxy1;
+};
+
+// v_i = phi_q(xi_i) for the corner q of vertex i's cell that lies in the class
+// (at most one: a cell's corners differ by 1 per direction), else 0
+__global__ __launch_bounds__(256) void k_probe_vec(int64_t nf, ProbeDev pr, const int32_t *__restrict__ jv_ptr,
+                                                   const int32_t *__restrict__ jv_base, const double *__restrict__ jv_xi,
+                                                   int64_t nent, double *__restrict__ v) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nf) return;
+  double out = 0.0;
+  const int k = jv_ptr[i];
+  if (k < jv_ptr[i + 1]) {
+    const int32_t g = jv_base[k];
+    const int32_t g3[3] = {g % pr.bx1, (g / pr.bx1) % (pr.bxy1 / pr.bx1), g / pr.bxy1};
+    int q = 0;
+    bool in = true;
+    for (int d = 0; d < 3; ++d) {
+      const int r = ((pr.c[d] - g3[d]) % pr.p[d] + pr.p[d]) % pr.p[d];
+      if (r > 1) in = false;
+      q |= (r & 1) << d;
+    }
+    if (in) out = trilin<double>(q, jv_xi[k], jv_xi[nent + k], jv_xi[2 * nent + k]);
+  }
+  v[i] = out;
+}
+
+// A_r[K, L] = rr[K] for the class member L within reach of K, stored when it
+// falls in a lower tile of the dense reduced system
+__global__ __launch_bounds__(256) void k_probe_scatter(int64_t nr, ProbeDev pr, const int32_t *__restrict__ act_bv,
+                                                       const int32_t *__restrict__ bv_act, const double *__restrict__ rr,
+                                                       double *__restrict__ M) {
+  const int64_t K = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (K >= nr) return;
+  const int32_t g = act_bv[K];
+  const int32_t g3[3] = {g % pr.bx1, (g / pr.bx1) % (pr.bxy1 / pr.bx1), g / pr.bxy1};
+  int32_t l3[3];
+  for (int d = 0; d < 3; ++d) {
+    // the class member nearest K in this direction: offset r or r - p, whichever
+    // is within reach and on the grid (a period of b + 1 leaves one member)
+    const int r = ((pr.c[d] - g3[d]) % pr.p[d] + pr.p[d]) % pr.p[d];
+    const bool up = r <= pr.d[d] && g3[d] + r <= pr.b[d];
+    const bool down = r - pr.p[d] >= -pr.d[d] && g3[d] + r - pr.p[d] >= 0;
+    if (!up && !down) return;
+    l3[d] = g3[d] + (up ? r : r - pr.p[d]);
+  }
+  const int32_t L = bv_act[l3[0] + pr.bx1 * l3[1] + pr.bxy1 * l3[2]];
+  if (L < 0 || L / TILE > (int)K / TILE) return;
+  *tile_elem(M, 0, (int)K, L) = rr[K];
+}
+
+// ---------------------------------------------------------------------------
 // Setup: batched inverse of SPD systems by the symmetric block sweep (block
 // Gauss-Jordan). Sweeping pivot block k of the current matrix M:
 //   D = M_kk^{-1};  M_OO -= M_Ok D M_kO;  M_Ok <- M_Ok D;  M_kO <- D M_kO;
@@ -1261,12 +1410,33 @@ __global__ __launch_bounds__(256) void k_sweep_update(int k, const SweepSys *__r
   for (int r = 0; r < 4; ++r) mo[4 * r * TILE] = acc[r];
 }
 
-// -M -> output tiles (symmetrised diagonal tiles), converted to T.
+// Per swept system: a power of two s with max |entry| / s <= 2^14 (1 when the
+// system is zero), the scale of its FP16 tiles.
+__global__ __launch_bounds__(256) void k_sys_scale(const SweepSys *__restrict__ sys, const double *__restrict__ M,
+                                                   float *__restrict__ scale) {
+  __shared__ double red[256 / WAVE];
+  const SweepSys S = sys[blockIdx.x];
+  const int64_t n = (int64_t)S.nb * (S.nb + 1) / 2 * (TILE * TILE);
+  const double *base = M + S.tile_off * (TILE * TILE);
+  double mx = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) mx = fmax(mx, fabs(base[i]));
+  for (int o = WAVE / 2; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, WAVE));
+  if ((threadIdx.x % WAVE) == 0) red[threadIdx.x / WAVE] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int w = 0; w < 256 / WAVE; ++w) m = fmax(m, red[w]);
+    scale[blockIdx.x] = (m > 0.0) ? (float)ldexp(1.0, ilogb(m) - 13) : 1.0f;
+  }
+}
+
+// -M -> output tiles (symmetrised diagonal tiles), divided by the system's scale
+// (NULL: 1) and converted to T.
 template <typename T>
 __global__ __launch_bounds__(256) void k_sweep_pack(const SweepSys *__restrict__ sys, const int32_t *__restrict__ tsys,
                                                     const int16_t *__restrict__ tI, const int16_t *__restrict__ tJ,
                                                     const int64_t *__restrict__ out_off, const double *__restrict__ M,
-                                                    T *__restrict__ out) {
+                                                    const float *__restrict__ scale, T *__restrict__ out) {
   const int t0 = blockIdx.x;
   const int s = tsys[t0];
   const SweepSys S = sys[s];
@@ -1277,6 +1447,7 @@ __global__ __launch_bounds__(256) void k_sweep_pack(const SweepSys *__restrict__
     const int i = t / TILE, j = t % TILE;
     double v = -Mt[t];
     if (I == J) v = -0.5 * (Mt[t] + Mt[j * TILE + i]);
+    if (scale) v /= (double)scale[s];
     o[t] = (T)v;
   }
 }
@@ -1301,9 +1472,11 @@ template __global__ void k_jt_corners<float>(int64_t, const int *, const int32_t
 template __global__ void k_combine<double>(const Seg *, int, int, const int *);
 template __global__ void k_combine<float>(const Seg *, int, int, const int *);
 template __global__ void k_sweep_pack<double>(const SweepSys *, const int32_t *, const int16_t *, const int16_t *,
-                                              const int64_t *, const double *, double *);
+                                              const int64_t *, const double *, const float *, double *);
 template __global__ void k_sweep_pack<float>(const SweepSys *, const int32_t *, const int16_t *, const int16_t *,
-                                             const int64_t *, const double *, float *);
+                                             const int64_t *, const double *, const float *, float *);
+template __global__ void k_sweep_pack<_Float16>(const SweepSys *, const int32_t *, const int16_t *, const int16_t *,
+                                                const int64_t *, const double *, const float *, _Float16 *);
 template __global__ void k_convert<float>(int64_t, const double *, float *);
 template __global__ void k_convert<double>(int64_t, const double *, double *);
 

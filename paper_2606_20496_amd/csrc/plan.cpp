@@ -589,6 +589,26 @@ int build_plan(const PlanInput &in, Plan &P) {
     }
   }
 
+  if (in.interp != 0) {
+    // J e_L lives on the vertices of the cells around box vertex L; A reaches one
+    // element further. With elements spanning at most ext_d in direction d, the
+    // column couples box vertices within 1 + ceil(ext_d / H_d) of L.
+    double ext[3] = {0, 0, 0};
+    for (int64_t e = 0; e < NE; ++e)
+      for (int d = 0; d < 3; ++d) {
+        double mn = 1e300, mx = -1e300;
+        for (int v = 0; v < 8; ++v) {
+          const double x = P.xyz[d * NV + E2V(e, v)];
+          mn = std::min(mn, x);
+          mx = std::max(mx, x);
+        }
+        ext[d] = std::max(ext[d], mx - mn);
+      }
+    for (int d = 0; d < 3; ++d) {
+      P.probe_d[d] = 1 + (int32_t)std::ceil(ext[d] / P.H[d]);
+      P.probe_p[d] = std::min<int32_t>(2 * P.probe_d[d] + 1, P.b[d] + 1);
+    }
+  }
   tr.mark("reduced space");
   // ---- dense systems, packed vectors, tiles and GEMV items --------------------
   {

@@ -94,6 +94,10 @@ struct Plan {
   // reduced space (Sec. 4)
   double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0}, H[3] = {1, 1, 1};
   int32_t b[3] = {1, 1, 1};
+  // standard interpolation: the Galerkin A_r = J^T A J is formed column by column
+  // from probes; box vertices congruent modulo probe_p share a probe, and a probe
+  // column couples box vertices at most probe_d apart per direction
+  int32_t probe_p[3] = {1, 1, 1}, probe_d[3] = {0, 0, 0};
   int64_t n_bv = 0;                      // (b+1)^3 box vertices
   std::vector<int32_t> elem_cell;        // internal element -> cell id
   std::vector<int32_t> occ_cells;        // occupied cells (ids)

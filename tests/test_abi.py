@@ -113,3 +113,13 @@ def test_plan_is_host_only():
     with pytest.raises(coarse.CoarseError) as ei:
         coarse.Plan(m.xyz, m.e2v, m.dirichlet, m.part, m.n_part, boxes=m.boxes, max_it=0)
     assert ei.value.code == -1
+
+
+def test_plan_standard_interp_matches_oracle():
+    # vertex-based J (Sec. 4, eq. (Psi)): the same active box vertices as the oracle
+    for m in (mg.small_cube(), mg.annulus_mesh(12, 5, block=4, boxes=(3, 3, 3))):
+        A, Ae, Afull, free, fidx = fem.stiffness(m.xyz, m.e2v, m.dirichlet)
+        S = reduced.StandardSpace(m.xyz, m.dirichlet, A, m.boxes, free)
+        info, _ = coarse.plan_info(m.xyz, m.e2v, m.dirichlet, m.part, m.n_part, boxes=m.boxes, interp="standard")
+        assert info["n_r"] == S.n_r
+        assert info["n_jent"] == free.size          # one entry per free vertex

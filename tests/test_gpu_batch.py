@@ -35,7 +35,7 @@ def _alone(ms, precision):
     return out
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed16"])
 @pytest.mark.parametrize("graph", [False, True])
 def test_batch_equals_alone(precision, graph):
     ms = _meshes()

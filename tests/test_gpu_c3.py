@@ -149,10 +149,11 @@ def test_c3_solve_fp64(c3, c3_fp64):
 
 
 @pytest.mark.timeout(900)
-def test_c3_solve_mixed(c3, c3_fp64):
+@pytest.mark.parametrize("precision", ["mixed", "mixed16"])
+def test_c3_solve_mixed(c3, c3_fp64, precision):
     m = c3["m"]
     u64, st64 = c3_fp64
-    S = coarse.CoarseSolver.from_mesh(m, precision="mixed")
+    S = coarse.CoarseSolver.from_mesh(m, precision=precision)
     u, st = S.solve(_gpu(m.b), tol=1e-8)
     u = _np(u)
     S.close()

@@ -82,6 +82,35 @@ def test_apply_precond_modes(mode):
     assert _rel(_np(S.apply_precond(_gpu(r))), P.apply_precond(r)) < 1e-12
 
 
+@pytest.mark.parametrize("name,make", SMALL, ids=[s[0] for s in SMALL])
+def test_standard_interp_precond_and_solve(name, make):
+    # vertex-based J with the Galerkin A_r = J^T A J (Sec. 4), formed on the GPU
+    # by probes: one preconditioner application at 1e-12, the same iterations
+    m = make()
+    P = problem.from_mesh(m, interp="standard")
+    S = coarse.CoarseSolver.from_mesh(m, interp="standard")
+    r = np.random.default_rng(10).standard_normal(m.n_vert)
+    assert _rel(_np(S.apply_precond(_gpu(r))), P.apply_precond(r)) < 1e-12
+    uo, io = P.solve(m.b, tol=1e-8)
+    u, st = S.solve(_gpu(m.b), tol=1e-8)
+    assert st["code"] == 0 and st["iters"] == io["iters"]
+    assert np.linalg.norm(_np(u) - uo) / np.linalg.norm(uo) < 1e-9
+
+
+def test_standard_interp_reduced_part_is_a_projection():
+    # with A_r = J^T A J, z = J A_r^{-1} J^T r is the A-orthogonal projection of
+    # A^{-1} r on range(J): J^T (r - A z) = 0 (the best-approximation property)
+    m = mg.box_mesh(12, 44, block=4, boxes=(3, 3, 3), faces=("z0",))
+    P = problem.from_mesh(m, interp="standard")
+    S = coarse.CoarseSolver.from_mesh(m, interp="standard", mode="reduced_only")
+    r = np.random.default_rng(11).standard_normal(m.n_vert)
+    z = S.apply_precond(_gpu(r))
+    q = _np(S.apply_A(z))
+    J = P.coarse.J
+    res = J.T @ (P.to_free(r) - P.to_free(q))
+    assert np.abs(res).max() < 1e-11 * np.abs(J.T @ P.to_free(r)).max()
+
+
 def test_overlap_two():
     m = mg.box_mesh(8, 32, block=4, boxes=(2, 2, 2))
     P, S = _case(m, overlap=2)
@@ -112,6 +141,26 @@ def test_solve_small_mixed(name, make):
     u, st = S.solve(_gpu(m.b), tol=1e-8)
     assert st["code"] == 0
     assert st["iters"] <= math.ceil(1.1 * io["iters"])
+    assert st["relres_true"] <= 1.05e-8
+    assert np.linalg.norm(_np(u) - uo) / np.linalg.norm(uo) < 1e-6
+
+
+@pytest.mark.parametrize("name,make", SMALL, ids=[s[0] for s in SMALL])
+def test_solve_small_mixed16(name, make):
+    # FP16 storage of the inverses (per-system power-of-two scale), FP32 arithmetic.
+    # A reduced-byte form of the local solves is judged by iterations x bytes: it
+    # must reach the same 1e-8 true residual and move no more bytes through the
+    # dense solves than the FP32 form (at most twice its iterations)
+    m = make()
+    P = problem.from_mesh(m)
+    uo, io = P.solve(m.b, tol=1e-8)
+    S = coarse.CoarseSolver.from_mesh(m, precision="mixed16")
+    S32 = coarse.CoarseSolver.from_mesh(m, precision="mixed")
+    assert S.info["inv_alg_bytes"] * 2 == S32.info["inv_alg_bytes"]
+    u, st = S.solve(_gpu(m.b), tol=1e-8)
+    _, st32 = S32.solve(_gpu(m.b), tol=1e-8)
+    assert st["code"] == 0
+    assert st["iters"] * S.info["inv_alg_bytes"] <= st32["iters"] * S32.info["inv_alg_bytes"]
     assert st["relres_true"] <= 1.05e-8
     assert np.linalg.norm(_np(u) - uo) / np.linalg.norm(uo) < 1e-6
 
@@ -209,6 +258,16 @@ def test_cube64_solve_fp64(cube64):
     assert st["code"] == 0 and st["iters"] == io["iters"]
     assert st["relres_true"] <= 1.01e-8
     assert np.linalg.norm(_np(u) - uo) / np.linalg.norm(uo) < 1e-8
+
+
+@pytest.mark.timeout(900)
+def test_cube64_solve_mixed16(cube64):
+    m, P, uo, io = cube64
+    S = coarse.CoarseSolver.from_mesh(m, precision="mixed16")
+    u, st = S.solve(_gpu(m.b), tol=1e-8)
+    assert st["code"] == 0
+    assert st["iters"] <= math.ceil(1.1 * io["iters"])
+    assert st["relres_true"] <= 1.05e-8
 
 
 @pytest.mark.timeout(900)

@@ -66,3 +66,23 @@ def test_setup_from_plan_equals_setup(precision):
         u, st = S.solve(b)
         assert st["iters"] == s1["iters"] and torch.equal(u, u1)
         assert S.device_bytes == S1.device_bytes
+
+
+def test_gemv_work_item_table_changes_rounding_only():
+    # every work-item length gives the same preconditioner to rounding and the same
+    # iteration count; a context reports the table it was built with
+    from paper_2606_20496_amd import meshgen as mg
+    m = mg.box_mesh(14, 43, block=7, boxes=(2, 2, 2), faces=("x1",))
+    r = torch.tensor(m.b, device="cuda")
+    ref = None
+    for t in (1, 3, 4, 16):
+        S = coarse.CoarseSolver.from_mesh(m, gemv_tiles=[t] * coarse.GEMV_BUCKETS)
+        assert S.info["gemv_tiles"] == (t,) * coarse.GEMV_BUCKETS
+        z = S.apply_precond(r)
+        u, st = S.solve(r)
+        if ref is None:
+            ref = (z, st["iters"])
+        else:
+            assert float((z - ref[0]).abs().max() / ref[0].abs().max()) < 1e-13
+            assert st["iters"] == ref[1]
+        S.close()
