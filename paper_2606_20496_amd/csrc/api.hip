@@ -287,7 +287,7 @@ struct coarse_ctx {
         break;
       case COARSE_HYBRID_SYM:
         // z0 = M_r r; z1 = z0 + M_loc (r - A z0); z = z1 + M_r (r - A z1)
-        precond_parts<T>(in, nullptr, false, true, t1, nullptr, nullptr, nullptr, done, false, 0, chk);
+        precond_parts<T>(in, nullptr, false, true, t1, nullptr, nullptr, nullptr, done, false, start, chk);
         apply_op(t1, q, nullptr, done);
         hipLaunchKernelGGL(k_sub, dim3(nvblk), dim3(VB), 0, stream, nf, done, in, q, t2);
         precond_parts<T>(t2, t1, true, false, t1, nullptr, nullptr, nullptr, done, false, 0, nullptr);

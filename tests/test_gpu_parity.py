@@ -111,6 +111,20 @@ def test_standard_interp_reduced_part_is_a_projection():
     assert np.abs(res).max() < 1e-11 * np.abs(J.T @ P.to_free(r)).max()
 
 
+@pytest.mark.parametrize("mode", ["hybrid_sym", "local_only"])
+def test_solve_modes_match_oracle(mode):
+    # the whole PCG loop with the symmetrised hybrid and with the local part alone:
+    # the same iterations as the oracle and the same solution to the tolerance
+    m = mg.box_mesh(12, 47, block=4, boxes=(3, 3, 3), faces=("x0",), rhs="bumps")
+    om = {"reduced_only": "coarse_only"}.get(mode, mode)
+    P = problem.from_mesh(m, mode=om)
+    uo, io = P.solve(m.b, tol=1e-8)
+    S = coarse.CoarseSolver.from_mesh(m, mode=mode)
+    u, st = S.solve(_gpu(m.b), tol=1e-8)
+    assert st["code"] == 0 and st["iters"] == io["iters"]
+    assert np.linalg.norm(_np(u) - uo) / np.linalg.norm(uo) < 1e-9
+
+
 def test_overlap_two():
     m = mg.box_mesh(8, 32, block=4, boxes=(2, 2, 2))
     P, S = _case(m, overlap=2)
