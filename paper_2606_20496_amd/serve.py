@@ -122,7 +122,7 @@ class Server:
         np_ = (vol ** (1 / 3) + 2) ** 3
         nb = np.ceil(np_ / 32)
         tiles = mesh.n_part * nb * (nb + 1) / 2
-        es = 8 if precision == "fp64" else 4
+        es = {"fp64": 8, "mixed": 4, "mixed16": 2}[precision]
         return int(E * 420 + n * 200 + tiles * 1024 * es * 1.1 + tiles * 32 * es)
 
     def run(self, requests, t0=None):
