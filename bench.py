@@ -248,6 +248,41 @@ def run_ablations(torch, coarse, mesh, b, tol, max_it=400):
     return out
 
 
+def run_warm_start(torch, coarse, mg, mesh, tol, steps=32, basis=8, precisions=("fp64", "mixed16")):
+    """A sequence of `steps` right-hand sides from a load that changes smoothly in
+    time (time step 0.005: features move about a third of an element per step at
+    64^3), solved cold (u_0 = 0) and from the projection onto the last `basis`
+    solutions (Sec. 5). Host-clock ms per solve, iterations, and the initial
+    residual the projection leaves."""
+    bs = [torch.tensor(b, device="cuda") for b in mg.rhs_sequence(mesh, 777, steps)]
+    out = {"steps": steps, "basis": basis, "dt": 0.005}
+    for prec in precisions:
+        S = coarse.CoarseSolver.from_mesh(mesh, precision=prec, projection=basis)
+        u = torch.empty_like(bs[0])
+        res = {}
+        for form, fn in (("cold", S.solve), ("projected", S.solve_projected)):
+            S.projection_reset()
+            fn(bs[0], tol, out=u)      # warm the kernels (and, projected, the first basis vector)
+            S.projection_reset()
+            torch.cuda.synchronize()
+            iters, r0, worst = [], [], 0.0
+            t0 = time.perf_counter()
+            for b in bs:
+                _, st = fn(b, tol, out=u)
+                iters.append(st["iters"])
+                r0.append(st["relres0"])
+                worst = max(worst, st["relres_true"])
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            res[form] = {"ms_per_solve": round(1e3 * t / steps, 3), "iters_mean": round(float(np.mean(iters)), 2),
+                         "iters_first": iters[0], "iters_last": iters[-1],
+                         "relres0_median": float(np.median(r0)), "worst_relres_true": worst}
+        res["speedup"] = round(res["cold"]["ms_per_solve"] / res["projected"]["ms_per_solve"], 3)
+        out[prec] = res
+        S.close()
+    return out
+
+
 def cpu_baseline(mesh, tol):
     """The FP64 oracle, as it stands, on the host cores: one full solve of the
     same workload (setup timed separately and excluded)."""
@@ -277,6 +312,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-mesh batched workload")
     ap.add_argument("--no-large", action="store_true", help="skip the 128^3 annulus kernel measurements")
     ap.add_argument("--no-ablations", action="store_true", help="skip the preconditioner-part study")
+    ap.add_argument("--no-warm-start", action="store_true", help="skip the successive right-hand-side study")
     ap.add_argument("--serving", action="store_true", help="also run a short serving-loop workload")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 1 GiB device copy (known bytes) to scale HBM counters")
@@ -339,6 +375,12 @@ def main():
         ablations = run_ablations(torch, coarse, mesh, rhs[0], args.tol)
         _log(f"ablations: { {k: v['iters'] for k, v in ablations.items()} }")
 
+    warm = None
+    if not args.no_warm_start:
+        _log("warm start")
+        warm = run_warm_start(torch, coarse, mg, mesh, args.tol)
+        _log(f"warm start: {warm}")
+
     large = None
     if not args.no_large:
         _log("annulus128 kernels")
@@ -394,6 +436,8 @@ def main():
         line["large_workload"] = large
     if ablations is not None:
         line["ablations"] = ablations
+    if warm is not None:
+        line["warm_start"] = warm
     if serving is not None:
         line["serving_workload"] = serving
     print(json.dumps(line), flush=True)

@@ -102,6 +102,9 @@ typedef struct {
   const uint8_t *dirichlet;   /* host [n_vert] */
 } coarse_bc;
 
+/* Largest basis of prior solutions a context may keep (opts.projection). */
+#define COARSE_PROJECTION_MAX 64
+
 /* Size buckets of the work-item table (upper bounds on nb; the last is open). */
 #define COARSE_GEMV_BUCKETS 8
 static const int coarse_gemv_bucket_max[COARSE_GEMV_BUCKETS] = {2, 4, 8, 12, 16, 24, 48, 1 << 30};
@@ -127,6 +130,10 @@ typedef struct {
                        the order of rounding inside a row sum and the speed; a
                        context keeps its choice for life (results stay bitwise
                        reproducible, alone or batched)                             */
+  int projection;   /* l >= 0 prior solutions kept for coarse_solve_projected
+                       (Sec. 5); 0 = none. The basis takes 2 l n_free doubles of
+                       device memory, allocated by the setup; l <=
+                       COARSE_PROJECTION_MAX                                       */
 } coarse_opts;
 
 typedef struct {
@@ -136,6 +143,9 @@ typedef struct {
   double relres_true;   /* ||b - A u||_2 / ||b||_2 recomputed at the end            */
   double t_setup;       /* seconds spent in coarse_setup                            */
   double t_solve;       /* seconds spent in this solve (host clock, stream synced)  */
+  double relres0;       /* ||b - A u_0||_2 / ||b||_2 of the initial guess u_0 (1 from
+                           u_0 = 0)                                                */
+  int n_basis;          /* prior solutions the initial guess was projected on      */
 } coarse_stats;
 
 typedef struct {
@@ -206,6 +216,25 @@ int coarse_apply_A(coarse_ctx *ctx, const double *p, double *q);
  * b, u: device float64 [n_vert]. st may be NULL. Returns COARSE_OK, COARSE_NOTCONV
  * (warning) or COARSE_EBREAKDOWN / COARSE_EINVAL. b = 0 gives u = 0, iters = 0. */
 int coarse_solve(coarse_ctx *ctx, const double *b, double *u, double tol, coarse_stats *st);
+
+/* Solve A u = b for one of a sequence of right-hand sides with the same A, by
+ * projection onto prior solutions (Sec. 5, the A-orthogonal best fit over the
+ * span of the last solutions): with the stored basis x_1..x_n, A-orthonormal
+ * (x_j^T A x_k = delta_jk, free entries), c_j = x_j^T b, u_bar = sum_j c_j x_j is
+ * the best approximation of u in the A-norm over that span, and PCG starts from
+ * u_0 = u_bar (r_0 = b - sum_j c_j A x_j), stopping at ||r||_2 <= tol ||b||_2 as
+ * coarse_solve does. The solution then joins the basis by A-Gram-Schmidt
+ * (classical, coefficients x_j^T A u) and normalisation; it is not added when its
+ * A-orthogonal part has A-norm at most 1e-6 of its own (already in the span) or
+ * is not finite. When the basis holds opts.projection vectors, the next append
+ * empties it first. Needs opts.projection >= 1 at setup (else EINVAL); no device
+ * allocation. b, u: device float64 [n_vert]; st as for coarse_solve, with
+ * relres0 = ||r_0|| / ||b|| and n_basis = n. Returns as coarse_solve. */
+int coarse_solve_projected(coarse_ctx *ctx, const double *b, double *u, double tol, coarse_stats *st);
+
+/* Forget the stored prior solutions (the next coarse_solve_projected starts from
+ * u_0 = 0). Errors: EINVAL. */
+int coarse_projection_reset(coarse_ctx *ctx);
 
 /* Solve `count` independent systems (any mix of contexts, each with its own right-
  * hand side) in lock step: every PCG phase of all live systems is issued before

@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcoarse.so")
 
 PRECISION = {"fp64": 0, "mixed": 1, "mixed16": 2}
+PROJECTION_MAX = 64   # COARSE_PROJECTION_MAX: largest basis of prior solutions
 MODE = {"additive": 0, "hybrid_sym": 1, "local_only": 2, "reduced_only": 3}
 INTERP = {"centroid": 0, "standard": 1}
 STATUS = {0: "ok", 1: "notconv", -1: "einval", -2: "enomem", -3: "emesh", -4: "esingular",
@@ -28,7 +29,8 @@ EXPORTS = ("coarse_default_opts", "coarse_setup", "coarse_apply_precond", "coars
            "coarse_get_info", "coarse_set_stream", "coarse_plan_info", "coarse_strerror",
            "coarse_last_error", "coarse_profile", "coarse_batch_create", "coarse_batch_submit",
            "coarse_batch_step", "coarse_batch_live", "coarse_batch_destroy", "coarse_plan_create",
-           "coarse_setup_from_plan", "coarse_plan_destroy", "coarse_plan_set_gemv_tiles")
+           "coarse_setup_from_plan", "coarse_plan_destroy", "coarse_plan_set_gemv_tiles",
+           "coarse_solve_projected", "coarse_projection_reset")
 
 PHASES = ("A+p", "R_p+J^T", "J^T corners", "A_p^-1/A_r^-1 gemv", "combine", "sum+J", "x,r update")
 
@@ -74,12 +76,13 @@ class _Opts(ctypes.Structure):
     _fields_ = [("overlap", ctypes.c_int), ("boxes", ctypes.c_int * 3), ("precision", ctypes.c_int),
                 ("mode", ctypes.c_int), ("interp", ctypes.c_int), ("max_it", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("flexible", ctypes.c_int), ("stream", ctypes.c_void_p),
-                ("gemv_tiles", ctypes.c_int * GEMV_BUCKETS)]
+                ("gemv_tiles", ctypes.c_int * GEMV_BUCKETS), ("projection", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("relres", ctypes.c_double),
-                ("relres_true", ctypes.c_double), ("t_setup", ctypes.c_double), ("t_solve", ctypes.c_double)]
+                ("relres_true", ctypes.c_double), ("t_setup", ctypes.c_double), ("t_solve", ctypes.c_double),
+                ("relres0", ctypes.c_double), ("n_basis", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -119,6 +122,10 @@ def load():
     L.coarse_apply_A.restype = i32
     L.coarse_solve.argtypes = [vp, vp, vp, dbl, ctypes.POINTER(_Stats)]
     L.coarse_solve.restype = i32
+    L.coarse_solve_projected.argtypes = [vp, vp, vp, dbl, ctypes.POINTER(_Stats)]
+    L.coarse_solve_projected.restype = i32
+    L.coarse_projection_reset.argtypes = [vp]
+    L.coarse_projection_reset.restype = i32
     L.coarse_solve_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i32, dbl,
                                      ctypes.POINTER(_Stats)]
     L.coarse_solve_batch.restype = i32
@@ -175,7 +182,8 @@ def _arrays(xyz, e2v, dirichlet, part, n_part):
     return m, bc, (xyz, e2v, dirichlet, part)
 
 
-def _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible, stream, gemv_tiles=None):
+def _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible, stream, gemv_tiles=None,
+          projection=0):
     o = _Opts()
     load().coarse_default_opts(ctypes.byref(o))
     o.overlap = int(overlap)
@@ -195,6 +203,7 @@ def _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible
         raise ValueError(f"gemv_tiles needs {GEMV_BUCKETS} entries")
     for b in range(GEMV_BUCKETS):
         o.gemv_tiles[b] = int(t[b])
+    o.projection = int(projection)
     return o
 
 
@@ -232,13 +241,14 @@ class Plan:
 
     def __init__(self, xyz, e2v, dirichlet, part=None, n_part=1, *, overlap=1, boxes=None,
                  precision="fp64", mode="additive", interp="centroid", max_it=1000, check_every=4,
-                 flexible=None, gemv_tiles=None):
+                 flexible=None, gemv_tiles=None, projection=0):
         L = load()
         self._L = L
         self.n_vert = int(np.asarray(xyz).shape[0])
         self.precision = precision
         m, bc, keep = _arrays(xyz, e2v, dirichlet, part, n_part)
-        o = _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible, None, gemv_tiles)
+        o = _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible, None, gemv_tiles,
+                  projection)
         pl = ctypes.c_void_p()
         rc = L.coarse_plan_create(ctypes.byref(m), ctypes.byref(bc), ctypes.byref(o), ctypes.byref(pl))
         if rc != 0:
@@ -278,7 +288,7 @@ class CoarseSolver:
 
     def __init__(self, xyz, e2v, dirichlet, part=None, n_part=1, *, overlap=1, boxes=None,
                  precision="fp64", mode="additive", interp="centroid", max_it=1000, check_every=4,
-                 flexible=None, gemv_tiles=None):
+                 flexible=None, gemv_tiles=None, projection=0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("CoarseSolver needs a GPU; no CPU fallback exists")
@@ -287,7 +297,8 @@ class CoarseSolver:
         self.n_vert = int(np.asarray(xyz).shape[0])
         self.precision = precision
         m, bc, keep = _arrays(xyz, e2v, dirichlet, part, n_part)
-        o = _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible, _stream(), gemv_tiles)
+        o = _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible, _stream(), gemv_tiles,
+                  projection)
         ctx = ctypes.c_void_p()
         rc = L.coarse_setup(ctypes.byref(m), ctypes.byref(bc), ctypes.byref(o), ctypes.byref(ctx))
         if rc != 0:
@@ -352,16 +363,27 @@ class CoarseSolver:
         self._check(self._L.coarse_apply_A(self._ctx, self._vec(p), self._vec(out)))
         return out
 
-    def solve(self, b, tol=1e-8, out=None):
+    def _solve(self, fn, b, tol, out):
         import torch
         self._sync_stream()
         out = torch.empty_like(b) if out is None else out
         st = _Stats()
-        rc = self._check(self._L.coarse_solve(self._ctx, self._vec(b), self._vec(out), float(tol),
-                                              ctypes.byref(st)))
+        rc = self._check(fn(self._ctx, self._vec(b), self._vec(out), float(tol), ctypes.byref(st)))
         stats = {f: getattr(st, f) for f, _ in _Stats._fields_}
         stats["code"] = rc
         return out, stats
+
+    def solve(self, b, tol=1e-8, out=None):
+        return self._solve(self._L.coarse_solve, b, tol, out)
+
+    def solve_projected(self, b, tol=1e-8, out=None):
+        """One solve of a sequence with the same A: PCG from the A-orthogonal
+        projection onto the stored prior solutions, which then take in this one
+        (needs ``projection`` >= 1 at construction)."""
+        return self._solve(self._L.coarse_solve_projected, b, tol, out)
+
+    def projection_reset(self):
+        self._check(self._L.coarse_projection_reset(self._ctx))
 
     def profile_start(self, mask=0x7F):
         """Time the phases whose bits are set in ``mask`` (bit i = PHASES[i])."""

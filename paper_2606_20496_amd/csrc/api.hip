@@ -104,6 +104,13 @@ struct coarse_ctx {
   int *zero_flag = nullptr;  // a device int that is always 0
   int *done_flag = nullptr;  // &sc->done
 
+  // initial guess by projection onto prior solutions: A-orthonormal basis X and
+  // A X, proj_max rows of nf entries each, proj_n of them in use
+  int proj_max = 0, proj_n = 0;
+  double *proj_x = nullptr, *proj_ax = nullptr, *proj_part = nullptr, *proj_coef = nullptr;
+  int *proj_count = nullptr;
+  int *h_proj_count = nullptr;   // pinned host copy of the basis size after an append
+
   // batched dense solves
   int32_t *sub_idx = nullptr;
   void *rp = nullptr, *tiles = nullptr, *rowpart = nullptr, *colpart = nullptr;
@@ -134,6 +141,7 @@ struct coarse_ctx {
 
   ~coarse_ctx() {
     if (h_sc) (void)hipHostFree(h_sc);
+    if (h_proj_count) (void)hipHostFree(h_proj_count);
     for (auto &p : ev_pending) {
       ev_pool.push_back(p.second.first);
       ev_pool.push_back(p.second.second);
@@ -351,10 +359,39 @@ struct coarse_ctx {
       final_step<float>(nullptr, true, true, z, r, part1, flexible ? part2 : nullptr, done_flag, true, 0);
   }
 
-  void start(const double *b, double tol) {
+  // nproj > 0: start from the projection of the solution onto the first nproj
+  // rows of the stored basis instead of u_0 = 0
+  void start(const double *b, double tol, int nproj = 0) {
     hipLaunchKernelGGL(k_start, dim3(nvblk), dim3(VB), 0, stream, nf, user_of_vint, b, r, x, p, pb, z, bint, prr, sc,
                        tol * tol, max_it, flexible);
-    precond(r, z, r, part1, flexible ? part2 : nullptr, done_flag, true, 1, prr);
+    if (nproj > 0) proj_guess(nproj);
+    precond(r, z, r, part1, flexible ? part2 : nullptr, done_flag, true, nproj > 0 ? 2 : 1, prr);
+  }
+
+  // Sec. 5: c_j = X_j . b (and ||b||^2 as the last row), u_bar = sum c_j X_j in x,
+  // r_0 = b - sum c_j A X_j in r with the partials of ||r_0||^2 in prr.
+  void proj_guess(int n) {
+    hipLaunchKernelGGL(k_proj_dots, dim3(nvblk, n + 1), dim3(VB), 0, stream, nf, n, (const double *)proj_x, nf,
+                       (const double *)bint, (const double *)bint, proj_part);
+    hipLaunchKernelGGL(k_proj_totals, dim3(n + 1), dim3(256), 0, stream, (const double *)proj_part, nvblk, proj_coef,
+                       sc);
+    hipLaunchKernelGGL(k_proj_guess, dim3(nvblk), dim3(VB), 0, stream, nf, n, (const double *)proj_coef,
+                       (const double *)proj_x, (const double *)proj_ax, nf, x, r, prr);
+  }
+
+  // Append the solution in x (with q = A x, as finish() leaves them) as row n of
+  // the basis: A-Gram-Schmidt against rows 0..n-1, then normalisation; the new
+  // basis size goes to *h_proj_count once the stream is synchronised.
+  void proj_append(int n) {
+    hipLaunchKernelGGL(k_proj_dots, dim3(nvblk, n + 1), dim3(VB), 0, stream, nf, n, (const double *)proj_x, nf,
+                       (const double *)q, (const double *)x, proj_part);
+    hipLaunchKernelGGL(k_proj_totals, dim3(n + 1), dim3(256), 0, stream, (const double *)proj_part, nvblk, proj_coef,
+                       nullptr);
+    hipLaunchKernelGGL(k_proj_orth, dim3(nvblk), dim3(VB), 0, stream, nf, n, (const double *)proj_coef, proj_x,
+                       proj_ax, nf, (const double *)x, (const double *)q, proj_part);
+    hipLaunchKernelGGL(k_proj_scale, dim3(nvblk), dim3(VB), 0, stream, nf, n, (const double *)proj_part, nvblk,
+                       (const double *)(proj_coef + n), proj_x, proj_ax, nf, proj_count);
+    HIPCHK(hipMemcpyAsync(h_proj_count, proj_count, sizeof(int), hipMemcpyDeviceToHost, stream));
   }
 
   void finish(double *u) {
@@ -371,6 +408,8 @@ struct coarse_ctx {
     st->status = h_sc->status;
     st->relres = h_sc->bb > 0 ? std::sqrt(h_sc->rr / h_sc->bb) : 0.0;
     st->relres_true = h_sc->bb > 0 ? std::sqrt(h_sc->res_true / h_sc->bb) : 0.0;
+    st->relres0 = h_sc->bb > 0 ? std::sqrt(h_sc->rr0 / h_sc->bb) : 0.0;
+    st->n_basis = 0;
     st->t_setup = t_setup;
     st->t_solve = now() - t0;
   }
@@ -541,6 +580,14 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
   c->prr = A.alloc<double>(npart);
   c->zero_flag = A.alloc<int>(1);
   HIPCHK(hipMemsetAsync(c->zero_flag, 0, sizeof(int), s));
+  if (c->proj_max > 0) {
+    c->proj_x = A.alloc<double>((size_t)c->proj_max * nf);
+    c->proj_ax = A.alloc<double>((size_t)c->proj_max * nf);
+    c->proj_part = A.alloc<double>((size_t)(c->proj_max + 1) * npart);
+    c->proj_coef = A.alloc<double>(c->proj_max + 1);
+    c->proj_count = A.alloc<int>(1);
+    HIPCHK(hipHostMalloc((void **)&c->h_proj_count, sizeof(int), hipHostMallocDefault));
+  }
 
   // packed vectors, systems, tiles
   c->n_local_sys = P.n_local_sys;
@@ -962,6 +1009,45 @@ struct coarse_batch {
   }
 };
 
+namespace {
+
+// PCG from u_0 = 0 (or, with `projected`, from the projection onto the stored
+// basis, which then takes in the new solution), with host convergence checks
+// every check_every queued iterations.
+int run_solve(coarse_ctx *c, const double *b, double *u, double tol, coarse_stats *st, bool projected) {
+  const double t0 = now();
+  const int nproj = projected ? c->proj_n : 0;
+  try {
+    c->start(b, tol, nproj);
+    int batch = std::max(c->check_every, c->last_iters);
+    for (;;) {
+      for (int j = 0; j < batch; ++j) c->iteration();
+      batch = c->check_every;
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(c->h_sc, c->sc, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      c->pcollect();
+      if (c->h_sc->done) break;
+    }
+    c->finish(u);
+    // a full basis starts again from the new solution alone
+    if (projected) c->proj_append(c->proj_n >= c->proj_max ? 0 : c->proj_n);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (projected) c->proj_n = *c->h_proj_count;
+  } catch (const Fail &f) {
+    return fail_ctx(c, f);
+  }
+  c->fill_stats(st, t0);
+  if (st) st->n_basis = nproj;
+  c->last_iters = c->h_sc->iters;
+  const int status = c->h_sc->status;
+  if (status == -6) c->err = "PCG breakdown (p.Ap <= 0 or non-finite value)";
+  if (status == 1) c->err = "iteration limit reached";
+  return status;
+}
+
+}  // namespace
+
 extern "C" {
 
 void coarse_default_opts(coarse_opts *o) {
@@ -975,6 +1061,7 @@ void coarse_default_opts(coarse_opts *o) {
   o->check_every = 4;
   o->flexible = 0;
   o->stream = nullptr;
+  o->projection = 0;
 }
 
 int coarse_plan_info(const coarse_mesh *mesh, const coarse_bc *bc, const coarse_opts *opts, coarse_info_t *info,
@@ -1021,6 +1108,10 @@ int coarse_plan_create(const coarse_mesh *mesh, const coarse_bc *bc, const coars
   }
   if (o.mode < 0 || o.mode > 3 || o.max_it < 1 || o.check_every < 1) {
     g_setup_error = "bad mode, max_it or check_every";
+    return COARSE_EINVAL;
+  }
+  if (o.projection < 0 || o.projection > COARSE_PROJECTION_MAX) {
+    g_setup_error = "projection must be in [0, COARSE_PROJECTION_MAX]";
     return COARSE_EINVAL;
   }
   try {
@@ -1079,6 +1170,7 @@ int coarse_setup_from_plan(const coarse_plan *plan, void *stream, coarse_ctx **o
   c->max_it = o.max_it;
   c->check_every = o.check_every;
   c->flexible = o.flexible ? 1 : 0;
+  c->proj_max = o.projection;
   try {
     HIPCHK(hipHostMalloc((void **)&c->h_sc, sizeof(Scalars), hipHostMallocDefault));
     if (o.precision == COARSE_FP64)
@@ -1131,30 +1223,22 @@ int coarse_apply_A(coarse_ctx *c, const double *p, double *q) {
 
 int coarse_solve(coarse_ctx *c, const double *b, double *u, double tol, coarse_stats *st) {
   if (!c || !b || !u || b == u || !(tol > 0)) return COARSE_EINVAL;
-  const double t0 = now();
-  try {
-    c->start(b, tol);
-    int batch = std::max(c->check_every, c->last_iters);
-    for (;;) {
-      for (int j = 0; j < batch; ++j) c->iteration();
-      batch = c->check_every;
-      HIPCHK(hipGetLastError());
-      HIPCHK(hipMemcpyAsync(c->h_sc, c->sc, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
-      HIPCHK(hipStreamSynchronize(c->stream));
-      c->pcollect();
-      if (c->h_sc->done) break;
-    }
-    c->finish(u);
-    HIPCHK(hipStreamSynchronize(c->stream));
-  } catch (const Fail &f) {
-    return fail_ctx(c, f);
+  return run_solve(c, b, u, tol, st, false);
+}
+
+int coarse_solve_projected(coarse_ctx *c, const double *b, double *u, double tol, coarse_stats *st) {
+  if (!c || !b || !u || b == u || !(tol > 0)) return COARSE_EINVAL;
+  if (c->proj_max <= 0) {
+    c->err = "the context was set up without a projection basis (opts.projection = 0)";
+    return COARSE_EINVAL;
   }
-  c->fill_stats(st, t0);
-  c->last_iters = c->h_sc->iters;
-  const int status = c->h_sc->status;
-  if (status == -6) c->err = "PCG breakdown (p.Ap <= 0 or non-finite value)";
-  if (status == 1) c->err = "iteration limit reached";
-  return status;
+  return run_solve(c, b, u, tol, st, true);
+}
+
+int coarse_projection_reset(coarse_ctx *c) {
+  if (!c) return COARSE_EINVAL;
+  c->proj_n = 0;
+  return COARSE_OK;
 }
 
 int coarse_solve_batch(coarse_ctx *const *ctxs, const double *const *b, double *const *u, int count, double tol,

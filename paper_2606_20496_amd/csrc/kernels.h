@@ -19,6 +19,7 @@ __host__ __device__ inline int64_t ae_at(int k, int64_t e) {
 // Solver scalars living in device memory (one per context).
 struct Scalars {
   double bb, rho[2], rr, pq, alpha, beta, tol2, res_true;
+  double rr0;      // ||r_0||^2 of the first convergence test
   int32_t iter;    // completed iterations (parity of the double buffers)
   int32_t iters;   // iterations reported when the solve ended
   int32_t done, status, max_it, flexible, pad0, pad1;

@@ -494,19 +494,26 @@ __global__ __launch_bounds__(VW) void k_update_fused(int64_t nf, OpDev op, Scala
 
 // Convergence test at the start of a preconditioner application inside PCG.
 // start = 1: the partials are those of ||b||^2 (b = 0 ends the solve at once);
+// start = 2: those of the initial residual, ended at once when it already meets
+// the tolerance;
 // otherwise of ||r_{k+1}||^2, tested against tol^2 ||b||^2 and the iteration cap.
 // Returns true when the solve is over (every workgroup reaches the same answer).
 __device__ bool pcg_check(Scalars *__restrict__ sc, const double *__restrict__ part, int n, int start, double *red) {
   const double s = block_total<256>(part, n, red);
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   if (start) {
-    const bool stop = !(s > 0.0) || !isfinite(s);
+    // start = 2 (initial guess by projection): the partials are those of
+    // ||b - A u_bar||^2 and ||b||^2 is already recorded
+    const double bb = (start == 2) ? sc->bb : s;
+    const bool bad = !isfinite(s) || !isfinite(bb);
+    const bool stop = bad || !(bb > 0.0) || (start == 2 && s <= sc->tol2 * bb);
     if (lead) {
-      sc->bb = s;
+      sc->bb = bb;
       sc->rr = s;
+      sc->rr0 = s;
       if (stop) {
         sc->done = 1;
-        sc->status = isfinite(s) ? 0 : -6;
+        sc->status = bad ? -6 : 0;
         sc->iters = 0;
       }
     }
@@ -538,6 +545,115 @@ __global__ __launch_bounds__(256) void k_check(Scalars *__restrict__ sc, const d
   __shared__ double red[256 / WAVE];
   if (sc->done) return;
   (void)pcg_check(sc, part, n, start, red);
+}
+
+// ---------------------------------------------------------------------------
+// Initial guess by projection onto prior solutions (Sec. 5). The basis
+// X_0 .. X_{n-1} is A-orthonormal and stored with AX_j = A X_j, row j at offset
+// j * ld. Every sum over the vector uses the fixed grid of the PCG vector kernels
+// followed by a fixed-order sum of the workgroup partials, so the basis and the
+// guesses are bitwise reproducible.
+// ---------------------------------------------------------------------------
+
+// part[j][blk] (row stride gridDim.x): workgroup partials of X_j . v for the rows
+// j = blockIdx.y < n, and of w . v for j = n when the grid has n + 1 rows.
+__global__ __launch_bounds__(VB) void k_proj_dots(int64_t nf, int n, const double *__restrict__ X, int64_t ld,
+                                                  const double *__restrict__ v, const double *__restrict__ w,
+                                                  double *__restrict__ part) {
+  __shared__ double red[VB / WAVE];
+  const int j = blockIdx.y;
+  const double *a = (j < n) ? X + (int64_t)j * ld : w;
+  double acc = 0.0;
+  const int64_t G = (int64_t)gridDim.x * VB;
+  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < nf; i += G) acc += a[i] * v[i];
+  const double s = block_sum<VB>(acc, red);
+  if (threadIdx.x == 0) part[(int64_t)j * gridDim.x + blockIdx.x] = s;
+}
+
+// out[j] = sum of row j of part (nblk entries, fixed order): one workgroup per
+// row. With sc given, the last workgroup records its total as ||b||^2.
+__global__ __launch_bounds__(256) void k_proj_totals(const double *__restrict__ part, int nblk,
+                                                     double *__restrict__ out, Scalars *__restrict__ sc) {
+  __shared__ double red[256 / WAVE];
+  const int j = blockIdx.x;
+  const double s = block_total<256>(part + (int64_t)j * nblk, nblk, red);
+  if (threadIdx.x == 0) {
+    if (sc && j == (int)gridDim.x - 1)
+      sc->bb = s;
+    else
+      out[j] = s;
+  }
+}
+
+// u_bar = sum_j c_j X_j into x, r_0 = r - sum_j c_j AX_j (r holds b), and the
+// partials of ||r_0||^2.
+__global__ __launch_bounds__(VB) void k_proj_guess(int64_t nf, int n, const double *__restrict__ c,
+                                                   const double *__restrict__ X, const double *__restrict__ AX,
+                                                   int64_t ld, double *__restrict__ x, double *__restrict__ r,
+                                                   double *__restrict__ part) {
+  __shared__ double red[VB / WAVE];
+  double acc = 0.0;
+  const int64_t G = (int64_t)gridDim.x * VB;
+  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < nf; i += G) {
+    double u = 0.0, ri = r[i];
+    for (int j = 0; j < n; ++j) {
+      const double cj = c[j];
+      u += cj * X[(int64_t)j * ld + i];
+      ri -= cj * AX[(int64_t)j * ld + i];
+    }
+    x[i] = u;
+    r[i] = ri;
+    acc += ri * ri;
+  }
+  const double s = block_sum<VB>(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// A-Gram-Schmidt of a new solution u (with q = A u) against the basis, with
+// e_j = X_j . (A u): w = u - sum_j e_j X_j into X_n, A w = q - sum_j e_j AX_j into
+// AX_n, and the partials of w . A w.
+__global__ __launch_bounds__(VB) void k_proj_orth(int64_t nf, int n, const double *__restrict__ e,
+                                                  double *__restrict__ X, double *__restrict__ AX, int64_t ld,
+                                                  const double *__restrict__ u, const double *__restrict__ q,
+                                                  double *__restrict__ part) {
+  __shared__ double red[VB / WAVE];
+  double acc = 0.0;
+  const int64_t G = (int64_t)gridDim.x * VB;
+  double *wn = X + (int64_t)n * ld, *awn = AX + (int64_t)n * ld;
+  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < nf; i += G) {
+    double w = u[i], aw = q[i];
+    for (int j = 0; j < n; ++j) {
+      const double ej = e[j];
+      w -= ej * X[(int64_t)j * ld + i];
+      aw -= ej * AX[(int64_t)j * ld + i];
+    }
+    wn[i] = w;
+    awn[i] = aw;
+    acc += w * aw;
+  }
+  const double s = block_sum<VB>(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// Normalise the new row n by 1/sqrt(w . A w), each workgroup forming that sum
+// itself from the nblk partials; the row is kept only when its A-norm exceeds
+// 1e-6 of that of u (uau = u . A u) and is finite. Workgroup 0 writes the new
+// basis size to *count.
+__global__ __launch_bounds__(VB) void k_proj_scale(int64_t nf, int n, const double *__restrict__ part, int nblk,
+                                                   const double *__restrict__ uau, double *__restrict__ X,
+                                                   double *__restrict__ AX, int64_t ld, int *__restrict__ count) {
+  __shared__ double red[VB / WAVE];
+  const double w2 = block_total<VB>(part, nblk, red);
+  const bool keep = isfinite(w2) && w2 > 1e-12 * (*uau);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *count = keep ? n + 1 : n;
+  if (!keep) return;
+  const double s = 1.0 / sqrt(w2);
+  double *wn = X + (int64_t)n * ld, *awn = AX + (int64_t)n * ld;
+  const int64_t G = (int64_t)gridDim.x * VB;
+  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < nf; i += G) {
+    wn[i] *= s;
+    awn[i] *= s;
+  }
 }
 
 // Restriction R_p r into the packed local vectors (workgroups [0, ng), grid-

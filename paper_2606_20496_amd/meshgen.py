@@ -287,6 +287,37 @@ def rhs_bumps(mesh: Mesh, seed: int, bumps: int = 20, noise: float = 1e-3) -> np
     return b
 
 
+def rhs_sequence(mesh: Mesh, seed: int, steps: int, dt: float = 0.005, bumps: int = 20,
+                 noise: float = 0.0) -> list:
+    """Right-hand sides at ``steps`` successive times t_m = m dt of a load that
+    changes smoothly in time, as a pressure equation sees it step after step:
+    ``bumps`` Gaussian bumps (width 0.05) whose centres start uniform in the
+    bounding box and move with fixed N(0, 1) velocities (in units of the box size
+    per unit time), with amplitudes a_k cos(w_k t + phi_k), a_k ~ N(0, 1),
+    w_k uniform in [1, 4], phi_k uniform in [0, 2 pi); plus fresh N(0, noise^2)
+    values at each step. Dirichlet entries 0."""
+    rng = np.random.default_rng(seed)
+    lo, hi = mesh.xyz.min(0), mesh.xyz.max(0)
+    c0 = lo + (hi - lo) * rng.random((bumps, 3))
+    vel = (hi - lo) * rng.standard_normal((bumps, 3))
+    amp = rng.standard_normal(bumps)
+    omega = rng.uniform(1.0, 4.0, bumps)
+    phase = rng.uniform(0.0, 2.0 * np.pi, bumps)
+    dmask = mesh.dirichlet.astype(bool)
+    out = []
+    for m in range(steps):
+        t = m * dt
+        b = np.zeros(mesh.n_vert)
+        for k in range(bumps):
+            c = c0[k] + vel[k] * t
+            b += amp[k] * np.cos(omega[k] * t + phase[k]) * np.exp(-((mesh.xyz - c) ** 2).sum(1) / (2.0 * 0.05 ** 2))
+        if noise > 0.0:
+            b += noise * rng.standard_normal(mesh.n_vert)
+        b[dmask] = 0.0
+        out.append(b)
+    return out
+
+
 def rhs_normal(mesh: Mesh, seed: int) -> np.ndarray:
     """A fresh i.i.d. N(0,1) RHS for ``mesh`` (0 on Dirichlet vertices)."""
     b = np.random.default_rng(seed).standard_normal(mesh.n_vert)
