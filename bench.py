@@ -132,14 +132,13 @@ def run_batch_workload(torch, coarse, mg, tol, reps=3):
             us = [torch.empty_like(b) for b in bs]
         stream.synchronize()
         bt = coarse.Batch(stream=stream, use_graph=True)
-        best = None
+        best, failed = None, 0
         for rep in range(reps + 1):
             t1 = time.perf_counter()
             for k, S in enumerate(solvers):
                 bt.submit(S, bs[k], us[k], tag=k, tol=tol)
-            n = 0
             while bt.live:
-                n += len(bt.step(2))
+                failed += sum(st["status"] != 0 for _, st in bt.step(2))
             stream.synchronize()
             dt = time.perf_counter() - t1
             if rep > 0:
@@ -147,14 +146,51 @@ def run_batch_workload(torch, coarse, mg, tol, reps=3):
         bt.close()
         t1 = time.perf_counter()
         for k, S in enumerate(solvers):
-            S.solve(bs[k], tol, out=us[k])
+            failed += S.solve(bs[k], tol, out=us[k])[1]["status"] != 0
         torch.cuda.synchronize()
         seq = time.perf_counter() - t1
         for S in solvers:
             S.close()
         out[prec] = {"batched_solves_per_s": round(len(meshes) / best, 2),
                      "one_at_a_time_solves_per_s": round(len(meshes) / seq, 2),
-                     "setup_s_total": round(t_setup, 3)}
+                     "setup_s_total": round(t_setup, 3), "failed": int(failed)}
+    return out
+
+
+def run_serving_resident(torch, coarse, mg, tol, rates=(250.0, 500.0, 1000.0, 2000.0), count=1024,
+                         precision="mixed"):
+    """Open-loop serving over resident contexts: the 64 batch meshes are set up
+    beforehand (both for the continuous-batching server, mixed precision, and for
+    the plain FP64 one-at-a-time path); requests arrive as a Poisson stream at
+    each rate, each for a uniformly drawn mesh with a fresh N(0,1) right-hand
+    side (uploaded from the host inside the loop). Latency is arrival to result."""
+    from paper_2606_20496_amd import serve
+    meshes = mg.batch_meshes(count=64)
+    srv = serve.Server(budget_bytes=200e9, precision=precision, use_graph=True, step_iters=2)
+    for k, m in enumerate(meshes):
+        srv.preload(k, m)
+    seq_cache = {k: coarse.CoarseSolver.from_mesh(m, precision="fp64") for k, m in enumerate(meshes)}
+    torch.cuda.synchronize()
+    out = {"meshes": len(meshes), "requests_per_rate": count, "precision": precision,
+           "resident_bytes": srv.used, "rates": {}}
+    # warm-up pass (graph capture, allocator) outside the measured runs
+    warm = serve.make_resident_requests(meshes, 4000.0, 128, seed=1)
+    srv.run(warm)
+    serve.serve_sequential(warm[:32], tol=tol, cache=seq_cache)
+    for rate in rates:
+        reqs = serve.make_resident_requests(meshes, rate, count, seed=int(rate))
+        rec, wall = srv.run(reqs)
+        served = serve.summarize(rec, wall)
+        rec2, wall2 = serve.serve_sequential(reqs, tol=tol, cache=seq_cache)
+        seq = serve.summarize(rec2, wall2)
+        keep = ("solves_per_s", "p50_ms", "p99_ms", "mean_iters", "max_relres_true", "failed")
+        out["rates"][str(int(rate))] = {"batched_" + precision: {k: served[k] for k in keep},
+                                        "one_at_a_time_fp64": {k: seq[k] for k in keep}}
+        _log(f"serving rate {rate}: batched {served['solves_per_s']:.0f}/s p99 {served['p99_ms']:.1f} ms; "
+             f"one-at-a-time {seq['solves_per_s']:.0f}/s p99 {seq['p99_ms']:.1f} ms")
+    srv.close()
+    for S in seq_cache.values():
+        S.close()
     return out
 
 
@@ -313,6 +349,8 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 128^3 annulus kernel measurements")
     ap.add_argument("--no-ablations", action="store_true", help="skip the preconditioner-part study")
     ap.add_argument("--no-warm-start", action="store_true", help="skip the successive right-hand-side study")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the open-loop serving study over resident contexts")
     ap.add_argument("--serving", action="store_true", help="also run a short serving-loop workload")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 1 GiB device copy (known bytes) to scale HBM counters")
@@ -374,6 +412,11 @@ def main():
         _log("ablations")
         ablations = run_ablations(torch, coarse, mesh, rhs[0], args.tol)
         _log(f"ablations: { {k: v['iters'] for k, v in ablations.items()} }")
+
+    resident = None
+    if not args.no_serving:
+        _log("serving over resident contexts")
+        resident = run_serving_resident(torch, coarse, mg, args.tol)
 
     warm = None
     if not args.no_warm_start:
@@ -438,6 +481,8 @@ def main():
         line["ablations"] = ablations
     if warm is not None:
         line["warm_start"] = warm
+    if resident is not None:
+        line["serving_resident"] = resident
     if serving is not None:
         line["serving_workload"] = serving
     print(json.dumps(line), flush=True)

@@ -334,29 +334,49 @@ struct coarse_ctx {
     pend(6);
   }
 
-  // The additive iteration split around the dense solves, for lock-step batches:
-  // front = operator, update, convergence test, R_p and J^T; back = overlap sum and
-  // prolongation. The batched GEMV + combine of all live solves goes in between.
-  template <typename T>
-  void front_t() {
-    op_update();
-    const int ng = pre_gather_blocks(), nt = pre_task_blocks();
-    hipLaunchKernelGGL(k_pre<T>, dim3(ng + nt), dim3(256), 0, stream, ng, coarse_vec_off, done_flag, sub_idx, r,
-                       (T *)rp, (int)ntask, jt_start, jc_vid, (const T *)jc_w, (const T *)jc_xi, nent, (T *)jt_part, sc,
-                       (const double *)prr, nvblk, 0);
-    corners<T>(done_flag);
-  }
-  void front() {
-    if (precision == COARSE_FP64)
-      front_t<double>();
-    else
-      front_t<float>();
-  }
-  void back() {
-    if (precision == COARSE_FP64)
-      final_step<double>(nullptr, true, true, z, r, part1, flexible ? part2 : nullptr, done_flag, true, 0);
-    else
-      final_step<float>(nullptr, true, true, z, r, part1, flexible ? part2 : nullptr, done_flag, true, 0);
+  // This context's per-iteration state for the grouped launches of a lock-step
+  // batch (the same arguments its own launches of op_update, k_pre, the J^T
+  // corners and k_final take in additive mode).
+  void fill_iter(IterDev &d) const {
+    d.op = op;
+    d.nf = nf;
+    d.n_pack = coarse_vec_off;
+    d.nent = nent;
+    d.n_r = n_r;
+    d.sc = sc;
+    d.x = x;
+    d.r = r;
+    d.pa = p;
+    d.pb = pb;
+    d.z = z;
+    d.q = q;
+    d.energy = energy;
+    d.part1 = part1;
+    d.part2 = part2;
+    d.prr = prr;
+    d.zp = zp;
+    d.yfull = yfull;
+    d.sub_idx = sub_idx;
+    d.jt_start = jt_start;
+    d.jc_vid = jc_vid;
+    d.jr_ptr = jr_ptr;
+    d.jr_src = jr_src;
+    d.cover_ptr = cover_ptr;
+    d.cover_pos = cover_pos;
+    d.jv_ptr = jv_ptr;
+    d.jv_base = jv_base;
+    d.rp = rp;
+    d.jt_part = jt_part;
+    d.jc_w = jc_w;
+    d.jc_xi = jc_xi;
+    d.jv_w = jv_w;
+    d.jv_xi = jv_xi;
+    d.nvblk = nvblk;
+    d.ng = pre_gather_blocks();
+    d.ntask = (int32_t)ntask;
+    d.bx1 = bx1;
+    d.bxy1 = bxy1;
+    d.flexible = flexible;
   }
 
   // nproj > 0: start from the projection of the solution onto the first nproj
@@ -830,11 +850,11 @@ PlanInput make_input(const coarse_mesh *mesh, const coarse_bc *bc, const coarse_
 // so its result is bitwise the same alone or in any mix.
 // ---------------------------------------------------------------------------
 struct coarse_batch {
-  static constexpr int NS = 4;
+  // grouped launches of one lock step: operator, update, restriction, J^T
+  // corners, overlap sum (the dense solves use the segment tables)
+  enum { G_OP, G_UPD, G_PRE, G_COR, G_FIN, NG };
   std::string err;
   hipStream_t main = nullptr;
-  hipStream_t side[NS] = {};
-  hipEvent_t ev_fork = nullptr, ev_mid = nullptr, ev_join[NS] = {};
   struct Entry {
     coarse_ctx *c;
     const double *b;
@@ -848,46 +868,38 @@ struct coarse_batch {
   bool dirty = true, use_graph = false;
   Seg *d_seg = nullptr;      // [2][cap]: item segments, then row segments
   Seg *h_seg = nullptr;      // pinned staging
+  IterDev *d_iter = nullptr, *h_iter = nullptr;   // [cap] per-solve state
+  int32_t *d_off = nullptr, *h_off = nullptr;     // [NG][cap + 1] workgroup offsets
   int cap = 0, n_items = 0, n_rows = 0;
+  int grid[NG] = {};
+  int op_lds = 0;
   hipGraphExec_t gexec = nullptr;
 
   void init(hipStream_t s, bool graph) {
     main = s;
     use_graph = graph && s != nullptr;   // the null stream cannot be captured
-    for (int k = 0; k < NS; ++k) {
-      HIPCHK(hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking));
-      HIPCHK(hipEventCreateWithFlags(&ev_join[k], hipEventDisableTiming));
-    }
-    HIPCHK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&ev_mid, hipEventDisableTiming));
   }
 
   ~coarse_batch() {
     if (main) (void)hipStreamSynchronize(main);
-    for (auto &e : live) {
-      (void)hipStreamSynchronize(e.c->stream);
-      e.c->stream = e.saved_stream;
-    }
+    for (auto &e : live) e.c->stream = e.saved_stream;
     if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (d_seg) (void)hipFree(d_seg);
-    if (h_seg) (void)hipHostFree(h_seg);
-    for (int k = 0; k < NS; ++k) {
-      if (side[k]) (void)hipStreamDestroy(side[k]);
-      if (ev_join[k]) (void)hipEventDestroy(ev_join[k]);
-    }
-    if (ev_fork) (void)hipEventDestroy(ev_fork);
-    if (ev_mid) (void)hipEventDestroy(ev_mid);
+    free_tables();
   }
 
-  void fork_sides(hipEvent_t ev) {
-    HIPCHK(hipEventRecord(ev, main));
-    for (int k = 0; k < NS; ++k) HIPCHK(hipStreamWaitEvent(side[k], ev, 0));
-  }
-  void join_sides() {
-    for (int k = 0; k < NS; ++k) {
-      HIPCHK(hipEventRecord(ev_join[k], side[k]));
-      HIPCHK(hipStreamWaitEvent(main, ev_join[k], 0));
-    }
+  void free_tables() {
+    if (d_seg) (void)hipFree(d_seg);
+    if (h_seg) (void)hipHostFree(h_seg);
+    if (d_iter) (void)hipFree(d_iter);
+    if (h_iter) (void)hipHostFree(h_iter);
+    if (d_off) (void)hipFree(d_off);
+    if (h_off) (void)hipHostFree(h_off);
+    d_seg = nullptr;
+    h_seg = nullptr;
+    d_iter = nullptr;
+    h_iter = nullptr;
+    d_off = nullptr;
+    h_off = nullptr;
   }
 
   int submit(coarse_ctx *c, const double *b, double *u, double tol, int64_t tag) {
@@ -907,34 +919,51 @@ struct coarse_batch {
     precision = c->precision;
     c->prof_mask = 0;   // no per-phase events inside lock steps (they may be captured)
     Entry e{c, b, u, tag, now(), c->stream};
-    c->stream = side[live.size() % NS];
-    fork_sides(ev_fork);   // inputs written on the main stream are visible
+    // every launch of a batched solve goes to the batch's stream, so the start
+    // is ordered before the lock steps (also when they are a replayed graph)
+    c->stream = main;
     c->start(b, 1.0 * tol);
     live.push_back(e);
     dirty = true;
     return COARSE_OK;
   }
 
-  void rebuild_segments() {
+  void rebuild_tables() {
     const int n = (int)live.size();
     if (n > cap) {
-      if (d_seg) HIPCHK(hipFree(d_seg));
-      if (h_seg) HIPCHK(hipHostFree(h_seg));
-      d_seg = nullptr;
-      h_seg = nullptr;
+      HIPCHK(hipStreamSynchronize(main));
+      free_tables();
       cap = std::max(2 * n, 16);
       HIPCHK(hipMalloc(&d_seg, 2 * cap * sizeof(Seg)));
       HIPCHK(hipHostMalloc((void **)&h_seg, 2 * cap * sizeof(Seg), hipHostMallocDefault));
+      HIPCHK(hipMalloc(&d_iter, cap * sizeof(IterDev)));
+      HIPCHK(hipHostMalloc((void **)&h_iter, cap * sizeof(IterDev), hipHostMallocDefault));
+      HIPCHK(hipMalloc(&d_off, NG * (cap + 1) * sizeof(int32_t)));
+      HIPCHK(hipHostMalloc((void **)&h_off, NG * (cap + 1) * sizeof(int32_t), hipHostMallocDefault));
     }
     n_items = n_rows = 0;
+    op_lds = 0;
+    for (int g = 0; g < NG; ++g) h_off[g * (cap + 1)] = 0;
     for (int k = 0; k < n; ++k) {
       coarse_ctx *c = live[k].c;
       h_seg[k] = Seg{c->items, c->rows, c->sysdev, c->done_flag, n_items, 0};
       h_seg[cap + k] = Seg{c->items, c->rows, c->sysdev, c->done_flag, n_rows, 0};
       n_items += c->items_total;
       n_rows += c->rows_total;
+      c->fill_iter(h_iter[k]);
+      const int64_t blocks[NG] = {c->op.n_blocks, c->nvblk, c->pre_gather_blocks() + c->pre_task_blocks(),
+                                  nblk(c->n_r, 4), c->nvblk};
+      for (int g = 0; g < NG; ++g) {
+        const int64_t next = h_off[g * (cap + 1) + k] + blocks[g];
+        if (next > INT32_MAX / 2) throw Fail(COARSE_EINVAL, "lock-step batch too large for one launch");
+        h_off[g * (cap + 1) + k + 1] = (int32_t)next;
+      }
+      op_lds = std::max(op_lds, (int)c->op.lds_bytes);
     }
+    for (int g = 0; g < NG; ++g) grid[g] = h_off[g * (cap + 1) + n];
     HIPCHK(hipMemcpyAsync(d_seg, h_seg, 2 * cap * sizeof(Seg), hipMemcpyHostToDevice, main));
+    HIPCHK(hipMemcpyAsync(d_iter, h_iter, n * sizeof(IterDev), hipMemcpyHostToDevice, main));
+    HIPCHK(hipMemcpyAsync(d_off, h_off, NG * (cap + 1) * sizeof(int32_t), hipMemcpyHostToDevice, main));
     if (gexec) {
       HIPCHK(hipGraphExecDestroy(gexec));
       gexec = nullptr;
@@ -942,34 +971,39 @@ struct coarse_batch {
     dirty = false;
   }
 
-  // one lock step of every live solve
-  void lock_step() {
+  // one lock step of every live solve: seven launches whatever the batch size
+  template <typename T>
+  void lock_step_t() {
     const int n = (int)live.size();
-    fork_sides(ev_fork);
-    for (auto &e : live) e.c->front();
-    join_sides();
+    const int32_t *off = d_off;
+    const int L = cap + 1;
+    hipLaunchKernelGGL(k_op_fused_grp, dim3(grid[G_OP]), dim3(OP_BLOCK), op_lds, main, (const IterDev *)d_iter, off, n);
+    hipLaunchKernelGGL(k_update_fused_grp, dim3(grid[G_UPD]), dim3(VW), 0, main, (const IterDev *)d_iter, off + L, n);
+    hipLaunchKernelGGL(k_pre_grp<T>, dim3(grid[G_PRE]), dim3(256), 0, main, (const IterDev *)d_iter, off + 2 * L, n);
+    hipLaunchKernelGGL(k_jt_corners_grp<T>, dim3(grid[G_COR]), dim3(256), 0, main, (const IterDev *)d_iter,
+                       off + 3 * L, n);
     const unsigned g = nblk(n_items, 4);
-    if (precision == COARSE_FP64) {
+    if (precision == COARSE_FP64)
       hipLaunchKernelGGL(k_gemv_f64, dim3(g), dim3(256), 0, main, (const Seg *)d_seg, n, n_items, (const int *)nullptr);
-      hipLaunchKernelGGL(k_combine<double>, dim3(nblk((int64_t)n_rows * TILE, 256)), dim3(256), 0, main,
-                         (const Seg *)(d_seg + cap), n, n_rows, (const int *)nullptr);
-    } else {
-      if (precision == COARSE_MIXED_F16)
-        hipLaunchKernelGGL(k_gemv_f16, dim3(g), dim3(256), 0, main, (const Seg *)d_seg, n, n_items, (const int *)nullptr);
-      else
-        hipLaunchKernelGGL(k_gemv_f32, dim3(g), dim3(256), 0, main, (const Seg *)d_seg, n, n_items, (const int *)nullptr);
-      hipLaunchKernelGGL(k_combine<float>, dim3(nblk((int64_t)n_rows * TILE, 256)), dim3(256), 0, main,
-                         (const Seg *)(d_seg + cap), n, n_rows, (const int *)nullptr);
-    }
-    fork_sides(ev_mid);
-    for (auto &e : live) e.c->back();
-    join_sides();
+    else if (precision == COARSE_MIXED_F16)
+      hipLaunchKernelGGL(k_gemv_f16, dim3(g), dim3(256), 0, main, (const Seg *)d_seg, n, n_items, (const int *)nullptr);
+    else
+      hipLaunchKernelGGL(k_gemv_f32, dim3(g), dim3(256), 0, main, (const Seg *)d_seg, n, n_items, (const int *)nullptr);
+    hipLaunchKernelGGL(k_combine<T>, dim3(nblk((int64_t)n_rows * TILE, 256)), dim3(256), 0, main,
+                       (const Seg *)(d_seg + cap), n, n_rows, (const int *)nullptr);
+    hipLaunchKernelGGL(k_final_grp<T>, dim3(grid[G_FIN]), dim3(VW), 0, main, (const IterDev *)d_iter, off + 4 * L, n);
+  }
+  void lock_step() {
+    if (precision == COARSE_FP64)
+      lock_step_t<double>();
+    else
+      lock_step_t<float>();
   }
 
   int step(int iters, int64_t *tags, coarse_stats *stats, int capn, int *n_done) {
     *n_done = 0;
     if (live.empty()) return COARSE_OK;
-    if (dirty) rebuild_segments();
+    if (dirty) rebuild_tables();
     if (use_graph) {
       if (!gexec) {
         hipGraph_t graph;
@@ -986,23 +1020,21 @@ struct coarse_batch {
     HIPCHK(hipGetLastError());
     for (auto &e : live) HIPCHK(hipMemcpyAsync(e.c->h_sc, e.c->sc, sizeof(Scalars), hipMemcpyDeviceToHost, main));
     HIPCHK(hipStreamSynchronize(main));
+    // retire at most capn finished solves; any others stay (their iterations are
+    // skipped on the device) and are retired by a later step
     std::vector<Entry> keep;
     std::vector<Entry> fin;
-    for (auto &e : live) (e.c->h_sc->done ? fin : keep).push_back(e);
+    for (auto &e : live) ((e.c->h_sc->done && (int)fin.size() < capn) ? fin : keep).push_back(e);
     if (fin.empty()) return COARSE_OK;
     for (auto &e : fin) e.c->finish(e.u);
+    HIPCHK(hipStreamSynchronize(main));
     for (auto &e : fin) {
-      HIPCHK(hipStreamSynchronize(e.c->stream));
       e.c->last_iters = e.c->h_sc->iters;
-      if (*n_done < capn) {
-        if (tags) tags[*n_done] = e.tag;
-        if (stats) e.c->fill_stats(&stats[*n_done], e.t0);
-        ++*n_done;
-      }
+      if (tags) tags[*n_done] = e.tag;
+      if (stats) e.c->fill_stats(&stats[*n_done], e.t0);
+      ++*n_done;
       e.c->stream = e.saved_stream;
     }
-    // finished solves' outputs were written on side streams: order them before main
-    join_sides();
     live.swap(keep);
     dirty = true;
     return COARSE_OK;

@@ -77,4 +77,22 @@ struct OpDev {
   int32_t lds_bytes;
 };
 
+// The per-iteration state of one solve, for launches that cover every solve of
+// a lock-step batch (T-typed arrays are float or double by the batch precision).
+struct IterDev {
+  OpDev op;
+  int64_t nf;        // free vertices
+  int64_t n_pack;    // packed local entries; the reduced system's entries follow
+  int64_t nent, n_r;
+  Scalars *sc;
+  double *x, *r, *pa, *pb, *z, *q, *energy, *part1, *part2, *prr;
+  const double *zp, *yfull;
+  const int32_t *sub_idx, *jt_start, *jc_vid, *jr_ptr, *jr_src, *cover_ptr, *cover_pos, *jv_ptr, *jv_base;
+  void *rp, *jt_part;
+  const void *jc_w, *jc_xi, *jv_w, *jv_xi;
+  int32_t nvblk;     // grid of the per-vertex kernels = number of their partials
+  int32_t ng;        // gather workgroups of the restriction kernel
+  int32_t ntask, bx1, bxy1, flexible;
+};
+
 }  // namespace coarse

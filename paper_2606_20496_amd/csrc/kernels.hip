@@ -372,15 +372,16 @@ __global__ __launch_bounds__(VB) void k_start(int64_t nf, const int32_t *__restr
 // application, p_k = z_k + beta_{k-1} p_{k-1} formed while the block's vertex
 // values are staged (p_0 = z_0), written once per vertex by its designated block,
 // then q = A p_k as in k_op_pass1 with per-workgroup partials of p.Ap.
-__global__ __launch_bounds__(OP_BLOCK) void k_op_fused(OpDev op, const double *__restrict__ z, double *__restrict__ pa,
-                                                       double *__restrict__ pb, double *__restrict__ q,
-                                                       double *__restrict__ energy, Scalars *__restrict__ sc,
-                                                       const double *__restrict__ rz1, const double *__restrict__ rz2,
-                                                       int nrz) {
-  extern __shared__ double lds[];
-  __shared__ double red[OP_BLOCK / WAVE];
+// The kernels of one PCG iteration are written as bodies that take their
+// workgroup index (blk) and, where they loop over the grid, the grid size (nblk)
+// explicitly, so that a launch covering several solves (a lock-step batch) runs
+// each workgroup exactly as the solo launch of its own solve would.
+__device__ __forceinline__ void op_fused_body(OpDev op, const double *__restrict__ z, double *__restrict__ pa,
+                                              double *__restrict__ pb, double *__restrict__ q,
+                                              double *__restrict__ energy, Scalars *__restrict__ sc,
+                                              const double *__restrict__ rz1, const double *__restrict__ rz2, int nrz,
+                                              int blk, double *lds, double *red) {
   if (sc->done) return;
-  const int blk = blockIdx.x;
   const int64_t e = (int64_t)blk * OP_BLOCK + threadIdx.x;
   double m[36];
   uint4 c = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
@@ -393,14 +394,14 @@ __global__ __launch_bounds__(OP_BLOCK) void k_op_fused(OpDev op, const double *_
     beta = num / sc->rho[(it - 1) & 1];
   }
   if (!isfinite(rho) || !isfinite(beta)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blk == 0 && threadIdx.x == 0) {
       sc->done = 1;
       sc->status = -6;
       sc->iters = it;
     }
     return;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (blk == 0 && threadIdx.x == 0) {
     sc->rho[it & 1] = rho;
     sc->beta = beta;
   }
@@ -436,21 +437,30 @@ __global__ __launch_bounds__(OP_BLOCK) void k_op_fused(OpDev op, const double *_
   if (threadIdx.x == 0) energy[blk] = tot;
 }
 
+__global__ __launch_bounds__(OP_BLOCK) void k_op_fused(OpDev op, const double *__restrict__ z, double *__restrict__ pa,
+                                                       double *__restrict__ pb, double *__restrict__ q,
+                                                       double *__restrict__ energy, Scalars *__restrict__ sc,
+                                                       const double *__restrict__ rz1, const double *__restrict__ rz2,
+                                                       int nrz) {
+  extern __shared__ double lds[];
+  __shared__ double red[OP_BLOCK / WAVE];
+  op_fused_body(op, z, pa, pb, q, energy, sc, rz1, rz2, nrz, blockIdx.x, lds, red);
+}
+
 // alpha = rho / p.Ap (from the operator's partials), x += alpha p,
 // r -= alpha q (q of vertices shared between operator blocks is summed here from
 // the operator's partials), and partials of ||r||^2.
-__global__ __launch_bounds__(VW) void k_update_fused(int64_t nf, OpDev op, Scalars *__restrict__ sc, double *__restrict__ x,
-                                                     double *__restrict__ r, const double *__restrict__ pa,
-                                                     const double *__restrict__ pb, const double *__restrict__ q,
-                                                     const double *__restrict__ energy, int nen,
-                                                     double *__restrict__ part) {
-  __shared__ double red[VW / WAVE];
+__device__ __forceinline__ void update_fused_body(int64_t nf, OpDev op, Scalars *__restrict__ sc,
+                                                  double *__restrict__ x, double *__restrict__ r,
+                                                  const double *__restrict__ pa, const double *__restrict__ pb,
+                                                  const double *__restrict__ q, const double *__restrict__ energy,
+                                                  int nen, double *__restrict__ part, int blk, int nblk, double *red) {
   if (sc->done) return;
   const int it = sc->iter;
   const double pq = block_total<VW>(energy, nen, red);
   const double rho = sc->rho[it & 1];
   if (!(pq > 0.0) || !isfinite(pq)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blk == 0 && threadIdx.x == 0) {
       sc->pq = pq;
       sc->done = 1;
       sc->status = -6;
@@ -459,14 +469,14 @@ __global__ __launch_bounds__(VW) void k_update_fused(int64_t nf, OpDev op, Scala
     return;
   }
   const double alpha = rho / pq;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (blk == 0 && threadIdx.x == 0) {
     sc->pq = pq;
     sc->alpha = alpha;
   }
   const double *p = (it & 1) ? pb : pa;
   double acc = 0.0;
-  const int64_t G = (int64_t)gridDim.x * VW;
-  for (int64_t i = blockIdx.x * (int64_t)VW + threadIdx.x; i < nf; i += G) {
+  const int64_t G = (int64_t)nblk * VW;
+  for (int64_t i = blk * (int64_t)VW + threadIdx.x; i < nf; i += G) {
     const int2 vq = op.vq[i];
     double qi;
     if (vq.y == 0) {
@@ -489,7 +499,16 @@ __global__ __launch_bounds__(VW) void k_update_fused(int64_t nf, OpDev op, Scala
     acc += ri * ri;
   }
   const double s = block_sum<VW>(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
+  if (threadIdx.x == 0) part[blk] = s;
+}
+
+__global__ __launch_bounds__(VW) void k_update_fused(int64_t nf, OpDev op, Scalars *__restrict__ sc, double *__restrict__ x,
+                                                     double *__restrict__ r, const double *__restrict__ pa,
+                                                     const double *__restrict__ pb, const double *__restrict__ q,
+                                                     const double *__restrict__ energy, int nen,
+                                                     double *__restrict__ part) {
+  __shared__ double red[VW / WAVE];
+  update_fused_body(nf, op, sc, x, r, pa, pb, q, energy, nen, part, blockIdx.x, gridDim.x, red);
 }
 
 // Convergence test at the start of a preconditioner application inside PCG.
@@ -498,9 +517,10 @@ __global__ __launch_bounds__(VW) void k_update_fused(int64_t nf, OpDev op, Scala
 // the tolerance;
 // otherwise of ||r_{k+1}||^2, tested against tol^2 ||b||^2 and the iteration cap.
 // Returns true when the solve is over (every workgroup reaches the same answer).
-__device__ bool pcg_check(Scalars *__restrict__ sc, const double *__restrict__ part, int n, int start, double *red) {
+__device__ bool pcg_check(Scalars *__restrict__ sc, const double *__restrict__ part, int n, int start, double *red,
+                          int blk) {
   const double s = block_total<256>(part, n, red);
-  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  const bool lead = blk == 0 && threadIdx.x == 0;
   if (start) {
     // start = 2 (initial guess by projection): the partials are those of
     // ||b - A u_bar||^2 and ||b||^2 is already recorded
@@ -544,7 +564,7 @@ __global__ __launch_bounds__(256) void k_check(Scalars *__restrict__ sc, const d
                                                int start) {
   __shared__ double red[256 / WAVE];
   if (sc->done) return;
-  (void)pcg_check(sc, part, n, start, red);
+  (void)pcg_check(sc, part, n, start, red, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -699,19 +719,19 @@ __device__ __forceinline__ void jt_task(int task, const int32_t *__restrict__ ts
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_pre(int ng, int64_t n, const int *__restrict__ done, const int32_t *__restrict__ idx,
-                                             const double *__restrict__ in, T *__restrict__ rp, int ntask,
-                                             const int32_t *__restrict__ tstart, const int32_t *__restrict__ vid,
-                                             const T *__restrict__ w, const T *__restrict__ xi, int64_t nent,
-                                             T *__restrict__ tpart, Scalars *__restrict__ sc,
-                                             const double *__restrict__ chk, int nchk, int start) {
-  __shared__ double red[256 / WAVE];
+__device__ __forceinline__ void pre_body(int ng, int64_t n, const int *__restrict__ done,
+                                         const int32_t *__restrict__ idx, const double *__restrict__ in,
+                                         T *__restrict__ rp, int ntask, const int32_t *__restrict__ tstart,
+                                         const int32_t *__restrict__ vid, const T *__restrict__ w,
+                                         const T *__restrict__ xi, int64_t nent, T *__restrict__ tpart,
+                                         Scalars *__restrict__ sc, const double *__restrict__ chk, int nchk, int start,
+                                         int blk, int nblk, double *red) {
   if (*done) return;
-  if (sc && pcg_check(sc, chk, nchk, start, red)) return;
-  if ((int)blockIdx.x < ng) {
+  if (sc && pcg_check(sc, chk, nchk, start, red, blk)) return;
+  if (blk < ng) {
     // UV entries per thread and step, index and value loads issued together
     const int64_t G = (int64_t)ng * 256;
-    for (int64_t j0 = blockIdx.x * (int64_t)256 + threadIdx.x; j0 < n; j0 += G * UV) {
+    for (int64_t j0 = blk * (int64_t)256 + threadIdx.x; j0 < n; j0 += G * UV) {
       int32_t ii[UV];
 #pragma unroll
       for (int u = 0; u < UV; ++u) ii[u] = (j0 + u * G < n) ? idx[j0 + u * G] : -1;
@@ -724,9 +744,21 @@ __global__ __launch_bounds__(256) void k_pre(int ng, int64_t n, const int *__res
     }
     return;
   }
-  const int nw = ((int)gridDim.x - ng) * 4;
-  for (int task = (blockIdx.x - ng) * 4 + (threadIdx.x >> 6); task < ntask; task += nw)
+  const int nw = (nblk - ng) * 4;
+  for (int task = (blk - ng) * 4 + (threadIdx.x >> 6); task < ntask; task += nw)
     jt_task<T>(task, tstart, vid, w, xi, nent, in, tpart);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_pre(int ng, int64_t n, const int *__restrict__ done, const int32_t *__restrict__ idx,
+                                             const double *__restrict__ in, T *__restrict__ rp, int ntask,
+                                             const int32_t *__restrict__ tstart, const int32_t *__restrict__ vid,
+                                             const T *__restrict__ w, const T *__restrict__ xi, int64_t nent,
+                                             T *__restrict__ tpart, Scalars *__restrict__ sc,
+                                             const double *__restrict__ chk, int nchk, int start) {
+  __shared__ double red[256 / WAVE];
+  pre_body<T>(ng, n, done, idx, in, rp, ntask, tstart, vid, w, xi, nent, tpart, sc, chk, nchk, start, blockIdx.x,
+              gridDim.x, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -764,17 +796,24 @@ __global__ __launch_bounds__(256) void k_jt_tasks(int ntask, const int *__restri
 // Second stage of J^T: one wavefront per active box vertex sums the task
 // partials of the occupied cells around it (lane-strided, then across the wave).
 template <typename T>
-__global__ __launch_bounds__(256) void k_jt_corners(int64_t nr, const int *__restrict__ done, const int32_t *__restrict__ ptr,
-                                                    const int32_t *__restrict__ src, const T *__restrict__ tpart,
-                                                    T *__restrict__ rr) {
+__device__ __forceinline__ void corners_body(int64_t nr, const int *__restrict__ done, const int32_t *__restrict__ ptr,
+                                             const int32_t *__restrict__ src, const T *__restrict__ tpart,
+                                             T *__restrict__ rr, int blk) {
   if (*done) return;
   const int lane = threadIdx.x & 63;
-  const int64_t K = blockIdx.x * (int64_t)4 + (threadIdx.x >> 6);
+  const int64_t K = blk * (int64_t)4 + (threadIdx.x >> 6);
   if (K >= nr) return;
   T acc = T(0);
   for (int k = ptr[K] + lane; k < ptr[K + 1]; k += 64) acc += tpart[src[k]];
   acc = wave_sum(acc);
   if (lane == 0) rr[K] = acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_jt_corners(int64_t nr, const int *__restrict__ done, const int32_t *__restrict__ ptr,
+                                                    const int32_t *__restrict__ src, const T *__restrict__ tpart,
+                                                    T *__restrict__ rr) {
+  corners_body<T>(nr, done, ptr, src, tpart, rr, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1104,19 +1143,19 @@ __global__ __launch_bounds__(256) void k_combine(const Seg *__restrict__ segs, i
 // plus partial sums of r.out and r.out_old for the PCG beta.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(VW) void k_final(int64_t nf, const int *__restrict__ done, const double *__restrict__ add,
-                                              const int32_t *__restrict__ cover_ptr, const int32_t *__restrict__ cover_pos,
-                                              const double *__restrict__ zp, const int32_t *__restrict__ jv_ptr,
-                                              const int32_t *__restrict__ jv_base, const T *__restrict__ jv_w,
-                                              const T *__restrict__ jv_xi, int64_t nent, int bx1, int bxy1,
-                                              const double *__restrict__ yfull, double *__restrict__ out,
-                                              const double *__restrict__ rdot, double *__restrict__ part1,
-                                              double *__restrict__ part2, Scalars *__restrict__ sc, int start) {
-  __shared__ double red[VW / WAVE];
+__device__ __forceinline__ void final_body(int64_t nf, const int *__restrict__ done, const double *__restrict__ add,
+                                           const int32_t *__restrict__ cover_ptr,
+                                           const int32_t *__restrict__ cover_pos, const double *__restrict__ zp,
+                                           const int32_t *__restrict__ jv_ptr, const int32_t *__restrict__ jv_base,
+                                           const T *__restrict__ jv_w, const T *__restrict__ jv_xi, int64_t nent,
+                                           int bx1, int bxy1, const double *__restrict__ yfull,
+                                           double *__restrict__ out, const double *__restrict__ rdot,
+                                           double *__restrict__ part1, double *__restrict__ part2,
+                                           Scalars *__restrict__ sc, int start, int blk, int nblk, double *red) {
   if (*done) return;
   double d1 = 0.0, d2 = 0.0;
-  const int64_t G = (int64_t)gridDim.x * VW;
-  for (int64_t i = blockIdx.x * (int64_t)VW + threadIdx.x; i < nf; i += G) {
+  const int64_t G = (int64_t)nblk * VW;
+  for (int64_t i = blk * (int64_t)VW + threadIdx.x; i < nf; i += G) {
     double acc = add ? add[i] : 0.0;
     if (cover_ptr) {
       // local solutions covering vertex i, loads issued eight at a time, summed in order
@@ -1159,14 +1198,96 @@ __global__ __launch_bounds__(VW) void k_final(int64_t nf, const int *__restrict_
   }
   if (rdot) {
     const double s1 = block_sum<VW>(d1, red);
-    if (threadIdx.x == 0) part1[blockIdx.x] = s1;
+    if (threadIdx.x == 0) part1[blk] = s1;
     if (part2) {
       const double s2 = block_sum<VW>(d2, red);
-      if (threadIdx.x == 0) part2[blockIdx.x] = s2;
+      if (threadIdx.x == 0) part2[blk] = s2;
     }
     // one completed iteration (not for the first application)
-    if (sc && !start && blockIdx.x == 0 && threadIdx.x == 0) sc->iter = sc->iter + 1;
+    if (sc && !start && blk == 0 && threadIdx.x == 0) sc->iter = sc->iter + 1;
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(VW) void k_final(int64_t nf, const int *__restrict__ done, const double *__restrict__ add,
+                                              const int32_t *__restrict__ cover_ptr, const int32_t *__restrict__ cover_pos,
+                                              const double *__restrict__ zp, const int32_t *__restrict__ jv_ptr,
+                                              const int32_t *__restrict__ jv_base, const T *__restrict__ jv_w,
+                                              const T *__restrict__ jv_xi, int64_t nent, int bx1, int bxy1,
+                                              const double *__restrict__ yfull, double *__restrict__ out,
+                                              const double *__restrict__ rdot, double *__restrict__ part1,
+                                              double *__restrict__ part2, Scalars *__restrict__ sc, int start) {
+  __shared__ double red[VW / WAVE];
+  final_body<T>(nf, done, add, cover_ptr, cover_pos, zp, jv_ptr, jv_base, jv_w, jv_xi, nent, bx1, bxy1, yfull, out,
+                rdot, part1, part2, sc, start, blockIdx.x, gridDim.x, red);
+}
+
+// ---------------------------------------------------------------------------
+// One PCG iteration of every solve of a lock-step batch in one launch per step:
+// workgroup g of a grouped launch belongs to the solve c with
+// off[c] <= g < off[c + 1] and runs as workgroup g - off[c] of that solve's own
+// launch (same grid per solve, same partial sums, so each result is bitwise the
+// solo one). The dense solves of the batch are already one launch (k_gemv_*).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int find_ctx(const int32_t *__restrict__ off, int n, int g) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= g)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(OP_BLOCK) void k_op_fused_grp(const IterDev *__restrict__ ctx,
+                                                           const int32_t *__restrict__ off, int n) {
+  extern __shared__ double lds[];
+  __shared__ double red[OP_BLOCK / WAVE];
+  const int c = find_ctx(off, n, blockIdx.x);
+  const IterDev &d = ctx[c];
+  op_fused_body(d.op, d.z, d.pa, d.pb, d.q, d.energy, d.sc, d.part1, d.part2, d.nvblk, blockIdx.x - off[c], lds, red);
+}
+
+__global__ __launch_bounds__(VW) void k_update_fused_grp(const IterDev *__restrict__ ctx,
+                                                         const int32_t *__restrict__ off, int n) {
+  __shared__ double red[VW / WAVE];
+  const int c = find_ctx(off, n, blockIdx.x);
+  const IterDev &d = ctx[c];
+  update_fused_body(d.nf, d.op, d.sc, d.x, d.r, d.pa, d.pb, d.q, d.energy, (int)d.op.n_blocks, d.prr,
+                    blockIdx.x - off[c], off[c + 1] - off[c], red);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_pre_grp(const IterDev *__restrict__ ctx, const int32_t *__restrict__ off,
+                                                 int n) {
+  __shared__ double red[256 / WAVE];
+  const int c = find_ctx(off, n, blockIdx.x);
+  const IterDev &d = ctx[c];
+  pre_body<T>(d.ng, d.n_pack, &d.sc->done, d.sub_idx, d.r, (T *)d.rp, d.ntask, d.jt_start, d.jc_vid,
+              (const T *)d.jc_w, (const T *)d.jc_xi, d.nent, (T *)d.jt_part, d.sc, d.prr, d.nvblk, 0,
+              blockIdx.x - off[c], off[c + 1] - off[c], red);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_jt_corners_grp(const IterDev *__restrict__ ctx,
+                                                        const int32_t *__restrict__ off, int n) {
+  const int c = find_ctx(off, n, blockIdx.x);
+  const IterDev &d = ctx[c];
+  corners_body<T>(d.n_r, &d.sc->done, d.jr_ptr, d.jr_src, (const T *)d.jt_part, (T *)d.rp + d.n_pack,
+                  blockIdx.x - off[c]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(VW) void k_final_grp(const IterDev *__restrict__ ctx, const int32_t *__restrict__ off,
+                                                  int n) {
+  __shared__ double red[VW / WAVE];
+  const int c = find_ctx(off, n, blockIdx.x);
+  const IterDev &d = ctx[c];
+  final_body<T>(d.nf, &d.sc->done, nullptr, d.cover_ptr, d.cover_pos, d.zp, d.jv_ptr, d.jv_base,
+                (const T *)d.jv_w, (const T *)d.jv_xi, d.nent, d.bx1, d.bxy1, d.yfull, d.z, d.r, d.part1,
+                d.flexible ? d.part2 : nullptr, d.sc, 0, blockIdx.x - off[c], off[c + 1] - off[c], red);
 }
 
 // ---------------------------------------------------------------------------

@@ -272,6 +272,16 @@ def serving_arrivals(rate, count=4096, seed=59999, reuse=0.3):
     return t, mesh_id, rhs_seed
 
 
+def resident_arrivals(rate, count, n_keys, seed=58999):
+    """Poisson arrival times at ``rate`` requests/s over ``n_keys`` meshes that are
+    all resident: per request, its mesh drawn uniformly and the seed of its RHS."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=count))
+    key = rng.integers(0, n_keys, size=count)
+    rhs_seed = rng.integers(0, 2 ** 31 - 1, size=count)
+    return t, key, rhs_seed
+
+
 def rhs_bumps(mesh: Mesh, seed: int, bumps: int = 20, noise: float = 1e-3) -> np.ndarray:
     """A fresh RHS of ``bumps`` Gaussian bumps (width 0.05, centres uniform in the
     bounding box, amplitudes N(0,1)) plus N(0, noise^2) values (0 on Dirichlet)."""

@@ -71,7 +71,7 @@ def summarize(records, wall):
 
 class Server:
     def __init__(self, budget_bytes, precision="mixed", use_graph=True, step_iters=2, tol=1e-8,
-                 plan_workers=2, solver_kw=None, keep_outputs=False):
+                 plan_workers=2, solver_kw=None, keep_outputs=False, adaptive_steps=True):
         import torch
         self.torch = torch
         self.budget = int(budget_bytes)
@@ -90,6 +90,8 @@ class Server:
         self.max_plans = 2 * plan_workers        # plans held on the host at once
         self.used = 0
         self.keep_outputs = keep_outputs
+        self.last_iters = {}                     # key -> iterations of its last solve
+        self.adaptive_steps = adaptive_steps
 
     def _plan(self, mesh):
         return coarse.Plan.from_mesh(mesh, precision=self.precision, **self.solver_kw)
@@ -98,6 +100,16 @@ class Server:
         with self.torch.cuda.stream(self.setup_stream):
             S = coarse.CoarseSolver.from_plan(plan)
         self.setup_stream.synchronize()
+        return S
+
+    def preload(self, key, mesh):
+        """Set up `mesh` now (both halves, on the calling thread) and keep its
+        context resident under `key`, as if an earlier request had brought it in."""
+        plan = self._plan(mesh)
+        S = self._device_setup(plan)
+        plan.close()
+        self.cache[key] = S
+        self.used += S.device_bytes
         return S
 
     def _evict_for(self, need, keep=()):
@@ -154,7 +166,7 @@ class Server:
                         u = torch.empty_like(b)
                     self.batch.submit(S, b, u, tag=rq.rid, tol=self.tol)
                     self.busy.add(rq.key)
-                    live[rq.rid] = (rq, u, b)
+                    live[rq.rid] = [rq, u, b, 0]
                 else:
                     keep.append(rq)
             waiting = keep
@@ -179,9 +191,18 @@ class Server:
                 self.planning[rq.key] = self.pool.submit(lambda m=rq.mesh, n=need: (self._plan(m), n))
                 missed.add(rq.rid)
             if live:
-                for tag, st in self.batch.step(self.step_iters):
-                    rq, u, b = live.pop(tag)
+                # as many iterations per lock step as the live solve expected to
+                # finish first still needs (its mesh's last count), at least
+                # step_iters: fewer host round trips when few solves are live
+                k = self.step_iters
+                if self.adaptive_steps:
+                    k = max(k, min(self.last_iters.get(e[0].key, 0) - e[3] for e in live.values()))
+                for e in live.values():
+                    e[3] += k
+                for tag, st in self.batch.step(k):
+                    rq, u, b, _ = live.pop(tag)
                     self.busy.discard(rq.key)
+                    self.last_iters[rq.key] = st["iters"]
                     records.append(Record(rid=rq.rid, key=rq.key, t_arrive=rq.t_arrive, t_done=now(),
                                           iters=st["iters"], relres_true=st["relres_true"],
                                           setup=rq.rid in missed, status=st["status"],
@@ -202,11 +223,13 @@ class Server:
         self.cache.clear()
 
 
-def serve_sequential(requests, precision="fp64", tol=1e-8, solver_kw=None):
+def serve_sequential(requests, precision="fp64", tol=1e-8, solver_kw=None, cache=None):
     """The plain one-at-a-time path: arrival order, one solve at a time, contexts
-    cached by mesh key, setup in line."""
+    cached by mesh key, setup in line. `cache` (key -> CoarseSolver) may hold
+    contexts set up beforehand; the caller keeps ownership of those."""
     import torch
-    cache = {}
+    cache = {} if cache is None else dict(cache)
+    given = set(cache)
     records = []
     t0 = time.perf_counter()
     for rq in sorted(requests, key=lambda r: r.t_arrive):
@@ -222,8 +245,9 @@ def serve_sequential(requests, precision="fp64", tol=1e-8, solver_kw=None):
                               iters=st["iters"], relres_true=st["relres_true"], setup=miss,
                               status=st["status"]))
     wall = time.perf_counter() - t0
-    for S in cache.values():
-        S.close()
+    for key, S in cache.items():
+        if key not in given:
+            S.close()
     return records, wall
 
 
@@ -242,6 +266,15 @@ def make_requests(rate, count, seed=59999, nmax=96, reuse=0.3):
         m = meshes[k]
         out.append(Request(t_arrive=float(t[q]), key=k, mesh=m, b=mg.rhs_normal(m, int(rhs_seed[q])), rid=q))
     return out
+
+
+def make_resident_requests(meshes, rate, count, seed=58999):
+    """Poisson arrivals at `rate` over the given meshes (all set up beforehand),
+    each request with its mesh drawn uniformly and a fresh N(0,1) right-hand side."""
+    from . import meshgen as mg
+    t, key, rhs_seed = mg.resident_arrivals(rate, count, len(meshes), seed=seed)
+    return [Request(t_arrive=float(t[q]), key=int(key[q]), mesh=meshes[int(key[q])],
+                    b=mg.rhs_normal(meshes[int(key[q])], int(rhs_seed[q])), rid=q) for q in range(count)]
 
 
 def main():

@@ -86,3 +86,44 @@ def test_gemv_work_item_table_changes_rounding_only():
             assert float((z - ref[0]).abs().max() / ref[0].abs().max()) < 1e-13
             assert st["iters"] == ref[1]
         S.close()
+
+
+def test_resident_serving_equals_solo_and_sequential():
+    # contexts set up beforehand: an open-loop stream over them needs no setup,
+    # and every result equals a solo solve of the same context, bit for bit; the
+    # one-at-a-time path on the same contexts gives the same results
+    from paper_2606_20496_amd import meshgen as mg
+    meshes = mg.batch_meshes(count=6, nmax=14)
+    reqs = serve.make_resident_requests(meshes, rate=2000.0, count=20, seed=3)
+    srv = serve.Server(budget_bytes=8e9, precision="mixed", use_graph=True, step_iters=2, keep_outputs=True)
+    solvers = {k: srv.preload(k, m) for k, m in enumerate(meshes)}
+    records, wall = srv.run(reqs)
+    assert len(records) == 20 and not any(r.setup for r in records)
+    assert all(r.status == 0 for r in records)
+    by_id = {r.rid: r for r in records}
+    for rq in reqs:
+        u, st = solvers[rq.key].solve(torch.tensor(rq.b, device="cuda"))
+        assert by_id[rq.rid].iters == st["iters"] and torch.equal(by_id[rq.rid].u, u), rq.rid
+    rec2, _ = serve.serve_sequential(reqs, cache=solvers)
+    assert len(rec2) == 20 and all(r.status == 0 and not r.setup for r in rec2)
+    assert [r.iters for r in sorted(rec2, key=lambda r: r.rid)] == [by_id[q].iters for q in range(20)]
+    srv.close()
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_graph_replay_waits_for_a_new_solves_start(precision):
+    # Arrivals far apart: every solve runs alone in the batch, so the captured
+    # lock step is small and is replayed right after the solve's start, which
+    # runs on a side stream. Each result must still equal the solo solve.
+    from paper_2606_20496_amd import meshgen as mg
+    meshes = mg.batch_meshes(count=4, nmax=12)
+    reqs = serve.make_resident_requests(meshes, rate=100.0, count=12, seed=5)
+    srv = serve.Server(budget_bytes=8e9, precision=precision, use_graph=True, step_iters=2, keep_outputs=True)
+    solvers = {k: srv.preload(k, m) for k, m in enumerate(meshes)}
+    records, _ = srv.run(reqs)
+    by_id = {r.rid: r for r in records}
+    for rq in reqs:
+        u, st = solvers[rq.key].solve(torch.tensor(rq.b, device="cuda"))
+        rec = by_id[rq.rid]
+        assert rec.status == 0 and rec.iters == st["iters"] and torch.equal(rec.u, u), rq.rid
+    srv.close()
