@@ -157,7 +157,7 @@ def run_batch_workload(torch, coarse, mg, tol, reps=3):
     return out
 
 
-def run_serving_resident(torch, coarse, mg, tol, rates=(250.0, 500.0, 1000.0, 2000.0), count=1024,
+def run_serving_resident(torch, coarse, mg, tol, rates=(500.0, 2000.0, 8000.0, 32000.0), count=2048,
                          precision="mixed"):
     """Open-loop serving over resident contexts: the 64 batch meshes are set up
     beforehand (both for the continuous-batching server, mixed precision, and for

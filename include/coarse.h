@@ -238,16 +238,20 @@ int coarse_projection_reset(coarse_ctx *ctx);
 
 /* Solve `count` independent systems (any mix of contexts, each with its own right-
  * hand side) in lock step: every PCG phase of all live systems is issued before
- * the next phase, and the local solves of all of them go into one launch.
- * Contexts must be distinct and share one stream (that of ctxs[0]). Each result
+ * the next phase, and each phase of all of them is one launch.
+ * Contexts must be distinct; the batch runs on the stream of ctxs[0]. Each result
  * equals what coarse_solve gives for that system alone (bitwise). */
 int coarse_solve_batch(coarse_ctx *const *ctxs, const double *const *b, double *const *u,
                        int count, double tol, coarse_stats *st);
 
 /* Continuous batching (lock-step solves). A batch advances every live solve by
- * whole PCG iterations: each solve's own kernels run on one of a few internal
- * side streams, and the dense local and reduced solves of all live solves run as
- * ONE GEMV launch (and one partial-sum launch) per iteration. Solves join with
+ * whole PCG iterations, all on `stream`, with seven launches per iteration
+ * whatever the number of live solves: the operator, the x/r update, the
+ * restriction (R_p and the first stage of J^T), the J^T corner sums, the dense
+ * local and reduced solves of all systems of all solves (one GEMV and one
+ * partial-sum launch), and the overlap sum with the prolongation. Each workgroup
+ * of such a launch works for one solve exactly as in that solve's own launch.
+ * A submitted solve's first preconditioner application runs at submit. Solves join with
  * coarse_batch_submit and leave when coarse_batch_step reports them finished, so
  * requests that arrive while others are running are admitted between steps.
  * Results are bitwise identical to coarse_solve of the same context and RHS.
@@ -261,9 +265,11 @@ int coarse_batch_create(void *stream, int use_graph, coarse_batch **out);
 /* Start the solve of ctx for right-hand side b into u (device, as in
  * coarse_solve); tag is returned by coarse_batch_step when it finishes. */
 int coarse_batch_submit(coarse_batch *bt, coarse_ctx *ctx, const double *b, double *u, double tol, int64_t tag);
-/* Advance all live solves by `iters` lock steps, then retire the finished ones:
- * their u is written (stream-ordered before later work on `stream`), and up to
- * cap of them are reported in tags[] / stats[] (*n_done of them). */
+/* Advance all live solves by `iters` lock steps, then retire up to cap of the
+ * finished ones: their u is written (stream-ordered before later work on
+ * `stream`) and they are reported in tags[] / stats[] (*n_done of them); other
+ * finished solves stay live (their iterations are skipped) until a later step
+ * retires them. */
 int coarse_batch_step(coarse_batch *bt, int iters, int64_t *tags, coarse_stats *stats, int cap, int *n_done);
 int coarse_batch_live(const coarse_batch *bt);
 int coarse_batch_destroy(coarse_batch *bt);

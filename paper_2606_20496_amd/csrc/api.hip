@@ -870,6 +870,7 @@ struct coarse_batch {
   Seg *h_seg = nullptr;      // pinned staging
   IterDev *d_iter = nullptr, *h_iter = nullptr;   // [cap] per-solve state
   int32_t *d_off = nullptr, *h_off = nullptr;     // [NG][cap + 1] workgroup offsets
+  Scalars *d_sc = nullptr, *h_sc = nullptr;       // [cap] solver states, gathered each step
   int cap = 0, n_items = 0, n_rows = 0;
   int grid[NG] = {};
   int op_lds = 0;
@@ -894,6 +895,10 @@ struct coarse_batch {
     if (h_iter) (void)hipHostFree(h_iter);
     if (d_off) (void)hipFree(d_off);
     if (h_off) (void)hipHostFree(h_off);
+    if (d_sc) (void)hipFree(d_sc);
+    if (h_sc) (void)hipHostFree(h_sc);
+    d_sc = nullptr;
+    h_sc = nullptr;
     d_seg = nullptr;
     h_seg = nullptr;
     d_iter = nullptr;
@@ -940,6 +945,8 @@ struct coarse_batch {
       HIPCHK(hipHostMalloc((void **)&h_iter, cap * sizeof(IterDev), hipHostMallocDefault));
       HIPCHK(hipMalloc(&d_off, NG * (cap + 1) * sizeof(int32_t)));
       HIPCHK(hipHostMalloc((void **)&h_off, NG * (cap + 1) * sizeof(int32_t), hipHostMallocDefault));
+      HIPCHK(hipMalloc(&d_sc, cap * sizeof(Scalars)));
+      HIPCHK(hipHostMalloc((void **)&h_sc, cap * sizeof(Scalars), hipHostMallocDefault));
     }
     n_items = n_rows = 0;
     op_lds = 0;
@@ -1017,9 +1024,12 @@ struct coarse_batch {
     } else {
       for (int i = 0; i < iters; ++i) lock_step();
     }
+    const int n = (int)live.size();
+    hipLaunchKernelGGL(k_gather_scalars, dim3(nblk(n, 64)), dim3(64), 0, main, (const IterDev *)d_iter, n, d_sc);
     HIPCHK(hipGetLastError());
-    for (auto &e : live) HIPCHK(hipMemcpyAsync(e.c->h_sc, e.c->sc, sizeof(Scalars), hipMemcpyDeviceToHost, main));
+    HIPCHK(hipMemcpyAsync(h_sc, d_sc, n * sizeof(Scalars), hipMemcpyDeviceToHost, main));
     HIPCHK(hipStreamSynchronize(main));
+    for (int k = 0; k < n; ++k) *live[k].c->h_sc = h_sc[k];
     // retire at most capn finished solves; any others stay (their iterations are
     // skipped on the device) and are retired by a later step
     std::vector<Entry> keep;

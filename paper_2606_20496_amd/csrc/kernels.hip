@@ -1229,6 +1229,14 @@ __global__ __launch_bounds__(VW) void k_final(int64_t nf, const int *__restrict_
 // launch (same grid per solve, same partial sums, so each result is bitwise the
 // solo one). The dense solves of the batch are already one launch (k_gemv_*).
 // ---------------------------------------------------------------------------
+// The solver state of every solve of a batch in one array, for one
+// device-to-host transfer per lock step.
+__global__ __launch_bounds__(64) void k_gather_scalars(const IterDev *__restrict__ ctx, int n,
+                                                       Scalars *__restrict__ out) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i < n) out[i] = *ctx[i].sc;
+}
+
 __device__ __forceinline__ int find_ctx(const int32_t *__restrict__ off, int n, int g) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {

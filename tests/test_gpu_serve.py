@@ -113,8 +113,9 @@ def test_resident_serving_equals_solo_and_sequential():
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 def test_graph_replay_waits_for_a_new_solves_start(precision):
     # Arrivals far apart: every solve runs alone in the batch, so the captured
-    # lock step is small and is replayed right after the solve's start, which
-    # runs on a side stream. Each result must still equal the solo solve.
+    # lock step is small and is replayed right after the solve's start (its first
+    # preconditioner application, issued at submit). Each result must still
+    # equal the solo solve.
     from paper_2606_20496_amd import meshgen as mg
     meshes = mg.batch_meshes(count=4, nmax=12)
     reqs = serve.make_resident_requests(meshes, rate=100.0, count=12, seed=5)
