@@ -197,7 +197,8 @@ def run_serving_resident(torch, coarse, mg, tol, rates=(500.0, 2000.0, 8000.0, 3
 def kernel_bytes(info, n_elem, precision):
     """Algorithmic bytes per launch of the per-iteration kernels (what the method
     must move with this storage; index tables of the blocking scheme excluded):
-    A+p  : A^e (36 unique FP64 = 288 B) + 8 u16 slots per element; z, p_old read,
+    A+p  : A^e (28 off-diagonal FP64 = 224 B; its rows sum to zero) + 8 u16 slots
+           per element; z, p_old read,
            p and q written per free vertex
     R_p+J^T stage 1: per packed entry index + r value + r_p write; per J entry
            vertex id, weight, 3 local coordinates and the r value
@@ -207,7 +208,7 @@ def kernel_bytes(info, n_elem, precision):
     es = 8 if precision == "fp64" else 4
     nf, snp, nj = info["n_free"], info["sum_np"], info["n_jent"]
     return {
-        "A+p": n_elem * (288 + 16) + nf * 32,
+        "A+p": n_elem * (224 + 16) + nf * 32,
         "R_p+J^T": snp * (4 + 8 + es) + nj * (4 + es + 3 * es + 8),
         "sum+J": snp * (4 + 8) + nf * (4 + 8 + 8 + 4) + nj * (4 + es + 3 * es),
         "x,r update": nf * 48,

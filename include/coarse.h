@@ -163,6 +163,10 @@ typedef struct {
                             inverses one preconditioner application must read     */
   int64_t n_jent;        /* entries of J: (free vertex, cell) pairs with a nonzero
                             weight fraction (Sec. 4, J = W Q^T J_L S)              */
+  int64_t n_inc_blocks;  /* operator blocks (256 elements) in which two elements
+                            hold one vertex at the same local corner; they sum
+                            element outputs through per-vertex incidence lists,
+                            all others corner by corner                         */
   int64_t device_bytes;  /* all device memory held by the context                   */
   int32_t boxes[3];
   int32_t precision;

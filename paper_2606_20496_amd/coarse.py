@@ -90,7 +90,7 @@ class _Info(ctypes.Structure):
                 ("max_np", ctypes.c_int64), ("n_r", ctypes.c_int64), ("n_cells", ctypes.c_int64),
                 ("local_bytes", ctypes.c_int64), ("reduced_bytes", ctypes.c_int64),
                 ("a_bytes", ctypes.c_int64), ("inv_alg_bytes", ctypes.c_int64),
-                ("n_jent", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("n_jent", ctypes.c_int64), ("n_inc_blocks", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("boxes", ctypes.c_int32 * 3), ("precision", ctypes.c_int32),
                 ("gemv_tiles", ctypes.c_int32 * GEMV_BUCKETS)]
 

@@ -548,10 +548,12 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
   Arena tmp;
   double *xyz = tmp.upload(P.xyz, s);
   int32_t *e2v = tmp.upload(P.e2v, s);
-  double *Ae = A.alloc<double>(36 * (int64_t)nblk(NE, OP_BLOCK) * OP_BLOCK);   // blocked, see ae_at
+  // all 36 entries for the setup's assemblies; the 28 off-diagonal ones stay for the operator
+  double *Ae = tmp.alloc<double>(36 * (int64_t)nblk(NE, OP_BLOCK) * OP_BLOCK);   // blocked, see ae_at
+  double *Ae28 = A.alloc<double>(28 * (int64_t)nblk(NE, OP_BLOCK) * OP_BLOCK);   // see ae28_at
   int *bad = tmp.alloc<int>(1);
   HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), s));
-  hipLaunchKernelGGL(k_elem_matrices, dim3(nblk(NE, 256)), dim3(256), 0, s, NE, NV, xyz, e2v, Ae, bad);
+  hipLaunchKernelGGL(k_elem_matrices, dim3(nblk(NE, 256)), dim3(256), 0, s, NE, NV, xyz, e2v, Ae, Ae28, bad);
   int hbad = 0;
   HIPCHK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -562,14 +564,16 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
   op.E = NE;
   op.n_blocks = P.n_blocks;
   op.n_shared = (int64_t)P.sh_vid.size();
-  op.Ae = Ae;
+  op.Ae = Ae28;
   op.lconn = A.upload(P.lconn, s);
   op.blk_slot_ptr = A.upload(P.blk_slot_ptr, s);
   op.slot_vid = A.upload(P.slot_vid, s);
   op.slot_dst = A.upload(P.slot_dst, s);
-  op.slot_inc_ptr = A.upload(P.slot_inc_ptr, s);
-  op.slot_inc = A.upload(P.slot_inc, s);
-  op.slot_inc8 = A.upload(P.slot_inc8, s);
+  // the incidence lists only serve blocks of differently oriented elements
+  op.blk_inc = A.upload(P.blk_inc, s);
+  op.slot_inc_ptr = P.any_blk_inc ? A.upload(P.slot_inc_ptr, s) : A.alloc<int32_t>(1);
+  op.slot_inc = P.any_blk_inc ? A.upload(P.slot_inc, s) : A.alloc<uint16_t>(1);
+  op.slot_inc8 = P.any_blk_inc ? A.upload(P.slot_inc8, s) : A.alloc<uint16_t>(1);
   op.partials = A.alloc<double>(std::max<int64_t>(1, P.n_partials));
   op.sh_vid = A.upload(P.sh_vid, s);
   op.sh_ptr = A.upload(P.sh_ptr, s);
@@ -810,7 +814,16 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
   in.inv_alg_bytes = 0;
   for (const System &S : P.sys) in.inv_alg_bytes += S.n * (S.n + 1) / 2 * (int64_t)sizeof(TT);
   in.n_jent = (int64_t)P.jv_w.size();
-  in.a_bytes = NE * (36 * 8 + 8 * 2) + (int64_t)P.slot_vid.size() * 12 + (int64_t)P.slot_inc.size() * 2 + nf * 16;
+  in.n_inc_blocks = 0;
+  int64_t inc_slots = 0;
+  for (int64_t blk = 0; blk < P.n_blocks; ++blk)
+    if (P.blk_inc[blk]) {
+      ++in.n_inc_blocks;
+      inc_slots += P.blk_slot_ptr[blk + 1] - P.blk_slot_ptr[blk];
+    }
+  // element matrices and connectivity; slot vertex, destination and writer flag;
+  // the 16-byte incidence record of slots in incidence-list blocks; p read, q written
+  in.a_bytes = NE * (28 * 8 + 8 * 2) + (int64_t)P.slot_vid.size() * 9 + inc_slots * 16 + nf * 16;
   for (int d = 0; d < 3; ++d) in.boxes[d] = P.b[d];
   in.precision = c->precision;
   for (int b = 0; b < COARSE_GEMV_BUCKETS; ++b) in.gemv_tiles[b] = c->gemv_tiles[b];
@@ -1128,6 +1141,7 @@ int coarse_plan_info(const coarse_mesh *mesh, const coarse_bc *bc, const coarse_
   info->n_r = P.n_r;
   info->n_cells = (int64_t)P.occ_cells.size();
   info->n_jent = (int64_t)P.jv_w.size();
+  for (int64_t blk = 0; blk < P.n_blocks; ++blk) info->n_inc_blocks += P.blk_inc[blk];
   for (int d = 0; d < 3; ++d) info->boxes[d] = P.b[d];
   info->precision = o.precision;
   if (sizes)

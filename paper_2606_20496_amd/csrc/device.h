@@ -48,6 +48,10 @@ __device__ __forceinline__ T trilin(int k, T x, T y, T z) {
   return fx * fy * fz;
 }
 
+// Index of entry (a, b), a < b, among the 28 strictly upper entries of an 8x8
+// matrix stored row by row.
+__host__ __device__ constexpr int off8(int a, int b) { return a * 7 - (a * (a - 1)) / 2 + (b - a - 1); }
+
 // Index of entry (a, b), a <= b, in the 36-entry upper triangle of an 8x8
 // symmetric element matrix stored row by row.
 __host__ __device__ constexpr int sym8(int a, int b) {

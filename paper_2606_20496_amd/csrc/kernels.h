@@ -16,6 +16,12 @@ __host__ __device__ inline int64_t ae_at(int k, int64_t e) {
   return ((e / OP_BLOCK) * 36 + k) * OP_BLOCK + (e % OP_BLOCK);
 }
 
+// The operator keeps only the 28 off-diagonal entries a < b of each A^e (its rows
+// sum to zero), in the same blocked layout: [block][28][OP_BLOCK].
+__host__ __device__ inline int64_t ae28_at(int k, int64_t e) {
+  return ((e / OP_BLOCK) * 28 + k) * OP_BLOCK + (e % OP_BLOCK);
+}
+
 // Solver scalars living in device memory (one per context).
 struct Scalars {
   double bb, rho[2], rr, pq, alpha, beta, tol2, res_true;
@@ -65,7 +71,7 @@ struct Seg {
 // Device pointers of one context used by the per-iteration kernels.
 struct OpDev {
   int64_t E, n_blocks, n_shared;
-  const double *Ae;
+  const double *Ae;           // [block][28][OP_BLOCK] off-diagonal element entries (ae28_at)
   const uint16_t *lconn;   // [E][8] block-local slots, one 16-byte load per element
   const int32_t *blk_slot_ptr, *slot_vid, *slot_dst, *slot_inc_ptr;
   const uint16_t *slot_inc;
@@ -73,6 +79,7 @@ struct OpDev {
   double *partials;
   const int32_t *sh_vid, *sh_ptr;
   const uint8_t *slot_pw;     // 1: this slot's block writes the vertex's search direction
+  const uint8_t *blk_inc;     // per block, 1: sum through the incidence lists (see block_accumulate)
   const int2 *vq;             // free vertex -> (first partial, count); count 0: owned by one block
   int32_t lds_bytes;
 };

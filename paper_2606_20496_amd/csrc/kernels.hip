@@ -10,11 +10,12 @@ namespace coarse {
 // ---------------------------------------------------------------------------
 // Setup: Q1 element matrices (Sec. 3, a^e_ij = int grad l_i . grad l_j) with the
 // 2x2x2 Gauss rule on the trilinear map of [-1,1]^3. One thread per element;
-// the 36 distinct entries are stored per operator block (ae_at).
+// the 36 distinct entries are stored per operator block (ae_at) for the setup,
+// and the 28 off-diagonal ones (ae28_at) for the operator.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_elem_matrices(int64_t E, int64_t NV, const double *__restrict__ xyz,
                                                        const int32_t *__restrict__ e2v, double *__restrict__ Ae,
-                                                       int *__restrict__ bad) {
+                                                       double *__restrict__ Ae28, int *__restrict__ bad) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= E) return;
   double X[8][3];
@@ -80,6 +81,10 @@ __global__ __launch_bounds__(256) void k_elem_matrices(int64_t E, int64_t NV, co
   if (!(detmin > 0.0)) atomicAdd(bad, 1);
 #pragma unroll
   for (int k = 0; k < 36; ++k) Ae[ae_at(k, e)] = A[k];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = a + 1; b < 8; ++b) Ae28[ae28_at(off8(a, b), e)] = A[sym8(a, b)];
 }
 
 // ---------------------------------------------------------------------------
@@ -94,10 +99,10 @@ __global__ __launch_bounds__(256) void k_elem_matrices(int64_t E, int64_t NV, co
 // An element's 8 block-local slots (one 16-byte record) and its 36 unique matrix
 // entries do not depend on the vector: their loads are issued first and stay in
 // flight while the block stages its vertex values.
-__device__ __forceinline__ void elem_load(const OpDev &op, int64_t e, double m[36], uint4 &c) {
+__device__ __forceinline__ void elem_load(const OpDev &op, int64_t e, double m[28], uint4 &c) {
   c = *(const uint4 *)(op.lconn + e * 8);
 #pragma unroll
-  for (int k = 0; k < 36; ++k) m[k] = op.Ae[ae_at(k, e)];
+  for (int k = 0; k < 28; ++k) m[k] = op.Ae[ae28_at(k, e)];
 }
 
 __device__ __forceinline__ unsigned slot_at(const uint4 &c, int a) {
@@ -105,9 +110,11 @@ __device__ __forceinline__ unsigned slot_at(const uint4 &c, int a) {
   return (a & 1) ? (w >> 16) : (w & 0xFFFFu);
 }
 
-// y = A^e p_e from the staged slot values (upper triangle row by row, mirrored)
-// into out[0..8); returns p_e . y.
-__device__ __forceinline__ double elem_apply(const double m[36], const uint4 &c, const double *lp, double *out) {
+// y = A^e p_e from the staged slot values into out[0..8); returns p_e . y. The
+// basis functions sum to one, so their gradients sum to zero and every row of
+// A^e sums to zero: (A^e p)_a = sum_{b != a} a_ab (p_b - p_a), from the 28
+// off-diagonal entries (a Dirichlet corner holds p = 0 and its row is dropped).
+__device__ __forceinline__ double elem_apply(const double m[28], const uint4 &c, const double *lp, double *out) {
   double pe[8];
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
@@ -120,10 +127,10 @@ __device__ __forceinline__ double elem_apply(const double m[36], const uint4 &c,
 #pragma unroll
   for (int a = 0; a < 8; ++a)
 #pragma unroll
-    for (int b = a; b < 8; ++b) {
-      const double v = m[sym8(a, b)];
-      y[a] += v * pe[b];
-      if (b != a) y[b] += v * pe[a];
+    for (int b = a + 1; b < 8; ++b) {
+      const double t = m[off8(a, b)] * (pe[b] - pe[a]);
+      y[a] += t;
+      y[b] -= t;
     }
   double en = 0.0;
 #pragma unroll
@@ -160,6 +167,44 @@ __device__ __forceinline__ void block_scatter(const OpDev &op, int s0, int ns, c
   }
 }
 
+// The block's element outputs y (registers of each element's thread) summed
+// into its slots, each written to q or to its partial. A block whose elements
+// never hold one vertex at the same local corner adds them in LDS corner by
+// corner (a = 0..7): each pass adds at most once to a slot, so no two threads
+// touch a slot at once and every slot sums in corner order. A block with
+// differently oriented elements sums its per-slot incidence lists instead.
+// Called after the last read of the staged values in lp, which it reuses.
+__device__ __forceinline__ void block_accumulate(const OpDev &op, int blk, int s0, int ns, bool valid, const uint4 &c,
+                                                 const double y[8], double *lp, double *out,
+                                                 double *__restrict__ q) {
+  if (op.blk_inc[blk]) {
+    if (valid) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a) out[threadIdx.x * 8 + a] = y[a];
+    }
+    __syncthreads();
+    block_scatter(op, s0, ns, out, q);
+    return;
+  }
+  for (int s = threadIdx.x; s < ns; s += OP_BLOCK) lp[s] = 0.0;
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    if (valid) {
+      const unsigned sl = slot_at(c, a);
+      if (sl != 0xFFFFu) lp[sl] += y[a];
+    }
+    __syncthreads();
+  }
+  for (int s = threadIdx.x; s < ns; s += OP_BLOCK) {
+    const int dst = op.slot_dst[s0 + s];
+    if (dst >= 0)
+      q[dst] = lp[s];
+    else
+      op.partials[-dst - 1] = lp[s];
+  }
+}
+
 __global__ __launch_bounds__(OP_BLOCK) void k_op_pass1(OpDev op, const double *__restrict__ p, double *__restrict__ q,
                                                        double *__restrict__ energy, const int *__restrict__ done) {
   extern __shared__ double lds[];
@@ -169,16 +214,16 @@ __global__ __launch_bounds__(OP_BLOCK) void k_op_pass1(OpDev op, const double *_
   double *lp = lds + OP_BLOCK * 8;   // [slots]
   const int blk = blockIdx.x;
   const int64_t e = (int64_t)blk * OP_BLOCK + threadIdx.x;
-  double m[36];
+  double m[28];
   uint4 c = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
   if (e < op.E) elem_load(op, e, m, c);
   const int s0 = op.blk_slot_ptr[blk], ns = op.blk_slot_ptr[blk + 1] - s0;
   for (int s = threadIdx.x; s < ns; s += OP_BLOCK) lp[s] = p[op.slot_vid[s0 + s]];
   __syncthreads();
-  double en = 0.0;
-  if (e < op.E) en = elem_apply(m, c, lp, out + threadIdx.x * 8);
+  double en = 0.0, y[8];
+  if (e < op.E) en = elem_apply(m, c, lp, y);
   __syncthreads();
-  block_scatter(op, s0, ns, out, q);
+  block_accumulate(op, blk, s0, ns, e < op.E, c, y, lp, out, q);
   if (energy) {
     const double tot = block_sum<OP_BLOCK>(en, red);
     if (threadIdx.x == 0) energy[blk] = tot;
@@ -383,7 +428,7 @@ __device__ __forceinline__ void op_fused_body(OpDev op, const double *__restrict
                                               int blk, double *lds, double *red) {
   if (sc->done) return;
   const int64_t e = (int64_t)blk * OP_BLOCK + threadIdx.x;
-  double m[36];
+  double m[28];
   uint4 c = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
   if (e < op.E) elem_load(op, e, m, c);
   const int it = sc->iter;
@@ -429,10 +474,10 @@ __device__ __forceinline__ void op_fused_body(OpDev op, const double *__restrict
     }
   }
   __syncthreads();
-  double en = 0.0;
-  if (e < op.E) en = elem_apply(m, c, lp, out + threadIdx.x * 8);
+  double en = 0.0, y[8];
+  if (e < op.E) en = elem_apply(m, c, lp, y);
   __syncthreads();
-  block_scatter(op, s0, ns, out, q);
+  block_accumulate(op, blk, s0, ns, e < op.E, c, y, lp, out, q);
   const double tot = block_sum<OP_BLOCK>(en, red);
   if (threadIdx.x == 0) energy[blk] = tot;
 }

@@ -247,6 +247,7 @@ int build_plan(const PlanInput &in, Plan &P) {
     const int64_t nb = (NE + OP_BLOCK - 1) / OP_BLOCK;
     P.n_blocks = nb;
     P.blk_slot_ptr.assign(1, 0);
+    P.blk_inc.assign(nb, 0);
     P.lconn.assign(8 * NE, 0xFFFF);
     std::vector<int32_t> slot_of(NV, -1), cnt(NV, 0);
     std::vector<int64_t> shared_blocks;  // (slot global index) of shared slots
@@ -264,15 +265,21 @@ int build_plan(const PlanInput &in, Plan &P) {
       std::sort(verts.begin(), verts.end());
       const int32_t s0 = P.blk_slot_ptr.back();
       for (size_t s = 0; s < verts.size(); ++s) slot_of[verts[s]] = (int32_t)s;
-      // incidence lists per slot (element order, then local vertex order)
+      // incidence lists per slot (element order, then local vertex order); a
+      // vertex seen twice at the same local corner marks the block
       std::vector<std::vector<uint16_t>> lists(verts.size());
+      std::vector<uint8_t> corners_seen(verts.size(), 0);
       for (int64_t e = e0; e < e1; ++e)
         for (int v = 0; v < 8; ++v) {
           int32_t u = E2V(e, v);
           if (u >= nf) continue;
-          P.lconn[e * 8 + v] = (uint16_t)slot_of[u];
-          lists[slot_of[u]].push_back((uint16_t)((e - e0) * 8 + v));
+          const int32_t sl = slot_of[u];
+          P.lconn[e * 8 + v] = (uint16_t)sl;
+          lists[sl].push_back((uint16_t)((e - e0) * 8 + v));
+          if ((corners_seen[sl] >> v) & 1) P.blk_inc[blk] = 1;
+          corners_seen[sl] |= (uint8_t)(1u << v);
         }
+      if (P.blk_inc[blk]) P.any_blk_inc = true;
       for (size_t s = 0; s < verts.size(); ++s) {
         int32_t u = verts[s];
         P.slot_vid.push_back(u);

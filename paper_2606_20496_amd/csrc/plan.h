@@ -65,6 +65,9 @@ struct Plan {
   std::vector<int32_t> slot_inc_ptr;   // [n_slots+1] into slot_inc
   std::vector<uint16_t> slot_inc;      // e_local*8 + a
   std::vector<uint16_t> slot_inc8;      // [slots][8]: the incidence list as one record (see plan.cpp)
+  std::vector<uint8_t> blk_inc;        // [n_blocks] 1: two elements hold a vertex at the same local
+                                       // corner, so the block sums through the incidence lists
+  bool any_blk_inc = false;
   std::vector<uint16_t> lconn;         // [E][8]: slot of local vertex a (0xFFFF = Dirichlet), 16 B per element
   int64_t n_partials = 0;
   std::vector<int32_t> sh_vid;         // shared vertices

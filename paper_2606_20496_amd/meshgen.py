@@ -22,6 +22,7 @@ permutation, then the right-hand side.
 from __future__ import annotations
 
 import dataclasses
+import itertools
 import math
 
 import numpy as np
@@ -270,6 +271,40 @@ def serving_arrivals(rate, count=4096, seed=59999, reuse=0.3):
             fresh += 1
     rhs_seed = rng.integers(0, 2 ** 31 - 1, size=count)
     return t, mesh_id, rhs_seed
+
+
+def _cube_rotations():
+    """The 24 proper rotations of the reference cube as maps of local vertex
+    v = i + 2j + 4k: (axis permutation, flips) with determinant +1, each given
+    as the array new_local[v]."""
+    out = []
+    for perm in itertools.permutations(range(3)):
+        inversions = sum(1 for a in range(3) for b in range(a + 1, 3) if perm[a] > perm[b])
+        for flips in itertools.product((0, 1), repeat=3):
+            if (inversions + sum(flips)) % 2:
+                continue
+            m = np.empty(8, dtype=np.int64)
+            for v in range(8):
+                c = (v & 1, (v >> 1) & 1, (v >> 2) & 1)
+                cn = [c[perm[d]] ^ flips[d] for d in range(3)]
+                m[v] = cn[0] + 2 * cn[1] + 4 * cn[2]
+            out.append(m)
+    return out
+
+
+def reorient(mesh: Mesh, seed: int) -> Mesh:
+    """The same mesh with each element's local vertex numbering turned by one of
+    the 24 rotations of the reference cube (drawn per element from ``seed``):
+    the elements, and so the operator, are unchanged, but neighbouring elements
+    no longer hold a shared vertex at matching local corners, as in meshes from
+    an unstructured mesher."""
+    rots = _cube_rotations()
+    pick = np.random.default_rng(seed).integers(0, len(rots), size=mesh.n_elem)
+    e2v = np.empty_like(mesh.e2v)
+    for r, m in enumerate(rots):
+        sel = pick == r
+        e2v[np.ix_(sel, m)] = mesh.e2v[sel]
+    return dataclasses.replace(mesh, e2v=np.ascontiguousarray(e2v), name=mesh.name + "_reoriented")
 
 
 def resident_arrivals(rate, count, n_keys, seed=58999):

@@ -123,3 +123,21 @@ def test_plan_standard_interp_matches_oracle():
         info, _ = coarse.plan_info(m.xyz, m.e2v, m.dirichlet, m.part, m.n_part, boxes=m.boxes, interp="standard")
         assert info["n_r"] == S.n_r
         assert info["n_jent"] == free.size          # one entry per free vertex
+
+
+def test_plan_flags_blocks_of_mixed_element_orientation():
+    # consistently oriented elements never hold one vertex at the same local
+    # corner, so every operator block sums corner by corner; turning each
+    # element's local numbering by a random rotation of the cube makes blocks
+    # fall back to incidence lists, with the subdomains and the reduced space
+    # unchanged
+    m = mg.box_mesh((10, 9, 7), 21, block=4, boxes=(3, 3, 2), faces=("y1",))
+    r = mg.reorient(m, 7)
+    info, sizes = coarse.plan_info(m.xyz, m.e2v, m.dirichlet, m.part, m.n_part, boxes=m.boxes)
+    info_r, sizes_r = coarse.plan_info(r.xyz, r.e2v, r.dirichlet, r.part, r.n_part, boxes=r.boxes)
+    assert info["n_inc_blocks"] == 0
+    n_blocks = -(-m.n_elem // 256)
+    assert 0 < info_r["n_inc_blocks"] <= n_blocks
+    assert list(sizes) == list(sizes_r)
+    for k in ("n_free", "n_sub", "sum_np", "n_r", "n_cells", "n_jent"):
+        assert info[k] == info_r[k], k

@@ -45,6 +45,8 @@ SMALL = [
     ("ragged", lambda: mg.box_mesh((10, 9, 7), 21, block=4, boxes=(3, 3, 2), faces=("y1",))),
     ("annulus", lambda: mg.annulus_mesh(12, 22, block=4, boxes=(3, 3, 3))),
     ("one_sub", lambda: mg.box_mesh(6, 23, block=6, boxes=(2, 2, 2), faces=("z0",))),
+    # elements of mixed local orientation: operator blocks sum through incidence lists
+    ("reoriented", lambda: mg.reorient(mg.box_mesh((10, 9, 7), 21, block=4, boxes=(3, 3, 2), faces=("y1",)), 7)),
 ]
 
 

@@ -54,3 +54,18 @@ def test_batch_and_serving_draws():
     assert np.all(np.diff(t) > 0) and ids.max() < 500
     reuse = np.mean([ids[q] in ids[:q] for q in range(1, 500)])
     assert 0.2 < reuse < 0.4
+
+
+def test_reorient_keeps_the_operator():
+    # 24 distinct proper rotations; the assembled operator is the same matrix
+    from oracle import fem
+    rots = mg._cube_rotations()
+    assert len({tuple(r) for r in rots}) == 24
+    m = mg.small_cube()
+    r = mg.reorient(m, 5)
+    assert not np.array_equal(r.e2v, m.e2v)
+    assert np.array_equal(np.sort(r.e2v, axis=1), np.sort(m.e2v, axis=1))
+    d = m.dirichlet.astype(bool)
+    A1 = fem.stiffness(m.xyz, m.e2v, d)[0]
+    A2 = fem.stiffness(r.xyz, r.e2v, d)[0]
+    assert abs(A1 - A2).max() <= 1e-14 * abs(A1).max()
