@@ -87,6 +87,8 @@ struct coarse_ctx {
   int64_t nv = 0, ne = 0, nf = 0, n_r = 0, nent = 0, ntask = 0;
   int64_t n_local_sys = 0, vec_len = 0, coarse_vec_off = 0;
   int32_t items_local = 0, items_total = 0, rows_local = 0, rows_total = 0;
+  int32_t whole_local = 0, whole_total = 0;   // systems solved by one workgroup each
+  int32_t whole_lds = 0;                      // LDS bytes of such a workgroup
   int nvblk = 1;
   double t_setup = 0.0;
   coarse_info_t info{};
@@ -116,6 +118,7 @@ struct coarse_ctx {
   void *rp = nullptr, *tiles = nullptr, *rowpart = nullptr, *colpart = nullptr;
   double *zp = nullptr;
   GItem *items = nullptr;
+  int32_t *whole = nullptr;
   GRow *rows = nullptr;
   SysDev *sysdev = nullptr;
   Seg *seg_all = nullptr, *seg_local = nullptr, *seg_coarse = nullptr;
@@ -212,19 +215,22 @@ struct coarse_ctx {
                        (const T *)jt_part, (T *)rp + coarse_vec_off);
   }
 
-  void gemv_combine(const Seg *segs, int nitems, int nrows, const int *done) {
-    if (nitems <= 0) return;
-    // one wavefront per work item (the kernel also loops over a smaller grid, but
-    // one item per wavefront measured fastest on MI355X at every size tried)
-    const unsigned g = nblk(nitems, 4);
+  void gemv_combine(const Seg *segs, int nitems, int nrows, int nwhole, const int *done) {
+    if (nitems <= 0 && nwhole <= 0) return;
+    // a workgroup per whole system, then one wavefront per work item (the kernel
+    // also loops over a smaller grid, but one item per wavefront measured fastest
+    // on MI355X at every size tried)
+    const unsigned g = (unsigned)nwhole + (nitems > 0 ? nblk(nitems, 4) : 0u);
+    const unsigned lds = nwhole > 0 ? (unsigned)whole_lds : 0u;
     pbeg(3);
     if (precision == COARSE_FP64)
-      hipLaunchKernelGGL(k_gemv_f64, dim3(g), dim3(256), 0, stream, segs, 1, nitems, done);
+      hipLaunchKernelGGL(k_gemv_f64, dim3(g), dim3(256), lds, stream, segs, 1, nitems, segs, nwhole, done);
     else if (precision == COARSE_MIXED_F16)
-      hipLaunchKernelGGL(k_gemv_f16, dim3(g), dim3(256), 0, stream, segs, 1, nitems, done);
+      hipLaunchKernelGGL(k_gemv_f16, dim3(g), dim3(256), lds, stream, segs, 1, nitems, segs, nwhole, done);
     else
-      hipLaunchKernelGGL(k_gemv_f32, dim3(g), dim3(256), 0, stream, segs, 1, nitems, done);
+      hipLaunchKernelGGL(k_gemv_f32, dim3(g), dim3(256), lds, stream, segs, 1, nitems, segs, nwhole, done);
     pend(3);
+    if (nrows <= 0) return;
     pbeg(4);
     if (precision == COARSE_FP64)
       hipLaunchKernelGGL(k_combine<double>, dim3(nblk((int64_t)nrows * TILE, 256)), dim3(256), 0, stream, segs, 1,
@@ -272,11 +278,11 @@ struct coarse_ctx {
       if (coarse) restrict_coarse<T>(in, done);
     }
     if (local && coarse)
-      gemv_combine(seg_all, items_total, rows_total, done);
+      gemv_combine(seg_all, items_total, rows_total, whole_total, done);
     else if (local)
-      gemv_combine(seg_local, items_local, rows_local, done);
+      gemv_combine(seg_local, items_local, rows_local, whole_local, done);
     else
-      gemv_combine(seg_coarse, items_total - items_local, rows_total - rows_local, done);
+      gemv_combine(seg_coarse, items_total - items_local, rows_total - rows_local, whole_total - whole_local, done);
     final_step<T>(add, local, coarse, out, rdot, p1, p2, done, scal, start);
   }
 
@@ -626,9 +632,24 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
   TT *tiles = A.alloc<TT>((size_t)P.n_tiles * TILE * TILE);
   std::vector<float> sys_scale(P.sys.size(), 1.0f);
   c->tiles = tiles;
-  c->colpart = A.alloc<T>((size_t)P.n_tiles * TILE);
   GemvTable G;
-  build_gemv_items(P, gemv_tiles, coarse_gemv_bucket_max, COARSE_GEMV_BUCKETS, G);
+  int dev = 0, n_cu = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  build_gemv_items(P, gemv_tiles, coarse_gemv_bucket_max, COARSE_GEMV_BUCKETS, n_cu, G);
+  // transposed partials only for the systems cut into work items
+  std::vector<int64_t> colpart_off(P.sys.size(), -1);
+  int64_t ncolpart = 0;
+  {
+    std::vector<char> is_whole(P.sys.size(), 0);
+    for (int32_t k : G.whole) is_whole[k] = 1;
+    for (size_t k = 0; k < P.sys.size(); ++k)
+      if (!is_whole[k]) {
+        colpart_off[k] = ncolpart;
+        ncolpart += P.sys[k].nb * (P.sys[k].nb + 1) / 2;
+      }
+  }
+  c->colpart = A.alloc<T>((size_t)std::max<int64_t>(1, ncolpart) * TILE);
   for (int b = 0; b < COARSE_GEMV_BUCKETS; ++b) c->gemv_tiles[b] = gemv_tiles[b] >= 1 ? gemv_tiles[b] : GEMV_SEG;
   c->rowpart = A.alloc<T>((size_t)G.items.size() * TILE);
   c->cover_ptr = A.upload(P.cover_ptr, s);
@@ -728,7 +749,7 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
     const System &S = P.sys[k];
     sd[k].tiles = tiles + (size_t)S.tile_off * TILE * TILE;
     sd[k].rp = (T *)c->rp + S.vec_off;
-    sd[k].colpart = (T *)c->colpart + (size_t)S.tile_off * TILE;
+    sd[k].colpart = colpart_off[k] >= 0 ? (T *)c->colpart + (size_t)colpart_off[k] * TILE : nullptr;
     sd[k].zp = c->zp + S.vec_off;
     sd[k].nb = (int32_t)S.nb;
     sd[k].n = (int32_t)S.n;
@@ -742,7 +763,8 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
   std::vector<int64_t> sys_item0(P.sys.size(), -1);
   for (size_t i = 0; i < G.items.size(); ++i)
     if (sys_item0[G.items[i].sys] < 0) sys_item0[G.items[i].sys] = (int64_t)i;
-  for (size_t k = 0; k < P.sys.size(); ++k) sd[k].rowpart = (T *)c->rowpart + (size_t)sys_item0[k] * TILE;
+  for (size_t k = 0; k < P.sys.size(); ++k)
+    sd[k].rowpart = sys_item0[k] >= 0 ? (T *)c->rowpart + (size_t)sys_item0[k] * TILE : nullptr;
   std::vector<GItem> gi(G.items.size());
   int32_t il = 0;
   for (size_t i = 0; i < G.items.size(); ++i) {
@@ -756,9 +778,9 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
     if (it.sys < P.n_local_sys) il = (int32_t)i + 1;
   }
   if (P.sys.back().nb > 32767 / 2) throw Fail(COARSE_EINVAL, "reduced system too large");
-  std::vector<GRow> gr(P.n_rows);
+  std::vector<GRow> gr(G.row_sys.size());
   int32_t rl = 0;
-  for (int64_t k = 0; k < P.n_rows; ++k) {
+  for (int64_t k = 0; k < (int64_t)gr.size(); ++k) {
     gr[k].sys = G.row_sys[k];
     gr[k].I = G.row_I[k];
     gr[k].slot0 = (int32_t)(G.row_item0[k] - sys_item0[G.row_sys[k]]);
@@ -767,14 +789,18 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
   }
   c->items = A.upload(gi, s);
   c->rows = A.upload(gr, s);
+  c->whole = A.upload(G.whole, s);
   c->sysdev = A.upload(sd, s);
   c->items_local = il;
   c->items_total = (int32_t)gi.size();
   c->rows_local = rl;
   c->rows_total = (int32_t)gr.size();
-  c->h_seg_all = Seg{c->items, c->rows, c->sysdev, nullptr, 0, 0};
+  c->whole_local = G.whole_local;
+  c->whole_total = (int32_t)G.whole.size();
+  c->whole_lds = WHOLE_WAVES * G.whole_nb_max * TILE * (int32_t)sizeof(T);
+  c->h_seg_all = Seg{c->items, c->rows, c->whole, c->sysdev, nullptr, 0, 0};
   c->h_seg_local = c->h_seg_all;
-  c->h_seg_coarse = Seg{c->items + il, c->rows + rl, c->sysdev, nullptr, 0, 0};
+  c->h_seg_coarse = Seg{c->items + il, c->rows + rl, c->whole + c->whole_local, c->sysdev, nullptr, 0, 0};
   c->seg_all = A.upload(std::vector<Seg>{c->h_seg_all}, s);
   c->seg_local = A.upload(std::vector<Seg>{c->h_seg_local}, s);
   c->seg_coarse = A.upload(std::vector<Seg>{c->h_seg_coarse}, s);
@@ -879,12 +905,12 @@ struct coarse_batch {
   std::vector<Entry> live;
   int precision = -1;
   bool dirty = true, use_graph = false;
-  Seg *d_seg = nullptr;      // [2][cap]: item segments, then row segments
+  Seg *d_seg = nullptr;      // [3][cap]: item, row and whole-system segments
   Seg *h_seg = nullptr;      // pinned staging
   IterDev *d_iter = nullptr, *h_iter = nullptr;   // [cap] per-solve state
   int32_t *d_off = nullptr, *h_off = nullptr;     // [NG][cap + 1] workgroup offsets
   Scalars *d_sc = nullptr, *h_sc = nullptr;       // [cap] solver states, gathered each step
-  int cap = 0, n_items = 0, n_rows = 0;
+  int cap = 0, n_items = 0, n_rows = 0, n_whole = 0, whole_lds = 0;
   int grid[NG] = {};
   int op_lds = 0;
   hipGraphExec_t gexec = nullptr;
@@ -952,8 +978,8 @@ struct coarse_batch {
       HIPCHK(hipStreamSynchronize(main));
       free_tables();
       cap = std::max(2 * n, 16);
-      HIPCHK(hipMalloc(&d_seg, 2 * cap * sizeof(Seg)));
-      HIPCHK(hipHostMalloc((void **)&h_seg, 2 * cap * sizeof(Seg), hipHostMallocDefault));
+      HIPCHK(hipMalloc(&d_seg, 3 * cap * sizeof(Seg)));
+      HIPCHK(hipHostMalloc((void **)&h_seg, 3 * cap * sizeof(Seg), hipHostMallocDefault));
       HIPCHK(hipMalloc(&d_iter, cap * sizeof(IterDev)));
       HIPCHK(hipHostMalloc((void **)&h_iter, cap * sizeof(IterDev), hipHostMallocDefault));
       HIPCHK(hipMalloc(&d_off, NG * (cap + 1) * sizeof(int32_t)));
@@ -961,15 +987,18 @@ struct coarse_batch {
       HIPCHK(hipMalloc(&d_sc, cap * sizeof(Scalars)));
       HIPCHK(hipHostMalloc((void **)&h_sc, cap * sizeof(Scalars), hipHostMallocDefault));
     }
-    n_items = n_rows = 0;
-    op_lds = 0;
+    n_items = n_rows = n_whole = 0;
+    op_lds = whole_lds = 0;
     for (int g = 0; g < NG; ++g) h_off[g * (cap + 1)] = 0;
     for (int k = 0; k < n; ++k) {
       coarse_ctx *c = live[k].c;
-      h_seg[k] = Seg{c->items, c->rows, c->sysdev, c->done_flag, n_items, 0};
-      h_seg[cap + k] = Seg{c->items, c->rows, c->sysdev, c->done_flag, n_rows, 0};
+      h_seg[k] = Seg{c->items, c->rows, c->whole, c->sysdev, c->done_flag, n_items, 0};
+      h_seg[cap + k] = Seg{c->items, c->rows, c->whole, c->sysdev, c->done_flag, n_rows, 0};
+      h_seg[2 * cap + k] = Seg{c->items, c->rows, c->whole, c->sysdev, c->done_flag, n_whole, 0};
       n_items += c->items_total;
       n_rows += c->rows_total;
+      n_whole += c->whole_total;
+      whole_lds = std::max(whole_lds, (int)c->whole_lds);
       c->fill_iter(h_iter[k]);
       const int64_t blocks[NG] = {c->op.n_blocks, c->nvblk, c->pre_gather_blocks() + c->pre_task_blocks(),
                                   nblk(c->n_r, 4), c->nvblk};
@@ -981,7 +1010,7 @@ struct coarse_batch {
       op_lds = std::max(op_lds, (int)c->op.lds_bytes);
     }
     for (int g = 0; g < NG; ++g) grid[g] = h_off[g * (cap + 1) + n];
-    HIPCHK(hipMemcpyAsync(d_seg, h_seg, 2 * cap * sizeof(Seg), hipMemcpyHostToDevice, main));
+    HIPCHK(hipMemcpyAsync(d_seg, h_seg, 3 * cap * sizeof(Seg), hipMemcpyHostToDevice, main));
     HIPCHK(hipMemcpyAsync(d_iter, h_iter, n * sizeof(IterDev), hipMemcpyHostToDevice, main));
     HIPCHK(hipMemcpyAsync(d_off, h_off, NG * (cap + 1) * sizeof(int32_t), hipMemcpyHostToDevice, main));
     if (gexec) {
@@ -1002,15 +1031,21 @@ struct coarse_batch {
     hipLaunchKernelGGL(k_pre_grp<T>, dim3(grid[G_PRE]), dim3(256), 0, main, (const IterDev *)d_iter, off + 2 * L, n);
     hipLaunchKernelGGL(k_jt_corners_grp<T>, dim3(grid[G_COR]), dim3(256), 0, main, (const IterDev *)d_iter,
                        off + 3 * L, n);
-    const unsigned g = nblk(n_items, 4);
+    const unsigned g = (unsigned)n_whole + (n_items > 0 ? nblk(n_items, 4) : 0u);
+    const unsigned lds = n_whole > 0 ? (unsigned)whole_lds : 0u;
+    const Seg *ws = d_seg + 2 * cap;
     if (precision == COARSE_FP64)
-      hipLaunchKernelGGL(k_gemv_f64, dim3(g), dim3(256), 0, main, (const Seg *)d_seg, n, n_items, (const int *)nullptr);
+      hipLaunchKernelGGL(k_gemv_f64, dim3(g), dim3(256), lds, main, (const Seg *)d_seg, n, n_items, ws, n_whole,
+                         (const int *)nullptr);
     else if (precision == COARSE_MIXED_F16)
-      hipLaunchKernelGGL(k_gemv_f16, dim3(g), dim3(256), 0, main, (const Seg *)d_seg, n, n_items, (const int *)nullptr);
+      hipLaunchKernelGGL(k_gemv_f16, dim3(g), dim3(256), lds, main, (const Seg *)d_seg, n, n_items, ws, n_whole,
+                         (const int *)nullptr);
     else
-      hipLaunchKernelGGL(k_gemv_f32, dim3(g), dim3(256), 0, main, (const Seg *)d_seg, n, n_items, (const int *)nullptr);
-    hipLaunchKernelGGL(k_combine<T>, dim3(nblk((int64_t)n_rows * TILE, 256)), dim3(256), 0, main,
-                       (const Seg *)(d_seg + cap), n, n_rows, (const int *)nullptr);
+      hipLaunchKernelGGL(k_gemv_f32, dim3(g), dim3(256), lds, main, (const Seg *)d_seg, n, n_items, ws, n_whole,
+                         (const int *)nullptr);
+    if (n_rows > 0)
+      hipLaunchKernelGGL(k_combine<T>, dim3(nblk((int64_t)n_rows * TILE, 256)), dim3(256), 0, main,
+                         (const Seg *)(d_seg + cap), n, n_rows, (const int *)nullptr);
     hipLaunchKernelGGL(k_final_grp<T>, dim3(grid[G_FIN]), dim3(VW), 0, main, (const IterDev *)d_iter, off + 4 * L, n);
   }
   void lock_step() {

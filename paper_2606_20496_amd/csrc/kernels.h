@@ -62,6 +62,7 @@ struct GRow {
 struct Seg {
   const GItem *items;
   const GRow *rows;
+  const int32_t *whole;   // systems solved by one workgroup each
   const SysDev *sys;
   const int *done;   // the owning solve's finished flag (batched launches), or null
   int32_t begin;     // first global index of this segment

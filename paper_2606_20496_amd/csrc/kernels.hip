@@ -902,15 +902,156 @@ __device__ __forceinline__ float4 ldnt(const float4 *p) {
   return o;
 }
 
+// Whole systems (nb <= WHOLE_NB_MAX): one workgroup of WHOLE_WAVES wavefronts per
+// system, launched ahead of the work items in the same grid. Wavefront w owns the
+// tile rows dealt to it in a snake order over the rows from longest to shortest
+// (so the waves hold nearly equal tile counts) and streams their tiles back to
+// back, the next one (across a row boundary too) loaded while the current one is
+// used. A row's own contribution is summed in registers; the transposed
+// contributions of its off-diagonal tiles go to the wavefront's copy of the
+// solution in LDS. The copies are summed in a fixed order at the end and written
+// as z_s: no partial sums leave the workgroup.
+__device__ __forceinline__ int snake_row(int nb, int w, int k) {
+  const int p = k * WHOLE_WAVES + ((k & 1) ? WHOLE_WAVES - 1 - w : w);
+  return p < nb ? nb - 1 - p : -1;
+}
+
+// the wavefront's next tile after (I, J) (its k-th row): (nI, nJ) in row nk, nI < 0 at the end
+__device__ __forceinline__ void whole_next(int nb, int w, int k, int I, int J, int &nk, int &nI, int &nJ) {
+  nk = k;
+  nI = I;
+  nJ = J + 1;
+  if (nJ > I) {
+    nk = k + 1;
+    nI = snake_row(nb, w, nk);
+    nJ = 0;
+  }
+}
+
+// z_s = scale times the sum of the wavefront copies, in a fixed order (the
+// reduced system also goes to the full box-vertex grid)
+template <typename A>
+__device__ __forceinline__ void whole_finish(const SysDev &S, A *ys, double scale) {
+  __syncthreads();
+  const int n = S.nb * TILE;
+  for (int i = threadIdx.x; i < n; i += WHOLE_WAVES * WAVE) {
+    A z = A(0);
+#pragma unroll
+    for (int q = 0; q < WHOLE_WAVES; ++q) z += ys[q * n + i];
+    const double zd = (double)z * scale;
+    S.zp[i] = zd;
+    if (S.yfull && i < S.n) S.yfull[S.act_bv[i]] = zd;
+  }
+}
+
+template <typename A>
+__device__ __forceinline__ A *whole_begin(const SysDev &S, A *ys) {
+  const int n = S.nb * TILE;
+  for (int i = threadIdx.x; i < WHOLE_WAVES * n; i += WHOLE_WAVES * WAVE) ys[i] = A(0);
+  __syncthreads();
+  return ys + (threadIdx.x >> 6) * n;
+}
+
+// FP64 tiles: lane layout of k_gemv_f64 below.
+__device__ __forceinline__ void whole_f64(const SysDev &S, double *ys) {
+  double *y = whole_begin(S, ys);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int grp = lane >> 4, c2 = (lane & 15) * 2;
+  const int nb = S.nb;
+  const double *__restrict__ r = (const double *)S.rp;
+  const double2 *__restrict__ base = (const double2 *)S.tiles;
+  int k = 0, I = snake_row(nb, w, 0), J = 0;
+  if (I >= 0) {
+    double2 v[8], nv[8];
+    const double2 *t = base + ((int64_t)I * (I + 1) / 2) * (TILE * TILE / 2);
+#pragma unroll
+    for (int m = 0; m < 8; ++m) v[m] = ldnt(t + m * 64 + lane);
+    double rI[8], acc[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      rI[m] = r[I * TILE + 4 * m + grp];
+      acc[m] = 0.0;
+    }
+    for (;;) {
+      int nk, nI, nJ;
+      whole_next(nb, w, k, I, J, nk, nI, nJ);
+      const bool more = nI >= 0;
+      if (more) {
+        const double2 *tn = base + ((int64_t)nI * (nI + 1) / 2 + nJ) * (TILE * TILE / 2);
+#pragma unroll
+        for (int m = 0; m < 8; ++m) nv[m] = ldnt(tn + m * 64 + lane);
+      }
+      const double2 rj = *(const double2 *)(r + J * TILE + c2);
+#pragma unroll
+      for (int m = 0; m < 8; ++m) acc[m] += v[m].x * rj.x + v[m].y * rj.y;
+      if (J != I) {
+        double cx = 0.0, cy = 0.0;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          cx += v[m].x * rI[m];
+          cy += v[m].y * rI[m];
+        }
+        cx += __shfl_xor(cx, 16, 64);
+        cy += __shfl_xor(cy, 16, 64);
+        cx += __shfl_xor(cx, 32, 64);
+        cy += __shfl_xor(cy, 32, 64);
+        if (lane < 16) {
+          y[J * TILE + c2] += cx;
+          y[J * TILE + c2 + 1] += cy;
+        }
+      } else {
+        // row I complete
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          double a = acc[m];
+          a += __shfl_xor(a, 1, 64);
+          a += __shfl_xor(a, 2, 64);
+          a += __shfl_xor(a, 4, 64);
+          a += __shfl_xor(a, 8, 64);
+          acc[m] = 0.0;
+          if ((lane & 15) == 0) y[I * TILE + 4 * m + grp] += a;
+        }
+        if (more) {
+#pragma unroll
+          for (int m = 0; m < 8; ++m) rI[m] = r[nI * TILE + 4 * m + grp];
+        }
+      }
+      if (!more) break;
+#pragma unroll
+      for (int m = 0; m < 8; ++m) v[m] = nv[m];
+      k = nk;
+      I = nI;
+      J = nJ;
+    }
+  }
+  whole_finish(S, ys, 1.0);
+}
+
+// The segment table of a launch covering several solves: whole-system
+// workgroups first (begin offsets in systems), then items (begin in items).
+__device__ __forceinline__ const Seg &seg_of(const Seg *__restrict__ segs, int nseg, int g) {
+  return segs[nseg == 1 ? 0 : find_seg(segs, nseg, g)];
+}
+
 // FP64: a wavefront covers a 32x32 tile with 8 loads of 16 bytes per lane; lane l
 // holds rows 4k + l/16 (k < 8), columns 2(l%16) and 2(l%16)+1. The next tile is
-// loaded while the current one is used.
+// loaded while the current one is used. Workgroups [0, nwhole) solve whole
+// systems (wsegs); the others take work items (segs), one per wavefront.
 __global__ __launch_bounds__(256) void k_gemv_f64(const Seg *__restrict__ segs, int nseg, int total,
+                                                  const Seg *__restrict__ wsegs, int nwhole,
                                                   const int *__restrict__ done) {
   if (done && *done) return;
+  if ((int)blockIdx.x < nwhole) {
+    extern __shared__ double ysd[];
+    const Seg &sg = seg_of(wsegs, nseg, blockIdx.x);
+    if (sg.done && *sg.done) return;
+    whole_f64(sg.sys[sg.whole[blockIdx.x - sg.begin]], ysd);
+    return;
+  }
   const int lane = threadIdx.x & 63;
   const int grp = lane >> 4, c2 = (lane & 15) * 2;
-  for (int g = blockIdx.x * 4 + (threadIdx.x >> 6); g < total; g += gridDim.x * 4) {
+  const int ngrid = (int)gridDim.x - nwhole;
+  for (int g = (blockIdx.x - nwhole) * 4 + (threadIdx.x >> 6); g < total; g += ngrid * 4) {
     const Seg sg = segs[nseg == 1 ? 0 : find_seg(segs, nseg, g)];
     if (sg.done && *sg.done) continue;
     const GItem it = sg.items[g - sg.begin];
@@ -980,12 +1121,97 @@ __global__ __launch_bounds__(256) void k_gemv_f64(const Seg *__restrict__ segs, 
 
 // FP32: 4 loads of 16 bytes per lane per tile; lane l holds rows 8m + l/8 (m < 4),
 // columns 4(l%8) .. 4(l%8)+3.
+__device__ __forceinline__ void whole_f32(const SysDev &S, float *ys) {
+  float *y = whole_begin(S, ys);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int grp = lane >> 3, c4 = (lane & 7) * 4;
+  const int nb = S.nb;
+  const float *__restrict__ r = (const float *)S.rp;
+  const float4 *__restrict__ base = (const float4 *)S.tiles;
+  int k = 0, I = snake_row(nb, w, 0), J = 0;
+  if (I >= 0) {
+    float4 v[4], nv[4];
+    const float4 *t = base + ((int64_t)I * (I + 1) / 2) * (TILE * TILE / 4);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v[m] = ldnt(t + m * 64 + lane);
+    float rI[4], acc[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      rI[m] = r[I * TILE + 8 * m + grp];
+      acc[m] = 0.0f;
+    }
+    for (;;) {
+      int nk, nI, nJ;
+      whole_next(nb, w, k, I, J, nk, nI, nJ);
+      const bool more = nI >= 0;
+      if (more) {
+        const float4 *tn = base + ((int64_t)nI * (nI + 1) / 2 + nJ) * (TILE * TILE / 4);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) nv[m] = ldnt(tn + m * 64 + lane);
+      }
+      const float4 rj = *(const float4 *)(r + J * TILE + c4);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) acc[m] += v[m].x * rj.x + v[m].y * rj.y + v[m].z * rj.z + v[m].w * rj.w;
+      if (J != I) {
+        float c[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          c[0] += v[m].x * rI[m];
+          c[1] += v[m].y * rI[m];
+          c[2] += v[m].z * rI[m];
+          c[3] += v[m].w * rI[m];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          c[j] += __shfl_xor(c[j], 8, 64);
+          c[j] += __shfl_xor(c[j], 16, 64);
+          c[j] += __shfl_xor(c[j], 32, 64);
+        }
+        if (lane < 8) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) y[J * TILE + c4 + j] += c[j];
+        }
+      } else {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          float a = acc[m];
+          a += __shfl_xor(a, 1, 64);
+          a += __shfl_xor(a, 2, 64);
+          a += __shfl_xor(a, 4, 64);
+          acc[m] = 0.0f;
+          if ((lane & 7) == 0) y[I * TILE + 8 * m + grp] += a;
+        }
+        if (more) {
+#pragma unroll
+          for (int m = 0; m < 4; ++m) rI[m] = r[nI * TILE + 8 * m + grp];
+        }
+      }
+      if (!more) break;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) v[m] = nv[m];
+      k = nk;
+      I = nI;
+      J = nJ;
+    }
+  }
+  whole_finish(S, ys, 1.0);
+}
+
 __global__ __launch_bounds__(256) void k_gemv_f32(const Seg *__restrict__ segs, int nseg, int total,
+                                                  const Seg *__restrict__ wsegs, int nwhole,
                                                   const int *__restrict__ done) {
   if (done && *done) return;
+  if ((int)blockIdx.x < nwhole) {
+    extern __shared__ float ysf[];
+    const Seg &sg = seg_of(wsegs, nseg, blockIdx.x);
+    if (sg.done && *sg.done) return;
+    whole_f32(sg.sys[sg.whole[blockIdx.x - sg.begin]], ysf);
+    return;
+  }
   const int lane = threadIdx.x & 63;
   const int grp = lane >> 3, c4 = (lane & 7) * 4;
-  for (int g = blockIdx.x * 4 + (threadIdx.x >> 6); g < total; g += gridDim.x * 4) {
+  const int ngrid = (int)gridDim.x - nwhole;
+  for (int g = (blockIdx.x - nwhole) * 4 + (threadIdx.x >> 6); g < total; g += ngrid * 4) {
     const Seg sg = segs[nseg == 1 ? 0 : find_seg(segs, nseg, g)];
     if (sg.done && *sg.done) continue;
     const GItem it = sg.items[g - sg.begin];
@@ -1063,12 +1289,97 @@ __global__ __launch_bounds__(256) void k_gemv_f32(const Seg *__restrict__ segs, 
 // lane l holds rows 16m + l/4 (m < 2), columns 8(l%4) .. 8(l%4)+7. The row and
 // column sums are multiplied back by the scale when written.
 typedef _Float16 nt_h8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ void whole_f16(const SysDev &S, float *ys) {
+  float *y = whole_begin(S, ys);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int grp = lane >> 2, c8 = (lane & 3) * 8;
+  const int nb = S.nb;
+  const float *__restrict__ r = (const float *)S.rp;
+  const nt_h8 *__restrict__ base = (const nt_h8 *)S.tiles;
+  int k = 0, I = snake_row(nb, w, 0), J = 0;
+  if (I >= 0) {
+    nt_h8 v[2], nv[2];
+    const nt_h8 *t = base + ((int64_t)I * (I + 1) / 2) * (TILE * TILE / 8);
+#pragma unroll
+    for (int m = 0; m < 2; ++m) v[m] = __builtin_nontemporal_load(t + m * 64 + lane);
+    float rI[2], acc[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      rI[m] = r[I * TILE + 16 * m + grp];
+      acc[m] = 0.0f;
+    }
+    for (;;) {
+      int nk, nI, nJ;
+      whole_next(nb, w, k, I, J, nk, nI, nJ);
+      const bool more = nI >= 0;
+      if (more) {
+        const nt_h8 *tn = base + ((int64_t)nI * (nI + 1) / 2 + nJ) * (TILE * TILE / 8);
+#pragma unroll
+        for (int m = 0; m < 2; ++m) nv[m] = __builtin_nontemporal_load(tn + m * 64 + lane);
+      }
+      const float4 ra = *(const float4 *)(r + J * TILE + c8);
+      const float4 rb = *(const float4 *)(r + J * TILE + c8 + 4);
+      const float rj[8] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w};
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[m] += (float)v[m][q] * rj[q];
+      if (J != I) {
+        float c[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) c[q] = (float)v[0][q] * rI[0] + (float)v[1][q] * rI[1];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          c[q] += __shfl_xor(c[q], 4, 64);
+          c[q] += __shfl_xor(c[q], 8, 64);
+          c[q] += __shfl_xor(c[q], 16, 64);
+          c[q] += __shfl_xor(c[q], 32, 64);
+        }
+        if (lane < 4) {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) y[J * TILE + c8 + q] += c[q];
+        }
+      } else {
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          float a = acc[m];
+          a += __shfl_xor(a, 1, 64);
+          a += __shfl_xor(a, 2, 64);
+          acc[m] = 0.0f;
+          if ((lane & 3) == 0) y[I * TILE + 16 * m + grp] += a;
+        }
+        if (more) {
+#pragma unroll
+          for (int m = 0; m < 2; ++m) rI[m] = r[nI * TILE + 16 * m + grp];
+        }
+      }
+      if (!more) break;
+#pragma unroll
+      for (int m = 0; m < 2; ++m) v[m] = nv[m];
+      k = nk;
+      I = nI;
+      J = nJ;
+    }
+  }
+  // the tiles hold A_s^{-1} / scale
+  whole_finish(S, ys, (double)S.scale);
+}
+
 __global__ __launch_bounds__(256) void k_gemv_f16(const Seg *__restrict__ segs, int nseg, int total,
+                                                  const Seg *__restrict__ wsegs, int nwhole,
                                                   const int *__restrict__ done) {
   if (done && *done) return;
+  if ((int)blockIdx.x < nwhole) {
+    extern __shared__ float ysh[];
+    const Seg &sg = seg_of(wsegs, nseg, blockIdx.x);
+    if (sg.done && *sg.done) return;
+    whole_f16(sg.sys[sg.whole[blockIdx.x - sg.begin]], ysh);
+    return;
+  }
   const int lane = threadIdx.x & 63;
   const int grp = lane >> 2, c8 = (lane & 3) * 8;
-  for (int g = blockIdx.x * 4 + (threadIdx.x >> 6); g < total; g += gridDim.x * 4) {
+  const int ngrid = (int)gridDim.x - nwhole;
+  for (int g = (blockIdx.x - nwhole) * 4 + (threadIdx.x >> 6); g < total; g += ngrid * 4) {
     const Seg sg = segs[nseg == 1 ? 0 : find_seg(segs, nseg, g)];
     if (sg.done && *sg.done) continue;
     const GItem it = sg.items[g - sg.begin];

@@ -670,11 +670,26 @@ int build_plan(const PlanInput &in, Plan &P) {
   return 0;
 }
 
-void build_gemv_items(const Plan &P, const int *tiles_of_bucket, const int *bucket_max, int nbucket,
+void build_gemv_items(const Plan &P, const int *tiles_of_bucket, const int *bucket_max, int nbucket, int n_cu,
                       GemvTable &out) {
   out = GemvTable();
+  // whole-system candidates, largest first; the smallest beyond a multiple of
+  // n_cu would form a last round that few compute units work on
+  std::vector<int32_t> cand;
+  for (int64_t s = 0; s < (int64_t)P.sys.size(); ++s)
+    if (P.sys[s].nb <= WHOLE_NB_MAX) cand.push_back((int32_t)s);
+  std::stable_sort(cand.begin(), cand.end(), [&](int32_t a, int32_t b) { return P.sys[a].nb > P.sys[b].nb; });
+  size_t keep = cand.size();
+  if (n_cu > 0 && keep > (size_t)n_cu) keep -= keep % (size_t)n_cu;
+  std::vector<char> whole(P.sys.size(), 0);
+  for (size_t i = 0; i < keep; ++i) whole[cand[i]] = 1;
   for (int64_t s = 0; s < (int64_t)P.sys.size(); ++s) {
     const System &S = P.sys[s];
+    if (whole[s]) {
+      out.whole.push_back((int32_t)s);
+      out.whole_nb_max = std::max<int32_t>(out.whole_nb_max, (int32_t)S.nb);
+      continue;
+    }
     int b = 0;
     while (b + 1 < nbucket && S.nb > bucket_max[b]) ++b;
     const int64_t seg = (tiles_of_bucket && tiles_of_bucket[b] >= 1) ? tiles_of_bucket[b] : GEMV_SEG;
@@ -693,6 +708,11 @@ void build_gemv_items(const Plan &P, const int *tiles_of_bucket, const int *buck
       out.row_I.push_back((int32_t)I);
     }
   }
+  // local systems largest first (the longest workgroups start first), then the
+  // reduced system
+  auto mid = std::stable_partition(out.whole.begin(), out.whole.end(), [&](int32_t s) { return s < P.n_local_sys; });
+  out.whole_local = (int32_t)(mid - out.whole.begin());
+  std::stable_sort(out.whole.begin(), mid, [&](int32_t a, int32_t b) { return P.sys[a].nb > P.sys[b].nb; });
 }
 
 }  // namespace coarse

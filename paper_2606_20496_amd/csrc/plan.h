@@ -15,6 +15,10 @@ constexpr int TILE = 32;
 constexpr int OP_BLOCK = 256;
 // Tiles per GEMV work item (one wavefront streams at most this many tiles).
 constexpr int GEMV_SEG = 4;
+// Systems with at most this many tile rows are solved by one workgroup each
+// (WHOLE_WAVES wavefronts); larger ones are cut into work items.
+constexpr int WHOLE_NB_MAX = 48;
+constexpr int WHOLE_WAVES = 4;
 // Reduced-space entries per restriction task (one wavefront).
 constexpr int JT_CHUNK = 256;
 
@@ -133,14 +137,21 @@ struct Plan {
 // Build the plan; returns 0 or a negative coarse_status (message in plan.err).
 int build_plan(const PlanInput &in, Plan &plan);
 
-// GEMV work items and the row table for the systems of a plan: each tile row I of
-// a system with nb tile rows is cut into items of tiles_of_bucket[bucket(nb)]
-// tiles (bucket b: nb <= bucket_max[b]; a value < 1 means GEMV_SEG).
+// The dense-solve work of the systems of a plan. Systems with nb <= WHOLE_NB_MAX
+// go to `whole` (one workgroup each; the local systems largest first, then the
+// reduced system), as many as fill whole rounds of n_cu compute units (all of
+// them when there are fewer): the smallest of the rest, and every larger system,
+// have each tile row I cut into items of tiles_of_bucket[bucket(nb)] tiles
+// (bucket b: nb <= bucket_max[b]; a value < 1 means GEMV_SEG), whose partial sums
+// the row table combines.
 struct GemvTable {
+  std::vector<int32_t> whole;
+  int32_t whole_local = 0;   // leading entries of `whole` that are local systems
+  int32_t whole_nb_max = 0;
   std::vector<GemvItem> items;
   std::vector<int32_t> row_item0, row_nitem, row_sys, row_I;
 };
-void build_gemv_items(const Plan &P, const int *tiles_of_bucket, const int *bucket_max, int nbucket,
+void build_gemv_items(const Plan &P, const int *tiles_of_bucket, const int *bucket_max, int nbucket, int n_cu,
                       GemvTable &out);
 
 }  // namespace coarse
