@@ -220,15 +220,16 @@ struct coarse_ctx {
     // a workgroup per whole system, then one wavefront per work item (the kernel
     // also loops over a smaller grid, but one item per wavefront measured fastest
     // on MI355X at every size tried)
-    const unsigned g = (unsigned)nwhole + (nitems > 0 ? nblk(nitems, 4) : 0u);
+    const int nw = precision == COARSE_FP64 ? WHOLE_WAVES_F64 : WHOLE_WAVES_NARROW;   // wavefronts per workgroup
+    const unsigned g = (unsigned)nwhole + (nitems > 0 ? nblk(nitems, nw) : 0u);
     const unsigned lds = nwhole > 0 ? (unsigned)whole_lds : 0u;
     pbeg(3);
     if (precision == COARSE_FP64)
-      hipLaunchKernelGGL(k_gemv_f64, dim3(g), dim3(256), lds, stream, segs, 1, nitems, segs, nwhole, done);
+      hipLaunchKernelGGL(k_gemv_f64, dim3(g), dim3(nw * WAVE), lds, stream, segs, 1, nitems, segs, nwhole, done);
     else if (precision == COARSE_MIXED_F16)
-      hipLaunchKernelGGL(k_gemv_f16, dim3(g), dim3(256), lds, stream, segs, 1, nitems, segs, nwhole, done);
+      hipLaunchKernelGGL(k_gemv_f16, dim3(g), dim3(nw * WAVE), lds, stream, segs, 1, nitems, segs, nwhole, done);
     else
-      hipLaunchKernelGGL(k_gemv_f32, dim3(g), dim3(256), lds, stream, segs, 1, nitems, segs, nwhole, done);
+      hipLaunchKernelGGL(k_gemv_f32, dim3(g), dim3(nw * WAVE), lds, stream, segs, 1, nitems, segs, nwhole, done);
     pend(3);
     if (nrows <= 0) return;
     pbeg(4);
@@ -797,7 +798,7 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
   c->rows_total = (int32_t)gr.size();
   c->whole_local = G.whole_local;
   c->whole_total = (int32_t)G.whole.size();
-  c->whole_lds = WHOLE_WAVES * G.whole_nb_max * TILE * (int32_t)sizeof(T);
+  c->whole_lds = (sizeof(TT) == 8 ? WHOLE_WAVES_F64 : WHOLE_WAVES_NARROW) * G.whole_nb_max * TILE * (int32_t)sizeof(T);
   c->h_seg_all = Seg{c->items, c->rows, c->whole, c->sysdev, nullptr, 0, 0};
   c->h_seg_local = c->h_seg_all;
   c->h_seg_coarse = Seg{c->items + il, c->rows + rl, c->whole + c->whole_local, c->sysdev, nullptr, 0, 0};
@@ -1031,17 +1032,18 @@ struct coarse_batch {
     hipLaunchKernelGGL(k_pre_grp<T>, dim3(grid[G_PRE]), dim3(256), 0, main, (const IterDev *)d_iter, off + 2 * L, n);
     hipLaunchKernelGGL(k_jt_corners_grp<T>, dim3(grid[G_COR]), dim3(256), 0, main, (const IterDev *)d_iter,
                        off + 3 * L, n);
-    const unsigned g = (unsigned)n_whole + (n_items > 0 ? nblk(n_items, 4) : 0u);
+    const int nw = precision == COARSE_FP64 ? WHOLE_WAVES_F64 : WHOLE_WAVES_NARROW;
+    const unsigned g = (unsigned)n_whole + (n_items > 0 ? nblk(n_items, nw) : 0u);
     const unsigned lds = n_whole > 0 ? (unsigned)whole_lds : 0u;
     const Seg *ws = d_seg + 2 * cap;
     if (precision == COARSE_FP64)
-      hipLaunchKernelGGL(k_gemv_f64, dim3(g), dim3(256), lds, main, (const Seg *)d_seg, n, n_items, ws, n_whole,
+      hipLaunchKernelGGL(k_gemv_f64, dim3(g), dim3(nw * WAVE), lds, main, (const Seg *)d_seg, n, n_items, ws, n_whole,
                          (const int *)nullptr);
     else if (precision == COARSE_MIXED_F16)
-      hipLaunchKernelGGL(k_gemv_f16, dim3(g), dim3(256), lds, main, (const Seg *)d_seg, n, n_items, ws, n_whole,
+      hipLaunchKernelGGL(k_gemv_f16, dim3(g), dim3(nw * WAVE), lds, main, (const Seg *)d_seg, n, n_items, ws, n_whole,
                          (const int *)nullptr);
     else
-      hipLaunchKernelGGL(k_gemv_f32, dim3(g), dim3(256), lds, main, (const Seg *)d_seg, n, n_items, ws, n_whole,
+      hipLaunchKernelGGL(k_gemv_f32, dim3(g), dim3(nw * WAVE), lds, main, (const Seg *)d_seg, n, n_items, ws, n_whole,
                          (const int *)nullptr);
     if (n_rows > 0)
       hipLaunchKernelGGL(k_combine<T>, dim3(nblk((int64_t)n_rows * TILE, 256)), dim3(256), 0, main,

@@ -902,8 +902,10 @@ __device__ __forceinline__ float4 ldnt(const float4 *p) {
   return o;
 }
 
-// Whole systems (nb <= WHOLE_NB_MAX): one workgroup of WHOLE_WAVES wavefronts per
-// system, launched ahead of the work items in the same grid. Wavefront w owns the
+// Whole systems (nb <= WHOLE_NB_MAX): one workgroup of NW wavefronts per system
+// (WHOLE_WAVES_F64 for FP64 tiles, WHOLE_WAVES_NARROW for the smaller FP32/FP16
+// tiles, so that a workgroup keeps as many bytes in flight), launched ahead of the
+// work items in the same grid. Wavefront w owns the
 // tile rows dealt to it in a snake order over the rows from longest to shortest
 // (so the waves hold nearly equal tile counts) and streams their tiles back to
 // back, the next one (across a row boundary too) loaded while the current one is
@@ -911,56 +913,59 @@ __device__ __forceinline__ float4 ldnt(const float4 *p) {
 // contributions of its off-diagonal tiles go to the wavefront's copy of the
 // solution in LDS. The copies are summed in a fixed order at the end and written
 // as z_s: no partial sums leave the workgroup.
+template <int NW>
 __device__ __forceinline__ int snake_row(int nb, int w, int k) {
-  const int p = k * WHOLE_WAVES + ((k & 1) ? WHOLE_WAVES - 1 - w : w);
+  const int p = k * NW + ((k & 1) ? NW - 1 - w : w);
   return p < nb ? nb - 1 - p : -1;
 }
 
 // the wavefront's next tile after (I, J) (its k-th row): (nI, nJ) in row nk, nI < 0 at the end
+template <int NW>
 __device__ __forceinline__ void whole_next(int nb, int w, int k, int I, int J, int &nk, int &nI, int &nJ) {
   nk = k;
   nI = I;
   nJ = J + 1;
   if (nJ > I) {
     nk = k + 1;
-    nI = snake_row(nb, w, nk);
+    nI = snake_row<NW>(nb, w, nk);
     nJ = 0;
   }
 }
 
 // z_s = scale times the sum of the wavefront copies, in a fixed order (the
 // reduced system also goes to the full box-vertex grid)
-template <typename A>
+template <int NW, typename A>
 __device__ __forceinline__ void whole_finish(const SysDev &S, A *ys, double scale) {
   __syncthreads();
   const int n = S.nb * TILE;
-  for (int i = threadIdx.x; i < n; i += WHOLE_WAVES * WAVE) {
+  for (int i = threadIdx.x; i < n; i += NW * WAVE) {
     A z = A(0);
 #pragma unroll
-    for (int q = 0; q < WHOLE_WAVES; ++q) z += ys[q * n + i];
+    for (int q = 0; q < NW; ++q) z += ys[q * n + i];
     const double zd = (double)z * scale;
     S.zp[i] = zd;
     if (S.yfull && i < S.n) S.yfull[S.act_bv[i]] = zd;
   }
 }
 
-template <typename A>
+template <int NW, typename A>
 __device__ __forceinline__ A *whole_begin(const SysDev &S, A *ys) {
   const int n = S.nb * TILE;
-  for (int i = threadIdx.x; i < WHOLE_WAVES * n; i += WHOLE_WAVES * WAVE) ys[i] = A(0);
+  for (int i = threadIdx.x; i < NW * n; i += NW * WAVE) ys[i] = A(0);
   __syncthreads();
   return ys + (threadIdx.x >> 6) * n;
 }
 
 // FP64 tiles: lane layout of k_gemv_f64 below.
 __device__ __forceinline__ void whole_f64(const SysDev &S, double *ys) {
-  double *y = whole_begin(S, ys);
+  constexpr int NW = WHOLE_WAVES_F64;
+  double *y = whole_begin<NW>(S, ys);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int grp = lane >> 4, c2 = (lane & 15) * 2;
   const int nb = S.nb;
   const double *__restrict__ r = (const double *)S.rp;
   const double2 *__restrict__ base = (const double2 *)S.tiles;
-  int k = 0, I = snake_row(nb, w, 0), J = 0;
+  int k = 0, I = snake_row<NW>(nb, w, 0), J = 0;
   if (I >= 0) {
     double2 v[8], nv[8];
     const double2 *t = base + ((int64_t)I * (I + 1) / 2) * (TILE * TILE / 2);
@@ -974,7 +979,7 @@ __device__ __forceinline__ void whole_f64(const SysDev &S, double *ys) {
     }
     for (;;) {
       int nk, nI, nJ;
-      whole_next(nb, w, k, I, J, nk, nI, nJ);
+      whole_next<NW>(nb, w, k, I, J, nk, nI, nJ);
       const bool more = nI >= 0;
       if (more) {
         const double2 *tn = base + ((int64_t)nI * (nI + 1) / 2 + nJ) * (TILE * TILE / 2);
@@ -1024,7 +1029,7 @@ __device__ __forceinline__ void whole_f64(const SysDev &S, double *ys) {
       J = nJ;
     }
   }
-  whole_finish(S, ys, 1.0);
+  whole_finish<NW>(S, ys, 1.0);
 }
 
 // The segment table of a launch covering several solves: whole-system
@@ -1122,13 +1127,14 @@ __global__ __launch_bounds__(256) void k_gemv_f64(const Seg *__restrict__ segs, 
 // FP32: 4 loads of 16 bytes per lane per tile; lane l holds rows 8m + l/8 (m < 4),
 // columns 4(l%8) .. 4(l%8)+3.
 __device__ __forceinline__ void whole_f32(const SysDev &S, float *ys) {
-  float *y = whole_begin(S, ys);
+  constexpr int NW = WHOLE_WAVES_NARROW;
+  float *y = whole_begin<NW>(S, ys);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int grp = lane >> 3, c4 = (lane & 7) * 4;
   const int nb = S.nb;
   const float *__restrict__ r = (const float *)S.rp;
   const float4 *__restrict__ base = (const float4 *)S.tiles;
-  int k = 0, I = snake_row(nb, w, 0), J = 0;
+  int k = 0, I = snake_row<NW>(nb, w, 0), J = 0;
   if (I >= 0) {
     float4 v[4], nv[4];
     const float4 *t = base + ((int64_t)I * (I + 1) / 2) * (TILE * TILE / 4);
@@ -1142,7 +1148,7 @@ __device__ __forceinline__ void whole_f32(const SysDev &S, float *ys) {
     }
     for (;;) {
       int nk, nI, nJ;
-      whole_next(nb, w, k, I, J, nk, nI, nJ);
+      whole_next<NW>(nb, w, k, I, J, nk, nI, nJ);
       const bool more = nI >= 0;
       if (more) {
         const float4 *tn = base + ((int64_t)nI * (nI + 1) / 2 + nJ) * (TILE * TILE / 4);
@@ -1194,12 +1200,12 @@ __device__ __forceinline__ void whole_f32(const SysDev &S, float *ys) {
       J = nJ;
     }
   }
-  whole_finish(S, ys, 1.0);
+  whole_finish<NW>(S, ys, 1.0);
 }
 
-__global__ __launch_bounds__(256) void k_gemv_f32(const Seg *__restrict__ segs, int nseg, int total,
-                                                  const Seg *__restrict__ wsegs, int nwhole,
-                                                  const int *__restrict__ done) {
+__global__ __launch_bounds__(WHOLE_WAVES_NARROW * WAVE) void k_gemv_f32(const Seg *__restrict__ segs, int nseg,
+                                                                        int total, const Seg *__restrict__ wsegs,
+                                                                        int nwhole, const int *__restrict__ done) {
   if (done && *done) return;
   if ((int)blockIdx.x < nwhole) {
     extern __shared__ float ysf[];
@@ -1211,7 +1217,8 @@ __global__ __launch_bounds__(256) void k_gemv_f32(const Seg *__restrict__ segs, 
   const int lane = threadIdx.x & 63;
   const int grp = lane >> 3, c4 = (lane & 7) * 4;
   const int ngrid = (int)gridDim.x - nwhole;
-  for (int g = (blockIdx.x - nwhole) * 4 + (threadIdx.x >> 6); g < total; g += ngrid * 4) {
+  for (int g = (blockIdx.x - nwhole) * WHOLE_WAVES_NARROW + (threadIdx.x >> 6); g < total;
+       g += ngrid * WHOLE_WAVES_NARROW) {
     const Seg sg = segs[nseg == 1 ? 0 : find_seg(segs, nseg, g)];
     if (sg.done && *sg.done) continue;
     const GItem it = sg.items[g - sg.begin];
@@ -1290,13 +1297,14 @@ __global__ __launch_bounds__(256) void k_gemv_f32(const Seg *__restrict__ segs, 
 // column sums are multiplied back by the scale when written.
 typedef _Float16 nt_h8 __attribute__((ext_vector_type(8)));
 __device__ __forceinline__ void whole_f16(const SysDev &S, float *ys) {
-  float *y = whole_begin(S, ys);
+  constexpr int NW = WHOLE_WAVES_NARROW;
+  float *y = whole_begin<NW>(S, ys);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int grp = lane >> 2, c8 = (lane & 3) * 8;
   const int nb = S.nb;
   const float *__restrict__ r = (const float *)S.rp;
   const nt_h8 *__restrict__ base = (const nt_h8 *)S.tiles;
-  int k = 0, I = snake_row(nb, w, 0), J = 0;
+  int k = 0, I = snake_row<NW>(nb, w, 0), J = 0;
   if (I >= 0) {
     nt_h8 v[2], nv[2];
     const nt_h8 *t = base + ((int64_t)I * (I + 1) / 2) * (TILE * TILE / 8);
@@ -1310,7 +1318,7 @@ __device__ __forceinline__ void whole_f16(const SysDev &S, float *ys) {
     }
     for (;;) {
       int nk, nI, nJ;
-      whole_next(nb, w, k, I, J, nk, nI, nJ);
+      whole_next<NW>(nb, w, k, I, J, nk, nI, nJ);
       const bool more = nI >= 0;
       if (more) {
         const nt_h8 *tn = base + ((int64_t)nI * (nI + 1) / 2 + nJ) * (TILE * TILE / 8);
@@ -1362,12 +1370,12 @@ __device__ __forceinline__ void whole_f16(const SysDev &S, float *ys) {
     }
   }
   // the tiles hold A_s^{-1} / scale
-  whole_finish(S, ys, (double)S.scale);
+  whole_finish<NW>(S, ys, (double)S.scale);
 }
 
-__global__ __launch_bounds__(256) void k_gemv_f16(const Seg *__restrict__ segs, int nseg, int total,
-                                                  const Seg *__restrict__ wsegs, int nwhole,
-                                                  const int *__restrict__ done) {
+__global__ __launch_bounds__(WHOLE_WAVES_NARROW * WAVE) void k_gemv_f16(const Seg *__restrict__ segs, int nseg,
+                                                                        int total, const Seg *__restrict__ wsegs,
+                                                                        int nwhole, const int *__restrict__ done) {
   if (done && *done) return;
   if ((int)blockIdx.x < nwhole) {
     extern __shared__ float ysh[];
@@ -1379,7 +1387,8 @@ __global__ __launch_bounds__(256) void k_gemv_f16(const Seg *__restrict__ segs, 
   const int lane = threadIdx.x & 63;
   const int grp = lane >> 2, c8 = (lane & 3) * 8;
   const int ngrid = (int)gridDim.x - nwhole;
-  for (int g = (blockIdx.x - nwhole) * 4 + (threadIdx.x >> 6); g < total; g += ngrid * 4) {
+  for (int g = (blockIdx.x - nwhole) * WHOLE_WAVES_NARROW + (threadIdx.x >> 6); g < total;
+       g += ngrid * WHOLE_WAVES_NARROW) {
     const Seg sg = segs[nseg == 1 ? 0 : find_seg(segs, nseg, g)];
     if (sg.done && *sg.done) continue;
     const GItem it = sg.items[g - sg.begin];

@@ -16,9 +16,11 @@ constexpr int OP_BLOCK = 256;
 // Tiles per GEMV work item (one wavefront streams at most this many tiles).
 constexpr int GEMV_SEG = 4;
 // Systems with at most this many tile rows are solved by one workgroup each
-// (WHOLE_WAVES wavefronts); larger ones are cut into work items.
+// (WHOLE_WAVES_F64 wavefronts for FP64 tiles, WHOLE_WAVES_NARROW for FP32/FP16);
+// larger ones are cut into work items.
 constexpr int WHOLE_NB_MAX = 48;
-constexpr int WHOLE_WAVES = 4;
+constexpr int WHOLE_WAVES_F64 = 4;
+constexpr int WHOLE_WAVES_NARROW = 8;
 // Reduced-space entries per restriction task (one wavefront).
 constexpr int JT_CHUNK = 256;
 

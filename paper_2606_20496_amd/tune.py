@@ -1,14 +1,17 @@
 """Autotuner for the batched dense solve.
 
-The GEMV over the stored inverses is split into work items, each a run of
-32 x 32 tiles of one tile row that one wavefront streams. How many tiles an item
-holds trades the per-item start-up (work-table loads, row-partial write) against
-load balance and the column-partial traffic, and the best value depends on the
-size of the systems. This script times the GEMV launch for every candidate item
-length on synthetic meshes whose subdomain systems fall in each size bucket
-(the buckets of ``coarse.GEMV_BUCKET_MAX``), for both precisions, and writes the
-fastest choice per bucket to ``gemv_tuning.json`` next to this file (or to
-``--out``). ``coarse.gemv_table`` reads that file for every new context.
+Systems of up to 48 tile rows are solved by one workgroup each. Larger systems
+(and the few smallest ones left over beyond a multiple of the compute-unit
+count) are split into work items, each a run of 32 x 32 tiles of one tile row
+that one wavefront streams. How many tiles an item holds trades the per-item
+start-up (work-table loads, row-partial write) against load balance and the
+column-partial traffic. This script times the dense-solve launches for every
+candidate item length on synthetic meshes whose subdomain systems fall in the
+tuned size buckets (those of ``coarse.GEMV_BUCKET_MAX`` above 48 tile rows),
+for every precision, and writes the fastest choice per bucket to
+``gemv_tuning.json`` next to this file (or to ``--out``), keeping the earlier
+entries of the other buckets. ``coarse.gemv_table`` reads that file for every
+new context.
 
 Run on the GPU: ``python -m paper_2606_20496_amd.tune [--out PATH]``.
 """
@@ -27,6 +30,7 @@ from . import coarse, meshgen as mg
 BUCKET_BLOCK = (3, 4, 5, 6, 7, 8, 10, 12)
 CANDIDATES = (1, 2, 3, 4, 6, 8, 12, 16)
 PRECISIONS = ("fp64", "mixed", "mixed16")
+TUNED_BUCKETS = (7,)   # systems above 48 tile rows: the ones cut into work items
 TILE_BYTES = {"fp64": 8, "mixed": 4, "mixed16": 2}
 GEMV_PHASE = 3
 
@@ -51,18 +55,24 @@ def time_gemv(torch, plan, n_vert, tiles, reps):
     for _ in range(3):
         S.apply_precond(r)
     torch.cuda.synchronize()
-    S.profile_start(1 << GEMV_PHASE)
+    S.profile_start((1 << GEMV_PHASE) | (1 << (GEMV_PHASE + 1)))
     for _ in range(reps):
         S.apply_precond(r)
-    ms, cnt = S.profile_stop()[coarse.PHASES[GEMV_PHASE]]
+    ph = S.profile_stop()
     S.close()
-    return 1e3 * ms / max(cnt, 1)
+    # the dense-solve launch and, when work items were used, their partial sums
+    ms, cnt = ph[coarse.PHASES[GEMV_PHASE]]
+    ms_c, _ = ph[coarse.PHASES[GEMV_PHASE + 1]]
+    return 1e3 * (ms + ms_c) / max(cnt, 1)
 
 
-def tune(precision, target_bytes=1.0e9, reps=20):
+def tune(precision, target_bytes=1.0e9, reps=20, previous=None):
     import torch
-    table, timings = [], {}
+    table = list(previous) if previous else [4] * coarse.GEMV_BUCKETS
+    timings = {}
     for b, block in enumerate(BUCKET_BLOCK):
+        if b not in TUNED_BUCKETS:
+            continue
         t0 = time.perf_counter()
         m, nb = _mesh_for(block, precision, target_bytes)
         plan = coarse.Plan.from_mesh(m, precision=precision)
@@ -75,7 +85,7 @@ def tune(precision, target_bytes=1.0e9, reps=20):
             res[c] = round(time_gemv(torch, plan, m.n_vert, tiles, reps), 2)
         plan.close()
         best = min(res, key=res.get)
-        table.append(best)
+        table[b] = best
         timings[str(b)] = {"block": block, "nb": nb, "n_elem": m.n_elem, "us": res}
         _log(f"{precision} bucket {b} (nb {nb}, {m.n_elem} elements): {res} -> {best} "
              f"({time.perf_counter() - t0:.1f} s)")
@@ -95,7 +105,7 @@ def main():
     out = {"device": torch.cuda.get_device_name(0), "bucket_max": list(coarse.GEMV_BUCKET_MAX),
            "candidates": list(CANDIDATES)}
     for prec in PRECISIONS:
-        table, timings = tune(prec, args.bytes, args.reps)
+        table, timings = tune(prec, args.bytes, args.reps, previous=coarse.gemv_table(prec))
         out[prec] = {"tiles_per_item": table, "timings_us": timings}
     with open(args.out, "w") as f:
         json.dump(out, f, indent=1)
