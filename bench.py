@@ -42,13 +42,13 @@ def _pct(a, q):
 
 GEMV_PHASE = 3
 
-# HBM bytes per k_gemv_f64 launch on the 64^3 workload from hardware counters
+# HBM bytes per dense-solve launch (k_gemv_whole_f64) on the 64^3 workload from hardware counters
 # (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, per dispatch, scaled by the same
 # counters read on a 1 GiB device copy: FETCH x2.0, WRITE x1.0), and the
 # fingerprint of the GEMV source they were taken on. A changed kernel reports
 # traffic as unknown until the counters are taken again.
-GEMV_TRAFFIC = {"bytes": 1142612062, "fetch_kib": 556422.44, "write_kib": 2987.22, "fetch_scale": 2.0,
-                "write_scale": 1.0, "src": "434f59f32bcd7f5f"}
+GEMV_TRAFFIC = {"bytes": 1142612987, "fetch_kib": 556422.89, "write_kib": 2987.22, "fetch_scale": 2.0,
+                "write_scale": 1.0, "src": "0c72c6b9fc27f9aa"}
 
 
 def _gemv_source_fingerprint():
@@ -398,7 +398,7 @@ def main():
     traffic = GEMV_TRAFFIC["bytes"] if (args.n == 64 and _gemv_source_fingerprint() == GEMV_TRAFFIC["src"]) else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_gemv_f64", "avg_launch_us": round(avg_s * 1e6, 2),
+            "kernel": "k_gemv_whole_f64", "avg_launch_us": round(avg_s * 1e6, 2),
             "launches": cnt, "work_launches": fp64["gemv_work_launches"],
             "alg_bytes_per_launch": alg_bytes}
     phases = {k: {"avg_us": round(1e3 * v[0] / max(v[1], 1), 2), "launches": v[1]} for k, v in fp64["phases"].items()}

@@ -70,6 +70,36 @@ struct Arena {
 
 inline unsigned nblk(int64_t n, int b) { return (unsigned)std::max<int64_t>(1, (n + b - 1) / b); }
 
+// The dense solves of one application: the whole-system workgroups (nwhole
+// systems, wsegs) and the work items (segs), in one launch when there are whole
+// systems; either may be empty.
+void launch_gemv(hipStream_t s, int precision, const Seg *segs, int nseg, int nitems, const Seg *wsegs, int nwhole,
+                 int whole_lds, const int *done) {
+  if (nwhole > 0) {
+    const int nw = precision == COARSE_FP64 ? WHOLE_WAVES_F64 : WHOLE_WAVES_NARROW;
+    const unsigned g = (unsigned)nwhole + (nitems > 0 ? nblk(nitems, nw) : 0u);
+    if (precision == COARSE_FP64)
+      hipLaunchKernelGGL(k_gemv_whole_f64, dim3(g), dim3(nw * WAVE), whole_lds, s, segs, nseg, nitems, wsegs, nwhole,
+                         done);
+    else if (precision == COARSE_MIXED_F16)
+      hipLaunchKernelGGL(k_gemv_whole_f16, dim3(g), dim3(nw * WAVE), whole_lds, s, segs, nseg, nitems, wsegs, nwhole,
+                         done);
+    else
+      hipLaunchKernelGGL(k_gemv_whole_f32, dim3(g), dim3(nw * WAVE), whole_lds, s, segs, nseg, nitems, wsegs, nwhole,
+                         done);
+  } else if (nitems > 0) {
+    // one wavefront per work item (the kernel also loops over a smaller grid, but
+    // one item per wavefront measured fastest on MI355X at every size tried)
+    const unsigned g = nblk(nitems, 4);
+    if (precision == COARSE_FP64)
+      hipLaunchKernelGGL(k_gemv_f64, dim3(g), dim3(256), 0, s, segs, nseg, nitems, done);
+    else if (precision == COARSE_MIXED_F16)
+      hipLaunchKernelGGL(k_gemv_f16, dim3(g), dim3(256), 0, s, segs, nseg, nitems, done);
+    else
+      hipLaunchKernelGGL(k_gemv_f32, dim3(g), dim3(256), 0, s, segs, nseg, nitems, done);
+  }
+}
+
 }  // namespace
 
 // Host half of a setup: everything the device half uploads, built without any
@@ -217,19 +247,8 @@ struct coarse_ctx {
 
   void gemv_combine(const Seg *segs, int nitems, int nrows, int nwhole, const int *done) {
     if (nitems <= 0 && nwhole <= 0) return;
-    // a workgroup per whole system, then one wavefront per work item (the kernel
-    // also loops over a smaller grid, but one item per wavefront measured fastest
-    // on MI355X at every size tried)
-    const int nw = precision == COARSE_FP64 ? WHOLE_WAVES_F64 : WHOLE_WAVES_NARROW;   // wavefronts per workgroup
-    const unsigned g = (unsigned)nwhole + (nitems > 0 ? nblk(nitems, nw) : 0u);
-    const unsigned lds = nwhole > 0 ? (unsigned)whole_lds : 0u;
     pbeg(3);
-    if (precision == COARSE_FP64)
-      hipLaunchKernelGGL(k_gemv_f64, dim3(g), dim3(nw * WAVE), lds, stream, segs, 1, nitems, segs, nwhole, done);
-    else if (precision == COARSE_MIXED_F16)
-      hipLaunchKernelGGL(k_gemv_f16, dim3(g), dim3(nw * WAVE), lds, stream, segs, 1, nitems, segs, nwhole, done);
-    else
-      hipLaunchKernelGGL(k_gemv_f32, dim3(g), dim3(nw * WAVE), lds, stream, segs, 1, nitems, segs, nwhole, done);
+    launch_gemv(stream, precision, segs, 1, nitems, segs, nwhole, whole_lds, done);
     pend(3);
     if (nrows <= 0) return;
     pbeg(4);
@@ -1032,19 +1051,7 @@ struct coarse_batch {
     hipLaunchKernelGGL(k_pre_grp<T>, dim3(grid[G_PRE]), dim3(256), 0, main, (const IterDev *)d_iter, off + 2 * L, n);
     hipLaunchKernelGGL(k_jt_corners_grp<T>, dim3(grid[G_COR]), dim3(256), 0, main, (const IterDev *)d_iter,
                        off + 3 * L, n);
-    const int nw = precision == COARSE_FP64 ? WHOLE_WAVES_F64 : WHOLE_WAVES_NARROW;
-    const unsigned g = (unsigned)n_whole + (n_items > 0 ? nblk(n_items, nw) : 0u);
-    const unsigned lds = n_whole > 0 ? (unsigned)whole_lds : 0u;
-    const Seg *ws = d_seg + 2 * cap;
-    if (precision == COARSE_FP64)
-      hipLaunchKernelGGL(k_gemv_f64, dim3(g), dim3(nw * WAVE), lds, main, (const Seg *)d_seg, n, n_items, ws, n_whole,
-                         (const int *)nullptr);
-    else if (precision == COARSE_MIXED_F16)
-      hipLaunchKernelGGL(k_gemv_f16, dim3(g), dim3(nw * WAVE), lds, main, (const Seg *)d_seg, n, n_items, ws, n_whole,
-                         (const int *)nullptr);
-    else
-      hipLaunchKernelGGL(k_gemv_f32, dim3(g), dim3(nw * WAVE), lds, main, (const Seg *)d_seg, n, n_items, ws, n_whole,
-                         (const int *)nullptr);
+    launch_gemv(main, precision, d_seg, n, n_items, d_seg + 2 * cap, n_whole, whole_lds, nullptr);
     if (n_rows > 0)
       hipLaunchKernelGGL(k_combine<T>, dim3(nblk((int64_t)n_rows * TILE, 256)), dim3(256), 0, main,
                          (const Seg *)(d_seg + cap), n, n_rows, (const int *)nullptr);

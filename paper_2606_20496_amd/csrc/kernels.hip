@@ -1038,25 +1038,15 @@ __device__ __forceinline__ const Seg &seg_of(const Seg *__restrict__ segs, int n
   return segs[nseg == 1 ? 0 : find_seg(segs, nseg, g)];
 }
 
+
 // FP64: a wavefront covers a 32x32 tile with 8 loads of 16 bytes per lane; lane l
 // holds rows 4k + l/16 (k < 8), columns 2(l%16) and 2(l%16)+1. The next tile is
-// loaded while the current one is used. Workgroups [0, nwhole) solve whole
-// systems (wsegs); the others take work items (segs), one per wavefront.
-__global__ __launch_bounds__(256) void k_gemv_f64(const Seg *__restrict__ segs, int nseg, int total,
-                                                  const Seg *__restrict__ wsegs, int nwhole,
-                                                  const int *__restrict__ done) {
-  if (done && *done) return;
-  if ((int)blockIdx.x < nwhole) {
-    extern __shared__ double ysd[];
-    const Seg &sg = seg_of(wsegs, nseg, blockIdx.x);
-    if (sg.done && *sg.done) return;
-    whole_f64(sg.sys[sg.whole[blockIdx.x - sg.begin]], ysd);
-    return;
-  }
+// loaded while the current one is used.
+__device__ __forceinline__ void items_f64(const Seg *__restrict__ segs, int nseg, int total, int g0,
+                                          int gstride) {
   const int lane = threadIdx.x & 63;
   const int grp = lane >> 4, c2 = (lane & 15) * 2;
-  const int ngrid = (int)gridDim.x - nwhole;
-  for (int g = (blockIdx.x - nwhole) * 4 + (threadIdx.x >> 6); g < total; g += ngrid * 4) {
+  for (int g = g0; g < total; g += gstride) {
     const Seg sg = segs[nseg == 1 ? 0 : find_seg(segs, nseg, g)];
     if (sg.done && *sg.done) continue;
     const GItem it = sg.items[g - sg.begin];
@@ -1122,6 +1112,30 @@ __global__ __launch_bounds__(256) void k_gemv_f64(const Seg *__restrict__ segs, 
       for (int k = 0; k < 8; ++k) rowp[4 * k + grp] = acc[k];
     }
   }
+}
+
+// Work items only, one per wavefront.
+__global__ __launch_bounds__(256) void k_gemv_f64(const Seg *__restrict__ segs, int nseg, int total,
+                                                  const int *__restrict__ done) {
+  if (done && *done) return;
+  items_f64(segs, nseg, total, blockIdx.x * 4 + (threadIdx.x >> 6), gridDim.x * 4);
+}
+
+// Workgroups [0, nwhole) solve whole systems (wsegs: begin offsets in systems),
+// the others take the work items (segs), WHOLE_WAVES_F64 per workgroup.
+__global__ __launch_bounds__(WHOLE_WAVES_F64 * WAVE) void k_gemv_whole_f64(const Seg *__restrict__ segs, int nseg,
+                                                                 int total, const Seg *__restrict__ wsegs,
+                                                                 int nwhole, const int *__restrict__ done) {
+  extern __shared__ double ys_whole_d[];
+  if (done && *done) return;
+  if ((int)blockIdx.x < nwhole) {
+    const Seg &sg = seg_of(wsegs, nseg, blockIdx.x);
+    if (sg.done && *sg.done) return;
+    whole_f64(sg.sys[sg.whole[blockIdx.x - sg.begin]], ys_whole_d);
+    return;
+  }
+  items_f64(segs, nseg, total, (blockIdx.x - nwhole) * WHOLE_WAVES_F64 + (threadIdx.x >> 6),
+            (gridDim.x - nwhole) * WHOLE_WAVES_F64);
 }
 
 // FP32: 4 loads of 16 bytes per lane per tile; lane l holds rows 8m + l/8 (m < 4),
@@ -1203,22 +1217,12 @@ __device__ __forceinline__ void whole_f32(const SysDev &S, float *ys) {
   whole_finish<NW>(S, ys, 1.0);
 }
 
-__global__ __launch_bounds__(WHOLE_WAVES_NARROW * WAVE) void k_gemv_f32(const Seg *__restrict__ segs, int nseg,
-                                                                        int total, const Seg *__restrict__ wsegs,
-                                                                        int nwhole, const int *__restrict__ done) {
-  if (done && *done) return;
-  if ((int)blockIdx.x < nwhole) {
-    extern __shared__ float ysf[];
-    const Seg &sg = seg_of(wsegs, nseg, blockIdx.x);
-    if (sg.done && *sg.done) return;
-    whole_f32(sg.sys[sg.whole[blockIdx.x - sg.begin]], ysf);
-    return;
-  }
+
+__device__ __forceinline__ void items_f32(const Seg *__restrict__ segs, int nseg, int total, int g0,
+                                          int gstride) {
   const int lane = threadIdx.x & 63;
   const int grp = lane >> 3, c4 = (lane & 7) * 4;
-  const int ngrid = (int)gridDim.x - nwhole;
-  for (int g = (blockIdx.x - nwhole) * WHOLE_WAVES_NARROW + (threadIdx.x >> 6); g < total;
-       g += ngrid * WHOLE_WAVES_NARROW) {
+  for (int g = g0; g < total; g += gstride) {
     const Seg sg = segs[nseg == 1 ? 0 : find_seg(segs, nseg, g)];
     if (sg.done && *sg.done) continue;
     const GItem it = sg.items[g - sg.begin];
@@ -1289,6 +1293,30 @@ __global__ __launch_bounds__(WHOLE_WAVES_NARROW * WAVE) void k_gemv_f32(const Se
       for (int m = 0; m < 4; ++m) rowp[8 * m + grp] = acc[m];
     }
   }
+}
+
+// Work items only, one per wavefront.
+__global__ __launch_bounds__(256) void k_gemv_f32(const Seg *__restrict__ segs, int nseg, int total,
+                                                  const int *__restrict__ done) {
+  if (done && *done) return;
+  items_f32(segs, nseg, total, blockIdx.x * 4 + (threadIdx.x >> 6), gridDim.x * 4);
+}
+
+// Workgroups [0, nwhole) solve whole systems (wsegs: begin offsets in systems),
+// the others take the work items (segs), WHOLE_WAVES_NARROW per workgroup.
+__global__ __launch_bounds__(WHOLE_WAVES_NARROW * WAVE) void k_gemv_whole_f32(const Seg *__restrict__ segs, int nseg,
+                                                                 int total, const Seg *__restrict__ wsegs,
+                                                                 int nwhole, const int *__restrict__ done) {
+  extern __shared__ float ys_whole[];
+  if (done && *done) return;
+  if ((int)blockIdx.x < nwhole) {
+    const Seg &sg = seg_of(wsegs, nseg, blockIdx.x);
+    if (sg.done && *sg.done) return;
+    whole_f32(sg.sys[sg.whole[blockIdx.x - sg.begin]], ys_whole);
+    return;
+  }
+  items_f32(segs, nseg, total, (blockIdx.x - nwhole) * WHOLE_WAVES_NARROW + (threadIdx.x >> 6),
+            (gridDim.x - nwhole) * WHOLE_WAVES_NARROW);
 }
 
 // FP16 tiles (the inverse divided by a power-of-two scale per system, so every
@@ -1373,22 +1401,12 @@ __device__ __forceinline__ void whole_f16(const SysDev &S, float *ys) {
   whole_finish<NW>(S, ys, (double)S.scale);
 }
 
-__global__ __launch_bounds__(WHOLE_WAVES_NARROW * WAVE) void k_gemv_f16(const Seg *__restrict__ segs, int nseg,
-                                                                        int total, const Seg *__restrict__ wsegs,
-                                                                        int nwhole, const int *__restrict__ done) {
-  if (done && *done) return;
-  if ((int)blockIdx.x < nwhole) {
-    extern __shared__ float ysh[];
-    const Seg &sg = seg_of(wsegs, nseg, blockIdx.x);
-    if (sg.done && *sg.done) return;
-    whole_f16(sg.sys[sg.whole[blockIdx.x - sg.begin]], ysh);
-    return;
-  }
+
+__device__ __forceinline__ void items_f16(const Seg *__restrict__ segs, int nseg, int total, int g0,
+                                          int gstride) {
   const int lane = threadIdx.x & 63;
   const int grp = lane >> 2, c8 = (lane & 3) * 8;
-  const int ngrid = (int)gridDim.x - nwhole;
-  for (int g = (blockIdx.x - nwhole) * WHOLE_WAVES_NARROW + (threadIdx.x >> 6); g < total;
-       g += ngrid * WHOLE_WAVES_NARROW) {
+  for (int g = g0; g < total; g += gstride) {
     const Seg sg = segs[nseg == 1 ? 0 : find_seg(segs, nseg, g)];
     if (sg.done && *sg.done) continue;
     const GItem it = sg.items[g - sg.begin];
@@ -1464,6 +1482,30 @@ __global__ __launch_bounds__(WHOLE_WAVES_NARROW * WAVE) void k_gemv_f16(const Se
       for (int m = 0; m < 2; ++m) rowp[16 * m + grp] = acc[m];
     }
   }
+}
+
+// Work items only, one per wavefront.
+__global__ __launch_bounds__(256) void k_gemv_f16(const Seg *__restrict__ segs, int nseg, int total,
+                                                  const int *__restrict__ done) {
+  if (done && *done) return;
+  items_f16(segs, nseg, total, blockIdx.x * 4 + (threadIdx.x >> 6), gridDim.x * 4);
+}
+
+// Workgroups [0, nwhole) solve whole systems (wsegs: begin offsets in systems),
+// the others take the work items (segs), WHOLE_WAVES_NARROW per workgroup.
+__global__ __launch_bounds__(WHOLE_WAVES_NARROW * WAVE) void k_gemv_whole_f16(const Seg *__restrict__ segs, int nseg,
+                                                                 int total, const Seg *__restrict__ wsegs,
+                                                                 int nwhole, const int *__restrict__ done) {
+  extern __shared__ float ys_whole[];
+  if (done && *done) return;
+  if ((int)blockIdx.x < nwhole) {
+    const Seg &sg = seg_of(wsegs, nseg, blockIdx.x);
+    if (sg.done && *sg.done) return;
+    whole_f16(sg.sys[sg.whole[blockIdx.x - sg.begin]], ys_whole);
+    return;
+  }
+  items_f16(segs, nseg, total, (blockIdx.x - nwhole) * WHOLE_WAVES_NARROW + (threadIdx.x >> 6),
+            (gridDim.x - nwhole) * WHOLE_WAVES_NARROW);
 }
 
 // z_s[I*TILE + c] = sum of the row partials of tile row I + sum over I' > I of

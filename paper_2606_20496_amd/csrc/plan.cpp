@@ -677,10 +677,13 @@ void build_gemv_items(const Plan &P, const int *tiles_of_bucket, const int *buck
   // n_cu would form a last round that few compute units work on
   std::vector<int32_t> cand;
   for (int64_t s = 0; s < (int64_t)P.sys.size(); ++s)
-    if (P.sys[s].nb <= WHOLE_NB_MAX) cand.push_back((int32_t)s);
+    if (P.sys[s].nb >= WHOLE_NB_MIN && P.sys[s].nb <= WHOLE_NB_MAX) cand.push_back((int32_t)s);
   std::stable_sort(cand.begin(), cand.end(), [&](int32_t a, int32_t b) { return P.sys[a].nb > P.sys[b].nb; });
+  // fewer systems than compute units: one workgroup per system would leave most
+  // of the chip idle and make one unit stream a whole system, so every system
+  // goes to work items
   size_t keep = cand.size();
-  if (n_cu > 0 && keep > (size_t)n_cu) keep -= keep % (size_t)n_cu;
+  if (n_cu > 0) keep -= keep % (size_t)n_cu;
   std::vector<char> whole(P.sys.size(), 0);
   for (size_t i = 0; i < keep; ++i) whole[cand[i]] = 1;
   for (int64_t s = 0; s < (int64_t)P.sys.size(); ++s) {

@@ -15,9 +15,11 @@ constexpr int TILE = 32;
 constexpr int OP_BLOCK = 256;
 // Tiles per GEMV work item (one wavefront streams at most this many tiles).
 constexpr int GEMV_SEG = 4;
-// Systems with at most this many tile rows are solved by one workgroup each
-// (WHOLE_WAVES_F64 wavefronts for FP64 tiles, WHOLE_WAVES_NARROW for FP32/FP16);
-// larger ones are cut into work items.
+// Systems of WHOLE_NB_MIN to WHOLE_NB_MAX tile rows are solved by one workgroup
+// each (WHOLE_WAVES_F64 wavefronts for FP64 tiles, WHOLE_WAVES_NARROW for
+// FP32/FP16); the others are cut into work items (a smaller system does too
+// little work for a workgroup's fixed costs, a larger one too much for one unit).
+constexpr int WHOLE_NB_MIN = 16;
 constexpr int WHOLE_NB_MAX = 48;
 constexpr int WHOLE_WAVES_F64 = 4;
 constexpr int WHOLE_WAVES_NARROW = 8;
@@ -139,10 +141,10 @@ struct Plan {
 // Build the plan; returns 0 or a negative coarse_status (message in plan.err).
 int build_plan(const PlanInput &in, Plan &plan);
 
-// The dense-solve work of the systems of a plan. Systems with nb <= WHOLE_NB_MAX
-// go to `whole` (one workgroup each; the local systems largest first, then the
-// reduced system), as many as fill whole rounds of n_cu compute units (all of
-// them when there are fewer): the smallest of the rest, and every larger system,
+// The dense-solve work of the systems of a plan. Systems with WHOLE_NB_MIN <= nb
+// <= WHOLE_NB_MAX go to `whole` (one workgroup each; the local systems largest first, then the
+// reduced system), as many as fill whole rounds of n_cu compute units (none when
+// there are fewer than n_cu): the smallest of the rest, and every larger system,
 // have each tile row I cut into items of tiles_of_bucket[bucket(nb)] tiles
 // (bucket b: nb <= bucket_max[b]; a value < 1 means GEMV_SEG), whose partial sums
 // the row table combines.

@@ -94,3 +94,31 @@ def test_batch_rejects_mixed_precisions():
     while bt.live:
         bt.step(4)
     bt.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed16"])
+def test_batch_of_meshes_with_whole_system_solves(precision):
+    # meshes with at least one system per compute unit take their dense solves
+    # one workgroup per system (the 512 subdomains of 4^3 elements here, the small
+    # remainder as work items); batched, those workgroups of several solves share
+    # one launch, and each result is still bitwise the solo one
+    ms = [mg.box_mesh(32, 61 + k, block=4, boxes=(8, 8, 8), faces=("x0",)) for k in range(2)]
+    ms.append(mg.box_mesh(20, 63, block=4, boxes=(5, 5, 5), faces=("z1",)))
+    ref = _alone(ms, precision)
+    stream = torch.cuda.Stream()
+    solvers = [coarse.CoarseSolver.from_mesh(m, precision=precision) for m in ms]
+    bs = [torch.tensor(m.b, device="cuda") for m in ms]
+    us = [torch.zeros_like(b) for b in bs]
+    torch.cuda.synchronize()
+    bt = coarse.Batch(stream=stream, use_graph=True)
+    for k in range(len(ms)):
+        bt.submit(solvers[k], bs[k], us[k], tag=k)
+    done = {}
+    while bt.live > 0:
+        for tag, st in bt.step(2):
+            done[tag] = st
+    stream.synchronize()
+    bt.close()
+    for k, (u, iters) in enumerate(ref):
+        assert done[k]["code"] == 0 and done[k]["iters"] == iters
+        assert torch.equal(us[k], u), k
