@@ -126,10 +126,14 @@ typedef struct {
   int gemv_tiles[COARSE_GEMV_BUCKETS];
                     /* tiles per work item of the batched dense solve, per size
                        bucket of a system's tile count nb = ceil(n/32): bucket b
-                       holds nb <= coarse_gemv_bucket_max[b]. 0 = 4. Changes only
-                       the order of rounding inside a row sum and the speed; a
-                       context keeps its choice for life (results stay bitwise
-                       reproducible, alone or batched)                             */
+                       holds nb <= coarse_gemv_bucket_max[b]. 0 = 4. Used for the
+                       systems cut into work items: those outside 16..48 tile
+                       rows, all systems of a context with fewer systems than the
+                       device has compute units, and the smallest ones past a
+                       multiple of that count (the others are solved by one
+                       workgroup each). Changes only the order of rounding inside
+                       a row sum and the speed; a context keeps its choice for
+                       life (results stay bitwise reproducible, alone or batched) */
   int projection;   /* l >= 0 prior solutions kept for coarse_solve_projected
                        (Sec. 5); 0 = none. The basis takes 2 l n_free doubles of
                        device memory, allocated by the setup; l <=
