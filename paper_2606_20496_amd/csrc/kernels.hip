@@ -251,26 +251,7 @@ constexpr int VB = 256;
 // more loads in flight.
 constexpr int VW = 512;
 
-__global__ __launch_bounds__(VB) void k_permute_in(int64_t nf, const int32_t *__restrict__ user_of, const double *__restrict__ b,
-                                                   double *__restrict__ r, double *__restrict__ x, double *__restrict__ p,
-                                                   double *__restrict__ z, double *__restrict__ bint, double *__restrict__ part) {
-  __shared__ double red[VB / WAVE];
-  double acc = 0.0;
-  const int64_t G = (int64_t)gridDim.x * VB;
-  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < nf; i += G) {
-    const double v = b[user_of[i]];
-    r[i] = v;
-    bint[i] = v;
-    x[i] = 0.0;
-    p[i] = 0.0;
-    z[i] = 0.0;
-    acc += v * v;
-  }
-  const double s = block_sum<VB>(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
-}
-
-// in-place permutation of a caller vector into internal order (no reduction)
+// a caller vector gathered into internal order (no reduction)
 __global__ __launch_bounds__(VB) void k_gather_user(int64_t nf, const int32_t *__restrict__ user_of, const double *__restrict__ b,
                                                     double *__restrict__ r) {
   const int64_t G = (int64_t)gridDim.x * VB;
@@ -283,32 +264,6 @@ __global__ __launch_bounds__(VB) void k_permute_out(int64_t nv, int64_t nf, cons
   if (i >= nv) return;
   const int32_t k = vint_of[i];
   u[i] = (k < nf) ? x[k] : 0.0;
-}
-
-__global__ __launch_bounds__(VB) void k_update(int64_t nf, const Scalars *__restrict__ sc, double *__restrict__ x,
-                                               double *__restrict__ r, const double *__restrict__ p,
-                                               const double *__restrict__ q, double *__restrict__ part) {
-  __shared__ double red[VB / WAVE];
-  if (sc->done) return;
-  const double alpha = sc->alpha;
-  double acc = 0.0;
-  const int64_t G = (int64_t)gridDim.x * VB;
-  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < nf; i += G) {
-    x[i] += alpha * p[i];
-    const double ri = r[i] - alpha * q[i];
-    r[i] = ri;
-    acc += ri * ri;
-  }
-  const double s = block_sum<VB>(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
-}
-
-__global__ __launch_bounds__(VB) void k_pupdate(int64_t nf, const Scalars *__restrict__ sc, const double *__restrict__ z,
-                                                double *__restrict__ p) {
-  if (sc->done) return;
-  const double beta = sc->beta;
-  const int64_t G = (int64_t)gridDim.x * VB;
-  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < nf; i += G) p[i] = z[i] + beta * p[i];
 }
 
 // t = a - q
@@ -2104,12 +2059,6 @@ __global__ __launch_bounds__(256) void k_sweep_pack(const SweepSys *__restrict__
   }
 }
 
-template <typename T>
-__global__ void k_convert(int64_t n, const double *__restrict__ in, T *__restrict__ out) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) out[i] = (T)in[i];
-}
-
 // explicit instantiations used by the host code
 template __global__ void k_gather<double>(int64_t, const int *, const int32_t *, const double *, double *);
 template __global__ void k_gather<float>(int64_t, const int *, const int32_t *, const double *, float *);
@@ -2129,7 +2078,5 @@ template __global__ void k_sweep_pack<float>(const SweepSys *, const int32_t *, 
                                              const int64_t *, const double *, const float *, float *);
 template __global__ void k_sweep_pack<_Float16>(const SweepSys *, const int32_t *, const int16_t *, const int16_t *,
                                                 const int64_t *, const double *, const float *, _Float16 *);
-template __global__ void k_convert<float>(int64_t, const double *, float *);
-template __global__ void k_convert<double>(int64_t, const double *, double *);
 
 }  // namespace coarse
