@@ -235,9 +235,12 @@ struct coarse_ctx {
     pend(2);
   }
 
-  // workgroups of k_pre: the gather part and the J^T task part (each loops)
-  int pre_gather_blocks() const { return (int)std::min<int64_t>(nblk(coarse_vec_off, 256), 1024); }
-  int pre_task_blocks() const { return (int)std::min<int64_t>(nblk(ntask, 4), 512); }
+  // workgroups of k_pre: the gather part (one pass of UV entries per thread when
+  // that takes at most 1024 workgroups, else several) and the J^T task part (one
+  // task per wavefront, at most 2048 workgroups; both measured best on MI355X at
+  // 64^3 and 128^3)
+  int pre_gather_blocks() const { return (int)std::min<int64_t>(nblk(coarse_vec_off, 256 * UV), 1024); }
+  int pre_task_blocks() const { return (int)std::min<int64_t>(nblk(ntask, 4), 2048); }
 
   template <typename T>
   void corners(const int *done) {
