@@ -1279,6 +1279,13 @@ __global__ __launch_bounds__(WHOLE_WAVES_NARROW * WAVE) void k_gemv_whole_f32(co
 // lane l holds rows 16m + l/4 (m < 2), columns 8(l%4) .. 8(l%4)+7. The row and
 // column sums are multiplied back by the scale when written.
 typedef _Float16 nt_h8 __attribute__((ext_vector_type(8)));
+
+// FP16 tiles, whole systems (lane layout of k_gemv_f16 below: 2 rows x 8 columns
+// per lane). Here the triangle is walked by column strips instead of tile rows: a
+// lane's 8 columns need a sum over 16 lane groups, its 2 rows over only 4 lanes,
+// so the transposed contribution is kept per lane down the whole strip (summed
+// across lanes once per strip) and the per-tile cross-lane work is the short row
+// sum. The waves take the strips, longest first, in the snake order.
 __device__ __forceinline__ void whole_f16(const SysDev &S, float *ys) {
   constexpr int NW = WHOLE_WAVES_NARROW;
   float *y = whole_begin<NW>(S, ys);
@@ -1287,69 +1294,84 @@ __device__ __forceinline__ void whole_f16(const SysDev &S, float *ys) {
   const int nb = S.nb;
   const float *__restrict__ r = (const float *)S.rp;
   const nt_h8 *__restrict__ base = (const nt_h8 *)S.tiles;
-  int k = 0, I = snake_row<NW>(nb, w, 0), J = 0;
-  if (I >= 0) {
+  // the wavefront's column strips, longest first in a snake order over the waves:
+  // strip J holds tiles (I, J), I = J .. nb-1
+  auto strip = [&](int k) {
+    const int p = k * NW + ((k & 1) ? NW - 1 - w : w);
+    return p < nb ? p : -1;
+  };
+  int k = 0, J = strip(0), I = J;
+  if (J >= 0) {
     nt_h8 v[2], nv[2];
-    const nt_h8 *t = base + ((int64_t)I * (I + 1) / 2) * (TILE * TILE / 8);
+    auto load = [&](int ti, int tj, nt_h8 *dst) {
+      const nt_h8 *t = base + ((int64_t)ti * (ti + 1) / 2 + tj) * (TILE * TILE / 8);
 #pragma unroll
-    for (int m = 0; m < 2; ++m) v[m] = __builtin_nontemporal_load(t + m * 64 + lane);
-    float rI[2], acc[2];
-#pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      rI[m] = r[I * TILE + 16 * m + grp];
-      acc[m] = 0.0f;
-    }
-    for (;;) {
-      int nk, nI, nJ;
-      whole_next<NW>(nb, w, k, I, J, nk, nI, nJ);
-      const bool more = nI >= 0;
-      if (more) {
-        const nt_h8 *tn = base + ((int64_t)nI * (nI + 1) / 2 + nJ) * (TILE * TILE / 8);
-#pragma unroll
-        for (int m = 0; m < 2; ++m) nv[m] = __builtin_nontemporal_load(tn + m * 64 + lane);
-      }
+      for (int m = 0; m < 2; ++m) dst[m] = __builtin_nontemporal_load(t + m * 64 + lane);
+    };
+    load(I, J, v);
+    float rj[8], c[8];
+    {
       const float4 ra = *(const float4 *)(r + J * TILE + c8);
       const float4 rb = *(const float4 *)(r + J * TILE + c8 + 4);
-      const float rj[8] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w};
+      const float t8[8] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w};
 #pragma unroll
-      for (int m = 0; m < 2; ++m)
+      for (int e = 0; e < 8; ++e) rj[e] = t8[e];
+    }
 #pragma unroll
-        for (int q = 0; q < 8; ++q) acc[m] += (float)v[m][q] * rj[q];
-      if (J != I) {
-        float c[8];
+    for (int e = 0; e < 8; ++e) c[e] = 0.0f;
+    for (;;) {
+      int nk = k, nJ = J, nI = I + 1;
+      if (nI >= nb) {
+        nk = k + 1;
+        nJ = strip(nk);
+        nI = nJ;
+      }
+      const bool more = nJ >= 0;
+      if (more) load(nI, nJ, nv);
+      float rI[2];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) c[q] = (float)v[0][q] * rI[0] + (float)v[1][q] * rI[1];
+      for (int m = 0; m < 2; ++m) rI[m] = r[I * TILE + 16 * m + grp];
+      // row contribution of tile (I, J): summed over the 4 lanes of a row group
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          c[q] += __shfl_xor(c[q], 4, 64);
-          c[q] += __shfl_xor(c[q], 8, 64);
-          c[q] += __shfl_xor(c[q], 16, 64);
-          c[q] += __shfl_xor(c[q], 32, 64);
-        }
-        if (lane < 4) {
+      for (int m = 0; m < 2; ++m) {
+        float a = 0.0f;
 #pragma unroll
-          for (int q = 0; q < 8; ++q) y[J * TILE + c8 + q] += c[q];
-        }
-      } else {
+        for (int e = 0; e < 8; ++e) a += (float)v[m][e] * rj[e];
+        a += __shfl_xor(a, 1, 64);
+        a += __shfl_xor(a, 2, 64);
+        if ((lane & 3) == 0) y[I * TILE + 16 * m + grp] += a;
+      }
+      // transposed contribution, kept per lane down the strip
+      if (I != J) {
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-          float a = acc[m];
-          a += __shfl_xor(a, 1, 64);
-          a += __shfl_xor(a, 2, 64);
-          acc[m] = 0.0f;
-          if ((lane & 3) == 0) y[I * TILE + 16 * m + grp] += a;
+        for (int e = 0; e < 8; ++e) c[e] += (float)v[0][e] * rI[0] + (float)v[1][e] * rI[1];
+      }
+      if (nJ != J) {
+        // strip J complete
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          float a = c[e];
+          a += __shfl_xor(a, 4, 64);
+          a += __shfl_xor(a, 8, 64);
+          a += __shfl_xor(a, 16, 64);
+          a += __shfl_xor(a, 32, 64);
+          c[e] = 0.0f;
+          if (lane < 4) y[J * TILE + c8 + e] += a;
         }
         if (more) {
+          const float4 ra = *(const float4 *)(r + nJ * TILE + c8);
+          const float4 rb = *(const float4 *)(r + nJ * TILE + c8 + 4);
+          const float t8[8] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w};
 #pragma unroll
-          for (int m = 0; m < 2; ++m) rI[m] = r[nI * TILE + 16 * m + grp];
+          for (int e = 0; e < 8; ++e) rj[e] = t8[e];
         }
       }
       if (!more) break;
 #pragma unroll
       for (int m = 0; m < 2; ++m) v[m] = nv[m];
       k = nk;
-      I = nI;
       J = nJ;
+      I = nI;
     }
   }
   // the tiles hold A_s^{-1} / scale
