@@ -1280,6 +1280,18 @@ __global__ __launch_bounds__(WHOLE_WAVES_NARROW * WAVE) void k_gemv_whole_f32(co
 // column sums are multiplied back by the scale when written.
 typedef _Float16 nt_h8 __attribute__((ext_vector_type(8)));
 
+// DPP lane moves inside rows of 16 lanes (no LDS permute); lanes with no source read 0.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+// every lane of each group of 4 receives the group's sum, (v0 + v1) + (v2 + v3)
+__device__ __forceinline__ float quad_sum(float v) {
+  v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
+  return v;
+}
+
 // FP16 tiles, whole systems (lane layout of k_gemv_f16 below: 2 rows x 8 columns
 // per lane). Here the triangle is walked by column strips instead of tile rows: a
 // lane's 8 columns need a sum over 16 lane groups, its 2 rows over only 4 lanes,
@@ -1337,8 +1349,7 @@ __device__ __forceinline__ void whole_f16(const SysDev &S, float *ys) {
         float a = 0.0f;
 #pragma unroll
         for (int e = 0; e < 8; ++e) a += (float)v[m][e] * rj[e];
-        a += __shfl_xor(a, 1, 64);
-        a += __shfl_xor(a, 2, 64);
+        a = quad_sum(a);
         if ((lane & 3) == 0) y[I * TILE + 16 * m + grp] += a;
       }
       // transposed contribution, kept per lane down the strip
