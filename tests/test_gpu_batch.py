@@ -122,3 +122,31 @@ def test_batch_of_meshes_with_whole_system_solves(precision):
     for k, (u, iters) in enumerate(ref):
         assert done[k]["code"] == 0 and done[k]["iters"] == iters
         assert torch.equal(us[k], u), k
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed16"])
+def test_batch_of_reoriented_meshes(precision):
+    # elements of mixed local orientation: the grouped operator launch runs the
+    # incidence-list blocks of these solves beside the corner-by-corner blocks of
+    # a consistently oriented mesh; each result is bitwise the solo one
+    base = _meshes(3)
+    ms = [mg.reorient(base[0], 11), mg.reorient(base[1], 12), base[2]]
+    ref = _alone(ms, precision)
+    stream = torch.cuda.Stream()
+    solvers = [coarse.CoarseSolver.from_mesh(m, precision=precision) for m in ms]
+    assert solvers[0].info["n_inc_blocks"] > 0 and solvers[2].info["n_inc_blocks"] == 0
+    bs = [torch.tensor(m.b, device="cuda") for m in ms]
+    us = [torch.zeros_like(b) for b in bs]
+    torch.cuda.synchronize()
+    bt = coarse.Batch(stream=stream, use_graph=True)
+    for k in range(len(ms)):
+        bt.submit(solvers[k], bs[k], us[k], tag=k)
+    done = {}
+    while bt.live > 0:
+        for tag, st in bt.step(2):
+            done[tag] = st
+    stream.synchronize()
+    bt.close()
+    for k, (u, iters) in enumerate(ref):
+        assert done[k]["code"] == 0 and done[k]["iters"] == iters
+        assert torch.equal(us[k], u), k
