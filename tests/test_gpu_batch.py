@@ -98,12 +98,13 @@ def test_batch_rejects_mixed_precisions():
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed16"])
 def test_batch_of_meshes_with_whole_system_solves(precision):
-    # meshes with at least one system per compute unit take their dense solves
-    # one workgroup per system (the 512 subdomains of 4^3 elements here, the small
-    # remainder as work items); batched, those workgroups of several solves share
-    # one launch, and each result is still bitwise the solo one
-    ms = [mg.box_mesh(32, 61 + k, block=4, boxes=(8, 8, 8), faces=("x0",)) for k in range(2)]
-    ms.append(mg.box_mesh(20, 63, block=4, boxes=(5, 5, 5), faces=("z1",)))
+    # a mesh with a system per compute unit (256 subdomains of 8^3 elements, 23
+    # tile rows each) takes its dense solves one workgroup per system; one with
+    # fewer systems cuts them into work items; batched, both kinds share one
+    # launch, and each result is still bitwise the solo one
+    ms = [mg.box_mesh((64, 64, 32), 61, block=8, boxes=(8, 8, 4), faces=("x0",)),
+          mg.box_mesh((64, 40, 32), 62, block=8, boxes=(8, 5, 4), faces=("y1",)),
+          mg.box_mesh(20, 63, block=4, boxes=(5, 5, 5), faces=("z1",))]
     ref = _alone(ms, precision)
     stream = torch.cuda.Stream()
     solvers = [coarse.CoarseSolver.from_mesh(m, precision=precision) for m in ms]
