@@ -175,6 +175,10 @@ typedef struct {
   int32_t boxes[3];
   int32_t precision;
   int32_t gemv_tiles[COARSE_GEMV_BUCKETS];   /* work-item table the context uses     */
+  int32_t reduced_stream; /* 1: the reduced system has more than 48 tile rows of
+                             32, and the additive preconditioner solves it on a
+                             second stream beside the local systems (profile
+                             phase 7); 0: one dense-solve launch holds both     */
 } coarse_info_t;
 
 /* Fill *o with the defaults: overlap 1, boxes auto, FP64, additive, centroid J,
@@ -296,15 +300,19 @@ int coarse_set_stream(coarse_ctx *ctx, void *stream);
 
 /* Phase timers (HIP events on the context's stream around every launch of a
  * phase). enable != 0 is a bit mask of the phases to time (bit i = phase i;
- * 0x7F = all): it clears the accumulators and starts timing. enable = 0 waits for
+ * 0xFF = all): it clears the accumulators and starts timing. enable = 0 waits for
  * the stream, stops, and writes the accumulated milliseconds and launch counts of
  * the first nphase phases into ms[] and counts[] (either may be NULL).
  * Phases: 0 operator A (with the search-direction update), 1 restriction R_p
  * gather (with the first stage of J^T in the additive mode), 2 reduced
  * restriction J^T (corner sums), 3 batched dense solves A_p^{-1} and A_r^{-1} (the
  * tiled GEMV kernel alone), 4 partial-sum combine, 5 overlap sum + J
- * prolongation (with (r, z)), 6 PCG vector update. */
-#define COARSE_NPHASE 7
+ * prolongation (with (r, z)), 6 PCG vector update, 7 the reduced branch of the
+ * additive two-level preconditioner (J^T corner sums, the dense solve of A_r and
+ * its partial sums) when it runs on the context's second stream beside the local
+ * dense solves (coarse_info_t.reduced_stream; phases 3 and 4 then cover the local
+ * systems alone, and phase 2 is not used). */
+#define COARSE_NPHASE 8
 int coarse_profile(coarse_ctx *ctx, int enable, double *ms, int64_t *counts, int nphase);
 
 /* Host-only dry run of the combinatorial setup (no device is touched): fills

@@ -32,7 +32,8 @@ EXPORTS = ("coarse_default_opts", "coarse_setup", "coarse_apply_precond", "coars
            "coarse_setup_from_plan", "coarse_plan_destroy", "coarse_plan_set_gemv_tiles",
            "coarse_solve_projected", "coarse_projection_reset")
 
-PHASES = ("A+p", "R_p+J^T", "J^T corners", "A_p^-1/A_r^-1 gemv", "combine", "sum+J", "x,r update")
+PHASES = ("A+p", "R_p+J^T", "J^T corners", "A_p^-1/A_r^-1 gemv", "combine", "sum+J", "x,r update",
+          "reduced branch (second stream)")
 
 
 class CoarseError(RuntimeError):
@@ -92,7 +93,7 @@ class _Info(ctypes.Structure):
                 ("a_bytes", ctypes.c_int64), ("inv_alg_bytes", ctypes.c_int64),
                 ("n_jent", ctypes.c_int64), ("n_inc_blocks", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("boxes", ctypes.c_int32 * 3), ("precision", ctypes.c_int32),
-                ("gemv_tiles", ctypes.c_int32 * GEMV_BUCKETS)]
+                ("gemv_tiles", ctypes.c_int32 * GEMV_BUCKETS), ("reduced_stream", ctypes.c_int32)]
 
 
 _lib = None
@@ -385,7 +386,7 @@ class CoarseSolver:
     def projection_reset(self):
         self._check(self._L.coarse_projection_reset(self._ctx))
 
-    def profile_start(self, mask=0x7F):
+    def profile_start(self, mask=0xFF):
         """Time the phases whose bits are set in ``mask`` (bit i = PHASES[i])."""
         self._check(self._L.coarse_profile(self._ctx, int(mask), None, None, 0))
 

@@ -113,6 +113,10 @@ struct coarse_plan {
 struct coarse_ctx {
   std::string err;
   hipStream_t stream = nullptr;
+  // second stream of the additive preconditioner: the reduced-space branch (J^T
+  // corner sums, the dense solve of A_r) runs beside the local dense solves
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int precision = 0, mode = 0, interp = 0, max_it = 1000, check_every = 4, flexible = 0;
   int64_t nv = 0, ne = 0, nf = 0, n_r = 0, nent = 0, ntask = 0;
   int64_t n_local_sys = 0, vec_len = 0, coarse_vec_off = 0;
@@ -153,6 +157,10 @@ struct coarse_ctx {
   SysDev *sysdev = nullptr;
   Seg *seg_all = nullptr, *seg_local = nullptr, *seg_coarse = nullptr;
   Seg h_seg_all{}, h_seg_local{}, h_seg_coarse{};
+  // the reduced system is too large for one workgroup: its dense solve (work
+  // items and their partial sums) and the J^T corner sums run on the second
+  // stream beside the local dense solves
+  bool reduced_aside = false;
   int32_t *cover_ptr = nullptr, *cover_pos = nullptr;
 
   // reduced space
@@ -164,7 +172,7 @@ struct coarse_ctx {
   int bx1 = 1, bxy1 = 1;
 
   // phase timers
-  static constexpr int NPH = 7;
+  static constexpr int NPH = 8;
   int prof_mask = 0;
   double prof_ms[NPH] = {};
   int64_t prof_cnt[NPH] = {};
@@ -173,6 +181,12 @@ struct coarse_ctx {
   hipEvent_t ev_open[NPH] = {};
 
   ~coarse_ctx() {
+    if (aux) {
+      (void)hipStreamSynchronize(aux);
+      (void)hipStreamDestroy(aux);
+    }
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
     if (h_sc) (void)hipHostFree(h_sc);
     if (h_proj_count) (void)hipHostFree(h_proj_count);
     for (auto &p : ev_pending) {
@@ -192,17 +206,19 @@ struct coarse_ctx {
     ev_pool.pop_back();
     return e;
   }
-  void pbeg(int ph) {
+  void pbeg(int ph, hipStream_t s) {
     if (!((prof_mask >> ph) & 1)) return;
     ev_open[ph] = get_event();
-    HIPCHK(hipEventRecord(ev_open[ph], stream));
+    HIPCHK(hipEventRecord(ev_open[ph], s));
   }
-  void pend(int ph) {
+  void pend(int ph, hipStream_t s) {
     if (!((prof_mask >> ph) & 1)) return;
     hipEvent_t e = get_event();
-    HIPCHK(hipEventRecord(e, stream));
+    HIPCHK(hipEventRecord(e, s));
     ev_pending.push_back({ph, {ev_open[ph], e}});
   }
+  void pbeg(int ph) { pbeg(ph, stream); }
+  void pend(int ph) { pend(ph, stream); }
   // after the stream has been synchronised: fold finished event pairs in
   void pcollect() {
     for (auto &p : ev_pending) {
@@ -243,25 +259,35 @@ struct coarse_ctx {
   int pre_task_blocks() const { return (int)std::min<int64_t>(nblk(ntask, 4), 2048); }
 
   template <typename T>
-  void corners(const int *done) {
-    hipLaunchKernelGGL(k_jt_corners<T>, dim3(nblk(n_r, 4)), dim3(256), 0, stream, n_r, done, jr_ptr, jr_src,
+  void corners(const int *done, hipStream_t s) {
+    hipLaunchKernelGGL(k_jt_corners<T>, dim3(nblk(n_r, 4)), dim3(256), 0, s, n_r, done, jr_ptr, jr_src,
                        (const T *)jt_part, (T *)rp + coarse_vec_off);
   }
+  template <typename T>
+  void corners(const int *done) {
+    corners<T>(done, stream);
+  }
 
-  void gemv_combine(const Seg *segs, int nitems, int nrows, int nwhole, const int *done) {
+  // the dense solves of a segment and the partial sums of its work items, on
+  // stream s; ph_gemv / ph_comb < 0: not timed
+  void gemv_combine(const Seg *segs, int nitems, int nrows, int nwhole, const int *done, hipStream_t s, int ph_gemv,
+                    int ph_comb) {
     if (nitems <= 0 && nwhole <= 0) return;
-    pbeg(3);
-    launch_gemv(stream, precision, segs, 1, nitems, segs, nwhole, whole_lds, done);
-    pend(3);
+    if (ph_gemv >= 0) pbeg(ph_gemv, s);
+    launch_gemv(s, precision, segs, 1, nitems, segs, nwhole, whole_lds, done);
+    if (ph_gemv >= 0) pend(ph_gemv, s);
     if (nrows <= 0) return;
-    pbeg(4);
+    if (ph_comb >= 0) pbeg(ph_comb, s);
     if (precision == COARSE_FP64)
-      hipLaunchKernelGGL(k_combine<double>, dim3(nblk((int64_t)nrows * TILE, 256)), dim3(256), 0, stream, segs, 1,
-                         nrows, done);
+      hipLaunchKernelGGL(k_combine<double>, dim3(nblk((int64_t)nrows * TILE, 256)), dim3(256), 0, s, segs, 1, nrows,
+                         done);
     else
-      hipLaunchKernelGGL(k_combine<float>, dim3(nblk((int64_t)nrows * TILE, 256)), dim3(256), 0, stream, segs, 1,
-                         nrows, done);
-    pend(4);
+      hipLaunchKernelGGL(k_combine<float>, dim3(nblk((int64_t)nrows * TILE, 256)), dim3(256), 0, s, segs, 1, nrows,
+                         done);
+    if (ph_comb >= 0) pend(ph_comb, s);
+  }
+  void gemv_combine(const Seg *segs, int nitems, int nrows, int nwhole, const int *done) {
+    gemv_combine(segs, nitems, nrows, nwhole, done, stream, 3, 4);
   }
 
   // scal: count the iteration in the solver state (PCG); start: first application
@@ -287,9 +313,32 @@ struct coarse_ctx {
                          (int)ntask, jt_start, jc_vid, (const T *)jc_w, (const T *)jc_xi, nent, (T *)jt_part,
                          chk ? sc : nullptr, chk, nvblk, start);
       pend(1);
-      pbeg(2);
-      corners<T>(done);
-      pend(2);
+      if (!reduced_aside) {
+        // a reduced system of at most WHOLE_NB_MAX tile rows joins the local
+        // systems in one dense-solve launch
+        pbeg(2);
+        corners<T>(done);
+        pend(2);
+        gemv_combine(seg_all, items_total, rows_total, whole_total, done);
+        final_step<T>(add, local, coarse, out, rdot, p1, p2, done, scal, start);
+        return;
+      }
+      // the reduced-space branch (J^T corner sums, the dense solve of A_r and its
+      // partial sums) on the second stream, beside the local dense solves; the
+      // two meet before the overlap sum. Across hardware queues each of the two
+      // waits costs some microseconds, which a large reduced system (its long
+      // tile rows end the fused launch late, and its partial sums need a combine
+      // pass) repays and a small one does not.
+      HIPCHK(hipEventRecord(ev_fork, stream));
+      HIPCHK(hipStreamWaitEvent(aux, ev_fork, 0));
+      pbeg(7, aux);
+      corners<T>(done, aux);
+      gemv_combine(seg_coarse, items_total - items_local, rows_total - rows_local, whole_total - whole_local, done, aux,
+                   -1, -1);
+      pend(7, aux);
+      HIPCHK(hipEventRecord(ev_join, aux));
+      gemv_combine(seg_local, items_local, rows_local, whole_local, done);
+      HIPCHK(hipStreamWaitEvent(stream, ev_join, 0));
     } else {
       if (chk) hipLaunchKernelGGL(k_check, dim3(1), dim3(256), 0, stream, sc, chk, nvblk, start);
       if (local) {
@@ -300,11 +349,9 @@ struct coarse_ctx {
       }
       if (coarse) restrict_coarse<T>(in, done);
     }
-    if (local && coarse)
-      gemv_combine(seg_all, items_total, rows_total, whole_total, done);
-    else if (local)
+    if (local && !coarse)
       gemv_combine(seg_local, items_local, rows_local, whole_local, done);
-    else
+    else if (coarse && !local)
       gemv_combine(seg_coarse, items_total - items_local, rows_total - rows_local, whole_total - whole_local, done);
     final_step<T>(add, local, coarse, out, rdot, p1, p2, done, scal, start);
   }
@@ -826,6 +873,7 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
   c->h_seg_coarse = Seg{c->items + il, c->rows + rl, c->whole + c->whole_local, c->sysdev, nullptr, 0, 0};
   c->seg_all = A.upload(std::vector<Seg>{c->h_seg_all}, s);
   c->seg_local = A.upload(std::vector<Seg>{c->h_seg_local}, s);
+  c->reduced_aside = P.n_r > 0 && P.sys[P.n_local_sys].nb > WHOLE_NB_MAX;
   c->seg_coarse = A.upload(std::vector<Seg>{c->h_seg_coarse}, s);
 
   // reduced-space interpolation entries
@@ -876,6 +924,7 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
   for (int d = 0; d < 3; ++d) in.boxes[d] = P.b[d];
   in.precision = c->precision;
   for (int b = 0; b < COARSE_GEMV_BUCKETS; ++b) in.gemv_tiles[b] = c->gemv_tiles[b];
+  in.reduced_stream = c->reduced_aside ? 1 : 0;
 }
 
 coarse_ctx *as_ctx(const coarse_ctx *c) { return const_cast<coarse_ctx *>(c); }
@@ -1275,6 +1324,9 @@ int coarse_setup_from_plan(const coarse_plan *plan, void *stream, coarse_ctx **o
   c->flexible = o.flexible ? 1 : 0;
   c->proj_max = o.projection;
   try {
+    HIPCHK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     HIPCHK(hipHostMalloc((void **)&c->h_sc, sizeof(Scalars), hipHostMallocDefault));
     if (o.precision == COARSE_FP64)
       setup_precision<double, double>(c.get(), P, o.gemv_tiles);

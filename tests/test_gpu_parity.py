@@ -47,7 +47,24 @@ SMALL = [
     ("one_sub", lambda: mg.box_mesh(6, 23, block=6, boxes=(2, 2, 2), faces=("z0",))),
     # elements of mixed local orientation: operator blocks sum through incidence lists
     ("reoriented", lambda: mg.reorient(mg.box_mesh((10, 9, 7), 21, block=4, boxes=(3, 3, 2), faces=("y1",)), 7)),
+    # 1859 reduced unknowns (59 tile rows): the reduced branch runs on a second stream
+    ("big_reduced", lambda: mg.box_mesh((24, 24, 20), 24, block=2, boxes=(12, 12, 10), faces=("x1",))),
 ]
+
+
+def test_reduced_branch_stream_choice():
+    # a reduced system of more than 48 tile rows is solved on the second stream
+    # (profile phase 7, no separate corner-sum phase); a smaller one shares the
+    # dense-solve launch of the local systems
+    for make, aside in ((SMALL[-1][1], 1), (mg.small_cube, 0)):
+        m = make()
+        S = coarse.CoarseSolver.from_mesh(m)
+        assert S.info["reduced_stream"] == aside
+        S.profile_start()
+        S.apply_precond(_gpu(np.ones(m.n_vert)))
+        ph = S.profile_stop()
+        assert ph[coarse.PHASES[7]][1] == aside and ph[coarse.PHASES[2]][1] == 1 - aside
+        assert ph[coarse.PHASES[3]][1] == 1
 
 
 @pytest.mark.parametrize("name,make", SMALL, ids=[s[0] for s in SMALL])
