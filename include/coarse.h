@@ -104,6 +104,8 @@ typedef struct {
 
 /* Largest basis of prior solutions a context may keep (opts.projection). */
 #define COARSE_PROJECTION_MAX 64
+/* right-hand sides of one block solve (coarse_solve_multi) */
+#define COARSE_MULTI_MAX 16
 
 /* Size buckets of the work-item table (upper bounds on nb; the last is open). */
 #define COARSE_GEMV_BUCKETS 8
@@ -247,6 +249,28 @@ int coarse_solve_projected(coarse_ctx *ctx, const double *b, double *u, double t
 /* Forget the stored prior solutions (the next coarse_solve_projected starts from
  * u_0 = 0). Errors: EINVAL. */
 int coarse_projection_reset(coarse_ctx *ctx);
+
+/* Block solve: k right-hand sides on the context's mesh (1 <= k <=
+ * COARSE_MULTI_MAX), k independent PCG recurrences (Sec. 2, the same iteration
+ * as coarse_solve for each column, to the same tolerance) advanced together so
+ * that every read of the element matrices and of the stored dense inverses
+ * serves all of them: the dense solves of the additive preconditioner (Sec. 3,
+ * eq. (asm), and the reduced solve of Sec. 4) become products of each inverse
+ * with a 16-column block, on the matrix cores. A column stops changing once it
+ * has converged; the others go on. b, u: device float64 [k][n_vert] (column j at
+ * offset j * n_vert), b != u. st: NULL or k entries, one per column (t_solve is
+ * the block's). Needs an FP64 context in the additive mode (else EINVAL). The
+ * first call allocates the block's vectors (about 9 * 16 doubles per free
+ * vertex) for the context's life. Returns the worst column status, as
+ * coarse_solve. Results per column are bitwise reproducible and independent of
+ * the other columns, but not bitwise those of coarse_solve (another summation
+ * order inside the dense solves). */
+int coarse_solve_multi(coarse_ctx *ctx, int k, const double *b, double *u, double tol, coarse_stats *st);
+
+/* z_j = M r_j for the k columns of r (the additive preconditioner of
+ * coarse_solve_multi); r, z: device float64 [k][n_vert], r != z. Errors as
+ * coarse_solve_multi. */
+int coarse_apply_precond_multi(coarse_ctx *ctx, int k, const double *r, double *z);
 
 /* Solve `count` independent systems (any mix of contexts, each with its own right-
  * hand side) in lock step: every PCG phase of all live systems is issued before

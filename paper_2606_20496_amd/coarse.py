@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libcoarse.so")
 
 PRECISION = {"fp64": 0, "mixed": 1, "mixed16": 2}
 PROJECTION_MAX = 64   # COARSE_PROJECTION_MAX: largest basis of prior solutions
+MULTI_MAX = 16        # COARSE_MULTI_MAX: right-hand sides of one block solve
 MODE = {"additive": 0, "hybrid_sym": 1, "local_only": 2, "reduced_only": 3}
 INTERP = {"centroid": 0, "standard": 1}
 STATUS = {0: "ok", 1: "notconv", -1: "einval", -2: "enomem", -3: "emesh", -4: "esingular",
@@ -30,7 +31,8 @@ EXPORTS = ("coarse_default_opts", "coarse_setup", "coarse_apply_precond", "coars
            "coarse_last_error", "coarse_profile", "coarse_batch_create", "coarse_batch_submit",
            "coarse_batch_step", "coarse_batch_live", "coarse_batch_destroy", "coarse_plan_create",
            "coarse_setup_from_plan", "coarse_plan_destroy", "coarse_plan_set_gemv_tiles",
-           "coarse_solve_projected", "coarse_projection_reset")
+           "coarse_solve_projected", "coarse_projection_reset", "coarse_solve_multi",
+           "coarse_apply_precond_multi")
 
 PHASES = ("A+p", "R_p+J^T", "J^T corners", "A_p^-1/A_r^-1 gemv", "combine", "sum+J", "x,r update",
           "reduced branch (second stream)")
@@ -127,6 +129,10 @@ def load():
     L.coarse_solve_projected.restype = i32
     L.coarse_projection_reset.argtypes = [vp]
     L.coarse_projection_reset.restype = i32
+    L.coarse_solve_multi.argtypes = [vp, i32, vp, vp, dbl, ctypes.POINTER(_Stats)]
+    L.coarse_solve_multi.restype = i32
+    L.coarse_apply_precond_multi.argtypes = [vp, i32, vp, vp]
+    L.coarse_apply_precond_multi.restype = i32
     L.coarse_solve_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i32, dbl,
                                      ctypes.POINTER(_Stats)]
     L.coarse_solve_batch.restype = i32
@@ -382,6 +388,44 @@ class CoarseSolver:
         projection onto the stored prior solutions, which then take in this one
         (needs ``projection`` >= 1 at construction)."""
         return self._solve(self._L.coarse_solve_projected, b, tol, out)
+
+    def _block(self, v):
+        import torch
+        if not (isinstance(v, torch.Tensor) and v.is_cuda and v.dtype == torch.float64 and v.is_contiguous()
+                and v.dim() == 2 and v.shape[1] == self.n_vert and 1 <= v.shape[0] <= MULTI_MAX):
+            raise ValueError(f"expected a contiguous float64 GPU tensor [k, n_vert], 1 <= k <= {MULTI_MAX}")
+        return ctypes.c_void_p(v.data_ptr())
+
+    def solve_multi(self, B, tol=1e-8, out=None):
+        """Block solve of the k = B.shape[0] right-hand sides (rows of B): k PCG
+        recurrences that share every read of the operator and of the stored
+        inverses (FP64, additive mode). Returns (U, [stats per column])."""
+        import torch
+        self._sync_stream()
+        out = torch.empty_like(B) if out is None else out
+        k = int(B.shape[0]) if B.dim() == 2 else 0
+        st = (_Stats * max(k, 1))()
+        pb, pu = self._block(B), self._block(out)
+        if out.shape != B.shape or out.data_ptr() == B.data_ptr():
+            raise ValueError("out must be a distinct tensor of the shape of B")
+        rc = self._check(self._L.coarse_solve_multi(self._ctx, k, pb, pu, float(tol), st))
+        stats = []
+        for j in range(k):
+            d = {f: getattr(st[j], f) for f, _ in _Stats._fields_}
+            d["code"] = rc
+            stats.append(d)
+        return out, stats
+
+    def apply_precond_multi(self, R, out=None):
+        """z_j = M r_j for the rows of R (the block form of apply_precond)."""
+        import torch
+        self._sync_stream()
+        out = torch.empty_like(R) if out is None else out
+        pr, pz = self._block(R), self._block(out)
+        if out.shape != R.shape or out.data_ptr() == R.data_ptr():
+            raise ValueError("out must be a distinct tensor of the shape of R")
+        self._check(self._L.coarse_apply_precond_multi(self._ctx, int(R.shape[0]), pr, pz))
+        return out
 
     def projection_reset(self):
         self._check(self._L.coarse_projection_reset(self._ctx))

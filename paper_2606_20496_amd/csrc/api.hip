@@ -1,6 +1,7 @@
 // C-ABI of the coarse solver: context setup, preconditioner application and
 // PCG, orchestrating the kernels of kernels.hip on one HIP stream.
 #include "kernels.hip"
+#include "multi.hip"
 
 #include <algorithm>
 #include <chrono>
@@ -171,6 +172,23 @@ struct coarse_ctx {
   double *yfull = nullptr;   // reduced solution on all (b+1)^3 box vertices (0 where inactive)
   int bx1 = 1, bxy1 = 1;
 
+  // block solve of up to MC right-hand sides (FP64 contexts; buffers allocated
+  // at its first use)
+  std::vector<MSys> h_msys;   // per system: tiles, packed offset, size
+  int64_t n_bv = 0, n_partials = 0, max_slots = 0;
+  struct Multi {
+    bool ready = false;
+    double *X = nullptr, *R = nullptr, *Pa = nullptr, *Pb = nullptr, *Z = nullptr, *Q = nullptr, *B = nullptr;
+    double *RP = nullptr, *ZP = nullptr, *tpart = nullptr, *yfull = nullptr, *partials = nullptr;
+    double *part = nullptr, *energy = nullptr;
+    MScal *ms = nullptr;
+    MScal *h_ms = nullptr;   // pinned host copy
+    int2 *rows = nullptr;
+    MSys *sys = nullptr;
+    int nrows = 0, nvb = 1, ng = 1, nt = 1, last_iters = 0;
+    int32_t lds = 0;
+  } mb;
+
   // phase timers
   static constexpr int NPH = 8;
   int prof_mask = 0;
@@ -189,6 +207,7 @@ struct coarse_ctx {
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (h_sc) (void)hipHostFree(h_sc);
     if (h_proj_count) (void)hipHostFree(h_proj_count);
+    if (mb.h_ms) (void)hipHostFree(mb.h_ms);
     for (auto &p : ev_pending) {
       ev_pool.push_back(p.second.first);
       ev_pool.push_back(p.second.second);
@@ -496,6 +515,121 @@ struct coarse_ctx {
     hipLaunchKernelGGL(k_res_total, dim3(1), dim3(VB), 0, stream, sc, (const double *)part1, nvblk);
     hipLaunchKernelGGL(k_permute_out, dim3(nblk(nv, VB)), dim3(VB), 0, stream, nv, nf, vint_of_user, x, u);
     HIPCHK(hipMemcpyAsync(h_sc, sc, sizeof(Scalars), hipMemcpyDeviceToHost, stream));
+  }
+
+  // ---- block solve (up to MC right-hand sides; FP64, additive) ---------------
+  void m_init() {
+    if (mb.ready) return;
+    hipStream_t s = stream;
+    Arena &A = arena;
+    const int64_t nfm = nf * MC;
+    mb.X = A.alloc<double>(nfm);
+    mb.R = A.alloc<double>(nfm);
+    mb.Pa = A.alloc<double>(nfm);
+    mb.Pb = A.alloc<double>(nfm);
+    mb.Z = A.alloc<double>(nfm);
+    mb.Q = A.alloc<double>(nfm);
+    mb.B = A.alloc<double>(nfm);
+    mb.RP = A.alloc<double>(vec_len * MC);
+    mb.ZP = A.alloc<double>(vec_len * MC);
+    mb.tpart = A.alloc<double>(std::max<int64_t>(1, ntask) * 8 * MC);
+    mb.yfull = A.alloc<double>(std::max<int64_t>(1, n_bv) * MC);
+    mb.partials = A.alloc<double>(std::max<int64_t>(1, n_partials) * MC);
+    mb.nvb = (int)std::min<int64_t>(1024, nblk(nfm, 256));
+    mb.ng = (int)std::min<int64_t>(1024, nblk(coarse_vec_off * MC, 256));
+    mb.nt = (int)std::min<int64_t>(2048, nblk(ntask, 4));
+    mb.part = A.alloc<double>((size_t)mb.nvb * MC);
+    mb.energy = A.alloc<double>(std::max<int64_t>(1, op.n_blocks) * MC);
+    mb.ms = A.alloc<MScal>(1);
+    // packing pads and inactive box vertices are never written and stay 0
+    HIPCHK(hipMemsetAsync(mb.RP, 0, vec_len * MC * sizeof(double), s));
+    HIPCHK(hipMemsetAsync(mb.ZP, 0, vec_len * MC * sizeof(double), s));
+    HIPCHK(hipMemsetAsync(mb.yfull, 0, std::max<int64_t>(1, n_bv) * MC * sizeof(double), s));
+    HIPCHK(hipMemsetAsync(mb.ms, 0, sizeof(MScal), s));
+    // one wavefront per tile row; rows of the largest systems first
+    std::vector<int32_t> order(h_msys.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = (int32_t)k;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return h_msys[a].nb > h_msys[b].nb; });
+    std::vector<int2> rows;
+    for (int32_t k : order)
+      for (int32_t I = 0; I < h_msys[k].nb; ++I) rows.push_back(make_int2(k, I));
+    mb.nrows = (int)rows.size();
+    mb.rows = A.upload(rows, s);
+    mb.sys = A.upload(h_msys, s);
+    HIPCHK(hipHostMalloc((void **)&mb.h_ms, sizeof(MScal), hipHostMallocDefault));
+    mb.lds = (int32_t)((OP_BLOCK * 8 + max_slots * MCW) * sizeof(double));
+    mb.ready = true;
+  }
+
+  void m_scal(const double *part, int n, int step) {
+    hipLaunchKernelGGL(k_m_scal, dim3(1), dim3(256), 0, stream, mb.ms, part, n, step);
+  }
+
+  // Z = M R for every column (additive two-level preconditioner)
+  void m_precond() {
+    pbeg(1);
+    hipLaunchKernelGGL(k_m_pre, dim3(mb.ng + mb.nt), dim3(256), 0, stream, mb.ng, coarse_vec_off,
+                       (const int32_t *)sub_idx, (const double *)mb.R, mb.RP, (int)ntask, (const int32_t *)jt_start,
+                       (const int32_t *)jc_vid, (const double *)jc_w, (const double *)jc_xi, nent, mb.tpart,
+                       (const MScal *)mb.ms);
+    pend(1);
+    pbeg(2);
+    hipLaunchKernelGGL(k_m_corners, dim3(nblk(n_r * MC, 256)), dim3(256), 0, stream, n_r, (const int32_t *)jr_ptr,
+                       (const int32_t *)jr_src, (const double *)mb.tpart, mb.RP + coarse_vec_off * MC,
+                       (const MScal *)mb.ms);
+    pend(2);
+    pbeg(3);
+    hipLaunchKernelGGL(k_m_gemv, dim3(nblk(mb.nrows, 4)), dim3(256), 0, stream, (const int2 *)mb.rows, mb.nrows,
+                       (const MSys *)mb.sys, (const double *)mb.RP, mb.ZP, mb.yfull, (const int32_t *)act_bv,
+                       (const MScal *)mb.ms);
+    pend(3);
+    pbeg(5);
+    hipLaunchKernelGGL(k_m_final, dim3(mb.nvb), dim3(256), 0, stream, nf, (const int32_t *)cover_ptr,
+                       (const int32_t *)cover_pos, (const double *)mb.ZP, (const int32_t *)jv_ptr,
+                       (const int32_t *)jv_base, (const double *)jv_w, (const double *)jv_xi, nent, bx1, bxy1,
+                       (const double *)mb.yfull, mb.Z, (const double *)mb.R, mb.part, (const MScal *)mb.ms);
+    pend(5);
+  }
+
+  // r = b for the k columns, x = 0, z_0 = M r_0, rho_0, beta_0 = 0
+  void m_start(const double *b, int k, double tol) {
+    hipLaunchKernelGGL(k_m_start, dim3(mb.nvb), dim3(256), 0, stream, nf, nv, (const int32_t *)user_of_vint, b, k,
+                       mb.R, mb.X, mb.Pa, mb.Pb, mb.Z, mb.B, mb.part, mb.ms, tol * tol, max_it);
+    m_scal(mb.part, mb.nvb, MS_BB);
+    m_precond();
+    m_scal(mb.part, mb.nvb, MS_RZ);
+  }
+
+  // one PCG iteration of every live column
+  void m_iteration() {
+    pbeg(0);
+    hipLaunchKernelGGL(k_m_op, dim3((unsigned)op.n_blocks), dim3(OP_BLOCK), mb.lds, stream, op,
+                       (const double *)mb.Z, mb.Pa, mb.Pb, mb.Q, mb.partials, mb.energy, (const MScal *)mb.ms, 1);
+    pend(0);
+    m_scal(mb.energy, (int)op.n_blocks, MS_PQ);
+    pbeg(6);
+    hipLaunchKernelGGL(k_m_update, dim3(mb.nvb), dim3(256), 0, stream, nf, op, (const double *)mb.partials,
+                       (const MScal *)mb.ms, mb.X, mb.R, (const double *)mb.Pa, (const double *)mb.Pb,
+                       (const double *)mb.Q, mb.part);
+    pend(6);
+    m_scal(mb.part, mb.nvb, MS_RR);
+    m_precond();
+    m_scal(mb.part, mb.nvb, MS_RZ);
+  }
+
+  // true residuals, the k solutions in caller order, the state to the host
+  void m_finish(double *u, int k) {
+    hipLaunchKernelGGL(k_m_op, dim3((unsigned)op.n_blocks), dim3(OP_BLOCK), mb.lds, stream, op, (const double *)mb.X,
+                       nullptr, nullptr, mb.Q, mb.partials, nullptr, (const MScal *)mb.ms, 0);
+    if (op.n_shared > 0)
+      hipLaunchKernelGGL(k_m_op_pass2, dim3(nblk(op.n_shared * MC, 256)), dim3(256), 0, stream, op,
+                         (const double *)mb.partials, mb.Q);
+    hipLaunchKernelGGL(k_m_resnorm, dim3(mb.nvb), dim3(256), 0, stream, nf, (const double *)mb.B,
+                       (const double *)mb.Q, mb.part);
+    m_scal(mb.part, mb.nvb, MS_RES);
+    hipLaunchKernelGGL(k_m_permute_out, dim3(nblk(nv * k, 256)), dim3(256), 0, stream, nv, nf,
+                       (const int32_t *)vint_of_user, (const double *)mb.X, k, u);
+    HIPCHK(hipMemcpyAsync(mb.h_ms, mb.ms, sizeof(MScal), hipMemcpyDeviceToHost, stream));
   }
 
   void fill_stats(coarse_stats *st, double t0) {
@@ -829,6 +963,22 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
     sd[k].yfull = red_sys ? c->yfull : nullptr;
     sd[k].act_bv = red_sys ? c->act_bv : nullptr;
   }
+  if (std::is_same<TT, double>::value) {
+    c->h_msys.resize(P.sys.size());
+    for (size_t k = 0; k < P.sys.size(); ++k) {
+      const System &S = P.sys[k];
+      MSys &m = c->h_msys[k];
+      m.tiles = (const double *)sd[k].tiles;
+      m.voff = S.vec_off;
+      m.nb = (int32_t)S.nb;
+      m.n = (int32_t)S.n;
+      m.red = (int64_t)k == P.n_local_sys ? 1 : 0;
+      m.pad = 0;
+    }
+  }
+  c->n_bv = P.n_bv;
+  c->n_partials = P.n_partials;
+  c->max_slots = P.max_slots;
   // item slots: index within the system's item list
   std::vector<int64_t> sys_item0(P.sys.size(), -1);
   for (size_t i = 0; i < G.items.size(); ++i)
@@ -1197,6 +1347,22 @@ int run_solve(coarse_ctx *c, const double *b, double *u, double tol, coarse_stat
   return status;
 }
 
+int check_multi(coarse_ctx *c, int k) {
+  if (k < 1 || k > COARSE_MULTI_MAX) {
+    c->err = "the block solve takes 1 to COARSE_MULTI_MAX right-hand sides";
+    return COARSE_EINVAL;
+  }
+  if (c->precision != COARSE_FP64 || c->mode != COARSE_ADDITIVE || c->h_msys.empty()) {
+    c->err = "the block solve needs an FP64 context with the additive preconditioner";
+    return COARSE_EINVAL;
+  }
+  if ((OP_BLOCK * 8 + c->max_slots * MCW) * (int64_t)sizeof(double) > 65536) {
+    c->err = "operator blocks with too many distinct vertices for the block solve";
+    return COARSE_EINVAL;
+  }
+  return COARSE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1379,6 +1545,71 @@ int coarse_apply_A(coarse_ctx *c, const double *p, double *q) {
 int coarse_solve(coarse_ctx *c, const double *b, double *u, double tol, coarse_stats *st) {
   if (!c || !b || !u || b == u || !(tol > 0)) return COARSE_EINVAL;
   return run_solve(c, b, u, tol, st, false);
+}
+
+int coarse_solve_multi(coarse_ctx *c, int k, const double *b, double *u, double tol, coarse_stats *st) {
+  if (!c || !b || !u || b == u || !(tol > 0)) return COARSE_EINVAL;
+  int rc = check_multi(c, k);
+  if (rc) return rc;
+  const double t0 = now();
+  try {
+    c->m_init();
+    c->m_start(b, k, tol);
+    int batch = std::max(c->check_every, c->mb.last_iters);
+    for (;;) {
+      for (int j = 0; j < batch; ++j) c->m_iteration();
+      batch = c->check_every;
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(c->mb.h_ms, c->mb.ms, sizeof(MScal), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      c->pcollect();
+      if (c->mb.h_ms->all_done) break;
+    }
+    c->m_finish(u, k);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->pcollect();
+  } catch (const Fail &f) {
+    return fail_ctx(c, f);
+  }
+  const MScal &m = *c->mb.h_ms;
+  int worst = COARSE_OK, most = 0;
+  for (int j = 0; j < k; ++j) {
+    most = std::max(most, m.iters[j]);
+    const int s = m.status[j];
+    if (s < 0 || (s > 0 && worst == COARSE_OK)) worst = s;
+    if (!st) continue;
+    coarse_stats &o = st[j];
+    o.iters = m.iters[j];
+    o.status = s;
+    o.relres = m.bb[j] > 0 ? std::sqrt(m.rr[j] / m.bb[j]) : 0.0;
+    o.relres_true = m.bb[j] > 0 ? std::sqrt(m.res_true[j] / m.bb[j]) : 0.0;
+    o.relres0 = m.bb[j] > 0 ? std::sqrt(m.rr0[j] / m.bb[j]) : 0.0;
+    o.n_basis = 0;
+    o.t_setup = c->t_setup;
+    o.t_solve = now() - t0;
+  }
+  c->mb.last_iters = most;
+  if (worst == -6) c->err = "PCG breakdown (p.Ap <= 0 or non-finite value)";
+  if (worst == 1) c->err = "iteration limit reached";
+  return worst;
+}
+
+int coarse_apply_precond_multi(coarse_ctx *c, int k, const double *r, double *z) {
+  if (!c || !r || !z || r == z) return COARSE_EINVAL;
+  int rc = check_multi(c, k);
+  if (rc) return rc;
+  try {
+    c->m_init();
+    c->m_start(r, k, 1.0);
+    hipLaunchKernelGGL(k_m_permute_out, dim3(nblk(c->nv * k, 256)), dim3(256), 0, c->stream, c->nv, c->nf,
+                       (const int32_t *)c->vint_of_user, (const double *)c->mb.Z, k, z);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->pcollect();
+  } catch (const Fail &f) {
+    return fail_ctx(c, f);
+  }
+  return COARSE_OK;
 }
 
 int coarse_solve_projected(coarse_ctx *c, const double *b, double *u, double tol, coarse_stats *st) {

@@ -1,0 +1,592 @@
+// Kernels of the block solve: up to MC right-hand sides on one mesh, solved by
+// MC independent PCG recurrences (Sec. 2, one per column) that share every read
+// of the operator's element matrices and of the stored dense inverses. Vectors
+// are vertex-major, MC doubles per vertex (one 128-byte line), so every gather
+// through an index list reads whole lines. The dense solves A_s^{-1} [r_1 .. r_MC]
+// of the additive preconditioner (Sec. 3, eq. (asm); Sec. 4) are small matrix
+// products on the matrix cores. FP64 throughout.
+//
+// Every sum over the vector runs over a fixed grid in a fixed order (per
+// workgroup, then one workgroup over the partials), so each column's result is
+// bitwise reproducible; columns never mix.
+#pragma once
+
+#include "kernels.h"
+
+namespace coarse {
+
+constexpr int MC = 16;    // columns of the block
+constexpr int MCW = 4;    // columns per operator pass (LDS holds MCW values per slot)
+
+// Solver state of the block solve (device memory, one per context).
+struct MScal {
+  double rho[2][MC];   // (r, z) of the last two preconditioner applications
+  double alpha[MC], beta[MC], pq[MC];
+  double bb[MC], rr[MC], rr0[MC], res_true[MC];
+  double tol2;
+  int32_t done[MC], status[MC], iters[MC];
+  int32_t iter;        // completed iterations
+  int32_t all_done;    // every column has finished
+  int32_t max_it, ncol;
+};
+
+// One dense system for the block GEMV.
+struct MSys {
+  const double *tiles;   // lower tiles of A_s^{-1}, TILE x TILE row-major each
+  int64_t voff;          // first packed entry of the system
+  int32_t nb, n;
+  int32_t red;           // 1: the reduced system (solution also goes to the box grid)
+  int32_t pad;
+};
+
+// what a k_m_scal launch forms from the column totals of its partials
+enum MScalStep : int { MS_BB = 0, MS_RZ = 1, MS_PQ = 2, MS_RR = 3, MS_RES = 4 };
+
+// Per-column sums over a workgroup of NT threads in which thread t holds a value
+// of column t % MC; returned in threads 0..MC-1 (fixed order: lanes c, c^16,
+// c^32, c^48 of each wave, then the waves in order). red: NT/WAVE*MC doubles.
+template <int NT>
+__device__ __forceinline__ double block_colsum(double v, double *red) {
+  v += __shfl_xor(v, 16, WAVE);
+  v += __shfl_xor(v, 32, WAVE);
+  const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+  if (l < MC) red[w * MC + l] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x < MC) {
+#pragma unroll
+    for (int q = 0; q < NT / WAVE; ++q) s += red[q * MC + threadIdx.x];
+  }
+  __syncthreads();
+  return s;
+}
+
+// caller vectors b[c][user] (c < k; zero columns beyond) into the block R in
+// internal order, x = p = z = 0, a copy of b for the final residual, and the
+// partials of ||b_c||^2; workgroup 0 resets the solver state
+__global__ __launch_bounds__(256) void k_m_start(int64_t nf, int64_t nv, const int32_t *__restrict__ user_of,
+                                                 const double *__restrict__ b, int k, double *__restrict__ R,
+                                                 double *__restrict__ X, double *__restrict__ Pa,
+                                                 double *__restrict__ Pb, double *__restrict__ Z,
+                                                 double *__restrict__ B, double *__restrict__ part,
+                                                 MScal *__restrict__ ms, double tol2, int max_it) {
+  __shared__ double red[256 / WAVE * MC];
+  const int c = threadIdx.x % MC;
+  double acc = 0.0;
+  const int64_t n = nf * MC, G = (int64_t)gridDim.x * 256;
+  for (int64_t g = blockIdx.x * (int64_t)256 + threadIdx.x; g < n; g += G) {
+    const int64_t i = g / MC;
+    const double v = (c < k) ? b[(int64_t)c * nv + user_of[i]] : 0.0;
+    R[g] = v;
+    B[g] = v;
+    X[g] = 0.0;
+    Pa[g] = 0.0;
+    Pb[g] = 0.0;
+    Z[g] = 0.0;
+    acc += v * v;
+  }
+  const double s = block_colsum<256>(acc, red);
+  if (threadIdx.x < MC) {
+    part[blockIdx.x * MC + threadIdx.x] = s;
+    if (blockIdx.x == 0) {
+      ms->rho[0][c] = ms->rho[1][c] = 0.0;
+      ms->alpha[c] = ms->beta[c] = ms->pq[c] = 0.0;
+      ms->bb[c] = ms->rr[c] = ms->rr0[c] = ms->res_true[c] = 0.0;
+      ms->done[c] = 0;
+      ms->status[c] = 0;
+      ms->iters[c] = 0;
+      if (c == 0) {
+        ms->tol2 = tol2;
+        ms->iter = 0;
+        ms->all_done = 0;
+        ms->max_it = max_it;
+        ms->ncol = k;
+      }
+    }
+  }
+}
+
+// One workgroup: the column totals of part[0..n)[MC] in a fixed order, then the
+// scalar step of every column (see MScalStep):
+//   MS_BB  ||b||^2; a zero (or beyond k) column is finished at once
+//   MS_RZ  rho_k = (r_k, z_k), beta_k = rho_k / rho_{k-1} (0 for k = 0)
+//   MS_PQ  alpha_k = rho_k / p_k.A p_k (breakdown when p.Ap <= 0)
+//   MS_RR  ||r_{k+1}||^2 against tol^2 ||b||^2 and the iteration cap; k + 1 done
+//   MS_RES ||b - A x||^2 of the result
+// A finished column keeps alpha = beta = 0, so its x and r stay as they are.
+__global__ __launch_bounds__(256) void k_m_scal(MScal *__restrict__ ms, const double *__restrict__ part, int n,
+                                                int step) {
+  __shared__ double red[256 / WAVE * MC];
+  __shared__ int live[MC];
+  if (step != MS_BB && step != MS_RES && ms->all_done) return;
+  const int c = threadIdx.x % MC, g = threadIdx.x / MC;
+  double acc = 0.0;
+  for (int i = g; i < n; i += 256 / MC) acc += part[i * MC + c];
+  const double tot = block_colsum<256>(acc, red);
+  const int it = ms->iter;
+  if (threadIdx.x < MC) {
+    bool done = ms->done[c] != 0;
+    int status = ms->status[c], iters = ms->iters[c];
+    switch (step) {
+      case MS_BB: {
+        ms->bb[c] = tot;
+        ms->rr[c] = tot;
+        ms->rr0[c] = tot;
+        if (c >= ms->ncol || !(tot > 0.0) || !isfinite(tot)) {
+          done = true;
+          status = isfinite(tot) ? 0 : -6;
+          iters = 0;
+        }
+        break;
+      }
+      case MS_RZ: {
+        double beta = 0.0;
+        if (!done) {
+          if (!isfinite(tot)) {
+            done = true;
+            status = -6;
+            iters = it;
+          } else if (it > 0) {
+            beta = tot / ms->rho[(it - 1) & 1][c];
+          }
+        }
+        ms->rho[it & 1][c] = tot;
+        ms->beta[c] = done ? 0.0 : beta;
+        break;
+      }
+      case MS_PQ: {
+        double alpha = 0.0;
+        ms->pq[c] = tot;
+        if (!done) {
+          if (!(tot > 0.0) || !isfinite(tot)) {
+            done = true;
+            status = -6;
+            iters = it;
+          } else {
+            alpha = ms->rho[it & 1][c] / tot;
+          }
+        }
+        ms->alpha[c] = alpha;
+        break;
+      }
+      case MS_RR: {
+        if (!done) {
+          ms->rr[c] = tot;
+          const int nit = it + 1;
+          if (!isfinite(tot)) {
+            done = true;
+            status = -6;
+            iters = nit;
+          } else if (tot <= ms->tol2 * ms->bb[c]) {
+            done = true;
+            status = 0;
+            iters = nit;
+          } else if (nit >= ms->max_it) {
+            done = true;
+            status = 1;
+            iters = nit;
+          }
+        }
+        break;
+      }
+      default:
+        ms->res_true[c] = tot;
+        break;
+    }
+    if (done) {
+      ms->alpha[c] = 0.0;
+      ms->beta[c] = 0.0;
+    }
+    ms->done[c] = done ? 1 : 0;
+    ms->status[c] = status;
+    ms->iters[c] = iters;
+    live[c] = done ? 0 : 1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && step != MS_RES) {
+    int any = 0;
+    for (int k = 0; k < MC; ++k) any |= live[k];
+    if (step == MS_RR) ms->iter = it + 1;
+    ms->all_done = any ? 0 : 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Operator on the block: q_c = A p_c for every column, with the element data
+// loaded once. The workgroup stages MCW columns of its slot values at a time in
+// LDS; the element products, the corner-by-corner slot sums (or the incidence
+// lists) and the writes to q / the shared-vertex partials follow k_op_pass1,
+// column by column, so every column sums in the same order as a single-vector
+// application. fused = 1: the PCG form, p_k = z_k + beta_c p_{k-1} formed while
+// staging (written once per vertex by its designated block) and the partials of
+// p_c.A p_c; fused = 0: q = A p for p given in z.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(OP_BLOCK) void k_m_op(OpDev op, const double *__restrict__ z, double *__restrict__ pa,
+                                                   double *__restrict__ pb, double *__restrict__ q,
+                                                   double *__restrict__ partials, double *__restrict__ energy,
+                                                   const MScal *__restrict__ ms, int fused) {
+  extern __shared__ double lds[];
+  __shared__ double red[OP_BLOCK / WAVE];
+  if (fused && ms->all_done) return;
+  double *out = lds;                  // [OP_BLOCK * 8], one column at a time
+  double *lp = lds + OP_BLOCK * 8;    // [slots][MCW]
+  const int blk = blockIdx.x;
+  const int64_t e = (int64_t)blk * OP_BLOCK + threadIdx.x;
+  const bool valid = e < op.E;
+  double m[28];
+  uint4 cn = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+  if (valid) elem_load(op, e, m, cn);
+  const int s0 = op.blk_slot_ptr[blk], ns = op.blk_slot_ptr[blk + 1] - s0;
+  const int it = fused ? ms->iter : 0;
+  double *pcur = (it & 1) ? pb : pa;
+  const double *pprev = (it & 1) ? pa : pb;
+  const bool inc = op.blk_inc[blk] != 0;
+  for (int ch = 0; ch < MC / MCW; ++ch) {
+    const int c0 = ch * MCW;
+    double beta[MCW];
+#pragma unroll
+    for (int cc = 0; cc < MCW; ++cc) beta[cc] = fused ? ms->beta[c0 + cc] : 0.0;
+    for (int s = threadIdx.x; s < ns; s += OP_BLOCK) {
+      const int64_t v = op.slot_vid[s0 + s];
+      const double2 z0 = *(const double2 *)(z + v * MC + c0);
+      const double2 z1 = *(const double2 *)(z + v * MC + c0 + 2);
+      double pv[MCW] = {z0.x, z0.y, z1.x, z1.y};
+      if (fused) {
+        const double2 q0 = *(const double2 *)(pprev + v * MC + c0);
+        const double2 q1 = *(const double2 *)(pprev + v * MC + c0 + 2);
+        pv[0] += beta[0] * q0.x;
+        pv[1] += beta[1] * q0.y;
+        pv[2] += beta[2] * q1.x;
+        pv[3] += beta[3] * q1.y;
+        if (op.slot_pw[s0 + s]) {
+          *(double2 *)(pcur + v * MC + c0) = make_double2(pv[0], pv[1]);
+          *(double2 *)(pcur + v * MC + c0 + 2) = make_double2(pv[2], pv[3]);
+        }
+      }
+#pragma unroll
+      for (int cc = 0; cc < MCW; ++cc) lp[s * MCW + cc] = pv[cc];
+    }
+    __syncthreads();
+    double y[MCW][8], en[MCW];
+#pragma unroll
+    for (int cc = 0; cc < MCW; ++cc) {
+      en[cc] = 0.0;
+#pragma unroll
+      for (int a = 0; a < 8; ++a) y[cc][a] = 0.0;
+    }
+    if (valid) {
+#pragma unroll
+      for (int cc = 0; cc < MCW; ++cc) {
+        double pe[8];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          const unsigned sl = slot_at(cn, a);
+          pe[a] = (sl == 0xFFFFu) ? 0.0 : lp[sl * MCW + cc];
+        }
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+#pragma unroll
+          for (int b2 = a + 1; b2 < 8; ++b2) {
+            const double t = m[off8(a, b2)] * (pe[b2] - pe[a]);
+            y[cc][a] += t;
+            y[cc][b2] -= t;
+          }
+#pragma unroll
+        for (int a = 0; a < 8; ++a) en[cc] += pe[a] * y[cc][a];
+      }
+    }
+    __syncthreads();
+    if (inc) {
+      // per slot, the element outputs of its incidences in list order
+#pragma unroll
+      for (int cc = 0; cc < MCW; ++cc) {
+        if (valid) {
+#pragma unroll
+          for (int a = 0; a < 8; ++a) out[threadIdx.x * 8 + a] = y[cc][a];
+        }
+        __syncthreads();
+        for (int s = threadIdx.x; s < ns; s += OP_BLOCK) {
+          const uint4 rec = *(const uint4 *)(op.slot_inc8 + (int64_t)(s0 + s) * 8);
+          const int dst = op.slot_dst[s0 + s];
+          double acc = 0.0;
+          if (slot_at(rec, 0) == 0xFFFEu) {
+            for (int k = op.slot_inc_ptr[s0 + s]; k < op.slot_inc_ptr[s0 + s + 1]; ++k) acc += out[op.slot_inc[k]];
+          } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+              const unsigned li = slot_at(rec, k);
+              if (li != 0xFFFFu) acc += out[li];
+            }
+          }
+          if (dst >= 0)
+            q[(int64_t)dst * MC + c0 + cc] = acc;
+          else
+            partials[(int64_t)(-dst - 1) * MC + c0 + cc] = acc;
+        }
+        __syncthreads();
+      }
+    } else {
+      for (int s = threadIdx.x; s < ns * MCW; s += OP_BLOCK) lp[s] = 0.0;
+      __syncthreads();
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        if (valid) {
+          const unsigned sl = slot_at(cn, a);
+          if (sl != 0xFFFFu) {
+#pragma unroll
+            for (int cc = 0; cc < MCW; ++cc) lp[sl * MCW + cc] += y[cc][a];
+          }
+        }
+        __syncthreads();
+      }
+      for (int s = threadIdx.x; s < ns; s += OP_BLOCK) {
+        const int dst = op.slot_dst[s0 + s];
+        double *d = (dst >= 0) ? q + (int64_t)dst * MC + c0 : partials + (int64_t)(-dst - 1) * MC + c0;
+        *(double2 *)d = make_double2(lp[s * MCW], lp[s * MCW + 1]);
+        *(double2 *)(d + 2) = make_double2(lp[s * MCW + 2], lp[s * MCW + 3]);
+      }
+      __syncthreads();
+    }
+    if (fused) {
+#pragma unroll
+      for (int cc = 0; cc < MCW; ++cc) {
+        const double tot = block_sum<OP_BLOCK>(en[cc], red);
+        if (threadIdx.x == 0) energy[blk * MC + c0 + cc] = tot;
+      }
+    }
+  }
+}
+
+// q of the vertices shared between operator blocks, from their partials (the
+// non-fused operator; the PCG update sums them itself)
+__global__ __launch_bounds__(256) void k_m_op_pass2(OpDev op, const double *__restrict__ partials,
+                                                    double *__restrict__ q) {
+  const int64_t g = blockIdx.x * (int64_t)256 + threadIdx.x;
+  const int64_t i = g / MC;
+  const int c = (int)(g % MC);
+  if (i >= op.n_shared) return;
+  double acc = 0.0;
+  for (int k = op.sh_ptr[i]; k < op.sh_ptr[i + 1]; ++k) acc += partials[(int64_t)k * MC + c];
+  q[(int64_t)op.sh_vid[i] * MC + c] = acc;
+}
+
+// alpha_c, x += alpha_c p, r -= alpha_c q (shared vertices summed from the
+// operator's partials), partials of ||r_c||^2
+__global__ __launch_bounds__(256) void k_m_update(int64_t nf, OpDev op, const double *__restrict__ partials,
+                                                  const MScal *__restrict__ ms, double *__restrict__ X,
+                                                  double *__restrict__ R, const double *__restrict__ pa,
+                                                  const double *__restrict__ pb, const double *__restrict__ Q,
+                                                  double *__restrict__ part) {
+  __shared__ double red[256 / WAVE * MC];
+  if (ms->all_done) return;
+  const int c = threadIdx.x % MC;
+  const double alpha = ms->alpha[c];
+  const double *P = (ms->iter & 1) ? pb : pa;
+  double acc = 0.0;
+  const int64_t n = nf * MC, G = (int64_t)gridDim.x * 256;
+  for (int64_t g = blockIdx.x * (int64_t)256 + threadIdx.x; g < n; g += G) {
+    const int2 vq = op.vq[g / MC];
+    double qi;
+    if (vq.y == 0) {
+      qi = Q[g];
+    } else {
+      qi = 0.0;
+      for (int k = 0; k < vq.y; ++k) qi += partials[(int64_t)(vq.x + k) * MC + c];
+    }
+    X[g] += alpha * P[g];
+    const double ri = R[g] - alpha * qi;
+    R[g] = ri;
+    acc += ri * ri;
+  }
+  const double s = block_colsum<256>(acc, red);
+  if (threadIdx.x < MC) part[blockIdx.x * MC + threadIdx.x] = s;
+}
+
+// Restriction of the block (Sec. 3 and Sec. 4): workgroups below ng gather
+// r_p = R_p r for every column into the packed vectors (padding = 0); the others
+// take one J^T task per wavefront, lanes (entry group g = l / MC, column l % MC),
+// and write its 8 corner sums per column.
+__global__ __launch_bounds__(256) void k_m_pre(int ng, int64_t n_pack, const int32_t *__restrict__ idx,
+                                               const double *__restrict__ R, double *__restrict__ RP, int ntask,
+                                               const int32_t *__restrict__ tstart, const int32_t *__restrict__ vid,
+                                               const double *__restrict__ w, const double *__restrict__ xi,
+                                               int64_t nent, double *__restrict__ tpart,
+                                               const MScal *__restrict__ ms) {
+  if (ms->all_done) return;
+  if ((int)blockIdx.x < ng) {
+    const int64_t n = n_pack * MC, G = (int64_t)ng * 256;
+    for (int64_t g = blockIdx.x * (int64_t)256 + threadIdx.x; g < n; g += G) {
+      const int32_t i = idx[g / MC];
+      RP[g] = (i >= 0) ? R[(int64_t)i * MC + g % MC] : 0.0;
+    }
+    return;
+  }
+  const int lane = threadIdx.x & 63, c = lane % MC, eg = lane / MC;
+  const int nw = ((int)gridDim.x - ng) * 4;
+  for (int task = ((int)blockIdx.x - ng) * 4 + (threadIdx.x >> 6); task < ntask; task += nw) {
+    double acc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = 0.0;
+    const int j1 = tstart[task + 1];
+    for (int j = tstart[task] + eg; j < j1; j += WAVE / MC) {
+      const double v = w[j] * R[(int64_t)vid[j] * MC + c];
+      const double x = xi[j], y = xi[nent + j], zz = xi[2 * nent + j];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) acc[k] += trilin<double>(k, x, y, zz) * v;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      acc[k] += __shfl_xor(acc[k], 16, WAVE);
+      acc[k] += __shfl_xor(acc[k], 32, WAVE);
+    }
+    if (eg == 0) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) tpart[((int64_t)task * 8 + k) * MC + c] = acc[k];
+    }
+  }
+}
+
+// Second stage of J^T: per active box vertex and column, the task sums of the
+// occupied cells around it in list order.
+__global__ __launch_bounds__(256) void k_m_corners(int64_t nr, const int32_t *__restrict__ ptr,
+                                                   const int32_t *__restrict__ src, const double *__restrict__ tpart,
+                                                   double *__restrict__ rr, const MScal *__restrict__ ms) {
+  if (ms->all_done) return;
+  const int64_t g = blockIdx.x * (int64_t)256 + threadIdx.x;
+  const int64_t K = g / MC;
+  const int c = (int)(g % MC);
+  if (K >= nr) return;
+  double acc = 0.0;
+  for (int k = ptr[K]; k < ptr[K + 1]; ++k) acc += tpart[(int64_t)src[k] * MC + c];
+  rr[K * MC + c] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Dense solves of the block: Z_s = A_s^{-1} R_s for every system, one wavefront
+// per tile row I of a system, on the matrix cores. Row I of the symmetric
+// inverse is the stored lower tiles (I, J <= I) followed by the transposes of
+// the stored tiles (J > I, I), so the wavefront owns its 32 x MC output rows
+// whole: no partial sums leave it and no combine pass follows (each
+// off-diagonal tile is read by two wavefronts, the second time mostly from the
+// caches). v_mfma_f64_16x16x4f64 takes A[16x4] (lane l holds A[l%16][l/16]) and
+// B[4x16] (lane l holds B[l/16][l%16]) and accumulates D[16x16], lane l holding
+// rows l/16 + 4r (r < 4) of column l%16. Output rows 0..15 and 16..31 of the
+// tile row are two accumulators; the K = 32 sum of a tile takes 8 steps.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_m_gemv(const int2 *__restrict__ rows, int nrows,
+                                                const MSys *__restrict__ sys, const double *__restrict__ RP,
+                                                double *__restrict__ ZP, double *__restrict__ yfull,
+                                                const int32_t *__restrict__ act_bv, const MScal *__restrict__ ms) {
+  if (ms->all_done) return;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= nrows) return;
+  const int lane = threadIdx.x & 63, li = lane % 16, lk = lane / 16;
+  const int2 sr = rows[row];
+  const MSys S = sys[sr.x];
+  const int I = sr.y, nb = S.nb;
+  const double *__restrict__ Rs = RP + S.voff * MC;
+  v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  for (int J = 0; J < nb; ++J) {
+    double a0[8], a1[8], bv[8];
+    if (J <= I) {
+      // stored tile (I, J): A[i][k] = t[i][k]
+      const double *t = S.tiles + ((int64_t)I * (I + 1) / 2 + J) * (TILE * TILE);
+#pragma unroll
+      for (int st = 0; st < 8; ++st) {
+        a0[st] = t[li * TILE + 4 * st + lk];
+        a1[st] = t[(16 + li) * TILE + 4 * st + lk];
+      }
+    } else {
+      // stored tile (J, I), transposed: A[i][k] = t[k][i]
+      const double *t = S.tiles + ((int64_t)J * (J + 1) / 2 + I) * (TILE * TILE);
+#pragma unroll
+      for (int st = 0; st < 8; ++st) {
+        a0[st] = t[(4 * st + lk) * TILE + li];
+        a1[st] = t[(4 * st + lk) * TILE + 16 + li];
+      }
+    }
+#pragma unroll
+    for (int st = 0; st < 8; ++st) bv[st] = Rs[(int64_t)(J * TILE + 4 * st + lk) * MC + li];
+#pragma unroll
+    for (int st = 0; st < 8; ++st) {
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[st], bv[st], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[st], bv[st], acc1, 0, 0, 0);
+    }
+  }
+  double *Zs = ZP + S.voff * MC;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i0 = I * TILE + lk + 4 * r, i1 = i0 + 16;
+    Zs[(int64_t)i0 * MC + li] = acc0[r];
+    Zs[(int64_t)i1 * MC + li] = acc1[r];
+    if (S.red) {
+      if (i0 < S.n) yfull[(int64_t)act_bv[i0] * MC + li] = acc0[r];
+      if (i1 < S.n) yfull[(int64_t)act_bv[i1] * MC + li] = acc1[r];
+    }
+  }
+}
+
+// z = sum_p R_p^T z_p + J y_r per column (Sec. 3, Sec. 4), and the partials of
+// (r_c, z_c)
+__global__ __launch_bounds__(256) void k_m_final(int64_t nf, const int32_t *__restrict__ cover_ptr,
+                                                 const int32_t *__restrict__ cover_pos, const double *__restrict__ ZP,
+                                                 const int32_t *__restrict__ jv_ptr, const int32_t *__restrict__ jv_base,
+                                                 const double *__restrict__ jv_w, const double *__restrict__ jv_xi,
+                                                 int64_t nent, int bx1, int bxy1, const double *__restrict__ yfull,
+                                                 double *__restrict__ Z, const double *__restrict__ R,
+                                                 double *__restrict__ part, const MScal *__restrict__ ms) {
+  __shared__ double red[256 / WAVE * MC];
+  if (ms->all_done) return;
+  const int c = threadIdx.x % MC;
+  double d = 0.0;
+  const int64_t n = nf * MC, G = (int64_t)gridDim.x * 256;
+  for (int64_t g = blockIdx.x * (int64_t)256 + threadIdx.x; g < n; g += G) {
+    const int64_t i = g / MC;
+    double acc = 0.0;
+    for (int k = cover_ptr[i]; k < cover_ptr[i + 1]; ++k) acc += ZP[(int64_t)cover_pos[k] * MC + c];
+    double cs = 0.0;
+    for (int k = jv_ptr[i]; k < jv_ptr[i + 1]; ++k) {
+      const int64_t b0 = jv_base[k];
+      const double x = jv_xi[k], y = jv_xi[nent + k], zz = jv_xi[2 * nent + k];
+      double sv = 0.0;
+#pragma unroll
+      for (int qq = 0; qq < 8; ++qq) {
+        const int64_t bvx = b0 + (qq & 1) + ((qq >> 1) & 1) * bx1 + ((qq >> 2) & 1) * bxy1;
+        sv += trilin<double>(qq, x, y, zz) * yfull[bvx * MC + c];
+      }
+      cs += jv_w[k] * sv;
+    }
+    acc += cs;
+    Z[g] = acc;
+    d += R[g] * acc;
+  }
+  const double s = block_colsum<256>(d, red);
+  if (threadIdx.x < MC) part[blockIdx.x * MC + threadIdx.x] = s;
+}
+
+// partials of ||b_c - q_c||^2 (q = A x)
+__global__ __launch_bounds__(256) void k_m_resnorm(int64_t nf, const double *__restrict__ B,
+                                                   const double *__restrict__ Q, double *__restrict__ part) {
+  __shared__ double red[256 / WAVE * MC];
+  double acc = 0.0;
+  const int64_t n = nf * MC, G = (int64_t)gridDim.x * 256;
+  for (int64_t g = blockIdx.x * (int64_t)256 + threadIdx.x; g < n; g += G) {
+    const double t = B[g] - Q[g];
+    acc += t * t;
+  }
+  const double s = block_colsum<256>(acc, red);
+  if (threadIdx.x < MC) part[blockIdx.x * MC + threadIdx.x] = s;
+}
+
+// columns c < k of the block back to the caller's vertex order (0 on Dirichlet
+// vertices)
+__global__ __launch_bounds__(256) void k_m_permute_out(int64_t nv, int64_t nf, const int32_t *__restrict__ vint_of,
+                                                       const double *__restrict__ X, int k, double *__restrict__ u) {
+  const int64_t g = blockIdx.x * (int64_t)256 + threadIdx.x;
+  const int64_t c = g / nv, v = g % nv;
+  if (c >= k) return;
+  const int32_t i = vint_of[v];
+  u[g] = (i < nf) ? X[(int64_t)i * MC + c] : 0.0;
+}
+
+}  // namespace coarse
