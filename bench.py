@@ -299,6 +299,50 @@ def run_ablations(torch, coarse, mesh, b, tol, max_it=400):
     return out
 
 
+FP64_MFMA_PEAK_TFS = 78.6   # MI355X dense FP64 matrix peak
+
+
+def run_multi(torch, coarse, mg, mesh, tol, steps, warmup, k=16):
+    """Block solve (coarse_solve_multi) of k right-hand sides on the bench mesh:
+    the load of the bench plus k - 1 bump loads, solved together in FP64. Host
+    clock over `steps` block solves; HIP events around each dense-solve launch
+    (k_m_gemv, MFMA FP64), whose algorithmic work is 2 n^2 k flops per system
+    and the packed inverse bytes read once."""
+    rhs = [mesh.b] + [mg.rhs_bumps(mesh, 300 + j) for j in range(1, k)]
+    B = torch.stack([torch.tensor(b, device="cuda") for b in rhs])
+    U = torch.empty_like(B)
+    S = coarse.CoarseSolver.from_mesh(mesh)
+    for _ in range(warmup):
+        S.solve_multi(B, tol, out=U)
+    torch.cuda.synchronize()
+    S.profile_start(1 << GEMV_PHASE)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, st = S.solve_multi(B, tol, out=U)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms, cnt = S.profile_stop()[coarse.PHASES[GEMV_PHASE]]
+    info = dict(S.info)
+    S.close()
+    iters = [s["iters"] for s in st]
+    # dense-solve launches with work per block solve: the start plus one per
+    # iteration until the last column converges
+    work = steps * (max(iters) + 1)
+    avg_s = ms / max(work, 1) / 1e3
+    sum_n = info["sum_np"] + info["n_r"]
+    sum_n2 = info["inv_alg_bytes"] // 4 - sum_n    # from sum n(n+1)/2 * 8 bytes
+    flops = 2 * sum_n2 * k
+    return {"k": k, "solves_per_s": round(k * steps / elapsed, 2), "ms_per_block": round(1e3 * elapsed / steps, 3),
+            "iters": iters, "relres_true_max": max(s["relres_true"] for s in st),
+            "status": sorted({s["status"] for s in st}),
+            "gemv": {"kernel": "k_m_gemv", "avg_launch_us": round(avg_s * 1e6, 2), "launches": cnt,
+                     "work_launches": work, "alg_flops": flops,
+                     "TFLOPs": round(flops / avg_s / 1e12, 2),
+                     "frac_mfma_fp64": round(flops / avg_s / 1e12 / FP64_MFMA_PEAK_TFS, 4),
+                     "alg_bytes": info["inv_alg_bytes"],
+                     "GBs": round(info["inv_alg_bytes"] / avg_s / 1e9, 1)}}
+
+
 def run_warm_start(torch, coarse, mg, mesh, tol, steps=32, basis=8, precisions=("fp64", "mixed16")):
     """A sequence of `steps` right-hand sides from a load that changes smoothly in
     time (time step 0.005: features move about a third of an element per step at
@@ -364,6 +408,7 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 128^3 annulus kernel measurements")
     ap.add_argument("--no-ablations", action="store_true", help="skip the preconditioner-part study")
     ap.add_argument("--no-warm-start", action="store_true", help="skip the successive right-hand-side study")
+    ap.add_argument("--no-multi", action="store_true", help="skip the 16-right-hand-side block solve")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the open-loop serving study over resident contexts")
     ap.add_argument("--serving", action="store_true", help="also run a short serving-loop workload")
@@ -439,6 +484,13 @@ def main():
         warm = run_warm_start(torch, coarse, mg, mesh, args.tol)
         _log(f"warm start: {warm}")
 
+    multi = None
+    if not args.no_multi:
+        _log("block solve, 16 right-hand sides")
+        multi = run_multi(torch, coarse, mg, mesh, args.tol, max(2, args.steps // 4), 1)
+        multi["vs_single_fp64"] = round(multi["solves_per_s"] / fp64["solves_per_s"], 2)
+        _log(f"block solve: {multi}")
+
     large = None
     if not args.no_large:
         _log("annulus128 kernels")
@@ -496,6 +548,8 @@ def main():
         line["ablations"] = ablations
     if warm is not None:
         line["warm_start"] = warm
+    if multi is not None:
+        line["multi_rhs"] = multi
     if resident is not None:
         line["serving_resident"] = resident
     if serving is not None:

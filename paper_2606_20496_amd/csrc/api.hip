@@ -579,7 +579,7 @@ struct coarse_ctx {
                        (const MScal *)mb.ms);
     pend(2);
     pbeg(3);
-    hipLaunchKernelGGL(k_m_gemv, dim3(nblk(mb.nrows, 4)), dim3(256), 0, stream, (const int2 *)mb.rows, mb.nrows,
+    hipLaunchKernelGGL(k_m_gemv, dim3((nblk(mb.nrows, 4) + 7) / 8 * 8), dim3(256), 0, stream, (const int2 *)mb.rows, mb.nrows,
                        (const MSys *)mb.sys, (const double *)mb.RP, mb.ZP, mb.yfull, (const int32_t *)act_bv,
                        (const MScal *)mb.ms);
     pend(3);

@@ -61,6 +61,46 @@ __device__ __forceinline__ double block_colsum(double v, double *red) {
   return s;
 }
 
+// The per-vertex kernels of the iteration give each vertex 4 lanes, lane q
+// holding columns 4q .. 4q + 3 (two 16-byte accesses per vector), so a
+// workgroup keeps 64 vertices in flight. Per-column sums over the workgroup:
+// lanes with the same q in a wave (xor 4, 8, 16, 32), then the waves in order;
+// returned in threads 0..MC-1 (column = thread).
+template <int NT>
+__device__ __forceinline__ double block_colsum4(const double v[4], double *red) {
+  const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    double x = v[j];
+    x += __shfl_xor(x, 4, WAVE);
+    x += __shfl_xor(x, 8, WAVE);
+    x += __shfl_xor(x, 16, WAVE);
+    x += __shfl_xor(x, 32, WAVE);
+    if (l < 4) red[w * MC + 4 * l + j] = x;
+  }
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x < MC) {
+#pragma unroll
+    for (int q = 0; q < NT / WAVE; ++q) s += red[q * MC + threadIdx.x];
+  }
+  __syncthreads();
+  return s;
+}
+
+__device__ __forceinline__ void ld4(const double *p, double v[4]) {
+  const double2 a = *(const double2 *)p, b = *(const double2 *)(p + 2);
+  v[0] = a.x;
+  v[1] = a.y;
+  v[2] = b.x;
+  v[3] = b.y;
+}
+
+__device__ __forceinline__ void st4(double *p, const double v[4]) {
+  *(double2 *)p = make_double2(v[0], v[1]);
+  *(double2 *)(p + 2) = make_double2(v[2], v[3]);
+}
+
 // caller vectors b[c][user] (c < k; zero columns beyond) into the block R in
 // internal order, x = p = z = 0, a copy of b for the final residual, and the
 // partials of ||b_c||^2; workgroup 0 resets the solver state
@@ -379,26 +419,42 @@ __global__ __launch_bounds__(256) void k_m_update(int64_t nf, OpDev op, const do
                                                   double *__restrict__ part) {
   __shared__ double red[256 / WAVE * MC];
   if (ms->all_done) return;
-  const int c = threadIdx.x % MC;
-  const double alpha = ms->alpha[c];
+  const int cq = (threadIdx.x % 4) * 4;
+  double alpha[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) alpha[j] = ms->alpha[cq + j];
   const double *P = (ms->iter & 1) ? pb : pa;
-  double acc = 0.0;
-  const int64_t n = nf * MC, G = (int64_t)gridDim.x * 256;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t n = nf * 4, G = (int64_t)gridDim.x * 256;
   for (int64_t g = blockIdx.x * (int64_t)256 + threadIdx.x; g < n; g += G) {
-    const int2 vq = op.vq[g / MC];
-    double qi;
+    const int64_t i = g / 4, o = i * MC + cq;
+    const int2 vq = op.vq[i];
+    double qi[4], x[4], r[4], p[4];
+    ld4(X + o, x);
+    ld4(R + o, r);
+    ld4(P + o, p);
     if (vq.y == 0) {
-      qi = Q[g];
+      ld4(Q + o, qi);
     } else {
-      qi = 0.0;
-      for (int k = 0; k < vq.y; ++k) qi += partials[(int64_t)(vq.x + k) * MC + c];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) qi[j] = 0.0;
+      for (int k = 0; k < vq.y; ++k) {
+        double t[4];
+        ld4(partials + (int64_t)(vq.x + k) * MC + cq, t);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) qi[j] += t[j];
+      }
     }
-    X[g] += alpha * P[g];
-    const double ri = R[g] - alpha * qi;
-    R[g] = ri;
-    acc += ri * ri;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      x[j] += alpha[j] * p[j];
+      r[j] = r[j] - alpha[j] * qi[j];
+      acc[j] += r[j] * r[j];
+    }
+    st4(X + o, x);
+    st4(R + o, r);
   }
-  const double s = block_colsum<256>(acc, red);
+  const double s = block_colsum4<256>(acc, red);
   if (threadIdx.x < MC) part[blockIdx.x * MC + threadIdx.x] = s;
 }
 
@@ -467,51 +523,105 @@ __global__ __launch_bounds__(256) void k_m_corners(int64_t nr, const int32_t *__
 // inverse is the stored lower tiles (I, J <= I) followed by the transposes of
 // the stored tiles (J > I, I), so the wavefront owns its 32 x MC output rows
 // whole: no partial sums leave it and no combine pass follows (each
-// off-diagonal tile is read by two wavefronts, the second time mostly from the
-// caches). v_mfma_f64_16x16x4f64 takes A[16x4] (lane l holds A[l%16][l/16]) and
-// B[4x16] (lane l holds B[l/16][l%16]) and accumulates D[16x16], lane l holding
-// rows l/16 + 4r (r < 4) of column l%16. Output rows 0..15 and 16..31 of the
-// tile row are two accumulators; the K = 32 sum of a tile takes 8 steps.
+// off-diagonal tile is read by two wavefronts of the same system, which run
+// on one XCD, so the second read mostly hits its L2). v_mfma_f64_16x16x4f64
+// takes A[16x4] (lane l holds A[l%16][l/16]) and B[4x16] (lane l holds
+// B[l/16][l%16]) and accumulates D[16x16], lane l holding rows l/16 + 4r (r < 4)
+// of column l%16. Output rows 0..15 and 16..31 of the tile row are two
+// accumulators; the K = 32 sum of a tile takes 8 steps. A tile is read with
+// 16-byte loads (one 128-byte line per four lanes), staged in the wavefront's own
+// LDS region (row stride MLD doubles) and read back in the operand layout, row-
+// or column-wise; the next tile's loads are in flight meanwhile.
 // ---------------------------------------------------------------------------
+constexpr int MLD = TILE + 2;
+
+// loads through the global address space (not flat: a flat load also counts
+// against the LDS wait below)
+__device__ __forceinline__ double2 ldg2(const double2 *p) {
+  const nt_d2 v = *(const __attribute__((address_space(1))) nt_d2 *)p;
+  double2 o;
+  o.x = v.x;
+  o.y = v.y;
+  return o;
+}
+__device__ __forceinline__ double ldg(const double *p) {
+  return *(const __attribute__((address_space(1))) double *)p;
+}
+
+// LDS accesses of one wavefront in program order: the wavefront's own LDS
+// operations complete (lgkmcnt 0; loads from global memory stay in flight) and
+// the compiler moves no memory access across this point
+__device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
 __global__ __launch_bounds__(256) void k_m_gemv(const int2 *__restrict__ rows, int nrows,
                                                 const MSys *__restrict__ sys, const double *__restrict__ RP,
                                                 double *__restrict__ ZP, double *__restrict__ yfull,
                                                 const int32_t *__restrict__ act_bv, const MScal *__restrict__ ms) {
+  __shared__ __attribute__((aligned(16))) double stage[4][TILE * MLD];
   if (ms->all_done) return;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= nrows) return;
+  // consecutive rows (those of one system) go to workgroups of one XCD: the
+  // grid is a multiple of 8 and workgroup b runs on XCD b % 8
+  const int per = (int)gridDim.x / 8;
+  const int wl = ((int)blockIdx.x % 8) * per + (int)blockIdx.x / 8;
+  const int row = wl * 4 + (threadIdx.x >> 6);
+  if (row >= nrows) return;   // no workgroup barrier below
   const int lane = threadIdx.x & 63, li = lane % 16, lk = lane / 16;
   const int2 sr = rows[row];
   const MSys S = sys[sr.x];
   const int I = sr.y, nb = S.nb;
   const double *__restrict__ Rs = RP + S.voff * MC;
+  double *L = stage[threadIdx.x >> 6];
+  const int wr = lane / 16, wc = 2 * (lane % 16);   // this lane's 16-byte pieces: rows wr + 4m, columns wc, wc + 1
+  // step s visits tile column J = (s - I) mod nb: the two wavefronts that need
+  // tile {I, J} (rows I and J of the system) reach it at the same step s = (I +
+  // J) mod nb, so its second read comes from the L2
+  auto tile_at = [&](int J) -> const double2 * {
+    const int64_t toff = (J <= I) ? (int64_t)I * (I + 1) / 2 + J : (int64_t)J * (J + 1) / 2 + I;
+    return (const double2 *)(S.tiles + toff * (TILE * TILE));
+  };
+  double2 tv[8];
+  double bv[8];
+  int J = (I == 0) ? 0 : nb - I;
+  {
+    const double2 *t = tile_at(J);
+#pragma unroll
+    for (int m = 0; m < 8; ++m) tv[m] = ldg2(t + m * 64 + lane);
+#pragma unroll
+    for (int st = 0; st < 8; ++st) bv[st] = ldg(Rs + (int64_t)(J * TILE + 4 * st + lk) * MC + li);
+  }
   v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-  for (int J = 0; J < nb; ++J) {
-    double a0[8], a1[8], bv[8];
-    if (J <= I) {
-      // stored tile (I, J): A[i][k] = t[i][k]
-      const double *t = S.tiles + ((int64_t)I * (I + 1) / 2 + J) * (TILE * TILE);
+  for (int s = 0; s < nb; ++s) {
 #pragma unroll
-      for (int st = 0; st < 8; ++st) {
-        a0[st] = t[li * TILE + 4 * st + lk];
-        a1[st] = t[(16 + li) * TILE + 4 * st + lk];
-      }
-    } else {
-      // stored tile (J, I), transposed: A[i][k] = t[k][i]
-      const double *t = S.tiles + ((int64_t)J * (J + 1) / 2 + I) * (TILE * TILE);
+    for (int m = 0; m < 8; ++m) *(double2 *)(L + (wr + 4 * m) * MLD + wc) = tv[m];
+    double bc[8];
 #pragma unroll
-      for (int st = 0; st < 8; ++st) {
-        a0[st] = t[(4 * st + lk) * TILE + li];
-        a1[st] = t[(4 * st + lk) * TILE + 16 + li];
-      }
+    for (int st = 0; st < 8; ++st) bc[st] = bv[st];
+    const bool low = J <= I;
+    // the next tile (the last step reloads its own, from the caches)
+    const int J1 = (s + 1 < nb) ? ((J + 1 == nb) ? 0 : J + 1) : J;
+    {
+      const double2 *t = tile_at(J1);
+#pragma unroll
+      for (int m = 0; m < 8; ++m) tv[m] = ldg2(t + m * 64 + lane);
+#pragma unroll
+      for (int st = 0; st < 8; ++st) bv[st] = ldg(Rs + (int64_t)(J1 * TILE + 4 * st + lk) * MC + li);
     }
-#pragma unroll
-    for (int st = 0; st < 8; ++st) bv[st] = Rs[(int64_t)(J * TILE + 4 * st + lk) * MC + li];
+    wave_lds_sync();
+    double a0[8], a1[8];
 #pragma unroll
     for (int st = 0; st < 8; ++st) {
-      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[st], bv[st], acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[st], bv[st], acc1, 0, 0, 0);
+      // stored tile (I, J): A[i][k] = t[i][k]; stored tile (J, I): A[i][k] = t[k][i]
+      const int k = 4 * st + lk;
+      a0[st] = L[low ? li * MLD + k : k * MLD + li];
+      a1[st] = L[low ? (16 + li) * MLD + k : k * MLD + 16 + li];
     }
+#pragma unroll
+    for (int st = 0; st < 8; ++st) {
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[st], bc[st], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[st], bc[st], acc1, 0, 0, 0);
+    }
+    wave_lds_sync();
+    J = J1;
   }
   double *Zs = ZP + S.voff * MC;
 #pragma unroll
@@ -537,30 +647,45 @@ __global__ __launch_bounds__(256) void k_m_final(int64_t nf, const int32_t *__re
                                                  double *__restrict__ part, const MScal *__restrict__ ms) {
   __shared__ double red[256 / WAVE * MC];
   if (ms->all_done) return;
-  const int c = threadIdx.x % MC;
-  double d = 0.0;
-  const int64_t n = nf * MC, G = (int64_t)gridDim.x * 256;
+  const int cq = (threadIdx.x % 4) * 4;
+  double d[4] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t n = nf * 4, G = (int64_t)gridDim.x * 256;
   for (int64_t g = blockIdx.x * (int64_t)256 + threadIdx.x; g < n; g += G) {
-    const int64_t i = g / MC;
-    double acc = 0.0;
-    for (int k = cover_ptr[i]; k < cover_ptr[i + 1]; ++k) acc += ZP[(int64_t)cover_pos[k] * MC + c];
-    double cs = 0.0;
+    const int64_t i = g / 4, o = i * MC + cq;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = cover_ptr[i]; k < cover_ptr[i + 1]; ++k) {
+      double t[4];
+      ld4(ZP + (int64_t)cover_pos[k] * MC + cq, t);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[j] += t[j];
+    }
+    double cs[4] = {0.0, 0.0, 0.0, 0.0};
     for (int k = jv_ptr[i]; k < jv_ptr[i + 1]; ++k) {
       const int64_t b0 = jv_base[k];
-      const double x = jv_xi[k], y = jv_xi[nent + k], zz = jv_xi[2 * nent + k];
-      double sv = 0.0;
+      const double x = jv_xi[k], y = jv_xi[nent + k], zz = jv_xi[2 * nent + k], wk = jv_w[k];
+      double sv[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int qq = 0; qq < 8; ++qq) {
         const int64_t bvx = b0 + (qq & 1) + ((qq >> 1) & 1) * bx1 + ((qq >> 2) & 1) * bxy1;
-        sv += trilin<double>(qq, x, y, zz) * yfull[bvx * MC + c];
+        const double f = trilin<double>(qq, x, y, zz);
+        double yv[4];
+        ld4(yfull + bvx * MC + cq, yv);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sv[j] += f * yv[j];
       }
-      cs += jv_w[k] * sv;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) cs[j] += wk * sv[j];
     }
-    acc += cs;
-    Z[g] = acc;
-    d += R[g] * acc;
+    double r[4];
+    ld4(R + o, r);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      acc[j] += cs[j];
+      d[j] += r[j] * acc[j];
+    }
+    st4(Z + o, acc);
   }
-  const double s = block_colsum<256>(d, red);
+  const double s = block_colsum4<256>(d, red);
   if (threadIdx.x < MC) part[blockIdx.x * MC + threadIdx.x] = s;
 }
 
