@@ -311,3 +311,24 @@ def test_cube64_solve_mixed(cube64):
     assert st["code"] == 0
     assert st["iters"] <= math.ceil(1.1 * io["iters"])
     assert st["relres_true"] <= 1.05e-8
+
+
+@pytest.mark.timeout(900)
+def test_leftover_reduced_system():
+    # 320 subdomains, 256 of them with 21-23 tile rows, and a reduced system of 16
+    # tile rows: 257 candidates for one workgroup each, so on a 256-unit device the
+    # smallest (the reduced system) is past the last full round and goes to work
+    # items in the same launch, whose partial sums the combine pass adds and
+    # scatters to the box grid
+    m = mg.box_mesh((64, 64, 36), 71, block=8, boxes=(8, 8, 5), faces=("z0",))
+    P = problem.from_mesh(m)
+    S = coarse.CoarseSolver.from_mesh(m)
+    r = np.random.default_rng(14).standard_normal(m.n_vert)
+    assert _rel(_np(S.apply_precond(_gpu(r))), P.apply_precond(r)) < 1e-12
+    uo, io = P.solve(m.b, tol=1e-8)
+    u, st = S.solve(_gpu(m.b), tol=1e-8)
+    assert st["code"] == 0 and st["iters"] == io["iters"]
+    assert np.linalg.norm(_np(u) - uo) / np.linalg.norm(uo) < 1e-9
+    S16 = coarse.CoarseSolver.from_mesh(m, precision="mixed16")
+    u16, st16 = S16.solve(_gpu(m.b), tol=1e-8)
+    assert st16["code"] == 0 and st16["relres_true"] <= 1.05e-8
