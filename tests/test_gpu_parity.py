@@ -181,7 +181,7 @@ def test_solve_small_mixed(name, make):
 @pytest.mark.parametrize("name,make", SMALL, ids=[s[0] for s in SMALL])
 def test_solve_small_mixed16(name, make):
     # FP16 storage of the inverses (per-system power-of-two scale), FP32 arithmetic.
-    # A reduced-byte form of the local solves is judged by iterations x bytes: it
+    # A reduced-byte form of the local solves is weighed by iterations x bytes: it
     # must reach the same 1e-8 true residual and move no more bytes through the
     # dense solves than the FP32 form (at most twice its iterations)
     m = make()
