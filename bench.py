@@ -299,19 +299,20 @@ def run_ablations(torch, coarse, mesh, b, tol, max_it=400):
     return out
 
 
-FP64_MFMA_PEAK_TFS = 78.6   # MI355X dense FP64 matrix peak
+FP64_MFMA_PEAK_TFS = 78.6    # MI355X dense FP64 matrix peak
+FP32_MFMA_PEAK_TFS = 157.3   # MI355X dense FP32 matrix peak
 
 
-def run_multi(torch, coarse, mg, mesh, tol, steps, warmup, k=16):
+def run_multi(torch, coarse, mg, mesh, tol, steps, warmup, k=16, precision="fp64"):
     """Block solve (coarse_solve_multi) of k right-hand sides on the bench mesh:
-    the load of the bench plus k - 1 bump loads, solved together in FP64. Host
-    clock over `steps` block solves; HIP events around each dense-solve launch
-    (k_m_gemv, MFMA FP64), whose algorithmic work is 2 n^2 k flops per system
-    and the packed inverse bytes read once."""
+    the load of the bench plus k - 1 bump loads, solved together. Host clock over
+    `steps` block solves; HIP events around each dense-solve launch (k_m_gemv on
+    the matrix cores: FP64, or FP32 for the mixed forms), whose algorithmic work
+    is 2 n^2 k flops per system and the packed inverse bytes read once."""
     rhs = [mesh.b] + [mg.rhs_bumps(mesh, 300 + j) for j in range(1, k)]
     B = torch.stack([torch.tensor(b, device="cuda") for b in rhs])
     U = torch.empty_like(B)
-    S = coarse.CoarseSolver.from_mesh(mesh)
+    S = coarse.CoarseSolver.from_mesh(mesh, precision=precision)
     for _ in range(warmup):
         S.solve_multi(B, tol, out=U)
     torch.cuda.synchronize()
@@ -330,15 +331,16 @@ def run_multi(torch, coarse, mg, mesh, tol, steps, warmup, k=16):
     work = steps * (max(iters) + 1)
     avg_s = ms / max(work, 1) / 1e3
     sum_n = info["sum_np"] + info["n_r"]
-    sum_n2 = info["inv_alg_bytes"] // 4 - sum_n    # from sum n(n+1)/2 * 8 bytes
+    sum_n2 = info["inv_alg_bytes"] // (INV_ELEM_BYTES[precision] // 2) - sum_n   # from sum n(n+1)/2 * es bytes
     flops = 2 * sum_n2 * k
-    return {"k": k, "solves_per_s": round(k * steps / elapsed, 2), "ms_per_block": round(1e3 * elapsed / steps, 3),
+    peak = FP64_MFMA_PEAK_TFS if precision == "fp64" else FP32_MFMA_PEAK_TFS
+    return {"k": k, "precision": precision, "solves_per_s": round(k * steps / elapsed, 2), "ms_per_block": round(1e3 * elapsed / steps, 3),
             "iters": iters, "relres_true_max": max(s["relres_true"] for s in st),
             "status": sorted({s["status"] for s in st}),
             "gemv": {"kernel": "k_m_gemv", "avg_launch_us": round(avg_s * 1e6, 2), "launches": cnt,
                      "work_launches": work, "alg_flops": flops,
-                     "TFLOPs": round(flops / avg_s / 1e12, 2),
-                     "frac_mfma_fp64": round(flops / avg_s / 1e12 / FP64_MFMA_PEAK_TFS, 4),
+                     "TFLOPs": round(flops / avg_s / 1e12, 2), "peak_TFLOPs": peak,
+                     "frac_mfma": round(flops / avg_s / 1e12 / peak, 4),
                      "alg_bytes": info["inv_alg_bytes"],
                      "GBs": round(info["inv_alg_bytes"] / avg_s / 1e9, 1)}}
 
@@ -489,6 +491,10 @@ def main():
         _log("block solve, 16 right-hand sides")
         multi = run_multi(torch, coarse, mg, mesh, args.tol, max(2, args.steps // 4), 1)
         multi["vs_single_fp64"] = round(multi["solves_per_s"] / fp64["solves_per_s"], 2)
+        if mixed16 is not None:
+            m16 = run_multi(torch, coarse, mg, mesh, args.tol, max(2, args.steps // 4), 1, precision="mixed16")
+            m16["vs_single_mixed16"] = round(m16["solves_per_s"] / mixed16["solves_per_s"], 2)
+            multi["mixed16"] = m16
         _log(f"block solve: {multi}")
 
     large = None

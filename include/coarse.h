@@ -256,10 +256,12 @@ int coarse_projection_reset(coarse_ctx *ctx);
  * that every read of the element matrices and of the stored dense inverses
  * serves all of them: the dense solves of the additive preconditioner (Sec. 3,
  * eq. (asm), and the reduced solve of Sec. 4) become products of each inverse
- * with a 16-column block, on the matrix cores. A column stops changing once it
- * has converged; the others go on. b, u: device float64 [k][n_vert] (column j at
- * offset j * n_vert), b != u. st: NULL or k entries, one per column (t_solve is
- * the block's). Needs an FP64 context in the additive mode (else EINVAL). The
+ * with a 16-column block, on the matrix cores (FP64 products for COARSE_FP64,
+ * FP32 products of the FP32 or FP16-stored inverses for the mixed forms; the
+ * operator, vectors and dot products are FP64 in every form). A column stops
+ * changing once it has converged; the others go on. b, u: device float64
+ * [k][n_vert] (column j at offset j * n_vert), b != u. st: NULL or k entries, one
+ * per column (t_solve is the block's). Needs the additive mode (else EINVAL). The
  * first call allocates the block's vectors (about 9 * 16 doubles per free
  * vertex) for the context's life. Returns the worst column status, as
  * coarse_solve. Results per column are bitwise reproducible and independent of

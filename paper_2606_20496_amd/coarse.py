@@ -399,7 +399,7 @@ class CoarseSolver:
     def solve_multi(self, B, tol=1e-8, out=None):
         """Block solve of the k = B.shape[0] right-hand sides (rows of B): k PCG
         recurrences that share every read of the operator and of the stored
-        inverses (FP64, additive mode). Returns (U, [stats per column])."""
+        inverses (additive mode, any precision). Returns (U, [stats per column])."""
         import torch
         self._sync_stream()
         out = torch.empty_like(B) if out is None else out

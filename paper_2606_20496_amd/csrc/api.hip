@@ -565,12 +565,21 @@ struct coarse_ctx {
     hipLaunchKernelGGL(k_m_scal, dim3(1), dim3(256), 0, stream, mb.ms, part, n, step);
   }
 
-  // Z = M R for every column (additive two-level preconditioner)
+  // Z = M R for every column (additive two-level preconditioner); T: the type
+  // the context stores J in
   void m_precond() {
+    if (precision == COARSE_FP64)
+      m_precond_t<double>();
+    else
+      m_precond_t<float>();
+  }
+
+  template <typename T>
+  void m_precond_t() {
     pbeg(1);
-    hipLaunchKernelGGL(k_m_pre, dim3(mb.ng + mb.nt), dim3(256), 0, stream, mb.ng, coarse_vec_off,
+    hipLaunchKernelGGL(k_m_pre<T>, dim3(mb.ng + mb.nt), dim3(256), 0, stream, mb.ng, coarse_vec_off,
                        (const int32_t *)sub_idx, (const double *)mb.R, mb.RP, (int)ntask, (const int32_t *)jt_start,
-                       (const int32_t *)jc_vid, (const double *)jc_w, (const double *)jc_xi, nent, mb.tpart,
+                       (const int32_t *)jc_vid, (const T *)jc_w, (const T *)jc_xi, nent, mb.tpart,
                        (const MScal *)mb.ms);
     pend(1);
     pbeg(2);
@@ -579,14 +588,24 @@ struct coarse_ctx {
                        (const MScal *)mb.ms);
     pend(2);
     pbeg(3);
-    hipLaunchKernelGGL(k_m_gemv, dim3((nblk(mb.nrows, 4) + 7) / 8 * 8), dim3(256), 0, stream, (const int2 *)mb.rows, mb.nrows,
-                       (const MSys *)mb.sys, (const double *)mb.RP, mb.ZP, mb.yfull, (const int32_t *)act_bv,
-                       (const MScal *)mb.ms);
+    const dim3 gg((nblk(mb.nrows, 4) + 7) / 8 * 8);
+    if (precision == COARSE_FP64)
+      hipLaunchKernelGGL(k_m_gemv<double>, gg, dim3(256), 0, stream, (const int2 *)mb.rows, mb.nrows,
+                         (const MSys *)mb.sys, (const double *)mb.RP, mb.ZP, mb.yfull, (const int32_t *)act_bv,
+                         (const MScal *)mb.ms);
+    else if (precision == COARSE_MIXED_F16)
+      hipLaunchKernelGGL(k_m_gemv<_Float16>, gg, dim3(256), 0, stream, (const int2 *)mb.rows, mb.nrows,
+                         (const MSys *)mb.sys, (const double *)mb.RP, mb.ZP, mb.yfull, (const int32_t *)act_bv,
+                         (const MScal *)mb.ms);
+    else
+      hipLaunchKernelGGL(k_m_gemv<float>, gg, dim3(256), 0, stream, (const int2 *)mb.rows, mb.nrows,
+                         (const MSys *)mb.sys, (const double *)mb.RP, mb.ZP, mb.yfull, (const int32_t *)act_bv,
+                         (const MScal *)mb.ms);
     pend(3);
     pbeg(5);
-    hipLaunchKernelGGL(k_m_final, dim3(mb.nvb), dim3(256), 0, stream, nf, (const int32_t *)cover_ptr,
+    hipLaunchKernelGGL(k_m_final<T>, dim3(mb.nvb), dim3(256), 0, stream, nf, (const int32_t *)cover_ptr,
                        (const int32_t *)cover_pos, (const double *)mb.ZP, (const int32_t *)jv_ptr,
-                       (const int32_t *)jv_base, (const double *)jv_w, (const double *)jv_xi, nent, bx1, bxy1,
+                       (const int32_t *)jv_base, (const T *)jv_w, (const T *)jv_xi, nent, bx1, bxy1,
                        (const double *)mb.yfull, mb.Z, (const double *)mb.R, mb.part, (const MScal *)mb.ms);
     pend(5);
   }
@@ -963,18 +982,16 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
     sd[k].yfull = red_sys ? c->yfull : nullptr;
     sd[k].act_bv = red_sys ? c->act_bv : nullptr;
   }
-  if (std::is_same<TT, double>::value) {
-    c->h_msys.resize(P.sys.size());
-    for (size_t k = 0; k < P.sys.size(); ++k) {
-      const System &S = P.sys[k];
-      MSys &m = c->h_msys[k];
-      m.tiles = (const double *)sd[k].tiles;
-      m.voff = S.vec_off;
-      m.nb = (int32_t)S.nb;
-      m.n = (int32_t)S.n;
-      m.red = (int64_t)k == P.n_local_sys ? 1 : 0;
-      m.pad = 0;
-    }
+  c->h_msys.resize(P.sys.size());
+  for (size_t k = 0; k < P.sys.size(); ++k) {
+    const System &S = P.sys[k];
+    MSys &m = c->h_msys[k];
+    m.tiles = sd[k].tiles;
+    m.voff = S.vec_off;
+    m.nb = (int32_t)S.nb;
+    m.n = (int32_t)S.n;
+    m.red = (int64_t)k == P.n_local_sys ? 1 : 0;
+    m.scale = sys_scale[k];
   }
   c->n_bv = P.n_bv;
   c->n_partials = P.n_partials;
@@ -1352,8 +1369,8 @@ int check_multi(coarse_ctx *c, int k) {
     c->err = "the block solve takes 1 to COARSE_MULTI_MAX right-hand sides";
     return COARSE_EINVAL;
   }
-  if (c->precision != COARSE_FP64 || c->mode != COARSE_ADDITIVE || c->h_msys.empty()) {
-    c->err = "the block solve needs an FP64 context with the additive preconditioner";
+  if (c->mode != COARSE_ADDITIVE || c->h_msys.empty()) {
+    c->err = "the block solve needs a context with the additive preconditioner";
     return COARSE_EINVAL;
   }
   if ((OP_BLOCK * 8 + c->max_slots * MCW) * (int64_t)sizeof(double) > 65536) {

@@ -4,7 +4,10 @@
 // are vertex-major, MC doubles per vertex (one 128-byte line), so every gather
 // through an index list reads whole lines. The dense solves A_s^{-1} [r_1 .. r_MC]
 // of the additive preconditioner (Sec. 3, eq. (asm); Sec. 4) are small matrix
-// products on the matrix cores. FP64 throughout.
+// products on the matrix cores: FP64 tiles on v_mfma_f64_16x16x4f64, FP32 and
+// FP16-stored tiles (widened to FP32 in LDS, the power-of-two scale applied to
+// the result) on v_mfma_f32_16x16x4f32. Vectors, dots and the operator are FP64
+// in every form.
 //
 // Every sum over the vector runs over a fixed grid in a fixed order (per
 // workgroup, then one workgroup over the partials), so each column's result is
@@ -12,6 +15,8 @@
 #pragma once
 
 #include "kernels.h"
+
+#include <type_traits>
 
 namespace coarse {
 
@@ -32,11 +37,11 @@ struct MScal {
 
 // One dense system for the block GEMV.
 struct MSys {
-  const double *tiles;   // lower tiles of A_s^{-1}, TILE x TILE row-major each
+  const void *tiles;     // lower tiles of A_s^{-1} (or of A_s^{-1} / scale), TILE x TILE row-major each
   int64_t voff;          // first packed entry of the system
   int32_t nb, n;
   int32_t red;           // 1: the reduced system (solution also goes to the box grid)
-  int32_t pad;
+  float scale;           // FP16 tiles hold A_s^{-1} / scale (1 otherwise)
 };
 
 // what a k_m_scal launch forms from the column totals of its partials
@@ -462,10 +467,11 @@ __global__ __launch_bounds__(256) void k_m_update(int64_t nf, OpDev op, const do
 // r_p = R_p r for every column into the packed vectors (padding = 0); the others
 // take one J^T task per wavefront, lanes (entry group g = l / MC, column l % MC),
 // and write its 8 corner sums per column.
+template <typename T>
 __global__ __launch_bounds__(256) void k_m_pre(int ng, int64_t n_pack, const int32_t *__restrict__ idx,
                                                const double *__restrict__ R, double *__restrict__ RP, int ntask,
                                                const int32_t *__restrict__ tstart, const int32_t *__restrict__ vid,
-                                               const double *__restrict__ w, const double *__restrict__ xi,
+                                               const T *__restrict__ w, const T *__restrict__ xi,
                                                int64_t nent, double *__restrict__ tpart,
                                                const MScal *__restrict__ ms) {
   if (ms->all_done) return;
@@ -485,7 +491,7 @@ __global__ __launch_bounds__(256) void k_m_pre(int ng, int64_t n_pack, const int
     for (int k = 0; k < 8; ++k) acc[k] = 0.0;
     const int j1 = tstart[task + 1];
     for (int j = tstart[task] + eg; j < j1; j += WAVE / MC) {
-      const double v = w[j] * R[(int64_t)vid[j] * MC + c];
+      const double v = (double)w[j] * R[(int64_t)vid[j] * MC + c];
       const double x = xi[j], y = xi[nent + j], zz = xi[2 * nent + j];
 #pragma unroll
       for (int k = 0; k < 8; ++k) acc[k] += trilin<double>(k, x, y, zz) * v;
@@ -553,12 +559,11 @@ __device__ __forceinline__ double ldg(const double *p) {
 // the compiler moves no memory access across this point
 __device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
-__global__ __launch_bounds__(256) void k_m_gemv(const int2 *__restrict__ rows, int nrows,
-                                                const MSys *__restrict__ sys, const double *__restrict__ RP,
-                                                double *__restrict__ ZP, double *__restrict__ yfull,
-                                                const int32_t *__restrict__ act_bv, const MScal *__restrict__ ms) {
+__device__ __forceinline__ void gemv_row_f64(const int2 *__restrict__ rows, int nrows,
+                                             const MSys *__restrict__ sys, const double *__restrict__ RP,
+                                             double *__restrict__ ZP, double *__restrict__ yfull,
+                                             const int32_t *__restrict__ act_bv) {
   __shared__ __attribute__((aligned(16))) double stage[4][TILE * MLD];
-  if (ms->all_done) return;
   // consecutive rows (those of one system) go to workgroups of one XCD: the
   // grid is a multiple of 8 and workgroup b runs on XCD b % 8
   const int per = (int)gridDim.x / 8;
@@ -577,7 +582,7 @@ __global__ __launch_bounds__(256) void k_m_gemv(const int2 *__restrict__ rows, i
   // J) mod nb, so its second read comes from the L2
   auto tile_at = [&](int J) -> const double2 * {
     const int64_t toff = (J <= I) ? (int64_t)I * (I + 1) / 2 + J : (int64_t)J * (J + 1) / 2 + I;
-    return (const double2 *)(S.tiles + toff * (TILE * TILE));
+    return (const double2 *)((const double *)S.tiles + toff * (TILE * TILE));
   };
   double2 tv[8];
   double bv[8];
@@ -636,12 +641,154 @@ __global__ __launch_bounds__(256) void k_m_gemv(const int2 *__restrict__ rows, i
   }
 }
 
+// FP32 and FP16-stored tiles: the same walk, with v_mfma_f32_16x16x4f32 (A and
+// B as for the FP64 form; lane l holds rows 4(l/16) .. 4(l/16) + 3 of column l%16
+// of the 16 x 16 accumulator) and FP32 arithmetic as in the single-vector mixed
+// forms. A tile is loaded with 16-byte loads (four per lane for FP32, two for
+// FP16), widened to FP32 and staged in the wavefront's LDS region (row stride
+// MLDF floats).
+constexpr int MLDF = TILE + 4;
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float nt_f4g __attribute__((ext_vector_type(4)));
+typedef _Float16 nt_h8g __attribute__((ext_vector_type(8)));
+
+template <typename TT>
+struct NarrowTile;
+
+template <>
+struct NarrowTile<float> {
+  static constexpr int NL = 4;   // 16-byte loads per lane
+  typedef nt_f4g V;
+  // piece m of lane `lane`: row, first column; 4 values
+  __device__ static void place(int m, int lane, int &row, int &col) {
+    const int c = m * 64 + lane;
+    row = c / 8;
+    col = 4 * (c % 8);
+  }
+  __device__ static void store(float *L, int row, int col, const V &v) {
+    *(float4 *)(L + row * MLDF + col) = make_float4(v.x, v.y, v.z, v.w);
+  }
+};
+
+template <>
+struct NarrowTile<_Float16> {
+  static constexpr int NL = 2;
+  typedef nt_h8g V;
+  __device__ static void place(int m, int lane, int &row, int &col) {
+    const int c = m * 64 + lane;
+    row = c / 4;
+    col = 8 * (c % 4);
+  }
+  __device__ static void store(float *L, int row, int col, const V &v) {
+    *(float4 *)(L + row * MLDF + col) = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+    *(float4 *)(L + row * MLDF + col + 4) = make_float4((float)v[4], (float)v[5], (float)v[6], (float)v[7]);
+  }
+};
+
+template <typename TT>
+__device__ __forceinline__ void gemv_row_narrow(const int2 *__restrict__ rows, int nrows,
+                                                const MSys *__restrict__ sys, const double *__restrict__ RP,
+                                                double *__restrict__ ZP, double *__restrict__ yfull,
+                                                const int32_t *__restrict__ act_bv) {
+  typedef NarrowTile<TT> NT;
+  __shared__ __attribute__((aligned(16))) float stage[4][TILE * MLDF];
+  const int per = (int)gridDim.x / 8;
+  const int wl = ((int)blockIdx.x % 8) * per + (int)blockIdx.x / 8;
+  const int row = wl * 4 + (threadIdx.x >> 6);
+  if (row >= nrows) return;   // no workgroup barrier below
+  const int lane = threadIdx.x & 63, li = lane % 16, lk = lane / 16;
+  const int2 sr = rows[row];
+  const MSys S = sys[sr.x];
+  const int I = sr.y, nb = S.nb;
+  const double *__restrict__ Rs = RP + S.voff * MC;
+  float *L = stage[threadIdx.x >> 6];
+  auto tile_at = [&](int J) -> const typename NT::V * {
+    const int64_t toff = (J <= I) ? (int64_t)I * (I + 1) / 2 + J : (int64_t)J * (J + 1) / 2 + I;
+    return (const typename NT::V *)((const TT *)S.tiles + toff * (TILE * TILE));
+  };
+  auto ld = [&](const typename NT::V *p) -> typename NT::V {
+    return *(const __attribute__((address_space(1))) typename NT::V *)p;
+  };
+  typename NT::V tv[NT::NL];
+  float bv[8];
+  int J = (I == 0) ? 0 : nb - I;
+  {
+    const typename NT::V *t = tile_at(J);
+#pragma unroll
+    for (int m = 0; m < NT::NL; ++m) tv[m] = ld(t + m * 64 + lane);
+#pragma unroll
+    for (int st = 0; st < 8; ++st) bv[st] = (float)ldg(Rs + (int64_t)(J * TILE + 4 * st + lk) * MC + li);
+  }
+  v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+  for (int s = 0; s < nb; ++s) {
+#pragma unroll
+    for (int m = 0; m < NT::NL; ++m) {
+      int r0, c0;
+      NT::place(m, lane, r0, c0);
+      NT::store(L, r0, c0, tv[m]);
+    }
+    float bc[8];
+#pragma unroll
+    for (int st = 0; st < 8; ++st) bc[st] = bv[st];
+    const bool low = J <= I;
+    const int J1 = (s + 1 < nb) ? ((J + 1 == nb) ? 0 : J + 1) : J;
+    {
+      const typename NT::V *t = tile_at(J1);
+#pragma unroll
+      for (int m = 0; m < NT::NL; ++m) tv[m] = ld(t + m * 64 + lane);
+#pragma unroll
+      for (int st = 0; st < 8; ++st) bv[st] = (float)ldg(Rs + (int64_t)(J1 * TILE + 4 * st + lk) * MC + li);
+    }
+    wave_lds_sync();
+    float a0[8], a1[8];
+#pragma unroll
+    for (int st = 0; st < 8; ++st) {
+      const int k = 4 * st + lk;
+      a0[st] = L[low ? li * MLDF + k : k * MLDF + li];
+      a1[st] = L[low ? (16 + li) * MLDF + k : k * MLDF + 16 + li];
+    }
+#pragma unroll
+    for (int st = 0; st < 8; ++st) {
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[st], bc[st], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[st], bc[st], acc1, 0, 0, 0);
+    }
+    wave_lds_sync();
+    J = J1;
+  }
+  double *Zs = ZP + S.voff * MC;
+  const double sc = (double)S.scale;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i0 = I * TILE + 4 * lk + r, i1 = i0 + 16;
+    const double z0 = (double)acc0[r] * sc, z1 = (double)acc1[r] * sc;
+    Zs[(int64_t)i0 * MC + li] = z0;
+    Zs[(int64_t)i1 * MC + li] = z1;
+    if (S.red) {
+      if (i0 < S.n) yfull[(int64_t)act_bv[i0] * MC + li] = z0;
+      if (i1 < S.n) yfull[(int64_t)act_bv[i1] * MC + li] = z1;
+    }
+  }
+}
+
+template <typename TT>
+__global__ __launch_bounds__(256) void k_m_gemv(const int2 *__restrict__ rows, int nrows,
+                                                const MSys *__restrict__ sys, const double *__restrict__ RP,
+                                                double *__restrict__ ZP, double *__restrict__ yfull,
+                                                const int32_t *__restrict__ act_bv, const MScal *__restrict__ ms) {
+  if (ms->all_done) return;
+  if constexpr (std::is_same<TT, double>::value)
+    gemv_row_f64(rows, nrows, sys, RP, ZP, yfull, act_bv);
+  else
+    gemv_row_narrow<TT>(rows, nrows, sys, RP, ZP, yfull, act_bv);
+}
+
 // z = sum_p R_p^T z_p + J y_r per column (Sec. 3, Sec. 4), and the partials of
 // (r_c, z_c)
+template <typename T>
 __global__ __launch_bounds__(256) void k_m_final(int64_t nf, const int32_t *__restrict__ cover_ptr,
                                                  const int32_t *__restrict__ cover_pos, const double *__restrict__ ZP,
                                                  const int32_t *__restrict__ jv_ptr, const int32_t *__restrict__ jv_base,
-                                                 const double *__restrict__ jv_w, const double *__restrict__ jv_xi,
+                                                 const T *__restrict__ jv_w, const T *__restrict__ jv_xi,
                                                  int64_t nent, int bx1, int bxy1, const double *__restrict__ yfull,
                                                  double *__restrict__ Z, const double *__restrict__ R,
                                                  double *__restrict__ part, const MScal *__restrict__ ms) {
@@ -662,7 +809,7 @@ __global__ __launch_bounds__(256) void k_m_final(int64_t nf, const int32_t *__re
     double cs[4] = {0.0, 0.0, 0.0, 0.0};
     for (int k = jv_ptr[i]; k < jv_ptr[i + 1]; ++k) {
       const int64_t b0 = jv_base[k];
-      const double x = jv_xi[k], y = jv_xi[nent + k], zz = jv_xi[2 * nent + k], wk = jv_w[k];
+      const double x = jv_xi[k], y = jv_xi[nent + k], zz = jv_xi[2 * nent + k], wk = (double)jv_w[k];
       double sv[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int qq = 0; qq < 8; ++qq) {

@@ -2,7 +2,11 @@
 one mesh, solved by independent PCG recurrences that share the operator's and the
 stored inverses' reads (the dense solves on the matrix cores). Each column is held
 to the single-vector bars against the FP64 oracle: one preconditioner application
-at 1e-12 (relative, max norm), PCG to 1e-8 with the oracle's iteration count."""
+at 1e-12 (relative, max norm), PCG to 1e-8 with the oracle's iteration count. The
+mixed forms (FP32 / FP16-stored inverses, FP32 matrix-core products) are held to
+the mixed bars: the same 1e-8 true residual with at most 10% more iterations."""
+import math
+
 import numpy as np
 import pytest
 
@@ -79,6 +83,28 @@ def test_multi_solve_matches_oracle(name, make):
         assert np.all(U[j][m.dirichlet.astype(bool)] == 0)
 
 
+@pytest.mark.parametrize("precision", ["mixed", "mixed16"])
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_multi_solve_mixed(name, make, precision):
+    m = make()
+    P = problem.from_mesh(m)
+    S = coarse.CoarseSolver.from_mesh(m, precision=precision)
+    # one application against the single-vector mixed path of the same context
+    # (both FP32 products of the same stored inverses, other summation orders)
+    R = np.random.default_rng(4).standard_normal((3, m.n_vert))
+    Z = _np(S.apply_precond_multi(_gpu(R)))
+    for j in range(R.shape[0]):
+        assert _rel(Z[j], _np(S.apply_precond(_gpu(R[j])))) < 2e-5
+    B = _rhs(m, 3, 45)
+    U, st = S.solve_multi(_gpu(B), tol=1e-8)
+    U = _np(U)
+    for j in range(B.shape[0]):
+        uo, io = P.solve(B[j], tol=1e-8)
+        assert st[j]["status"] == 0 and st[j]["iters"] <= math.ceil(1.1 * io["iters"])
+        assert st[j]["relres_true"] <= 1.05e-8
+        assert np.linalg.norm(U[j] - uo) / np.linalg.norm(uo) < 1e-6
+
+
 def test_multi_columns_independent():
     # 16 columns with a zero column and a repeated one: every column equals,
     # bitwise, the block solve of that column alone; the zero column gives u = 0
@@ -108,13 +134,10 @@ def test_multi_rejects_bad_arguments():
     S = coarse.CoarseSolver.from_mesh(m)
     with pytest.raises(ValueError):
         S.solve_multi(torch.zeros((17, m.n_vert), dtype=torch.float64, device="cuda"))
-    S16 = coarse.CoarseSolver.from_mesh(m, precision="mixed16")
-    with pytest.raises(coarse.CoarseError) as ei:
-        S16.solve_multi(torch.zeros((2, m.n_vert), dtype=torch.float64, device="cuda"))
-    assert ei.value.code == -1
     Sl = coarse.CoarseSolver.from_mesh(m, mode="local_only")
-    with pytest.raises(coarse.CoarseError):
+    with pytest.raises(coarse.CoarseError) as ei:
         Sl.apply_precond_multi(torch.zeros((2, m.n_vert), dtype=torch.float64, device="cuda"))
+    assert ei.value.code == -1
 
 
 # ---------------------------------------------------------------------------
@@ -143,3 +166,9 @@ def test_multi_cube64():
         u, s = S.solve(_gpu(B[j]), tol=1e-8)
         assert s["iters"] == st[j]["iters"]
         assert np.linalg.norm(_np(u) - U[j]) / np.linalg.norm(U[j]) < 1e-8
+    # the FP16-stored form on the same block
+    S16 = coarse.CoarseSolver.from_mesh(m, precision="mixed16")
+    U16, st16 = S16.solve_multi(_gpu(B), tol=1e-8)
+    for j in range(16):
+        assert st16[j]["status"] == 0 and st16[j]["relres_true"] <= 1.05e-8
+        assert st16[j]["iters"] <= math.ceil(1.1 * st[j]["iters"])
