@@ -164,7 +164,10 @@ def run_serving_resident(torch, coarse, mg, tol, rates=(500.0, 2000.0, 8000.0, 3
     beforehand (both for the continuous-batching server, mixed precision, and for
     the plain FP64 one-at-a-time path); requests arrive as a Poisson stream at
     each rate, each for a uniformly drawn mesh with a fresh N(0,1) right-hand
-    side (uploaded from the host inside the loop). Latency is arrival to result."""
+    side (uploaded from the host inside the loop). Latency is arrival to result.
+    Each rate runs three ways: the lock-step batch alone; the batch plus block
+    solves of same-mesh requests that wait for their context; and FP64 one at a
+    time."""
     from paper_2606_20496_amd import serve
     meshes = mg.batch_meshes(count=64)
     srv = serve.Server(budget_bytes=200e9, precision=precision, use_graph=True, step_iters=2)
@@ -177,17 +180,32 @@ def run_serving_resident(torch, coarse, mg, tol, rates=(500.0, 2000.0, 8000.0, 3
     # warm-up pass (graph capture, allocator) outside the measured runs
     warm = serve.make_resident_requests(meshes, 4000.0, 128, seed=1)
     srv.run(warm)
+    # the block solve's vectors of every context (allocated at its first use)
+    for S in srv.cache.values():
+        S.solve_multi(torch.zeros((1, S.n_vert), dtype=torch.float64, device="cuda"))
+    srv.block_min = 2
+    srv.run(warm)
+    srv.block_min = 0
     serve.serve_sequential(warm[:32], tol=tol, cache=seq_cache)
     for rate in rates:
         reqs = serve.make_resident_requests(meshes, rate, count, seed=int(rate))
         rec, wall = srv.run(reqs)
         served = serve.summarize(rec, wall)
+        # the same server with block solves for same-mesh requests that wait (4
+        # or more: a block solve runs synchronously between lock steps, so small
+        # groups stall the batch more than they save)
+        srv.block_min = 4
+        rec3, wall3 = srv.run(reqs)
+        srv.block_min = 0
+        blocked = serve.summarize(rec3, wall3)
         rec2, wall2 = serve.serve_sequential(reqs, tol=tol, cache=seq_cache)
         seq = serve.summarize(rec2, wall2)
         keep = ("solves_per_s", "p50_ms", "p99_ms", "mean_iters", "max_relres_true", "failed")
         out["rates"][str(int(rate))] = {"batched_" + precision: {k: served[k] for k in keep},
+                                        "batched_block_" + precision: {k: blocked[k] for k in keep},
                                         "one_at_a_time_fp64": {k: seq[k] for k in keep}}
         _log(f"serving rate {rate}: batched {served['solves_per_s']:.0f}/s p99 {served['p99_ms']:.1f} ms; "
+             f"with block solves {blocked['solves_per_s']:.0f}/s p99 {blocked['p99_ms']:.1f} ms; "
              f"one-at-a-time {seq['solves_per_s']:.0f}/s p99 {seq['p99_ms']:.1f} ms")
     srv.close()
     for S in seq_cache.values():

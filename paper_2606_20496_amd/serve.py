@@ -71,7 +71,7 @@ def summarize(records, wall):
 
 class Server:
     def __init__(self, budget_bytes, precision="mixed", use_graph=True, step_iters=2, tol=1e-8,
-                 plan_workers=2, solver_kw=None, keep_outputs=False, adaptive_steps=True):
+                 plan_workers=2, solver_kw=None, keep_outputs=False, adaptive_steps=True, block_min=0):
         import torch
         self.torch = torch
         self.budget = int(budget_bytes)
@@ -92,6 +92,11 @@ class Server:
         self.keep_outputs = keep_outputs
         self.last_iters = {}                     # key -> iterations of its last solve
         self.adaptive_steps = adaptive_steps
+        # block_min >= 2: when at least that many requests wait for one idle
+        # resident mesh, up to coarse.MULTI_MAX of them are solved together by
+        # one block solve (the dense solves on the matrix cores), between lock
+        # steps of the batch
+        self.block_min = int(block_min)
 
     def _plan(self, mesh):
         return coarse.Plan.from_mesh(mesh, precision=self.precision, **self.solver_kw)
@@ -155,6 +160,32 @@ class Server:
                 if fut.done():
                     del self.planning[key]
                     self.ready[key] = fut.result()
+            # same-mesh requests waiting for an idle resident context: one block solve
+            if self.block_min >= 2 and waiting:
+                groups = collections.OrderedDict()
+                for rq in waiting:
+                    if rq.key in self.cache and rq.key not in self.busy:
+                        groups.setdefault(rq.key, []).append(rq)
+                solved = set()
+                for key, rqs in groups.items():
+                    if len(rqs) < self.block_min:
+                        continue
+                    rqs = rqs[:coarse.MULTI_MAX]
+                    S = self.cache[key]
+                    self.cache.move_to_end(key)
+                    with torch.cuda.stream(self.stream):
+                        B = torch.tensor(np.stack([rq.b for rq in rqs]), device="cuda")
+                        U, sts = S.solve_multi(B, self.tol)
+                    t_done = now()
+                    for j, rq in enumerate(rqs):
+                        records.append(Record(rid=rq.rid, key=rq.key, t_arrive=rq.t_arrive, t_done=t_done,
+                                              iters=sts[j]["iters"], relres_true=sts[j]["relres_true"],
+                                              setup=rq.rid in missed, status=sts[j]["status"],
+                                              u=U[j] if self.keep_outputs else None))
+                        solved.add(rq.rid)
+                    self.last_iters[key] = max(s["iters"] for s in sts)
+                if solved:
+                    waiting = collections.deque(rq for rq in waiting if rq.rid not in solved)
             # admit waiting requests whose context is resident and idle
             keep = collections.deque()
             for rq in waiting:

@@ -128,3 +128,35 @@ def test_graph_replay_waits_for_a_new_solves_start(precision):
         rec = by_id[rq.rid]
         assert rec.status == 0 and rec.iters == st["iters"] and torch.equal(rec.u, u), rq.rid
     srv.close()
+
+
+def test_resident_serving_with_block_solves():
+    # a burst of 40 requests on three resident meshes: same-mesh requests that wait
+    # for an idle context are solved together by block solves; every result equals,
+    # bit for bit, the block solve of that right-hand side alone (the columns of a
+    # block never mix), and reaches the tolerance
+    from paper_2606_20496_amd import meshgen as mg
+    meshes = mg.batch_meshes(count=3, nmax=12)
+    reqs = serve.make_resident_requests(meshes, rate=200000.0, count=40, seed=5)
+    srv = serve.Server(budget_bytes=8e9, precision="mixed", use_graph=True, step_iters=2, keep_outputs=True,
+                       block_min=2)
+    solvers = {k: srv.preload(k, m) for k, m in enumerate(meshes)}
+    # every request has arrived when the loop starts
+    import time
+    records, wall = srv.run(reqs, t0=time.perf_counter() - 1.0)
+    assert len(records) == 40 and all(r.status == 0 and r.relres_true <= 1.05e-8 for r in records)
+    by_id = {r.rid: r for r in records}
+    blocked = 0
+    for rq in reqs:
+        b = torch.tensor(rq.b, device="cuda")
+        u1, st1 = solvers[rq.key].solve_multi(b[None])
+        u, st = solvers[rq.key].solve(b)
+        r = by_id[rq.rid]
+        if torch.equal(r.u, u1[0]):
+            blocked += 1
+            assert r.iters == st1[0]["iters"]
+        else:
+            # admitted alone into the lock-step batch: bitwise the solo solve
+            assert torch.equal(r.u, u) and r.iters == st["iters"], rq.rid
+    assert blocked >= 30
+    srv.close()
