@@ -159,7 +159,7 @@ def run_batch_workload(torch, coarse, mg, tol, reps=3):
 
 
 def run_serving_resident(torch, coarse, mg, tol, rates=(500.0, 2000.0, 8000.0, 32000.0), count=2048,
-                         precision="mixed"):
+                         precision="mixed", block_min=8):
     """Open-loop serving over resident contexts: the 64 batch meshes are set up
     beforehand (both for the continuous-batching server, mixed precision, and for
     the plain FP64 one-at-a-time path); requests arrive as a Poisson stream at
@@ -176,7 +176,7 @@ def run_serving_resident(torch, coarse, mg, tol, rates=(500.0, 2000.0, 8000.0, 3
     seq_cache = {k: coarse.CoarseSolver.from_mesh(m, precision="fp64") for k, m in enumerate(meshes)}
     torch.cuda.synchronize()
     out = {"meshes": len(meshes), "requests_per_rate": count, "precision": precision,
-           "resident_bytes": srv.used, "rates": {}}
+           "resident_bytes": srv.used, "block_min": block_min, "rates": {}}
     # warm-up pass (graph capture, allocator) outside the measured runs
     warm = serve.make_resident_requests(meshes, 4000.0, 128, seed=1)
     srv.run(warm)
@@ -191,10 +191,9 @@ def run_serving_resident(torch, coarse, mg, tol, rates=(500.0, 2000.0, 8000.0, 3
         reqs = serve.make_resident_requests(meshes, rate, count, seed=int(rate))
         rec, wall = srv.run(reqs)
         served = serve.summarize(rec, wall)
-        # the same server with block solves for same-mesh requests that wait (4
-        # or more: a block solve runs synchronously between lock steps, so small
-        # groups stall the batch more than they save)
-        srv.block_min = 4
+        # the same server with block solves for same-mesh requests that wait
+        # (block_min or more), stepped beside the lock steps
+        srv.block_min = block_min
         rec3, wall3 = srv.run(reqs)
         srv.block_min = 0
         blocked = serve.summarize(rec3, wall3)

@@ -274,6 +274,23 @@ int coarse_solve_multi(coarse_ctx *ctx, int k, const double *b, double *u, doubl
  * coarse_solve_multi. */
 int coarse_apply_precond_multi(coarse_ctx *ctx, int k, const double *r, double *z);
 
+/* The block solve in steps, for a loop that interleaves it with other work on the
+ * context's stream (a serving loop's lock steps). Same iteration and results as
+ * coarse_solve_multi. begin enqueues r = b and the first preconditioner
+ * application (b: device float64 [k][n_vert], kept alive by the caller until end);
+ * advance enqueues `iters` iterations of the live columns and a copy of the solver
+ * state to pinned host memory; once the caller has synchronised the stream,
+ * coarse_multi_done returns 1 when every column has finished (0 if not, as of the
+ * last advance); end enqueues the true residuals and the solutions (u: [k][n_vert],
+ * u != b), synchronises the stream, fills st (NULL or k entries) and returns the
+ * worst column status. One block solve per context at a time: begin (and the other
+ * block calls) fail with EINVAL while one is in progress, and so do advance, done
+ * and end without one. */
+int coarse_multi_begin(coarse_ctx *ctx, int k, const double *b, double tol);
+int coarse_multi_advance(coarse_ctx *ctx, int iters);
+int coarse_multi_done(const coarse_ctx *ctx);
+int coarse_multi_end(coarse_ctx *ctx, double *u, coarse_stats *st);
+
 /* Solve `count` independent systems (any mix of contexts, each with its own right-
  * hand side) in lock step: every PCG phase of all live systems is issued before
  * the next phase, and each phase of all of them is one launch.

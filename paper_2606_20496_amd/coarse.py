@@ -32,7 +32,8 @@ EXPORTS = ("coarse_default_opts", "coarse_setup", "coarse_apply_precond", "coars
            "coarse_batch_step", "coarse_batch_live", "coarse_batch_destroy", "coarse_plan_create",
            "coarse_setup_from_plan", "coarse_plan_destroy", "coarse_plan_set_gemv_tiles",
            "coarse_solve_projected", "coarse_projection_reset", "coarse_solve_multi",
-           "coarse_apply_precond_multi")
+           "coarse_apply_precond_multi", "coarse_multi_begin", "coarse_multi_advance", "coarse_multi_done",
+           "coarse_multi_end")
 
 PHASES = ("A+p", "R_p+J^T", "J^T corners", "A_p^-1/A_r^-1 gemv", "combine", "sum+J", "x,r update",
           "reduced branch (second stream)")
@@ -133,6 +134,14 @@ def load():
     L.coarse_solve_multi.restype = i32
     L.coarse_apply_precond_multi.argtypes = [vp, i32, vp, vp]
     L.coarse_apply_precond_multi.restype = i32
+    L.coarse_multi_begin.argtypes = [vp, i32, vp, dbl]
+    L.coarse_multi_begin.restype = i32
+    L.coarse_multi_advance.argtypes = [vp, i32]
+    L.coarse_multi_advance.restype = i32
+    L.coarse_multi_done.argtypes = [vp]
+    L.coarse_multi_done.restype = i32
+    L.coarse_multi_end.argtypes = [vp, vp, ctypes.POINTER(_Stats)]
+    L.coarse_multi_end.restype = i32
     L.coarse_solve_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i32, dbl,
                                      ctypes.POINTER(_Stats)]
     L.coarse_solve_batch.restype = i32
@@ -409,6 +418,40 @@ class CoarseSolver:
         if out.shape != B.shape or out.data_ptr() == B.data_ptr():
             raise ValueError("out must be a distinct tensor of the shape of B")
         rc = self._check(self._L.coarse_solve_multi(self._ctx, k, pb, pu, float(tol), st))
+        stats = []
+        for j in range(k):
+            d = {f: getattr(st[j], f) for f, _ in _Stats._fields_}
+            d["code"] = rc
+            stats.append(d)
+        return out, stats
+
+    def multi_begin(self, B, tol=1e-8):
+        """Start a block solve of the rows of B without waiting for it (the
+        stepped form of solve_multi); B must stay alive until multi_end."""
+        self._sync_stream()
+        self._check(self._L.coarse_multi_begin(self._ctx, int(B.shape[0]), self._block(B), float(tol)))
+        self._multi_b = B
+
+    def multi_advance(self, iters):
+        """Enqueue `iters` iterations of the live columns (no wait)."""
+        self._sync_stream()
+        self._check(self._L.coarse_multi_advance(self._ctx, int(iters)))
+
+    def multi_done(self):
+        """Whether every column had finished at the last advance (call after the
+        stream has been synchronised)."""
+        return self._check(self._L.coarse_multi_done(self._ctx)) == 1
+
+    def multi_end(self, out=None):
+        """Finish the block solve begun by multi_begin: (U, [stats per column])."""
+        import torch
+        self._sync_stream()
+        B = self._multi_b
+        out = torch.empty_like(B) if out is None else out
+        k = int(B.shape[0])
+        st = (_Stats * k)()
+        rc = self._check(self._L.coarse_multi_end(self._ctx, self._block(out), st))
+        self._multi_b = None
         stats = []
         for j in range(k):
             d = {f: getattr(st[j], f) for f, _ in _Stats._fields_}

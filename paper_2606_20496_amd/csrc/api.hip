@@ -187,6 +187,9 @@ struct coarse_ctx {
     MSys *sys = nullptr;
     int nrows = 0, nvb = 1, ng = 1, nt = 1, last_iters = 0;
     int32_t lds = 0;
+    bool active = false;   // a block solve begun by coarse_multi_begin and not yet ended
+    int k = 0;
+    double t0 = 0.0;
   } mb;
 
   // phase timers
@@ -1564,30 +1567,10 @@ int coarse_solve(coarse_ctx *c, const double *b, double *u, double tol, coarse_s
   return run_solve(c, b, u, tol, st, false);
 }
 
-int coarse_solve_multi(coarse_ctx *c, int k, const double *b, double *u, double tol, coarse_stats *st) {
-  if (!c || !b || !u || b == u || !(tol > 0)) return COARSE_EINVAL;
-  int rc = check_multi(c, k);
-  if (rc) return rc;
-  const double t0 = now();
-  try {
-    c->m_init();
-    c->m_start(b, k, tol);
-    int batch = std::max(c->check_every, c->mb.last_iters);
-    for (;;) {
-      for (int j = 0; j < batch; ++j) c->m_iteration();
-      batch = c->check_every;
-      HIPCHK(hipGetLastError());
-      HIPCHK(hipMemcpyAsync(c->mb.h_ms, c->mb.ms, sizeof(MScal), hipMemcpyDeviceToHost, c->stream));
-      HIPCHK(hipStreamSynchronize(c->stream));
-      c->pcollect();
-      if (c->mb.h_ms->all_done) break;
-    }
-    c->m_finish(u, k);
-    HIPCHK(hipStreamSynchronize(c->stream));
-    c->pcollect();
-  } catch (const Fail &f) {
-    return fail_ctx(c, f);
-  }
+namespace {
+
+// the per-column statistics of a finished block solve; returns the worst status
+int multi_stats(coarse_ctx *c, int k, coarse_stats *st, double t0) {
   const MScal &m = *c->mb.h_ms;
   int worst = COARSE_OK, most = 0;
   for (int j = 0; j < k; ++j) {
@@ -1611,10 +1594,107 @@ int coarse_solve_multi(coarse_ctx *c, int k, const double *b, double *u, double 
   return worst;
 }
 
+}  // namespace
+
+int coarse_multi_begin(coarse_ctx *c, int k, const double *b, double tol) {
+  if (!c || !b || !(tol > 0)) return COARSE_EINVAL;
+  int rc = check_multi(c, k);
+  if (rc) return rc;
+  if (c->mb.active) {
+    c->err = "a block solve is in progress on this context";
+    return COARSE_EINVAL;
+  }
+  try {
+    c->m_init();
+    c->mb.t0 = now();
+    c->m_start(b, k, tol);
+    HIPCHK(hipMemcpyAsync(c->mb.h_ms, c->mb.ms, sizeof(MScal), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipGetLastError());
+  } catch (const Fail &f) {
+    return fail_ctx(c, f);
+  }
+  c->mb.active = true;
+  c->mb.k = k;
+  return COARSE_OK;
+}
+
+int coarse_multi_advance(coarse_ctx *c, int iters) {
+  if (!c || iters < 0) return COARSE_EINVAL;
+  if (!c->mb.active) {
+    c->err = "no block solve in progress on this context";
+    return COARSE_EINVAL;
+  }
+  try {
+    for (int j = 0; j < iters; ++j) c->m_iteration();
+    HIPCHK(hipMemcpyAsync(c->mb.h_ms, c->mb.ms, sizeof(MScal), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipGetLastError());
+  } catch (const Fail &f) {
+    return fail_ctx(c, f);
+  }
+  return COARSE_OK;
+}
+
+int coarse_multi_done(const coarse_ctx *c) {
+  if (!c || !c->mb.active) return COARSE_EINVAL;
+  return c->mb.h_ms->all_done ? 1 : 0;
+}
+
+int coarse_multi_end(coarse_ctx *c, double *u, coarse_stats *st) {
+  if (!c || !u) return COARSE_EINVAL;
+  if (!c->mb.active) {
+    c->err = "no block solve in progress on this context";
+    return COARSE_EINVAL;
+  }
+  c->mb.active = false;
+  try {
+    c->m_finish(u, c->mb.k);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->pcollect();
+  } catch (const Fail &f) {
+    return fail_ctx(c, f);
+  }
+  return multi_stats(c, c->mb.k, st, c->mb.t0);
+}
+
+int coarse_solve_multi(coarse_ctx *c, int k, const double *b, double *u, double tol, coarse_stats *st) {
+  if (!c || !b || !u || b == u || !(tol > 0)) return COARSE_EINVAL;
+  int rc = check_multi(c, k);
+  if (rc) return rc;
+  if (c->mb.active) {
+    c->err = "a block solve is in progress on this context";
+    return COARSE_EINVAL;
+  }
+  const double t0 = now();
+  try {
+    c->m_init();
+    c->m_start(b, k, tol);
+    int batch = std::max(c->check_every, c->mb.last_iters);
+    for (;;) {
+      for (int j = 0; j < batch; ++j) c->m_iteration();
+      batch = c->check_every;
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(c->mb.h_ms, c->mb.ms, sizeof(MScal), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      c->pcollect();
+      if (c->mb.h_ms->all_done) break;
+    }
+    c->m_finish(u, k);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->pcollect();
+  } catch (const Fail &f) {
+    return fail_ctx(c, f);
+  }
+  return multi_stats(c, k, st, t0);
+}
+
 int coarse_apply_precond_multi(coarse_ctx *c, int k, const double *r, double *z) {
   if (!c || !r || !z || r == z) return COARSE_EINVAL;
   int rc = check_multi(c, k);
   if (rc) return rc;
+  if (c->mb.active) {
+    c->err = "a block solve is in progress on this context";
+    return COARSE_EINVAL;
+  }
   try {
     c->m_init();
     c->m_start(r, k, 1.0);

@@ -94,9 +94,10 @@ class Server:
         self.adaptive_steps = adaptive_steps
         # block_min >= 2: when at least that many requests wait for one idle
         # resident mesh, up to coarse.MULTI_MAX of them are solved together by
-        # one block solve (the dense solves on the matrix cores), between lock
-        # steps of the batch
+        # one block solve (the dense solves on the matrix cores), advanced on the
+        # serving stream by the same number of iterations as each lock step
         self.block_min = int(block_min)
+        self.blocks = {}                         # key -> [requests, iterations issued]
 
     def _plan(self, mesh):
         return coarse.Plan.from_mesh(mesh, precision=self.precision, **self.solver_kw)
@@ -151,7 +152,7 @@ class Server:
         records = []
         t0 = time.perf_counter() if t0 is None else t0
         now = lambda: time.perf_counter() - t0
-        while reqs or waiting or live or self.planning or self.ready:
+        while reqs or waiting or live or self.blocks or self.planning or self.ready:
             t = now()
             while reqs and reqs[0].t_arrive <= t:
                 waiting.append(reqs.popleft())
@@ -160,13 +161,14 @@ class Server:
                 if fut.done():
                     del self.planning[key]
                     self.ready[key] = fut.result()
-            # same-mesh requests waiting for an idle resident context: one block solve
+            # same-mesh requests waiting for an idle resident context: one block
+            # solve, stepped on the serving stream beside the lock steps
             if self.block_min >= 2 and waiting:
                 groups = collections.OrderedDict()
                 for rq in waiting:
                     if rq.key in self.cache and rq.key not in self.busy:
                         groups.setdefault(rq.key, []).append(rq)
-                solved = set()
+                started = set()
                 for key, rqs in groups.items():
                     if len(rqs) < self.block_min:
                         continue
@@ -175,17 +177,12 @@ class Server:
                     self.cache.move_to_end(key)
                     with torch.cuda.stream(self.stream):
                         B = torch.tensor(np.stack([rq.b for rq in rqs]), device="cuda")
-                        U, sts = S.solve_multi(B, self.tol)
-                    t_done = now()
-                    for j, rq in enumerate(rqs):
-                        records.append(Record(rid=rq.rid, key=rq.key, t_arrive=rq.t_arrive, t_done=t_done,
-                                              iters=sts[j]["iters"], relres_true=sts[j]["relres_true"],
-                                              setup=rq.rid in missed, status=sts[j]["status"],
-                                              u=U[j] if self.keep_outputs else None))
-                        solved.add(rq.rid)
-                    self.last_iters[key] = max(s["iters"] for s in sts)
-                if solved:
-                    waiting = collections.deque(rq for rq in waiting if rq.rid not in solved)
+                        S.multi_begin(B, self.tol)
+                    self.busy.add(key)
+                    self.blocks[key] = [rqs, 0]
+                    started.update(rq.rid for rq in rqs)
+                if started:
+                    waiting = collections.deque(rq for rq in waiting if rq.rid not in started)
             # admit waiting requests whose context is resident and idle
             keep = collections.deque()
             for rq in waiting:
@@ -221,16 +218,40 @@ class Server:
                 need = self.estimate_bytes(rq.mesh, self.precision)
                 self.planning[rq.key] = self.pool.submit(lambda m=rq.mesh, n=need: (self._plan(m), n))
                 missed.add(rq.rid)
-            if live:
-                # as many iterations per lock step as the live solve expected to
-                # finish first still needs (its mesh's last count), at least
-                # step_iters: fewer host round trips when few solves are live
+            if live or self.blocks:
+                # as many iterations per lock step as the live solve (or block)
+                # expected to finish first still needs (its mesh's last count), at
+                # least step_iters: fewer host round trips when few solves are live
                 k = self.step_iters
                 if self.adaptive_steps:
-                    k = max(k, min(self.last_iters.get(e[0].key, 0) - e[3] for e in live.values()))
+                    rem = [self.last_iters.get(e[0].key, 0) - e[3] for e in live.values()]
+                    rem += [self.last_iters.get(key, 0) - blk[1] for key, blk in self.blocks.items()]
+                    k = max(k, min(rem))
+                for key, blk in self.blocks.items():
+                    with torch.cuda.stream(self.stream):
+                        self.cache[key].multi_advance(k)
+                    blk[1] += k
                 for e in live.values():
                     e[3] += k
-                for tag, st in self.batch.step(k):
+                finished = self.batch.step(k) if live else []
+                if not live:
+                    self.stream.synchronize()
+                for key in list(self.blocks):
+                    S = self.cache[key]
+                    if not S.multi_done():
+                        continue
+                    rqs, _ = self.blocks.pop(key)
+                    with torch.cuda.stream(self.stream):
+                        U, sts = S.multi_end()
+                    t_done = now()
+                    for j, rq in enumerate(rqs):
+                        records.append(Record(rid=rq.rid, key=rq.key, t_arrive=rq.t_arrive, t_done=t_done,
+                                              iters=sts[j]["iters"], relres_true=sts[j]["relres_true"],
+                                              setup=rq.rid in missed, status=sts[j]["status"],
+                                              u=U[j] if self.keep_outputs else None))
+                    self.busy.discard(key)
+                    self.last_iters[key] = max(st["iters"] for st in sts)
+                for tag, st in finished:
                     rq, u, b, _ = live.pop(tag)
                     self.busy.discard(rq.key)
                     self.last_iters[rq.key] = st["iters"]

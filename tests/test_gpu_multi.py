@@ -172,3 +172,33 @@ def test_multi_cube64():
     for j in range(16):
         assert st16[j]["status"] == 0 and st16[j]["relres_true"] <= 1.05e-8
         assert st16[j]["iters"] <= math.ceil(1.1 * st[j]["iters"])
+
+
+def test_multi_stepped_equals_solve_multi():
+    # the stepped form (begin, advance, done after a synchronisation, end) gives the
+    # block solve's results bit for bit; misuse is refused
+    m = mg.box_mesh((10, 9, 7), 21, block=4, boxes=(3, 3, 2), faces=("y1",))
+    for precision in ("fp64", "mixed16"):
+        S = coarse.CoarseSolver.from_mesh(m, precision=precision)
+        B = _gpu(_rhs(m, 5, 70))
+        U0, st0 = S.solve_multi(B, tol=1e-8)
+        with pytest.raises(coarse.CoarseError):
+            S.multi_advance(2)
+        S.multi_begin(B, tol=1e-8)
+        with pytest.raises(coarse.CoarseError):
+            S.multi_begin(B, tol=1e-8)
+        with pytest.raises(coarse.CoarseError):
+            S.solve_multi(B, tol=1e-8)
+        steps = 0
+        while True:
+            S.multi_advance(3)
+            torch.cuda.synchronize()
+            steps += 1
+            if S.multi_done():
+                break
+            assert steps < 1000
+        U1, st1 = S.multi_end()
+        assert torch.equal(U0, U1)
+        assert [s["iters"] for s in st0] == [s["iters"] for s in st1]
+        assert all(s["status"] == 0 for s in st1)
+        S.close()
