@@ -189,6 +189,7 @@ struct coarse_ctx {
     int32_t lds = 0;
     bool active = false;   // a block solve begun by coarse_multi_begin and not yet ended
     int k = 0;
+    const double *b = nullptr;   // its right-hand sides
     double t0 = 0.0;
   } mb;
 
@@ -1615,6 +1616,7 @@ int coarse_multi_begin(coarse_ctx *c, int k, const double *b, double tol) {
   }
   c->mb.active = true;
   c->mb.k = k;
+  c->mb.b = b;
   return COARSE_OK;
 }
 
@@ -1643,6 +1645,10 @@ int coarse_multi_end(coarse_ctx *c, double *u, coarse_stats *st) {
   if (!c || !u) return COARSE_EINVAL;
   if (!c->mb.active) {
     c->err = "no block solve in progress on this context";
+    return COARSE_EINVAL;
+  }
+  if (u == c->mb.b) {
+    c->err = "the solutions may not overwrite the right-hand sides";
     return COARSE_EINVAL;
   }
   c->mb.active = false;
