@@ -518,8 +518,17 @@ __global__ __launch_bounds__(256) void k_m_corners(int64_t nr, const int32_t *__
   const int64_t K = g / MC;
   const int c = (int)(g % MC);
   if (K >= nr) return;
+  // the list in order, eight loads issued together
   double acc = 0.0;
-  for (int k = ptr[K]; k < ptr[K + 1]; ++k) acc += tpart[(int64_t)src[k] * MC + c];
+  const int k1 = ptr[K + 1];
+  for (int kb = ptr[K]; kb < k1; kb += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = (kb + u < k1) ? tpart[(int64_t)src[kb + u] * MC + c] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (kb + u < k1) acc += v[u];
+  }
   rr[K * MC + c] = acc;
 }
 
