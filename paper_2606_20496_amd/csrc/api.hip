@@ -424,8 +424,12 @@ struct coarse_ctx {
 
   void op_update() {
     pbeg(0);
-    hipLaunchKernelGGL(k_op_fused, dim3((unsigned)op.n_blocks), dim3(OP_BLOCK), op.lds_bytes, stream, op,
-                       (const double *)z, p, pb, q, energy, sc, (const double *)part1, (const double *)part2, nvblk);
+    if (op.ae_nt)
+      hipLaunchKernelGGL((k_op_fused<true>), dim3((unsigned)op.n_blocks), dim3(OP_BLOCK), op.lds_bytes, stream, op,
+                         (const double *)z, p, pb, q, energy, sc, (const double *)part1, (const double *)part2, nvblk);
+    else
+      hipLaunchKernelGGL((k_op_fused<false>), dim3((unsigned)op.n_blocks), dim3(OP_BLOCK), op.lds_bytes, stream, op,
+                         (const double *)z, p, pb, q, energy, sc, (const double *)part1, (const double *)part2, nvblk);
     pend(0);
     pbeg(6);
     hipLaunchKernelGGL(k_update_fused, dim3(nvblk), dim3(VW), 0, stream, nf, op, sc, x, r, (const double *)p,
@@ -813,6 +817,8 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
   op.slot_pw = A.upload(P.slot_pw, s);
   op.vq = (const int2 *)A.upload(P.vq, s);
   op.lds_bytes = (int32_t)((OP_BLOCK * 8 + P.max_slots) * sizeof(double));
+  // 256 MB: the MI355X last-level (Infinity) cache
+  op.ae_nt = (P.n_elem * 28 * (int64_t)sizeof(double) > (int64_t)(256ull << 20)) ? 1 : 0;
   if (op.lds_bytes > 64 * 1024) throw Fail(COARSE_EINVAL, "operator block touches too many vertices");
 
   // vectors

@@ -83,6 +83,8 @@ struct OpDev {
   const uint8_t *blk_inc;     // per block, 1: sum through the incidence lists (see block_accumulate)
   const int2 *vq;             // free vertex -> (first partial, count); count 0: owned by one block
   int32_t lds_bytes;
+  int32_t ae_nt;              // 1: the element matrices outgrow the last-level cache; stream them
+                              // with non-temporal loads
 };
 
 // The per-iteration state of one solve, for launches that cover every solve of

@@ -99,10 +99,14 @@ __global__ __launch_bounds__(256) void k_elem_matrices(int64_t E, int64_t NV, co
 // An element's 8 block-local slots (one 16-byte record) and its 36 unique matrix
 // entries do not depend on the vector: their loads are issued first and stay in
 // flight while the block stages its vertex values.
+// The element matrices are read once per application; when they are larger than
+// the last-level cache (OpDev.ae_nt), the PCG operator reads them with
+// non-temporal loads (NT = true), which keep them from evicting the vectors.
+template <bool NT = false>
 __device__ __forceinline__ void elem_load(const OpDev &op, int64_t e, double m[28], uint4 &c) {
   c = *(const uint4 *)(op.lconn + e * 8);
 #pragma unroll
-  for (int k = 0; k < 28; ++k) m[k] = op.Ae[ae28_at(k, e)];
+  for (int k = 0; k < 28; ++k) m[k] = NT ? __builtin_nontemporal_load(op.Ae + ae28_at(k, e)) : op.Ae[ae28_at(k, e)];
 }
 
 __device__ __forceinline__ unsigned slot_at(const uint4 &c, int a) {
@@ -376,6 +380,7 @@ __global__ __launch_bounds__(VB) void k_start(int64_t nf, const int32_t *__restr
 // workgroup index (blk) and, where they loop over the grid, the grid size (nblk)
 // explicitly, so that a launch covering several solves (a lock-step batch) runs
 // each workgroup exactly as the solo launch of its own solve would.
+template <bool NT = false>
 __device__ __forceinline__ void op_fused_body(OpDev op, const double *__restrict__ z, double *__restrict__ pa,
                                               double *__restrict__ pb, double *__restrict__ q,
                                               double *__restrict__ energy, Scalars *__restrict__ sc,
@@ -385,7 +390,7 @@ __device__ __forceinline__ void op_fused_body(OpDev op, const double *__restrict
   const int64_t e = (int64_t)blk * OP_BLOCK + threadIdx.x;
   double m[28];
   uint4 c = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
-  if (e < op.E) elem_load(op, e, m, c);
+  if (e < op.E) elem_load<NT>(op, e, m, c);
   const int it = sc->iter;
   const double rho = block_total<OP_BLOCK>(rz1, nrz, red);
   double beta = 0.0;
@@ -437,6 +442,7 @@ __device__ __forceinline__ void op_fused_body(OpDev op, const double *__restrict
   if (threadIdx.x == 0) energy[blk] = tot;
 }
 
+template <bool NT>
 __global__ __launch_bounds__(OP_BLOCK) void k_op_fused(OpDev op, const double *__restrict__ z, double *__restrict__ pa,
                                                        double *__restrict__ pb, double *__restrict__ q,
                                                        double *__restrict__ energy, Scalars *__restrict__ sc,
@@ -444,7 +450,7 @@ __global__ __launch_bounds__(OP_BLOCK) void k_op_fused(OpDev op, const double *_
                                                        int nrz) {
   extern __shared__ double lds[];
   __shared__ double red[OP_BLOCK / WAVE];
-  op_fused_body(op, z, pa, pb, q, energy, sc, rz1, rz2, nrz, blockIdx.x, lds, red);
+  op_fused_body<NT>(op, z, pa, pb, q, energy, sc, rz1, rz2, nrz, blockIdx.x, lds, red);
 }
 
 // alpha = rho / p.Ap (from the operator's partials), x += alpha p,
