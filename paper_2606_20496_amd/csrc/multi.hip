@@ -271,7 +271,7 @@ __global__ __launch_bounds__(OP_BLOCK) void k_m_op(OpDev op, const double *__res
                                                    double *__restrict__ partials, double *__restrict__ energy,
                                                    const MScal *__restrict__ ms, int fused) {
   extern __shared__ double lds[];
-  __shared__ double red[OP_BLOCK / WAVE];
+  __shared__ double red[OP_BLOCK / WAVE * MCW];
   if (fused && ms->all_done) return;
   double *out = lds;                  // [OP_BLOCK * 8], one column at a time
   double *lp = lds + OP_BLOCK * 8;    // [slots][MCW]
@@ -393,11 +393,22 @@ __global__ __launch_bounds__(OP_BLOCK) void k_m_op(OpDev op, const double *__res
       __syncthreads();
     }
     if (fused) {
+      // the MCW column sums of p.Ap over the workgroup together: each wave's sums,
+      // then the waves in order (one barrier pair for all columns)
+      const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
 #pragma unroll
       for (int cc = 0; cc < MCW; ++cc) {
-        const double tot = block_sum<OP_BLOCK>(en[cc], red);
-        if (threadIdx.x == 0) energy[blk * MC + c0 + cc] = tot;
+        const double t = wave_sum(en[cc]);
+        if (l == 0) red[w * MCW + cc] = t;
       }
+      __syncthreads();
+      if (threadIdx.x < MCW) {
+        double tot = 0.0;
+#pragma unroll
+        for (int q = 0; q < OP_BLOCK / WAVE; ++q) tot += red[q * MCW + threadIdx.x];
+        energy[blk * MC + c0 + threadIdx.x] = tot;
+      }
+      __syncthreads();
     }
   }
 }
