@@ -165,8 +165,17 @@ __global__ __launch_bounds__(256) void k_m_scal(MScal *__restrict__ ms, const do
   __shared__ int live[MC];
   if (step != MS_BB && step != MS_RES && ms->all_done) return;
   const int c = threadIdx.x % MC, g = threadIdx.x / MC;
+  constexpr int GS = 256 / MC;   // partial rows per step of one thread group
+  // rows g, g + GS, ... in order, eight loads issued together
   double acc = 0.0;
-  for (int i = g; i < n; i += 256 / MC) acc += part[i * MC + c];
+  for (int i0 = g; i0 < n; i0 += 8 * GS) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = (i0 + u * GS < n) ? part[(int64_t)(i0 + u * GS) * MC + c] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (i0 + u * GS < n) acc += v[u];
+  }
   const double tot = block_colsum<256>(acc, red);
   const int it = ms->iter;
   if (threadIdx.x < MC) {
