@@ -496,10 +496,18 @@ __global__ __launch_bounds__(256) void k_m_pre(int ng, int64_t n_pack, const int
                                                const MScal *__restrict__ ms) {
   if (ms->all_done) return;
   if ((int)blockIdx.x < ng) {
+    // four entries per thread and step, their index and value loads issued together
     const int64_t n = n_pack * MC, G = (int64_t)ng * 256;
-    for (int64_t g = blockIdx.x * (int64_t)256 + threadIdx.x; g < n; g += G) {
-      const int32_t i = idx[g / MC];
-      RP[g] = (i >= 0) ? R[(int64_t)i * MC + g % MC] : 0.0;
+    for (int64_t g0 = blockIdx.x * (int64_t)256 + threadIdx.x; g0 < n; g0 += 4 * G) {
+      int32_t ii[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) ii[u] = (g0 + u * G < n) ? idx[(g0 + u * G) / MC] : -1;
+      double vv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) vv[u] = (ii[u] >= 0) ? R[(int64_t)ii[u] * MC + (g0 + u * G) % MC] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (g0 + u * G < n) RP[g0 + u * G] = vv[u];
     }
     return;
   }
