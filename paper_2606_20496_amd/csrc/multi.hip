@@ -283,7 +283,8 @@ __global__ __launch_bounds__(OP_BLOCK) void k_m_op(OpDev op, const double *__res
   __shared__ double red[OP_BLOCK / WAVE * MCW];
   if (fused && ms->all_done) return;
   double *out = lds;                  // [OP_BLOCK * 8], one column at a time
-  double *lp = lds + OP_BLOCK * 8;    // [slots][MCW]
+  double *lp = lds + OP_BLOCK * 8;    // [MCW][slots]: one column's slots contiguous (a slot-major
+                                      // layout put lanes of one column 32 bytes apart: 8-way bank conflicts)
   const int blk = blockIdx.x;
   const int64_t e = (int64_t)blk * OP_BLOCK + threadIdx.x;
   const bool valid = e < op.E;
@@ -318,7 +319,7 @@ __global__ __launch_bounds__(OP_BLOCK) void k_m_op(OpDev op, const double *__res
         }
       }
 #pragma unroll
-      for (int cc = 0; cc < MCW; ++cc) lp[s * MCW + cc] = pv[cc];
+      for (int cc = 0; cc < MCW; ++cc) lp[cc * ns + s] = pv[cc];
     }
     __syncthreads();
     double y[MCW][8], en[MCW];
@@ -335,7 +336,7 @@ __global__ __launch_bounds__(OP_BLOCK) void k_m_op(OpDev op, const double *__res
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
           const unsigned sl = slot_at(cn, a);
-          pe[a] = (sl == 0xFFFFu) ? 0.0 : lp[sl * MCW + cc];
+          pe[a] = (sl == 0xFFFFu) ? 0.0 : lp[cc * ns + sl];
         }
 #pragma unroll
         for (int a = 0; a < 8; ++a)
@@ -388,7 +389,7 @@ __global__ __launch_bounds__(OP_BLOCK) void k_m_op(OpDev op, const double *__res
           const unsigned sl = slot_at(cn, a);
           if (sl != 0xFFFFu) {
 #pragma unroll
-            for (int cc = 0; cc < MCW; ++cc) lp[sl * MCW + cc] += y[cc][a];
+            for (int cc = 0; cc < MCW; ++cc) lp[cc * ns + sl] += y[cc][a];
           }
         }
         __syncthreads();
@@ -396,8 +397,8 @@ __global__ __launch_bounds__(OP_BLOCK) void k_m_op(OpDev op, const double *__res
       for (int s = threadIdx.x; s < ns; s += OP_BLOCK) {
         const int dst = op.slot_dst[s0 + s];
         double *d = (dst >= 0) ? q + (int64_t)dst * MC + c0 : partials + (int64_t)(-dst - 1) * MC + c0;
-        *(double2 *)d = make_double2(lp[s * MCW], lp[s * MCW + 1]);
-        *(double2 *)(d + 2) = make_double2(lp[s * MCW + 2], lp[s * MCW + 3]);
+        *(double2 *)d = make_double2(lp[s], lp[ns + s]);
+        *(double2 *)(d + 2) = make_double2(lp[2 * ns + s], lp[3 * ns + s]);
       }
       __syncthreads();
     }
