@@ -251,7 +251,7 @@ int coarse_solve_projected(coarse_ctx *ctx, const double *b, double *u, double t
 int coarse_projection_reset(coarse_ctx *ctx);
 
 /* Block solve: k right-hand sides on the context's mesh (1 <= k <=
- * COARSE_MULTI_MAX), k independent PCG recurrences (Sec. 2, the same iteration
+ * COARSE_MULTI_MAX), k independent PCG recurrences (Sec. 1, the same iteration
  * as coarse_solve for each column, to the same tolerance) advanced together so
  * that every read of the element matrices and of the stored dense inverses
  * serves all of them: the dense solves of the additive preconditioner (Sec. 3,

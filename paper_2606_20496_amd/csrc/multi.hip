@@ -1,5 +1,5 @@
 // Kernels of the block solve: up to MC right-hand sides on one mesh, solved by
-// MC independent PCG recurrences (Sec. 2, one per column) that share every read
+// MC independent PCG recurrences (Sec. 1, one per column) that share every read
 // of the operator's element matrices and of the stored dense inverses. Vectors
 // are vertex-major, MC doubles per vertex (one 128-byte line), so every gather
 // through an index list reads whole lines. The dense solves A_s^{-1} [r_1 .. r_MC]
