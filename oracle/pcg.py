@@ -17,7 +17,7 @@ def pcg(matvec, precond, b, tol=1e-8, max_it=1000, flexible=False, record=False)
     b = np.asarray(b, dtype=np.float64)
     x = np.zeros_like(b)
     bnorm = float(np.sqrt(b @ b))
-    info = {"iters": 0, "relres": 0.0, "alphas": [], "betas": [], "converged": True}
+    info = {"iters": 0, "relres": 0.0, "alphas": [], "betas": [], "relres_hist": [], "converged": True}
     if bnorm == 0.0:
         return x, info
     r = b.copy()
@@ -38,6 +38,7 @@ def pcg(matvec, precond, b, tol=1e-8, max_it=1000, flexible=False, record=False)
         relres = float(np.sqrt(r @ r)) / bnorm
         if record:
             info["alphas"].append(alpha)
+            info["relres_hist"].append(relres)
         if relres <= tol:
             break
         znew = precond(r)

@@ -16,7 +16,9 @@ class Problem:
     """Sec. 3-4 assembled once per mesh.
 
     interp: "centroid" (cell-assembled A_r, default) or "standard" (Galerkin).
-    mode:   "additive" (eq. (asm)), "hybrid_sym", "local_only", "coarse_only".
+    mode:   "additive" (eq. (asm)), "hybrid" (eqs. (asm1)-(asm2) as written; not
+            symmetric, so solve with ``flexible=True``), "hybrid_sym",
+            "local_only", "coarse_only".
     """
 
     def __init__(self, xyz, e2v, dirichlet, part, n_part, boxes, overlap=1,
@@ -41,6 +43,7 @@ class Problem:
         self.mode = mode
         self.M = {
             "additive": lambda: precond.Additive(self.local, self.coarse),
+            "hybrid": lambda: precond.HybridPaper(self.A, self.local, self.coarse),
             "hybrid_sym": lambda: precond.HybridSymmetric(self.A, self.local, self.coarse),
             "local_only": lambda: precond.LocalOnly(self.local),
             "coarse_only": lambda: precond.CoarseOnly(self.coarse),
