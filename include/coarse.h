@@ -25,7 +25,10 @@
  *     and output must not alias.
  *   - All device work is ordered on the context's stream (coarse_opts.stream, or
  *     coarse_set_stream). A context must not be used from two streams or threads
- *     at once. No call after coarse_setup allocates device memory.
+ *     at once. No call after coarse_setup allocates device memory, except
+ *     the first block solve of a context set up without opts.block_rhs (see
+ *     coarse_solve_multi) and the lock-step batch calls, which hold their own
+ *     tables.
  */
 #ifndef COARSE_H
 #define COARSE_H
@@ -68,7 +71,11 @@ enum coarse_mode {
                               z0 = M_r r, z1 = z0 + M_loc (r - A z0),
                               z = z1 + M_r (r - A z1)                              */
   COARSE_LOCAL_ONLY = 2,   /* eq. (asm1) alone (ablation)                          */
-  COARSE_REDUCED_ONLY = 3  /* J A_r^{-1} J^T alone (ablation)                      */
+  COARSE_REDUCED_ONLY = 3, /* J A_r^{-1} J^T alone (ablation)                      */
+  COARSE_HYBRID = 4        /* eqs. (asm1)-(asm2) as written: z_loc = M_loc r,
+                              z = z_loc + M_r (r - A z_loc). Not symmetric: the
+                              default beta of a context in this mode is the
+                              flexible one (opts.flexible is forced to 1)          */
 };
 
 enum coarse_interp {
@@ -107,9 +114,10 @@ typedef struct {
 /* right-hand sides of one block solve (coarse_solve_multi) */
 #define COARSE_MULTI_MAX 16
 
-/* Size buckets of the work-item table (upper bounds on nb; the last is open). */
+/* Size buckets of the work-item table: bucket b holds the systems whose tile
+ * count nb = ceil(n/32) is at most 2, 4, 8, 12, 16, 24, 48 for b = 0..6; bucket 7
+ * holds all larger ones. */
 #define COARSE_GEMV_BUCKETS 8
-static const int coarse_gemv_bucket_max[COARSE_GEMV_BUCKETS] = {2, 4, 8, 12, 16, 24, 48, 1 << 30};
 
 typedef struct {
   int overlap;      /* element layers added to each subdomain (Sec. 3), >= 1        */
@@ -127,8 +135,8 @@ typedef struct {
   void *stream;     /* hipStream_t; NULL = the null stream                         */
   int gemv_tiles[COARSE_GEMV_BUCKETS];
                     /* tiles per work item of the batched dense solve, per size
-                       bucket of a system's tile count nb = ceil(n/32): bucket b
-                       holds nb <= coarse_gemv_bucket_max[b]. 0 = 4. Used for the
+                       bucket of a system's tile count nb = ceil(n/32) (see
+                       COARSE_GEMV_BUCKETS). 0 = 4. Used for the
                        systems cut into work items: those outside 16..48 tile
                        rows, all systems of a context with fewer systems than the
                        device has compute units, and the smallest ones past a
@@ -140,6 +148,10 @@ typedef struct {
                        (Sec. 5); 0 = none. The basis takes 2 l n_free doubles of
                        device memory, allocated by the setup; l <=
                        COARSE_PROJECTION_MAX                                       */
+  int block_rhs;    /* 1: the setup also allocates the vectors of the block solve
+                       (coarse_solve_multi, about 9 * 16 doubles per free vertex),
+                       so that no later call on the context allocates; 0 (default):
+                       the first block-solve call allocates them                   */
 } coarse_opts;
 
 typedef struct {
@@ -226,7 +238,14 @@ int coarse_apply_precond(coarse_ctx *ctx, const double *r, double *z);
 /* q = A p, the Q1 operator of Sec. 3 (free rows/columns). Device float64 [n_vert]. */
 int coarse_apply_A(coarse_ctx *ctx, const double *p, double *q);
 
-/* Solve A u = b by PCG from u0 = 0 until ||r||_2 <= tol ||b||_2 (free entries).
+/* Solve the coarse system A u = b of Sec. 3 (the element-vertex problem that the
+ * paper's Sec. 1 embeds in a Krylov method) by preconditioned conjugate
+ * gradients from u0 = 0 with the preconditioner of opts.mode, until
+ * ||r||_2 <= tol ||b||_2 over the free entries (recurrence residual). Each
+ * iteration: q = A p, alpha = (r,z)/(p,q), x += alpha p, r -= alpha q, the
+ * convergence test, z = M^{-1} r, beta (Fletcher-Reeves, or Polak-Ribiere with
+ * opts.flexible), p = z + beta p; iterations count the products with A. The
+ * true residual ||b - A u|| is recomputed at the end (stats.relres_true).
  * b, u: device float64 [n_vert]. st may be NULL. Returns COARSE_OK, COARSE_NOTCONV
  * (warning) or COARSE_EBREAKDOWN / COARSE_EINVAL. b = 0 gives u = 0, iters = 0. */
 int coarse_solve(coarse_ctx *ctx, const double *b, double *u, double tol, coarse_stats *st);

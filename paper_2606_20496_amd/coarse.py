@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libcoarse.so")
 PRECISION = {"fp64": 0, "mixed": 1, "mixed16": 2}
 PROJECTION_MAX = 64   # COARSE_PROJECTION_MAX: largest basis of prior solutions
 MULTI_MAX = 16        # COARSE_MULTI_MAX: right-hand sides of one block solve
-MODE = {"additive": 0, "hybrid_sym": 1, "local_only": 2, "reduced_only": 3}
+MODE = {"additive": 0, "hybrid_sym": 1, "local_only": 2, "reduced_only": 3, "hybrid": 4}
 INTERP = {"centroid": 0, "standard": 1}
 STATUS = {0: "ok", 1: "notconv", -1: "einval", -2: "enomem", -3: "emesh", -4: "esingular",
           -5: "edevice", -6: "ebreakdown"}
@@ -80,7 +80,8 @@ class _Opts(ctypes.Structure):
     _fields_ = [("overlap", ctypes.c_int), ("boxes", ctypes.c_int * 3), ("precision", ctypes.c_int),
                 ("mode", ctypes.c_int), ("interp", ctypes.c_int), ("max_it", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("flexible", ctypes.c_int), ("stream", ctypes.c_void_p),
-                ("gemv_tiles", ctypes.c_int * GEMV_BUCKETS), ("projection", ctypes.c_int)]
+                ("gemv_tiles", ctypes.c_int * GEMV_BUCKETS), ("projection", ctypes.c_int),
+                ("block_rhs", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -199,7 +200,7 @@ def _arrays(xyz, e2v, dirichlet, part, n_part):
 
 
 def _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible, stream, gemv_tiles=None,
-          projection=0):
+          projection=0, block_rhs=0):
     o = _Opts()
     load().coarse_default_opts(ctypes.byref(o))
     o.overlap = int(overlap)
@@ -211,7 +212,7 @@ def _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible
     o.max_it = int(max_it)
     o.check_every = int(check_every)
     if flexible is None:
-        flexible = precision in ("mixed", "mixed16")
+        flexible = precision in ("mixed", "mixed16") or mode == "hybrid"
     o.flexible = int(bool(flexible))
     o.stream = stream
     t = gemv_table(precision) if gemv_tiles is None else list(gemv_tiles)
@@ -220,6 +221,7 @@ def _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible
     for b in range(GEMV_BUCKETS):
         o.gemv_tiles[b] = int(t[b])
     o.projection = int(projection)
+    o.block_rhs = int(bool(block_rhs))
     return o
 
 
@@ -257,14 +259,14 @@ class Plan:
 
     def __init__(self, xyz, e2v, dirichlet, part=None, n_part=1, *, overlap=1, boxes=None,
                  precision="fp64", mode="additive", interp="centroid", max_it=1000, check_every=4,
-                 flexible=None, gemv_tiles=None, projection=0):
+                 flexible=None, gemv_tiles=None, projection=0, block_rhs=0):
         L = load()
         self._L = L
         self.n_vert = int(np.asarray(xyz).shape[0])
         self.precision = precision
         m, bc, keep = _arrays(xyz, e2v, dirichlet, part, n_part)
         o = _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible, None, gemv_tiles,
-                  projection)
+                  projection, block_rhs)
         pl = ctypes.c_void_p()
         rc = L.coarse_plan_create(ctypes.byref(m), ctypes.byref(bc), ctypes.byref(o), ctypes.byref(pl))
         if rc != 0:
@@ -304,7 +306,7 @@ class CoarseSolver:
 
     def __init__(self, xyz, e2v, dirichlet, part=None, n_part=1, *, overlap=1, boxes=None,
                  precision="fp64", mode="additive", interp="centroid", max_it=1000, check_every=4,
-                 flexible=None, gemv_tiles=None, projection=0):
+                 flexible=None, gemv_tiles=None, projection=0, block_rhs=0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("CoarseSolver needs a GPU; no CPU fallback exists")
@@ -314,7 +316,7 @@ class CoarseSolver:
         self.precision = precision
         m, bc, keep = _arrays(xyz, e2v, dirichlet, part, n_part)
         o = _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible, _stream(), gemv_tiles,
-                  projection)
+                  projection, block_rhs)
         ctx = ctypes.c_void_p()
         rc = L.coarse_setup(ctypes.byref(m), ctypes.byref(bc), ctypes.byref(o), ctypes.byref(ctx))
         if rc != 0:

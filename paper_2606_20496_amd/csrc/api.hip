@@ -2,6 +2,7 @@
 // PCG, orchestrating the kernels of kernels.hip on one HIP stream.
 #include "kernels.hip"
 #include "multi.hip"
+#include "capture_guard.h"
 
 #include <algorithm>
 #include <chrono>
@@ -21,6 +22,10 @@ using namespace coarse;
 namespace {
 
 thread_local std::string g_setup_error;   // setups may run on several host threads
+
+// graph captures of lock-step batches against setups, destructions and block-
+// solve allocations made by any host thread
+CaptureGuard g_guard;
 
 struct Fail : std::runtime_error {
   int code;
@@ -68,6 +73,9 @@ struct Arena {
   }
   ~Arena() { release(); }
 };
+
+// upper bounds on a system's tile count per work-item bucket (the last is open)
+const int kGemvBucketMax[COARSE_GEMV_BUCKETS] = {2, 4, 8, 12, 16, 24, 48, 1 << 30};
 
 inline unsigned nblk(int64_t n, int b) { return (unsigned)std::max<int64_t>(1, (n + b - 1) / b); }
 
@@ -180,7 +188,7 @@ struct coarse_ctx {
     bool ready = false;
     double *X = nullptr, *R = nullptr, *Pa = nullptr, *Pb = nullptr, *Z = nullptr, *Q = nullptr, *B = nullptr;
     double *RP = nullptr, *ZP = nullptr, *tpart = nullptr, *yfull = nullptr, *partials = nullptr;
-    double *part = nullptr, *energy = nullptr;
+    double *part = nullptr, *part2 = nullptr, *energy = nullptr;
     MScal *ms = nullptr;
     MScal *h_ms = nullptr;   // pinned host copy
     int2 *rows = nullptr;
@@ -402,6 +410,13 @@ struct coarse_ctx {
         hipLaunchKernelGGL(k_sub, dim3(nvblk), dim3(VB), 0, stream, nf, done, in, q, t2);
         precond_parts<T>(t2, t1, false, true, out, rdot, p1, p2, done, scal, start, nullptr);
         break;
+      case COARSE_HYBRID:
+        // eqs. (asm1)-(asm2): z_loc = M_loc r; z = z_loc + M_r (r - A z_loc)
+        precond_parts<T>(in, nullptr, true, false, t1, nullptr, nullptr, nullptr, done, false, start, chk);
+        apply_op(t1, q, nullptr, done);
+        hipLaunchKernelGGL(k_sub, dim3(nvblk), dim3(VB), 0, stream, nf, done, in, q, t2);
+        precond_parts<T>(t2, t1, false, true, out, rdot, p1, p2, done, scal, start, nullptr);
+        break;
     }
   }
 
@@ -528,6 +543,7 @@ struct coarse_ctx {
   // ---- block solve (up to MC right-hand sides; FP64, additive) ---------------
   void m_init() {
     if (mb.ready) return;
+    DeviceCallScope dc(g_guard);
     hipStream_t s = stream;
     Arena &A = arena;
     const int64_t nfm = nf * MC;
@@ -547,6 +563,7 @@ struct coarse_ctx {
     mb.ng = (int)std::min<int64_t>(1024, nblk(coarse_vec_off * MC, 256));
     mb.nt = (int)std::min<int64_t>(2048, nblk(ntask, 4));
     mb.part = A.alloc<double>((size_t)mb.nvb * MC);
+    mb.part2 = A.alloc<double>((size_t)mb.nvb * MC);
     mb.energy = A.alloc<double>(std::max<int64_t>(1, op.n_blocks) * MC);
     mb.ms = A.alloc<MScal>(1);
     // packing pads and inactive box vertices are never written and stay 0
@@ -570,7 +587,9 @@ struct coarse_ctx {
   }
 
   void m_scal(const double *part, int n, int step) {
-    hipLaunchKernelGGL(k_m_scal, dim3(1), dim3(256), 0, stream, mb.ms, part, n, step);
+    // a flexible context takes the Polak-Ribiere beta: (r_{k+1}, z_k) from k_m_final
+    const double *p2 = (step == MS_RZ && flexible) ? mb.part2 : nullptr;
+    hipLaunchKernelGGL(k_m_scal, dim3(1), dim3(256), 0, stream, mb.ms, part, n, step, p2);
   }
 
   // Z = M R for every column (additive two-level preconditioner); T: the type
@@ -614,7 +633,8 @@ struct coarse_ctx {
     hipLaunchKernelGGL(k_m_final<T>, dim3(mb.nvb), dim3(256), 0, stream, nf, (const int32_t *)cover_ptr,
                        (const int32_t *)cover_pos, (const double *)mb.ZP, (const int32_t *)jv_ptr,
                        (const int32_t *)jv_base, (const T *)jv_w, (const T *)jv_xi, nent, bx1, bxy1,
-                       (const double *)mb.yfull, mb.Z, (const double *)mb.R, mb.part, (const MScal *)mb.ms);
+                       (const double *)mb.yfull, mb.Z, (const double *)mb.R, mb.part, flexible ? mb.part2 : nullptr,
+                       (const MScal *)mb.ms);
     pend(5);
   }
 
@@ -869,7 +889,7 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
   int dev = 0, n_cu = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-  build_gemv_items(P, gemv_tiles, coarse_gemv_bucket_max, COARSE_GEMV_BUCKETS, n_cu, G);
+  build_gemv_items(P, gemv_tiles, kGemvBucketMax, COARSE_GEMV_BUCKETS, n_cu, G);
   // transposed partials only for the systems cut into work items
   std::vector<int64_t> colpart_off(P.sys.size(), -1);
   int64_t ncolpart = 0;
@@ -1163,7 +1183,6 @@ struct coarse_batch {
   int grid[NG] = {};
   int op_lds = 0;
   hipGraphExec_t gexec = nullptr;
-
   void init(hipStream_t s, bool graph) {
     main = s;
     use_graph = graph && s != nullptr;   // the null stream cannot be captured
@@ -1224,6 +1243,7 @@ struct coarse_batch {
   void rebuild_tables() {
     const int n = (int)live.size();
     if (n > cap) {
+      DeviceCallScope dc(g_guard);
       HIPCHK(hipStreamSynchronize(main));
       free_tables();
       cap = std::max(2 * n, 16);
@@ -1297,15 +1317,30 @@ struct coarse_batch {
     *n_done = 0;
     if (live.empty()) return COARSE_OK;
     if (dirty) rebuild_tables();
-    if (use_graph) {
-      if (!gexec) {
-        hipGraph_t graph;
-        HIPCHK(hipStreamBeginCapture(main, hipStreamCaptureModeRelaxed));
-        lock_step();
-        HIPCHK(hipStreamEndCapture(main, &graph));
-        HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
-        HIPCHK(hipGraphDestroy(graph));
+    // a graph is captured only while no setup, destruction or allocation runs
+    // on another thread; otherwise this step's launches go out directly (the
+    // same kernels and arguments, so the same results)
+    if (use_graph && !gexec && g_guard.try_begin_capture()) {
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamBeginCapture(main, hipStreamCaptureModeRelaxed);
+      if (e == hipSuccess) {
+        try {
+          lock_step();
+        } catch (...) {
+          (void)hipStreamEndCapture(main, &graph);
+          if (graph) (void)hipGraphDestroy(graph);
+          g_guard.end_capture();
+          throw;
+        }
+        e = hipStreamEndCapture(main, &graph);
       }
+      g_guard.end_capture();
+      HIPCHK(e);
+      e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      HIPCHK(e);
+    }
+    if (use_graph && gexec) {
       for (int i = 0; i < iters; ++i) HIPCHK(hipGraphLaunch(gexec, main));
     } else {
       for (int i = 0; i < iters; ++i) lock_step();
@@ -1451,7 +1486,7 @@ int coarse_plan_create(const coarse_mesh *mesh, const coarse_bc *bc, const coars
     g_setup_error = "unknown precision";
     return COARSE_EINVAL;
   }
-  if (o.mode < 0 || o.mode > 3 || o.max_it < 1 || o.check_every < 1) {
+  if (o.mode < 0 || o.mode > COARSE_HYBRID || o.max_it < 1 || o.check_every < 1) {
     g_setup_error = "bad mode, max_it or check_every";
     return COARSE_EINVAL;
   }
@@ -1507,6 +1542,7 @@ int coarse_setup_from_plan(const coarse_plan *plan, void *stream, coarse_ctx **o
   const coarse_opts &o = plan->o;
   const Plan &P = plan->P;
   const double t0 = now() - plan->t_plan;
+  DeviceCallScope dc(g_guard);
   std::unique_ptr<coarse_ctx> c(new coarse_ctx());
   c->stream = (hipStream_t)stream;
   c->precision = o.precision;
@@ -1514,7 +1550,8 @@ int coarse_setup_from_plan(const coarse_plan *plan, void *stream, coarse_ctx **o
   c->interp = o.interp;
   c->max_it = o.max_it;
   c->check_every = o.check_every;
-  c->flexible = o.flexible ? 1 : 0;
+  // the hybrid of eqs. (asm1)-(asm2) is not symmetric: always the flexible beta
+  c->flexible = (o.flexible || o.mode == COARSE_HYBRID) ? 1 : 0;
   c->proj_max = o.projection;
   try {
     HIPCHK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
@@ -1534,6 +1571,16 @@ int coarse_setup_from_plan(const coarse_plan *plan, void *stream, coarse_ctx **o
   } catch (const std::bad_alloc &) {
     g_setup_error = "host allocation failed";
     return COARSE_ENOMEM;
+  }
+  // the block solve's vectors, when asked for and the context can run it
+  if (o.block_rhs && check_multi(c.get(), 1) == COARSE_OK) {
+    try {
+      c->m_init();
+      HIPCHK(hipStreamSynchronize(c->stream));
+    } catch (const Fail &f) {
+      g_setup_error = f.what();
+      return f.code;
+    }
   }
   c->t_setup = now() - t0;
   c->info.device_bytes = (int64_t)c->arena.bytes;
@@ -1808,12 +1855,14 @@ int coarse_batch_live(const coarse_batch *bt) { return bt ? (int)bt->live.size()
 
 int coarse_batch_destroy(coarse_batch *bt) {
   if (!bt) return COARSE_OK;
+  DeviceCallScope dc(g_guard);
   delete bt;
   return COARSE_OK;
 }
 
 int coarse_destroy(coarse_ctx *c) {
   if (!c) return COARSE_OK;
+  DeviceCallScope dc(g_guard);
   (void)hipStreamSynchronize(c->stream);
   delete c;
   return COARSE_OK;

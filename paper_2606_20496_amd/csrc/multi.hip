@@ -159,14 +159,12 @@ __global__ __launch_bounds__(256) void k_m_start(int64_t nf, int64_t nv, const i
 //   MS_RR  ||r_{k+1}||^2 against tol^2 ||b||^2 and the iteration cap; k + 1 done
 //   MS_RES ||b - A x||^2 of the result
 // A finished column keeps alpha = beta = 0, so its x and r stay as they are.
-__global__ __launch_bounds__(256) void k_m_scal(MScal *__restrict__ ms, const double *__restrict__ part, int n,
-                                                int step) {
-  __shared__ double red[256 / WAVE * MC];
-  __shared__ int live[MC];
-  if (step != MS_BB && step != MS_RES && ms->all_done) return;
+// Column totals of part[0..n)[MC] in a fixed order (rows g, g + GS, ... per
+// thread group, eight loads issued together, then the groups in order); returned
+// in threads 0..MC-1.
+__device__ __forceinline__ double m_coltotal(const double *__restrict__ part, int n, double *red) {
   const int c = threadIdx.x % MC, g = threadIdx.x / MC;
   constexpr int GS = 256 / MC;   // partial rows per step of one thread group
-  // rows g, g + GS, ... in order, eight loads issued together
   double acc = 0.0;
   for (int i0 = g; i0 < n; i0 += 8 * GS) {
     double v[8];
@@ -176,7 +174,19 @@ __global__ __launch_bounds__(256) void k_m_scal(MScal *__restrict__ ms, const do
     for (int u = 0; u < 8; ++u)
       if (i0 + u * GS < n) acc += v[u];
   }
-  const double tot = block_colsum<256>(acc, red);
+  return block_colsum<256>(acc, red);
+}
+
+// part2 (MS_RZ only, may be null): the partials of (r_{k+1}, z_k), for the
+// Polak-Ribiere beta (rho_{k+1} - (r_{k+1}, z_k)) / rho_k of a flexible context.
+__global__ __launch_bounds__(256) void k_m_scal(MScal *__restrict__ ms, const double *__restrict__ part, int n,
+                                                int step, const double *__restrict__ part2) {
+  __shared__ double red[256 / WAVE * MC];
+  __shared__ int live[MC];
+  if (step != MS_BB && step != MS_RES && ms->all_done) return;
+  const int c = threadIdx.x % MC;
+  const double tot = m_coltotal(part, n, red);
+  const double tot2 = (step == MS_RZ && part2) ? m_coltotal(part2, n, red) : 0.0;
   const int it = ms->iter;
   if (threadIdx.x < MC) {
     bool done = ms->done[c] != 0;
@@ -201,7 +211,7 @@ __global__ __launch_bounds__(256) void k_m_scal(MScal *__restrict__ ms, const do
             status = -6;
             iters = it;
           } else if (it > 0) {
-            beta = tot / ms->rho[(it - 1) & 1][c];
+            beta = (tot - tot2) / ms->rho[(it - 1) & 1][c];
           }
         }
         ms->rho[it & 1][c] = tot;
@@ -829,11 +839,13 @@ __global__ __launch_bounds__(256) void k_m_final(int64_t nf, const int32_t *__re
                                                  const T *__restrict__ jv_w, const T *__restrict__ jv_xi,
                                                  int64_t nent, int bx1, int bxy1, const double *__restrict__ yfull,
                                                  double *__restrict__ Z, const double *__restrict__ R,
-                                                 double *__restrict__ part, const MScal *__restrict__ ms) {
+                                                 double *__restrict__ part, double *__restrict__ part2,
+                                                 const MScal *__restrict__ ms) {
   __shared__ double red[256 / WAVE * MC];
   if (ms->all_done) return;
   const int cq = (threadIdx.x % 4) * 4;
   double d[4] = {0.0, 0.0, 0.0, 0.0};
+  double d2[4] = {0.0, 0.0, 0.0, 0.0};   // (r_{k+1}, z_k) for the Polak-Ribiere beta
   const int64_t n = nf * 4, G = (int64_t)gridDim.x * 256;
   for (int64_t g = blockIdx.x * (int64_t)256 + threadIdx.x; g < n; g += G) {
     const int64_t i = g / 4, o = i * MC + cq;
@@ -863,6 +875,12 @@ __global__ __launch_bounds__(256) void k_m_final(int64_t nf, const int32_t *__re
     }
     double r[4];
     ld4(R + o, r);
+    if (part2) {
+      double zo[4];
+      ld4(Z + o, zo);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) d2[j] += r[j] * zo[j];
+    }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       acc[j] += cs[j];
@@ -872,6 +890,10 @@ __global__ __launch_bounds__(256) void k_m_final(int64_t nf, const int32_t *__re
   }
   const double s = block_colsum4<256>(d, red);
   if (threadIdx.x < MC) part[blockIdx.x * MC + threadIdx.x] = s;
+  if (part2) {
+    const double s2 = block_colsum4<256>(d2, red);
+    if (threadIdx.x < MC) part2[blockIdx.x * MC + threadIdx.x] = s2;
+  }
 }
 
 // partials of ||b_c - q_c||^2 (q = A x)

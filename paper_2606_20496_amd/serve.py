@@ -29,13 +29,53 @@ import numpy as np
 from . import coarse
 
 
+class LazyMesh:
+    """A request's mesh, generated when first needed (by a plan worker) and
+    dropped once its setup plan holds what it needs; the sizes and Dirichlet
+    flags a right-hand side needs stay. Generated again if its context is
+    evicted and the mesh comes back."""
+
+    def __init__(self, make):
+        import threading
+        self._make = make
+        self._mesh = None
+        self._lock = threading.Lock()
+        self.n_vert = None
+        self.dirichlet = None
+
+    def get(self):
+        with self._lock:
+            if self._mesh is None:
+                m = self._make()
+                self._mesh = m
+                self.n_vert, self.dirichlet = m.n_vert, m.dirichlet.copy()
+            return self._mesh
+
+    def release(self):
+        with self._lock:
+            self._mesh = None
+
+
+def _mesh_of(mesh):
+    return mesh.get() if isinstance(mesh, LazyMesh) else mesh
+
+
 @dataclasses.dataclass
 class Request:
     t_arrive: float          # seconds after the start of the run
     key: int                 # mesh identity (requests with the same key share a context)
-    mesh: object             # meshgen.Mesh (or any object with its fields)
-    b: np.ndarray            # right-hand side, one value per vertex
+    mesh: object             # meshgen.Mesh (or any object with its fields), or a LazyMesh
+    b: np.ndarray = None     # right-hand side, one value per vertex (or drawn from rhs_seed)
     rid: int = 0
+    rhs_seed: int = -1       # with b None: b = N(0,1) from this seed, 0 on Dirichlet vertices
+
+    def rhs(self):
+        if self.b is not None:
+            return self.b
+        from . import meshgen as mg
+        if isinstance(self.mesh, LazyMesh) and self.mesh.n_vert is None:
+            self.mesh.get()
+        return mg.rhs_normal(self.mesh, self.rhs_seed)
 
 
 @dataclasses.dataclass
@@ -88,7 +128,13 @@ class Server:
         self.planning = {}                       # key -> Future of a Plan (host only)
         self.ready = {}                          # key -> (Plan, estimated bytes)
         self.max_plans = 2 * plan_workers        # plans held on the host at once
-        self.used = 0
+        self.used = 0                            # sum of acct over the resident contexts
+        self.acct = {}                           # key -> device bytes counted for its context
+        self.estimate_ratio_max = 0.0            # largest device_bytes / estimate_bytes seen
+        self.evictions = 0
+        # per cache miss: mesh generation and host plan (worker threads), device
+        # half of the setup (serving thread)
+        self.setup_times = {"mesh_s": [], "plan_s": [], "device_s": []}
         self.keep_outputs = keep_outputs
         self.last_iters = {}                     # key -> iterations of its last solve
         self.adaptive_steps = adaptive_steps
@@ -100,7 +146,42 @@ class Server:
         self.blocks = {}                         # key -> [requests, iterations issued]
 
     def _plan(self, mesh):
-        return coarse.Plan.from_mesh(mesh, precision=self.precision, **self.solver_kw)
+        kw = dict(self.solver_kw)
+        # a server that runs block solves has their vectors allocated by the
+        # setup, so a context's footprint is known when it is admitted
+        if self.block_min >= 2:
+            kw.setdefault("block_rhs", 1)
+        plan = coarse.Plan.from_mesh(_mesh_of(mesh), precision=self.precision, **kw)
+        if isinstance(mesh, LazyMesh):
+            mesh.release()
+        return plan
+
+    def _plan_job(self, mesh):
+        """Worker thread: the mesh (generated here when lazy), its footprint
+        estimate and its setup plan; no GPU call."""
+        t0 = time.perf_counter()
+        m = _mesh_of(mesh)
+        t1 = time.perf_counter()
+        need = self.estimate_bytes(m, self.precision)
+        plan = self._plan(mesh)
+        self.setup_times["mesh_s"].append(t1 - t0)
+        self.setup_times["plan_s"].append(time.perf_counter() - t1)
+        return plan, need
+
+    def _admit(self, key, S, estimate=None):
+        """Count a new resident context against the budget."""
+        self.cache[key] = S
+        self.acct[key] = S.device_bytes
+        self.used += self.acct[key]
+        if estimate:
+            self.estimate_ratio_max = max(self.estimate_ratio_max, S.device_bytes / estimate)
+
+    def _recount(self, key):
+        """A context's footprint may grow after its setup (the block solve's
+        vectors, when the setup did not allocate them): count the difference."""
+        now_bytes = self.cache[key].device_bytes
+        self.used += now_bytes - self.acct[key]
+        self.acct[key] = now_bytes
 
     def _device_setup(self, plan):
         with self.torch.cuda.stream(self.setup_stream):
@@ -114,21 +195,26 @@ class Server:
         plan = self._plan(mesh)
         S = self._device_setup(plan)
         plan.close()
-        self.cache[key] = S
-        self.used += S.device_bytes
+        self._admit(key, S)
         return S
 
     def _evict_for(self, need, keep=()):
         """Evict idle contexts (least recently used first, never those in `keep`)
-        until `need` more bytes fit the budget; True if they do."""
-        for key in list(self.cache):
+        until `need` more bytes fit the budget; True if they do. Nothing is
+        evicted when evicting every idle context would still not make room."""
+        if self.used + need <= self.budget:
+            return True
+        idle = [k for k in self.cache if k not in self.busy and k not in keep]
+        if self.used - sum(self.acct[k] for k in idle) + need > self.budget:
+            return False
+        for key in idle:
             if self.used + need <= self.budget:
-                return True
-            if key in self.busy or key in keep:
-                continue
+                break
             S = self.cache.pop(key)
-            self.used -= S.device_bytes
+            self.used -= self.acct.pop(key)
+            self.last_iters.pop(key, None)
             S.close()
+            self.evictions += 1
         return self.used + need <= self.budget
 
     @staticmethod
@@ -143,8 +229,12 @@ class Server:
         es = {"fp64": 8, "mixed": 4, "mixed16": 2}[precision]
         return int(E * 420 + n * 200 + tiles * 1024 * es * 1.1 + tiles * 32 * es)
 
-    def run(self, requests, t0=None):
+    def run(self, requests, t0=None, progress=None, progress_every=10.0):
+        """Serve `requests` (open loop: each is admitted at its arrival time) until
+        every one has finished; returns (records, wall seconds). `progress`, when
+        given, is called with a short status string every `progress_every` s."""
         torch = self.torch
+        t_report = time.perf_counter()
         reqs = collections.deque(sorted(requests, key=lambda r: r.t_arrive))
         waiting = collections.deque()      # arrived, not yet in the batch
         live = {}                          # rid -> (Request, u, b)
@@ -154,6 +244,11 @@ class Server:
         now = lambda: time.perf_counter() - t0
         while reqs or waiting or live or self.blocks or self.planning or self.ready:
             t = now()
+            if progress is not None and time.perf_counter() - t_report >= progress_every:
+                t_report = time.perf_counter()
+                progress(f"t={t:.1f}s done={len(records)} live={len(live)} waiting={len(waiting)} "
+                         f"planning={len(self.planning)} ready={len(self.ready)} resident={len(self.cache)} "
+                         f"used={self.used / 1e9:.1f}GB")
             while reqs and reqs[0].t_arrive <= t:
                 waiting.append(reqs.popleft())
             # plans finished on the worker threads
@@ -176,8 +271,9 @@ class Server:
                     S = self.cache[key]
                     self.cache.move_to_end(key)
                     with torch.cuda.stream(self.stream):
-                        B = torch.tensor(np.stack([rq.b for rq in rqs]), device="cuda")
+                        B = torch.tensor(np.stack([rq.rhs() for rq in rqs]), device="cuda")
                         S.multi_begin(B, self.tol)
+                    self._recount(key)
                     self.busy.add(key)
                     self.blocks[key] = [rqs, 0]
                     started.update(rq.rid for rq in rqs)
@@ -190,7 +286,7 @@ class Server:
                     S = self.cache[rq.key]
                     self.cache.move_to_end(rq.key)
                     with torch.cuda.stream(self.stream):
-                        b = torch.tensor(rq.b, device="cuda")
+                        b = torch.tensor(rq.rhs(), device="cuda")
                         u = torch.empty_like(b)
                     self.batch.submit(S, b, u, tag=rq.rid, tol=self.tol)
                     self.busy.add(rq.key)
@@ -203,20 +299,20 @@ class Server:
             # fit even with everything idle evicted is built only when no solve runs
             needed = {rq.key for rq in waiting}
             for key, (plan, need) in list(self.ready.items()):
-                if self._evict_for(need, keep=needed) or not live:
+                if self._evict_for(need, keep=needed) or (not live and not self.blocks):
+                    td = time.perf_counter()
                     S = self._device_setup(plan)
+                    self.setup_times["device_s"].append(time.perf_counter() - td)
                     plan.close()
                     del self.ready[key]
-                    self.cache[key] = S
-                    self.used += S.device_bytes
+                    self._admit(key, S, estimate=need)
             # host plans for new meshes
             for rq in waiting:
                 if rq.key in self.cache or rq.key in self.planning or rq.key in self.ready:
                     continue
                 if len(self.planning) + len(self.ready) >= self.max_plans:
                     break
-                need = self.estimate_bytes(rq.mesh, self.precision)
-                self.planning[rq.key] = self.pool.submit(lambda m=rq.mesh, n=need: (self._plan(m), n))
+                self.planning[rq.key] = self.pool.submit(self._plan_job, rq.mesh)
                 missed.add(rq.rid)
             if live or self.blocks:
                 # as many iterations per lock step as the live solve (or block)
@@ -273,25 +369,49 @@ class Server:
         for S in self.cache.values():
             S.close()
         self.cache.clear()
+        self.acct.clear()
+        self.used = 0
 
 
-def serve_sequential(requests, precision="fp64", tol=1e-8, solver_kw=None, cache=None):
+def serve_sequential(requests, precision="fp64", tol=1e-8, solver_kw=None, cache=None, budget_bytes=None,
+                     progress=None, progress_every=10.0):
     """The plain one-at-a-time path: arrival order, one solve at a time, contexts
     cached by mesh key, setup in line. `cache` (key -> CoarseSolver) may hold
-    contexts set up beforehand; the caller keeps ownership of those."""
+    contexts set up beforehand; the caller keeps ownership of those. With
+    `budget_bytes`, contexts it set up are evicted least recently used first to
+    stay within that many device bytes."""
     import torch
-    cache = {} if cache is None else dict(cache)
+    cache = collections.OrderedDict() if cache is None else collections.OrderedDict(cache)
     given = set(cache)
+    used = 0
     records = []
     t0 = time.perf_counter()
+    t_report = t0
     for rq in sorted(requests, key=lambda r: r.t_arrive):
+        if progress is not None and time.perf_counter() - t_report >= progress_every:
+            t_report = time.perf_counter()
+            progress(f"t={t_report - t0:.1f}s done={len(records)} resident={len(cache)} used={used / 1e9:.1f}GB")
         while time.perf_counter() - t0 < rq.t_arrive:
             time.sleep(0.0002)
         miss = rq.key not in cache
         if miss:
-            cache[rq.key] = coarse.CoarseSolver.from_mesh(rq.mesh, precision=precision, **(solver_kw or {}))
+            S = coarse.CoarseSolver.from_mesh(_mesh_of(rq.mesh), precision=precision, **(solver_kw or {}))
+            if isinstance(rq.mesh, LazyMesh):
+                rq.mesh.release()
+            used += S.device_bytes
+            cache[rq.key] = S
+            if budget_bytes is not None:
+                for key in list(cache):
+                    if used <= budget_bytes:
+                        break
+                    if key in given or key == rq.key:
+                        continue
+                    old = cache.pop(key)
+                    used -= old.device_bytes
+                    old.close()
+        cache.move_to_end(rq.key)
         S = cache[rq.key]
-        b = torch.tensor(rq.b, device="cuda")
+        b = torch.tensor(rq.rhs(), device="cuda")
         u, st = S.solve(b, tol)
         records.append(Record(rid=rq.rid, key=rq.key, t_arrive=rq.t_arrive, t_done=time.perf_counter() - t0,
                               iters=st["iters"], relres_true=st["relres_true"], setup=miss,
@@ -303,10 +423,12 @@ def serve_sequential(requests, precision="fp64", tol=1e-8, solver_kw=None, cache
     return records, wall
 
 
-def make_requests(rate, count, seed=59999, nmax=96, reuse=0.3):
+def make_requests(rate, count, seed=59999, nmax=96, reuse=0.3, lazy=False):
     """The serving workload: Poisson arrivals at `rate`, meshes drawn by
     meshgen.serving_request_mesh (n log-uniform in [8, nmax], graded z), 30% of
-    requests reusing an earlier mesh with a new N(0,1) right-hand side."""
+    requests reusing an earlier mesh with a new N(0,1) right-hand side. With
+    `lazy`, meshes and right-hand sides are generated when the server first needs
+    them (thousands of distinct meshes do not fit host memory at once)."""
     from . import meshgen as mg
     t, mesh_id, rhs_seed = mg.serving_arrivals(rate, count=count, seed=seed, reuse=reuse)
     meshes = {}
@@ -314,9 +436,13 @@ def make_requests(rate, count, seed=59999, nmax=96, reuse=0.3):
     for q in range(count):
         k = int(mesh_id[q])
         if k not in meshes:
-            meshes[k] = mg.serving_request_mesh(k, nmax=nmax)
+            meshes[k] = (LazyMesh(lambda k=k: mg.serving_request_mesh(k, nmax=nmax)) if lazy
+                         else mg.serving_request_mesh(k, nmax=nmax))
         m = meshes[k]
-        out.append(Request(t_arrive=float(t[q]), key=k, mesh=m, b=mg.rhs_normal(m, int(rhs_seed[q])), rid=q))
+        if lazy:
+            out.append(Request(t_arrive=float(t[q]), key=k, mesh=m, rid=q, rhs_seed=int(rhs_seed[q])))
+        else:
+            out.append(Request(t_arrive=float(t[q]), key=k, mesh=m, b=mg.rhs_normal(m, int(rhs_seed[q])), rid=q))
     return out
 
 

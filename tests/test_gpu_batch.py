@@ -151,3 +151,58 @@ def test_batch_of_reoriented_meshes(precision):
     for k, (u, iters) in enumerate(ref):
         assert done[k]["code"] == 0 and done[k]["iters"] == iters
         assert torch.equal(us[k], u), k
+
+
+@pytest.mark.timeout(900)
+def test_batch_workload_against_oracle():
+    # the 64 meshes of the batched workload (n log-uniform in [6, 48], blocks of 4,
+    # 6 or 8 elements, a drawn Dirichlet face), solved in one lock-step batch with
+    # graph replay in FP64 and in mixed precision, each against the oracle's solve
+    # of that mesh: FP64 at the oracle's iteration count, mixed within 10% more;
+    # the solutions within 1e-7 (FP64) and 1e-6 (mixed) of the oracle's, relative:
+    # two PCG iterates at a 1e-8 residual that differ only by rounding (about
+    # 4e-9 apart on these i.i.d. right-hand sides)
+    import math
+    import time
+    ms = mg.batch_meshes(count=64)
+    t0 = time.perf_counter()
+    ref = []
+    for k, m in enumerate(ms):
+        P = problem.from_mesh(m)
+        ref.append(P.solve(m.b, tol=1e-8))
+        if k % 16 == 15:
+            print(f"oracle: {k + 1} of 64 batch meshes solved", flush=True)
+    t_oracle = time.perf_counter() - t0
+    print(f"oracle: 64 batch meshes one at a time in {t_oracle:.1f} s ({64 / t_oracle:.2f} solves/s)")
+    stream = torch.cuda.Stream()
+    for precision, tol_u in (("fp64", 1e-7), ("mixed", 1e-6)):
+        solvers = [coarse.CoarseSolver.from_mesh(m, precision=precision) for m in ms]
+        with torch.cuda.stream(stream):
+            bs = [torch.tensor(m.b, device="cuda") for m in ms]
+            us = [torch.zeros_like(b) for b in bs]
+        stream.synchronize()
+        bt = coarse.Batch(stream=stream, use_graph=True)
+        for k in range(len(ms)):
+            bt.submit(solvers[k], bs[k], us[k], tag=k)
+        done = {}
+        while bt.live > 0:
+            for tag, st in bt.step(2):
+                done[tag] = st
+        stream.synchronize()
+        bt.close()
+        for k, (uo, io) in enumerate(ref):
+            st = done[k]
+            assert st["status"] == 0 and st["relres"] <= 1e-8, (precision, k)
+            if precision == "fp64":
+                assert st["iters"] == io["iters"], (k, st["iters"], io["iters"])
+            else:
+                # 10% more, but at least two more: a mesh of one subdomain has an
+                # exact local part and the FP64 method converges in two
+                # iterations (M A has two eigenvalue clusters); FP32 inverses
+                # widen both clusters and CG needs two more to reach 1e-8
+                bar = max(math.ceil(1.1 * io["iters"]), io["iters"] + 2)
+                assert st["iters"] <= bar, (k, st["iters"], io["iters"])
+            u = us[k].cpu().numpy()
+            assert np.linalg.norm(u - uo) <= tol_u * np.linalg.norm(uo), (precision, k)
+        for S in solvers:
+            S.close()

@@ -202,3 +202,37 @@ def test_multi_stepped_equals_solve_multi():
         assert [s["iters"] for s in st0] == [s["iters"] for s in st1]
         assert all(s["status"] == 0 for s in st1)
         S.close()
+
+
+@pytest.mark.parametrize("precision", ["mixed", "mixed16"])
+@pytest.mark.parametrize("name,make", CASES[:3], ids=[c[0] for c in CASES[:3]])
+def test_multi_flexible_beta_matches_single(name, make, precision):
+    # the mixed forms take the Polak-Ribiere beta in the block solve as in
+    # coarse_solve: one column solved as a block takes the single-vector
+    # iteration count (only the summation order inside the dense solves differs)
+    m = make()
+    S = coarse.CoarseSolver.from_mesh(m, precision=precision)
+    assert S.info["precision"] > 0
+    _, st1 = S.solve(_gpu(m.b), tol=1e-8)
+    _, stm = S.solve_multi(_gpu(m.b[None, :]), tol=1e-8)
+    assert stm[0]["iters"] == st1["iters"]
+    assert stm[0]["relres"] <= 1e-8
+    S.close()
+
+
+def test_block_rhs_allocates_at_setup():
+    # opts.block_rhs: the block solve's vectors are allocated by the setup, so the
+    # first block solve leaves the context's device footprint unchanged
+    m = mg.small_cube()
+    S0 = coarse.CoarseSolver.from_mesh(m)
+    S1 = coarse.CoarseSolver.from_mesh(m, block_rhs=1)
+    assert S1.device_bytes > S0.device_bytes
+    before = S1.device_bytes
+    B = _gpu(_rhs(m, 3, 5))
+    U1, st1 = S1.solve_multi(B, tol=1e-8)
+    assert S1.device_bytes == before
+    U0, st0 = S0.solve_multi(B, tol=1e-8)
+    assert S0.device_bytes == before
+    assert torch.equal(U0, U1)
+    S0.close()
+    S1.close()

@@ -91,7 +91,7 @@ def test_apply_precond_small(name, make):
         assert np.all(z[m.dirichlet.astype(bool)] == 0)
 
 
-@pytest.mark.parametrize("mode", ["local_only", "reduced_only", "hybrid_sym"])
+@pytest.mark.parametrize("mode", ["local_only", "reduced_only", "hybrid_sym", "hybrid"])
 def test_apply_precond_modes(mode):
     m = mg.box_mesh(8, 31, block=4, boxes=(2, 2, 2), faces=("x0", "z1"))
     om = {"reduced_only": "coarse_only"}.get(mode, mode)
@@ -130,17 +130,34 @@ def test_standard_interp_reduced_part_is_a_projection():
     assert np.abs(res).max() < 1e-11 * np.abs(J.T @ P.to_free(r)).max()
 
 
-@pytest.mark.parametrize("mode", ["hybrid_sym", "local_only"])
+@pytest.mark.parametrize("mode", ["hybrid_sym", "local_only", "hybrid"])
 def test_solve_modes_match_oracle(mode):
-    # the whole PCG loop with the symmetrised hybrid and with the local part alone:
-    # the same iterations as the oracle and the same solution to the tolerance
+    # the whole PCG loop with the symmetrised hybrid, the paper's hybrid of eqs.
+    # (asm1)-(asm2) (not symmetric: flexible beta on both sides) and the local part
+    # alone: the same iterations as the oracle and the same solution to the tolerance
     m = mg.box_mesh(12, 47, block=4, boxes=(3, 3, 3), faces=("x0",), rhs="bumps")
     om = {"reduced_only": "coarse_only"}.get(mode, mode)
     P = problem.from_mesh(m, mode=om)
-    uo, io = P.solve(m.b, tol=1e-8)
+    uo, io = P.solve(m.b, tol=1e-8, flexible=(mode == "hybrid"))
     S = coarse.CoarseSolver.from_mesh(m, mode=mode)
     u, st = S.solve(_gpu(m.b), tol=1e-8)
     assert st["code"] == 0 and st["iters"] == io["iters"]
+    assert np.linalg.norm(_np(u) - uo) / np.linalg.norm(uo) < 1e-9
+
+
+@pytest.mark.parametrize("name,make", SMALL, ids=[s[0] for s in SMALL])
+def test_hybrid_paper_small(name, make):
+    # eqs. (asm1)-(asm2) as written: one application at 1e-12 against the oracle,
+    # and flexible PCG with the oracle's iteration count
+    m = make()
+    P = problem.from_mesh(m, mode="hybrid")
+    S = coarse.CoarseSolver.from_mesh(m, mode="hybrid")
+    r = np.random.default_rng(15).standard_normal(m.n_vert)
+    assert _rel(_np(S.apply_precond(_gpu(r))), P.apply_precond(r)) < 1e-12
+    uo, io = P.solve(m.b, tol=1e-8, flexible=True)
+    u, st = S.solve(_gpu(m.b), tol=1e-8)
+    assert st["code"] == 0 and st["iters"] == io["iters"]
+    assert st["relres_true"] <= 1.01e-8
     assert np.linalg.norm(_np(u) - uo) / np.linalg.norm(uo) < 1e-9
 
 
@@ -301,6 +318,7 @@ def test_cube64_solve_mixed16(cube64):
     assert st["code"] == 0
     assert st["iters"] <= math.ceil(1.1 * io["iters"])
     assert st["relres_true"] <= 1.05e-8
+    assert np.linalg.norm(_np(u) - uo) / np.linalg.norm(uo) < 1e-6
 
 
 @pytest.mark.timeout(900)
@@ -311,6 +329,30 @@ def test_cube64_solve_mixed(cube64):
     assert st["code"] == 0
     assert st["iters"] <= math.ceil(1.1 * io["iters"])
     assert st["relres_true"] <= 1.05e-8
+    assert np.linalg.norm(_np(u) - uo) / np.linalg.norm(uo) < 1e-6
+
+
+# Error of one mixed-precision preconditioner application against the FP64 oracle
+# (relative, max norm), in full on the 8^3 and 64^3 cubes: at most 16 FP32 unit
+# roundoffs (2^-24) with FP32 inverses and J, at most 4 FP16 unit roundoffs
+# (2^-11) with FP16-stored inverses (each entry of A_p^{-1} is rounded once to
+# that precision; the sums and J run in FP32).
+MIXED_PRECOND_BAR = {"mixed": 16 * 2.0 ** -24, "mixed16": 4 * 2.0 ** -11}
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("precision", ["mixed", "mixed16"])
+def test_mixed_precond_error_vs_oracle(cube64, precision):
+    errs = {}
+    r = np.random.default_rng(16).standard_normal
+    for name, (m, P) in (("cube8", (mg.small_cube(), None)), ("cube64", (cube64[0], cube64[1]))):
+        P = problem.from_mesh(m) if P is None else P
+        S = coarse.CoarseSolver.from_mesh(m, precision=precision)
+        rv = r(m.n_vert)
+        errs[name] = _rel(_np(S.apply_precond(_gpu(rv))), P.apply_precond(rv))
+        S.close()
+    print(f"{precision} preconditioner error vs oracle: {errs}")
+    assert max(errs.values()) < MIXED_PRECOND_BAR[precision]
 
 
 @pytest.mark.timeout(900)

@@ -130,21 +130,25 @@ def test_graph_replay_waits_for_a_new_solves_start(precision):
     srv.close()
 
 
-def test_resident_serving_with_block_solves():
+@pytest.mark.parametrize("block_rhs", [1, 0])
+def test_resident_serving_with_block_solves(block_rhs):
     # a burst of 40 requests on three resident meshes: same-mesh requests that wait
     # for an idle context are solved together by block solves; every result equals,
     # bit for bit, the block solve of that right-hand side alone (the columns of a
-    # block never mix), and reaches the tolerance
+    # block never mix), and reaches the tolerance. The budget counts every
+    # context's footprint, also when its block vectors come after its setup
+    # (block_rhs = 0)
     from paper_2606_20496_amd import meshgen as mg
     meshes = mg.batch_meshes(count=3, nmax=12)
     reqs = serve.make_resident_requests(meshes, rate=200000.0, count=40, seed=5)
     srv = serve.Server(budget_bytes=8e9, precision="mixed", use_graph=True, step_iters=2, keep_outputs=True,
-                       block_min=2)
+                       block_min=2, solver_kw={"block_rhs": block_rhs})
     solvers = {k: srv.preload(k, m) for k, m in enumerate(meshes)}
     # every request has arrived when the loop starts
     import time
     records, wall = srv.run(reqs, t0=time.perf_counter() - 1.0)
     assert len(records) == 40 and all(r.status == 0 and r.relres_true <= 1.05e-8 for r in records)
+    assert srv.used == sum(S.device_bytes for S in srv.cache.values())
     by_id = {r.rid: r for r in records}
     blocked = 0
     for rq in reqs:
