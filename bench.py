@@ -1,20 +1,22 @@
 """Benchmark: coarse solves per second to a 1e-8 relative residual on one MI355X.
 
-One step = one full PCG solve of the coarse Q1 Poisson system A u = b, two-level
-additive Schwarz preconditioned (every row of the hot path: A apply, R_p gather,
-batched dense local and reduced solves, J^T / J, overlap sum, PCG vector ops), on
-the one-GPU-share workload: the 64^3 jittered, randomly renumbered unit cube
-(262,144 elements), 512 subdomains of 8^3 elements with one layer of overlap,
-8 boxes per axis (9^3 reduced grid), RHS = 20 Gaussian bumps + noise (a
-different seeded RHS per step, up to 32 distinct ones). Inputs are resident on
-the GPU before timing; the per-mesh setup (factorisations) is done
-once before the timed region and reported separately.
+One step = one full PCG solve of the coarse Q1 Poisson system A u = b with the
+two-level additive Schwarz preconditioner (every row of the hot path: A apply,
+R_p gather, batched dense local and reduced solves, J^T / J, overlap sum, PCG
+vector ops) on the mixed-versus-FP64 workload: the 128^3 quarter annulus (2.1M
+elements, radial stretching 1.05, randomly renumbered), 4096 subdomains of 8^3
+elements with one layer of overlap, 16 boxes per axis (17^3 reduced grid),
+Dirichlet on r = 1, RHS i.i.d. N(0,1) (a different seeded RHS per step, up to 8
+distinct ones). Inputs are resident on the GPU before timing; the per-mesh setup
+(factorisations) is done once before the timed region and reported separately.
 
-Prints one JSON line (rank 0). The FP64 solve rate is `value`. Two mixed forms
-are reported beside it: FP32 local/reduced inverses and interpolation, and the
-same with the inverses stored in FP16; both keep the operator, residual, dot
-products and outer iteration in FP64. Also reported: the 64-mesh batched
-workload, and the per-kernel figures on the 128^3 quarter-annulus.
+Prints one JSON line. The FP64 solve rate is `value`; the two mixed forms are
+reported beside it (FP32 local/reduced inverses and interpolation, and the same
+with the inverses stored in FP16; both keep the operator, residual, dot products
+and outer iteration in FP64), each with p50/p99 latency. Also reported: the
+64^3 cube (one GPU's share of a larger problem) with its own oracle baseline,
+the 64-mesh batched workload, the preconditioner ablations, serving over
+resident contexts, the warm start and the 16-right-hand-side block solve.
 """
 from __future__ import annotations
 
@@ -47,8 +49,10 @@ GEMV_PHASE = 3
 # counters read on a 1 GiB device copy: FETCH x2.0, WRITE x1.0), and the
 # fingerprint of the GEMV source they were taken on. A changed kernel reports
 # traffic as unknown until the counters are taken again.
-GEMV_TRAFFIC = {"bytes": 1142612987, "fetch_kib": 556422.89, "write_kib": 2987.22, "fetch_scale": 2.0,
-                "write_scale": 1.0, "src": "0c72c6b9fc27f9aa"}
+GEMV_TRAFFIC = {
+    "cube64": {"bytes": 1142612987, "fetch_kib": 556422.89, "write_kib": 2987.22, "fetch_scale": 2.0,
+               "write_scale": 1.0, "src": "0c72c6b9fc27f9aa"},
+}
 
 
 def _gemv_source_fingerprint():
@@ -59,6 +63,11 @@ def _gemv_source_fingerprint():
     a = src.rindex("\n// ----", 0, src.rindex("// ----", 0, i))
     b = src.index("__global__", i)
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+
+
+def _traffic(workload):
+    t = GEMV_TRAFFIC.get(workload)
+    return t["bytes"] if t and _gemv_source_fingerprint() == t["src"] else None
 
 
 def run_form(torch, coarse, mesh, rhs, precision, steps, warmup, tol):
@@ -212,6 +221,51 @@ def run_serving_resident(torch, coarse, mg, tol, rates=(500.0, 2000.0, 8000.0, 3
     return out
 
 
+def _dist(v):
+    v = np.asarray(v, dtype=float)
+    if not len(v):
+        return None
+    return {"n": int(v.size), "mean": round(float(v.mean()), 4), "p50": round(_pct(v, 50), 4),
+            "p99": round(_pct(v, 99), 4)}
+
+
+def run_serving_workload(torch, coarse, mg, tol, rates=(50.0, 2000.0), count=4096, budget_gb=64.0,
+                         precision="mixed", plan_workers=8, sequential=True):
+    """The serving workload with setups in the loop: Poisson arrivals at each rate,
+    `count` requests, each a coarse solve on a seeded mesh with n log-uniform in
+    [8, 96] and a z stretch of up to 20, 30% of them reusing an earlier mesh with
+    a new N(0,1) right-hand side. Meshes are generated when first needed (by the
+    plan workers, counted in the latency). The continuous-batching server (mixed
+    precision, FP64 outer iteration, admission by an HBM budget that binds,
+    least-recently-used eviction) against the plain FP64 one-at-a-time path on
+    the same stream with the same budget. Latency is arrival to result."""
+    from paper_2606_20496_amd import serve
+    out = {"requests_per_rate": count, "n_range": [8, 96], "reuse": 0.3, "budget_GB": budget_gb,
+           "precision": precision, "plan_workers": plan_workers, "rates": {}}
+    keep = ("requests", "wall_s", "solves_per_s", "p50_ms", "p99_ms", "mean_iters", "max_relres_true",
+            "cache_misses", "failed")
+    for rate in rates:
+        reqs = serve.make_requests(rate, count, lazy=True)
+        srv = serve.Server(budget_gb * 1e9, precision=precision, use_graph=True, step_iters=2,
+                           plan_workers=plan_workers)
+        rec, wall = srv.run(reqs, progress=lambda m, r=rate: _log(f"serving {r:g} req/s: {m}"))
+        summ = {k: v for k, v in serve.summarize(rec, wall).items() if k in keep}
+        summ.update(evictions=srv.evictions, estimate_ratio_max=round(srv.estimate_ratio_max, 3),
+                    setup_per_miss_s={k: _dist(v) for k, v in srv.setup_times.items()})
+        srv.close()
+        res = {"batched_" + precision: summ}
+        _log(f"serving {rate:g} req/s: batched {summ['solves_per_s']:.1f}/s p50 {summ['p50_ms']:.0f} ms "
+             f"p99 {summ['p99_ms']:.0f} ms, failed {summ['failed']}")
+        if sequential:
+            rec2, wall2 = serve.serve_sequential(reqs, tol=tol, budget_bytes=budget_gb * 1e9,
+                                                 progress=lambda m, r=rate: _log(f"sequential {r:g}: {m}"))
+            seq = {k: v for k, v in serve.summarize(rec2, wall2).items() if k in keep}
+            res["one_at_a_time_fp64"] = seq
+            _log(f"serving {rate:g} req/s: one at a time {seq['solves_per_s']:.1f}/s p99 {seq['p99_ms']:.0f} ms")
+        out["rates"][str(int(rate))] = res
+    return out
+
+
 INV_ELEM_BYTES = {"fp64": 8, "mixed": 4, "mixed16": 2}
 
 
@@ -246,61 +300,16 @@ def kernel_bytes(info, n_elem, precision):
     }
 
 
-def run_kernels_large(torch, coarse, mg, tol):
-    """The operator and interpolation kernels on the 128^3 quarter-annulus (2.1M
-    elements, 4096 subdomains), where launch latency is amortised: HIP-event
-    timings of every launch over one whole solve, against algorithmic bytes."""
-    mesh = mg.large_annulus()
-    out = {"workload": "annulus128: 128^3 quarter-annulus, radial ratio 1.05, 4096 subdomains of 8^3, "
-                       "16^3 boxes", "n_elem": mesh.n_elem}
-    b = torch.tensor(mesh.b, device="cuda")
-    u = torch.empty_like(b)
-    for prec in ("fp64", "mixed", "mixed16"):
-        t0 = time.perf_counter()
-        S = coarse.CoarseSolver.from_mesh(mesh, precision=prec)
-        torch.cuda.synchronize()
-        t_setup = time.perf_counter() - t0
-        S.solve(b, tol, out=u)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        _, st = S.solve(b, tol, out=u)
-        torch.cuda.synchronize()
-        t_solve = time.perf_counter() - t1
-        S.profile_start(0xFF)
-        S.solve(b, tol, out=u)
-        ph = S.profile_stop()
-        info = dict(S.info)
-        S.close()
-        kb = kernel_bytes(info, mesh.n_elem, prec)
-        ks = {}
-        for name, (ms, cnt) in ph.items():
-            avg = ms / max(cnt, 1) * 1e3
-            e = {"avg_us": round(avg, 2), "launches": cnt}
-            if name in kb and avg > 0:
-                gbs = kb[name] / (avg * 1e-6) / 1e9
-                e.update(alg_bytes=kb[name], GBs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4))
-            ks[name] = e
-        gm = ph[coarse.PHASES[GEMV_PHASE]]
-        gavg = gm[0] / max(st["iters"], 1) * 1e3
-        lb = local_inv_bytes(info, prec)
-        ks[coarse.PHASES[GEMV_PHASE]].update(
-            alg_bytes=lb, avg_us_work=round(gavg, 2), GBs=round(lb / (gavg * 1e-6) / 1e9, 1),
-            frac=round(lb / (gavg * 1e-6) / 1e9 / HBM_PEAK_GBS, 4))
-        out[prec] = {"iters": st["iters"], "relres_true": st["relres_true"], "solve_ms": round(1e3 * t_solve, 3),
-                     "solves_per_s": round(1.0 / t_solve, 3), "setup_s": round(t_setup, 3), "kernels": ks}
-        _log(f"annulus128 {prec}: {st['iters']} iters, {1e3 * t_solve:.2f} ms/solve")
-    return out
-
-
 def run_ablations(torch, coarse, mesh, b, tol, max_it=400):
     """Iterations to the tolerance for the preconditioner's parts and variants on
-    the bench mesh (FP64): the additive two-level method, its local part alone,
-    its reduced part alone, the symmetrised coarse-local-coarse hybrid, and two
-    layers of overlap (the paper's study of the parts, Sec. 5)."""
+    the 64^3 cube (FP64): the additive two-level method, its local part alone,
+    its reduced part alone, the symmetrised coarse-local-coarse hybrid, the
+    paper's hybrid of eqs. (asm1)-(asm2) under the flexible beta, and two layers
+    of overlap (the paper's study of the parts, Sec. 5)."""
     out = {}
     for name, kw in (("additive", {}), ("local_only", {"mode": "local_only"}),
                      ("reduced_only", {"mode": "reduced_only"}), ("hybrid_sym", {"mode": "hybrid_sym"}),
-                     ("additive_overlap2", {"overlap": 2})):
+                     ("hybrid", {"mode": "hybrid"}), ("additive_overlap2", {"overlap": 2})):
         S = coarse.CoarseSolver.from_mesh(mesh, max_it=max_it, **kw)
         u = torch.empty_like(b)
         t0 = time.perf_counter()
@@ -397,40 +406,156 @@ def run_warm_start(torch, coarse, mg, mesh, tol, steps=32, basis=8, precisions=(
     return out
 
 
-def cpu_baseline(mesh, tol):
-    """The FP64 oracle, as it stands, on the host cores: one full solve of the
-    same workload (setup timed separately and excluded)."""
-    cores = len(os.sched_getaffinity(0))
+def _host():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = "unknown"
+    try:
+        b = np.show_config(mode="dicts")["Build Dependencies"]["blas"]
+        blas = f"{b.get('name', '?')} {b.get('version', '')}".strip()
+    except Exception:  # noqa: BLE001
+        pass
+    return {"cores": len(os.sched_getaffinity(0)), "cpu_model": model, "blas": blas}
+
+
+def cpu_baseline_cube64(mesh, tol, runs=3):
+    """The FP64 oracle, as it stands, on the host cores: full solves of the 64^3
+    workload's first right-hand side (setup timed separately and excluded),
+    median of `runs`."""
     from oracle import problem
     t0 = time.perf_counter()
     P = problem.from_mesh(mesh)
     t_setup = time.perf_counter() - t0
+    ts = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        u, info = P.solve(mesh.b, tol=tol)
+        ts.append(time.perf_counter() - t0)
+    t = float(np.median(ts))
+    h = _host()
+    return {"value": round(1.0 / t, 4), "unit": "solves/s", "cores": h["cores"], "kind": "oracle",
+            "sample": f"full FP64 PCG solves of the 64^3 workload (first RHS), median of {runs} "
+                      f"({info['iters']} iterations, {t:.2f} s; oracle setup {t_setup:.1f} s excluded)",
+            "iters": info["iters"], "setup_s": round(t_setup, 2), "cpu_model": h["cpu_model"], "blas": h["blas"]}
+
+
+C3_GOLDEN = os.path.join(ROOT, "tests", "golden", "c3_oracle.json")
+
+
+def cpu_baseline_c3(mesh, n_local=256, iters=2):
+    """The FP64 oracle, as it stands, on a bounded sample of the 128^3 annulus
+    solve: its own routines time the work of one PCG iteration there (the
+    operator product, the local solves of `n_local` of the 4096 subdomains,
+    scaled to all of them, the reduced solve, the vector updates), and the rate
+    is one solve of the oracle's iteration count at that cost. The oracle's setup
+    of the sampled parts is excluded; its full setup of this workload is not run
+    (minutes; the stored oracle solve records it)."""
+    from oracle import fem, reduced, schwarz
+    with open(C3_GOLDEN) as f:
+        golden = json.load(f)
+    d = mesh.dirichlet.astype(bool)
     t0 = time.perf_counter()
-    u, info = P.solve(mesh.b, tol=tol)
-    t = time.perf_counter() - t0
-    return {"value": 1.0 / t, "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": f"one full FP64 PCG solve of the 64^3 workload (first RHS) ({info['iters']} iterations, "
-                      f"{t:.1f} s; oracle setup {t_setup:.1f} s excluded)",
-            "iters": info["iters"]}
+    A, Ae, _, free, fidx = fem.stiffness(mesh.xyz, mesh.e2v, d)
+    mult = fem.multiplicity(mesh.e2v, mesh.n_vert)
+    red = reduced.CentroidSpace(mesh.xyz, mesh.e2v, d, Ae, mesh.boxes, fidx, mult)
+    sel = np.sort(np.random.default_rng(0).choice(mesh.n_part, n_local, replace=False))
+    part = np.asarray(mesh.part)
+    keep = np.isin(part, sel)
+    # the sampled subdomains' overlapping sets and R_p (element layers are grown
+    # over the whole mesh, so the sets equal those of the full construction)
+    sets = schwarz.overlapping_subdomains(mesh.e2v, np.where(keep, np.searchsorted(sel, part), n_local),
+                                          n_local + 1, 1)[:n_local]
+    R = [fidx[r] for r in schwarz.restriction_sets(mesh.e2v, sets, d)]
+    loc = schwarz.LocalSolves(A, R)
+    t_setup = time.perf_counter() - t0
+    rng = np.random.default_rng(1)
+    r = rng.standard_normal(free.size)
+    p = rng.standard_normal(free.size)
+    x = np.zeros(free.size)
+    ts = []
+    for _ in range(iters):
+        t0 = time.perf_counter()
+        q = A @ p                          # operator
+        alpha = float(r @ r) / float(p @ q)
+        x += alpha * p                     # vector updates
+        r -= alpha * q
+        t_vec0 = time.perf_counter()
+        z = loc.apply(r)                   # sampled local solves
+        t_loc = time.perf_counter() - t_vec0
+        t1 = time.perf_counter()
+        z = z + red.apply(r)               # reduced solve
+        beta = float(r @ z) / float(r @ r)
+        p = z + beta * p
+        t_other = time.perf_counter() - t1 + (t_vec0 - t0)
+        ts.append(t_other + t_loc * mesh.n_part / n_local)
+    t_iter = float(np.median(ts))
+    n_it = int(golden["iters"])
+    h = _host()
+    return {"value": round(1.0 / (t_iter * n_it), 5), "unit": "solves/s", "cores": h["cores"], "kind": "oracle",
+            "sample": f"oracle routines timing one PCG iteration of the 128^3 annulus workload (operator, local "
+                      f"solves of {n_local} of {mesh.n_part} subdomains scaled to all, reduced solve, vector "
+                      f"updates; median of {iters}), times the oracle's {n_it} iterations; sampled setup "
+                      f"{t_setup:.1f} s excluded",
+            "s_per_iter": round(t_iter, 4), "iters": n_it, "cpu_model": h["cpu_model"], "blas": h["blas"],
+            "full_oracle_solve_s_stored": golden.get("oracle_solve_s"),
+            "full_oracle_host_stored": golden.get("host")}
+
+
+def run_ablations_c1(mesh, tol):
+    """Iterations of the preconditioner's parts and variants on the 8^3 cube from
+    the oracle (the GPU reaches the same counts; tested)."""
+    from oracle import problem
+    out = {}
+    for name, kw, flex in (("additive", {}, False), ("local_only", {"mode": "local_only"}, False),
+                           ("hybrid_sym", {"mode": "hybrid_sym"}, False), ("hybrid", {"mode": "hybrid"}, True),
+                           ("additive_overlap2", {"overlap": 2}, False)):
+        P = problem.from_mesh(mesh, **kw)
+        u, info = P.solve(mesh.b, tol=tol, flexible=flex)
+        out[name] = {"iters": info["iters"], "converged": bool(info["converged"])}
+    return out
+
+
+def _kernel_table(coarse, f, n_elem, precision):
+    kb = kernel_bytes(f["info"], n_elem, precision)
+    ks = {}
+    for name, (ms, cnt) in f["phases"].items():
+        avg = ms / max(cnt, 1) * 1e3
+        e = {"avg_us": round(avg, 2), "launches": cnt}
+        if name in kb and avg > 0:
+            gbs = kb[name] / (avg * 1e-6) / 1e9
+            e.update(alg_bytes=kb[name], GBs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4))
+        ks[name] = e
+    return ks
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--n", type=int, default=64, help="cube edge in elements (64 = one GPU's share)")
+    ap.add_argument("--n", type=int, default=128, help="annulus edge in elements (128 = the mixed-vs-FP64 mesh)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-cube64", action="store_true", help="skip the 64^3 cube forms and their oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-mesh batched workload")
-    ap.add_argument("--no-large", action="store_true", help="skip the 128^3 annulus kernel measurements")
     ap.add_argument("--no-ablations", action="store_true", help="skip the preconditioner-part study")
     ap.add_argument("--no-warm-start", action="store_true", help="skip the successive right-hand-side study")
     ap.add_argument("--no-multi", action="store_true", help="skip the 16-right-hand-side block solve")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the open-loop serving study over resident contexts")
-    ap.add_argument("--serving", action="store_true", help="also run a short serving-loop workload")
+    ap.add_argument("--serving", action="store_true", help="also run the serving workload with setups in the loop")
+    ap.add_argument("--serving-rates", default="50,2000", help="arrival rates (req/s) of --serving")
+    ap.add_argument("--serving-count", type=int, default=4096, help="requests per rate of --serving")
+    ap.add_argument("--serving-no-sequential", action="store_true",
+                    help="skip the FP64 one-at-a-time comparison of --serving")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 1 GiB device copy (known bytes) to scale HBM counters")
     args = ap.parse_args()
@@ -453,33 +578,76 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    mesh = mg.gpu_share_cube(n=args.n)
-    nrhs = min(args.steps + args.warmup, 32)
-    rhs = [torch.tensor(mesh.b if i == 0 else mg.rhs_bumps(mesh, 100 + i), device="cuda") for i in range(nrhs)]
 
+    # ---- headline: the 128^3 quarter annulus, FP64 and the two mixed forms ----
+    _log(f"annulus{args.n}: mesh")
+    mesh = mg.large_annulus(n=args.n)
+    workload = f"annulus{args.n}"
+    nrhs = min(args.steps + args.warmup, 8)
+    rhs = [torch.tensor(mesh.b if i == 0 else mg.rhs_normal(mesh, 100 + i), device="cuda") for i in range(nrhs)]
     _log("fp64 form")
     fp64 = run_form(torch, coarse, mesh, rhs, "fp64", args.steps, args.warmup, args.tol)
-    _log(f"fp64: {fp64['solves_per_s']:.2f} solves/s")
+    _log(f"fp64: {fp64['solves_per_s']:.3f} solves/s, {fp64['iters']} iterations")
     mixed = mixed16 = None
     if not args.no_mixed:
         mixed = run_form(torch, coarse, mesh, rhs, "mixed", args.steps, args.warmup, args.tol)
-        _log(f"mixed: {mixed['solves_per_s']:.2f} solves/s")
+        _log(f"mixed: {mixed['solves_per_s']:.3f} solves/s, {mixed['iters']} iterations")
         mixed16 = run_form(torch, coarse, mesh, rhs, "mixed16", args.steps, args.warmup, args.tol)
-        _log(f"mixed16: {mixed16['solves_per_s']:.2f} solves/s")
+        _log(f"mixed16: {mixed16['solves_per_s']:.3f} solves/s, {mixed16['iters']} iterations")
+    del rhs
 
     # roofline of the dominant kernel: the batched dense solve of the local systems
-    # (tiled symmetric GEMV over their stored inverses), HBM-bound
+    # (symmetric GEMV over their stored inverses, one workgroup per system), HBM-bound
     ms, cnt = fp64["gemv"]
     avg_s = ms / max(fp64["gemv_work_launches"], 1) / 1e3
     alg_bytes = local_inv_bytes(fp64["info"], "fp64")
     achieved = alg_bytes / avg_s / 1e9 if avg_s > 0 else 0.0
-    traffic = GEMV_TRAFFIC["bytes"] if (args.n == 64 and _gemv_source_fingerprint() == GEMV_TRAFFIC["src"]) else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _traffic(workload),
             "kernel": "k_gemv_whole_f64", "avg_launch_us": round(avg_s * 1e6, 2),
             "launches": cnt, "work_launches": fp64["gemv_work_launches"],
             "alg_bytes_per_launch": alg_bytes}
-    phases = {k: {"avg_us": round(1e3 * v[0] / max(v[1], 1), 2), "launches": v[1]} for k, v in fp64["phases"].items()}
+    kernels = {"fp64": _kernel_table(coarse, fp64, mesh.n_elem, "fp64")}
+    if mixed is not None:
+        kernels["mixed"] = _kernel_table(coarse, mixed, mesh.n_elem, "mixed")
+        kernels["mixed16"] = _kernel_table(coarse, mixed16, mesh.n_elem, "mixed16")
+
+    cpu = None
+    if not args.no_cpu_baseline and args.n == 128:
+        _log("cpu baseline (oracle, sampled iteration of the 128^3 annulus)")
+        cpu = cpu_baseline_c3(mesh)
+        _log(f"cpu baseline: {cpu['value']} solves/s ({cpu['s_per_iter']} s per iteration)")
+    mesh_info = {"n_elem": mesh.n_elem, "n_free": mesh.n_free, "n_sub": fp64["info"]["n_sub"],
+                 "n_r": fp64["info"]["n_r"]}
+    del mesh
+
+    # ---- the 64^3 cube: one GPU's share of a larger problem ----
+    cube = None
+    c2 = mg.gpu_share_cube()
+    if not args.no_cube64:
+        _log("cube64 forms")
+        nr2 = min(20 + 3, 32)
+        rhs2 = [torch.tensor(c2.b if i == 0 else mg.rhs_bumps(c2, 100 + i), device="cuda") for i in range(nr2)]
+        cube = {"workload": "cube64: 64^3 jittered Q1 hex cube, randomly renumbered, Dirichlet x=0; 512 "
+                            "subdomains of 8^3 elements, overlap 1; 8^3 boxes; RHS 20 Gaussian bumps + noise"}
+        c2_fp64 = run_form(torch, coarse, c2, rhs2, "fp64", 20, 3, args.tol)
+        cube["fp64"] = _form_summary(c2_fp64, "f64", "fp64")
+        ms2, _ = c2_fp64["gemv"]
+        avg2 = ms2 / max(c2_fp64["gemv_work_launches"], 1) / 1e3
+        lb2 = local_inv_bytes(c2_fp64["info"], "fp64")
+        cube["fp64"]["roofline"] = {"kernel": "k_gemv_whole_f64", "avg_launch_us": round(avg2 * 1e6, 2),
+                                    "alg_bytes_per_launch": lb2, "frac": round(lb2 / avg2 / 1e9 / HBM_PEAK_GBS, 4),
+                                    "traffic": _traffic("cube64")}
+        if not args.no_mixed:
+            cube["mixed"] = _form_summary(run_form(torch, coarse, c2, rhs2, "mixed", 20, 3, args.tol), "f32",
+                                          "mixed")
+            cube["mixed16"] = _form_summary(run_form(torch, coarse, c2, rhs2, "mixed16", 20, 3, args.tol),
+                                            "f16-stored", "mixed16")
+        if not args.no_cpu_baseline:
+            _log("cube64 cpu baseline (oracle, median of 3)")
+            cube["cpu_baseline"] = cpu_baseline_cube64(c2, args.tol)
+        _log(f"cube64: fp64 {cube['fp64']['value']} solves/s")
+        del rhs2
 
     batch = None
     if not args.no_batch:
@@ -489,8 +657,10 @@ def main():
     ablations = None
     if not args.no_ablations:
         _log("ablations")
-        ablations = run_ablations(torch, coarse, mesh, rhs[0], args.tol)
-        _log(f"ablations: { {k: v['iters'] for k, v in ablations.items()} }")
+        b2 = torch.tensor(c2.b, device="cuda")
+        ablations = {"cube64": run_ablations(torch, coarse, c2, b2, args.tol),
+                     "cube8_oracle": run_ablations_c1(mg.small_cube(), args.tol)}
+        _log(f"ablations: { {k: v['iters'] for k, v in ablations['cube64'].items()} }")
 
     resident = None
     if not args.no_serving:
@@ -500,41 +670,32 @@ def main():
     warm = None
     if not args.no_warm_start:
         _log("warm start")
-        warm = run_warm_start(torch, coarse, mg, mesh, args.tol)
+        warm = run_warm_start(torch, coarse, mg, c2, args.tol)
         _log(f"warm start: {warm}")
 
     multi = None
     if not args.no_multi:
         _log("block solve, 16 right-hand sides")
-        multi = run_multi(torch, coarse, mg, mesh, args.tol, max(2, args.steps // 4), 1)
-        multi["vs_single_fp64"] = round(multi["solves_per_s"] / fp64["solves_per_s"], 2)
-        if mixed16 is not None:
-            m16 = run_multi(torch, coarse, mg, mesh, args.tol, max(2, args.steps // 4), 1, precision="mixed16")
-            m16["vs_single_mixed16"] = round(m16["solves_per_s"] / mixed16["solves_per_s"], 2)
+        multi = run_multi(torch, coarse, mg, c2, args.tol, 5, 1)
+        if cube is not None:
+            multi["vs_single_fp64"] = round(multi["solves_per_s"] / cube["fp64"]["value"], 2)
+        if not args.no_mixed:
+            m16 = run_multi(torch, coarse, mg, c2, args.tol, 5, 1, precision="mixed16")
+            if cube is not None:
+                m16["vs_single_mixed16"] = round(m16["solves_per_s"] / cube["mixed16"]["value"], 2)
             multi["mixed16"] = m16
         _log(f"block solve: {multi}")
 
-    large = None
-    if not args.no_large:
-        _log("annulus128 kernels")
-        large = run_kernels_large(torch, coarse, mg, args.tol)
-
     serving = None
     if args.serving:
-        # the full-size serving workload once ended in a host segmentation fault
-        # whose cause has not been found; it stays switched off until it is
-        print("--serving is disabled: a full-size serving run crashed (host segmentation fault) "
-              "and the cause has not been found", file=sys.stderr)
-        sys.exit(2)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        _log("cpu baseline (oracle)")
-        cpu = cpu_baseline(mesh, args.tol)
+        _log("serving workload with setups in the loop")
+        serving = run_serving_workload(torch, coarse, mg, args.tol,
+                                       rates=tuple(float(x) for x in args.serving_rates.split(",")),
+                                       count=args.serving_count, sequential=not args.serving_no_sequential)
 
     line = {
         "metric": "coarse solves/sec to 1e-8 rel. residual (mixed vs FP64); p50/p99 latency",
-        "value": round(fp64["solves_per_s"], 3),
+        "value": round(fp64["solves_per_s"], 4),
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -545,11 +706,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"cube{args.n}: {args.n}^3 jittered Q1 hex cube, randomly renumbered, "
-                               f"Dirichlet x=0; {mesh.n_part} subdomains of 8^3 elements, overlap 1; "
-                               f"{mesh.boxes[0]}^3 boxes; PCG to {args.tol:g}",
-                   "n_elem": mesh.n_elem, "n_free": mesh.n_free, "n_sub": fp64["info"]["n_sub"],
-                   "n_r": fp64["info"]["n_r"]},
+        "config": {"workload": f"{workload}: {args.n}^3 quarter annulus r in [1,2], theta in [0,pi/2], "
+                               f"z in [0,1], radial ratio 1.05, jitter 0.05, randomly renumbered, Dirichlet r=1; "
+                               f"{mesh_info['n_sub']} subdomains of 8^3 elements, overlap 1; {args.n // 8}^3 "
+                               f"boxes; RHS N(0,1); PCG to {args.tol:g}", **mesh_info},
         "p50_ms": round(fp64["p50_ms"], 4),
         "p99_ms": round(fp64["p99_ms"], 4),
         "iters": fp64["iters"],
@@ -559,24 +719,15 @@ def main():
         "mixed": _form_summary(mixed, "f32 local/reduced inverses, f32 J, f64 operator/vectors/dots", "mixed"),
         "mixed16": _form_summary(mixed16, "f16 storage of the local/reduced inverses (power-of-two scale per "
                                           "system), f32 arithmetic, f32 J, f64 operator/vectors/dots", "mixed16"),
-        "phases_fp64": phases,
+        "kernels": kernels,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
-    if batch is not None:
-        line["batch_workload"] = batch
-    if large is not None:
-        line["large_workload"] = large
-    if ablations is not None:
-        line["ablations"] = ablations
-    if warm is not None:
-        line["warm_start"] = warm
-    if multi is not None:
-        line["multi_rhs"] = multi
-    if resident is not None:
-        line["serving_resident"] = resident
-    if serving is not None:
-        line["serving_workload"] = serving
+    for key, val in (("cube64", cube), ("batch_workload", batch), ("ablations", ablations),
+                     ("warm_start", warm), ("multi_rhs", multi), ("serving_resident", resident),
+                     ("serving_workload", serving)):
+        if val is not None:
+            line[key] = val
     print(json.dumps(line), flush=True)
 
 
