@@ -44,7 +44,7 @@ def _pct(a, q):
 
 GEMV_PHASE = 3
 
-# HBM bytes per dense-solve launch (k_gemv_whole_f64) on the 64^3 workload from hardware counters
+# HBM bytes per dense-solve launch (k_gemv_whole_f64) per workload from hardware counters
 # (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, per dispatch, scaled by the same
 # counters read on a 1 GiB device copy: FETCH x2.0, WRITE x1.0), and the
 # fingerprint of the GEMV source they were taken on. A changed kernel reports
@@ -52,6 +52,8 @@ GEMV_PHASE = 3
 GEMV_TRAFFIC = {
     "cube64": {"bytes": 1142612987, "fetch_kib": 556422.89, "write_kib": 2987.22, "fetch_scale": 2.0,
                "write_scale": 1.0, "src": "0c72c6b9fc27f9aa"},
+    "annulus128": {"bytes": 9215641600, "fetch_kib": 4488113.0, "write_kib": 23424.0, "fetch_scale": 2.0,
+                   "write_scale": 1.0, "src": "0c72c6b9fc27f9aa"},
 }
 
 
@@ -632,6 +634,7 @@ def main():
                             "subdomains of 8^3 elements, overlap 1; 8^3 boxes; RHS 20 Gaussian bumps + noise"}
         c2_fp64 = run_form(torch, coarse, c2, rhs2, "fp64", 20, 3, args.tol)
         cube["fp64"] = _form_summary(c2_fp64, "f64", "fp64")
+        cube["kernels_fp64"] = _kernel_table(coarse, c2_fp64, c2.n_elem, "fp64")
         ms2, _ = c2_fp64["gemv"]
         avg2 = ms2 / max(c2_fp64["gemv_work_launches"], 1) / 1e3
         lb2 = local_inv_bytes(c2_fp64["info"], "fp64")
