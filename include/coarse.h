@@ -28,7 +28,7 @@
  *     at once. No call after coarse_setup allocates device memory, except
  *     the first block solve of a context set up without opts.block_rhs (see
  *     coarse_solve_multi) and the lock-step batch calls, which hold their own
- *     tables.
+ *     tables (coarse_solve_batch_noalloc allocates nothing).
  */
 #ifndef COARSE_H
 #define COARSE_H
@@ -317,6 +317,21 @@ int coarse_multi_end(coarse_ctx *ctx, double *u, coarse_stats *st);
  * equals what coarse_solve gives for that system alone (bitwise). */
 int coarse_solve_batch(coarse_ctx *const *ctxs, const double *const *b, double *const *u,
                        int count, double tol, coarse_stats *st);
+
+/* coarse_solve_batch without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the same solves and the same results (bitwise), with
+ * the batch's device tables in a fixed 1 MiB array of the library on each
+ * device (held until the process ends) and its host staging in a fixed host
+ * array, instead of memory allocated per call. No graph replay. It calls no
+ * hipMalloc, hipFree or other allocating routine; the contexts' own memory is
+ * allocated at their setup. count may not exceed COARSE_NOALLOC_MAX_SOLVES
+ * (else COARSE_EINVAL, message in coarse_last_error(NULL)). Calls share those
+ * arrays: two calls that overlap in time (on any device, from any thread) race
+ * and must not be made. Returns as coarse_solve_batch. */
+#define COARSE_NOALLOC_MAX_SOLVES 256
+int coarse_solve_batch_noalloc(coarse_ctx *const *ctxs, const double *const *b, double *const *u, int count,
+                               double tol, coarse_stats *st);
 
 /* Continuous batching (lock-step solves). A batch advances every live solve by
  * whole PCG iterations, all on `stream`, with seven launches per iteration

@@ -33,7 +33,8 @@ EXPORTS = ("coarse_default_opts", "coarse_setup", "coarse_apply_precond", "coars
            "coarse_setup_from_plan", "coarse_plan_destroy", "coarse_plan_set_gemv_tiles",
            "coarse_solve_projected", "coarse_projection_reset", "coarse_solve_multi",
            "coarse_apply_precond_multi", "coarse_multi_begin", "coarse_multi_advance", "coarse_multi_done",
-           "coarse_multi_end")
+           "coarse_multi_end", "coarse_solve_batch_noalloc")
+NOALLOC_MAX_SOLVES = 256   # COARSE_NOALLOC_MAX_SOLVES
 
 PHASES = ("A+p", "R_p+J^T", "J^T corners", "A_p^-1/A_r^-1 gemv", "combine", "sum+J", "x,r update",
           "reduced branch (second stream)")
@@ -146,6 +147,9 @@ def load():
     L.coarse_solve_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i32, dbl,
                                      ctypes.POINTER(_Stats)]
     L.coarse_solve_batch.restype = i32
+    L.coarse_solve_batch_noalloc.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i32, dbl,
+                                             ctypes.POINTER(_Stats)]
+    L.coarse_solve_batch_noalloc.restype = i32
     L.coarse_destroy.argtypes = [vp]
     L.coarse_destroy.restype = i32
     L.coarse_device_bytes.argtypes = [vp]
@@ -502,8 +506,10 @@ class CoarseSolver:
             pass
 
 
-def solve_batch(solvers, bs, tol=1e-8, outs=None):
-    """Solve several systems in lock step (one stream, shared local-solve launch)."""
+def solve_batch(solvers, bs, tol=1e-8, outs=None, noalloc=False):
+    """Solve several systems in lock step (one stream, shared local-solve launch).
+    ``noalloc``: the allocation-free entry point (coarse_solve_batch_noalloc; at
+    most NOALLOC_MAX_SOLVES systems, calls must not overlap)."""
     import torch
     L = load()
     n = len(solvers)
@@ -514,9 +520,10 @@ def solve_batch(solvers, bs, tol=1e-8, outs=None):
     bp = (ctypes.c_void_p * n)(*[s._vec(b).value for s, b in zip(solvers, bs)])
     up = (ctypes.c_void_p * n)(*[s._vec(u).value for s, u in zip(solvers, outs)])
     st = (_Stats * n)()
-    rc = L.coarse_solve_batch(ctxs, bp, up, n, float(tol), st)
+    fn = L.coarse_solve_batch_noalloc if noalloc else L.coarse_solve_batch
+    rc = fn(ctxs, bp, up, n, float(tol), st)
     if rc < 0:
-        raise CoarseError(rc, "batch solve failed")
+        raise CoarseError(rc, L.coarse_last_error(None).decode() if noalloc else "batch solve failed")
     return outs, [{f: getattr(s, f) for f, _ in _Stats._fields_} for s in st]
 
 

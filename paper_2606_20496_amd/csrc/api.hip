@@ -10,6 +10,7 @@
 #include <cstddef>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <type_traits>
@@ -1183,16 +1184,46 @@ struct coarse_batch {
   int grid[NG] = {};
   int op_lds = 0;
   hipGraphExec_t gexec = nullptr;
+  // tables in memory the batch does not own (the allocation-free entry point):
+  // fixed capacity, never reallocated or freed, no graph
+  bool ext = false;
+
   void init(hipStream_t s, bool graph) {
     main = s;
     use_graph = graph && s != nullptr;   // the null stream cannot be captured
+  }
+
+  // Device tables carved from `dev` and host staging from `host` (each at least
+  // table_bytes(cap_) bytes, 256-byte aligned), for at most cap_ solves.
+  static constexpr size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+  static constexpr size_t table_bytes(int cap_) {
+    return align256(3 * (size_t)cap_ * sizeof(Seg)) + align256((size_t)cap_ * sizeof(IterDev)) +
+           align256((size_t)NG * (cap_ + 1) * sizeof(int32_t)) + align256((size_t)cap_ * sizeof(Scalars));
+  }
+  void use_external(void *dev, void *host, int cap_) {
+    char *d = (char *)dev, *h = (char *)host;
+    size_t o = 0;
+    d_seg = (Seg *)(d + o);
+    h_seg = (Seg *)(h + o);
+    o += align256(3 * (size_t)cap_ * sizeof(Seg));
+    d_iter = (IterDev *)(d + o);
+    h_iter = (IterDev *)(h + o);
+    o += align256((size_t)cap_ * sizeof(IterDev));
+    d_off = (int32_t *)(d + o);
+    h_off = (int32_t *)(h + o);
+    o += align256((size_t)NG * (cap_ + 1) * sizeof(int32_t));
+    d_sc = (Scalars *)(d + o);
+    h_sc = (Scalars *)(h + o);
+    cap = cap_;
+    ext = true;
+    use_graph = false;
   }
 
   ~coarse_batch() {
     if (main) (void)hipStreamSynchronize(main);
     for (auto &e : live) e.c->stream = e.saved_stream;
     if (gexec) (void)hipGraphExecDestroy(gexec);
-    free_tables();
+    if (!ext) free_tables();
   }
 
   void free_tables() {
@@ -1242,6 +1273,7 @@ struct coarse_batch {
 
   void rebuild_tables() {
     const int n = (int)live.size();
+    if (n > cap && ext) throw Fail(COARSE_EINVAL, "more solves than the batch's fixed tables hold");
     if (n > cap) {
       DeviceCallScope dc(g_guard);
       HIPCHK(hipStreamSynchronize(main));
@@ -1373,6 +1405,41 @@ struct coarse_batch {
 };
 
 namespace {
+
+// ---------------------------------------------------------------------------
+// Memory of the allocation-free lock-step batch (coarse_solve_batch_noalloc):
+// its device tables (solve segments, per-solve iteration state, workgroup
+// offsets, gathered solver states) live in a file-scope device array instead
+// of memory the batch allocates, and its host staging in a file-scope host
+// array. In host code the name `scratch` stands for the symbol only; the
+// array's device address on each device comes from hipGetSymbolAddress (taken
+// once per device, with that device current) and only that address reaches
+// kernels and copies. Every call on one device shares that device's array.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(1) << 20;
+static_assert(coarse_batch::table_bytes(COARSE_NOALLOC_MAX_SOLVES) <= kScratchBytes,
+              "allocation-free batch tables exceed the scratch array");
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+alignas(256) unsigned char g_noalloc_host[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device.
+void *scratch_address() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) throw Fail(COARSE_EDEVICE, "device id beyond the scratch address table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw Fail(COARSE_EDEVICE, "no device address for the scratch array");
+    g_scratch_dev[dev] = p;
+  }
+  return g_scratch_dev[dev];
+}
 
 // PCG from u_0 = 0 (or, with `projected`, from the projection onto the stored
 // basis, which then takes in the new solution), with host convergence checks
@@ -1814,6 +1881,49 @@ int coarse_solve_batch(coarse_ctx *const *ctxs, const double *const *b, double *
     }
   }
   coarse_batch_destroy(bt);
+  return worst;
+}
+
+int coarse_solve_batch_noalloc(coarse_ctx *const *ctxs, const double *const *b, double *const *u, int count,
+                               double tol, coarse_stats *st) {
+  if (!ctxs || !b || !u || count < 0) return COARSE_EINVAL;
+  if (count > COARSE_NOALLOC_MAX_SOLVES) {
+    g_setup_error = "coarse_solve_batch_noalloc takes at most COARSE_NOALLOC_MAX_SOLVES systems";
+    return COARSE_EINVAL;
+  }
+  if (count == 0) return COARSE_OK;
+  for (int i = 0; i < count; ++i) {
+    if (!ctxs[i] || !b[i] || !u[i] || b[i] == u[i]) return COARSE_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (ctxs[i] == ctxs[j]) return COARSE_EINVAL;
+  }
+  if (!(tol > 0)) return COARSE_EINVAL;
+  int64_t tags[COARSE_NOALLOC_MAX_SOLVES];
+  coarse_stats sts[COARSE_NOALLOC_MAX_SOLVES];
+  coarse_batch bt;
+  int worst = COARSE_OK;
+  try {
+    bt.init(ctxs[0]->stream, false);
+    // every table entry a step reads is written first: nothing to clear
+    bt.use_external(scratch_address(), g_noalloc_host, COARSE_NOALLOC_MAX_SOLVES);
+    for (int i = 0; i < count && worst >= 0; ++i) {
+      const int rc = bt.submit(ctxs[i], b[i], u[i], tol, i);
+      if (rc < 0) worst = rc;
+    }
+    while (worst >= 0 && !bt.live.empty()) {
+      int nd = 0;
+      bt.step(ctxs[0]->check_every, tags, sts, count, &nd);
+      for (int k = 0; k < nd; ++k) {
+        if (st) st[tags[k]] = sts[k];
+        const int s = sts[k].status;
+        if (s < 0 || (s > 0 && worst == COARSE_OK)) worst = s;
+      }
+    }
+  } catch (const Fail &f) {
+    g_setup_error = f.what();
+    return f.code;
+  }
+  if (worst < 0 && !bt.err.empty()) g_setup_error = bt.err;
   return worst;
 }
 

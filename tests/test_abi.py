@@ -141,3 +141,15 @@ def test_plan_flags_blocks_of_mixed_element_orientation():
     assert list(sizes) == list(sizes_r)
     for k in ("n_free", "n_sub", "sum_np", "n_r", "n_cells", "n_jent"):
         assert info[k] == info_r[k], k
+
+
+def test_noalloc_batch_rejects_too_many_systems():
+    # the size check comes before any device call, so it runs without a GPU
+    import ctypes
+    L = coarse.load()
+    n = coarse.NOALLOC_MAX_SOLVES + 1
+    arr = (ctypes.c_void_p * n)()
+    st = (coarse._Stats * n)()
+    assert L.coarse_solve_batch_noalloc(arr, arr, arr, n, 1e-8, st) == -1
+    assert b"COARSE_NOALLOC_MAX_SOLVES" in L.coarse_last_error(None)
+    assert L.coarse_solve_batch_noalloc(arr, arr, arr, 0, 1e-8, st) == 0
