@@ -45,14 +45,44 @@ double now() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// The device's default stream-ordered memory pool keeps what it holds between
+// setups (by default it would give memory back at every synchronisation).
+std::mutex g_pool_mu;
+bool g_pool_ready[64] = {};
+
+void keep_pool_memory() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return;
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  if (g_pool_ready[dev]) return;
+  hipMemPool_t pool = nullptr;
+  HIPCHK(hipDeviceGetDefaultMemPool(&pool, dev));
+  uint64_t keep = UINT64_MAX;
+  HIPCHK(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+  g_pool_ready[dev] = true;
+}
+
+// Device memory of a context (hipMalloc, freed at release), or with a stream
+// the temporaries of a setup: stream-ordered allocations from the device's
+// pool, freed in stream order, so that releasing them does not synchronise the
+// device (a plain hipFree would wait for every stream, the solves of other
+// contexts included).
 struct Arena {
   std::vector<void *> ptrs;
   size_t bytes = 0;
+  hipStream_t ordered = nullptr;
+  bool stream_ordered = false;
+  Arena() = default;
+  explicit Arena(hipStream_t s) : ordered(s), stream_ordered(true) { keep_pool_memory(); }
   template <typename T>
   T *alloc(size_t n) {
     if (n == 0) n = 1;
     void *p = nullptr;
-    HIPCHK(hipMalloc(&p, n * sizeof(T)));
+    if (stream_ordered)
+      HIPCHK(hipMallocAsync(&p, n * sizeof(T), ordered));
+    else
+      HIPCHK(hipMalloc(&p, n * sizeof(T)));
     ptrs.push_back(p);
     bytes += n * sizeof(T);
     return (T *)p;
@@ -68,12 +98,16 @@ struct Arena {
     return p;
   }
   void release() {
-    for (void *p : ptrs) (void)hipFree(p);
+    for (void *p : ptrs) (void)(stream_ordered ? hipFreeAsync(p, ordered) : hipFree(p));
     ptrs.clear();
     bytes = 0;
   }
   ~Arena() { release(); }
 };
+
+// largest box grid whose reduced solution the final kernel stages in LDS (with
+// 512-thread workgroups, four per compute unit still fit its 160 KiB)
+constexpr int64_t kYLdsMaxBytes = 40 * 1024;
 
 // upper bounds on a system's tile count per work-item bucket (the last is open)
 const int kGemvBucketMax[COARSE_GEMV_BUCKETS] = {2, 4, 8, 12, 16, 24, 48, 1 << 30};
@@ -172,6 +206,7 @@ struct coarse_ctx {
   // stream beside the local dense solves
   bool reduced_aside = false;
   int32_t *cover_ptr = nullptr, *cover_pos = nullptr;
+  int y_lds = 0;   // the final kernel stages the reduced solution (n_bv doubles) in LDS
 
   // reduced space
   int32_t *jv_ptr = nullptr, *jv_occ = nullptr, *jc_vid = nullptr, *jt_start = nullptr, *jr_ptr = nullptr,
@@ -327,9 +362,12 @@ struct coarse_ctx {
   void final_step(const double *add, bool local, bool coarse, double *out, const double *rdot, double *p1, double *p2,
                   const int *done, bool scal, int start) {
     pbeg(5);
-    hipLaunchKernelGGL(k_final<T>, dim3(nvblk), dim3(VW), 0, stream, nf, done, add, local ? cover_ptr : nullptr,
-                       cover_pos, zp, coarse ? jv_ptr : nullptr, jv_base, (const T *)jv_w, (const T *)jv_xi, nent, bx1,
-                       bxy1, (const double *)yfull, out, rdot, p1, p2, scal ? sc : nullptr, start);
+    const int yl = (coarse && y_lds) ? 1 : 0;
+    hipLaunchKernelGGL(k_final<T>, dim3(nvblk), dim3(VW), yl ? n_bv * sizeof(double) : 0, stream, nf, done, add,
+                       local ? cover_ptr : nullptr, (const int32_t *)cover_pos, (const double *)zp,
+                       coarse ? jv_ptr : nullptr, jv_base,
+                       (const T *)jv_w, (const T *)jv_xi, nent, bx1, bxy1, (const double *)yfull, (int)n_bv, yl, out,
+                       rdot, p1, p2, scal ? sc : nullptr, start);
     pend(5);
   }
 
@@ -475,6 +513,8 @@ struct coarse_ctx {
     d.prr = prr;
     d.zp = zp;
     d.yfull = yfull;
+    d.n_bv = (int32_t)n_bv;
+    d.y_lds = y_lds;
     d.sub_idx = sub_idx;
     d.jt_start = jt_start;
     d.jc_vid = jc_vid;
@@ -546,6 +586,7 @@ struct coarse_ctx {
     if (mb.ready) return;
     DeviceCallScope dc(g_guard);
     hipStream_t s = stream;
+    arena.ordered = s;
     Arena &A = arena;
     const int64_t nfm = nf * MC;
     mb.X = A.alloc<double>(nfm);
@@ -751,7 +792,7 @@ int64_t invert_systems(coarse_ctx *c, const std::vector<System> &sys, const std:
       poff += S.nb;
       maxnb = std::max<int64_t>(maxnb, S.nb);
     }
-    Arena tmp;
+    Arena tmp(s);
     double *M = tmp.alloc<double>((size_t)toff * TILE * TILE);
     double *Pb = tmp.alloc<double>((size_t)poff * TILE * TILE);
     double *Gb = tmp.alloc<double>((size_t)poff * TILE * TILE);
@@ -803,7 +844,7 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
   Arena &A = c->arena;
   const int64_t NE = P.n_elem, NV = P.n_vert, nf = P.n_free;
   // geometry and element matrices
-  Arena tmp;
+  Arena tmp(s);
   double *xyz = tmp.upload(P.xyz, s);
   int32_t *e2v = tmp.upload(P.e2v, s);
   // all 36 entries for the setup's assemblies; the 28 off-diagonal ones stay for the operator
@@ -992,6 +1033,7 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
 
   // reduced solution on the full box-vertex grid (inactive vertices stay 0)
   c->yfull = A.alloc<double>(P.n_bv);
+  c->y_lds = (P.n_bv * (int64_t)sizeof(double) <= kYLdsMaxBytes) ? 1 : 0;
   HIPCHK(hipMemsetAsync(c->yfull, 0, P.n_bv * sizeof(double), s));
   c->act_bv = A.upload(P.act_bv, s);
   c->bx1 = P.b[0] + 1;
@@ -1182,7 +1224,7 @@ struct coarse_batch {
   Scalars *d_sc = nullptr, *h_sc = nullptr;       // [cap] solver states, gathered each step
   int cap = 0, n_items = 0, n_rows = 0, n_whole = 0, whole_lds = 0;
   int grid[NG] = {};
-  int op_lds = 0;
+  int op_lds = 0, fin_lds = 0;
   hipGraphExec_t gexec = nullptr;
   // tables in memory the batch does not own (the allocation-free entry point):
   // fixed capacity, never reallocated or freed, no graph
@@ -1289,7 +1331,7 @@ struct coarse_batch {
       HIPCHK(hipHostMalloc((void **)&h_sc, cap * sizeof(Scalars), hipHostMallocDefault));
     }
     n_items = n_rows = n_whole = 0;
-    op_lds = whole_lds = 0;
+    op_lds = whole_lds = fin_lds = 0;
     for (int g = 0; g < NG; ++g) h_off[g * (cap + 1)] = 0;
     for (int k = 0; k < n; ++k) {
       coarse_ctx *c = live[k].c;
@@ -1309,6 +1351,7 @@ struct coarse_batch {
         h_off[g * (cap + 1) + k + 1] = (int32_t)next;
       }
       op_lds = std::max(op_lds, (int)c->op.lds_bytes);
+      if (c->y_lds) fin_lds = std::max(fin_lds, (int)(c->n_bv * sizeof(double)));
     }
     for (int g = 0; g < NG; ++g) grid[g] = h_off[g * (cap + 1) + n];
     HIPCHK(hipMemcpyAsync(d_seg, h_seg, 3 * cap * sizeof(Seg), hipMemcpyHostToDevice, main));
@@ -1336,7 +1379,8 @@ struct coarse_batch {
     if (n_rows > 0)
       hipLaunchKernelGGL(k_combine<T>, dim3(nblk((int64_t)n_rows * TILE, 256)), dim3(256), 0, main,
                          (const Seg *)(d_seg + cap), n, n_rows, (const int *)nullptr);
-    hipLaunchKernelGGL(k_final_grp<T>, dim3(grid[G_FIN]), dim3(VW), 0, main, (const IterDev *)d_iter, off + 4 * L, n);
+    hipLaunchKernelGGL(k_final_grp<T>, dim3(grid[G_FIN]), dim3(VW), fin_lds, main, (const IterDev *)d_iter,
+                       off + 4 * L, n);
   }
   void lock_step() {
     if (precision == COARSE_FP64)
@@ -1612,6 +1656,16 @@ int coarse_setup_from_plan(const coarse_plan *plan, void *stream, coarse_ctx **o
   DeviceCallScope dc(g_guard);
   std::unique_ptr<coarse_ctx> c(new coarse_ctx());
   c->stream = (hipStream_t)stream;
+  try {
+    // the context's memory is stream-ordered too: destroying it (evictions in a
+    // serving loop) then never synchronises the device
+    keep_pool_memory();
+  } catch (const Fail &f) {
+    g_setup_error = f.what();
+    return f.code;
+  }
+  c->arena.ordered = c->stream;
+  c->arena.stream_ordered = true;
   c->precision = o.precision;
   c->mode = o.mode;
   c->interp = o.interp;
@@ -1974,6 +2028,9 @@ int coarse_destroy(coarse_ctx *c) {
   if (!c) return COARSE_OK;
   DeviceCallScope dc(g_guard);
   (void)hipStreamSynchronize(c->stream);
+  // the memory goes back to the pool in the order of the context's stream (its
+  // second stream is drained by the destructor first)
+  c->arena.ordered = c->stream;
   delete c;
   return COARSE_OK;
 }

@@ -103,6 +103,8 @@ struct IterDev {
   int32_t nvblk;     // grid of the per-vertex kernels = number of their partials
   int32_t ng;        // gather workgroups of the restriction kernel
   int32_t ntask, bx1, bxy1, flexible;
+  int32_t n_bv;      // box vertices of the full reduced grid
+  int32_t y_lds;     // 1: the final kernel stages the reduced solution in LDS
 };
 
 }  // namespace coarse

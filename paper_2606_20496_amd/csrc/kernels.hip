@@ -312,16 +312,17 @@ __global__ __launch_bounds__(VB) void k_res_total(Scalars *__restrict__ sc, cons
 // ---------------------------------------------------------------------------
 constexpr int UV = 4;   // entries per thread and step in the restriction gather
 
-// Sum of part[0..n) in a fixed order, returned to every thread (NT threads).
-template <int NT>
+// Sum of part[0..n) in a fixed order, returned to every thread (NT threads); U
+// loads per thread are issued together.
+template <int NT, int U = 4>
 __device__ __forceinline__ double block_total(const double *__restrict__ part, int n, double *red) {
   double acc = 0.0;
-  for (int i0 = threadIdx.x; i0 < n; i0 += 4 * NT) {
-    double v[4];
+  for (int i0 = threadIdx.x; i0 < n; i0 += U * NT) {
+    double v[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = (i0 + u * NT < n) ? part[i0 + u * NT] : 0.0;
+    for (int u = 0; u < U; ++u) v[u] = (i0 + u * NT < n) ? part[i0 + u * NT] : 0.0;
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < U; ++u)
       if (i0 + u * NT < n) acc += v[u];
   }
   acc = wave_sum(acc);
@@ -455,7 +456,50 @@ __global__ __launch_bounds__(OP_BLOCK) void k_op_fused(OpDev op, const double *_
 
 // alpha = rho / p.Ap (from the operator's partials), x += alpha p,
 // r -= alpha q (q of vertices shared between operator blocks is summed here from
-// the operator's partials), and partials of ||r||^2.
+// the operator's partials), and partials of ||r||^2. A thread takes its vertices
+// two at a time (i and i + G, then i + 2G and i + 3G, ...): their loads are
+// issued together, the first pair's before the sum of the operator's partials,
+// and q[i] is loaded whatever the vertex (a shared vertex then ignores it), so
+// an owned vertex needs one round of loads. The squares are summed in the order
+// i, i + G, i + 2G, ...
+struct UpdV {
+  int2 vq;
+  double q, p, x, r;
+};
+
+__device__ __forceinline__ void update_load(int64_t i, int64_t nf, const OpDev &op, const double *__restrict__ q,
+                                            const double *__restrict__ p, const double *__restrict__ x,
+                                            const double *__restrict__ r, UpdV &v) {
+  if (i < nf) {
+    v.vq = op.vq[i];
+    v.q = q[i];
+    v.p = p[i];
+    v.x = x[i];
+    v.r = r[i];
+  }
+}
+
+__device__ __forceinline__ void update_one(int64_t i, const OpDev &op, double alpha, const UpdV &v,
+                                           double *__restrict__ x, double *__restrict__ r, double &acc) {
+  double qi = v.q;
+  if (v.vq.y != 0) {
+    // the partials of a shared vertex are contiguous: issue the loads together
+    qi = 0.0;
+    for (int k0 = 0; k0 < v.vq.y; k0 += 8) {
+      double pv[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) pv[k] = (k0 + k < v.vq.y) ? op.partials[v.vq.x + k0 + k] : 0.0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (k0 + k < v.vq.y) qi += pv[k];
+    }
+  }
+  x[i] = v.x + alpha * v.p;
+  const double ri = v.r - alpha * qi;
+  r[i] = ri;
+  acc += ri * ri;
+}
+
 __device__ __forceinline__ void update_fused_body(int64_t nf, OpDev op, Scalars *__restrict__ sc,
                                                   double *__restrict__ x, double *__restrict__ r,
                                                   const double *__restrict__ pa, const double *__restrict__ pb,
@@ -463,7 +507,13 @@ __device__ __forceinline__ void update_fused_body(int64_t nf, OpDev op, Scalars 
                                                   int nen, double *__restrict__ part, int blk, int nblk, double *red) {
   if (sc->done) return;
   const int it = sc->iter;
-  const double pq = block_total<VW>(energy, nen, red);
+  const double *p = (it & 1) ? pb : pa;
+  const int64_t G = (int64_t)nblk * VW;
+  const int64_t i0 = blk * (int64_t)VW + threadIdx.x;
+  UpdV a{}, b{};
+  update_load(i0, nf, op, q, p, x, r, a);
+  update_load(i0 + G, nf, op, q, p, x, r, b);
+  const double pq = block_total<VW, 8>(energy, nen, red);
   const double rho = sc->rho[it & 1];
   if (!(pq > 0.0) || !isfinite(pq)) {
     if (blk == 0 && threadIdx.x == 0) {
@@ -479,30 +529,12 @@ __device__ __forceinline__ void update_fused_body(int64_t nf, OpDev op, Scalars 
     sc->pq = pq;
     sc->alpha = alpha;
   }
-  const double *p = (it & 1) ? pb : pa;
   double acc = 0.0;
-  const int64_t G = (int64_t)nblk * VW;
-  for (int64_t i = blk * (int64_t)VW + threadIdx.x; i < nf; i += G) {
-    const int2 vq = op.vq[i];
-    double qi;
-    if (vq.y == 0) {
-      qi = q[i];
-    } else {
-      // the partials of a shared vertex are contiguous: issue the loads together
-      qi = 0.0;
-      for (int k0 = 0; k0 < vq.y; k0 += 8) {
-        double pv[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) pv[k] = (k0 + k < vq.y) ? op.partials[vq.x + k0 + k] : 0.0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-          if (k0 + k < vq.y) qi += pv[k];
-      }
-    }
-    x[i] += alpha * p[i];
-    const double ri = r[i] - alpha * qi;
-    r[i] = ri;
-    acc += ri * ri;
+  for (int64_t i = i0; i < nf; i += 2 * G) {
+    update_one(i, op, alpha, a, x, r, acc);
+    if (i + G < nf) update_one(i + G, op, alpha, b, x, r, acc);
+    update_load(i + 2 * G, nf, op, q, p, x, r, a);
+    update_load(i + 3 * G, nf, op, q, p, x, r, b);
   }
   const double s = block_sum<VW>(acc, red);
   if (threadIdx.x == 0) part[blk] = s;
@@ -1542,57 +1574,119 @@ __global__ __launch_bounds__(256) void k_combine(const Seg *__restrict__ segs, i
 //   out_i = add_i + sum_{(p,a) covering i} z_p[a]             (local part)
 //               + sum_c f_ic sum_k Phi_k(xi_ic) y_r[corner]  (J y_r, Sec. 4)
 // plus partial sums of r.out and r.out_old for the PCG beta.
+// The loads of a vertex go out in three rounds, each issued together: its list
+// bounds (cover and J pointers) with r_i (and out_i, add_i); the positions of
+// its first eight local solutions with its first J entry; then those solutions
+// and the entry's eight box-grid corners. Further entries (more than eight
+// covering subdomains, more than one cell) are walked one by one. With LY the
+// reduced solution on the box grid (n_bv doubles) is first staged in LDS and the
+// corner gathers read LDS. The sums run in the same order either way: the local
+// solutions in list order, then the J entries in list order.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <bool LY>
+__device__ __forceinline__ double y_at(const double *__restrict__ yfull, const double *ly, int64_t b) {
+  if constexpr (LY)
+    return ly[b];
+  else
+    return yfull[b];
+}
+
+template <typename T, bool LY>
 __device__ __forceinline__ void final_body(int64_t nf, const int *__restrict__ done, const double *__restrict__ add,
                                            const int32_t *__restrict__ cover_ptr,
                                            const int32_t *__restrict__ cover_pos, const double *__restrict__ zp,
                                            const int32_t *__restrict__ jv_ptr, const int32_t *__restrict__ jv_base,
                                            const T *__restrict__ jv_w, const T *__restrict__ jv_xi, int64_t nent,
-                                           int bx1, int bxy1, const double *__restrict__ yfull,
+                                           int bx1, int bxy1, const double *__restrict__ yfull, int n_bv, double *ly,
                                            double *__restrict__ out, const double *__restrict__ rdot,
                                            double *__restrict__ part1, double *__restrict__ part2,
                                            Scalars *__restrict__ sc, int start, int blk, int nblk, double *red) {
   if (*done) return;
+  if constexpr (LY) {
+    // eight loads per thread in flight, then their LDS stores
+    for (int t0 = threadIdx.x; t0 < n_bv; t0 += 8 * VW) {
+      double v[8];
+#pragma unroll
+      for (int m = 0; m < 8; ++m) v[m] = (t0 + m * VW < n_bv) ? yfull[t0 + m * VW] : 0.0;
+#pragma unroll
+      for (int m = 0; m < 8; ++m)
+        if (t0 + m * VW < n_bv) ly[t0 + m * VW] = v[m];
+    }
+    __syncthreads();
+  }
   double d1 = 0.0, d2 = 0.0;
   const int64_t G = (int64_t)nblk * VW;
   for (int64_t i = blk * (int64_t)VW + threadIdx.x; i < nf; i += G) {
-    double acc = add ? add[i] : 0.0;
+    // round 1: list bounds and the per-vertex values
+    int c0 = 0, c1 = 0, j0 = 0, j1 = 0;
     if (cover_ptr) {
-      // local solutions covering vertex i, loads issued eight at a time, summed in order
-      const int c0 = cover_ptr[i], c1 = cover_ptr[i + 1];
-      for (int k0 = c0; k0 < c1; k0 += 8) {
-        int pos[8];
-#pragma unroll
-        for (int m = 0; m < 8; ++m) pos[m] = (k0 + m < c1) ? cover_pos[k0 + m] : -1;
-        double v[8];
-#pragma unroll
-        for (int m = 0; m < 8; ++m) v[m] = (pos[m] >= 0) ? zp[pos[m]] : 0.0;
-#pragma unroll
-        for (int m = 0; m < 8; ++m)
-          if (pos[m] >= 0) acc += v[m];
-      }
+      c0 = cover_ptr[i];
+      c1 = cover_ptr[i + 1];
     }
+    if (jv_ptr) {
+      j0 = jv_ptr[i];
+      j1 = jv_ptr[i + 1];
+    }
+    const double ad = add ? add[i] : 0.0;
+    double ri = 0.0, zo = 0.0;
+    if (rdot) {
+      ri = rdot[i];
+      if (part2) zo = out[i];
+    }
+    // round 2: positions of the first eight local solutions; the first J entry
+    constexpr int NC = 8;
+    int pos[NC];
+#pragma unroll
+    for (int m = 0; m < NC; ++m) pos[m] = (c0 + m < c1) ? cover_pos[c0 + m] : -1;
+    const bool hj = j0 < j1;
+    int b0 = 0;
+    T w0 = T(0), x0 = T(0), y0 = T(0), z0 = T(0);
+    if (hj) {
+      b0 = jv_base[j0];
+      w0 = jv_w[j0];
+      x0 = jv_xi[j0];
+      y0 = jv_xi[nent + j0];
+      z0 = jv_xi[2 * nent + j0];
+    }
+    // round 3: the local solutions and the entry's box-grid corners
+    double v[NC];
+#pragma unroll
+    for (int m = 0; m < NC; ++m) v[m] = (pos[m] >= 0) ? zp[pos[m]] : 0.0;
+    double yc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      yc[q] = hj ? y_at<LY>(yfull, ly, b0 + (q & 1) + ((q >> 1) & 1) * bx1 + ((q >> 2) & 1) * bxy1) : 0.0;
+    double acc = ad;
+#pragma unroll
+    for (int m = 0; m < NC; ++m)
+      if (pos[m] >= 0) acc += v[m];
+    // further covering subdomains (more than eight: two or more layers of overlap)
+    for (int k = c0 + NC; k < c1; ++k) acc += zp[cover_pos[k]];
     if (jv_ptr) {
       // J y_r: the corners of the entry's cell are box vertices base + {0,1} +
       // bx1 {0,1} + bxy1 {0,1} of the full grid (inactive ones hold 0)
       T cs = T(0);
-      for (int k = jv_ptr[i]; k < jv_ptr[i + 1]; ++k) {
-        const int b0 = jv_base[k];
-        const T x = jv_xi[k], y = jv_xi[nent + k], z = jv_xi[2 * nent + k];
-        double yc[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) yc[q] = yfull[b0 + (q & 1) + ((q >> 1) & 1) * bx1 + ((q >> 2) & 1) * bxy1];
+      if (hj) {
         T sv = T(0);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) sv += trilin<T>(q, x, y, z) * (T)yc[q];
+        for (int q = 0; q < 8; ++q) sv += trilin<T>(q, x0, y0, z0) * (T)yc[q];
+        cs += w0 * sv;
+      }
+      for (int k = j0 + 1; k < j1; ++k) {
+        const int bk = jv_base[k];
+        const T x = jv_xi[k], y = jv_xi[nent + k], z = jv_xi[2 * nent + k];
+        double yk[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) yk[q] = y_at<LY>(yfull, ly, bk + (q & 1) + ((q >> 1) & 1) * bx1 + ((q >> 2) & 1) * bxy1);
+        T sv = T(0);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sv += trilin<T>(q, x, y, z) * (T)yk[q];
         cs += jv_w[k] * sv;
       }
       acc += (double)cs;
     }
     if (rdot) {
-      const double ri = rdot[i];
-      if (part2) d2 += ri * out[i];
+      if (part2) d2 += ri * zo;
       d1 += ri * acc;
     }
     out[i] = acc;
@@ -1609,18 +1703,25 @@ __device__ __forceinline__ void final_body(int64_t nf, const int *__restrict__ d
   }
 }
 
+// y_lds = 1: stage the reduced solution (n_bv doubles of dynamic LDS)
 template <typename T>
 __global__ __launch_bounds__(VW) void k_final(int64_t nf, const int *__restrict__ done, const double *__restrict__ add,
-                                              const int32_t *__restrict__ cover_ptr, const int32_t *__restrict__ cover_pos,
-                                              const double *__restrict__ zp, const int32_t *__restrict__ jv_ptr,
-                                              const int32_t *__restrict__ jv_base, const T *__restrict__ jv_w,
-                                              const T *__restrict__ jv_xi, int64_t nent, int bx1, int bxy1,
-                                              const double *__restrict__ yfull, double *__restrict__ out,
-                                              const double *__restrict__ rdot, double *__restrict__ part1,
-                                              double *__restrict__ part2, Scalars *__restrict__ sc, int start) {
+                                              const int32_t *__restrict__ cover_ptr,
+                                              const int32_t *__restrict__ cover_pos, const double *__restrict__ zp,
+                                              const int32_t *__restrict__ jv_ptr, const int32_t *__restrict__ jv_base,
+                                              const T *__restrict__ jv_w, const T *__restrict__ jv_xi, int64_t nent,
+                                              int bx1, int bxy1, const double *__restrict__ yfull, int n_bv, int y_lds,
+                                              double *__restrict__ out, const double *__restrict__ rdot,
+                                              double *__restrict__ part1, double *__restrict__ part2,
+                                              Scalars *__restrict__ sc, int start) {
+  extern __shared__ double ly[];
   __shared__ double red[VW / WAVE];
-  final_body<T>(nf, done, add, cover_ptr, cover_pos, zp, jv_ptr, jv_base, jv_w, jv_xi, nent, bx1, bxy1, yfull, out,
-                rdot, part1, part2, sc, start, blockIdx.x, gridDim.x, red);
+  if (y_lds && jv_ptr)
+    final_body<T, true>(nf, done, add, cover_ptr, cover_pos, zp, jv_ptr, jv_base, jv_w, jv_xi, nent, bx1, bxy1,
+                        yfull, n_bv, ly, out, rdot, part1, part2, sc, start, blockIdx.x, gridDim.x, red);
+  else
+    final_body<T, false>(nf, done, add, cover_ptr, cover_pos, zp, jv_ptr, jv_base, jv_w, jv_xi, nent, bx1, bxy1,
+                         yfull, n_bv, nullptr, out, rdot, part1, part2, sc, start, blockIdx.x, gridDim.x, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -1691,12 +1792,20 @@ __global__ __launch_bounds__(256) void k_jt_corners_grp(const IterDev *__restric
 template <typename T>
 __global__ __launch_bounds__(VW) void k_final_grp(const IterDev *__restrict__ ctx, const int32_t *__restrict__ off,
                                                   int n) {
+  extern __shared__ double ly[];
   __shared__ double red[VW / WAVE];
   const int c = find_ctx(off, n, blockIdx.x);
   const IterDev &d = ctx[c];
-  final_body<T>(d.nf, &d.sc->done, nullptr, d.cover_ptr, d.cover_pos, d.zp, d.jv_ptr, d.jv_base,
-                (const T *)d.jv_w, (const T *)d.jv_xi, d.nent, d.bx1, d.bxy1, d.yfull, d.z, d.r, d.part1,
-                d.flexible ? d.part2 : nullptr, d.sc, 0, blockIdx.x - off[c], off[c + 1] - off[c], red);
+  if (d.y_lds)
+    final_body<T, true>(d.nf, &d.sc->done, nullptr, d.cover_ptr, d.cover_pos, d.zp, d.jv_ptr, d.jv_base,
+                        (const T *)d.jv_w, (const T *)d.jv_xi, d.nent, d.bx1, d.bxy1, d.yfull, d.n_bv, ly, d.z, d.r,
+                        d.part1, d.flexible ? d.part2 : nullptr, d.sc, 0, blockIdx.x - off[c],
+                        off[c + 1] - off[c], red);
+  else
+    final_body<T, false>(d.nf, &d.sc->done, nullptr, d.cover_ptr, d.cover_pos, d.zp, d.jv_ptr, d.jv_base,
+                         (const T *)d.jv_w, (const T *)d.jv_xi, d.nent, d.bx1, d.bxy1, d.yfull, d.n_bv, nullptr,
+                         d.z, d.r, d.part1, d.flexible ? d.part2 : nullptr, d.sc, 0, blockIdx.x - off[c],
+                         off[c + 1] - off[c], red);
 }
 
 // ---------------------------------------------------------------------------
