@@ -63,6 +63,37 @@ void keep_pool_memory() {
   g_pool_ready[dev] = true;
 }
 
+// Small pinned host blocks (solver states read back by the host) carved from
+// 1 MiB slabs that the process keeps: setting up and destroying contexts then
+// allocates and frees no pinned memory (freeing pinned memory synchronises the
+// device).
+class PinnedPool {
+ public:
+  static constexpr size_t kBlock = 4096, kSlab = size_t(1) << 20;
+  void *get(size_t n) {
+    if (n > kBlock) throw Fail(COARSE_EINVAL, "pinned block request too large");
+    std::lock_guard<std::mutex> lk(mu_);
+    if (free_.empty()) {
+      void *slab = nullptr;
+      HIPCHK(hipHostMalloc(&slab, kSlab, hipHostMallocDefault));
+      for (size_t k = 0; k < kSlab / kBlock; ++k) free_.push_back((char *)slab + k * kBlock);
+    }
+    void *p = free_.back();
+    free_.pop_back();
+    return p;
+  }
+  void put(void *p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(mu_);
+    free_.push_back(p);
+  }
+
+ private:
+  std::mutex mu_;
+  std::vector<void *> free_;
+};
+PinnedPool g_pinned;
+
 // Device memory of a context (hipMalloc, freed at release), or with a stream
 // the temporaries of a setup: stream-ordered allocations from the device's
 // pool, freed in stream order, so that releasing them does not synchronise the
@@ -87,16 +118,24 @@ struct Arena {
     bytes += n * sizeof(T);
     return (T *)p;
   }
-  // The source may be a temporary: the copy is complete when this returns.
+  // Uploads are stream-ordered and not waited for: the source must live until the
+  // caller's next synchronisation of the stream. A temporary source (an rvalue)
+  // is kept in `hold` until drop_hold(), which the caller calls after that
+  // synchronisation.
+  std::vector<std::shared_ptr<void>> hold;
   template <typename T>
   T *upload(const std::vector<T> &v, hipStream_t s) {
     T *p = alloc<T>(v.size());
-    if (!v.empty()) {
-      HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
-      HIPCHK(hipStreamSynchronize(s));
-    }
+    if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
     return p;
   }
+  template <typename T>
+  T *upload(std::vector<T> &&v, hipStream_t s) {
+    auto kept = std::make_shared<std::vector<T>>(std::move(v));
+    hold.push_back(kept);
+    return upload(*kept, s);
+  }
+  void drop_hold() { hold.clear(); }
   void release() {
     for (void *p : ptrs) (void)(stream_ordered ? hipFreeAsync(p, ordered) : hipFree(p));
     ptrs.clear();
@@ -253,9 +292,9 @@ struct coarse_ctx {
     }
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
-    if (h_sc) (void)hipHostFree(h_sc);
-    if (h_proj_count) (void)hipHostFree(h_proj_count);
-    if (mb.h_ms) (void)hipHostFree(mb.h_ms);
+    g_pinned.put(h_sc);
+    g_pinned.put(h_proj_count);
+    g_pinned.put(mb.h_ms);
     for (auto &p : ev_pending) {
       ev_pool.push_back(p.second.first);
       ev_pool.push_back(p.second.second);
@@ -623,8 +662,11 @@ struct coarse_ctx {
     mb.nrows = (int)rows.size();
     mb.rows = A.upload(rows, s);
     mb.sys = A.upload(h_msys, s);
-    HIPCHK(hipHostMalloc((void **)&mb.h_ms, sizeof(MScal), hipHostMallocDefault));
+    mb.h_ms = (MScal *)g_pinned.get(sizeof(MScal));
     mb.lds = (int32_t)((OP_BLOCK * 8 + max_slots * MCW) * sizeof(double));
+    // the uploads above read host vectors of this function
+    HIPCHK(hipStreamSynchronize(s));
+    A.drop_hold();
     mb.ready = true;
   }
 
@@ -911,7 +953,7 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
     c->proj_part = A.alloc<double>((size_t)(c->proj_max + 1) * npart);
     c->proj_coef = A.alloc<double>(c->proj_max + 1);
     c->proj_count = A.alloc<int>(1);
-    HIPCHK(hipHostMalloc((void **)&c->h_proj_count, sizeof(int), hipHostMallocDefault));
+    c->h_proj_count = (int *)g_pinned.get(sizeof(int));
   }
 
   // packed vectors, systems, tiles
@@ -1132,6 +1174,7 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
   c->jr_src = A.upload(P.jr_src, s);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
+  A.drop_hold();
 
   // sizes
   coarse_info_t &in = c->info;
@@ -1678,7 +1721,7 @@ int coarse_setup_from_plan(const coarse_plan *plan, void *stream, coarse_ctx **o
     HIPCHK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
-    HIPCHK(hipHostMalloc((void **)&c->h_sc, sizeof(Scalars), hipHostMallocDefault));
+    c->h_sc = (Scalars *)g_pinned.get(sizeof(Scalars));
     if (o.precision == COARSE_FP64)
       setup_precision<double, double>(c.get(), P, o.gemv_tiles);
     else if (o.precision == COARSE_MIXED)
