@@ -16,13 +16,15 @@ class Problem:
     """Sec. 3-4 assembled once per mesh.
 
     interp: "centroid" (cell-assembled A_r, default) or "standard" (Galerkin).
+    local_iters: 0 (exact local solves) or k > 0 (k steps of Jacobi-PCG per
+            subdomain; nonlinear in r, so solve with ``flexible=True``).
     mode:   "additive" (eq. (asm)), "hybrid" (eqs. (asm1)-(asm2) as written; not
             symmetric, so solve with ``flexible=True``), "hybrid_sym",
             "local_only", "coarse_only".
     """
 
     def __init__(self, xyz, e2v, dirichlet, part, n_part, boxes, overlap=1,
-                 interp="centroid", mode="additive"):
+                 interp="centroid", mode="additive", local_iters=0):
         self.xyz = np.asarray(xyz, dtype=np.float64)
         self.e2v = np.asarray(e2v, dtype=np.int64)
         self.dirichlet = np.asarray(dirichlet).astype(bool)
@@ -32,7 +34,9 @@ class Problem:
         self.elem_sets = schwarz.overlapping_subdomains(self.e2v, part, n_part, overlap)
         self.R_user = schwarz.restriction_sets(self.e2v, self.elem_sets, self.dirichlet)
         self.R = [self.fidx[R] for R in self.R_user]
-        self.local = schwarz.LocalSolves(self.A, self.R)
+        # exact local solves, or with local_iters = k > 0 k steps of Jacobi-PCG
+        self.local = (schwarz.InexactLocalSolves(self.A, self.R, local_iters) if local_iters > 0
+                      else schwarz.LocalSolves(self.A, self.R))
         if interp == "centroid":
             self.coarse = reduced.CentroidSpace(self.xyz, self.e2v, self.dirichlet, self.Ae, boxes,
                                                 self.fidx, self.mult)

@@ -108,3 +108,50 @@ def local_part_at(A, R_free, rows, r):
         hit = R[order][pos] == rows
         out[hit] += zp[order[pos[hit]]]
     return out, which
+
+
+class InexactLocalSolves:
+    """Inexact local solves: on every subdomain, k iterations of conjugate
+    gradients preconditioned by the diagonal of A_p (Jacobi), from a zero initial
+    guess, in place of A_p^{-1} (the paper's suggestion, in its conclusions, of an
+    iterative method such as preconditioned CG as an inexact local solver on the
+    GPU). The local corrections are summed as in eq. (asm). The result depends
+    on r nonlinearly (the CG coefficients are formed from it), so an outer Krylov
+    method must be the flexible one."""
+
+    def __init__(self, A, R_free, iters):
+        self.R = [np.asarray(R, dtype=np.int64) for R in R_free]
+        self.n = A.shape[0]
+        self.k = int(iters)
+        A = A.tocsr()
+        self.A_p = [A[R][:, R].tocsr() for R in self.R]
+        self.dinv = [1.0 / Ap.diagonal() for Ap in self.A_p]
+
+    @staticmethod
+    def jacobi_pcg(Ap, dinv, b, k):
+        """k steps of Jacobi-preconditioned CG on Ap x = b from x = 0."""
+        x = np.zeros_like(b)
+        r = b.copy()
+        z = dinv * r
+        p = z.copy()
+        rz = float(r @ z)
+        for it in range(k):
+            if rz == 0.0:
+                break
+            q = Ap @ p
+            alpha = rz / float(p @ q)
+            x += alpha * p
+            r -= alpha * q
+            if it == k - 1:
+                break
+            z = dinv * r
+            rz_new = float(r @ z)
+            p = z + (rz_new / rz) * p
+            rz = rz_new
+        return x
+
+    def apply(self, r):
+        z = np.zeros(self.n)
+        for R, Ap, dinv in zip(self.R, self.A_p, self.dinv):
+            z[R] += self.jacobi_pcg(Ap, dinv, r[R], self.k)
+        return z

@@ -3,7 +3,7 @@ R_p on the interior nodes of bar-Omega_p, A_p = R_p A R_p^T, eq. (asm) local
 term), checked by counting, brute force and dense library inverses."""
 import numpy as np
 
-from oracle import fem, schwarz
+from oracle import fem, problem, schwarz
 from paper_2606_20496_amd import meshgen as mg
 
 
@@ -109,3 +109,69 @@ def test_sampled_local_part_against_dense_inverses():
     got, which = schwarz.local_part_at(A, R, rows, r)
     assert np.abs(got - full[rows]).max() < 1e-12 * np.abs(full).max()
     assert 0 < len(which) < len(R)          # only the covering subdomains were factored
+
+
+def _inexact_case():
+    m = mg.box_mesh(6, 3, block=3, boxes=(2, 2, 2), faces=("x0",))
+    P = problem.from_mesh(m, local_iters=2)
+    return m, P
+
+
+def test_inexact_local_one_step_closed_form():
+    # one Jacobi-PCG step from zero: z_p = alpha D^{-1} r_p with
+    # alpha = (r, D^{-1} r) / (D^{-1} r, A_p D^{-1} r)
+    m, P = _inexact_case()
+    loc = schwarz.InexactLocalSolves(P.A, P.R, 1)
+    r = np.random.default_rng(3).standard_normal(P.A.shape[0])
+    Ad = P.A.toarray()
+    ref = np.zeros_like(r)
+    for R in P.R:
+        Ap = Ad[np.ix_(R, R)]
+        g = r[R] / np.diag(Ap)
+        ref[R] += (r[R] @ g) / (g @ Ap @ g) * g
+    assert np.abs(loc.apply(r) - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+def test_inexact_local_converges_to_exact():
+    # n_p steps of CG reach the exact local solve (finite termination), and the
+    # A_p-norm error of the local solve never grows with the number of steps
+    m, P = _inexact_case()
+    r = np.random.default_rng(4).standard_normal(P.A.shape[0])
+    exact = P.local.apply(r) if isinstance(P.local, schwarz.LocalSolves) else \
+        schwarz.LocalSolves(P.A, P.R).apply(r)
+    nmax = max(len(R) for R in P.R)
+    full = schwarz.InexactLocalSolves(P.A, P.R, nmax).apply(r)
+    assert np.abs(full - exact).max() < 1e-8 * np.abs(exact).max()
+    Ad = P.A.toarray()
+    R0 = P.R[0]
+    Ap = Ad[np.ix_(R0, R0)]
+    xs = np.linalg.solve(Ap, r[R0])
+    errs = []
+    for k in range(1, 8):
+        x = schwarz.InexactLocalSolves.jacobi_pcg(Ap, 1.0 / np.diag(Ap), r[R0], k)
+        errs.append(float(np.sqrt((x - xs) @ Ap @ (x - xs))))
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(errs, errs[1:]))
+    assert errs[-1] < 0.5 * errs[0]
+
+
+def test_inexact_local_is_nonlinear_but_homogeneous():
+    # the CG coefficients come from r: M(2r) = 2 M(r), M(r1 + r2) != M(r1) + M(r2)
+    m, P = _inexact_case()
+    rng = np.random.default_rng(5)
+    r1, r2 = rng.standard_normal((2, P.A.shape[0]))
+    f = P.local.apply
+    assert np.abs(f(2 * r1) - 2 * f(r1)).max() < 1e-13 * np.abs(f(r1)).max()
+    assert np.abs(f(r1 + r2) - f(r1) - f(r2)).max() > 1e-6 * np.abs(f(r1)).max()
+
+
+def test_inexact_local_solves_under_flexible_pcg():
+    # with the reduced space of eq. (asm) and flexible CG the solve reaches the
+    # tolerance; weaker local solves take more iterations than exact ones
+    m = mg.box_mesh(12, 5, block=3, boxes=(4, 4, 4))
+    its = {}
+    for k in (0, 1, 8):
+        P = problem.from_mesh(m, local_iters=k)
+        u, info = P.solve(m.b, tol=1e-8, flexible=True)
+        assert info["converged"] and info["relres_true"] <= 1.01e-8
+        its[k] = info["iters"]
+    assert its[0] <= its[8] < its[1]
