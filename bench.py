@@ -232,7 +232,7 @@ def _dist(v):
 
 
 def run_serving_workload(torch, coarse, mg, tol, rates=(50.0, 2000.0), count=4096, budget_gb=64.0,
-                         precision="mixed", plan_workers=8, sequential=True):
+                         precision="mixed", plan_workers=12, sequential=True):
     """The serving workload with setups in the loop: Poisson arrivals at each rate,
     `count` requests, each a coarse solve on a seeded mesh with n log-uniform in
     [8, 96] and a z stretch of up to 20, 30% of them reusing an earlier mesh with
@@ -258,7 +258,7 @@ def run_serving_workload(torch, coarse, mg, tol, rates=(50.0, 2000.0), count=409
         res = {"batched_" + precision: summ}
         _log(f"serving {rate:g} req/s: batched {summ['solves_per_s']:.1f}/s p50 {summ['p50_ms']:.0f} ms "
              f"p99 {summ['p99_ms']:.0f} ms, failed {summ['failed']}")
-        if sequential:
+        if sequential is True or (sequential and rate in sequential):
             rec2, wall2 = serve.serve_sequential(reqs, tol=tol, budget_bytes=budget_gb * 1e9,
                                                  progress=lambda m, r=rate: _log(f"sequential {r:g}: {m}"))
             seq = {k: v for k, v in serve.summarize(rec2, wall2).items() if k in keep}
@@ -558,6 +558,8 @@ def main():
     ap.add_argument("--serving-count", type=int, default=4096, help="requests per rate of --serving")
     ap.add_argument("--serving-no-sequential", action="store_true",
                     help="skip the FP64 one-at-a-time comparison of --serving")
+    ap.add_argument("--serving-sequential-rates", default="",
+                    help="run the FP64 one-at-a-time comparison at these rates only (default: every rate)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 1 GiB device copy (known bytes) to scale HBM counters")
     args = ap.parse_args()
@@ -694,7 +696,10 @@ def main():
         _log("serving workload with setups in the loop")
         serving = run_serving_workload(torch, coarse, mg, args.tol,
                                        rates=tuple(float(x) for x in args.serving_rates.split(",")),
-                                       count=args.serving_count, sequential=not args.serving_no_sequential)
+                                       count=args.serving_count,
+                                       sequential=(False if args.serving_no_sequential else
+                                                   {float(x) for x in args.serving_sequential_rates.split(",")}
+                                                   if args.serving_sequential_rates else True))
 
     line = {
         "metric": "coarse solves/sec to 1e-8 rel. residual (mixed vs FP64); p50/p99 latency",

@@ -148,6 +148,12 @@ typedef struct {
                        (Sec. 5); 0 = none. The basis takes 2 l n_free doubles of
                        device memory, allocated by the setup; l <=
                        COARSE_PROJECTION_MAX                                       */
+  int whole_waves;  /* wavefronts per workgroup of the systems solved by one
+                       workgroup each (those of 16..48 tile rows, in contexts with
+                       at least one system per compute unit): 2, 4 or 8 for FP64
+                       tiles, 4, 8 or 16 for FP32/FP16 tiles; 0 = 4 (FP64) or 8.
+                       Halved while the workgroup's LDS copies of the solution
+                       would exceed 64 KiB. Changes the order of rounding only   */
   int block_rhs;    /* 1: the setup also allocates the vectors of the block solve
                        (coarse_solve_multi, about 9 * 16 doubles per free vertex),
                        so that no later call on the context allocates; 0 (default):
@@ -189,6 +195,7 @@ typedef struct {
   int32_t boxes[3];
   int32_t precision;
   int32_t gemv_tiles[COARSE_GEMV_BUCKETS];   /* work-item table the context uses     */
+  int32_t whole_waves;    /* wavefronts per whole-system workgroup in use          */
   int32_t reduced_stream; /* 1: the reduced system has more than 48 tile rows of
                              32, and the additive preconditioner solves it on a
                              second stream beside the local systems (profile
@@ -343,7 +350,10 @@ int coarse_solve_batch_noalloc(coarse_ctx *const *ctxs, const double *const *b, 
  * A submitted solve's first preconditioner application runs at submit. Solves join with
  * coarse_batch_submit and leave when coarse_batch_step reports them finished, so
  * requests that arrive while others are running are admitted between steps.
- * Results are bitwise identical to coarse_solve of the same context and RHS.
+ * Results are bitwise identical to coarse_solve of the same context and RHS, or,
+ * for a context set up with opts.projection > 0, to coarse_solve_projected (the
+ * solve starts from the projection onto the context's prior solutions, and its
+ * solution joins them when it is retired).
  * Contexts must use the additive preconditioner and share one precision; while
  * in a batch a context must not be used otherwise. `stream` orders the batch
  * against the caller (inputs must be ready on it before submit); use_graph = 1

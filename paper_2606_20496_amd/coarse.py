@@ -77,12 +77,23 @@ def gemv_table(precision="fp64"):
     return [4] * GEMV_BUCKETS
 
 
+def whole_waves_choice(precision="fp64"):
+    """Wavefronts per whole-system workgroup for a precision from the tuner's
+    table (0, the library's default, when there is none)."""
+    try:
+        with open(TUNING_PATH) as f:
+            w = int(json.load(f)[precision].get("whole_waves", 0))
+        return w if w in (0, 2, 4, 8, 16) else 0
+    except (OSError, ValueError, KeyError, TypeError, AttributeError):
+        return 0
+
+
 class _Opts(ctypes.Structure):
     _fields_ = [("overlap", ctypes.c_int), ("boxes", ctypes.c_int * 3), ("precision", ctypes.c_int),
                 ("mode", ctypes.c_int), ("interp", ctypes.c_int), ("max_it", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("flexible", ctypes.c_int), ("stream", ctypes.c_void_p),
                 ("gemv_tiles", ctypes.c_int * GEMV_BUCKETS), ("projection", ctypes.c_int),
-                ("block_rhs", ctypes.c_int)]
+                ("whole_waves", ctypes.c_int), ("block_rhs", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -98,7 +109,8 @@ class _Info(ctypes.Structure):
                 ("a_bytes", ctypes.c_int64), ("inv_alg_bytes", ctypes.c_int64),
                 ("n_jent", ctypes.c_int64), ("n_inc_blocks", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("boxes", ctypes.c_int32 * 3), ("precision", ctypes.c_int32),
-                ("gemv_tiles", ctypes.c_int32 * GEMV_BUCKETS), ("reduced_stream", ctypes.c_int32)]
+                ("gemv_tiles", ctypes.c_int32 * GEMV_BUCKETS), ("whole_waves", ctypes.c_int32),
+                ("reduced_stream", ctypes.c_int32)]
 
 
 _lib = None
@@ -204,7 +216,7 @@ def _arrays(xyz, e2v, dirichlet, part, n_part):
 
 
 def _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible, stream, gemv_tiles=None,
-          projection=0, block_rhs=0):
+          projection=0, block_rhs=0, whole_waves=None):
     o = _Opts()
     load().coarse_default_opts(ctypes.byref(o))
     o.overlap = int(overlap)
@@ -226,6 +238,7 @@ def _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible
         o.gemv_tiles[b] = int(t[b])
     o.projection = int(projection)
     o.block_rhs = int(bool(block_rhs))
+    o.whole_waves = whole_waves_choice(precision) if whole_waves is None else int(whole_waves)
     return o
 
 
@@ -263,14 +276,14 @@ class Plan:
 
     def __init__(self, xyz, e2v, dirichlet, part=None, n_part=1, *, overlap=1, boxes=None,
                  precision="fp64", mode="additive", interp="centroid", max_it=1000, check_every=4,
-                 flexible=None, gemv_tiles=None, projection=0, block_rhs=0):
+                 flexible=None, gemv_tiles=None, projection=0, block_rhs=0, whole_waves=None):
         L = load()
         self._L = L
         self.n_vert = int(np.asarray(xyz).shape[0])
         self.precision = precision
         m, bc, keep = _arrays(xyz, e2v, dirichlet, part, n_part)
         o = _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible, None, gemv_tiles,
-                  projection, block_rhs)
+                  projection, block_rhs, whole_waves)
         pl = ctypes.c_void_p()
         rc = L.coarse_plan_create(ctypes.byref(m), ctypes.byref(bc), ctypes.byref(o), ctypes.byref(pl))
         if rc != 0:
@@ -310,7 +323,7 @@ class CoarseSolver:
 
     def __init__(self, xyz, e2v, dirichlet, part=None, n_part=1, *, overlap=1, boxes=None,
                  precision="fp64", mode="additive", interp="centroid", max_it=1000, check_every=4,
-                 flexible=None, gemv_tiles=None, projection=0, block_rhs=0):
+                 flexible=None, gemv_tiles=None, projection=0, block_rhs=0, whole_waves=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("CoarseSolver needs a GPU; no CPU fallback exists")
@@ -320,7 +333,7 @@ class CoarseSolver:
         self.precision = precision
         m, bc, keep = _arrays(xyz, e2v, dirichlet, part, n_part)
         o = _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible, _stream(), gemv_tiles,
-                  projection, block_rhs)
+                  projection, block_rhs, whole_waves)
         ctx = ctypes.c_void_p()
         rc = L.coarse_setup(ctypes.byref(m), ctypes.byref(bc), ctypes.byref(o), ctypes.byref(ctx))
         if rc != 0:

@@ -154,22 +154,32 @@ const int kGemvBucketMax[COARSE_GEMV_BUCKETS] = {2, 4, 8, 12, 16, 24, 48, 1 << 3
 inline unsigned nblk(int64_t n, int b) { return (unsigned)std::max<int64_t>(1, (n + b - 1) / b); }
 
 // The dense solves of one application: the whole-system workgroups (nwhole
-// systems, wsegs) and the work items (segs), in one launch when there are whole
-// systems; either may be empty.
-void launch_gemv(hipStream_t s, int precision, const Seg *segs, int nseg, int nitems, const Seg *wsegs, int nwhole,
-                 int whole_lds, const int *done) {
+// systems, wsegs, nw wavefronts each) and the work items (segs), in one launch
+// when there are whole systems; either may be empty.
+template <int NW>
+void launch_whole(hipStream_t s, int precision, const Seg *segs, int nseg, int nitems, const Seg *wsegs, int nwhole,
+                  int whole_lds, const int *done) {
+  const unsigned g = (unsigned)nwhole + (nitems > 0 ? nblk(nitems, NW) : 0u);
+  if (precision == COARSE_FP64)
+    hipLaunchKernelGGL(k_gemv_whole_f64<NW>, dim3(g), dim3(NW * WAVE), whole_lds, s, segs, nseg, nitems, wsegs,
+                       nwhole, done);
+  else if (precision == COARSE_MIXED_F16)
+    hipLaunchKernelGGL(k_gemv_whole_f16<NW>, dim3(g), dim3(NW * WAVE), whole_lds, s, segs, nseg, nitems, wsegs,
+                       nwhole, done);
+  else
+    hipLaunchKernelGGL(k_gemv_whole_f32<NW>, dim3(g), dim3(NW * WAVE), whole_lds, s, segs, nseg, nitems, wsegs,
+                       nwhole, done);
+}
+
+void launch_gemv(hipStream_t s, int precision, int nw, const Seg *segs, int nseg, int nitems, const Seg *wsegs,
+                 int nwhole, int whole_lds, const int *done) {
   if (nwhole > 0) {
-    const int nw = precision == COARSE_FP64 ? WHOLE_WAVES_F64 : WHOLE_WAVES_NARROW;
-    const unsigned g = (unsigned)nwhole + (nitems > 0 ? nblk(nitems, nw) : 0u);
-    if (precision == COARSE_FP64)
-      hipLaunchKernelGGL(k_gemv_whole_f64, dim3(g), dim3(nw * WAVE), whole_lds, s, segs, nseg, nitems, wsegs, nwhole,
-                         done);
-    else if (precision == COARSE_MIXED_F16)
-      hipLaunchKernelGGL(k_gemv_whole_f16, dim3(g), dim3(nw * WAVE), whole_lds, s, segs, nseg, nitems, wsegs, nwhole,
-                         done);
-    else
-      hipLaunchKernelGGL(k_gemv_whole_f32, dim3(g), dim3(nw * WAVE), whole_lds, s, segs, nseg, nitems, wsegs, nwhole,
-                         done);
+    switch (nw) {
+      case 2: launch_whole<2>(s, precision, segs, nseg, nitems, wsegs, nwhole, whole_lds, done); break;
+      case 8: launch_whole<8>(s, precision, segs, nseg, nitems, wsegs, nwhole, whole_lds, done); break;
+      case 16: launch_whole<16>(s, precision, segs, nseg, nitems, wsegs, nwhole, whole_lds, done); break;
+      default: launch_whole<4>(s, precision, segs, nseg, nitems, wsegs, nwhole, whole_lds, done); break;
+    }
   } else if (nitems > 0) {
     // one wavefront per work item (the kernel also loops over a smaller grid, but
     // one item per wavefront measured fastest on MI355X at every size tried)
@@ -181,6 +191,11 @@ void launch_gemv(hipStream_t s, int precision, const Seg *segs, int nseg, int ni
     else
       hipLaunchKernelGGL(k_gemv_f32, dim3(g), dim3(256), 0, s, segs, nseg, nitems, done);
   }
+}
+
+// Wavefronts per whole-system workgroup that a context may choose, per tile type
+inline bool whole_waves_ok(int precision, int nw) {
+  return precision == COARSE_FP64 ? (nw == 2 || nw == 4 || nw == 8) : (nw == 4 || nw == 8 || nw == 16);
 }
 
 }  // namespace
@@ -206,6 +221,7 @@ struct coarse_ctx {
   int32_t items_local = 0, items_total = 0, rows_local = 0, rows_total = 0;
   int32_t whole_local = 0, whole_total = 0;   // systems solved by one workgroup each
   int32_t whole_lds = 0;                      // LDS bytes of such a workgroup
+  int whole_waves = 4;                        // wavefronts of such a workgroup
   int nvblk = 1;
   double t_setup = 0.0;
   coarse_info_t info{};
@@ -380,7 +396,7 @@ struct coarse_ctx {
                     int ph_comb) {
     if (nitems <= 0 && nwhole <= 0) return;
     if (ph_gemv >= 0) pbeg(ph_gemv, s);
-    launch_gemv(s, precision, segs, 1, nitems, segs, nwhole, whole_lds, done);
+    launch_gemv(s, precision, whole_waves, segs, 1, nitems, segs, nwhole, whole_lds, done);
     if (ph_gemv >= 0) pend(ph_gemv, s);
     if (nrows <= 0) return;
     if (ph_comb >= 0) pbeg(ph_comb, s);
@@ -881,7 +897,7 @@ int64_t invert_systems(coarse_ctx *c, const std::vector<System> &sys, const std:
 
 // T: vectors, interpolation and partial sums; TT: the stored inverse tiles.
 template <typename T, typename TT>
-void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
+void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles, int whole_waves) {
   hipStream_t s = c->stream;
   Arena &A = c->arena;
   const int64_t NE = P.n_elem, NV = P.n_vert, nf = P.n_free;
@@ -1149,7 +1165,14 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
   c->rows_total = (int32_t)gr.size();
   c->whole_local = G.whole_local;
   c->whole_total = (int32_t)G.whole.size();
-  c->whole_lds = (sizeof(TT) == 8 ? WHOLE_WAVES_F64 : WHOLE_WAVES_NARROW) * G.whole_nb_max * TILE * (int32_t)sizeof(T);
+  // wavefronts per whole-system workgroup: the caller's choice or the default for
+  // the tile type, halved while one wavefront copy per wave of the largest such
+  // system would not fit the 64 KiB of LDS a workgroup may use
+  int nw = whole_waves_ok(c->precision, whole_waves) ? whole_waves
+                                                     : (sizeof(TT) == 8 ? WHOLE_WAVES_F64 : WHOLE_WAVES_NARROW);
+  while (nw > 2 && (int64_t)nw * G.whole_nb_max * TILE * (int64_t)sizeof(T) > 65536) nw /= 2;
+  c->whole_waves = nw;
+  c->whole_lds = nw * G.whole_nb_max * TILE * (int32_t)sizeof(T);
   c->h_seg_all = Seg{c->items, c->rows, c->whole, c->sysdev, nullptr, 0, 0};
   c->h_seg_local = c->h_seg_all;
   c->h_seg_coarse = Seg{c->items + il, c->rows + rl, c->whole + c->whole_local, c->sysdev, nullptr, 0, 0};
@@ -1208,6 +1231,7 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles) {
   in.precision = c->precision;
   for (int b = 0; b < COARSE_GEMV_BUCKETS; ++b) in.gemv_tiles[b] = c->gemv_tiles[b];
   in.reduced_stream = c->reduced_aside ? 1 : 0;
+  in.whole_waves = c->whole_waves;
 }
 
 coarse_ctx *as_ctx(const coarse_ctx *c) { return const_cast<coarse_ctx *>(c); }
@@ -1256,9 +1280,10 @@ struct coarse_batch {
     int64_t tag;
     double t0;
     hipStream_t saved_stream;
+    int nproj;   // prior solutions its initial guess was projected on
   };
   std::vector<Entry> live;
-  int precision = -1;
+  int precision = -1, whole_waves = 4;
   bool dirty = true, use_graph = false;
   Seg *d_seg = nullptr;      // [3][cap]: item, row and whole-system segments
   Seg *h_seg = nullptr;      // pinned staging
@@ -1339,18 +1364,26 @@ struct coarse_batch {
       err = "all solves of a batch share one precision";
       return COARSE_EINVAL;
     }
+    if (!live.empty() && c->whole_waves != whole_waves) {
+      err = "all solves of a batch share one whole-system wavefront count";
+      return COARSE_EINVAL;
+    }
     for (auto &e : live)
       if (e.c == c) {
         err = "context already in the batch";
         return COARSE_EINVAL;
       }
     precision = c->precision;
+    whole_waves = c->whole_waves;
     c->prof_mask = 0;   // no per-phase events inside lock steps (they may be captured)
-    Entry e{c, b, u, tag, now(), c->stream};
+    Entry e{c, b, u, tag, now(), c->stream, c->proj_max > 0 ? c->proj_n : 0};
     // every launch of a batched solve goes to the batch's stream, so the start
     // is ordered before the lock steps (also when they are a replayed graph)
     c->stream = main;
-    c->start(b, 1.0 * tol);
+    // a context set up with a projection basis starts from the projection onto
+    // its prior solutions (Sec. 5), as coarse_solve_projected does
+    const int nproj = c->proj_max > 0 ? c->proj_n : 0;
+    c->start(b, 1.0 * tol, nproj);
     live.push_back(e);
     dirty = true;
     return COARSE_OK;
@@ -1418,7 +1451,7 @@ struct coarse_batch {
     hipLaunchKernelGGL(k_pre_grp<T>, dim3(grid[G_PRE]), dim3(256), 0, main, (const IterDev *)d_iter, off + 2 * L, n);
     hipLaunchKernelGGL(k_jt_corners_grp<T>, dim3(grid[G_COR]), dim3(256), 0, main, (const IterDev *)d_iter,
                        off + 3 * L, n);
-    launch_gemv(main, precision, d_seg, n, n_items, d_seg + 2 * cap, n_whole, whole_lds, nullptr);
+    launch_gemv(main, precision, whole_waves, d_seg, n, n_items, d_seg + 2 * cap, n_whole, whole_lds, nullptr);
     if (n_rows > 0)
       hipLaunchKernelGGL(k_combine<T>, dim3(nblk((int64_t)n_rows * TILE, 256)), dim3(256), 0, main,
                          (const Seg *)(d_seg + cap), n, n_rows, (const int *)nullptr);
@@ -1476,12 +1509,21 @@ struct coarse_batch {
     std::vector<Entry> fin;
     for (auto &e : live) ((e.c->h_sc->done && (int)fin.size() < capn) ? fin : keep).push_back(e);
     if (fin.empty()) return COARSE_OK;
-    for (auto &e : fin) e.c->finish(e.u);
+    for (auto &e : fin) {
+      e.c->finish(e.u);
+      // the solution joins the basis of a context that keeps one (a full basis
+      // starts again from it)
+      if (e.c->proj_max > 0) e.c->proj_append(e.c->proj_n >= e.c->proj_max ? 0 : e.c->proj_n);
+    }
     HIPCHK(hipStreamSynchronize(main));
     for (auto &e : fin) {
       e.c->last_iters = e.c->h_sc->iters;
+      if (e.c->proj_max > 0) e.c->proj_n = *e.c->h_proj_count;
       if (tags) tags[*n_done] = e.tag;
-      if (stats) e.c->fill_stats(&stats[*n_done], e.t0);
+      if (stats) {
+        e.c->fill_stats(&stats[*n_done], e.t0);
+        stats[*n_done].n_basis = e.nproj;
+      }
       ++*n_done;
       e.c->stream = e.saved_stream;
     }
@@ -1644,6 +1686,10 @@ int coarse_plan_create(const coarse_mesh *mesh, const coarse_bc *bc, const coars
     g_setup_error = "bad mode, max_it or check_every";
     return COARSE_EINVAL;
   }
+  if (o.whole_waves != 0 && !whole_waves_ok(o.precision, o.whole_waves)) {
+    g_setup_error = "whole_waves must be 0, or 2, 4 or 8 for FP64 tiles and 4, 8 or 16 for FP32/FP16 tiles";
+    return COARSE_EINVAL;
+  }
   if (o.projection < 0 || o.projection > COARSE_PROJECTION_MAX) {
     g_setup_error = "projection must be in [0, COARSE_PROJECTION_MAX]";
     return COARSE_EINVAL;
@@ -1723,11 +1769,11 @@ int coarse_setup_from_plan(const coarse_plan *plan, void *stream, coarse_ctx **o
     HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     c->h_sc = (Scalars *)g_pinned.get(sizeof(Scalars));
     if (o.precision == COARSE_FP64)
-      setup_precision<double, double>(c.get(), P, o.gemv_tiles);
+      setup_precision<double, double>(c.get(), P, o.gemv_tiles, o.whole_waves);
     else if (o.precision == COARSE_MIXED)
-      setup_precision<float, float>(c.get(), P, o.gemv_tiles);
+      setup_precision<float, float>(c.get(), P, o.gemv_tiles, o.whole_waves);
     else
-      setup_precision<float, _Float16>(c.get(), P, o.gemv_tiles);
+      setup_precision<float, _Float16>(c.get(), P, o.gemv_tiles, o.whole_waves);
   } catch (const Fail &f) {
     g_setup_error = f.what();
     (void)hipStreamSynchronize(c->stream);

@@ -896,9 +896,9 @@ __device__ __forceinline__ float4 ldnt(const float4 *p) {
 }
 
 // Whole systems (nb <= WHOLE_NB_MAX): one workgroup of NW wavefronts per system
-// (WHOLE_WAVES_F64 for FP64 tiles, WHOLE_WAVES_NARROW for the smaller FP32/FP16
-// tiles, so that a workgroup keeps as many bytes in flight), launched ahead of the
-// work items in the same grid. Wavefront w owns the
+// (the context's choice, by default WHOLE_WAVES_F64 for FP64 tiles and
+// WHOLE_WAVES_NARROW for the smaller FP32/FP16 tiles, so that a workgroup keeps
+// as many bytes in flight), launched ahead of the work items in the same grid. Wavefront w owns the
 // tile rows dealt to it in a snake order over the rows from longest to shortest
 // (so the waves hold nearly equal tile counts) and streams their tiles back to
 // back, the next one (across a row boundary too) loaded while the current one is
@@ -950,8 +950,8 @@ __device__ __forceinline__ A *whole_begin(const SysDev &S, A *ys) {
 }
 
 // FP64 tiles: lane layout of k_gemv_f64 below.
+template <int NW>
 __device__ __forceinline__ void whole_f64(const SysDev &S, double *ys) {
-  constexpr int NW = WHOLE_WAVES_F64;
   double *y = whole_begin<NW>(S, ys);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int grp = lane >> 4, c2 = (lane & 15) * 2;
@@ -1115,26 +1115,26 @@ __global__ __launch_bounds__(256) void k_gemv_f64(const Seg *__restrict__ segs, 
 }
 
 // Workgroups [0, nwhole) solve whole systems (wsegs: begin offsets in systems),
-// the others take the work items (segs), WHOLE_WAVES_F64 per workgroup.
-__global__ __launch_bounds__(WHOLE_WAVES_F64 * WAVE) void k_gemv_whole_f64(const Seg *__restrict__ segs, int nseg,
-                                                                 int total, const Seg *__restrict__ wsegs,
-                                                                 int nwhole, const int *__restrict__ done) {
+// the others take the work items (segs), NW wavefronts per workgroup.
+template <int NW>
+__global__ __launch_bounds__(NW * WAVE) void k_gemv_whole_f64(const Seg *__restrict__ segs, int nseg, int total,
+                                                              const Seg *__restrict__ wsegs, int nwhole,
+                                                              const int *__restrict__ done) {
   extern __shared__ double ys_whole_d[];
   if (done && *done) return;
   if ((int)blockIdx.x < nwhole) {
     const Seg &sg = seg_of(wsegs, nseg, blockIdx.x);
     if (sg.done && *sg.done) return;
-    whole_f64(sg.sys[sg.whole[blockIdx.x - sg.begin]], ys_whole_d);
+    whole_f64<NW>(sg.sys[sg.whole[blockIdx.x - sg.begin]], ys_whole_d);
     return;
   }
-  items_f64(segs, nseg, total, (blockIdx.x - nwhole) * WHOLE_WAVES_F64 + (threadIdx.x >> 6),
-            (gridDim.x - nwhole) * WHOLE_WAVES_F64);
+  items_f64(segs, nseg, total, (blockIdx.x - nwhole) * NW + (threadIdx.x >> 6), (gridDim.x - nwhole) * NW);
 }
 
 // FP32: 4 loads of 16 bytes per lane per tile; lane l holds rows 8m + l/8 (m < 4),
 // columns 4(l%8) .. 4(l%8)+3.
+template <int NW>
 __device__ __forceinline__ void whole_f32(const SysDev &S, float *ys) {
-  constexpr int NW = WHOLE_WAVES_NARROW;
   float *y = whole_begin<NW>(S, ys);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int grp = lane >> 3, c4 = (lane & 7) * 4;
@@ -1296,8 +1296,9 @@ __global__ __launch_bounds__(256) void k_gemv_f32(const Seg *__restrict__ segs, 
 }
 
 // Workgroups [0, nwhole) solve whole systems (wsegs: begin offsets in systems),
-// the others take the work items (segs), WHOLE_WAVES_NARROW per workgroup.
-__global__ __launch_bounds__(WHOLE_WAVES_NARROW * WAVE) void k_gemv_whole_f32(const Seg *__restrict__ segs, int nseg,
+// the others take the work items (segs), NW wavefronts per workgroup.
+template <int NW>
+__global__ __launch_bounds__(NW * WAVE) void k_gemv_whole_f32(const Seg *__restrict__ segs, int nseg,
                                                                  int total, const Seg *__restrict__ wsegs,
                                                                  int nwhole, const int *__restrict__ done) {
   extern __shared__ float ys_whole[];
@@ -1305,11 +1306,11 @@ __global__ __launch_bounds__(WHOLE_WAVES_NARROW * WAVE) void k_gemv_whole_f32(co
   if ((int)blockIdx.x < nwhole) {
     const Seg &sg = seg_of(wsegs, nseg, blockIdx.x);
     if (sg.done && *sg.done) return;
-    whole_f32(sg.sys[sg.whole[blockIdx.x - sg.begin]], ys_whole);
+    whole_f32<NW>(sg.sys[sg.whole[blockIdx.x - sg.begin]], ys_whole);
     return;
   }
-  items_f32(segs, nseg, total, (blockIdx.x - nwhole) * WHOLE_WAVES_NARROW + (threadIdx.x >> 6),
-            (gridDim.x - nwhole) * WHOLE_WAVES_NARROW);
+  items_f32(segs, nseg, total, (blockIdx.x - nwhole) * NW + (threadIdx.x >> 6),
+            (gridDim.x - nwhole) * NW);
 }
 
 // FP16 tiles (the inverse divided by a power-of-two scale per system, so every
@@ -1336,8 +1337,8 @@ __device__ __forceinline__ float quad_sum(float v) {
 // so the transposed contribution is kept per lane down the whole strip (summed
 // across lanes once per strip) and the per-tile cross-lane work is the short row
 // sum. The waves take the strips, longest first, in the snake order.
+template <int NW>
 __device__ __forceinline__ void whole_f16(const SysDev &S, float *ys) {
-  constexpr int NW = WHOLE_WAVES_NARROW;
   float *y = whole_begin<NW>(S, ys);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int grp = lane >> 2, c8 = (lane & 3) * 8;
@@ -1518,8 +1519,9 @@ __global__ __launch_bounds__(256) void k_gemv_f16(const Seg *__restrict__ segs, 
 }
 
 // Workgroups [0, nwhole) solve whole systems (wsegs: begin offsets in systems),
-// the others take the work items (segs), WHOLE_WAVES_NARROW per workgroup.
-__global__ __launch_bounds__(WHOLE_WAVES_NARROW * WAVE) void k_gemv_whole_f16(const Seg *__restrict__ segs, int nseg,
+// the others take the work items (segs), NW wavefronts per workgroup.
+template <int NW>
+__global__ __launch_bounds__(NW * WAVE) void k_gemv_whole_f16(const Seg *__restrict__ segs, int nseg,
                                                                  int total, const Seg *__restrict__ wsegs,
                                                                  int nwhole, const int *__restrict__ done) {
   extern __shared__ float ys_whole[];
@@ -1527,11 +1529,11 @@ __global__ __launch_bounds__(WHOLE_WAVES_NARROW * WAVE) void k_gemv_whole_f16(co
   if ((int)blockIdx.x < nwhole) {
     const Seg &sg = seg_of(wsegs, nseg, blockIdx.x);
     if (sg.done && *sg.done) return;
-    whole_f16(sg.sys[sg.whole[blockIdx.x - sg.begin]], ys_whole);
+    whole_f16<NW>(sg.sys[sg.whole[blockIdx.x - sg.begin]], ys_whole);
     return;
   }
-  items_f16(segs, nseg, total, (blockIdx.x - nwhole) * WHOLE_WAVES_NARROW + (threadIdx.x >> 6),
-            (gridDim.x - nwhole) * WHOLE_WAVES_NARROW);
+  items_f16(segs, nseg, total, (blockIdx.x - nwhole) * NW + (threadIdx.x >> 6),
+            (gridDim.x - nwhole) * NW);
 }
 
 // z_s[I*TILE + c] = sum of the row partials of tile row I + sum over I' > I of

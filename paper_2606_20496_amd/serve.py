@@ -127,7 +127,7 @@ class Server:
         self.busy = set()                        # keys with a live solve
         self.planning = {}                       # key -> Future of a Plan (host only)
         self.ready = {}                          # key -> (Plan, estimated bytes)
-        self.max_plans = 2 * plan_workers        # plans held on the host at once
+        self.max_plans = 3 * plan_workers        # plans held on the host at once
         self.used = 0                            # sum of acct over the resident contexts
         self.acct = {}                           # key -> device bytes counted for its context
         self.estimate_ratio_max = 0.0            # largest device_bytes / estimate_bytes seen

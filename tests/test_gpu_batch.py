@@ -206,3 +206,38 @@ def test_batch_workload_against_oracle():
             assert np.linalg.norm(u - uo) <= tol_u * np.linalg.norm(uo), (precision, k)
         for S in solvers:
             S.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_warm_start_equals_projected_solo(precision):
+    # contexts set up with a projection basis start batched solves from the
+    # projection onto their prior solutions (Sec. 5) and take in each retired
+    # solution: a sequence of batched solves per context equals, bit for bit,
+    # the same sequence of coarse_solve_projected calls on a twin context
+    ms = _meshes(3)
+    seqs = [mg.rhs_sequence(m, 31 + k, 5) for k, m in enumerate(ms)]
+    twins = [coarse.CoarseSolver.from_mesh(m, precision=precision, projection=3) for m in ms]
+    solvers = [coarse.CoarseSolver.from_mesh(m, precision=precision, projection=3) for m in ms]
+    stream = torch.cuda.Stream()
+    bt = coarse.Batch(stream=stream, use_graph=True)
+    for step in range(5):
+        with torch.cuda.stream(stream):
+            bs = [torch.tensor(seqs[k][step], device="cuda") for k in range(len(ms))]
+            us = [torch.zeros_like(b) for b in bs]
+        stream.synchronize()
+        for k in range(len(ms)):
+            bt.submit(solvers[k], bs[k], us[k], tag=k)
+        done = {}
+        while bt.live > 0:
+            for tag, st in bt.step(2):
+                done[tag] = st
+        stream.synchronize()
+        for k in range(len(ms)):
+            u1, s1 = twins[k].solve_projected(torch.tensor(seqs[k][step], device="cuda"), 1e-8)
+            assert done[k]["iters"] == s1["iters"] and done[k]["n_basis"] == s1["n_basis"], (step, k)
+            assert torch.equal(us[k], u1), (step, k)
+            if step > 0:
+                assert s1["n_basis"] >= 1
+    bt.close()
+    for S in solvers + twins:
+        S.close()

@@ -374,3 +374,26 @@ def test_leftover_reduced_system():
     S16 = coarse.CoarseSolver.from_mesh(m, precision="mixed16")
     u16, st16 = S16.solve(_gpu(m.b), tol=1e-8)
     assert st16["code"] == 0 and st16["relres_true"] <= 1.05e-8
+
+
+@pytest.mark.timeout(900)
+def test_whole_waves_change_rounding_only(cube64):
+    # the wavefront count of the whole-system workgroups (a tuned choice) changes
+    # only the order of rounding: every choice meets the 1e-12 preconditioner bar
+    # and the oracle's iteration count
+    m, P, uo, io = cube64
+    r = np.random.default_rng(17).standard_normal(m.n_vert)
+    zo = P.apply_precond(r)
+    for precision, waves in (("fp64", (2, 4, 8)), ("mixed16", (4, 8, 16))):
+        for w in waves:
+            S = coarse.CoarseSolver.from_mesh(m, precision=precision, whole_waves=w)
+            assert S.info["whole_waves"] == w
+            z = _np(S.apply_precond(_gpu(r)))
+            u, st = S.solve(_gpu(m.b), tol=1e-8)
+            S.close()
+            if precision == "fp64":
+                assert _rel(z, zo) < 1e-12, w
+                assert st["iters"] == io["iters"], w
+            else:
+                assert _rel(z, zo) < MIXED_PRECOND_BAR["mixed16"], w
+                assert st["iters"] <= math.ceil(1.1 * io["iters"]), w
