@@ -158,6 +158,20 @@ typedef struct {
                        (coarse_solve_multi, about 9 * 16 doubles per free vertex),
                        so that no later call on the context allocates; 0 (default):
                        the first block-solve call allocates them                   */
+  int local_iters;  /* 0 (default): exact local solves with the stored inverses
+                       A_p^{-1} (Sec. 3, eq. (asm)). k > 0: inexact local solves
+                       (the iterative local solver of Sec. 6.3): each r_p is solved
+                       by k steps of conjugate gradients preconditioned by the
+                       diagonal of A_p, from zero; A_p is stored sparse (ELL) and no
+                       local inverse is formed. The preconditioner then depends
+                       on r nonlinearly, so the flexible beta is used whatever
+                       opts.flexible says. Needs every |R_p| <= 1024 and at most 26
+                       off-diagonal entries per row of A_p (the 27-point coupling
+                       of a vertex inside a structured hex block; else
+                       COARSE_EINVAL at setup). Single solves only
+                       (coarse_solve, coarse_solve_projected,
+                       coarse_apply_precond): block solves and lock-step batches
+                       reject such a context (COARSE_EINVAL)                      */
 } coarse_opts;
 
 typedef struct {
@@ -200,6 +214,11 @@ typedef struct {
                              32, and the additive preconditioner solves it on a
                              second stream beside the local systems (profile
                              phase 7); 0: one dense-solve launch holds both     */
+  int32_t local_iters;    /* opts.local_iters of the context (0: exact solves)    */
+  int32_t ell_width;      /* inexact local solves: off-diagonal entries stored per
+                             row of A_p (even; the largest row count rounded up);
+                             local_bytes then counts the stored A_p (ELL entries
+                             and diagonals), not inverses                         */
 } coarse_info_t;
 
 /* Fill *o with the defaults: overlap 1, boxes auto, FP64, additive, centroid J,

@@ -93,7 +93,7 @@ class _Opts(ctypes.Structure):
                 ("mode", ctypes.c_int), ("interp", ctypes.c_int), ("max_it", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("flexible", ctypes.c_int), ("stream", ctypes.c_void_p),
                 ("gemv_tiles", ctypes.c_int * GEMV_BUCKETS), ("projection", ctypes.c_int),
-                ("whole_waves", ctypes.c_int), ("block_rhs", ctypes.c_int)]
+                ("whole_waves", ctypes.c_int), ("block_rhs", ctypes.c_int), ("local_iters", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -110,7 +110,8 @@ class _Info(ctypes.Structure):
                 ("n_jent", ctypes.c_int64), ("n_inc_blocks", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("boxes", ctypes.c_int32 * 3), ("precision", ctypes.c_int32),
                 ("gemv_tiles", ctypes.c_int32 * GEMV_BUCKETS), ("whole_waves", ctypes.c_int32),
-                ("reduced_stream", ctypes.c_int32)]
+                ("reduced_stream", ctypes.c_int32), ("local_iters", ctypes.c_int32),
+                ("ell_width", ctypes.c_int32)]
 
 
 _lib = None
@@ -216,7 +217,7 @@ def _arrays(xyz, e2v, dirichlet, part, n_part):
 
 
 def _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible, stream, gemv_tiles=None,
-          projection=0, block_rhs=0, whole_waves=None):
+          projection=0, block_rhs=0, whole_waves=None, local_iters=0):
     o = _Opts()
     load().coarse_default_opts(ctypes.byref(o))
     o.overlap = int(overlap)
@@ -228,7 +229,7 @@ def _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible
     o.max_it = int(max_it)
     o.check_every = int(check_every)
     if flexible is None:
-        flexible = precision in ("mixed", "mixed16") or mode == "hybrid"
+        flexible = precision in ("mixed", "mixed16") or mode == "hybrid" or local_iters > 0
     o.flexible = int(bool(flexible))
     o.stream = stream
     t = gemv_table(precision) if gemv_tiles is None else list(gemv_tiles)
@@ -239,6 +240,7 @@ def _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible
     o.projection = int(projection)
     o.block_rhs = int(bool(block_rhs))
     o.whole_waves = whole_waves_choice(precision) if whole_waves is None else int(whole_waves)
+    o.local_iters = int(local_iters)
     return o
 
 
@@ -276,14 +278,14 @@ class Plan:
 
     def __init__(self, xyz, e2v, dirichlet, part=None, n_part=1, *, overlap=1, boxes=None,
                  precision="fp64", mode="additive", interp="centroid", max_it=1000, check_every=4,
-                 flexible=None, gemv_tiles=None, projection=0, block_rhs=0, whole_waves=None):
+                 flexible=None, gemv_tiles=None, projection=0, block_rhs=0, whole_waves=None, local_iters=0):
         L = load()
         self._L = L
         self.n_vert = int(np.asarray(xyz).shape[0])
         self.precision = precision
         m, bc, keep = _arrays(xyz, e2v, dirichlet, part, n_part)
         o = _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible, None, gemv_tiles,
-                  projection, block_rhs, whole_waves)
+                  projection, block_rhs, whole_waves, local_iters)
         pl = ctypes.c_void_p()
         rc = L.coarse_plan_create(ctypes.byref(m), ctypes.byref(bc), ctypes.byref(o), ctypes.byref(pl))
         if rc != 0:
@@ -323,7 +325,7 @@ class CoarseSolver:
 
     def __init__(self, xyz, e2v, dirichlet, part=None, n_part=1, *, overlap=1, boxes=None,
                  precision="fp64", mode="additive", interp="centroid", max_it=1000, check_every=4,
-                 flexible=None, gemv_tiles=None, projection=0, block_rhs=0, whole_waves=None):
+                 flexible=None, gemv_tiles=None, projection=0, block_rhs=0, whole_waves=None, local_iters=0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("CoarseSolver needs a GPU; no CPU fallback exists")
@@ -333,7 +335,7 @@ class CoarseSolver:
         self.precision = precision
         m, bc, keep = _arrays(xyz, e2v, dirichlet, part, n_part)
         o = _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible, _stream(), gemv_tiles,
-                  projection, block_rhs, whole_waves)
+                  projection, block_rhs, whole_waves, local_iters)
         ctx = ctypes.c_void_p()
         rc = L.coarse_setup(ctypes.byref(m), ctypes.byref(bc), ctypes.byref(o), ctypes.byref(ctx))
         if rc != 0:

@@ -2,6 +2,7 @@
 // PCG, orchestrating the kernels of kernels.hip on one HIP stream.
 #include "kernels.hip"
 #include "multi.hip"
+#include "local_pcg.hip"
 #include "capture_guard.h"
 
 #include <algorithm>
@@ -263,6 +264,14 @@ struct coarse_ctx {
   int32_t *cover_ptr = nullptr, *cover_pos = nullptr;
   int y_lds = 0;   // the final kernel stages the reduced solution (n_bv doubles) in LDS
 
+  // inexact local solves (local_iters > 0): A_p in ELL form, one workgroup of
+  // loc_nt threads per subdomain
+  int local_iters = 0, loc_w = 0, loc_nt = 0;
+  LocSys *locsys = nullptr;
+  double *loc_diag = nullptr;
+  uint32_t *loc_col = nullptr;
+  void *loc_val = nullptr;
+
   // reduced space
   int32_t *jv_ptr = nullptr, *jv_occ = nullptr, *jc_vid = nullptr, *jt_start = nullptr, *jr_ptr = nullptr,
           *jr_src = nullptr, *corner_act = nullptr;
@@ -412,6 +421,27 @@ struct coarse_ctx {
     gemv_combine(segs, nitems, nrows, nwhole, done, stream, 3, 4);
   }
 
+  // the local solves of one application on the context's stream: the stored
+  // inverses, or local_iters steps of Jacobi-PCG per subdomain (phase 3 either way)
+  template <typename T>
+  void local_part(const int *done) {
+    if (local_iters <= 0) {
+      gemv_combine(seg_local, items_local, rows_local, whole_local, done);
+      return;
+    }
+    if (n_local_sys <= 0) return;
+    pbeg(3);
+    if (precision == COARSE_FP64)
+      hipLaunchKernelGGL((k_local_pcg<double, T>), dim3((unsigned)n_local_sys), dim3(loc_nt), 0, stream, locsys, loc_w,
+                         local_iters, done, (const T *)rp, (const double *)loc_diag, (const uint32_t *)loc_col,
+                         (const double *)loc_val, zp);
+    else
+      hipLaunchKernelGGL((k_local_pcg<float, T>), dim3((unsigned)n_local_sys), dim3(loc_nt), 0, stream, locsys, loc_w,
+                         local_iters, done, (const T *)rp, (const double *)loc_diag, (const uint32_t *)loc_col,
+                         (const float *)loc_val, zp);
+    pend(3);
+  }
+
   // scal: count the iteration in the solver state (PCG); start: first application
   template <typename T>
   void final_step(const double *add, bool local, bool coarse, double *out, const double *rdot, double *p1, double *p2,
@@ -438,7 +468,7 @@ struct coarse_ctx {
                          (int)ntask, jt_start, jc_vid, (const T *)jc_w, (const T *)jc_xi, nent, (T *)jt_part,
                          chk ? sc : nullptr, chk, nvblk, start);
       pend(1);
-      if (!reduced_aside) {
+      if (!reduced_aside && local_iters <= 0) {
         // a reduced system of at most WHOLE_NB_MAX tile rows joins the local
         // systems in one dense-solve launch
         pbeg(2);
@@ -449,11 +479,12 @@ struct coarse_ctx {
         return;
       }
       // the reduced-space branch (J^T corner sums, the dense solve of A_r and its
-      // partial sums) on the second stream, beside the local dense solves; the
-      // two meet before the overlap sum. Across hardware queues each of the two
+      // partial sums) on the second stream, beside the local solves; the two
+      // meet before the overlap sum. Across hardware queues each of the two
       // waits costs some microseconds, which a large reduced system (its long
       // tile rows end the fused launch late, and its partial sums need a combine
-      // pass) repays and a small one does not.
+      // pass) repays and a small one does not. Inexact local solves have a
+      // launch of their own, so the reduced branch always runs beside them.
       HIPCHK(hipEventRecord(ev_fork, stream));
       HIPCHK(hipStreamWaitEvent(aux, ev_fork, 0));
       pbeg(7, aux);
@@ -462,7 +493,7 @@ struct coarse_ctx {
                    -1, -1);
       pend(7, aux);
       HIPCHK(hipEventRecord(ev_join, aux));
-      gemv_combine(seg_local, items_local, rows_local, whole_local, done);
+      local_part<T>(done);
       HIPCHK(hipStreamWaitEvent(stream, ev_join, 0));
     } else {
       if (chk) hipLaunchKernelGGL(k_check, dim3(1), dim3(256), 0, stream, sc, chk, nvblk, start);
@@ -475,7 +506,7 @@ struct coarse_ctx {
       if (coarse) restrict_coarse<T>(in, done);
     }
     if (local && !coarse)
-      gemv_combine(seg_local, items_local, rows_local, whole_local, done);
+      local_part<T>(done);
     else if (coarse && !local)
       gemv_combine(seg_coarse, items_total - items_local, rows_total - rows_local, whole_total - whole_local, done);
     final_step<T>(add, local, coarse, out, rdot, p1, p2, done, scal, start);
@@ -982,21 +1013,31 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles, int wh
   HIPCHK(hipMemsetAsync(c->rp, 0, P.vec_len * sizeof(T), s));
   c->zp = A.alloc<double>(P.vec_len);
   HIPCHK(hipMemsetAsync(c->zp, 0, P.vec_len * sizeof(double), s));
-  TT *tiles = A.alloc<TT>((size_t)P.n_tiles * TILE * TILE);
+  // with inexact local solves only the reduced system has an inverse: its tiles
+  // start the store and the dense-solve tables leave the local systems out
+  const bool inexact = c->local_iters > 0;
+  std::vector<System> sysv = P.sys;
+  int64_t n_tiles = P.n_tiles;
+  if (inexact) {
+    for (int64_t k = 0; k < P.n_local_sys; ++k) sysv[k].tile_off = 0;
+    n_tiles -= P.sys[P.n_local_sys].tile_off;
+    sysv[P.n_local_sys].tile_off = 0;
+  }
+  TT *tiles = A.alloc<TT>((size_t)n_tiles * TILE * TILE);
   std::vector<float> sys_scale(P.sys.size(), 1.0f);
   c->tiles = tiles;
   GemvTable G;
   int dev = 0, n_cu = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-  build_gemv_items(P, gemv_tiles, kGemvBucketMax, COARSE_GEMV_BUCKETS, n_cu, G);
+  build_gemv_items(P, gemv_tiles, kGemvBucketMax, COARSE_GEMV_BUCKETS, n_cu, G, inexact ? P.n_local_sys : 0);
   // transposed partials only for the systems cut into work items
   std::vector<int64_t> colpart_off(P.sys.size(), -1);
   int64_t ncolpart = 0;
   {
     std::vector<char> is_whole(P.sys.size(), 0);
     for (int32_t k : G.whole) is_whole[k] = 1;
-    for (size_t k = 0; k < P.sys.size(); ++k)
+    for (size_t k = inexact ? (size_t)P.n_local_sys : 0; k < P.sys.size(); ++k)
       if (!is_whole[k]) {
         colpart_off[k] = ncolpart;
         ncolpart += P.sys[k].nb * (P.sys[k].nb + 1) / 2;
@@ -1008,17 +1049,74 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles, int wh
   c->cover_ptr = A.upload(P.cover_ptr, s);
   c->cover_pos = A.upload(P.cover_pos, s);
 
-  // inverses of the local systems (dense assembly of A_p) ...
+  // inverses of the local systems (dense assembly of A_p), or A_p itself in
+  // ELL form for the inexact local solves ...
   const size_t scratch_tiles = (size_t)(1536ull << 20) / (TILE * TILE * sizeof(double));
-  std::vector<int64_t> loc(P.n_local_sys);
-  for (int64_t k = 0; k < P.n_local_sys; ++k) loc[k] = k;
   int32_t *vinc_ptr = tmp.upload(P.vinc_ptr, s);
   int32_t *vinc = tmp.upload(P.vinc, s);
-  int64_t nbad = invert_systems<TT>(c, P.sys, loc, tiles, scratch_tiles, sys_scale, [&](AsmSys *das, int ns, double *M) {
-    hipLaunchKernelGGL(k_assemble_local, dim3((unsigned)ns), dim3(256), 0, s, das, c->sub_idx, vinc_ptr, vinc, e2v, NE,
-                       nf, (const double *)Ae, M);
-  });
-  if (nbad) throw Fail(COARSE_ESINGULAR, std::to_string(nbad) + " local system(s) A_p not positive definite");
+  int64_t nbad = 0;
+  int64_t ell_entries = 0;
+  if (inexact) {
+    using V = typename std::conditional<std::is_same<TT, double>::value, double, float>::type;
+    std::vector<LocSys> ls((size_t)P.n_local_sys);
+    int64_t maxn = 0;
+    for (int64_t k = 0; k < P.n_local_sys; ++k) {
+      ls[k].vec_off = (int32_t)P.sys[k].vec_off;
+      ls[k].n = (int32_t)P.sys[k].n;
+      ls[k].npad = (int32_t)((P.sys[k].n + 31) / 32 * 32);
+      ls[k].pad = 0;
+      maxn = std::max<int64_t>(maxn, P.sys[k].n);
+    }
+    if (maxn > LOC_NT_MAX)
+      throw Fail(COARSE_EINVAL, "inexact local solves need subdomains of at most " + std::to_string(LOC_NT_MAX) +
+                                    " free vertices (largest: " + std::to_string(maxn) + ")");
+    LocSys *dls = tmp.upload(ls, s);
+    int *wmax = tmp.alloc<int>(1);
+    HIPCHK(hipMemsetAsync(wmax, 0, sizeof(int), s));
+    if (P.n_local_sys > 0)
+      hipLaunchKernelGGL(k_loc_count, dim3((unsigned)P.n_local_sys), dim3(256), 0, s, (const LocSys *)dls,
+                         (const int32_t *)c->sub_idx, (const int32_t *)vinc_ptr, (const int32_t *)vinc,
+                         (const int32_t *)e2v, NE, nf, wmax);
+    int hw = 0;
+    HIPCHK(hipMemcpyAsync(&hw, wmax, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hw > LOC_WMAX)
+      throw Fail(COARSE_EINVAL, "inexact local solves need at most " + std::to_string(LOC_WMAX) +
+                                    " off-diagonal entries per row of A_p");
+    const int W = (hw + 1) / 2 * 2;
+    for (int64_t k = 0; k < P.n_local_sys; ++k) {
+      ls[k].ell_off = ell_entries;
+      ell_entries += (int64_t)W * ls[k].npad;
+    }
+    c->locsys = A.upload(ls, s);
+    c->loc_w = W;
+    c->loc_nt = (int)std::max<int64_t>(WAVE, (maxn + WAVE - 1) / WAVE * WAVE);
+    c->loc_diag = A.alloc<double>(std::max<int64_t>(1, c->coarse_vec_off));
+    c->loc_col = A.alloc<uint32_t>(std::max<int64_t>(1, ell_entries / 2));
+    V *val = A.alloc<V>(std::max<int64_t>(1, ell_entries));
+    c->loc_val = val;
+    HIPCHK(hipMemsetAsync(c->loc_diag, 0, std::max<int64_t>(1, c->coarse_vec_off) * sizeof(double), s));
+    HIPCHK(hipMemsetAsync(c->loc_col, 0, std::max<int64_t>(1, ell_entries / 2) * sizeof(uint32_t), s));
+    HIPCHK(hipMemsetAsync(val, 0, std::max<int64_t>(1, ell_entries) * sizeof(V), s));
+    int *lbad = tmp.alloc<int>(1);
+    HIPCHK(hipMemsetAsync(lbad, 0, sizeof(int), s));
+    if (P.n_local_sys > 0)
+      hipLaunchKernelGGL(k_loc_fill<V>, dim3((unsigned)P.n_local_sys), dim3(256), 0, s, (const LocSys *)c->locsys, W,
+                         (const int32_t *)c->sub_idx, (const int32_t *)vinc_ptr, (const int32_t *)vinc,
+                         (const int32_t *)e2v, NE, nf, (const double *)Ae, c->loc_diag, c->loc_col, val, lbad);
+    int hb = 0;
+    HIPCHK(hipMemcpyAsync(&hb, lbad, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hb) throw Fail(COARSE_ESINGULAR, std::to_string(hb) + " row(s) of a local A_p with a non-positive diagonal");
+  } else {
+    std::vector<int64_t> loc(P.n_local_sys);
+    for (int64_t k = 0; k < P.n_local_sys; ++k) loc[k] = k;
+    nbad = invert_systems<TT>(c, P.sys, loc, tiles, scratch_tiles, sys_scale, [&](AsmSys *das, int ns, double *M) {
+      hipLaunchKernelGGL(k_assemble_local, dim3((unsigned)ns), dim3(256), 0, s, das, c->sub_idx, vinc_ptr, vinc, e2v,
+                         NE, nf, (const double *)Ae, M);
+    });
+    if (nbad) throw Fail(COARSE_ESINGULAR, std::to_string(nbad) + " local system(s) A_p not positive definite");
+  }
 
   // ... and of the reduced system (cell assembly, eq. (Aij))
   BoxDev box;
@@ -1040,7 +1138,7 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles, int wh
   if (c->interp == COARSE_J_CENTROID) {
     hipLaunchKernelGGL(k_cell_mats, dim3((unsigned)nocc), dim3(64), 0, s, box, occ_cells, occ_ptr, occ_elems, e2v, NE,
                        NV, nf, xyz, (const double *)Ae, cellmat);
-    nbad = invert_systems<TT>(c, P.sys, red, tiles, scratch_tiles, sys_scale, [&](AsmSys *, int, double *M) {
+    nbad = invert_systems<TT>(c, sysv, red, tiles, scratch_tiles, sys_scale, [&](AsmSys *, int, double *M) {
       hipLaunchKernelGGL(k_assemble_reduced, dim3(nblk(nr, 256)), dim3(256), 0, s, nr, ar_ptr, ar_src,
                          (const int32_t *)c->corner_act, (const double *)cellmat, M);
     });
@@ -1069,7 +1167,7 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles, int wh
     }
     pr.bx1 = P.b[0] + 1;
     pr.bxy1 = (P.b[0] + 1) * (P.b[1] + 1);
-    nbad = invert_systems<TT>(c, P.sys, red, tiles, scratch_tiles, sys_scale, [&](AsmSys *, int, double *M) {
+    nbad = invert_systems<TT>(c, sysv, red, tiles, scratch_tiles, sys_scale, [&](AsmSys *, int, double *M) {
       for (pr.c[2] = 0; pr.c[2] < pr.p[2]; ++pr.c[2])
         for (pr.c[1] = 0; pr.c[1] < pr.p[1]; ++pr.c[1])
           for (pr.c[0] = 0; pr.c[0] < pr.p[0]; ++pr.c[0]) {
@@ -1100,8 +1198,9 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles, int wh
   // GEMV items, combine rows, system table, segments
   std::vector<SysDev> sd(P.sys.size());
   for (size_t k = 0; k < P.sys.size(); ++k) {
-    const System &S = P.sys[k];
-    sd[k].tiles = tiles + (size_t)S.tile_off * TILE * TILE;
+    const System &S = sysv[k];
+    const bool no_inverse = inexact && (int64_t)k < P.n_local_sys;
+    sd[k].tiles = no_inverse ? nullptr : tiles + (size_t)S.tile_off * TILE * TILE;
     sd[k].rp = (T *)c->rp + S.vec_off;
     sd[k].colpart = colpart_off[k] >= 0 ? (T *)c->colpart + (size_t)colpart_off[k] * TILE : nullptr;
     sd[k].zp = c->zp + S.vec_off;
@@ -1215,7 +1314,15 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles, int wh
   in.local_bytes = tl * TILE * TILE * (int64_t)sizeof(TT);
   in.reduced_bytes = (P.n_tiles - tl) * TILE * TILE * (int64_t)sizeof(TT);
   in.inv_alg_bytes = 0;
-  for (const System &S : P.sys) in.inv_alg_bytes += S.n * (S.n + 1) / 2 * (int64_t)sizeof(TT);
+  for (size_t k = inexact ? (size_t)P.n_local_sys : 0; k < P.sys.size(); ++k)
+    in.inv_alg_bytes += P.sys[k].n * (P.sys[k].n + 1) / 2 * (int64_t)sizeof(TT);
+  in.local_iters = c->local_iters;
+  in.ell_width = c->loc_w;
+  if (inexact) {
+    // ELL values and column words, and the diagonals
+    const int64_t vb = std::is_same<TT, double>::value ? 8 : 4;
+    in.local_bytes = ell_entries * (vb + 2) + c->coarse_vec_off * 8;
+  }
   in.n_jent = (int64_t)P.jv_w.size();
   in.n_inc_blocks = 0;
   int64_t inc_slots = 0;
@@ -1230,7 +1337,7 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles, int wh
   for (int d = 0; d < 3; ++d) in.boxes[d] = P.b[d];
   in.precision = c->precision;
   for (int b = 0; b < COARSE_GEMV_BUCKETS; ++b) in.gemv_tiles[b] = c->gemv_tiles[b];
-  in.reduced_stream = c->reduced_aside ? 1 : 0;
+  in.reduced_stream = (c->reduced_aside || inexact) ? 1 : 0;
   in.whole_waves = c->whole_waves;
 }
 
@@ -1358,6 +1465,10 @@ struct coarse_batch {
   int submit(coarse_ctx *c, const double *b, double *u, double tol, int64_t tag) {
     if (c->mode != COARSE_ADDITIVE) {
       err = "batched solves use the additive preconditioner";
+      return COARSE_EINVAL;
+    }
+    if (c->local_iters > 0) {
+      err = "batched solves use exact local solves (opts.local_iters = 0)";
       return COARSE_EINVAL;
     }
     if (precision >= 0 && c->precision != precision) {
@@ -1614,6 +1725,10 @@ int check_multi(coarse_ctx *c, int k) {
     c->err = "the block solve needs a context with the additive preconditioner";
     return COARSE_EINVAL;
   }
+  if (c->local_iters > 0) {
+    c->err = "the block solve needs exact local solves (opts.local_iters = 0)";
+    return COARSE_EINVAL;
+  }
   if ((OP_BLOCK * 8 + c->max_slots * MCW) * (int64_t)sizeof(double) > 65536) {
     c->err = "operator blocks with too many distinct vertices for the block solve";
     return COARSE_EINVAL;
@@ -1694,6 +1809,10 @@ int coarse_plan_create(const coarse_mesh *mesh, const coarse_bc *bc, const coars
     g_setup_error = "projection must be in [0, COARSE_PROJECTION_MAX]";
     return COARSE_EINVAL;
   }
+  if (o.local_iters < 0 || o.local_iters > 10000) {
+    g_setup_error = "local_iters must be in [0, 10000]";
+    return COARSE_EINVAL;
+  }
   try {
     const double t0 = now();
     std::unique_ptr<coarse_plan> pl(new coarse_plan());
@@ -1760,8 +1879,10 @@ int coarse_setup_from_plan(const coarse_plan *plan, void *stream, coarse_ctx **o
   c->interp = o.interp;
   c->max_it = o.max_it;
   c->check_every = o.check_every;
-  // the hybrid of eqs. (asm1)-(asm2) is not symmetric: always the flexible beta
-  c->flexible = (o.flexible || o.mode == COARSE_HYBRID) ? 1 : 0;
+  // the hybrid of eqs. (asm1)-(asm2) is not symmetric, and inexact local solves
+  // are not linear in r (their CG coefficients depend on it): the flexible beta
+  c->flexible = (o.flexible || o.mode == COARSE_HYBRID || o.local_iters > 0) ? 1 : 0;
+  c->local_iters = o.local_iters;
   c->proj_max = o.projection;
   try {
     HIPCHK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));

@@ -1,0 +1,231 @@
+// Inexact local solves: in place of the stored inverse A_p^{-1} of the additive
+// preconditioner's local term (Sec. 3, eq. (asm)), each subdomain's r_p is solved
+// approximately by k steps of conjugate gradients preconditioned by the diagonal
+// of A_p, from a zero initial guess (the iterative inexact local solver the paper
+// proposes for GPUs in its conclusions, Sec. 6.3). The corrections are summed
+// over the overlap exactly as the dense ones are. Because the CG coefficients are
+// formed from r_p, the preconditioner is a nonlinear function of r and the outer
+// iteration must be the flexible (Polak-Ribiere) one.
+//
+// A_p = R_p A R_p^T is stored per subdomain in ELL form: the diagonal (FP64) and
+// W off-diagonal entries per row (local column as uint16, value FP64 or FP32),
+// entry (k, i) of a system at ell_off + k * npad + i, so that lane i of a
+// workgroup reads its row with coalesced loads. The columns are packed two per
+// 32-bit word. One workgroup solves one subdomain with one thread per row: the
+// row is loaded into registers once and reused by all k steps; the search
+// direction lives in LDS, where the row products gather it. Every sum has a
+// fixed order, so results are bitwise reproducible.
+#pragma once
+
+#include "kernels.h"
+
+namespace coarse {
+
+constexpr int LOC_WMAX = 26;       // off-diagonal entries per row of A_p at most
+constexpr int LOC_NT_MAX = 1024;   // rows of a subdomain at most (one thread each)
+
+struct LocSys {
+  int64_t ell_off;   // first entry of the system's ELL block (values; the
+                     // column words start at ell_off / 2)
+  int32_t vec_off;   // offset of R_p in the packed vectors (sub_idx, rp, zp, diag)
+  int32_t n, npad, pad;
+};
+
+// Position of internal vertex u in the sorted list R[0..n), or -1.
+__device__ __forceinline__ int loc_find(const int32_t *__restrict__ R, int n, int32_t u) {
+  int lo = 0, hi = n - 1;
+  while (lo <= hi) {
+    const int mid = (lo + hi) >> 1;
+    const int32_t x = R[mid];
+    if (x == u) return mid;
+    if (x < u)
+      lo = mid + 1;
+    else
+      hi = mid - 1;
+  }
+  return -1;
+}
+
+// ---------------------------------------------------------------------------
+// Setup, pass 1: the number of distinct off-diagonal columns of each row of A_p
+// (the free vertices of R_p that share an element with the row's vertex; every
+// element holding a vertex of R_p lies in the overlapping subdomain), maximised
+// over all rows into *wmax. A row with more than LOC_WMAX reports LOC_WMAX + 1.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_loc_count(const LocSys *__restrict__ sys, const int32_t *__restrict__ sub_idx,
+                                                   const int32_t *__restrict__ vinc_ptr,
+                                                   const int32_t *__restrict__ vinc, const int32_t *__restrict__ e2v,
+                                                   int64_t E, int64_t nf, int *__restrict__ wmax) {
+  const LocSys S = sys[blockIdx.x];
+  const int32_t *R = sub_idx + S.vec_off;
+  for (int a = threadIdx.x; a < S.n; a += blockDim.x) {
+    int32_t seen[LOC_WMAX];
+    int cnt = 0;
+    const int32_t v = R[a];
+    for (int k = vinc_ptr[v]; k < vinc_ptr[v + 1] && cnt <= LOC_WMAX; ++k) {
+      const int64_t e = vinc[k] >> 3;
+      for (int lb = 0; lb < 8; ++lb) {
+        const int32_t u = e2v[lb * E + e];
+        if (u >= nf || u == v) continue;
+        const int pos = loc_find(R, S.n, u);
+        if (pos < 0) continue;
+        bool dup = false;
+        for (int j = 0; j < cnt; ++j) dup |= (seen[j] == pos);
+        if (dup) continue;
+        if (cnt == LOC_WMAX) {
+          cnt = LOC_WMAX + 1;
+          break;
+        }
+        seen[cnt++] = pos;
+      }
+    }
+    atomicMax(wmax, cnt);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Setup, pass 2: the ELL rows. Row a sums, over the elements incident to vertex
+// R_p[a] in their stored order, the element-matrix row of that vertex restricted
+// to the columns in R_p (the same entries the dense assembly adds); columns are
+// kept in increasing order, unused slots hold column a with value 0. *bad counts
+// rows whose diagonal is not positive.
+// ---------------------------------------------------------------------------
+template <typename V>
+__global__ __launch_bounds__(256) void k_loc_fill(const LocSys *__restrict__ sys, int W,
+                                                  const int32_t *__restrict__ sub_idx,
+                                                  const int32_t *__restrict__ vinc_ptr,
+                                                  const int32_t *__restrict__ vinc, const int32_t *__restrict__ e2v,
+                                                  int64_t E, int64_t nf, const double *__restrict__ Ae,
+                                                  double *__restrict__ diag, uint32_t *__restrict__ col,
+                                                  V *__restrict__ val, int *__restrict__ bad) {
+  const LocSys S = sys[blockIdx.x];
+  const int32_t *R = sub_idx + S.vec_off;
+  for (int a = threadIdx.x; a < S.n; a += blockDim.x) {
+    int32_t cs[LOC_WMAX];
+    double vs[LOC_WMAX];
+    int cnt = 0;
+    double d = 0.0;
+    const int32_t v = R[a];
+    for (int k = vinc_ptr[v]; k < vinc_ptr[v + 1]; ++k) {
+      const int64_t e = vinc[k] >> 3;
+      const int la = vinc[k] & 7;
+      for (int lb = 0; lb < 8; ++lb) {
+        const int32_t u = e2v[lb * E + e];
+        if (u >= nf) continue;
+        const double x = Ae[ae_at(sym8(la, lb), e)];
+        if (u == v) {
+          d += x;
+          continue;
+        }
+        const int pos = loc_find(R, S.n, u);
+        if (pos < 0) continue;
+        int j = 0;
+        while (j < cnt && cs[j] < pos) ++j;
+        if (j < cnt && cs[j] == pos) {
+          vs[j] += x;
+          continue;
+        }
+        if (cnt == W) continue;   // cannot happen: W is the maximum count of pass 1
+        for (int m = cnt; m > j; --m) {
+          cs[m] = cs[m - 1];
+          vs[m] = vs[m - 1];
+        }
+        cs[j] = pos;
+        vs[j] = x;
+        ++cnt;
+      }
+    }
+    if (!(d > 0.0)) atomicAdd(bad, 1);
+    diag[S.vec_off + a] = d;
+    for (int k = 0; k < W; k += 2) {
+      const uint32_t c0 = (uint32_t)(k < cnt ? cs[k] : a);
+      const uint32_t c1 = (uint32_t)(k + 1 < cnt ? cs[k + 1] : a);
+      col[S.ell_off / 2 + (int64_t)(k / 2) * S.npad + a] = c0 | (c1 << 16);
+      val[S.ell_off + (int64_t)k * S.npad + a] = (V)(k < cnt ? vs[k] : 0.0);
+      val[S.ell_off + (int64_t)(k + 1) * S.npad + a] = (V)(k + 1 < cnt ? vs[k + 1] : 0.0);
+    }
+  }
+}
+
+// Sum over the workgroup, returned to every thread: per-wave sums, then each
+// thread adds the wave sums in wave order. `red` must not be reused before the
+// next barrier of every thread has passed.
+__device__ __forceinline__ double loc_block_sum(double v, double *red, int nw) {
+  v = wave_sum(v);
+  if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < nw; ++w) s += red[w];
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// The local solves of one preconditioner application: workgroup s runs `iters`
+// steps of Jacobi-preconditioned CG on A_p z_p = r_p of local system s,
+//   x = 0, r = r_p, z = D^{-1} r, p = z;  each step: q = A_p p,
+//   alpha = (r,z)/(p,q), x += alpha p, r -= alpha q, then (but for the last step)
+//   z = D^{-1} r, beta = (r,z)_new/(r,z), p = z + beta p,
+// stopping early when (r, z) is exactly 0 (a zero right-hand side), and writes x
+// to the packed solution zp. blockDim.x >= the largest n (a multiple of 64).
+// T: the type of the packed right-hand sides; V: the stored entries of A_p.
+// ---------------------------------------------------------------------------
+template <typename V, typename T>
+__global__ __launch_bounds__(LOC_NT_MAX) void k_local_pcg(const LocSys *__restrict__ sys, int W, int iters,
+                                                          const int *__restrict__ done, const T *__restrict__ rp,
+                                                          const double *__restrict__ diag,
+                                                          const uint32_t *__restrict__ col,
+                                                          const V *__restrict__ val, double *__restrict__ zp) {
+  if (*done) return;
+  __shared__ double sp[LOC_NT_MAX];
+  __shared__ double red[2][LOC_NT_MAX / WAVE];
+  const LocSys S = sys[blockIdx.x];
+  const int i = threadIdx.x;
+  const int nw = blockDim.x / WAVE;
+  const bool act = i < S.n;
+  V a[LOC_WMAX];
+  uint32_t c[LOC_WMAX / 2];
+  double d = 1.0, r = 0.0;
+  if (act) {
+    r = (double)rp[S.vec_off + i];
+    d = diag[S.vec_off + i];
+#pragma unroll
+    for (int k = 0; k < LOC_WMAX; k += 2)
+      if (k < W) {
+        c[k / 2] = col[S.ell_off / 2 + (int64_t)(k / 2) * S.npad + i];
+        a[k] = val[S.ell_off + (int64_t)k * S.npad + i];
+        a[k + 1] = val[S.ell_off + (int64_t)(k + 1) * S.npad + i];
+      }
+  }
+  const double dinv = 1.0 / d;
+  double x = 0.0;
+  double z = dinv * r;
+  double p = z;
+  double rz = loc_block_sum(r * z, red[0], nw);
+  for (int it = 0; it < iters; ++it) {
+    if (rz == 0.0) break;
+    sp[i] = p;
+    __syncthreads();
+    double q = 0.0;
+    if (act) {
+      q = d * p;
+#pragma unroll
+      for (int k = 0; k < LOC_WMAX; k += 2)
+        if (k < W) {
+          q += (double)a[k] * sp[c[k / 2] & 0xFFFF];
+          q += (double)a[k + 1] * sp[c[k / 2] >> 16];
+        }
+    }
+    const double pq = loc_block_sum(p * q, red[1], nw);
+    const double alpha = rz / pq;
+    x += alpha * p;
+    r -= alpha * q;
+    if (it == iters - 1) break;
+    z = dinv * r;
+    const double rz1 = loc_block_sum(r * z, red[0], nw);
+    p = z + (rz1 / rz) * p;
+    rz = rz1;
+  }
+  if (act) zp[S.vec_off + i] = x;
+}
+
+}  // namespace coarse

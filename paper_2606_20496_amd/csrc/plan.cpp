@@ -671,12 +671,12 @@ int build_plan(const PlanInput &in, Plan &P) {
 }
 
 void build_gemv_items(const Plan &P, const int *tiles_of_bucket, const int *bucket_max, int nbucket, int n_cu,
-                      GemvTable &out) {
+                      GemvTable &out, int64_t first_sys) {
   out = GemvTable();
   // whole-system candidates, largest first; the smallest beyond a multiple of
   // n_cu would form a last round that few compute units work on
   std::vector<int32_t> cand;
-  for (int64_t s = 0; s < (int64_t)P.sys.size(); ++s)
+  for (int64_t s = first_sys; s < (int64_t)P.sys.size(); ++s)
     if (P.sys[s].nb >= WHOLE_NB_MIN && P.sys[s].nb <= WHOLE_NB_MAX) cand.push_back((int32_t)s);
   std::stable_sort(cand.begin(), cand.end(), [&](int32_t a, int32_t b) { return P.sys[a].nb > P.sys[b].nb; });
   // fewer systems than compute units: one workgroup per system would leave most
@@ -686,7 +686,7 @@ void build_gemv_items(const Plan &P, const int *tiles_of_bucket, const int *buck
   if (n_cu > 0) keep -= keep % (size_t)n_cu;
   std::vector<char> whole(P.sys.size(), 0);
   for (size_t i = 0; i < keep; ++i) whole[cand[i]] = 1;
-  for (int64_t s = 0; s < (int64_t)P.sys.size(); ++s) {
+  for (int64_t s = first_sys; s < (int64_t)P.sys.size(); ++s) {
     const System &S = P.sys[s];
     if (whole[s]) {
       out.whole.push_back((int32_t)s);

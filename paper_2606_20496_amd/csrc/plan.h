@@ -155,7 +155,8 @@ struct GemvTable {
   std::vector<GemvItem> items;
   std::vector<int32_t> row_item0, row_nitem, row_sys, row_I;
 };
+// Systems before first_sys are left out (their solves are not dense).
 void build_gemv_items(const Plan &P, const int *tiles_of_bucket, const int *bucket_max, int nbucket, int n_cu,
-                      GemvTable &out);
+                      GemvTable &out, int64_t first_sys = 0);
 
 }  // namespace coarse
