@@ -72,12 +72,14 @@ def _traffic(workload):
     return t["bytes"] if t and _gemv_source_fingerprint() == t["src"] else None
 
 
-def run_form(torch, coarse, mesh, rhs, precision, steps, warmup, tol):
+def run_form(torch, coarse, mesh, rhs, precision, steps, warmup, tol, local_iters=0):
     """Set up once, then time `steps` solves, each on its own right-hand side (all
     resident on the GPU). Only the dominant kernel is bracketed by HIP events in
-    the timed region; a separate pass afterwards times every phase."""
+    the timed region; a separate pass afterwards times every phase. local_iters
+    > 0: inexact local solves (that many Jacobi-PCG steps per subdomain), whose
+    launch is then the one timed."""
     t0 = time.perf_counter()
-    S = coarse.CoarseSolver.from_mesh(mesh, precision=precision)
+    S = coarse.CoarseSolver.from_mesh(mesh, precision=precision, local_iters=local_iters)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     u = torch.empty_like(rhs[0])
@@ -125,6 +127,49 @@ def _form_summary(f, dtype, precision):
             "relres_true_max": f["relres_true_max"], "setup_s": round(f["setup_s"], 3),
             "gemv_avg_launch_us": round(avg_ms * 1e3, 2), "gemv_alg_bytes": lb,
             "gemv_achieved_GBs": round(lb / (avg_ms / 1e3) / 1e9, 1)}
+
+
+def inexact_launch_bytes(info, precision):
+    """Bytes one launch of the inexact local solves must move: the stored A_p
+    (ELL values and column words, FP64 diagonals) read once, whatever the number
+    of steps (each row stays in registers), r_p read and z_p written per packed
+    entry."""
+    return info["local_bytes"] + info["sum_np"] * ((8 if precision == "fp64" else 4) + 8)
+
+
+def run_inexact(torch, coarse, mesh, rhs, exact, ks, steps, warmup, tol, precisions=("fp64", "mixed")):
+    """Inexact local solves (k Jacobi-PCG steps per subdomain, flexible outer PCG)
+    against the stored inverses of the same mesh: solves/s, iterations, the local
+    launch's time, and iterations x bytes of the local solves (the bytes the local
+    term reads per application times the iterations)."""
+    out = {"note": "k steps of diagonally preconditioned CG per subdomain (A_p in ELL form, FP64 values; FP32 "
+                   "values in the mixed form) in place of the stored inverses; flexible outer PCG",
+           "exact": {}, "inexact": {}}
+    for prec, f in exact.items():
+        if f is None:
+            continue
+        lb = local_inv_bytes(f["info"], prec)
+        out["exact"][prec] = {"value": round(f["solves_per_s"], 3), "iters": f["iters"],
+                              "local_bytes_per_application": lb,
+                              "iters_x_local_GB": round(f["iters"] * lb / 1e9, 2),
+                              "local_launch_us": round(f["gemv"][0] / max(f["gemv_work_launches"], 1) * 1e3, 2),
+                              "device_GB": round(f["info"]["device_bytes"] / 1e9, 3)}
+    for prec in precisions:
+        for k in ks:
+            f = run_form(torch, coarse, mesh, rhs, prec, steps, warmup, tol, local_iters=k)
+            lb = inexact_launch_bytes(f["info"], prec)
+            us = f["gemv"][0] / max(f["gemv_work_launches"], 1) * 1e3
+            out["inexact"][f"{prec}_k{k}"] = {
+                "value": round(f["solves_per_s"], 3), "ms_per_step": round(f["ms_per_solve"], 4),
+                "p50_ms": round(f["p50_ms"], 4), "p99_ms": round(f["p99_ms"], 4), "iters": f["iters"],
+                "relres_true_max": f["relres_true_max"], "setup_s": round(f["setup_s"], 3),
+                "ell_width": f["info"]["ell_width"], "local_bytes_per_application": lb,
+                "iters_x_local_GB": round(f["iters"] * lb / 1e9, 2), "local_launch_us": round(us, 2),
+                "local_launch_GBs": round(lb / us / 1e3, 1) if us > 0 else None,
+                "device_GB": round(f["info"]["device_bytes"] / 1e9, 3)}
+            _log(f"inexact {prec} k={k}: {f['solves_per_s']:.3f} solves/s, {f['iters']} iterations, "
+                 f"local launch {us:.1f} us")
+    return out
 
 
 def run_batch_workload(torch, coarse, mg, tol, reps=3):
@@ -232,7 +277,7 @@ def _dist(v):
 
 
 def run_serving_workload(torch, coarse, mg, tol, rates=(50.0, 2000.0), count=4096, budget_gb=64.0,
-                         precision="mixed", plan_workers=12, sequential=True):
+                         precision="mixed", plan_workers=12, sequential=True, projection=0):
     """The serving workload with setups in the loop: Poisson arrivals at each rate,
     `count` requests, each a coarse solve on a seeded mesh with n log-uniform in
     [8, 96] and a z stretch of up to 20, 30% of them reusing an earlier mesh with
@@ -240,12 +285,17 @@ def run_serving_workload(torch, coarse, mg, tol, rates=(50.0, 2000.0), count=409
     plan workers, counted in the latency). The continuous-batching server (mixed
     precision, FP64 outer iteration, admission by an HBM budget that binds,
     least-recently-used eviction) against the plain FP64 one-at-a-time path on
-    the same stream with the same budget. Latency is arrival to result."""
+    the same stream with the same budget. Latency is arrival to result. With
+    projection = l > 0 the batched server runs a second time with a basis of l
+    prior solutions per cached mesh (Sec. 5), so that requests that reuse a mesh
+    start from the projection onto its earlier solutions."""
     from paper_2606_20496_amd import serve
     out = {"requests_per_rate": count, "n_range": [8, 96], "reuse": 0.3, "budget_GB": budget_gb,
            "precision": precision, "plan_workers": plan_workers, "rates": {}}
+    keep_proj = ("solves_per_s", "p50_ms", "p99_ms", "mean_iters", "max_relres_true", "cache_misses", "failed",
+                 "mean_iters_reused", "median_relres0_reused")
     keep = ("requests", "wall_s", "solves_per_s", "p50_ms", "p99_ms", "mean_iters", "max_relres_true",
-            "cache_misses", "failed")
+            "cache_misses", "failed", "mean_iters_reused")
     for rate in rates:
         reqs = serve.make_requests(rate, count, lazy=True)
         srv = serve.Server(budget_gb * 1e9, precision=precision, use_graph=True, step_iters=2,
@@ -258,6 +308,16 @@ def run_serving_workload(torch, coarse, mg, tol, rates=(50.0, 2000.0), count=409
         res = {"batched_" + precision: summ}
         _log(f"serving {rate:g} req/s: batched {summ['solves_per_s']:.1f}/s p50 {summ['p50_ms']:.0f} ms "
              f"p99 {summ['p99_ms']:.0f} ms, failed {summ['failed']}")
+        if projection > 0:
+            srv = serve.Server(budget_gb * 1e9, precision=precision, use_graph=True, step_iters=2,
+                               plan_workers=plan_workers, solver_kw={"projection": int(projection)})
+            rec3, wall3 = srv.run(reqs, progress=lambda m, r=rate: _log(f"serving {r:g} req/s, projected: {m}"))
+            pj = {k: v for k, v in serve.summarize(rec3, wall3).items() if k in keep_proj}
+            pj.update(basis=int(projection), evictions=srv.evictions)
+            srv.close()
+            res[f"batched_{precision}_projected"] = pj
+            _log(f"serving {rate:g} req/s: projected {pj['solves_per_s']:.1f}/s p99 {pj['p99_ms']:.0f} ms, "
+                 f"mean iterations {pj['mean_iters']:.1f} against {summ['mean_iters']:.1f}")
         if sequential is True or (sequential and rate in sequential):
             rec2, wall2 = serve.serve_sequential(reqs, tol=tol, budget_bytes=budget_gb * 1e9,
                                                  progress=lambda m, r=rate: _log(f"sequential {r:g}: {m}"))
@@ -551,6 +611,8 @@ def main():
     ap.add_argument("--no-ablations", action="store_true", help="skip the preconditioner-part study")
     ap.add_argument("--no-warm-start", action="store_true", help="skip the successive right-hand-side study")
     ap.add_argument("--no-multi", action="store_true", help="skip the 16-right-hand-side block solve")
+    ap.add_argument("--no-inexact", action="store_true", help="skip the inexact local solves study")
+    ap.add_argument("--inexact-k", default="4,8,12", help="Jacobi-PCG steps per subdomain of the inexact study")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the open-loop serving study over resident contexts")
     ap.add_argument("--serving", action="store_true", help="also run the serving workload with setups in the loop")
@@ -560,6 +622,8 @@ def main():
                     help="skip the FP64 one-at-a-time comparison of --serving")
     ap.add_argument("--serving-sequential-rates", default="",
                     help="run the FP64 one-at-a-time comparison at these rates only (default: every rate)")
+    ap.add_argument("--serving-projection", type=int, default=0,
+                    help="also run --serving with a basis of this many prior solutions per cached mesh")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 1 GiB device copy (known bytes) to scale HBM counters")
     args = ap.parse_args()
@@ -598,6 +662,14 @@ def main():
         _log(f"mixed: {mixed['solves_per_s']:.3f} solves/s, {mixed['iters']} iterations")
         mixed16 = run_form(torch, coarse, mesh, rhs, "mixed16", args.steps, args.warmup, args.tol)
         _log(f"mixed16: {mixed16['solves_per_s']:.3f} solves/s, {mixed16['iters']} iterations")
+    inexact = None
+    ks = tuple(int(x) for x in args.inexact_k.split(",") if x)
+    if not args.no_inexact and ks:
+        _log("inexact local solves")
+        inexact = {workload: run_inexact(torch, coarse, mesh, rhs,
+                                         {"fp64": fp64, "mixed": mixed, "mixed16": mixed16}, ks,
+                                         args.steps, args.warmup, args.tol,
+                                         precisions=("fp64",) if args.no_mixed else ("fp64", "mixed"))}
     del rhs
 
     # roofline of the dominant kernel: the batched dense solve of the local systems
@@ -643,11 +715,17 @@ def main():
         cube["fp64"]["roofline"] = {"kernel": "k_gemv_whole_f64", "avg_launch_us": round(avg2 * 1e6, 2),
                                     "alg_bytes_per_launch": lb2, "frac": round(lb2 / avg2 / 1e9 / HBM_PEAK_GBS, 4),
                                     "traffic": _traffic("cube64")}
+        c2_mixed = c2_mixed16 = None
         if not args.no_mixed:
-            cube["mixed"] = _form_summary(run_form(torch, coarse, c2, rhs2, "mixed", 20, 3, args.tol), "f32",
-                                          "mixed")
-            cube["mixed16"] = _form_summary(run_form(torch, coarse, c2, rhs2, "mixed16", 20, 3, args.tol),
-                                            "f16-stored", "mixed16")
+            c2_mixed = run_form(torch, coarse, c2, rhs2, "mixed", 20, 3, args.tol)
+            c2_mixed16 = run_form(torch, coarse, c2, rhs2, "mixed16", 20, 3, args.tol)
+            cube["mixed"] = _form_summary(c2_mixed, "f32", "mixed")
+            cube["mixed16"] = _form_summary(c2_mixed16, "f16-stored", "mixed16")
+        if inexact is not None:
+            inexact["cube64"] = run_inexact(torch, coarse, c2, rhs2,
+                                            {"fp64": c2_fp64, "mixed": c2_mixed, "mixed16": c2_mixed16}, ks,
+                                            20, 3, args.tol,
+                                            precisions=("fp64",) if args.no_mixed else ("fp64", "mixed"))
         if not args.no_cpu_baseline:
             _log("cube64 cpu baseline (oracle, median of 3)")
             cube["cpu_baseline"] = cpu_baseline_cube64(c2, args.tol)
@@ -699,7 +777,8 @@ def main():
                                        count=args.serving_count,
                                        sequential=(False if args.serving_no_sequential else
                                                    {float(x) for x in args.serving_sequential_rates.split(",")}
-                                                   if args.serving_sequential_rates else True))
+                                                   if args.serving_sequential_rates else True),
+                                       projection=args.serving_projection)
 
     line = {
         "metric": "coarse solves/sec to 1e-8 rel. residual (mixed vs FP64); p50/p99 latency",
@@ -731,7 +810,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
-    for key, val in (("cube64", cube), ("batch_workload", batch), ("ablations", ablations),
+    for key, val in (("cube64", cube), ("inexact_local_solves", inexact), ("batch_workload", batch),
+                     ("ablations", ablations),
                      ("warm_start", warm), ("multi_rhs", multi), ("serving_resident", resident),
                      ("serving_workload", serving)):
         if val is not None:

@@ -147,11 +147,33 @@ __global__ __launch_bounds__(256) void k_loc_fill(const LocSys *__restrict__ sys
   }
 }
 
+// Sum over the 64 lanes of a wavefront with DPP lane moves (no LDS traffic),
+// in a fixed order: pairs, quads, half rows, rows, then the rows into lane 63,
+// whose value every lane receives.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double loc_dpp(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double loc_wave_sum(double v) {
+  v += loc_dpp<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+  v += loc_dpp<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+  v += loc_dpp<0x141, 0xF>(v);   // row_half_mirror
+  v += loc_dpp<0x140, 0xF>(v);   // row_mirror
+  v += loc_dpp<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+  v += loc_dpp<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
 // Sum over the workgroup, returned to every thread: per-wave sums, then each
 // thread adds the wave sums in wave order. `red` must not be reused before the
 // next barrier of every thread has passed.
 __device__ __forceinline__ double loc_block_sum(double v, double *red, int nw) {
-  v = wave_sum(v);
+  v = loc_wave_sum(v);
   if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = v;
   __syncthreads();
   double s = 0.0;
@@ -162,11 +184,15 @@ __device__ __forceinline__ double loc_block_sum(double v, double *red, int nw) {
 // ---------------------------------------------------------------------------
 // The local solves of one preconditioner application: workgroup s runs `iters`
 // steps of Jacobi-preconditioned CG on A_p z_p = r_p of local system s,
-//   x = 0, r = r_p, z = D^{-1} r, p = z;  each step: q = A_p p,
-//   alpha = (r,z)/(p,q), x += alpha p, r -= alpha q, then (but for the last step)
-//   z = D^{-1} r, beta = (r,z)_new/(r,z), p = z + beta p,
+//   x = 0, r = r_p, z = D^{-1} r;  step j: beta = (r,z)_j / (r,z)_{j-1} (0 for
+//   j = 0), p = z + beta p, q = A_p p, alpha = (r,z)_j / (p,q), x += alpha p,
+//   r -= alpha q, z = D^{-1} r (but for the last step),
 // stopping early when (r, z) is exactly 0 (a zero right-hand side), and writes x
-// to the packed solution zp. blockDim.x >= the largest n (a multiple of 64).
+// to the packed solution zp. q = A_p p is formed as A_p z + beta q (the same
+// product, split by linearity), so that the new z, not p, is what the threads
+// exchange through LDS: its write goes before the barrier of the (r, z) sum,
+// which then also publishes it, and a step needs two barriers instead of three.
+// blockDim.x >= the largest n (a multiple of 64).
 // T: the type of the packed right-hand sides; V: the stored entries of A_p.
 // ---------------------------------------------------------------------------
 template <typename V, typename T>
@@ -176,7 +202,7 @@ __global__ __launch_bounds__(LOC_NT_MAX) void k_local_pcg(const LocSys *__restri
                                                           const uint32_t *__restrict__ col,
                                                           const V *__restrict__ val, double *__restrict__ zp) {
   if (*done) return;
-  __shared__ double sp[LOC_NT_MAX];
+  __shared__ double sz[LOC_NT_MAX];
   __shared__ double red[2][LOC_NT_MAX / WAVE];
   const LocSys S = sys[blockIdx.x];
   const int i = threadIdx.x;
@@ -197,33 +223,35 @@ __global__ __launch_bounds__(LOC_NT_MAX) void k_local_pcg(const LocSys *__restri
       }
   }
   const double dinv = 1.0 / d;
-  double x = 0.0;
+  double x = 0.0, p = 0.0, q = 0.0;
   double z = dinv * r;
-  double p = z;
+  sz[i] = z;
   double rz = loc_block_sum(r * z, red[0], nw);
+  double rz_old = 1.0;
   for (int it = 0; it < iters; ++it) {
     if (rz == 0.0) break;
-    sp[i] = p;
-    __syncthreads();
-    double q = 0.0;
+    double s = 0.0;
     if (act) {
-      q = d * p;
+      s = d * z;
 #pragma unroll
       for (int k = 0; k < LOC_WMAX; k += 2)
         if (k < W) {
-          q += (double)a[k] * sp[c[k / 2] & 0xFFFF];
-          q += (double)a[k + 1] * sp[c[k / 2] >> 16];
+          s += (double)a[k] * sz[c[k / 2] & 0xFFFF];
+          s += (double)a[k + 1] * sz[c[k / 2] >> 16];
         }
     }
+    const double beta = it == 0 ? 0.0 : rz / rz_old;
+    p = z + beta * p;
+    q = s + beta * q;
     const double pq = loc_block_sum(p * q, red[1], nw);
     const double alpha = rz / pq;
     x += alpha * p;
     r -= alpha * q;
     if (it == iters - 1) break;
     z = dinv * r;
-    const double rz1 = loc_block_sum(r * z, red[0], nw);
-    p = z + (rz1 / rz) * p;
-    rz = rz1;
+    sz[i] = z;
+    rz_old = rz;
+    rz = loc_block_sum(r * z, red[0], nw);
   }
   if (act) zp[S.vec_off + i] = x;
 }

@@ -89,6 +89,7 @@ class Record:
     setup: bool              # this request's mesh was set up for it (cache miss)
     status: int
     u: object = None         # the solution (kept only when asked for)
+    relres0: float = 1.0     # relative residual of the initial guess (1 from u_0 = 0)
 
     @property
     def latency(self):
@@ -106,6 +107,11 @@ def summarize(records, wall):
         "max_relres_true": float(max((r.relres_true for r in records), default=0.0)),
         "cache_misses": int(sum(r.setup for r in records)),
         "failed": int(sum(r.status != 0 for r in records)),
+        # requests on a mesh already resident (a projection basis can help only these)
+        "mean_iters_reused": (float(np.mean([r.iters for r in records if not r.setup]))
+                              if any(not r.setup for r in records) else float("nan")),
+        "median_relres0_reused": (float(np.median([r.relres0 for r in records if not r.setup]))
+                                  if any(not r.setup for r in records) else float("nan")),
     }
 
 
@@ -162,7 +168,7 @@ class Server:
         t0 = time.perf_counter()
         m = _mesh_of(mesh)
         t1 = time.perf_counter()
-        need = self.estimate_bytes(m, self.precision)
+        need = self.estimate_bytes(m, self.precision, self.solver_kw.get("projection", 0))
         plan = self._plan(mesh)
         self.setup_times["mesh_s"].append(t1 - t0)
         self.setup_times["plan_s"].append(time.perf_counter() - t1)
@@ -218,16 +224,17 @@ class Server:
         return self.used + need <= self.budget
 
     @staticmethod
-    def estimate_bytes(mesh, precision):
+    def estimate_bytes(mesh, precision, projection=0):
         """Rough device footprint of a context before it exists: element data, the
-        stored inverses (packed symmetric, padded to 32) and vectors."""
+        stored inverses (packed symmetric, padded to 32), vectors and the basis of
+        `projection` prior solutions (and their products with A)."""
         E, n = mesh.n_elem, mesh.n_vert
         vol = E / max(mesh.n_part, 1)
         np_ = (vol ** (1 / 3) + 2) ** 3
         nb = np.ceil(np_ / 32)
         tiles = mesh.n_part * nb * (nb + 1) / 2
         es = {"fp64": 8, "mixed": 4, "mixed16": 2}[precision]
-        return int(E * 420 + n * 200 + tiles * 1024 * es * 1.1 + tiles * 32 * es)
+        return int(E * 420 + n * 200 + tiles * 1024 * es * 1.1 + tiles * 32 * es + 16 * projection * n)
 
     def run(self, requests, t0=None, progress=None, progress_every=10.0):
         """Serve `requests` (open loop: each is admitted at its arrival time) until
@@ -354,7 +361,7 @@ class Server:
                     records.append(Record(rid=rq.rid, key=rq.key, t_arrive=rq.t_arrive, t_done=now(),
                                           iters=st["iters"], relres_true=st["relres_true"],
                                           setup=rq.rid in missed, status=st["status"],
-                                          u=u if self.keep_outputs else None))
+                                          u=u if self.keep_outputs else None, relres0=st["relres0"]))
             else:
                 time.sleep(0.0005)
         self.stream.synchronize()
