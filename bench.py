@@ -277,7 +277,7 @@ def _dist(v):
 
 
 def run_serving_workload(torch, coarse, mg, tol, rates=(50.0, 2000.0), count=4096, budget_gb=64.0,
-                         precision="mixed", plan_workers=12, sequential=True, projection=0):
+                         precision="mixed", plan_workers=12, sequential=True, projection=0, local_iters=0):
     """The serving workload with setups in the loop: Poisson arrivals at each rate,
     `count` requests, each a coarse solve on a seeded mesh with n log-uniform in
     [8, 96] and a z stretch of up to 20, 30% of them reusing an earlier mesh with
@@ -288,7 +288,9 @@ def run_serving_workload(torch, coarse, mg, tol, rates=(50.0, 2000.0), count=409
     the same stream with the same budget. Latency is arrival to result. With
     projection = l > 0 the batched server runs a second time with a basis of l
     prior solutions per cached mesh (Sec. 5), so that requests that reuse a mesh
-    start from the projection onto its earlier solutions."""
+    start from the projection onto its earlier solutions. With local_iters = k > 0
+    it runs again with inexact local solves (k Jacobi-PCG steps per subdomain):
+    no local inverses, so less device memory per mesh and a shorter setup."""
     from paper_2606_20496_amd import serve
     out = {"requests_per_rate": count, "n_range": [8, 96], "reuse": 0.3, "budget_GB": budget_gb,
            "precision": precision, "plan_workers": plan_workers, "rates": {}}
@@ -308,16 +310,23 @@ def run_serving_workload(torch, coarse, mg, tol, rates=(50.0, 2000.0), count=409
         res = {"batched_" + precision: summ}
         _log(f"serving {rate:g} req/s: batched {summ['solves_per_s']:.1f}/s p50 {summ['p50_ms']:.0f} ms "
              f"p99 {summ['p99_ms']:.0f} ms, failed {summ['failed']}")
+        variants = []
         if projection > 0:
+            variants.append(("projected", {"projection": int(projection)}))
+        if local_iters > 0:
+            variants.append((f"inexact_k{int(local_iters)}", {"local_iters": int(local_iters)}))
+        for name, kw in variants:
             srv = serve.Server(budget_gb * 1e9, precision=precision, use_graph=True, step_iters=2,
-                               plan_workers=plan_workers, solver_kw={"projection": int(projection)})
-            rec3, wall3 = srv.run(reqs, progress=lambda m, r=rate: _log(f"serving {r:g} req/s, projected: {m}"))
+                               plan_workers=plan_workers, solver_kw=kw)
+            rec3, wall3 = srv.run(reqs, progress=lambda m, r=rate, v=name: _log(f"serving {r:g} req/s, {v}: {m}"))
             pj = {k: v for k, v in serve.summarize(rec3, wall3).items() if k in keep_proj}
-            pj.update(basis=int(projection), evictions=srv.evictions)
+            pj.update(solver_kw=kw, evictions=srv.evictions,
+                      setup_per_miss_s={k: _dist(v) for k, v in srv.setup_times.items()})
             srv.close()
-            res[f"batched_{precision}_projected"] = pj
-            _log(f"serving {rate:g} req/s: projected {pj['solves_per_s']:.1f}/s p99 {pj['p99_ms']:.0f} ms, "
-                 f"mean iterations {pj['mean_iters']:.1f} against {summ['mean_iters']:.1f}")
+            res[f"batched_{precision}_{name}"] = pj
+            _log(f"serving {rate:g} req/s: {name} {pj['solves_per_s']:.1f}/s p50 {pj['p50_ms']:.0f} ms "
+                 f"p99 {pj['p99_ms']:.0f} ms, mean iterations {pj['mean_iters']:.1f} against "
+                 f"{summ['mean_iters']:.1f}, failed {pj['failed']}")
         if sequential is True or (sequential and rate in sequential):
             rec2, wall2 = serve.serve_sequential(reqs, tol=tol, budget_bytes=budget_gb * 1e9,
                                                  progress=lambda m, r=rate: _log(f"sequential {r:g}: {m}"))
@@ -624,6 +633,8 @@ def main():
                     help="run the FP64 one-at-a-time comparison at these rates only (default: every rate)")
     ap.add_argument("--serving-projection", type=int, default=0,
                     help="also run --serving with a basis of this many prior solutions per cached mesh")
+    ap.add_argument("--serving-local-iters", type=int, default=0,
+                    help="also run --serving with inexact local solves of this many steps")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 1 GiB device copy (known bytes) to scale HBM counters")
     args = ap.parse_args()
@@ -778,7 +789,8 @@ def main():
                                        sequential=(False if args.serving_no_sequential else
                                                    {float(x) for x in args.serving_sequential_rates.split(",")}
                                                    if args.serving_sequential_rates else True),
-                                       projection=args.serving_projection)
+                                       projection=args.serving_projection,
+                                       local_iters=args.serving_local_iters)
 
     line = {
         "metric": "coarse solves/sec to 1e-8 rel. residual (mixed vs FP64); p50/p99 latency",

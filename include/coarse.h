@@ -168,10 +168,9 @@ typedef struct {
                        opts.flexible says. Needs every |R_p| <= 1024 and at most 26
                        off-diagonal entries per row of A_p (the 27-point coupling
                        of a vertex inside a structured hex block; else
-                       COARSE_EINVAL at setup). Single solves only
-                       (coarse_solve, coarse_solve_projected,
-                       coarse_apply_precond): block solves and lock-step batches
-                       reject such a context (COARSE_EINVAL)                      */
+                       COARSE_EINVAL at setup). Block solves (coarse_solve_multi,
+                       coarse_multi_*) reject such a context (COARSE_EINVAL);
+                       single solves and lock-step batches take it             */
 } coarse_opts;
 
 typedef struct {
@@ -364,7 +363,8 @@ int coarse_solve_batch_noalloc(coarse_ctx *const *ctxs, const double *const *b, 
  * whatever the number of live solves: the operator, the x/r update, the
  * restriction (R_p and the first stage of J^T), the J^T corner sums, the dense
  * local and reduced solves of all systems of all solves (one GEMV and one
- * partial-sum launch), and the overlap sum with the prolongation. Each workgroup
+ * partial-sum launch), and the overlap sum with the prolongation; an eighth
+ * runs the inexact local solves of the solves set up with opts.local_iters > 0. Each workgroup
  * of such a launch works for one solve exactly as in that solve's own launch.
  * A submitted solve's first preconditioner application runs at submit. Solves join with
  * coarse_batch_submit and leave when coarse_batch_step reports them finished, so

@@ -622,6 +622,14 @@ struct coarse_ctx {
     d.bx1 = bx1;
     d.bxy1 = bxy1;
     d.flexible = flexible;
+    d.loc_sys = locsys;
+    d.loc_diag = loc_diag;
+    d.loc_col = loc_col;
+    d.loc_val = loc_val;
+    d.loc_w = loc_w;
+    d.loc_iters = local_iters;
+    d.n_loc = local_iters > 0 ? (int32_t)n_local_sys : 0;
+    d.pad_loc = 0;
   }
 
   // nproj > 0: start from the projection of the solution onto the first nproj
@@ -1377,7 +1385,7 @@ PlanInput make_input(const coarse_mesh *mesh, const coarse_bc *bc, const coarse_
 struct coarse_batch {
   // grouped launches of one lock step: operator, update, restriction, J^T
   // corners, overlap sum (the dense solves use the segment tables)
-  enum { G_OP, G_UPD, G_PRE, G_COR, G_FIN, NG };
+  enum { G_OP, G_UPD, G_PRE, G_COR, G_FIN, G_LOC, NG };
   std::string err;
   hipStream_t main = nullptr;
   struct Entry {
@@ -1400,6 +1408,7 @@ struct coarse_batch {
   int cap = 0, n_items = 0, n_rows = 0, n_whole = 0, whole_lds = 0;
   int grid[NG] = {};
   int op_lds = 0, fin_lds = 0;
+  int loc_nt = 0;   // workgroup size of the grouped inexact local solves
   hipGraphExec_t gexec = nullptr;
   // tables in memory the batch does not own (the allocation-free entry point):
   // fixed capacity, never reallocated or freed, no graph
@@ -1467,10 +1476,6 @@ struct coarse_batch {
       err = "batched solves use the additive preconditioner";
       return COARSE_EINVAL;
     }
-    if (c->local_iters > 0) {
-      err = "batched solves use exact local solves (opts.local_iters = 0)";
-      return COARSE_EINVAL;
-    }
     if (precision >= 0 && c->precision != precision) {
       err = "all solves of a batch share one precision";
       return COARSE_EINVAL;
@@ -1518,7 +1523,7 @@ struct coarse_batch {
       HIPCHK(hipHostMalloc((void **)&h_sc, cap * sizeof(Scalars), hipHostMallocDefault));
     }
     n_items = n_rows = n_whole = 0;
-    op_lds = whole_lds = fin_lds = 0;
+    op_lds = whole_lds = fin_lds = loc_nt = 0;
     for (int g = 0; g < NG; ++g) h_off[g * (cap + 1)] = 0;
     for (int k = 0; k < n; ++k) {
       coarse_ctx *c = live[k].c;
@@ -1531,7 +1536,8 @@ struct coarse_batch {
       whole_lds = std::max(whole_lds, (int)c->whole_lds);
       c->fill_iter(h_iter[k]);
       const int64_t blocks[NG] = {c->op.n_blocks, c->nvblk, c->pre_gather_blocks() + c->pre_task_blocks(),
-                                  nblk(c->n_r, 4), c->nvblk};
+                                  nblk(c->n_r, 4), c->nvblk, c->local_iters > 0 ? c->n_local_sys : 0};
+      if (c->local_iters > 0) loc_nt = std::max(loc_nt, c->loc_nt);
       for (int g = 0; g < NG; ++g) {
         const int64_t next = h_off[g * (cap + 1) + k] + blocks[g];
         if (next > INT32_MAX / 2) throw Fail(COARSE_EINVAL, "lock-step batch too large for one launch");
@@ -1552,6 +1558,7 @@ struct coarse_batch {
   }
 
   // one lock step of every live solve: seven launches whatever the batch size
+  // (eight when some of the solves use inexact local solves)
   template <typename T>
   void lock_step_t() {
     const int n = (int)live.size();
@@ -1566,6 +1573,15 @@ struct coarse_batch {
     if (n_rows > 0)
       hipLaunchKernelGGL(k_combine<T>, dim3(nblk((int64_t)n_rows * TILE, 256)), dim3(256), 0, main,
                          (const Seg *)(d_seg + cap), n, n_rows, (const int *)nullptr);
+    // inexact local solves of the solves that use them
+    if (grid[G_LOC] > 0) {
+      if (precision == COARSE_FP64)
+        hipLaunchKernelGGL((k_local_pcg_grp<double, T>), dim3(grid[G_LOC]), dim3(loc_nt), 0, main,
+                           (const IterDev *)d_iter, off + 5 * L, n);
+      else
+        hipLaunchKernelGGL((k_local_pcg_grp<float, T>), dim3(grid[G_LOC]), dim3(loc_nt), 0, main,
+                           (const IterDev *)d_iter, off + 5 * L, n);
+    }
     hipLaunchKernelGGL(k_final_grp<T>, dim3(grid[G_FIN]), dim3(VW), fin_lds, main, (const IterDev *)d_iter,
                        off + 4 * L, n);
   }

@@ -87,6 +87,15 @@ struct OpDev {
                               // with non-temporal loads
 };
 
+// One local system of the inexact local solves, A_p in ELL form: entry (k, i) of
+// the system at ell_off + k * npad + i (values; the column words, two uint16
+// columns each, at ell_off / 2 + (k / 2) * npad + i).
+struct LocSys {
+  int64_t ell_off;
+  int32_t vec_off;   // offset of R_p in the packed vectors (sub_idx, rp, zp, diag)
+  int32_t n, npad, pad;
+};
+
 // The per-iteration state of one solve, for launches that cover every solve of
 // a lock-step batch (T-typed arrays are float or double by the batch precision).
 struct IterDev {
@@ -105,6 +114,12 @@ struct IterDev {
   int32_t ntask, bx1, bxy1, flexible;
   int32_t n_bv;      // box vertices of the full reduced grid
   int32_t y_lds;     // 1: the final kernel stages the reduced solution in LDS
+  // inexact local solves (loc_iters > 0): n_loc systems, W entries per row
+  const LocSys *loc_sys;
+  const double *loc_diag;
+  const uint32_t *loc_col;
+  const void *loc_val;   // double (FP64 contexts) or float
+  int32_t loc_w, loc_iters, n_loc, pad_loc;
 };
 
 }  // namespace coarse

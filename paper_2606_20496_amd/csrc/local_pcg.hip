@@ -24,13 +24,6 @@ namespace coarse {
 constexpr int LOC_WMAX = 26;       // off-diagonal entries per row of A_p at most
 constexpr int LOC_NT_MAX = 1024;   // rows of a subdomain at most (one thread each)
 
-struct LocSys {
-  int64_t ell_off;   // first entry of the system's ELL block (values; the
-                     // column words start at ell_off / 2)
-  int32_t vec_off;   // offset of R_p in the packed vectors (sub_idx, rp, zp, diag)
-  int32_t n, npad, pad;
-};
-
 // Position of internal vertex u in the sorted list R[0..n), or -1.
 __device__ __forceinline__ int loc_find(const int32_t *__restrict__ R, int n, int32_t u) {
   int lo = 0, hi = n - 1;
@@ -196,15 +189,10 @@ __device__ __forceinline__ double loc_block_sum(double v, double *red, int nw) {
 // T: the type of the packed right-hand sides; V: the stored entries of A_p.
 // ---------------------------------------------------------------------------
 template <typename V, typename T>
-__global__ __launch_bounds__(LOC_NT_MAX) void k_local_pcg(const LocSys *__restrict__ sys, int W, int iters,
-                                                          const int *__restrict__ done, const T *__restrict__ rp,
-                                                          const double *__restrict__ diag,
-                                                          const uint32_t *__restrict__ col,
-                                                          const V *__restrict__ val, double *__restrict__ zp) {
-  if (*done) return;
-  __shared__ double sz[LOC_NT_MAX];
-  __shared__ double red[2][LOC_NT_MAX / WAVE];
-  const LocSys S = sys[blockIdx.x];
+__device__ __forceinline__ void local_pcg_body(const LocSys &S, int W, int iters, const T *__restrict__ rp,
+                                               const double *__restrict__ diag, const uint32_t *__restrict__ col,
+                                               const V *__restrict__ val, double *__restrict__ zp, double *sz,
+                                               double (*red)[LOC_NT_MAX / WAVE]) {
   const int i = threadIdx.x;
   const int nw = blockDim.x / WAVE;
   const bool act = i < S.n;
@@ -254,6 +242,33 @@ __global__ __launch_bounds__(LOC_NT_MAX) void k_local_pcg(const LocSys *__restri
     rz = loc_block_sum(r * z, red[0], nw);
   }
   if (act) zp[S.vec_off + i] = x;
+}
+
+template <typename V, typename T>
+__global__ __launch_bounds__(LOC_NT_MAX) void k_local_pcg(const LocSys *__restrict__ sys, int W, int iters,
+                                                          const int *__restrict__ done, const T *__restrict__ rp,
+                                                          const double *__restrict__ diag,
+                                                          const uint32_t *__restrict__ col,
+                                                          const V *__restrict__ val, double *__restrict__ zp) {
+  if (*done) return;
+  __shared__ double sz[LOC_NT_MAX];
+  __shared__ double red[2][LOC_NT_MAX / WAVE];
+  local_pcg_body<V, T>(sys[blockIdx.x], W, iters, rp, diag, col, val, zp, sz, red);
+}
+
+// The same for every solve of a lock-step batch that uses inexact local solves:
+// workgroup g works for the solve whose range of `off` holds g (its local system
+// g - off[c]). blockDim.x >= the largest n of every such solve.
+template <typename V, typename T>
+__global__ __launch_bounds__(LOC_NT_MAX) void k_local_pcg_grp(const IterDev *__restrict__ ctx,
+                                                              const int32_t *__restrict__ off, int n) {
+  __shared__ double sz[LOC_NT_MAX];
+  __shared__ double red[2][LOC_NT_MAX / WAVE];
+  const int c = find_ctx(off, n, blockIdx.x);
+  const IterDev &d = ctx[c];
+  if (d.sc->done) return;
+  local_pcg_body<V, T>(d.loc_sys[blockIdx.x - off[c]], d.loc_w, d.loc_iters, (const T *)d.rp, d.loc_diag, d.loc_col,
+                       (const V *)d.loc_val, (double *)d.zp, sz, red);
 }
 
 }  // namespace coarse

@@ -168,7 +168,8 @@ class Server:
         t0 = time.perf_counter()
         m = _mesh_of(mesh)
         t1 = time.perf_counter()
-        need = self.estimate_bytes(m, self.precision, self.solver_kw.get("projection", 0))
+        need = self.estimate_bytes(m, self.precision, self.solver_kw.get("projection", 0),
+                                   self.solver_kw.get("local_iters", 0))
         plan = self._plan(mesh)
         self.setup_times["mesh_s"].append(t1 - t0)
         self.setup_times["plan_s"].append(time.perf_counter() - t1)
@@ -224,9 +225,10 @@ class Server:
         return self.used + need <= self.budget
 
     @staticmethod
-    def estimate_bytes(mesh, precision, projection=0):
+    def estimate_bytes(mesh, precision, projection=0, local_iters=0):
         """Rough device footprint of a context before it exists: element data, the
-        stored inverses (packed symmetric, padded to 32), vectors and the basis of
+        stored inverses (packed symmetric, padded to 32) or, with inexact local
+        solves, the sparse A_p (26 entries per row), vectors and the basis of
         `projection` prior solutions (and their products with A)."""
         E, n = mesh.n_elem, mesh.n_vert
         vol = E / max(mesh.n_part, 1)
@@ -234,6 +236,12 @@ class Server:
         nb = np.ceil(np_ / 32)
         tiles = mesh.n_part * nb * (nb + 1) / 2
         es = {"fp64": 8, "mixed": 4, "mixed16": 2}[precision]
+        if local_iters > 0:
+            ev = 8 if precision == "fp64" else 4
+            rows = mesh.n_part * np_
+            loc = rows * (26 * (ev + 2) + 8 + 32) * 1.1
+            nbr = np.ceil(np.prod([b + 1 for b in mesh.boxes]) / 32)   # reduced system's tile rows
+            return int(E * 420 + n * 200 + loc + nbr * (nbr + 1) / 2 * 1024 * es + 16 * projection * n)
         return int(E * 420 + n * 200 + tiles * 1024 * es * 1.1 + tiles * 32 * es + 16 * projection * n)
 
     def run(self, requests, t0=None, progress=None, progress_every=10.0):

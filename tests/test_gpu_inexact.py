@@ -137,8 +137,6 @@ def test_inexact_rejected_where_unsupported():
     S = coarse.CoarseSolver.from_mesh(m, local_iters=2)
     with pytest.raises(coarse.CoarseError):
         S.solve_multi(torch.stack([_gpu(m.b), _gpu(m.b)], 0))
-    with pytest.raises(coarse.CoarseError):
-        coarse.solve_batch([S], [_gpu(m.b)])
     # subdomains of more than 1024 free vertices
     big = mg.box_mesh(20, 34, block=10, boxes=(2, 2, 2))
     with pytest.raises(coarse.CoarseError) as ei:
@@ -159,3 +157,64 @@ def test_inexact_cube64():
     _, io = P.solve(m.b, tol=1e-8, flexible=True)
     u, st = S.solve(_gpu(m.b), tol=1e-8)
     assert st["code"] == 0 and st["iters"] == io["iters"] and st["relres_true"] <= 1.01e-8
+
+
+def _batch_case(precision):
+    # batch-workload meshes (n <= 24, blocks of 4, 6 or 8 elements); every other
+    # context uses inexact local solves, with different step counts
+    ms = mg.batch_meshes(count=8, nmax=24)
+    kw = [dict(local_iters=(0 if j % 2 else 2 + j)) for j in range(len(ms))]
+    return ms, kw
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("graph", [False, True])
+def test_inexact_in_batch_equals_alone(precision, graph):
+    # the grouped launch of the inexact local solves (one workgroup size for all
+    # solves) gives bitwise the solve alone, beside exact-solve contexts
+    ms, kw = _batch_case(precision)
+    ref = []
+    for m, k in zip(ms, kw):
+        S = coarse.CoarseSolver.from_mesh(m, precision=precision, **k)
+        u, st = S.solve(_gpu(m.b))
+        ref.append((u, st["iters"]))
+    solvers = [coarse.CoarseSolver.from_mesh(m, precision=precision, **k) for m, k in zip(ms, kw)]
+    bs = [_gpu(m.b) for m in ms]
+    us = [torch.zeros_like(b) for b in bs]
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    bt = coarse.Batch(stream=stream, use_graph=graph)
+    done = {}
+    for j in range(4):
+        bt.submit(solvers[j], bs[j], us[j], tag=j)
+    for tag, st in bt.step(3):
+        done[tag] = st
+    for j in range(4, len(ms)):
+        bt.submit(solvers[j], bs[j], us[j], tag=j)
+    guard = 0
+    while bt.live > 0:
+        for tag, st in bt.step(2):
+            done[tag] = st
+        guard += 1
+        assert guard < 1000
+    stream.synchronize()
+    for j in range(len(ms)):
+        assert done[j]["code"] == 0 and done[j]["iters"] == ref[j][1]
+        assert torch.equal(us[j], ref[j][0]), j
+    bt.close()
+
+
+def test_inexact_batch_matches_oracle_and_noalloc():
+    ms, kw = _batch_case("fp64")
+    ms, kw = ms[:4], kw[:4]
+    solvers = [coarse.CoarseSolver.from_mesh(m, **k) for m, k in zip(ms, kw)]
+    bs = [_gpu(m.b) for m in ms]
+    us, sts = coarse.solve_batch(solvers, bs)
+    us2, sts2 = coarse.solve_batch(solvers, bs, noalloc=True)
+    for m, k, u, u2, st, st2 in zip(ms, kw, us, us2, sts, sts2):
+        P = problem.from_mesh(m, **k)
+        uo, io = P.solve(m.b, tol=1e-8, flexible=k["local_iters"] > 0)
+        assert st["iters"] == io["iters"] and st2["iters"] == st["iters"]
+        assert torch.equal(u, u2)
+        # i.i.d. right-hand sides on the batch meshes: the 1e-7 bar of those meshes
+        assert np.linalg.norm(_np(u) - uo) / np.linalg.norm(uo) < 1e-7

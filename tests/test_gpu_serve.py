@@ -18,10 +18,12 @@ def _need_gpu():
     coarse.load()
 
 
-@pytest.mark.parametrize("precision", ["mixed", "fp64"])
-def test_serving_results_equal_solo(precision):
+@pytest.mark.parametrize("precision,local_iters", [("mixed", 0), ("fp64", 0), ("mixed", 6), ("fp64", 6)])
+def test_serving_results_equal_solo(precision, local_iters):
+    # local_iters > 0: every context uses inexact local solves
     reqs = serve.make_requests(rate=400.0, count=24, nmax=20)
-    srv = serve.Server(budget_bytes=2e9, precision=precision, use_graph=True, step_iters=2, keep_outputs=True)
+    srv = serve.Server(budget_bytes=2e9, precision=precision, use_graph=True, step_iters=2, keep_outputs=True,
+                       solver_kw={"local_iters": local_iters})
     records, wall = srv.run(reqs)
     srv.close()
     assert len(records) == len(reqs)
@@ -32,7 +34,7 @@ def test_serving_results_equal_solo(precision):
     solo = {}
     for rq in reqs:
         if rq.key not in solo:
-            solo[rq.key] = coarse.CoarseSolver.from_mesh(rq.mesh, precision=precision)
+            solo[rq.key] = coarse.CoarseSolver.from_mesh(rq.mesh, precision=precision, local_iters=local_iters)
         u, st = solo[rq.key].solve(torch.tensor(rq.b, device="cuda"))
         rec = by_id[rq.rid]
         assert rec.iters == st["iters"]
