@@ -14,7 +14,8 @@
 // 32-bit word. One workgroup solves one subdomain with one thread per row: the
 // row is loaded into registers once and reused by all k steps; the search
 // direction lives in LDS, where the row products gather it. Every sum has a
-// fixed order, so results are bitwise reproducible.
+// fixed order, so results are bitwise reproducible. FP64 contexts run the local
+// CG in FP64; the mixed forms run it in FP32.
 #pragma once
 
 #include "kernels.h"
@@ -150,26 +151,41 @@ __device__ __forceinline__ double loc_dpp(double v) {
   return __hiloint2double(hi, lo);
 }
 
-__device__ __forceinline__ double loc_wave_sum(double v) {
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float loc_dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, false));
+}
+
+__device__ __forceinline__ double loc_lane63(double v) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ float loc_lane63(float v) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+template <typename C>
+__device__ __forceinline__ C loc_wave_sum(C v) {
   v += loc_dpp<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
   v += loc_dpp<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
   v += loc_dpp<0x141, 0xF>(v);   // row_half_mirror
   v += loc_dpp<0x140, 0xF>(v);   // row_mirror
   v += loc_dpp<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
   v += loc_dpp<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
-  return __hiloint2double(hi, lo);
+  return loc_lane63(v);
 }
 
 // Sum over the workgroup, returned to every thread: per-wave sums, then each
 // thread adds the wave sums in wave order. `red` must not be reused before the
 // next barrier of every thread has passed.
-__device__ __forceinline__ double loc_block_sum(double v, double *red, int nw) {
+template <typename C>
+__device__ __forceinline__ C loc_block_sum(C v, C *red, int nw) {
   v = loc_wave_sum(v);
   if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = v;
   __syncthreads();
-  double s = 0.0;
+  C s = C(0);
   for (int w = 0; w < nw; ++w) s += red[w];
   return s;
 }
@@ -186,22 +202,26 @@ __device__ __forceinline__ double loc_block_sum(double v, double *red, int nw) {
 // exchange through LDS: its write goes before the barrier of the (r, z) sum,
 // which then also publishes it, and a step needs two barriers instead of three.
 // blockDim.x >= the largest n (a multiple of 64).
-// T: the type of the packed right-hand sides; V: the stored entries of A_p.
+// T: the type of the packed right-hand sides. V: the stored entries of A_p and
+// the arithmetic of the local CG: double in FP64 contexts; float in the mixed
+// forms, whose local solves are approximations under a flexible outer iteration
+// anyway (half the registers and LDS bytes, so more subdomains share a compute
+// unit).
 // ---------------------------------------------------------------------------
 template <typename V, typename T>
 __device__ __forceinline__ void local_pcg_body(const LocSys &S, int W, int iters, const T *__restrict__ rp,
                                                const double *__restrict__ diag, const uint32_t *__restrict__ col,
-                                               const V *__restrict__ val, double *__restrict__ zp, double *sz,
-                                               double (*red)[LOC_NT_MAX / WAVE]) {
+                                               const V *__restrict__ val, double *__restrict__ zp, V *sz,
+                                               V (*red)[LOC_NT_MAX / WAVE]) {
   const int i = threadIdx.x;
   const int nw = blockDim.x / WAVE;
   const bool act = i < S.n;
   V a[LOC_WMAX];
   uint32_t c[LOC_WMAX / 2];
-  double d = 1.0, r = 0.0;
+  V d = V(1), r = V(0);
   if (act) {
-    r = (double)rp[S.vec_off + i];
-    d = diag[S.vec_off + i];
+    r = (V)rp[S.vec_off + i];
+    d = (V)diag[S.vec_off + i];
 #pragma unroll
     for (int k = 0; k < LOC_WMAX; k += 2)
       if (k < W) {
@@ -210,29 +230,29 @@ __device__ __forceinline__ void local_pcg_body(const LocSys &S, int W, int iters
         a[k + 1] = val[S.ell_off + (int64_t)(k + 1) * S.npad + i];
       }
   }
-  const double dinv = 1.0 / d;
-  double x = 0.0, p = 0.0, q = 0.0;
-  double z = dinv * r;
+  const V dinv = V(1) / d;
+  V x = V(0), p = V(0), q = V(0);
+  V z = dinv * r;
   sz[i] = z;
-  double rz = loc_block_sum(r * z, red[0], nw);
-  double rz_old = 1.0;
+  V rz = loc_block_sum(r * z, red[0], nw);
+  V rz_old = V(1);
   for (int it = 0; it < iters; ++it) {
-    if (rz == 0.0) break;
-    double s = 0.0;
+    if (rz == V(0)) break;
+    V s = V(0);
     if (act) {
       s = d * z;
 #pragma unroll
       for (int k = 0; k < LOC_WMAX; k += 2)
         if (k < W) {
-          s += (double)a[k] * sz[c[k / 2] & 0xFFFF];
-          s += (double)a[k + 1] * sz[c[k / 2] >> 16];
+          s += a[k] * sz[c[k / 2] & 0xFFFF];
+          s += a[k + 1] * sz[c[k / 2] >> 16];
         }
     }
-    const double beta = it == 0 ? 0.0 : rz / rz_old;
+    const V beta = it == 0 ? V(0) : rz / rz_old;
     p = z + beta * p;
     q = s + beta * q;
-    const double pq = loc_block_sum(p * q, red[1], nw);
-    const double alpha = rz / pq;
+    const V pq = loc_block_sum(p * q, red[1], nw);
+    const V alpha = rz / pq;
     x += alpha * p;
     r -= alpha * q;
     if (it == iters - 1) break;
@@ -241,7 +261,7 @@ __device__ __forceinline__ void local_pcg_body(const LocSys &S, int W, int iters
     rz_old = rz;
     rz = loc_block_sum(r * z, red[0], nw);
   }
-  if (act) zp[S.vec_off + i] = x;
+  if (act) zp[S.vec_off + i] = (double)x;
 }
 
 template <typename V, typename T>
@@ -251,8 +271,8 @@ __global__ __launch_bounds__(LOC_NT_MAX) void k_local_pcg(const LocSys *__restri
                                                           const uint32_t *__restrict__ col,
                                                           const V *__restrict__ val, double *__restrict__ zp) {
   if (*done) return;
-  __shared__ double sz[LOC_NT_MAX];
-  __shared__ double red[2][LOC_NT_MAX / WAVE];
+  __shared__ V sz[LOC_NT_MAX];
+  __shared__ V red[2][LOC_NT_MAX / WAVE];
   local_pcg_body<V, T>(sys[blockIdx.x], W, iters, rp, diag, col, val, zp, sz, red);
 }
 
@@ -262,8 +282,8 @@ __global__ __launch_bounds__(LOC_NT_MAX) void k_local_pcg(const LocSys *__restri
 template <typename V, typename T>
 __global__ __launch_bounds__(LOC_NT_MAX) void k_local_pcg_grp(const IterDev *__restrict__ ctx,
                                                               const int32_t *__restrict__ off, int n) {
-  __shared__ double sz[LOC_NT_MAX];
-  __shared__ double red[2][LOC_NT_MAX / WAVE];
+  __shared__ V sz[LOC_NT_MAX];
+  __shared__ V red[2][LOC_NT_MAX / WAVE];
   const int c = find_ctx(off, n, blockIdx.x);
   const IterDev &d = ctx[c];
   if (d.sc->done) return;
