@@ -171,6 +171,15 @@ typedef struct {
                        COARSE_EINVAL at setup). Block solves (coarse_solve_multi,
                        coarse_multi_*) reject such a context (COARSE_EINVAL);
                        single solves and lock-step batches take it             */
+  int reduced_refine; /* 1: after each reduced solve y = A_r^{-1} r_r, one step of
+                       iterative refinement y += A_r^{-1} (r_r - A_r y), the
+                       residual formed in FP64 by the 27-point stencil of A_r on
+                       the box grid (Sec. 4, eq. (Aij)) and the correction by the
+                       same stored inverse: brings the FP32 or FP16-stored reduced
+                       solve of the mixed forms to about FP64 accuracy. Centroid
+                       interpolation only (else COARSE_EINVAL at setup); block
+                       solves and lock-step batches reject such a context.
+                       0 (default): no refinement                              */
 } coarse_opts;
 
 typedef struct {
@@ -218,6 +227,7 @@ typedef struct {
                              row of A_p (even; the largest row count rounded up);
                              local_bytes then counts the stored A_p (ELL entries
                              and diagonals), not inverses                         */
+  int32_t reduced_refine; /* opts.reduced_refine of the context                   */
 } coarse_info_t;
 
 /* Fill *o with the defaults: overlap 1, boxes auto, FP64, additive, centroid J,
@@ -400,6 +410,17 @@ size_t coarse_device_bytes(const coarse_ctx *ctx);
 
 /* Sizes of the built context. */
 int coarse_get_info(const coarse_ctx *ctx, coarse_info_t *info);
+
+/* w = A_r y with the 27-point stencil of the reduced operator on the structured
+ * box grid (Sec. 4, eq. (Aij): the cell-assembled A_r of the centroid
+ * interpolation couples a box vertex only with box vertices at most one box away
+ * per direction). y and w are device arrays of (b_x+1)(b_y+1)(b_z+1) doubles,
+ * box vertex (i, j, k) at i + (b_x+1)(j + (b_y+1)k) (coarse_info_t.boxes gives
+ * b); w is written at every box vertex, 0 at the inactive ones (those that hold
+ * no reduced unknown), and y is not read there. Ordered on the context's stream.
+ * COARSE_EINVAL for a context with the standard interpolation (its Galerkin A_r
+ * has a wider stencil) or without reduced unknowns. */
+int coarse_apply_reduced_operator(coarse_ctx *ctx, const double *y, double *w);
 
 /* Change the stream used by later calls on this context. */
 int coarse_set_stream(coarse_ctx *ctx, void *stream);

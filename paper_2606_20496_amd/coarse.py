@@ -33,7 +33,7 @@ EXPORTS = ("coarse_default_opts", "coarse_setup", "coarse_apply_precond", "coars
            "coarse_setup_from_plan", "coarse_plan_destroy", "coarse_plan_set_gemv_tiles",
            "coarse_solve_projected", "coarse_projection_reset", "coarse_solve_multi",
            "coarse_apply_precond_multi", "coarse_multi_begin", "coarse_multi_advance", "coarse_multi_done",
-           "coarse_multi_end", "coarse_solve_batch_noalloc")
+           "coarse_multi_end", "coarse_solve_batch_noalloc", "coarse_apply_reduced_operator")
 NOALLOC_MAX_SOLVES = 256   # COARSE_NOALLOC_MAX_SOLVES
 
 PHASES = ("A+p", "R_p+J^T", "J^T corners", "A_p^-1/A_r^-1 gemv", "combine", "sum+J", "x,r update",
@@ -93,7 +93,8 @@ class _Opts(ctypes.Structure):
                 ("mode", ctypes.c_int), ("interp", ctypes.c_int), ("max_it", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("flexible", ctypes.c_int), ("stream", ctypes.c_void_p),
                 ("gemv_tiles", ctypes.c_int * GEMV_BUCKETS), ("projection", ctypes.c_int),
-                ("whole_waves", ctypes.c_int), ("block_rhs", ctypes.c_int), ("local_iters", ctypes.c_int)]
+                ("whole_waves", ctypes.c_int), ("block_rhs", ctypes.c_int), ("local_iters", ctypes.c_int),
+                ("reduced_refine", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -111,7 +112,7 @@ class _Info(ctypes.Structure):
                 ("boxes", ctypes.c_int32 * 3), ("precision", ctypes.c_int32),
                 ("gemv_tiles", ctypes.c_int32 * GEMV_BUCKETS), ("whole_waves", ctypes.c_int32),
                 ("reduced_stream", ctypes.c_int32), ("local_iters", ctypes.c_int32),
-                ("ell_width", ctypes.c_int32)]
+                ("ell_width", ctypes.c_int32), ("reduced_refine", ctypes.c_int32)]
 
 
 _lib = None
@@ -139,6 +140,8 @@ def load():
     L.coarse_apply_precond.restype = i32
     L.coarse_apply_A.argtypes = [vp, vp, vp]
     L.coarse_apply_A.restype = i32
+    L.coarse_apply_reduced_operator.argtypes = [vp, vp, vp]
+    L.coarse_apply_reduced_operator.restype = i32
     L.coarse_solve.argtypes = [vp, vp, vp, dbl, ctypes.POINTER(_Stats)]
     L.coarse_solve.restype = i32
     L.coarse_solve_projected.argtypes = [vp, vp, vp, dbl, ctypes.POINTER(_Stats)]
@@ -217,7 +220,7 @@ def _arrays(xyz, e2v, dirichlet, part, n_part):
 
 
 def _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible, stream, gemv_tiles=None,
-          projection=0, block_rhs=0, whole_waves=None, local_iters=0):
+          projection=0, block_rhs=0, whole_waves=None, local_iters=0, reduced_refine=0):
     o = _Opts()
     load().coarse_default_opts(ctypes.byref(o))
     o.overlap = int(overlap)
@@ -241,6 +244,7 @@ def _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible
     o.block_rhs = int(bool(block_rhs))
     o.whole_waves = whole_waves_choice(precision) if whole_waves is None else int(whole_waves)
     o.local_iters = int(local_iters)
+    o.reduced_refine = int(bool(reduced_refine))
     return o
 
 
@@ -278,14 +282,15 @@ class Plan:
 
     def __init__(self, xyz, e2v, dirichlet, part=None, n_part=1, *, overlap=1, boxes=None,
                  precision="fp64", mode="additive", interp="centroid", max_it=1000, check_every=4,
-                 flexible=None, gemv_tiles=None, projection=0, block_rhs=0, whole_waves=None, local_iters=0):
+                 flexible=None, gemv_tiles=None, projection=0, block_rhs=0, whole_waves=None, local_iters=0,
+                 reduced_refine=0):
         L = load()
         self._L = L
         self.n_vert = int(np.asarray(xyz).shape[0])
         self.precision = precision
         m, bc, keep = _arrays(xyz, e2v, dirichlet, part, n_part)
         o = _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible, None, gemv_tiles,
-                  projection, block_rhs, whole_waves, local_iters)
+                  projection, block_rhs, whole_waves, local_iters, reduced_refine)
         pl = ctypes.c_void_p()
         rc = L.coarse_plan_create(ctypes.byref(m), ctypes.byref(bc), ctypes.byref(o), ctypes.byref(pl))
         if rc != 0:
@@ -325,7 +330,8 @@ class CoarseSolver:
 
     def __init__(self, xyz, e2v, dirichlet, part=None, n_part=1, *, overlap=1, boxes=None,
                  precision="fp64", mode="additive", interp="centroid", max_it=1000, check_every=4,
-                 flexible=None, gemv_tiles=None, projection=0, block_rhs=0, whole_waves=None, local_iters=0):
+                 flexible=None, gemv_tiles=None, projection=0, block_rhs=0, whole_waves=None, local_iters=0,
+                 reduced_refine=0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("CoarseSolver needs a GPU; no CPU fallback exists")
@@ -335,7 +341,7 @@ class CoarseSolver:
         self.precision = precision
         m, bc, keep = _arrays(xyz, e2v, dirichlet, part, n_part)
         o = _opts(overlap, boxes, precision, mode, interp, max_it, check_every, flexible, _stream(), gemv_tiles,
-                  projection, block_rhs, whole_waves, local_iters)
+                  projection, block_rhs, whole_waves, local_iters, reduced_refine)
         ctx = ctypes.c_void_p()
         rc = L.coarse_setup(ctypes.byref(m), ctypes.byref(bc), ctypes.byref(o), ctypes.byref(ctx))
         if rc != 0:
@@ -398,6 +404,21 @@ class CoarseSolver:
         self._sync_stream()
         out = torch.empty_like(p) if out is None else out
         self._check(self._L.coarse_apply_A(self._ctx, self._vec(p), self._vec(out)))
+        return out
+
+    def apply_reduced_operator(self, y, out=None):
+        """w = A_r y by the 27-point stencil on the box grid: y and w are float64
+        GPU tensors of (b_x+1)(b_y+1)(b_z+1) entries, box vertex (i, j, k) at
+        i + (b_x+1)(j + (b_y+1)k); w is 0 at inactive box vertices."""
+        import torch
+        self._sync_stream()
+        nbv = int(np.prod([b + 1 for b in self.info["boxes"]]))
+        if not (isinstance(y, torch.Tensor) and y.is_cuda and y.dtype == torch.float64 and y.is_contiguous()
+                and y.numel() == nbv):
+            raise ValueError(f"expected a contiguous float64 GPU tensor of {nbv} box-vertex values")
+        out = torch.empty_like(y) if out is None else out
+        self._check(self._L.coarse_apply_reduced_operator(self._ctx, ctypes.c_void_p(y.data_ptr()),
+                                                          ctypes.c_void_p(out.data_ptr())))
         return out
 
     def _solve(self, fn, b, tol, out):

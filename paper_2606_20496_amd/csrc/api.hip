@@ -3,6 +3,7 @@
 #include "kernels.hip"
 #include "multi.hip"
 #include "local_pcg.hip"
+#include "stencil.hip"
 #include "capture_guard.h"
 
 #include <algorithm>
@@ -266,6 +267,18 @@ struct coarse_ctx {
 
   // inexact local solves (local_iters > 0): A_p in ELL form, one workgroup of
   // loc_nt threads per subdomain
+  // the reduced operator as a 27-point stencil on the box grid (centroid J), and
+  // the refinement of the reduced solve (reduced_refine): its right-hand side,
+  // solution and box-grid correction, and a copy of the system table that
+  // points the reduced system at them
+  double *ar_coef = nullptr;
+  BoxGrid bgrid{};
+  int reduced_refine = 0;
+  void *r_res = nullptr;
+  double *zcorr = nullptr, *ycorr = nullptr;
+  SysDev *sysdev_corr = nullptr;
+  Seg *seg_coarse_corr = nullptr;
+
   int local_iters = 0, loc_w = 0, loc_nt = 0;
   LocSys *locsys = nullptr;
   double *loc_diag = nullptr;
@@ -421,6 +434,21 @@ struct coarse_ctx {
     gemv_combine(segs, nitems, nrows, nwhole, done, stream, 3, 4);
   }
 
+  // one step of iterative refinement of the reduced solve just made on stream s:
+  // the residual r_r - A_r y by the stencil sweep, its solve with the same
+  // stored inverse, and y += the correction
+  template <typename T>
+  void refine_reduced(const int *done, hipStream_t s) {
+    if (!reduced_refine || n_r <= 0) return;
+    hipLaunchKernelGGL(k_ar_resid<T>, dim3(nblk(n_r, 256)), dim3(256), 0, s, n_r, done, (const int32_t *)act_bv,
+                       (const double *)ar_coef, bgrid, (const double *)yfull, (const T *)rp + coarse_vec_off,
+                       (T *)r_res);
+    gemv_combine(seg_coarse_corr, items_total - items_local, rows_total - rows_local, whole_total - whole_local, done,
+                 s, -1, -1);
+    hipLaunchKernelGGL(k_ar_add, dim3(nblk(n_r, 256)), dim3(256), 0, s, n_r, done, (const int32_t *)act_bv,
+                       (const double *)ycorr, yfull);
+  }
+
   // the local solves of one application on the context's stream: the stored
   // inverses, or local_iters steps of Jacobi-PCG per subdomain (phase 3 either way)
   template <typename T>
@@ -475,6 +503,7 @@ struct coarse_ctx {
         corners<T>(done);
         pend(2);
         gemv_combine(seg_all, items_total, rows_total, whole_total, done);
+        refine_reduced<T>(done, stream);
         final_step<T>(add, local, coarse, out, rdot, p1, p2, done, scal, start);
         return;
       }
@@ -491,6 +520,7 @@ struct coarse_ctx {
       corners<T>(done, aux);
       gemv_combine(seg_coarse, items_total - items_local, rows_total - rows_local, whole_total - whole_local, done, aux,
                    -1, -1);
+      refine_reduced<T>(done, aux);
       pend(7, aux);
       HIPCHK(hipEventRecord(ev_join, aux));
       local_part<T>(done);
@@ -507,8 +537,10 @@ struct coarse_ctx {
     }
     if (local && !coarse)
       local_part<T>(done);
-    else if (coarse && !local)
+    else if (coarse && !local) {
       gemv_combine(seg_coarse, items_total - items_local, rows_total - rows_local, whole_total - whole_local, done);
+      refine_reduced<T>(done, stream);
+    }
     final_step<T>(add, local, coarse, out, rdot, p1, p2, done, scal, start);
   }
 
@@ -1141,11 +1173,21 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles, int wh
   c->corner_act = A.upload(P.occ_corner_act, s);
   int32_t *ar_ptr = tmp.upload(P.ar_ptr, s);
   int32_t *ar_src = tmp.upload(P.ar_src, s);
+  c->act_bv = A.upload(P.act_bv, s);
+  c->bgrid = BoxGrid{P.b[0] + 1, P.b[1] + 1, P.b[2] + 1, 0};
   std::vector<int64_t> red = {P.n_local_sys};
   const int64_t nr = P.n_r;
   if (c->interp == COARSE_J_CENTROID) {
     hipLaunchKernelGGL(k_cell_mats, dim3((unsigned)nocc), dim3(64), 0, s, box, occ_cells, occ_ptr, occ_elems, e2v, NE,
                        NV, nf, xyz, (const double *)Ae, cellmat);
+    // A_r also as its 27-point stencil on the box grid
+    if (nr > 0) {
+      c->ar_coef = A.alloc<double>(27 * nr);
+      HIPCHK(hipMemsetAsync(c->ar_coef, 0, 27 * nr * sizeof(double), s));
+      hipLaunchKernelGGL(k_ar_stencil_build, dim3(nblk(nr, 256)), dim3(256), 0, s, nr, (const int32_t *)ar_ptr,
+                         (const int32_t *)ar_src, (const int32_t *)c->corner_act, (const int32_t *)occ_cells,
+                         (const int32_t *)c->act_bv, c->bgrid, P.b[0], P.b[1], (const double *)cellmat, c->ar_coef);
+    }
     nbad = invert_systems<TT>(c, sysv, red, tiles, scratch_tiles, sys_scale, [&](AsmSys *, int, double *M) {
       hipLaunchKernelGGL(k_assemble_reduced, dim3(nblk(nr, 256)), dim3(256), 0, s, nr, ar_ptr, ar_src,
                          (const int32_t *)c->corner_act, (const double *)cellmat, M);
@@ -1199,7 +1241,6 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles, int wh
   c->yfull = A.alloc<double>(P.n_bv);
   c->y_lds = (P.n_bv * (int64_t)sizeof(double) <= kYLdsMaxBytes) ? 1 : 0;
   HIPCHK(hipMemsetAsync(c->yfull, 0, P.n_bv * sizeof(double), s));
-  c->act_bv = A.upload(P.act_bv, s);
   c->bx1 = P.b[0] + 1;
   c->bxy1 = (P.b[0] + 1) * (P.b[1] + 1);
 
@@ -1287,6 +1328,22 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles, int wh
   c->seg_local = A.upload(std::vector<Seg>{c->h_seg_local}, s);
   c->reduced_aside = P.n_r > 0 && P.sys[P.n_local_sys].nb > WHOLE_NB_MAX;
   c->seg_coarse = A.upload(std::vector<Seg>{c->h_seg_coarse}, s);
+  if (c->reduced_refine && P.n_r > 0) {
+    const System &R = P.sys[P.n_local_sys];
+    c->r_res = A.alloc<T>(R.nb * TILE);
+    HIPCHK(hipMemsetAsync(c->r_res, 0, R.nb * TILE * sizeof(T), s));
+    c->zcorr = A.alloc<double>(R.nb * TILE);
+    c->ycorr = A.alloc<double>(P.n_bv);
+    HIPCHK(hipMemsetAsync(c->ycorr, 0, P.n_bv * sizeof(double), s));
+    std::vector<SysDev> sc = sd;
+    sc[P.n_local_sys].rp = c->r_res;
+    sc[P.n_local_sys].zp = c->zcorr;
+    sc[P.n_local_sys].yfull = c->ycorr;
+    c->sysdev_corr = A.upload(sc, s);
+    Seg h = c->h_seg_coarse;
+    h.sys = c->sysdev_corr;
+    c->seg_coarse_corr = A.upload(std::vector<Seg>{h}, s);
+  }
 
   // reduced-space interpolation entries
   c->nent = (int64_t)P.jv_w.size();
@@ -1326,6 +1383,7 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles, int wh
     in.inv_alg_bytes += P.sys[k].n * (P.sys[k].n + 1) / 2 * (int64_t)sizeof(TT);
   in.local_iters = c->local_iters;
   in.ell_width = c->loc_w;
+  in.reduced_refine = c->reduced_refine;
   if (inexact) {
     // ELL values and column words, and the diagonals
     const int64_t vb = std::is_same<TT, double>::value ? 8 : 4;
@@ -1474,6 +1532,10 @@ struct coarse_batch {
   int submit(coarse_ctx *c, const double *b, double *u, double tol, int64_t tag) {
     if (c->mode != COARSE_ADDITIVE) {
       err = "batched solves use the additive preconditioner";
+      return COARSE_EINVAL;
+    }
+    if (c->reduced_refine) {
+      err = "batched solves do not refine the reduced solve (opts.reduced_refine = 0)";
       return COARSE_EINVAL;
     }
     if (precision >= 0 && c->precision != precision) {
@@ -1741,8 +1803,8 @@ int check_multi(coarse_ctx *c, int k) {
     c->err = "the block solve needs a context with the additive preconditioner";
     return COARSE_EINVAL;
   }
-  if (c->local_iters > 0) {
-    c->err = "the block solve needs exact local solves (opts.local_iters = 0)";
+  if (c->local_iters > 0 || c->reduced_refine) {
+    c->err = "the block solve needs exact local solves and no reduced refinement";
     return COARSE_EINVAL;
   }
   if ((OP_BLOCK * 8 + c->max_slots * MCW) * (int64_t)sizeof(double) > 65536) {
@@ -1829,6 +1891,10 @@ int coarse_plan_create(const coarse_mesh *mesh, const coarse_bc *bc, const coars
     g_setup_error = "local_iters must be in [0, 10000]";
     return COARSE_EINVAL;
   }
+  if (o.reduced_refine && o.interp != COARSE_J_CENTROID) {
+    g_setup_error = "reduced_refine needs the centroid interpolation (27-point A_r)";
+    return COARSE_EINVAL;
+  }
   try {
     const double t0 = now();
     std::unique_ptr<coarse_plan> pl(new coarse_plan());
@@ -1899,6 +1965,7 @@ int coarse_setup_from_plan(const coarse_plan *plan, void *stream, coarse_ctx **o
   // are not linear in r (their CG coefficients depend on it): the flexible beta
   c->flexible = (o.flexible || o.mode == COARSE_HYBRID || o.local_iters > 0) ? 1 : 0;
   c->local_iters = o.local_iters;
+  c->reduced_refine = o.reduced_refine ? 1 : 0;
   c->proj_max = o.projection;
   try {
     HIPCHK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
@@ -1956,6 +2023,23 @@ int coarse_apply_A(coarse_ctx *c, const double *p, double *q) {
     c->apply_op(c->p, c->q, nullptr, c->zero_flag);
     hipLaunchKernelGGL(k_permute_out, dim3(nblk(c->nv, VB)), dim3(VB), 0, c->stream, c->nv, c->nf, c->vint_of_user,
                        c->q, q);
+    HIPCHK(hipGetLastError());
+  } catch (const Fail &f) {
+    return fail_ctx(c, f);
+  }
+  return COARSE_OK;
+}
+
+int coarse_apply_reduced_operator(coarse_ctx *c, const double *y, double *w) {
+  if (!c || !y || !w || y == w) return COARSE_EINVAL;
+  if (!c->ar_coef) {
+    c->err = "no stencil of A_r (standard interpolation, or no reduced unknowns)";
+    return COARSE_EINVAL;
+  }
+  try {
+    HIPCHK(hipMemsetAsync(w, 0, c->n_bv * sizeof(double), c->stream));
+    hipLaunchKernelGGL(k_ar_apply, dim3(nblk(c->n_r, 256)), dim3(256), 0, c->stream, c->n_r,
+                       (const int32_t *)c->act_bv, (const double *)c->ar_coef, c->bgrid, y, w);
     HIPCHK(hipGetLastError());
   } catch (const Fail &f) {
     return fail_ctx(c, f);
