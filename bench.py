@@ -72,14 +72,14 @@ def _traffic(workload):
     return t["bytes"] if t and _gemv_source_fingerprint() == t["src"] else None
 
 
-def run_form(torch, coarse, mesh, rhs, precision, steps, warmup, tol, local_iters=0):
+def run_form(torch, coarse, mesh, rhs, precision, steps, warmup, tol, local_iters=0, **solver_kw):
     """Set up once, then time `steps` solves, each on its own right-hand side (all
     resident on the GPU). Only the dominant kernel is bracketed by HIP events in
     the timed region; a separate pass afterwards times every phase. local_iters
     > 0: inexact local solves (that many Jacobi-PCG steps per subdomain), whose
     launch is then the one timed."""
     t0 = time.perf_counter()
-    S = coarse.CoarseSolver.from_mesh(mesh, precision=precision, local_iters=local_iters)
+    S = coarse.CoarseSolver.from_mesh(mesh, precision=precision, local_iters=local_iters, **solver_kw)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     u = torch.empty_like(rhs[0])
@@ -335,6 +335,55 @@ def run_serving_workload(torch, coarse, mg, tol, rates=(50.0, 2000.0), count=409
             _log(f"serving {rate:g} req/s: one at a time {seq['solves_per_s']:.1f}/s p99 {seq['p99_ms']:.0f} ms")
         out["rates"][str(int(rate))] = res
     return out
+
+
+def c5_oracle_subset(torch, coarse, mg, tol, count=64, nmax=40, precision="mixed", rate=2000.0):
+    """The serving workload's oracle check and CPU baseline on a seeded subset:
+    the first `count` requests of the arrival stream whose mesh has n <= nmax
+    (the oracle's setup of the largest meshes takes minutes), served together by
+    the batched server, each checked against the FP64 oracle (iterations within
+    the mixed forms' bar, solution within 1e-6), and the oracle's own rate on them
+    (setup of each distinct mesh plus every solve, one at a time)."""
+    import math as _m
+    import os as _os
+    from oracle import problem
+    from paper_2606_20496_amd import serve
+    t, mesh_id, rhs_seed = mg.serving_arrivals(rate, count=4096)
+    picked, meshes = [], {}
+    for q in range(len(t)):
+        k = int(mesh_id[q])
+        if mg.serving_request_n(k) > nmax:
+            continue
+        if k not in meshes:
+            meshes[k] = mg.serving_request_mesh(k)
+        picked.append(serve.Request(t_arrive=0.0, key=k, mesh=meshes[k], b=mg.rhs_normal(meshes[k], int(rhs_seed[q])),
+                                    rid=q))
+        if len(picked) == count:
+            break
+    srv = serve.Server(64e9, precision=precision, use_graph=True, step_iters=2, keep_outputs=True)
+    rec, wall = srv.run(picked)
+    srv.close()
+    by = {r.rid: r for r in rec}
+    probs, worst, t_setup, t_solve, iters_ok = {}, 0.0, 0.0, 0.0, True
+    for rq in picked:
+        t0 = time.perf_counter()
+        if rq.key not in probs:
+            probs[rq.key] = problem.from_mesh(rq.mesh)
+        t1 = time.perf_counter()
+        uo, io = probs[rq.key].solve(rq.b, tol=tol)
+        t2 = time.perf_counter()
+        t_setup += t1 - t0
+        t_solve += t2 - t1
+        r = by[rq.rid]
+        u = r.u.detach().cpu().numpy()
+        worst = max(worst, float(np.linalg.norm(u - uo) / np.linalg.norm(uo)))
+        iters_ok &= r.status == 0 and r.iters <= max(_m.ceil(1.1 * io["iters"]), io["iters"] + 2)
+    cores = len(_os.sched_getaffinity(0))
+    return {"requests": len(picked), "distinct_meshes": len(probs), "n_max": nmax,
+            "served_solves_per_s": round(len(picked) / wall, 2),
+            "oracle": {"value": round(len(picked) / (t_setup + t_solve), 4), "unit": "solves/s", "cores": cores,
+                       "kind": "oracle", "setup_s": round(t_setup, 2), "solve_s": round(t_solve, 2)},
+            "max_rel_err_u": worst, "iters_within_bar": bool(iters_ok)}
 
 
 INV_ELEM_BYTES = {"fp64": 8, "mixed": 4, "mixed16": 2}
@@ -635,6 +684,8 @@ def main():
                     help="also run --serving with a basis of this many prior solutions per cached mesh")
     ap.add_argument("--serving-local-iters", type=int, default=0,
                     help="also run --serving with inexact local solves of this many steps")
+    ap.add_argument("--serving-oracle-subset", type=int, default=64,
+                    help="requests of the seeded oracle subset of --serving (0: none)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 1 GiB device copy (known bytes) to scale HBM counters")
     args = ap.parse_args()
@@ -667,12 +718,14 @@ def main():
     _log("fp64 form")
     fp64 = run_form(torch, coarse, mesh, rhs, "fp64", args.steps, args.warmup, args.tol)
     _log(f"fp64: {fp64['solves_per_s']:.3f} solves/s, {fp64['iters']} iterations")
-    mixed = mixed16 = None
+    mixed = mixed16 = mixed16r = None
     if not args.no_mixed:
         mixed = run_form(torch, coarse, mesh, rhs, "mixed", args.steps, args.warmup, args.tol)
         _log(f"mixed: {mixed['solves_per_s']:.3f} solves/s, {mixed['iters']} iterations")
         mixed16 = run_form(torch, coarse, mesh, rhs, "mixed16", args.steps, args.warmup, args.tol)
         _log(f"mixed16: {mixed16['solves_per_s']:.3f} solves/s, {mixed16['iters']} iterations")
+        mixed16r = run_form(torch, coarse, mesh, rhs, "mixed16", args.steps, args.warmup, args.tol, reduced_refine=1)
+        _log(f"mixed16, refined reduced solve: {mixed16r['solves_per_s']:.3f} solves/s, {mixed16r['iters']} iterations")
     inexact = None
     ks = tuple(int(x) for x in args.inexact_k.split(",") if x)
     if not args.no_inexact and ks:
@@ -791,6 +844,10 @@ def main():
                                                    if args.serving_sequential_rates else True),
                                        projection=args.serving_projection,
                                        local_iters=args.serving_local_iters)
+        if args.serving_oracle_subset > 0 and not args.no_cpu_baseline:
+            _log("serving: oracle subset")
+            serving["oracle_subset"] = c5_oracle_subset(torch, coarse, mg, args.tol, count=args.serving_oracle_subset)
+            _log(f"serving oracle subset: {serving['oracle_subset']}")
 
     line = {
         "metric": "coarse solves/sec to 1e-8 rel. residual (mixed vs FP64); p50/p99 latency",
@@ -818,6 +875,8 @@ def main():
         "mixed": _form_summary(mixed, "f32 local/reduced inverses, f32 J, f64 operator/vectors/dots", "mixed"),
         "mixed16": _form_summary(mixed16, "f16 storage of the local/reduced inverses (power-of-two scale per "
                                           "system), f32 arithmetic, f32 J, f64 operator/vectors/dots", "mixed16"),
+        "mixed16_refined": _form_summary(mixed16r, "mixed16 with one step of refinement of every reduced solve "
+                                                   "(FP64 residual by the 27-point stencil of A_r)", "mixed16"),
         "kernels": kernels,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -1705,9 +1705,12 @@ __device__ __forceinline__ void final_body(int64_t nf, const int *__restrict__ d
   }
 }
 
-// y_lds = 1: stage the reduced solution (n_bv doubles of dynamic LDS)
+// y_lds = 1: stage the reduced solution (n_bv doubles of dynamic LDS). Held to
+// the register budget of eight wavefronts per SIMD, so that four workgroups fit
+// a compute unit and the 1024-workgroup grid runs in one round (its many pointer
+// arguments otherwise take more scalar registers than eight waves allow).
 template <typename T>
-__global__ __launch_bounds__(VW) void k_final(int64_t nf, const int *__restrict__ done, const double *__restrict__ add,
+__global__ __launch_bounds__(VW) __attribute__((amdgpu_waves_per_eu(8))) void k_final(int64_t nf, const int *__restrict__ done, const double *__restrict__ add,
                                               const int32_t *__restrict__ cover_ptr,
                                               const int32_t *__restrict__ cover_pos, const double *__restrict__ zp,
                                               const int32_t *__restrict__ jv_ptr, const int32_t *__restrict__ jv_base,

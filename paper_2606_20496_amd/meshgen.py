@@ -241,6 +241,13 @@ def batch_meshes(count=64, seed0=4000, nmin=6, nmax=48):
     return out
 
 
+def serving_request_n(k, seed0=5000, nmin=8, nmax=96):
+    """Edge length n of serving request ``k``'s mesh (the first draw that
+    ``serving_request_mesh`` makes), without building the mesh."""
+    rng = np.random.default_rng(seed0 + k)
+    return int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
+
+
 def serving_request_mesh(k, seed0=5000, nmin=8, nmax=96):
     """Mesh of serving request ``k``: n log-uniform in [nmin, nmax], z spacing
     graded by 1.1 per layer with the aspect stretch capped at 20, jitter 0.1 of

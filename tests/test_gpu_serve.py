@@ -166,3 +166,43 @@ def test_resident_serving_with_block_solves(block_rhs):
             assert torch.equal(r.u, u) and r.iters == st["iters"], rq.rid
     assert blocked >= 30
     srv.close()
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_served_stretched_meshes_match_oracle(precision):
+    # the serving workload's own meshes (graded z, stretch up to 20): the first
+    # requests of the arrival stream with n <= 16, served together, against the
+    # FP64 oracle (FP64: the oracle's iteration count; mixed: the mixed forms' bar)
+    import math
+
+    import numpy as np
+
+    from oracle import problem
+    from paper_2606_20496_amd import meshgen as mg
+
+    t, mesh_id, rhs_seed = mg.serving_arrivals(2000.0, count=512)
+    reqs, meshes = [], {}
+    for q in range(len(t)):
+        k = int(mesh_id[q])
+        if mg.serving_request_n(k) > 16:
+            continue
+        meshes.setdefault(k, mg.serving_request_mesh(k))
+        reqs.append(serve.Request(t_arrive=0.0, key=k, mesh=meshes[k], b=mg.rhs_normal(meshes[k], int(rhs_seed[q])),
+                                  rid=q))
+        if len(reqs) == 6:
+            break
+    assert len(reqs) == 6
+    srv = serve.Server(budget_bytes=4e9, precision=precision, use_graph=True, step_iters=2, keep_outputs=True)
+    records, _ = srv.run(reqs)
+    srv.close()
+    by = {r.rid: r for r in records}
+    for rq in reqs:
+        uo, io = problem.from_mesh(rq.mesh).solve(rq.b, tol=1e-8)
+        r = by[rq.rid]
+        assert r.status == 0 and r.relres_true <= 1.01e-8
+        if precision == "fp64":
+            assert r.iters == io["iters"]
+        else:
+            assert r.iters <= max(math.ceil(1.1 * io["iters"]), io["iters"] + 2)
+        u = r.u.detach().cpu().numpy()
+        assert np.linalg.norm(u - uo) / np.linalg.norm(uo) < (1e-7 if precision == "fp64" else 1e-6)
