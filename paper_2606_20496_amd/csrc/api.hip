@@ -96,54 +96,164 @@ class PinnedPool {
 };
 PinnedPool g_pinned;
 
+// Pinned host slabs for staging small uploads (a copy from pinned memory runs
+// asynchronously; one from pageable memory is staged by the runtime, call by
+// call). A setup takes slabs as it needs them and returns them once its stream
+// has been synchronised. The slabs are kept for the life of the process.
+class StagingPool {
+ public:
+  static constexpr size_t kSlab = size_t(1) << 20;
+  void *get() {
+    std::lock_guard<std::mutex> lk(mu_);
+    if (free_.empty()) {
+      void *slab = nullptr;
+      HIPCHK(hipHostMalloc(&slab, kSlab, hipHostMallocDefault));
+      return slab;
+    }
+    void *p = free_.back();
+    free_.pop_back();
+    return p;
+  }
+  void put(void *p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(mu_);
+    free_.push_back(p);
+  }
+
+ private:
+  std::mutex mu_;
+  std::vector<void *> free_;
+};
+StagingPool g_staging;
+
+// Non-blocking streams for the contexts' second stream, kept for reuse:
+// creating a stream costs far more than the rest of a small context's setup.
+class StreamPool {
+ public:
+  hipStream_t get() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      if (!free_.empty()) {
+        hipStream_t s = free_.back();
+        free_.pop_back();
+        return s;
+      }
+    }
+    hipStream_t s = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    return s;
+  }
+  // the caller has synchronised the stream
+  void put(hipStream_t s) {
+    if (!s) return;
+    std::lock_guard<std::mutex> lk(mu_);
+    free_.push_back(s);
+  }
+
+ private:
+  std::mutex mu_;
+  std::vector<hipStream_t> free_;
+};
+StreamPool g_streams;
+
 // Device memory of a context (hipMalloc, freed at release), or with a stream
 // the temporaries of a setup: stream-ordered allocations from the device's
 // pool, freed in stream order, so that releasing them does not synchronise the
 // device (a plain hipFree would wait for every stream, the solves of other
 // contexts included).
+//
+// Small allocations (at most kSmall bytes) are carved from kChunk-byte blocks
+// (256-byte aligned), so a context makes a handful of allocations instead of a
+// hundred; `bytes` counts what the arena holds from the device.
 struct Arena {
+  static constexpr size_t kSmall = size_t(64) << 10, kChunk = size_t(512) << 10, kAlign = 256;
   std::vector<void *> ptrs;
   size_t bytes = 0;
   hipStream_t ordered = nullptr;
   bool stream_ordered = false;
+  char *chunk = nullptr;
+  size_t chunk_used = kChunk;
   Arena() = default;
   explicit Arena(hipStream_t s) : ordered(s), stream_ordered(true) { keep_pool_memory(); }
+  void *raw(size_t nb) {
+    void *p = nullptr;
+    if (stream_ordered)
+      HIPCHK(hipMallocAsync(&p, nb, ordered));
+    else
+      HIPCHK(hipMalloc(&p, nb));
+    ptrs.push_back(p);
+    bytes += nb;
+    return p;
+  }
   template <typename T>
   T *alloc(size_t n) {
     if (n == 0) n = 1;
-    void *p = nullptr;
-    if (stream_ordered)
-      HIPCHK(hipMallocAsync(&p, n * sizeof(T), ordered));
-    else
-      HIPCHK(hipMalloc(&p, n * sizeof(T)));
-    ptrs.push_back(p);
-    bytes += n * sizeof(T);
-    return (T *)p;
+    const size_t nb = n * sizeof(T);
+    if (nb > kSmall) return (T *)raw(nb);
+    const size_t nba = (nb + kAlign - 1) / kAlign * kAlign;
+    if (chunk_used + nba > kChunk) {
+      chunk = (char *)raw(kChunk);
+      chunk_used = 0;
+    }
+    T *p = (T *)(chunk + chunk_used);
+    chunk_used += nba;
+    return p;
   }
-  // Uploads are stream-ordered and not waited for: the source must live until the
-  // caller's next synchronisation of the stream. A temporary source (an rvalue)
-  // is kept in `hold` until drop_hold(), which the caller calls after that
-  // synchronisation.
+  // Uploads are stream-ordered and not waited for. Small ones go through pinned
+  // staging (the host data is copied at once, so the source may go away); the
+  // staging slabs, like a temporary source of a large upload (an rvalue, kept in
+  // `hold`), are released by drop_hold(), which the caller calls after its next
+  // synchronisation of the stream. A large upload from an lvalue needs its
+  // source to live until then.
   std::vector<std::shared_ptr<void>> hold;
+  std::vector<void *> staging;
+  size_t staging_used = StagingPool::kSlab;
   template <typename T>
   T *upload(const std::vector<T> &v, hipStream_t s) {
     T *p = alloc<T>(v.size());
-    if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    const size_t nb = v.size() * sizeof(T);
+    if (nb == 0) return p;
+    if (nb <= kSmall) {
+      const size_t nba = (nb + kAlign - 1) / kAlign * kAlign;
+      if (staging_used + nba > StagingPool::kSlab) {
+        staging.push_back(g_staging.get());
+        staging_used = 0;
+      }
+      char *h = (char *)staging.back() + staging_used;
+      staging_used += nba;
+      std::memcpy(h, v.data(), nb);
+      HIPCHK(hipMemcpyAsync(p, h, nb, hipMemcpyHostToDevice, s));
+    } else {
+      HIPCHK(hipMemcpyAsync(p, v.data(), nb, hipMemcpyHostToDevice, s));
+    }
     return p;
   }
   template <typename T>
   T *upload(std::vector<T> &&v, hipStream_t s) {
+    if (v.size() * sizeof(T) <= kSmall) return upload(v, s);
     auto kept = std::make_shared<std::vector<T>>(std::move(v));
     hold.push_back(kept);
     return upload(*kept, s);
   }
-  void drop_hold() { hold.clear(); }
+  void drop_hold() {
+    hold.clear();
+    for (void *h : staging) g_staging.put(h);
+    staging.clear();
+    staging_used = StagingPool::kSlab;
+  }
   void release() {
     for (void *p : ptrs) (void)(stream_ordered ? hipFreeAsync(p, ordered) : hipFree(p));
     ptrs.clear();
     bytes = 0;
+    chunk = nullptr;
+    chunk_used = kChunk;
   }
-  ~Arena() { release(); }
+  ~Arena() {
+    // staging still held: its copies may be in flight
+    if (!staging.empty() && ordered) (void)hipStreamSynchronize(ordered);
+    drop_hold();
+    release();
+  }
 };
 
 // largest box grid whose reduced solution the final kernel stages in LDS (with
@@ -326,7 +436,7 @@ struct coarse_ctx {
   ~coarse_ctx() {
     if (aux) {
       (void)hipStreamSynchronize(aux);
-      (void)hipStreamDestroy(aux);
+      g_streams.put(aux);
     }
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
@@ -1114,7 +1224,7 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles, int wh
     int *wmax = tmp.alloc<int>(1);
     HIPCHK(hipMemsetAsync(wmax, 0, sizeof(int), s));
     if (P.n_local_sys > 0)
-      hipLaunchKernelGGL(k_loc_count, dim3((unsigned)P.n_local_sys), dim3(256), 0, s, (const LocSys *)dls,
+      hipLaunchKernelGGL(k_loc_count, dim3((unsigned)P.n_local_sys), dim3(512), 0, s, (const LocSys *)dls,
                          (const int32_t *)c->sub_idx, (const int32_t *)vinc_ptr, (const int32_t *)vinc,
                          (const int32_t *)e2v, NE, nf, wmax);
     int hw = 0;
@@ -1141,7 +1251,7 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles, int wh
     int *lbad = tmp.alloc<int>(1);
     HIPCHK(hipMemsetAsync(lbad, 0, sizeof(int), s));
     if (P.n_local_sys > 0)
-      hipLaunchKernelGGL(k_loc_fill<V>, dim3((unsigned)P.n_local_sys), dim3(256), 0, s, (const LocSys *)c->locsys, W,
+      hipLaunchKernelGGL(k_loc_fill<V>, dim3((unsigned)P.n_local_sys), dim3(512), 0, s, (const LocSys *)c->locsys, W,
                          (const int32_t *)c->sub_idx, (const int32_t *)vinc_ptr, (const int32_t *)vinc,
                          (const int32_t *)e2v, NE, nf, (const double *)Ae, c->loc_diag, c->loc_col, val, lbad);
     int hb = 0;
@@ -1151,9 +1261,13 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles, int wh
   } else {
     std::vector<int64_t> loc(P.n_local_sys);
     for (int64_t k = 0; k < P.n_local_sys; ++k) loc[k] = k;
+    // the searches of the assembly run in LDS when the largest R_p fits
+    int64_t maxn = 0;
+    for (int64_t k = 0; k < P.n_local_sys; ++k) maxn = std::max<int64_t>(maxn, P.sys[k].n);
+    const int lds_n = maxn * (int64_t)sizeof(int32_t) <= 32768 ? (int)maxn : 0;
     nbad = invert_systems<TT>(c, P.sys, loc, tiles, scratch_tiles, sys_scale, [&](AsmSys *das, int ns, double *M) {
-      hipLaunchKernelGGL(k_assemble_local, dim3((unsigned)ns), dim3(256), 0, s, das, c->sub_idx, vinc_ptr, vinc, e2v,
-                         NE, nf, (const double *)Ae, M);
+      hipLaunchKernelGGL(k_assemble_local, dim3((unsigned)ns), dim3(256), lds_n * sizeof(int32_t), s, das, c->sub_idx,
+                         vinc_ptr, vinc, e2v, NE, nf, (const double *)Ae, M, lds_n);
     });
     if (nbad) throw Fail(COARSE_ESINGULAR, std::to_string(nbad) + " local system(s) A_p not positive definite");
   }
@@ -1968,7 +2082,7 @@ int coarse_setup_from_plan(const coarse_plan *plan, void *stream, coarse_ctx **o
   c->reduced_refine = o.reduced_refine ? 1 : 0;
   c->proj_max = o.projection;
   try {
-    HIPCHK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+    c->aux = g_streams.get();
     HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     c->h_sc = (Scalars *)g_pinned.get(sizeof(Scalars));

@@ -1831,12 +1831,20 @@ __device__ __forceinline__ double *tile_elem(double *M, int64_t tile_off, int i,
   return M + (tile_off + (int64_t)I * (I + 1) / 2 + J) * (TILE * TILE) + (i % TILE) * TILE + (j % TILE);
 }
 
+// lds_n > 0: R_p (at most lds_n entries) is staged in dynamic LDS for the searches.
 __global__ __launch_bounds__(256) void k_assemble_local(const AsmSys *__restrict__ sys, const int32_t *__restrict__ sub_idx,
                                                         const int32_t *__restrict__ vinc_ptr, const int32_t *__restrict__ vinc,
                                                         const int32_t *__restrict__ e2v, int64_t E, int64_t nf,
-                                                        const double *__restrict__ Ae, double *__restrict__ M) {
+                                                        const double *__restrict__ Ae, double *__restrict__ M,
+                                                        int lds_n) {
+  extern __shared__ int32_t lrs[];
   const AsmSys S = sys[blockIdx.x];
   const int32_t *R = sub_idx + S.vec_off;
+  if (lds_n > 0) {
+    for (int a = threadIdx.x; a < S.n; a += blockDim.x) lrs[a] = R[a];
+    __syncthreads();
+    R = lrs;
+  }
   for (int a = threadIdx.x; a < S.n; a += blockDim.x) {
     const int32_t v = R[a];
     for (int k = vinc_ptr[v]; k < vinc_ptr[v + 1]; ++k) {

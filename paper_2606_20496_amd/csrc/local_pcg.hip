@@ -26,7 +26,7 @@ constexpr int LOC_WMAX = 26;       // off-diagonal entries per row of A_p at mos
 constexpr int LOC_NT_MAX = 1024;   // rows of a subdomain at most (one thread each)
 
 // Position of internal vertex u in the sorted list R[0..n), or -1.
-__device__ __forceinline__ int loc_find(const int32_t *__restrict__ R, int n, int32_t u) {
+__device__ __forceinline__ int loc_find(const int32_t *R, int n, int32_t u) {
   int lo = 0, hi = n - 1;
   while (lo <= hi) {
     const int mid = (lo + hi) >> 1;
@@ -45,13 +45,22 @@ __device__ __forceinline__ int loc_find(const int32_t *__restrict__ R, int n, in
 // (the free vertices of R_p that share an element with the row's vertex; every
 // element holding a vertex of R_p lies in the overlapping subdomain), maximised
 // over all rows into *wmax. A row with more than LOC_WMAX reports LOC_WMAX + 1.
+// Both setup passes search the sorted R_p in LDS (LOC_NT_MAX entries at most).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_loc_count(const LocSys *__restrict__ sys, const int32_t *__restrict__ sub_idx,
+__device__ __forceinline__ const int32_t *loc_stage_R(const LocSys &S, const int32_t *__restrict__ sub_idx,
+                                                      int32_t *lr) {
+  for (int a = threadIdx.x; a < S.n; a += blockDim.x) lr[a] = sub_idx[S.vec_off + a];
+  __syncthreads();
+  return lr;
+}
+
+__global__ __launch_bounds__(512) void k_loc_count(const LocSys *__restrict__ sys, const int32_t *__restrict__ sub_idx,
                                                    const int32_t *__restrict__ vinc_ptr,
                                                    const int32_t *__restrict__ vinc, const int32_t *__restrict__ e2v,
                                                    int64_t E, int64_t nf, int *__restrict__ wmax) {
+  __shared__ int32_t lr[LOC_NT_MAX];
   const LocSys S = sys[blockIdx.x];
-  const int32_t *R = sub_idx + S.vec_off;
+  const int32_t *R = loc_stage_R(S, sub_idx, lr);
   for (int a = threadIdx.x; a < S.n; a += blockDim.x) {
     int32_t seen[LOC_WMAX];
     int cnt = 0;
@@ -85,15 +94,16 @@ __global__ __launch_bounds__(256) void k_loc_count(const LocSys *__restrict__ sy
 // rows whose diagonal is not positive.
 // ---------------------------------------------------------------------------
 template <typename V>
-__global__ __launch_bounds__(256) void k_loc_fill(const LocSys *__restrict__ sys, int W,
+__global__ __launch_bounds__(512) void k_loc_fill(const LocSys *__restrict__ sys, int W,
                                                   const int32_t *__restrict__ sub_idx,
                                                   const int32_t *__restrict__ vinc_ptr,
                                                   const int32_t *__restrict__ vinc, const int32_t *__restrict__ e2v,
                                                   int64_t E, int64_t nf, const double *__restrict__ Ae,
                                                   double *__restrict__ diag, uint32_t *__restrict__ col,
                                                   V *__restrict__ val, int *__restrict__ bad) {
+  __shared__ int32_t lr[LOC_NT_MAX];
   const LocSys S = sys[blockIdx.x];
-  const int32_t *R = sub_idx + S.vec_off;
+  const int32_t *R = loc_stage_R(S, sub_idx, lr);
   for (int a = threadIdx.x; a < S.n; a += blockDim.x) {
     int32_t cs[LOC_WMAX];
     double vs[LOC_WMAX];
