@@ -277,7 +277,8 @@ def _dist(v):
 
 
 def run_serving_workload(torch, coarse, mg, tol, rates=(50.0, 2000.0), count=4096, budget_gb=64.0,
-                         precision="mixed", plan_workers=12, sequential=True, projection=0, local_iters=0):
+                         precision="mixed", plan_workers=12, sequential=True, projection=0, local_iters=0,
+                         graph_off=False):
     """The serving workload with setups in the loop: Poisson arrivals at each rate,
     `count` requests, each a coarse solve on a seeded mesh with n log-uniform in
     [8, 96] and a z stretch of up to 20, 30% of them reusing an earlier mesh with
@@ -312,15 +313,19 @@ def run_serving_workload(torch, coarse, mg, tol, rates=(50.0, 2000.0), count=409
              f"p99 {summ['p99_ms']:.0f} ms, failed {summ['failed']}")
         variants = []
         if projection > 0:
-            variants.append(("projected", {"projection": int(projection)}))
+            variants.append(("projected", {"projection": int(projection)}, True))
         if local_iters > 0:
-            variants.append((f"inexact_k{int(local_iters)}", {"local_iters": int(local_iters)}))
-        for name, kw in variants:
-            srv = serve.Server(budget_gb * 1e9, precision=precision, use_graph=True, step_iters=2,
+            variants.append((f"inexact_k{int(local_iters)}", {"local_iters": int(local_iters)}, True))
+        if graph_off:
+            variants.append(("no_graph", {}, False))
+            if local_iters > 0:
+                variants.append((f"inexact_k{int(local_iters)}_no_graph", {"local_iters": int(local_iters)}, False))
+        for name, kw, graph in variants:
+            srv = serve.Server(budget_gb * 1e9, precision=precision, use_graph=graph, step_iters=2,
                                plan_workers=plan_workers, solver_kw=kw)
             rec3, wall3 = srv.run(reqs, progress=lambda m, r=rate, v=name: _log(f"serving {r:g} req/s, {v}: {m}"))
             pj = {k: v for k, v in serve.summarize(rec3, wall3).items() if k in keep_proj}
-            pj.update(solver_kw=kw, evictions=srv.evictions,
+            pj.update(solver_kw=kw, use_graph=graph, evictions=srv.evictions,
                       setup_per_miss_s={k: _dist(v) for k, v in srv.setup_times.items()})
             srv.close()
             res[f"batched_{precision}_{name}"] = pj
@@ -684,6 +689,8 @@ def main():
                     help="also run --serving with a basis of this many prior solutions per cached mesh")
     ap.add_argument("--serving-local-iters", type=int, default=0,
                     help="also run --serving with inexact local solves of this many steps")
+    ap.add_argument("--serving-graph-off", action="store_true",
+                    help="also run --serving without graph replay of the lock step")
     ap.add_argument("--serving-oracle-subset", type=int, default=64,
                     help="requests of the seeded oracle subset of --serving (0: none)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -843,7 +850,7 @@ def main():
                                                    {float(x) for x in args.serving_sequential_rates.split(",")}
                                                    if args.serving_sequential_rates else True),
                                        projection=args.serving_projection,
-                                       local_iters=args.serving_local_iters)
+                                       local_iters=args.serving_local_iters, graph_off=args.serving_graph_off)
         if args.serving_oracle_subset > 0 and not args.no_cpu_baseline:
             _log("serving: oracle subset")
             serving["oracle_subset"] = c5_oracle_subset(torch, coarse, mg, args.tol, count=args.serving_oracle_subset)
