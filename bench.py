@@ -52,8 +52,8 @@ GEMV_PHASE = 3
 GEMV_TRAFFIC = {
     "cube64": {"bytes": 1142612987, "fetch_kib": 556422.89, "write_kib": 2987.22, "fetch_scale": 2.0,
                "write_scale": 1.0, "src": "0c72c6b9fc27f9aa"},
-    "annulus128": {"bytes": 9215641600, "fetch_kib": 4488113.0, "write_kib": 23424.0, "fetch_scale": 2.0,
-                   "write_scale": 1.0, "src": "0c72c6b9fc27f9aa"},
+    "annulus128": {"bytes": 9215655424, "fetch_kib": 4488119.75, "write_kib": 23424.0, "fetch_scale": 2.0,
+                   "write_scale": 1.0, "src": "59e70f0b38569163"},
 }
 
 
