@@ -52,21 +52,28 @@ __global__ __launch_bounds__(256) void k_ar_stencil_build(int64_t nr, const int3
 }
 
 // (A_r y) at active vertex K, y given on the full box grid. Neighbours with a
-// zero coefficient (inactive ones among them) are not read, so y may hold
-// anything at inactive vertices.
+// zero coefficient (inactive ones among them) do not contribute, so y may hold
+// anything (NaN included) at inactive vertices.
 __device__ __forceinline__ double ar_row(int64_t nr, int64_t K, const int32_t *__restrict__ act_bv,
                                          const double *__restrict__ coef, BoxGrid g,
                                          const double *__restrict__ y) {
   const int32_t v = act_bv[K];
   const int vi = v % g.d0, vj = (v / g.d0) % g.d1, vk = v / (g.d0 * g.d1);
-  double s = 0.0;
+  // all 27 coefficient and neighbour loads go out together (outside the grid
+  // the address is the vertex itself, and the value is not used)
+  double c[27], yv[27];
+#pragma unroll
+  for (int t = 0; t < 27; ++t) c[t] = coef[(int64_t)t * nr + K];
 #pragma unroll
   for (int t = 0; t < 27; ++t) {
-    const double c = coef[(int64_t)t * nr + K];
     const int i = vi + t % 3 - 1, j = vj + (t / 3) % 3 - 1, k = vk + t / 9 - 1;
-    if (c != 0.0 && i >= 0 && i < g.d0 && j >= 0 && j < g.d1 && k >= 0 && k < g.d2)
-      s += c * y[i + g.d0 * (j + g.d1 * k)];
+    const bool in = i >= 0 && i < g.d0 && j >= 0 && j < g.d1 && k >= 0 && k < g.d2;
+    yv[t] = y[in ? i + g.d0 * (j + g.d1 * k) : v];
   }
+  double s = 0.0;
+#pragma unroll
+  for (int t = 0; t < 27; ++t)
+    if (c[t] != 0.0) s += c[t] * yv[t];
   return s;
 }
 

@@ -218,3 +218,20 @@ def test_inexact_batch_matches_oracle_and_noalloc():
         assert torch.equal(u, u2)
         # i.i.d. right-hand sides on the batch meshes: the 1e-7 bar of those meshes
         assert np.linalg.norm(_np(u) - uo) / np.linalg.norm(uo) < 1e-7
+
+
+@pytest.mark.parametrize("precision", ["mixed", "mixed16"])
+def test_inexact_mixed_application_error(precision):
+    # the mixed forms store A_p in FP32 and run the local CG in FP32: one
+    # application against the FP64 oracle of the same k, relative, max norm. The
+    # local CG's FP32 rounding (k steps, a few dozen operations per value) sits
+    # far below 1e-4; the reduced term keeps its FP32 / FP16-storage error
+    m = mg.box_mesh((10, 9, 7), 21, block=4, boxes=(3, 3, 2), faces=("y1",))
+    errs = {}
+    for k in (2, 6):
+        P = problem.from_mesh(m, local_iters=k)
+        S = coarse.CoarseSolver.from_mesh(m, local_iters=k, precision=precision)
+        r = np.random.default_rng(70 + k).standard_normal(m.n_vert)
+        errs[k] = _rel(_np(S.apply_precond(_gpu(r))), P.apply_precond(r))
+    print(f"{precision} inexact application error vs FP64 oracle: {errs}")
+    assert max(errs.values()) < (1e-4 if precision == "mixed" else 4 * 2.0 ** -11)
