@@ -10,12 +10,15 @@
 #include "plan.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <numeric>
+#include <thread>
 
 namespace coarse {
 
@@ -74,6 +77,28 @@ inline double phi(int k, const double xi[3]) {
   return fx * fy * fz;
 }
 
+// Run f(begin, end, t) over [0, n) cut into nt contiguous ranges, one thread
+// each (t = 0..nt-1); the ranges, and so every result, do not depend on timing.
+template <typename F>
+void parallel_for(int64_t n, int nt, F f) {
+  if (nt <= 1 || n < 2 * nt) {
+    f((int64_t)0, n, 0);
+    return;
+  }
+  std::vector<std::thread> ts;
+  for (int t = 1; t < nt; ++t) ts.emplace_back([&f, n, nt, t] { f(n * t / nt, n * (t + 1) / nt, t); });
+  f((int64_t)0, n / nt, 0);
+  for (auto &th : ts) th.join();
+}
+
+// Host threads for a plan: large meshes only (the plans of small meshes run
+// side by side on a server's own worker threads).
+int plan_threads(int64_t n_elem) {
+  if (n_elem < (int64_t(1) << 20)) return 1;
+  const unsigned hw = std::thread::hardware_concurrency();
+  return (int)std::max<unsigned>(1, std::min<unsigned>(8, hw));
+}
+
 // Phase timings of the host setup on stderr when COARSE_TRACE is set.
 struct Trace {
   bool on = std::getenv("COARSE_TRACE") != nullptr;
@@ -91,6 +116,7 @@ struct Trace {
 int build_plan(const PlanInput &in, Plan &P) {
   Trace tr;
   const int64_t NV = in.n_vert, NE = in.n_elem;
+  const int NT = in.threads > 0 ? std::min(in.threads, 64) : plan_threads(NE);
   if (NV <= 0 || NE <= 0 || !in.xyz || !in.e2v || !in.dirichlet) {
     P.err = "empty mesh or null array";
     return -1;
@@ -132,7 +158,9 @@ int build_plan(const PlanInput &in, Plan &P) {
   tr.mark("validate");
   // ---- partition labels -------------------------------------------------------
   std::vector<double> cen(3 * NE);
-  for (int64_t e = 0; e < NE; ++e) centroid(in.xyz, in.e2v + 8 * e, &cen[3 * e]);
+  parallel_for(NE, NT, [&](int64_t e0, int64_t e1, int) {
+    for (int64_t e = e0; e < e1; ++e) centroid(in.xyz, in.e2v + 8 * e, &cen[3 * e]);
+  });
   std::vector<int32_t> part(NE);
   P.n_part = in.n_part;
   if (in.part) {
@@ -165,33 +193,90 @@ int build_plan(const PlanInput &in, Plan &P) {
   // ---- element order: (subdomain, Morton code of centroid) --------------------
   {
     std::vector<uint64_t> key(NE);
-    for (int64_t e = 0; e < NE; ++e) {
-      uint64_t q[3];
-      for (int d = 0; d < 3; ++d) {
-        double ext = P.hi[d] - P.lo[d];
-        double t = ext > 0 ? (cen[3 * e + d] - P.lo[d]) / ext : 0.0;
-        t = std::min(std::max(t, 0.0), 1.0);
-        q[d] = (uint64_t)(t * 2097151.0);
+    parallel_for(NE, NT, [&](int64_t e0, int64_t e1, int) {
+      for (int64_t e = e0; e < e1; ++e) {
+        uint64_t q[3];
+        for (int d = 0; d < 3; ++d) {
+          double ext = P.hi[d] - P.lo[d];
+          double t = ext > 0 ? (cen[3 * e + d] - P.lo[d]) / ext : 0.0;
+          t = std::min(std::max(t, 0.0), 1.0);
+          q[d] = (uint64_t)(t * 2097151.0);
+        }
+        key[e] = spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2);
       }
-      key[e] = spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2);
-    }
+    });
+    // order by (subdomain, key, element): elements bucketed by subdomain (in
+    // element order), then each subdomain's run sorted by (key, element)
+    std::vector<int64_t> pst(in.n_part + 1, 0);
+    for (int64_t e = 0; e < NE; ++e) pst[part[e] + 1]++;
+    for (int32_t q = 0; q < in.n_part; ++q) pst[q + 1] += pst[q];
     P.elem_user.resize(NE);
-    std::iota(P.elem_user.begin(), P.elem_user.end(), 0);
-    std::sort(P.elem_user.begin(), P.elem_user.end(), [&](int32_t a, int32_t b) {
-      if (part[a] != part[b]) return part[a] < part[b];
-      if (key[a] != key[b]) return key[a] < key[b];
-      return a < b;
+    {
+      std::vector<int64_t> fill(pst.begin(), pst.end() - 1);
+      for (int64_t e = 0; e < NE; ++e) P.elem_user[fill[part[e]]++] = (int32_t)e;
+    }
+    parallel_for(in.n_part, NT, [&](int64_t q0, int64_t q1, int) {
+      for (int64_t q = q0; q < q1; ++q)
+        std::sort(P.elem_user.begin() + pst[q], P.elem_user.begin() + pst[q + 1], [&](int32_t a, int32_t b) {
+          if (key[a] != key[b]) return key[a] < key[b];
+          return a < b;
+        });
     });
   }
 
   tr.mark("element order");
   // ---- vertex numbering: free vertices first, by first touch -------------------
+  // The first touch of a vertex is the least slot 8 ei + v (element ei in the
+  // order above, corner v) naming it. Free vertices are numbered in first-touch
+  // order, then the Dirichlet vertices that elements use, in the same order:
+  // first touches found by an atomic minimum, counted per range of elements,
+  // then numbered per range from the ranges' prefix sums.
   P.vint_of_user.assign(NV, -1);
-  int64_t nf = 0;
-  for (int64_t ei = 0; ei < NE; ++ei) {
-    const int32_t *ev = in.e2v + 8 * (int64_t)P.elem_user[ei];
-    for (int v = 0; v < 8; ++v)
-      if (!in.dirichlet[ev[v]] && P.vint_of_user[ev[v]] < 0) P.vint_of_user[ev[v]] = (int32_t)nf++;
+  int64_t nf = 0, nd = 0;
+  {
+    const int64_t NONE = INT64_MAX;
+    std::unique_ptr<std::atomic<int64_t>[]> first(new std::atomic<int64_t>[NV]);
+    parallel_for(NV, NT, [&](int64_t u0, int64_t u1, int) {
+      for (int64_t u = u0; u < u1; ++u) first[u].store(NONE, std::memory_order_relaxed);
+    });
+    parallel_for(NE, NT, [&](int64_t e0, int64_t e1, int) {
+      for (int64_t ei = e0; ei < e1; ++ei) {
+        const int32_t *ev = in.e2v + 8 * (int64_t)P.elem_user[ei];
+        for (int v = 0; v < 8; ++v) {
+          const int64_t key = 8 * ei + v;
+          std::atomic<int64_t> &f = first[ev[v]];
+          int64_t cur = f.load(std::memory_order_relaxed);
+          while (key < cur && !f.compare_exchange_weak(cur, key, std::memory_order_relaxed)) {
+          }
+        }
+      }
+    });
+    std::vector<int64_t> cnt_f(NT + 1, 0), cnt_d(NT + 1, 0);
+    parallel_for(NE, NT, [&](int64_t e0, int64_t e1, int t) {
+      int64_t cf = 0, cd = 0;
+      for (int64_t ei = e0; ei < e1; ++ei) {
+        const int32_t *ev = in.e2v + 8 * (int64_t)P.elem_user[ei];
+        for (int v = 0; v < 8; ++v)
+          if (first[ev[v]].load(std::memory_order_relaxed) == 8 * ei + v) (in.dirichlet[ev[v]] ? cd : cf)++;
+      }
+      cnt_f[t + 1] = cf;
+      cnt_d[t + 1] = cd;
+    });
+    for (int t = 0; t < NT; ++t) {
+      cnt_f[t + 1] += cnt_f[t];
+      cnt_d[t + 1] += cnt_d[t];
+    }
+    nf = cnt_f[NT];
+    parallel_for(NE, NT, [&](int64_t e0, int64_t e1, int t) {
+      int64_t idf = cnt_f[t], idd = nf + cnt_d[t];
+      for (int64_t ei = e0; ei < e1; ++ei) {
+        const int32_t *ev = in.e2v + 8 * (int64_t)P.elem_user[ei];
+        for (int v = 0; v < 8; ++v)
+          if (first[ev[v]].load(std::memory_order_relaxed) == 8 * ei + v)
+            P.vint_of_user[ev[v]] = (int32_t)(in.dirichlet[ev[v]] ? idd++ : idf++);
+      }
+    });
+    nd = nf + cnt_d[NT];
   }
   for (int64_t u = 0; u < NV; ++u)
     if (!in.dirichlet[u] && P.vint_of_user[u] < 0) {
@@ -199,12 +284,6 @@ int build_plan(const PlanInput &in, Plan &P) {
       return -1;
     }
   P.n_free = nf;
-  int64_t nd = nf;
-  for (int64_t ei = 0; ei < NE; ++ei) {
-    const int32_t *ev = in.e2v + 8 * (int64_t)P.elem_user[ei];
-    for (int v = 0; v < 8; ++v)
-      if (P.vint_of_user[ev[v]] < 0) P.vint_of_user[ev[v]] = (int32_t)nd++;
-  }
   // unused Dirichlet vertices get the remaining ids
   for (int64_t u = 0; u < NV; ++u)
     if (P.vint_of_user[u] < 0) P.vint_of_user[u] = (int32_t)nd++;
@@ -213,17 +292,22 @@ int build_plan(const PlanInput &in, Plan &P) {
     return -1;
   }
   P.user_of_vint.assign(NV, 0);
-  for (int64_t u = 0; u < NV; ++u) P.user_of_vint[P.vint_of_user[u]] = (int32_t)u;
   P.xyz.resize(3 * NV);
-  for (int64_t u = 0; u < NV; ++u)
-    for (int d = 0; d < 3; ++d) P.xyz[d * NV + P.vint_of_user[u]] = in.xyz[3 * u + d];
+  parallel_for(NV, NT, [&](int64_t u0, int64_t u1, int) {
+    for (int64_t u = u0; u < u1; ++u) {
+      P.user_of_vint[P.vint_of_user[u]] = (int32_t)u;
+      for (int d = 0; d < 3; ++d) P.xyz[d * NV + P.vint_of_user[u]] = in.xyz[3 * u + d];
+    }
+  });
   P.e2v.resize(8 * NE);
   std::vector<int32_t> part_int(NE);
-  for (int64_t ei = 0; ei < NE; ++ei) {
-    const int32_t *ev = in.e2v + 8 * (int64_t)P.elem_user[ei];
-    for (int v = 0; v < 8; ++v) P.e2v[v * NE + ei] = P.vint_of_user[ev[v]];
-    part_int[ei] = part[P.elem_user[ei]];
-  }
+  parallel_for(NE, NT, [&](int64_t e0, int64_t e1, int) {
+    for (int64_t ei = e0; ei < e1; ++ei) {
+      const int32_t *ev = in.e2v + 8 * (int64_t)P.elem_user[ei];
+      for (int v = 0; v < 8; ++v) P.e2v[v * NE + ei] = P.vint_of_user[ev[v]];
+      part_int[ei] = part[P.elem_user[ei]];
+    }
+  });
   auto E2V = [&](int64_t e, int v) { return P.e2v[v * NE + e]; };
 
   tr.mark("vertex numbering");
@@ -249,59 +333,80 @@ int build_plan(const PlanInput &in, Plan &P) {
     P.blk_slot_ptr.assign(1, 0);
     P.blk_inc.assign(nb, 0);
     P.lconn.assign(8 * NE, 0xFFFF);
-    std::vector<int32_t> slot_of(NV, -1), cnt(NV, 0);
+    // each block on its own (in parallel): its vertices (sorted), each vertex's
+    // incidence list in (element, local vertex) order, its local connectivity,
+    // whether the block holds all of a vertex's incidences; then the blocks are
+    // concatenated in order
+    struct BlockOut {
+      std::vector<int32_t> verts, list_ptr;
+      std::vector<uint16_t> lists;
+      std::vector<uint8_t> owned;
+      uint8_t inc = 0;
+    };
+    std::vector<BlockOut> bo(nb);
+    parallel_for(nb, NT, [&](int64_t b0, int64_t b1, int) {
+      std::vector<std::pair<int32_t, uint16_t>> pr;
+      for (int64_t blk = b0; blk < b1; ++blk) {
+        const int64_t e0 = blk * OP_BLOCK, e1 = std::min<int64_t>(NE, e0 + OP_BLOCK);
+        pr.clear();
+        for (int64_t e = e0; e < e1; ++e)
+          for (int v = 0; v < 8; ++v) {
+            const int32_t u = E2V(e, v);
+            if (u < nf) pr.push_back({u, (uint16_t)((e - e0) * 8 + v)});
+          }
+        // by vertex; a vertex's incidences keep their (element, local vertex) order
+        std::stable_sort(pr.begin(), pr.end(), [](const std::pair<int32_t, uint16_t> &a,
+                                                  const std::pair<int32_t, uint16_t> &b) { return a.first < b.first; });
+        BlockOut &o = bo[blk];
+        o.list_ptr.push_back(0);
+        for (size_t a = 0; a < pr.size();) {
+          size_t c = a;
+          uint8_t seen = 0;
+          const int32_t sl = (int32_t)o.verts.size();
+          while (c < pr.size() && pr[c].first == pr[a].first) {
+            const uint16_t x = pr[c].second;
+            const int v = x & 7;
+            P.lconn[(e0 + (x >> 3)) * 8 + v] = (uint16_t)sl;
+            if ((seen >> v) & 1) o.inc = 1;
+            seen |= (uint8_t)(1u << v);
+            o.lists.push_back(x);
+            ++c;
+          }
+          o.verts.push_back(pr[a].first);
+          o.list_ptr.push_back((int32_t)o.lists.size());
+          o.owned.push_back((int64_t)(c - a) == (int64_t)P.mult[pr[a].first] ? 1 : 0);
+          a = c;
+        }
+      }
+    });
     std::vector<int64_t> shared_blocks;  // (slot global index) of shared slots
-    std::vector<int32_t> slot_block;
     for (int64_t blk = 0; blk < nb; ++blk) {
-      const int64_t e0 = blk * OP_BLOCK, e1 = std::min<int64_t>(NE, e0 + OP_BLOCK);
-      std::vector<int32_t> verts;
-      for (int64_t e = e0; e < e1; ++e)
-        for (int v = 0; v < 8; ++v) {
-          int32_t u = E2V(e, v);
-          if (u >= nf) continue;
-          if (cnt[u] == 0) verts.push_back(u);
-          cnt[u]++;
-        }
-      std::sort(verts.begin(), verts.end());
+      BlockOut &o = bo[blk];
       const int32_t s0 = P.blk_slot_ptr.back();
-      for (size_t s = 0; s < verts.size(); ++s) slot_of[verts[s]] = (int32_t)s;
-      // incidence lists per slot (element order, then local vertex order); a
-      // vertex seen twice at the same local corner marks the block
-      std::vector<std::vector<uint16_t>> lists(verts.size());
-      std::vector<uint8_t> corners_seen(verts.size(), 0);
-      for (int64_t e = e0; e < e1; ++e)
-        for (int v = 0; v < 8; ++v) {
-          int32_t u = E2V(e, v);
-          if (u >= nf) continue;
-          const int32_t sl = slot_of[u];
-          P.lconn[e * 8 + v] = (uint16_t)sl;
-          lists[sl].push_back((uint16_t)((e - e0) * 8 + v));
-          if ((corners_seen[sl] >> v) & 1) P.blk_inc[blk] = 1;
-          corners_seen[sl] |= (uint8_t)(1u << v);
-        }
-      if (P.blk_inc[blk]) P.any_blk_inc = true;
-      for (size_t s = 0; s < verts.size(); ++s) {
-        int32_t u = verts[s];
+      P.blk_inc[blk] = o.inc;
+      if (o.inc) P.any_blk_inc = true;
+      for (size_t sl = 0; sl < o.verts.size(); ++sl) {
+        const int32_t u = o.verts[sl];
         P.slot_vid.push_back(u);
         if (P.slot_inc_ptr.empty()) P.slot_inc_ptr.push_back(0);
-        for (auto x : lists[s]) P.slot_inc.push_back(x);
+        const int32_t l0 = o.list_ptr[sl], l1 = o.list_ptr[sl + 1];
+        for (int32_t k = l0; k < l1; ++k) P.slot_inc.push_back(o.lists[k]);
         P.slot_inc_ptr.push_back((int32_t)P.slot_inc.size());
         // the same list as one 16-byte record (0xFFFF ends it; 0xFFFE first: the
         // list is longer than 8 and only the CSR form holds it)
+        const int len = l1 - l0;
         for (int k = 0; k < 8; ++k)
-          P.slot_inc8.push_back(lists[s].size() > 8 ? (k == 0 ? 0xFFFE : 0xFFFF)
-                                                    : (k < (int)lists[s].size() ? lists[s][k] : 0xFFFF));
-        if (cnt[u] == P.mult[u]) {
+          P.slot_inc8.push_back(len > 8 ? (k == 0 ? 0xFFFE : 0xFFFF) : (k < len ? o.lists[l0 + k] : 0xFFFF));
+        if (o.owned[sl]) {
           P.slot_dst.push_back(u);
         } else {
           P.slot_dst.push_back(-1);  // patched below
-          shared_blocks.push_back(s0 + (int64_t)s);
+          shared_blocks.push_back(s0 + (int64_t)sl);
         }
-        cnt[u] = 0;
-        slot_of[u] = -1;
       }
-      P.blk_slot_ptr.push_back(s0 + (int32_t)verts.size());
-      P.max_slots = std::max<int64_t>(P.max_slots, (int64_t)verts.size());
+      P.blk_slot_ptr.push_back(s0 + (int32_t)o.verts.size());
+      P.max_slots = std::max<int64_t>(P.max_slots, (int64_t)o.verts.size());
+      o = BlockOut();   // release the block's lists once they are copied
     }
     if (P.slot_inc_ptr.empty()) P.slot_inc_ptr.push_back(0);
     // partial ids grouped by vertex (vertices in order of first appearance, each
@@ -354,10 +459,12 @@ int build_plan(const PlanInput &in, Plan &P) {
     std::vector<int64_t> pstart(in.n_part + 1, 0);
     for (int64_t e = 0; e < NE; ++e) pstart[part_int[e] + 1]++;
     for (int p = 0; p < in.n_part; ++p) pstart[p + 1] += pstart[p];
-    std::vector<int32_t> emark(NE, -1), vmark(NV, -1);
     P.R.assign(in.n_part, {});
+    // subdomains in parallel, each thread with its own marks
+    parallel_for(in.n_part, NT, [&](int64_t p0, int64_t p1, int) {
+    std::vector<int32_t> emark(NE, -1), vmark(NV, -1);
     std::vector<int32_t> cur, nxt;
-    for (int32_t p = 0; p < in.n_part; ++p) {
+    for (int32_t p = (int32_t)p0; p < (int32_t)p1; ++p) {
       cur.clear();
       for (int64_t e = pstart[p]; e < pstart[p + 1]; ++e) {
         cur.push_back((int32_t)e);
@@ -392,6 +499,7 @@ int build_plan(const PlanInput &in, Plan &P) {
         }
       std::sort(R.begin(), R.end());
     }
+    });
   }
 
   tr.mark("overlap and R_p");
@@ -431,51 +539,82 @@ int build_plan(const PlanInput &in, Plan &P) {
   };
 
   P.elem_cell.resize(NE);
-  for (int64_t e = 0; e < NE; ++e) {
-    int32_t ev[8];
-    for (int v = 0; v < 8; ++v) ev[v] = P.user_of_vint[E2V(e, v)];
-    double c[3];
-    centroid(in.xyz, ev, c);
-    int32_t c3[3];
-    cell_of(c, c3);
-    P.elem_cell[e] = (int32_t)cell_id(c3);
-  }
+  parallel_for(NE, NT, [&](int64_t e0, int64_t e1, int) {
+    for (int64_t e = e0; e < e1; ++e) {
+      int32_t ev[8];
+      for (int v = 0; v < 8; ++v) ev[v] = P.user_of_vint[E2V(e, v)];
+      double c[3];
+      centroid(in.xyz, ev, c);
+      int32_t c3[3];
+      cell_of(c, c3);
+      P.elem_cell[e] = (int32_t)cell_id(c3);
+    }
+  });
 
-  // vertex-major entries: (free vertex, cell) with weight fraction n_ic / m_i
+  // vertex-major entries: (free vertex, cell) with weight fraction n_ic / m_i;
+  // ranges of vertices in parallel, concatenated in vertex order
   std::vector<int32_t> ent_cell;  // cell id of each entry
   P.jv_ptr.assign(1, 0);
   {
-    std::vector<int32_t> cells;
-    for (int64_t i = 0; i < nf; ++i) {
-      const int32_t u = P.user_of_vint[i];
-      const double x[3] = {in.xyz[3 * (int64_t)u], in.xyz[3 * (int64_t)u + 1], in.xyz[3 * (int64_t)u + 2]};
-      if (in.interp == 0) {
-        cells.clear();
-        for (int32_t k = inc_ptr[i]; k < inc_ptr[i + 1]; ++k) cells.push_back(P.elem_cell[inc[k] >> 3]);
-        std::sort(cells.begin(), cells.end());
-        for (size_t a = 0; a < cells.size();) {
-          size_t b2 = a;
-          while (b2 < cells.size() && cells[b2] == cells[a]) ++b2;
+    struct EntOut {
+      std::vector<int32_t> cell, count;
+      std::vector<double> w, xi;
+    };
+    const int nt = (nf >= 2 * NT) ? NT : 1;
+    std::vector<EntOut> eo(nt);
+    parallel_for(nf, nt, [&](int64_t i0, int64_t i1, int t) {
+      EntOut &o = eo[t];
+      std::vector<int32_t> cells;
+      for (int64_t i = i0; i < i1; ++i) {
+        const int32_t u = P.user_of_vint[i];
+        const double x[3] = {in.xyz[3 * (int64_t)u], in.xyz[3 * (int64_t)u + 1], in.xyz[3 * (int64_t)u + 2]};
+        const size_t before = o.cell.size();
+        if (in.interp == 0) {
+          cells.clear();
+          for (int32_t k = inc_ptr[i]; k < inc_ptr[i + 1]; ++k) cells.push_back(P.elem_cell[inc[k] >> 3]);
+          std::sort(cells.begin(), cells.end());
+          for (size_t a = 0; a < cells.size();) {
+            size_t b2 = a;
+            while (b2 < cells.size() && cells[b2] == cells[a]) ++b2;
+            int32_t c3[3];
+            cell_xyz(cells[a], c3);
+            double xi[3];
+            local_xi(x, c3, xi);
+            o.cell.push_back(cells[a]);
+            o.w.push_back((double)(b2 - a) / (double)P.mult[i]);
+            for (int d = 0; d < 3; ++d) o.xi.push_back(xi[d]);
+            a = b2;
+          }
+        } else {
           int32_t c3[3];
-          cell_xyz(cells[a], c3);
+          cell_of(x, c3);
           double xi[3];
           local_xi(x, c3, xi);
-          ent_cell.push_back(cells[a]);
-          P.jv_w.push_back((double)(b2 - a) / (double)P.mult[i]);
-          for (int d = 0; d < 3; ++d) P.jv_xi.push_back(xi[d]);
-          a = b2;
+          o.cell.push_back((int32_t)cell_id(c3));
+          o.w.push_back(1.0);
+          for (int d = 0; d < 3; ++d) o.xi.push_back(xi[d]);
         }
-      } else {
-        int32_t c3[3];
-        cell_of(x, c3);
-        double xi[3];
-        local_xi(x, c3, xi);
-        ent_cell.push_back((int32_t)cell_id(c3));
-        P.jv_w.push_back(1.0);
-        for (int d = 0; d < 3; ++d) P.jv_xi.push_back(xi[d]);
+        o.count.push_back((int32_t)(o.cell.size() - before));
       }
-      P.jv_ptr.push_back((int32_t)ent_cell.size());
-    }
+    });
+    std::vector<int64_t> base(nt + 1, 0);
+    for (int t = 0; t < nt; ++t) base[t + 1] = base[t] + (int64_t)eo[t].cell.size();
+    P.jv_ptr.resize(nf + 1);
+    ent_cell.resize(base[nt]);
+    P.jv_w.resize(base[nt]);
+    P.jv_xi.resize(3 * base[nt]);
+    parallel_for(nf, nt, [&](int64_t i0, int64_t, int t) {
+      EntOut &o = eo[t];
+      int64_t k = base[t];
+      for (size_t a = 0; a < o.count.size(); ++a) {
+        k += o.count[a];
+        P.jv_ptr[i0 + 1 + (int64_t)a] = (int32_t)k;
+      }
+      std::copy(o.cell.begin(), o.cell.end(), ent_cell.begin() + base[t]);
+      std::copy(o.w.begin(), o.w.end(), P.jv_w.begin() + base[t]);
+      std::copy(o.xi.begin(), o.xi.end(), P.jv_xi.begin() + 3 * base[t]);
+      o = EntOut();
+    });
   }
   const int64_t nent = (int64_t)ent_cell.size();
 
@@ -541,24 +680,35 @@ int build_plan(const PlanInput &in, Plan &P) {
   // cell-major copy of the entries, cut into restriction tasks
   {
     std::vector<int32_t> ent_vid(nent);
-    for (int64_t i = 0; i < nf; ++i)
-      for (int32_t k = P.jv_ptr[i]; k < P.jv_ptr[i + 1]; ++k) ent_vid[k] = (int32_t)i;
+    parallel_for(nf, NT, [&](int64_t i0, int64_t i1, int) {
+      for (int64_t i = i0; i < i1; ++i)
+        for (int32_t k = P.jv_ptr[i]; k < P.jv_ptr[i + 1]; ++k) ent_vid[k] = (int32_t)i;
+    });
+    // entries by occupied cell, in entry order within a cell (a counting sort)
     std::vector<int32_t> order(nent);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return P.jv_occ[a] < P.jv_occ[b]; });
+    {
+      std::vector<int64_t> ost(nocc + 1, 0);
+      for (int64_t k = 0; k < nent; ++k) ost[P.jv_occ[k] + 1]++;
+      for (int64_t o = 0; o < nocc; ++o) ost[o + 1] += ost[o];
+      for (int64_t k = 0; k < nent; ++k) order[ost[P.jv_occ[k]]++] = (int32_t)k;
+    }
     P.jc_vid.resize(nent);
     P.jc_w.resize(nent);
     P.jc_xi.resize(3 * nent);
-    for (int64_t j = 0; j < nent; ++j) {
-      int32_t k = order[j];
-      P.jc_vid[j] = ent_vid[k];
-      P.jc_w[j] = P.jv_w[k];
-      for (int d = 0; d < 3; ++d) P.jc_xi[d * nent + j] = P.jv_xi[3 * (int64_t)k + d];
-    }
+    parallel_for(nent, NT, [&](int64_t j0, int64_t j1, int) {
+      for (int64_t j = j0; j < j1; ++j) {
+        int32_t k = order[j];
+        P.jc_vid[j] = ent_vid[k];
+        P.jc_w[j] = P.jv_w[k];
+        for (int d = 0; d < 3; ++d) P.jc_xi[d * nent + j] = P.jv_xi[3 * (int64_t)k + d];
+      }
+    });
     // vertex-major xi to SoA as well
     std::vector<double> soa(3 * nent);
-    for (int64_t k = 0; k < nent; ++k)
-      for (int d = 0; d < 3; ++d) soa[d * nent + k] = P.jv_xi[3 * k + d];
+    parallel_for(nent, NT, [&](int64_t k0, int64_t k1, int) {
+      for (int64_t k = k0; k < k1; ++k)
+        for (int d = 0; d < 3; ++d) soa[d * nent + k] = P.jv_xi[3 * k + d];
+    });
     P.jv_xi.swap(soa);
     P.jt_task_start.assign(1, 0);
     std::vector<std::vector<int32_t>> occ_tasks(nocc);

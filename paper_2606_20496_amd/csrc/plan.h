@@ -36,6 +36,9 @@ struct PlanInput {
   int overlap = 1;
   int boxes[3] = {0, 0, 0};
   int interp = 0;
+  // host threads: 0 = by mesh size (one below 2^20 elements, else up to 8); the
+  // plan is the same for every thread count
+  int threads = 0;
 };
 
 // One dense SPD system whose inverse is stored in lower-triangular tiles.
