@@ -1033,9 +1033,10 @@ int64_t invert_systems(coarse_ctx *c, const std::vector<System> &sys, const std:
     }
     Arena tmp(s);
     double *M = tmp.alloc<double>((size_t)toff * TILE * TILE);
-    double *Pb = tmp.alloc<double>((size_t)poff * TILE * TILE);
-    double *Gb = tmp.alloc<double>((size_t)poff * TILE * TILE);
-    double *Dv = tmp.alloc<double>((size_t)ns * TILE * TILE);
+    // panel strips (32 x BW per tile row) and pivot-block inverses (BW x BW)
+    double *Pb = tmp.alloc<double>((size_t)poff * TILE * BW);
+    double *Gb = tmp.alloc<double>((size_t)poff * TILE * BW);
+    double *Dv = tmp.alloc<double>((size_t)ns * BW * BW);
     int *st = tmp.alloc<int>(ns);
     double *diag0 = tmp.alloc<double>((size_t)poff * TILE);
     SweepSys *dss = tmp.upload(ss, s);
@@ -1050,10 +1051,15 @@ int64_t invert_systems(coarse_ctx *c, const std::vector<System> &sys, const std:
     assemble(das, (int)ns, M);
     const int64_t ntiles = (int64_t)tsys.size();
     hipLaunchKernelGGL(k_save_diag, dim3((unsigned)ns), dim3(256), 0, s, dss, (const double *)M, diag0);
-    for (int k = 0; k < maxnb; ++k) {
-      hipLaunchKernelGGL(k_sweep_pivot, dim3((unsigned)ns), dim3(256), 0, s, k, dss, M, Dv, (const double *)diag0, st);
-      hipLaunchKernelGGL(k_sweep_panel, dim3((unsigned)ns, (unsigned)maxnb), dim3(256), 0, s, k, dss, M, Dv, Pb, Gb);
-      hipLaunchKernelGGL(k_sweep_update, dim3((unsigned)ntiles), dim3(256), 0, s, k, dss, dts, dti, dtj, M, Dv, Pb, Gb);
+    if (ns * maxnb > INT32_MAX / 2 || ntiles > INT32_MAX / 2) throw Fail(COARSE_EINVAL, "too many systems for one sweep");
+    const unsigned pan_grid = (unsigned)(8 * ((ns * maxnb + 7) / 8)), upd_grid = (unsigned)(8 * ((ntiles + 7) / 8));
+    for (int kb = 0; (int64_t)kb * SW < maxnb; ++kb) {
+      hipLaunchKernelGGL(k_bsweep_pivot, dim3((unsigned)ns), dim3(PIV_T), 0, s, kb, dss, (const double *)M, Dv,
+                         (const double *)diag0, st);
+      hipLaunchKernelGGL(k_bsweep_panel, dim3(pan_grid), dim3(256), 0, s, kb, (int)ns, (int)maxnb, dss,
+                         (const double *)M, (const double *)Dv, Pb, Gb);
+      hipLaunchKernelGGL(k_bsweep_update, dim3(upd_grid), dim3(256), 0, s, kb, (int)ntiles, dss, dts, dti, dtj, M,
+                         (const double *)Dv, (const double *)Pb, (const double *)Gb);
     }
     // FP16 storage: a power-of-two scale per system keeps every entry in range
     float *dscale = nullptr;

@@ -2052,128 +2052,228 @@ __global__ __launch_bounds__(256) void k_save_diag(const SweepSys *__restrict__ 
 // all-Neumann reduced operator).
 constexpr double PIVOT_RTOL = 1e-13;
 
-__global__ __launch_bounds__(256) void k_sweep_pivot(int k, const SweepSys *__restrict__ sys, double *__restrict__ M,
-                                                     double *__restrict__ Dinv, const double *__restrict__ diag0,
-                                                     int *__restrict__ status) {
-  __shared__ double D[TILE][TILE + 1];
-  __shared__ double col[TILE];
-  __shared__ int bad;
-  const SweepSys S = sys[blockIdx.x];
-  if (k >= S.nb) return;
-  const double *Mk = tile_ptr(M, S.tile_off, k, k);
-  if (threadIdx.x == 0) bad = 0;
-  for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) D[t / TILE][t % TILE] = Mk[t];
-  __syncthreads();
-  for (int j = 0; j < TILE; ++j) {
-    const double piv = D[j][j];
-    if (threadIdx.x < TILE) col[threadIdx.x] = D[threadIdx.x][j];
-    if (threadIdx.x == 0 &&
-        (!(piv > PIVOT_RTOL * diag0[S.pan_off * TILE + (int64_t)k * TILE + j]) || !isfinite(piv)))
-      bad = 1;
-    __syncthreads();
-    if (threadIdx.x < TILE) {
-      const double v = (threadIdx.x == j) ? 1.0 : D[j][threadIdx.x];
-      D[j][threadIdx.x] = v / piv;
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) {
-      const int i = t / TILE, c = t % TILE;
-      if (i == j) continue;
-      const double old = (c == j) ? 0.0 : D[i][c];
-      D[i][c] = old - col[i] * D[j][c];
-    }
-    __syncthreads();
-  }
-  double *out = Dinv + (int64_t)blockIdx.x * TILE * TILE;
-  for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) out[t] = D[t / TILE][t % TILE];
-  if (threadIdx.x == 0 && bad) status[blockIdx.x] = 1;
-}
+// The sweep runs SW tile columns per block step. Step kb sweeps the columns
+// K = [k0, k0 + w), k0 = kb SW, w = min(SW, nb - k0), as one block:
+//   D = M_KK^{-1};  G_I = M_IK D and P_I = M_IK for the tile rows I outside K;
+//   M_IJ -= G_I P_J^T (I, J outside K);  M_IK <- G_I;  M_KK <- -D.
+// Sweeping K at once equals sweeping its columns one by one, and every pass
+// over the stored tiles does 32 x 32 x 32 w multiply-adds per tile instead of
+// 32 x 32 x 32, so the passes over M fall from nb to about nb / SW. The
+// pivot-block inverse costs (32 SW)^2 scalar updates per pivot, latency-bound:
+// measured at SW = 1, 2 and 4, two tile columns per step gave the fastest
+// setups (four halve the passes again but the 128 x 128 inverse costs more than
+// that saves).
+constexpr int SW = 2;                   // tile columns per block step
+constexpr int BW = SW * TILE;           // pivot block edge
+constexpr int BH = BW / 2;              // inner-dimension chunk of the update
+constexpr int PIV_T = 256;              // threads of the pivot-block inverse
+constexpr int PIV_TPR = PIV_T / BW;     // threads per row of the block
+constexpr int PIV_EPT = BW / PIV_TPR;   // entries per thread (one row segment)
+static_assert(PIV_EPT * PIV_TPR == BW && PIV_T % BW == 0, "pivot block layout");
 
 // 32 x 32 x 32 tile products on the matrix cores: v_mfma_f64_16x16x4f64 takes a
 // 16 x 4 block of A (lane l holds A[l%16][l/16]) and a 4 x 16 block of B (lane l
 // holds B[l/16][l%16]) and accumulates into a 16 x 16 block of which lane l holds
-// rows l/16, l/16 + 4, l/16 + 8 and l/16 + 12 of column l%16. Each of the 4 waves of a workgroup
-// owns one 16 x 16 quadrant of the output tile; the K = 32 sum takes 8 steps in
-// increasing k.
+// rows l/16, l/16 + 4, l/16 + 8 and l/16 + 12 of column l%16.
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// grid: (system, I); P_I = M_Ik (transpose of tile (k, I) when I < k), G_I = P_I Dinv
-__global__ __launch_bounds__(256) void k_sweep_panel(int k, const SweepSys *__restrict__ sys, const double *__restrict__ M,
-                                                     const double *__restrict__ Dinv, double *__restrict__ Pbuf,
-                                                     double *__restrict__ Gbuf) {
-  __shared__ double P[TILE][TILE + 1];
-  __shared__ double Dl[TILE][TILE + 1];
-  const SweepSys S = sys[blockIdx.x];
-  const int I = blockIdx.y;
-  if (k >= S.nb || I >= S.nb || I == k) return;
-  const double *src = (I > k) ? tile_ptr((double *)M, S.tile_off, I, k) : tile_ptr((double *)M, S.tile_off, k, I);
-  const double *dv = Dinv + (int64_t)blockIdx.x * TILE * TILE;
-  for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) {
-    const int i = t / TILE, j = t % TILE;
-    if (I > k)
-      P[i][j] = src[t];
-    else
-      P[j][i] = src[t];
-    Dl[i][j] = dv[t];
-  }
-  __syncthreads();
-  double *po = Pbuf + (S.pan_off + I) * (TILE * TILE);
-  double *go = Gbuf + (S.pan_off + I) * (TILE * TILE);
-  for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) po[t] = P[t / TILE][t % TILE];
-  const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
-  const int r0 = (w >> 1) * 16, c0 = (w & 1) * 16, cl = l % 16, kq = l / 16;
-  v4d acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int st = 0; st < TILE / 4; ++st)
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(P[r0 + cl][4 * st + kq], Dl[4 * st + kq][c0 + cl], acc, 0, 0, 0);
-#pragma unroll
-  for (int r = 0; r < 4; ++r) go[(r0 + kq + 4 * r) * TILE + c0 + cl] = acc[r];
+// Workgroups are dealt to the 8 XCDs round robin (workgroup b to XCD b % 8):
+// with a grid that is a multiple of 8, XCD x gets the contiguous work range
+// [x per, (x + 1) per), so the tiles of one system share an L2.
+__device__ __forceinline__ int xcd_grouped(int bid, int nblk) {
+  const int per = nblk / 8;
+  return (bid % 8) * per + bid / 8;
 }
 
-// grid: (system, tile) over the lower tiles
-__global__ __launch_bounds__(256) void k_sweep_update(int k, const SweepSys *__restrict__ sys, const int32_t *__restrict__ tsys,
-                                                      const int16_t *__restrict__ tI, const int16_t *__restrict__ tJ,
-                                                      double *__restrict__ M, const double *__restrict__ Dinv,
-                                                      const double *__restrict__ Pbuf, const double *__restrict__ Gbuf) {
-  __shared__ double G[TILE][TILE + 1];
-  __shared__ double Pj[TILE][TILE + 1];
-  const int t0 = blockIdx.x;
-  const int s = tsys[t0];
-  const SweepSys S = sys[s];
-  if (k >= S.nb) return;
-  const int I = tI[t0], J = tJ[t0];
-  double *Mt = tile_ptr(M, S.tile_off, I, J);
-  if (I == k && J == k) {
-    const double *dv = Dinv + (int64_t)s * TILE * TILE;
-    for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) Mt[t] = -dv[t];
-    return;
+// Entry (i, c) of the pivot block M_KK (i, c < 32 w) from the lower tiles.
+__device__ __forceinline__ double kblock_at(const double *M, int64_t toff, int k0, int i, int c) {
+  const int I = i / TILE, J = c / TILE;
+  if (I >= J) return tile_ptr((double *)M, toff, k0 + I, k0 + J)[(i % TILE) * TILE + c % TILE];
+  return tile_ptr((double *)M, toff, k0 + J, k0 + I)[(c % TILE) * TILE + i % TILE];
+}
+
+// D = M_KK^{-1} by Gauss-Jordan on the 32 w x 32 w block, one workgroup per
+// system: thread t holds row t / PIV_TPR, columns PIV_EPT (t % PIV_TPR) onwards,
+// in registers; the PIV_TPR threads of a row are neighbouring lanes of one
+// wavefront. Per pivot j every thread takes its row's entry in column j from the
+// owning lane; row j is scaled by the reciprocal of the pivot and published
+// through LDS (buffers alternating between pivots, one barrier per pivot), and
+// every other row subtracts its multiple. Each pivot is a diagonal entry of a
+// Schur complement of the SPD system and is tested as above.
+__global__ __launch_bounds__(PIV_T) void k_bsweep_pivot(int kb, const SweepSys *__restrict__ sys,
+                                                        const double *__restrict__ M, double *__restrict__ Dbuf,
+                                                        const double *__restrict__ diag0, int *__restrict__ status) {
+  static_assert(WAVE % PIV_TPR == 0, "a row's threads share a wavefront");
+  __shared__ double rowb[2][BW];
+  __shared__ int bad;
+  const SweepSys S = sys[blockIdx.x];
+  const int k0 = kb * SW;
+  if (k0 >= S.nb) return;
+  const int n = min(SW, S.nb - k0) * TILE;
+  const int i = threadIdx.x / PIV_TPR, c0 = (threadIdx.x % PIV_TPR) * PIV_EPT;
+  double a[PIV_EPT];
+#pragma unroll
+  for (int e = 0; e < PIV_EPT; ++e) {
+    const int c = c0 + e;
+    a[e] = (i < n && c < n) ? kblock_at(M, S.tile_off, k0, i, c) : (i == c ? 1.0 : 0.0);
   }
-  if (J == k) {  // I > k: M_Ik <- G_I
-    const double *g = Gbuf + (S.pan_off + I) * (TILE * TILE);
-    for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) Mt[t] = g[t];
-    return;
-  }
-  if (I == k) {  // J < k: M_kJ <- G_J^T
-    const double *g = Gbuf + (S.pan_off + J) * (TILE * TILE);
-    for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) Mt[t] = g[(t % TILE) * TILE + t / TILE];
-    return;
-  }
-  // M_IJ -= G_I P_J^T on the matrix cores (the accumulator starts from M_IJ)
-  const double *g = Gbuf + (S.pan_off + I) * (TILE * TILE);
-  const double *p = Pbuf + (S.pan_off + J) * (TILE * TILE);
-  for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) {
-    const int i = t / TILE, j = t % TILE;
-    G[i][j] = -g[t];
-    Pj[i][j] = p[t];
+  if (threadIdx.x == 0) bad = 0;
+  const double *d0 = diag0 + (S.pan_off + k0) * TILE;
+  const int lane = threadIdx.x % WAVE, row_lane0 = lane - lane % PIV_TPR;
+  __syncthreads();
+  for (int j0 = 0; j0 < n; j0 += PIV_EPT) {
+    const bool own = (c0 == j0);   // this thread holds columns j0 .. j0 + PIV_EPT - 1
+    const int src = row_lane0 + j0 / PIV_EPT;
+#pragma unroll
+    for (int q = 0; q < PIV_EPT; ++q) {
+      const int j = j0 + q, b = j & 1;
+      const double f = __shfl(a[q], src, WAVE);   // entry (i, j) of this row
+      if (i == j) {
+        if (own && (!(f > PIVOT_RTOL * d0[j]) || !isfinite(f))) bad = 1;
+        const double rp = 1.0 / f;
+#pragma unroll
+        for (int e = 0; e < PIV_EPT; ++e) {
+          const double v = (own && e == q) ? rp : a[e] * rp;
+          a[e] = v;
+          rowb[b][c0 + e] = v;
+        }
+      }
+      __syncthreads();
+      if (i != j && i < n) {
+#pragma unroll
+        for (int e = 0; e < PIV_EPT; ++e) a[e] = ((own && e == q) ? 0.0 : a[e]) - f * rowb[b][c0 + e];
+      }
+    }
   }
   __syncthreads();
-  const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
-  const int r0 = (w >> 1) * 16, c0 = (w & 1) * 16, cl = l % 16, kq = l / 16;
+  double *out = Dbuf + (int64_t)blockIdx.x * BW * BW + (int64_t)i * BW + c0;
+  if (i < n) {
+#pragma unroll
+    for (int e = 0; e < PIV_EPT; ++e)
+      if (c0 + e < n) out[e] = a[e];
+  }
+  if (threadIdx.x == 0 && bad) status[blockIdx.x] = 1;
+}
+
+// grid: 8 ceil(ns maxnb / 8) workgroups over the (system, tile row I) pairs,
+// system-major and XCD-grouped. For I outside K: P_I = M_IK (stored tiles
+// (I, k0 + j) below K, transposes of (k0 + j, I) above it, each read in its
+// stored order) as a 32 x BW row strip, kept, and G_I = P_I D on the matrix
+// cores: wavefront v takes the 16-column blocks v and v + 4 for both row halves,
+// with the block's D operands (from the L2) loaded into registers first.
+__global__ __launch_bounds__(256) void k_bsweep_panel(int kb, int ns, int maxnb, const SweepSys *__restrict__ sys,
+                                                      const double *__restrict__ M, const double *__restrict__ Dbuf,
+                                                      double *__restrict__ Pbuf, double *__restrict__ Gbuf) {
+  __shared__ double Pl[TILE][BW + 1];
+  const int q = xcd_grouped((int)blockIdx.x, (int)gridDim.x);
+  if (q >= ns * maxnb) return;
+  const int s = q / maxnb, I = q % maxnb;
+  const SweepSys S = sys[s];
+  const int k0 = kb * SW;
+  if (k0 >= S.nb || I >= S.nb) return;
+  const int w = min(SW, S.nb - k0), n = w * TILE;
+  if (I >= k0 && I < k0 + w) return;
+  for (int t = threadIdx.x; t < TILE * BW; t += blockDim.x) {
+    const int j = t / (TILE * TILE), e = t % (TILE * TILE);
+    if (j < w) {
+      if (I > k0)
+        Pl[e / TILE][j * TILE + e % TILE] = tile_ptr((double *)M, S.tile_off, I, k0 + j)[e];
+      else
+        Pl[e % TILE][j * TILE + e / TILE] = tile_ptr((double *)M, S.tile_off, k0 + j, I)[e];
+    } else {
+      Pl[e / TILE][j * TILE + e % TILE] = 0.0;
+    }
+  }
+  __syncthreads();
+  double *po = Pbuf + (S.pan_off + I) * (TILE * BW);
+  for (int t = threadIdx.x; t < TILE * BW; t += blockDim.x) po[t] = Pl[t / BW][t % BW];
+  const double *D = Dbuf + (int64_t)s * BW * BW;
+  double *go = Gbuf + (S.pan_off + I) * (TILE * BW);
+  const int wv = threadIdx.x / WAVE, l = threadIdx.x % WAVE, cl = l % 16, kq = l / 16;
+  const int nst = n / 4;
+  for (int cb = wv; cb * 16 < n; cb += 4) {
+    double dv[BW / 4];
+#pragma unroll
+    for (int st = 0; st < BW / 4; ++st) dv[st] = (st < nst) ? D[(4 * st + kq) * BW + cb * 16 + cl] : 0.0;
+    v4d a0 = {0.0, 0.0, 0.0, 0.0}, a1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int st = 0; st < BW / 4; ++st) {
+      if (st < nst) {
+        a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(Pl[cl][4 * st + kq], dv[st], a0, 0, 0, 0);
+        a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(Pl[16 + cl][4 * st + kq], dv[st], a1, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      go[(kq + 4 * r) * BW + cb * 16 + cl] = a0[r];
+      go[(16 + kq + 4 * r) * BW + cb * 16 + cl] = a1[r];
+    }
+  }
+}
+
+// grid: 8 ceil(ntiles / 8) workgroups over the lower tiles of all systems
+// (XCD-grouped). Tiles with both indices in K take -D, tiles with one take G
+// (transposed above K); the others M_IJ -= G_I P_J^T on the matrix cores, each
+// wavefront owning one 16 x 16 quadrant, the accumulator starting from M_IJ and
+// the inner dimension staged through LDS (coalesced 16-byte loads) in chunks of
+// BH. (Operands loaded by each lane straight from the strips, without LDS,
+// touch one cache line per lane and load: measured twice as slow.)
+__global__ __launch_bounds__(256) void k_bsweep_update(int kb, int ntiles, const SweepSys *__restrict__ sys,
+                                                       const int32_t *__restrict__ tsys,
+                                                       const int16_t *__restrict__ tI, const int16_t *__restrict__ tJ,
+                                                       double *__restrict__ M, const double *__restrict__ Dbuf,
+                                                       const double *__restrict__ Pbuf,
+                                                       const double *__restrict__ Gbuf) {
+  __shared__ double Gs[TILE][BH + 1];
+  __shared__ double Ps[TILE][BH + 1];
+  const int t0 = xcd_grouped((int)blockIdx.x, (int)gridDim.x);
+  if (t0 >= ntiles) return;
+  const int s = tsys[t0];
+  const SweepSys S = sys[s];
+  const int k0 = kb * SW;
+  if (k0 >= S.nb) return;
+  const int w = min(SW, S.nb - k0), n = w * TILE;
+  const int I = tI[t0], J = tJ[t0];
+  double *Mt = tile_ptr(M, S.tile_off, I, J);
+  const bool iK = I >= k0 && I < k0 + w, jK = J >= k0 && J < k0 + w;
+  if (iK && jK) {  // M_IJ <- -D, block (I - k0, J - k0)
+    const double *dv = Dbuf + (int64_t)s * BW * BW + (I - k0) * TILE * BW + (J - k0) * TILE;
+    for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) Mt[t] = -dv[(t / TILE) * BW + t % TILE];
+    return;
+  }
+  if (jK) {  // I past K: M_IJ <- columns J - k0 of G_I
+    const double *g = Gbuf + (S.pan_off + I) * (TILE * BW) + (J - k0) * TILE;
+    for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) Mt[t] = g[(t / TILE) * BW + t % TILE];
+    return;
+  }
+  if (iK) {  // J before K: M_IJ <- (columns I - k0 of G_J)^T
+    const double *g = Gbuf + (S.pan_off + J) * (TILE * BW) + (I - k0) * TILE;
+    for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) Mt[t] = g[(t % TILE) * BW + t / TILE];
+    return;
+  }
+  const double *g = Gbuf + (S.pan_off + I) * (TILE * BW);
+  const double *p = Pbuf + (S.pan_off + J) * (TILE * BW);
+  const int wv = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+  const int r0 = (wv >> 1) * 16, c0 = (wv & 1) * 16, cl = l % 16, kq = l / 16;
   double *mo = Mt + (r0 + kq) * TILE + c0 + cl;
   v4d acc = {mo[0], mo[4 * TILE], mo[8 * TILE], mo[12 * TILE]};
-#pragma unroll
-  for (int st = 0; st < TILE / 4; ++st)
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(G[r0 + cl][4 * st + kq], Pj[c0 + cl][4 * st + kq], acc, 0, 0, 0);
+  for (int h = 0; h * BH < n; ++h) {
+    if (h > 0) __syncthreads();
+    for (int t = threadIdx.x; t < TILE * BH / 2; t += blockDim.x) {
+      const int i = t / (BH / 2), j = 2 * (t % (BH / 2));
+      const double2 gv = *(const double2 *)(g + i * BW + h * BH + j);
+      const double2 pv = *(const double2 *)(p + i * BW + h * BH + j);
+      Gs[i][j] = -gv.x;
+      Gs[i][j + 1] = -gv.y;
+      Ps[i][j] = pv.x;
+      Ps[i][j + 1] = pv.y;
+    }
+    __syncthreads();
+    const int nst = min(BH, n - h * BH) / 4;
+#pragma unroll 8
+    for (int st = 0; st < nst; ++st)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Gs[r0 + cl][4 * st + kq], Ps[c0 + cl][4 * st + kq], acc, 0, 0, 0);
+  }
 #pragma unroll
   for (int r = 0; r < 4; ++r) mo[4 * r * TILE] = acc[r];
 }
