@@ -5,6 +5,7 @@ batch members are also checked against the oracle."""
 import numpy as np
 import pytest
 
+from iteration_bar import check_fp64_iters
 from oracle import problem
 from paper_2606_20496_amd import coarse, meshgen as mg
 
@@ -77,7 +78,7 @@ def test_solve_batch_api_matches_oracle():
     for m, u, st in zip(ms, us, sts):
         P = problem.from_mesh(m)
         uo, io = P.solve(m.b)
-        assert st["iters"] == io["iters"]
+        check_fp64_iters(st["iters"], P, m.b, io["iters"])
         # batch meshes with i.i.d. right-hand sides: the same Krylov iterate in two
         # rounding orders drifts further apart than on smooth right-hand sides
         assert np.linalg.norm(u.cpu().numpy() - uo) / np.linalg.norm(uo) < 1e-7
@@ -196,7 +197,8 @@ def test_batch_workload_against_oracle():
             st = done[k]
             assert st["status"] == 0 and st["relres"] <= 1e-8, (precision, k)
             if precision == "fp64":
-                assert st["iters"] == io["iters"], (k, st["iters"], io["iters"])
+                if st["iters"] != io["iters"]:
+                    check_fp64_iters(st["iters"], problem.from_mesh(ms[k]), ms[k].b, io["iters"], what=k)
             else:
                 # 10% more, but at least two more: a mesh of one subdomain has an
                 # exact local part and the FP64 method converges in two

@@ -3,6 +3,7 @@ reused ones, admitted while others run) completes with the same result,
 bitwise, as a solo solve of its mesh and right-hand side, within the HBM
 budget's admission rules."""
 import pytest
+from iteration_bar import check_fp64_iters
 
 from paper_2606_20496_amd import coarse, serve
 
@@ -202,14 +203,9 @@ def test_served_stretched_meshes_match_oracle(precision):
         r = by[rq.rid]
         assert r.status == 0 and r.relres_true <= 1.01e-8
         if precision == "fp64":
-            # the iteration counts the oracle itself reaches when b is perturbed at
-            # the rounding level (on these stretched meshes the residual history
-            # near the tolerance moves by up to 20% under a 1e-13 perturbation)
-            counts = {io["iters"]}
-            for seed in range(4):
-                xi = np.random.default_rng(seed).standard_normal(rq.mesh.n_vert)
-                counts.add(P.solve(rq.b * (1 + 1e-13 * xi), tol=1e-8)[1]["iters"])
-            assert r.iters in counts, (r.iters, counts)
+            # on these stretched meshes the residual history near the tolerance
+            # moves by up to 20% under a 1e-13 perturbation: the knife-edge bar
+            check_fp64_iters(r.iters, P, rq.b, io["iters"], what=rq.rid)
         else:
             assert r.iters <= max(math.ceil(1.1 * io["iters"]), io["iters"] + 2)
         u = r.u.detach().cpu().numpy()
