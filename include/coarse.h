@@ -399,6 +399,17 @@ int coarse_batch_submit(coarse_batch *bt, coarse_ctx *ctx, const double *b, doub
  * finished solves stay live (their iterations are skipped) until a later step
  * retires them. */
 int coarse_batch_step(coarse_batch *bt, int iters, int64_t *tags, coarse_stats *stats, int cap, int *n_done);
+/* coarse_batch_step in two halves, so that the caller can do other work (for
+ * instance the device half of another context's setup, on another stream) while
+ * the lock steps run. coarse_batch_launch queues `iters` lock steps and the copy
+ * of the solver states to the host, and returns without waiting;
+ * coarse_batch_collect waits for them and retires finished solves exactly as
+ * coarse_batch_step does (0 of them when nothing was launched). Between the two,
+ * coarse_batch_submit and a second launch return COARSE_EINVAL, and the contexts
+ * in the batch must not be used. launch followed by collect gives the same
+ * results, bit for bit, as step. */
+int coarse_batch_launch(coarse_batch *bt, int iters);
+int coarse_batch_collect(coarse_batch *bt, int64_t *tags, coarse_stats *stats, int cap, int *n_done);
 int coarse_batch_live(const coarse_batch *bt);
 int coarse_batch_destroy(coarse_batch *bt);
 

@@ -29,7 +29,7 @@ EXPORTS = ("coarse_default_opts", "coarse_setup", "coarse_apply_precond", "coars
            "coarse_solve", "coarse_solve_batch", "coarse_destroy", "coarse_device_bytes",
            "coarse_get_info", "coarse_set_stream", "coarse_plan_info", "coarse_strerror",
            "coarse_last_error", "coarse_profile", "coarse_batch_create", "coarse_batch_submit",
-           "coarse_batch_step", "coarse_batch_live", "coarse_batch_destroy", "coarse_plan_create",
+           "coarse_batch_step", "coarse_batch_launch", "coarse_batch_collect", "coarse_batch_live", "coarse_batch_destroy", "coarse_plan_create",
            "coarse_setup_from_plan", "coarse_plan_destroy", "coarse_plan_set_gemv_tiles",
            "coarse_solve_projected", "coarse_projection_reset", "coarse_solve_multi",
            "coarse_apply_precond_multi", "coarse_multi_begin", "coarse_multi_advance", "coarse_multi_done",
@@ -187,6 +187,10 @@ def load():
     L.coarse_batch_submit.restype = i32
     L.coarse_batch_step.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(_Stats), i32, ctypes.POINTER(i32)]
     L.coarse_batch_step.restype = i32
+    L.coarse_batch_launch.argtypes = [vp, i32]
+    L.coarse_batch_launch.restype = i32
+    L.coarse_batch_collect.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(_Stats), i32, ctypes.POINTER(i32)]
+    L.coarse_batch_collect.restype = i32
     L.coarse_batch_live.argtypes = [vp]
     L.coarse_batch_live.restype = i32
     L.coarse_batch_destroy.argtypes = [vp]
@@ -601,6 +605,27 @@ class Batch:
         rc = self._L.coarse_batch_step(self._bt, int(iters), tags, st, int(cap), ctypes.byref(nd))
         if rc != 0:
             raise CoarseError(rc, "batch step failed")
+        return self._retired(tags, st, nd)
+
+    def launch(self, iters=1):
+        """First half of :meth:`step`: queue ``iters`` iterations of every live solve
+        and return at once (no submit until :meth:`collect`)."""
+        rc = self._L.coarse_batch_launch(self._bt, int(iters))
+        if rc != 0:
+            raise CoarseError(rc, "batch launch failed")
+
+    def collect(self, cap=4096):
+        """Second half of :meth:`step`: wait for the launched iterations; returns
+        [(tag, stats)] of the solves that finished ([] when nothing was launched)."""
+        tags = (ctypes.c_int64 * cap)()
+        st = (_Stats * cap)()
+        nd = ctypes.c_int(0)
+        rc = self._L.coarse_batch_collect(self._bt, tags, st, int(cap), ctypes.byref(nd))
+        if rc != 0:
+            raise CoarseError(rc, "batch collect failed")
+        return self._retired(tags, st, nd)
+
+    def _retired(self, tags, st, nd):
         out = []
         for k in range(nd.value):
             d = {f: getattr(st[k], f) for f, _ in _Stats._fields_}

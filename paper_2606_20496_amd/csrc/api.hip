@@ -1578,6 +1578,7 @@ struct coarse_batch {
   std::vector<Entry> live;
   int precision = -1, whole_waves = 4;
   bool dirty = true, use_graph = false;
+  bool pending = false;      // lock steps launched, their solver states not yet collected
   Seg *d_seg = nullptr;      // [3][cap]: item, row and whole-system segments
   Seg *h_seg = nullptr;      // pinned staging
   IterDev *d_iter = nullptr, *h_iter = nullptr;   // [cap] per-solve state
@@ -1650,6 +1651,10 @@ struct coarse_batch {
   }
 
   int submit(coarse_ctx *c, const double *b, double *u, double tol, int64_t tag) {
+    if (pending) {
+      err = "lock steps launched and not yet collected";
+      return COARSE_EINVAL;
+    }
     if (c->mode != COARSE_ADDITIVE) {
       err = "batched solves use the additive preconditioner";
       return COARSE_EINVAL;
@@ -1775,7 +1780,18 @@ struct coarse_batch {
   }
 
   int step(int iters, int64_t *tags, coarse_stats *stats, int capn, int *n_done) {
-    *n_done = 0;
+    const int rc = launch(iters);
+    if (rc != COARSE_OK) return rc;
+    return collect(tags, stats, capn, n_done);
+  }
+
+  // Queue `iters` lock steps and the copy of the solver states to the host,
+  // without waiting for them.
+  int launch(int iters) {
+    if (pending) {
+      err = "lock steps launched and not yet collected";
+      return COARSE_EINVAL;
+    }
     if (live.empty()) return COARSE_OK;
     if (dirty) rebuild_tables();
     // a graph is captured only while no setup, destruction or allocation runs
@@ -1810,6 +1826,16 @@ struct coarse_batch {
     hipLaunchKernelGGL(k_gather_scalars, dim3(nblk(n, 64)), dim3(64), 0, main, (const IterDev *)d_iter, n, d_sc);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(h_sc, d_sc, n * sizeof(Scalars), hipMemcpyDeviceToHost, main));
+    pending = true;
+    return COARSE_OK;
+  }
+
+  // Wait for the launched lock steps, then retire up to capn finished solves.
+  int collect(int64_t *tags, coarse_stats *stats, int capn, int *n_done) {
+    *n_done = 0;
+    if (!pending) return COARSE_OK;
+    pending = false;
+    const int n = (int)live.size();
     HIPCHK(hipStreamSynchronize(main));
     for (int k = 0; k < n; ++k) *live[k].c->h_sc = h_sc[k];
     // retire at most capn finished solves; any others stay (their iterations are
@@ -2439,6 +2465,26 @@ int coarse_batch_step(coarse_batch *bt, int iters, int64_t *tags, coarse_stats *
   if (!bt || iters < 1 || !n_done || cap < 0) return COARSE_EINVAL;
   try {
     return bt->step(iters, tags, stats, cap, n_done);
+  } catch (const Fail &f) {
+    bt->err = f.what();
+    return f.code;
+  }
+}
+
+int coarse_batch_launch(coarse_batch *bt, int iters) {
+  if (!bt || iters < 1) return COARSE_EINVAL;
+  try {
+    return bt->launch(iters);
+  } catch (const Fail &f) {
+    bt->err = f.what();
+    return f.code;
+  }
+}
+
+int coarse_batch_collect(coarse_batch *bt, int64_t *tags, coarse_stats *stats, int cap, int *n_done) {
+  if (!bt || !n_done || cap < 0) return COARSE_EINVAL;
+  try {
+    return bt->collect(tags, stats, cap, n_done);
   } catch (const Fail &f) {
     bt->err = f.what();
     return f.code;

@@ -309,18 +309,21 @@ class Server:
                 else:
                     keep.append(rq)
             waiting = keep
-            # device halves of ready plans while the budget allows; contexts a
-            # waiting request needs are never evicted, and a context that does not
-            # fit even with everything idle evicted is built only when no solve runs
             needed = {rq.key for rq in waiting}
-            for key, (plan, need) in list(self.ready.items()):
-                if self._evict_for(need, keep=needed) or (not live and not self.blocks):
-                    td = time.perf_counter()
-                    S = self._device_setup(plan)
-                    self.setup_times["device_s"].append(time.perf_counter() - td)
-                    plan.close()
-                    del self.ready[key]
-                    self._admit(key, S, estimate=need)
+
+            def device_setups():
+                # device halves of ready plans while the budget allows; contexts a
+                # waiting request needs are never evicted, and a context that does
+                # not fit even with everything idle evicted is built only when no
+                # solve runs
+                for key, (plan, need) in list(self.ready.items()):
+                    if self._evict_for(need, keep=needed) or (not live and not self.blocks):
+                        td = time.perf_counter()
+                        S = self._device_setup(plan)
+                        self.setup_times["device_s"].append(time.perf_counter() - td)
+                        plan.close()
+                        del self.ready[key]
+                        self._admit(key, S, estimate=need)
             # host plans for new meshes
             for rq in waiting:
                 if rq.key in self.cache or rq.key in self.planning or rq.key in self.ready:
@@ -344,7 +347,12 @@ class Server:
                     blk[1] += k
                 for e in live.values():
                     e[3] += k
-                finished = self.batch.step(k) if live else []
+                # the lock steps are queued first and collected after the device
+                # setups, which run on the setup stream meanwhile
+                if live:
+                    self.batch.launch(k)
+                device_setups()
+                finished = self.batch.collect() if live else []
                 if not live:
                     self.stream.synchronize()
                 for key in list(self.blocks):
@@ -371,7 +379,10 @@ class Server:
                                           setup=rq.rid in missed, status=st["status"],
                                           u=u if self.keep_outputs else None, relres0=st["relres0"]))
             else:
-                time.sleep(0.0005)
+                n_ready = len(self.ready)
+                device_setups()
+                if len(self.ready) == n_ready:
+                    time.sleep(0.0005)
         self.stream.synchronize()
         return records, now()
 

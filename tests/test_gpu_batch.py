@@ -70,6 +70,55 @@ def test_batch_equals_alone(precision, graph):
     bt.close()
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_launch_collect_with_setups_between_equals_alone(graph):
+    # the two halves of a step with device setups of other meshes (on another
+    # stream) between them, as the server runs them: bitwise the solo solves
+    ms = _meshes()
+    ref = _alone(ms, "mixed")
+    others = mg.batch_meshes(count=12, nmax=24)[8:]
+    stream = torch.cuda.Stream()
+    setup_stream = torch.cuda.Stream()
+    solvers = [coarse.CoarseSolver.from_mesh(m, precision="mixed") for m in ms]
+    plans = [coarse.Plan.from_mesh(m, precision="mixed") for m in others]
+    bs = [torch.tensor(m.b, device="cuda") for m in ms]
+    us = [torch.zeros_like(b) for b in bs]
+    torch.cuda.synchronize()
+    bt = coarse.Batch(stream=stream, use_graph=graph)
+    for k in range(4):
+        bt.submit(solvers[k], bs[k], us[k], tag=k)
+    done, built, guard = {}, [], 0
+    while bt.live > 0 or len(done) < len(ms):
+        bt.launch(3)
+        with pytest.raises(coarse.CoarseError):
+            bt.launch(1)   # a second launch before the collect is refused
+        if guard == 0:
+            with pytest.raises(coarse.CoarseError):
+                bt.submit(solvers[4], bs[4], us[4], tag=4)   # and so is a submit
+        if plans:
+            with torch.cuda.stream(setup_stream):
+                built.append(coarse.CoarseSolver.from_plan(plans.pop()))
+            setup_stream.synchronize()
+        for tag, st in bt.collect():
+            done[tag] = st
+        if guard == 1:
+            for k in range(4, len(ms)):
+                bt.submit(solvers[k], bs[k], us[k], tag=k)
+        guard += 1
+        assert guard < 500
+    stream.synchronize()
+    assert bt.collect() == []   # nothing launched
+    for k in range(len(ms)):
+        assert done[k]["code"] == 0 and done[k]["iters"] == ref[k][1]
+        assert torch.equal(us[k], ref[k][0]), k
+    # the contexts built meanwhile solve like freshly set up ones
+    for S, m in zip(built, reversed(mg.batch_meshes(count=12, nmax=24)[8:])):
+        u, st = S.solve(torch.tensor(m.b, device="cuda"))
+        u0, st0 = coarse.CoarseSolver.from_mesh(m, precision="mixed").solve(torch.tensor(m.b, device="cuda"))
+        assert st["iters"] == st0["iters"] and torch.equal(u, u0)
+    bt.close()
+
+
 def test_solve_batch_api_matches_oracle():
     ms = _meshes(4)
     solvers = [coarse.CoarseSolver.from_mesh(m) for m in ms]
