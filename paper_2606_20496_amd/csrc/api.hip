@@ -1298,7 +1298,7 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles, int wh
   std::vector<int64_t> red = {P.n_local_sys};
   const int64_t nr = P.n_r;
   if (c->interp == COARSE_J_CENTROID) {
-    hipLaunchKernelGGL(k_cell_mats, dim3((unsigned)nocc), dim3(64), 0, s, box, occ_cells, occ_ptr, occ_elems, e2v, NE,
+    hipLaunchKernelGGL(k_cell_mats, dim3((unsigned)nocc), dim3(64 * CM_SLOTS), 0, s, box, occ_cells, occ_ptr, occ_elems, e2v, NE,
                        NV, nf, xyz, (const double *)Ae, cellmat);
     // A_r also as its 27-point stencil on the box grid
     if (nr > 0) {

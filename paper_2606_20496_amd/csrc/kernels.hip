@@ -1886,27 +1886,39 @@ __global__ void k_pad_identity(const AsmSys *__restrict__ sys, int nsys, double 
 // Setup: reduced operator by cell assembly, eq. (Aij): for each occupied cell,
 // A_cell = sum over its elements of (J^e)^T A^e J^e, J^e[a][k] = Phi_k(xi_a) with
 // xi_a the local coordinates of element vertex a in the cell (zero rows at
-// Dirichlet vertices). One 64-thread workgroup per cell.
+// Dirichlet vertices). One workgroup per cell of CM_SLOTS wavefronts: slot g
+// (one wavefront, thread (a, l) of the 8 x 8 products) takes the cell's
+// elements g, g + CM_SLOTS, ... in order, and the slots' sums are added in slot
+// order at the end.
 // ---------------------------------------------------------------------------
+constexpr int CM_SLOTS = 8;
 struct BoxDev {
   double lo[3], H[3];
   int32_t b[3], pad;
 };
 
-__global__ __launch_bounds__(64) void k_cell_mats(BoxDev box, const int32_t *__restrict__ occ_cells,
-                                                  const int32_t *__restrict__ occ_ptr, const int32_t *__restrict__ occ_elems,
-                                                  const int32_t *__restrict__ e2v, int64_t E, int64_t NV, int64_t nf,
-                                                  const double *__restrict__ xyz, const double *__restrict__ Ae,
-                                                  double *__restrict__ cellmat) {
-  __shared__ double Je[8][8], T1[8][8];
+__global__ __launch_bounds__(64 * CM_SLOTS) void k_cell_mats(BoxDev box, const int32_t *__restrict__ occ_cells,
+                                                             const int32_t *__restrict__ occ_ptr,
+                                                             const int32_t *__restrict__ occ_elems,
+                                                             const int32_t *__restrict__ e2v, int64_t E, int64_t NV,
+                                                             int64_t nf, const double *__restrict__ xyz,
+                                                             const double *__restrict__ Ae,
+                                                             double *__restrict__ cellmat) {
+  __shared__ double Je[CM_SLOTS][8][8], T1[CM_SLOTS][8][8], part[CM_SLOTS][64];
   const int o = blockIdx.x;
   const int c = occ_cells[o];
   const int c3[3] = {c % box.b[0], (c / box.b[0]) % box.b[1], c / (box.b[0] * box.b[1])};
-  const int t = threadIdx.x, ta = t >> 3, tk = t & 7;
+  const int g = threadIdx.x / 64, t = threadIdx.x % 64, ta = t >> 3, tk = t & 7;
+  const int k0 = occ_ptr[o], ne = occ_ptr[o + 1] - k0;
   double acc = 0.0;
-  for (int k = occ_ptr[o]; k < occ_ptr[o + 1]; ++k) {
-    const int64_t e = occ_elems[k];
-    {
+  for (int r = 0; r * CM_SLOTS < ne; ++r) {
+    const int kk = r * CM_SLOTS + g;
+    const bool has = kk < ne;
+    const int64_t e = has ? occ_elems[k0 + kk] : 0;
+    double ae[8];
+    if (has) {
+#pragma unroll
+      for (int b = 0; b < 8; ++b) ae[b] = Ae[ae_at(sym8(ta, b), e)];
       const int32_t u = e2v[ta * E + e];
       double w = 0.0;
       if (u < nf) {
@@ -1915,25 +1927,32 @@ __global__ __launch_bounds__(64) void k_cell_mats(BoxDev box, const int32_t *__r
         for (int d = 0; d < 3; ++d) xi[d] = ((xyz[d * NV + u] - box.lo[d]) - (double)c3[d] * box.H[d]) / box.H[d];
         w = trilin<double>(tk, xi[0], xi[1], xi[2]);
       }
-      Je[ta][tk] = w;
+      Je[g][ta][tk] = w;
     }
     __syncthreads();
-    {  // T1 = A^e J^e : thread (a, l)
+    if (has) {  // T1 = A^e J^e : thread (a, l)
       double s = 0.0;
 #pragma unroll
-      for (int b = 0; b < 8; ++b) s += Ae[ae_at(sym8(ta, b), e)] * Je[b][tk];
-      T1[ta][tk] = s;
+      for (int b = 0; b < 8; ++b) s += ae[b] * Je[g][b][tk];
+      T1[g][ta][tk] = s;
     }
     __syncthreads();
-    {  // (J^e)^T T1 : thread (k, l) = (ta, tk)
+    if (has) {  // (J^e)^T T1 : thread (k, l) = (ta, tk)
       double s = 0.0;
 #pragma unroll
-      for (int a = 0; a < 8; ++a) s += Je[a][ta] * T1[a][tk];
+      for (int a = 0; a < 8; ++a) s += Je[g][a][ta] * T1[g][a][tk];
       acc += s;
     }
     __syncthreads();
   }
-  cellmat[(int64_t)o * 64 + t] = acc;
+  part[g][t] = acc;
+  __syncthreads();
+  if (g == 0) {
+    double sum = 0.0;
+#pragma unroll
+    for (int h = 0; h < CM_SLOTS; ++h) sum += part[h][t];
+    cellmat[(int64_t)o * 64 + t] = sum;
+  }
 }
 
 // Dense A_r from the cell matrices: row K sums, over the occupied cells around

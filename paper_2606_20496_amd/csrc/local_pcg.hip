@@ -62,7 +62,11 @@ __global__ __launch_bounds__(512) void k_loc_count(const LocSys *__restrict__ sy
   const LocSys S = sys[blockIdx.x];
   const int32_t *R = loc_stage_R(S, sub_idx, lr);
   for (int a = threadIdx.x; a < S.n; a += blockDim.x) {
+    // the distinct columns so far, newest first (compile-time indices only, so
+    // the list stays in registers); unused slots hold -1
     int32_t seen[LOC_WMAX];
+#pragma unroll
+    for (int j = 0; j < LOC_WMAX; ++j) seen[j] = -1;
     int cnt = 0;
     const int32_t v = R[a];
     for (int k = vinc_ptr[v]; k < vinc_ptr[v + 1] && cnt <= LOC_WMAX; ++k) {
@@ -73,13 +77,17 @@ __global__ __launch_bounds__(512) void k_loc_count(const LocSys *__restrict__ sy
         const int pos = loc_find(R, S.n, u);
         if (pos < 0) continue;
         bool dup = false;
-        for (int j = 0; j < cnt; ++j) dup |= (seen[j] == pos);
+#pragma unroll
+        for (int j = 0; j < LOC_WMAX; ++j) dup |= (seen[j] == pos);
         if (dup) continue;
         if (cnt == LOC_WMAX) {
           cnt = LOC_WMAX + 1;
           break;
         }
-        seen[cnt++] = pos;
+#pragma unroll
+        for (int j = LOC_WMAX - 1; j > 0; --j) seen[j] = seen[j - 1];
+        seen[0] = pos;
+        ++cnt;
       }
     }
     atomicMax(wmax, cnt);
@@ -91,7 +99,10 @@ __global__ __launch_bounds__(512) void k_loc_count(const LocSys *__restrict__ sy
 // R_p[a] in their stored order, the element-matrix row of that vertex restricted
 // to the columns in R_p (the same entries the dense assembly adds); columns are
 // kept in increasing order, unused slots hold column a with value 0. *bad counts
-// rows whose diagonal is not positive.
+// rows whose diagonal is not positive. The row under construction is a sorted
+// register list (INT32_MAX in unused slots) updated with compile-time indices
+// only: a column already present takes the value, a new one is inserted by one
+// downward pass that moves the larger columns up a slot.
 // ---------------------------------------------------------------------------
 template <typename V>
 __global__ __launch_bounds__(512) void k_loc_fill(const LocSys *__restrict__ sys, int W,
@@ -107,6 +118,11 @@ __global__ __launch_bounds__(512) void k_loc_fill(const LocSys *__restrict__ sys
   for (int a = threadIdx.x; a < S.n; a += blockDim.x) {
     int32_t cs[LOC_WMAX];
     double vs[LOC_WMAX];
+#pragma unroll
+    for (int j = 0; j < LOC_WMAX; ++j) {
+      cs[j] = INT32_MAX;
+      vs[j] = 0.0;
+    }
     int cnt = 0;
     double d = 0.0;
     const int32_t v = R[a];
@@ -123,25 +139,35 @@ __global__ __launch_bounds__(512) void k_loc_fill(const LocSys *__restrict__ sys
         }
         const int pos = loc_find(R, S.n, u);
         if (pos < 0) continue;
-        int j = 0;
-        while (j < cnt && cs[j] < pos) ++j;
-        if (j < cnt && cs[j] == pos) {
-          vs[j] += x;
-          continue;
-        }
+        bool found = false;
+#pragma unroll
+        for (int j = 0; j < LOC_WMAX; ++j)
+          if (cs[j] == pos) {
+            vs[j] += x;
+            found = true;
+          }
+        if (found) continue;
         if (cnt == W) continue;   // cannot happen: W is the maximum count of pass 1
-        for (int m = cnt; m > j; --m) {
-          cs[m] = cs[m - 1];
-          vs[m] = vs[m - 1];
+#pragma unroll
+        for (int j = LOC_WMAX - 1; j >= 0; --j) {
+          const int32_t below = j > 0 ? cs[j - 1] : INT32_MIN;
+          const double vbelow = j > 0 ? vs[j - 1] : 0.0;
+          if (below > pos) {
+            cs[j] = below;
+            vs[j] = vbelow;
+          } else if (cs[j] > pos) {
+            cs[j] = pos;
+            vs[j] = x;
+          }
         }
-        cs[j] = pos;
-        vs[j] = x;
         ++cnt;
       }
     }
     if (!(d > 0.0)) atomicAdd(bad, 1);
     diag[S.vec_off + a] = d;
-    for (int k = 0; k < W; k += 2) {
+#pragma unroll
+    for (int k = 0; k < LOC_WMAX; k += 2) {
+      if (k >= W) break;
       const uint32_t c0 = (uint32_t)(k < cnt ? cs[k] : a);
       const uint32_t c1 = (uint32_t)(k + 1 < cnt ? cs[k + 1] : a);
       col[S.ell_off / 2 + (int64_t)(k / 2) * S.npad + a] = c0 | (c1 << 16);
