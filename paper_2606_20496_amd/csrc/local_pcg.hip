@@ -165,15 +165,17 @@ __global__ __launch_bounds__(512) void k_loc_fill(const LocSys *__restrict__ sys
     }
     if (!(d > 0.0)) atomicAdd(bad, 1);
     diag[S.vec_off + a] = d;
+    // (a guard, not a break: leaving the unrolled loop early would put the row
+    // lists in scratch memory)
 #pragma unroll
-    for (int k = 0; k < LOC_WMAX; k += 2) {
-      if (k >= W) break;
-      const uint32_t c0 = (uint32_t)(k < cnt ? cs[k] : a);
-      const uint32_t c1 = (uint32_t)(k + 1 < cnt ? cs[k + 1] : a);
-      col[S.ell_off / 2 + (int64_t)(k / 2) * S.npad + a] = c0 | (c1 << 16);
-      val[S.ell_off + (int64_t)k * S.npad + a] = (V)(k < cnt ? vs[k] : 0.0);
-      val[S.ell_off + (int64_t)(k + 1) * S.npad + a] = (V)(k + 1 < cnt ? vs[k + 1] : 0.0);
-    }
+    for (int k = 0; k < LOC_WMAX; k += 2)
+      if (k < W) {
+        const uint32_t c0 = (uint32_t)(k < cnt ? cs[k] : a);
+        const uint32_t c1 = (uint32_t)(k + 1 < cnt ? cs[k + 1] : a);
+        col[S.ell_off / 2 + (int64_t)(k / 2) * S.npad + a] = c0 | (c1 << 16);
+        val[S.ell_off + (int64_t)k * S.npad + a] = (V)(k < cnt ? vs[k] : 0.0);
+        val[S.ell_off + (int64_t)(k + 1) * S.npad + a] = (V)(k + 1 < cnt ? vs[k + 1] : 0.0);
+      }
   }
 }
 
