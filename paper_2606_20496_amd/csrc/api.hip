@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <mutex>
 #include <stdexcept>
@@ -254,6 +255,66 @@ struct Arena {
     drop_hold();
     release();
   }
+};
+
+// Several small uploads as one copy: add() packs a host array into the arena's
+// pinned staging and notes where its device address goes; commit() (also at the
+// end of the batch's scope) carves one device block for all of them, issues one
+// copy and writes the addresses. Arrays of more than Arena::kSmall bytes are
+// uploaded on their own at add(). Commit before anything reads the addresses or
+// the data.
+class UploadBatch {
+ public:
+  UploadBatch(Arena &a, hipStream_t s) : a_(a), s_(s) {}
+  UploadBatch(const UploadBatch &) = delete;
+  UploadBatch &operator=(const UploadBatch &) = delete;
+  ~UploadBatch() {
+    try {
+      commit();
+    } catch (...) {
+    }
+  }
+  template <typename P, typename T>
+  void add(P *dst, const std::vector<T> &v) {
+    const size_t nb = v.size() * sizeof(T);
+    if (nb > Arena::kSmall) {
+      *dst = (P)a_.upload(v, s_);
+      return;
+    }
+    const size_t nba = (std::max<size_t>(nb, sizeof(T)) + Arena::kAlign - 1) / Arena::kAlign * Arena::kAlign;
+    if (a_.staging_used + nba > StagingPool::kSlab) {
+      commit();
+      a_.staging.push_back(g_staging.get());
+      a_.staging_used = 0;
+    }
+    if (fix_.empty()) start_ = a_.staging_used;
+    const size_t off = a_.staging_used - start_;
+    if (nb) std::memcpy((char *)a_.staging.back() + a_.staging_used, v.data(), nb);
+    a_.staging_used += nba;
+    fix_.push_back([dst, off](char *base) { *dst = (P)(base + off); });
+  }
+  template <typename P, typename T>
+  void add(P *dst, std::vector<T> &&v) {
+    if (v.size() * sizeof(T) > Arena::kSmall) {
+      *dst = (P)a_.upload(std::move(v), s_);
+      return;
+    }
+    add(dst, static_cast<const std::vector<T> &>(v));
+  }
+  void commit() {
+    if (fix_.empty()) return;
+    const size_t total = a_.staging_used - start_;
+    char *d = a_.alloc<char>(total);
+    HIPCHK(hipMemcpyAsync(d, (char *)a_.staging.back() + start_, total, hipMemcpyHostToDevice, s_));
+    for (auto &f : fix_) f(d);
+    fix_.clear();
+  }
+
+ private:
+  Arena &a_;
+  hipStream_t s_;
+  size_t start_ = 0;
+  std::vector<std::function<void(char *)>> fix_;
 };
 
 // largest box grid whose reduced solution the final kernel stages in LDS (with
@@ -1039,12 +1100,20 @@ int64_t invert_systems(coarse_ctx *c, const std::vector<System> &sys, const std:
     double *Dv = tmp.alloc<double>((size_t)ns * BW * BW);
     int *st = tmp.alloc<int>(ns);
     double *diag0 = tmp.alloc<double>((size_t)poff * TILE);
-    SweepSys *dss = tmp.upload(ss, s);
-    AsmSys *das = tmp.upload(as, s);
-    int64_t *doo = tmp.upload(oo, s);
-    int32_t *dts = tmp.upload(tsys, s);
-    int16_t *dti = tmp.upload(tI, s);
-    int16_t *dtj = tmp.upload(tJ, s);
+    SweepSys *dss;
+    AsmSys *das;
+    int64_t *doo;
+    int32_t *dts;
+    int16_t *dti, *dtj;
+    {
+      UploadBatch ub(tmp, s);
+      ub.add(&dss, ss);
+      ub.add(&das, as);
+      ub.add(&doo, oo);
+      ub.add(&dts, tsys);
+      ub.add(&dti, tI);
+      ub.add(&dtj, tJ);
+    }
     HIPCHK(hipMemsetAsync(M, 0, (size_t)toff * TILE * TILE * sizeof(double), s));
     HIPCHK(hipMemsetAsync(st, 0, ns * sizeof(int), s));
     hipLaunchKernelGGL(k_pad_identity, dim3((unsigned)ns), dim3(256), 0, s, das, (int)ns, M);
@@ -1109,20 +1178,29 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles, int wh
   op.n_blocks = P.n_blocks;
   op.n_shared = (int64_t)P.sh_vid.size();
   op.Ae = Ae28;
-  op.lconn = A.upload(P.lconn, s);
-  op.blk_slot_ptr = A.upload(P.blk_slot_ptr, s);
-  op.slot_vid = A.upload(P.slot_vid, s);
-  op.slot_dst = A.upload(P.slot_dst, s);
-  // the incidence lists only serve blocks of differently oriented elements
-  op.blk_inc = A.upload(P.blk_inc, s);
-  op.slot_inc_ptr = P.any_blk_inc ? A.upload(P.slot_inc_ptr, s) : A.alloc<int32_t>(1);
-  op.slot_inc = P.any_blk_inc ? A.upload(P.slot_inc, s) : A.alloc<uint16_t>(1);
-  op.slot_inc8 = P.any_blk_inc ? A.upload(P.slot_inc8, s) : A.alloc<uint16_t>(1);
+  {
+    UploadBatch ub(A, s);
+    ub.add(&op.lconn, P.lconn);
+    ub.add(&op.blk_slot_ptr, P.blk_slot_ptr);
+    ub.add(&op.slot_vid, P.slot_vid);
+    ub.add(&op.slot_dst, P.slot_dst);
+    // the incidence lists only serve blocks of differently oriented elements
+    ub.add(&op.blk_inc, P.blk_inc);
+    if (P.any_blk_inc) {
+      ub.add(&op.slot_inc_ptr, P.slot_inc_ptr);
+      ub.add(&op.slot_inc, P.slot_inc);
+      ub.add(&op.slot_inc8, P.slot_inc8);
+    } else {
+      op.slot_inc_ptr = A.alloc<int32_t>(1);
+      op.slot_inc = A.alloc<uint16_t>(1);
+      op.slot_inc8 = A.alloc<uint16_t>(1);
+    }
+    ub.add(&op.sh_vid, P.sh_vid);
+    ub.add(&op.sh_ptr, P.sh_ptr);
+    ub.add(&op.slot_pw, P.slot_pw);
+    ub.add(&op.vq, P.vq);
+  }
   op.partials = A.alloc<double>(std::max<int64_t>(1, P.n_partials));
-  op.sh_vid = A.upload(P.sh_vid, s);
-  op.sh_ptr = A.upload(P.sh_ptr, s);
-  op.slot_pw = A.upload(P.slot_pw, s);
-  op.vq = (const int2 *)A.upload(P.vq, s);
   op.lds_bytes = (int32_t)((OP_BLOCK * 8 + P.max_slots) * sizeof(double));
   // 256 MB: the MI355X last-level (Infinity) cache
   op.ae_nt = (P.n_elem * 28 * (int64_t)sizeof(double) > (int64_t)(256ull << 20)) ? 1 : 0;
@@ -1134,8 +1212,11 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles, int wh
   c->ne = NE;
   c->nvblk = (int)std::min<int64_t>(1024, nblk(nf, VB));
   std::vector<int32_t> uov(P.user_of_vint.begin(), P.user_of_vint.begin() + nf);
-  c->user_of_vint = A.upload(uov, s);
-  c->vint_of_user = A.upload(P.vint_of_user, s);
+  {
+    UploadBatch ub(A, s);
+    ub.add(&c->user_of_vint, uov);
+    ub.add(&c->vint_of_user, P.vint_of_user);
+  }
   for (double **v : {&c->x, &c->r, &c->p, &c->pb, &c->z, &c->q, &c->bint, &c->t1, &c->t2}) {
     *v = A.alloc<double>(nf);
     HIPCHK(hipMemsetAsync(*v, 0, nf * sizeof(double), s));
@@ -1202,14 +1283,21 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles, int wh
   c->colpart = A.alloc<T>((size_t)std::max<int64_t>(1, ncolpart) * TILE);
   for (int b = 0; b < COARSE_GEMV_BUCKETS; ++b) c->gemv_tiles[b] = gemv_tiles[b] >= 1 ? gemv_tiles[b] : GEMV_SEG;
   c->rowpart = A.alloc<T>((size_t)G.items.size() * TILE);
-  c->cover_ptr = A.upload(P.cover_ptr, s);
-  c->cover_pos = A.upload(P.cover_pos, s);
+  {
+    UploadBatch ub(A, s);
+    ub.add(&c->cover_ptr, P.cover_ptr);
+    ub.add(&c->cover_pos, P.cover_pos);
+  }
 
   // inverses of the local systems (dense assembly of A_p), or A_p itself in
   // ELL form for the inexact local solves ...
   const size_t scratch_tiles = (size_t)(1536ull << 20) / (TILE * TILE * sizeof(double));
-  int32_t *vinc_ptr = tmp.upload(P.vinc_ptr, s);
-  int32_t *vinc = tmp.upload(P.vinc, s);
+  int32_t *vinc_ptr, *vinc;
+  {
+    UploadBatch ub(tmp, s);
+    ub.add(&vinc_ptr, P.vinc_ptr);
+    ub.add(&vinc, P.vinc);
+  }
   int64_t nbad = 0;
   int64_t ell_entries = 0;
   if (inexact) {
@@ -1286,14 +1374,21 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles, int wh
     box.b[d] = P.b[d];
   }
   const int64_t nocc = (int64_t)P.occ_cells.size();
-  int32_t *occ_cells = tmp.upload(P.occ_cells, s);
-  int32_t *occ_ptr = tmp.upload(P.occ_elem_ptr, s);
-  int32_t *occ_elems = tmp.upload(P.occ_elems, s);
+  int32_t *occ_cells, *occ_ptr, *occ_elems, *ar_ptr, *ar_src;
+  {
+    UploadBatch ub(tmp, s);
+    ub.add(&occ_cells, P.occ_cells);
+    ub.add(&occ_ptr, P.occ_elem_ptr);
+    ub.add(&occ_elems, P.occ_elems);
+    ub.add(&ar_ptr, P.ar_ptr);
+    ub.add(&ar_src, P.ar_src);
+  }
   double *cellmat = tmp.alloc<double>(64 * std::max<int64_t>(1, nocc));
-  c->corner_act = A.upload(P.occ_corner_act, s);
-  int32_t *ar_ptr = tmp.upload(P.ar_ptr, s);
-  int32_t *ar_src = tmp.upload(P.ar_src, s);
-  c->act_bv = A.upload(P.act_bv, s);
+  {
+    UploadBatch ub(A, s);
+    ub.add(&c->corner_act, P.occ_corner_act);
+    ub.add(&c->act_bv, P.act_bv);
+  }
   c->bgrid = BoxGrid{P.b[0] + 1, P.b[1] + 1, P.b[2] + 1, 0};
   std::vector<int64_t> red = {P.n_local_sys};
   const int64_t nr = P.n_r;
@@ -1423,10 +1518,13 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles, int wh
     gr[k].nslot = G.row_nitem[k];
     if (G.row_sys[k] < P.n_local_sys) rl = (int32_t)k + 1;
   }
-  c->items = A.upload(gi, s);
-  c->rows = A.upload(gr, s);
-  c->whole = A.upload(G.whole, s);
-  c->sysdev = A.upload(sd, s);
+  {
+    UploadBatch ub(A, s);
+    ub.add(&c->items, gi);
+    ub.add(&c->rows, gr);
+    ub.add(&c->whole, G.whole);
+    ub.add(&c->sysdev, sd);
+  }
   c->items_local = il;
   c->items_total = (int32_t)gi.size();
   c->rows_local = rl;
@@ -1444,10 +1542,13 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles, int wh
   c->h_seg_all = Seg{c->items, c->rows, c->whole, c->sysdev, nullptr, 0, 0};
   c->h_seg_local = c->h_seg_all;
   c->h_seg_coarse = Seg{c->items + il, c->rows + rl, c->whole + c->whole_local, c->sysdev, nullptr, 0, 0};
-  c->seg_all = A.upload(std::vector<Seg>{c->h_seg_all}, s);
-  c->seg_local = A.upload(std::vector<Seg>{c->h_seg_local}, s);
+  {
+    UploadBatch ub(A, s);
+    ub.add(&c->seg_all, std::vector<Seg>{c->h_seg_all});
+    ub.add(&c->seg_local, std::vector<Seg>{c->h_seg_local});
+    ub.add(&c->seg_coarse, std::vector<Seg>{c->h_seg_coarse});
+  }
   c->reduced_aside = P.n_r > 0 && P.sys[P.n_local_sys].nb > WHOLE_NB_MAX;
-  c->seg_coarse = A.upload(std::vector<Seg>{c->h_seg_coarse}, s);
   if (c->reduced_refine && P.n_r > 0) {
     const System &R = P.sys[P.n_local_sys];
     c->r_res = A.alloc<T>(R.nb * TILE);
@@ -1467,18 +1568,21 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles, int wh
 
   // reduced-space interpolation entries
   c->nent = (int64_t)P.jv_w.size();
-  c->jv_ptr = A.upload(P.jv_ptr, s);
-  c->jv_base = A.upload(P.jv_base, s);
-  c->jv_w = A.upload(cast_vec<T>(P.jv_w), s);
-  c->jv_xi = A.upload(cast_vec<T>(P.jv_xi), s);
-  c->jc_vid = A.upload(P.jc_vid, s);
-  c->jc_w = A.upload(cast_vec<T>(P.jc_w), s);
-  c->jc_xi = A.upload(cast_vec<T>(P.jc_xi), s);
   c->ntask = (int64_t)P.jt_task_occ.size();
-  c->jt_start = A.upload(P.jt_task_start, s);
+  {
+    UploadBatch ub(A, s);
+    ub.add(&c->jv_ptr, P.jv_ptr);
+    ub.add(&c->jv_base, P.jv_base);
+    ub.add(&c->jv_w, cast_vec<T>(P.jv_w));
+    ub.add(&c->jv_xi, cast_vec<T>(P.jv_xi));
+    ub.add(&c->jc_vid, P.jc_vid);
+    ub.add(&c->jc_w, cast_vec<T>(P.jc_w));
+    ub.add(&c->jc_xi, cast_vec<T>(P.jc_xi));
+    ub.add(&c->jt_start, P.jt_task_start);
+    ub.add(&c->jr_ptr, P.jr_ptr);
+    ub.add(&c->jr_src, P.jr_src);
+  }
   c->jt_part = A.alloc<T>(8 * std::max<int64_t>(1, c->ntask));
-  c->jr_ptr = A.upload(P.jr_ptr, s);
-  c->jr_src = A.upload(P.jr_src, s);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
   A.drop_hold();
