@@ -18,6 +18,7 @@
 #include <cstring>
 #include <memory>
 #include <numeric>
+#include <stdexcept>
 #include <thread>
 
 namespace coarse {
@@ -233,7 +234,20 @@ int build_plan(const PlanInput &in, Plan &P) {
   // then numbered per range from the ranges' prefix sums.
   P.vint_of_user.assign(NV, -1);
   int64_t nf = 0, nd = 0;
-  {
+  if (NT == 1) {
+    // one thread: the same numbering in two plain passes
+    for (int64_t ei = 0; ei < NE; ++ei) {
+      const int32_t *ev = in.e2v + 8 * (int64_t)P.elem_user[ei];
+      for (int v = 0; v < 8; ++v)
+        if (!in.dirichlet[ev[v]] && P.vint_of_user[ev[v]] < 0) P.vint_of_user[ev[v]] = (int32_t)nf++;
+    }
+    nd = nf;
+    for (int64_t ei = 0; ei < NE; ++ei) {
+      const int32_t *ev = in.e2v + 8 * (int64_t)P.elem_user[ei];
+      for (int v = 0; v < 8; ++v)
+        if (P.vint_of_user[ev[v]] < 0) P.vint_of_user[ev[v]] = (int32_t)nd++;
+    }
+  } else {
     const int64_t NONE = INT64_MAX;
     std::unique_ptr<std::atomic<int64_t>[]> first(new std::atomic<int64_t>[NV]);
     parallel_for(NV, NT, [&](int64_t u0, int64_t u1, int) {
@@ -344,71 +358,108 @@ int build_plan(const PlanInput &in, Plan &P) {
       uint8_t inc = 0;
     };
     std::vector<BlockOut> bo(nb);
-    parallel_for(nb, NT, [&](int64_t b0, int64_t b1, int) {
-      std::vector<std::pair<int32_t, uint16_t>> pr;
+    const int nt_blk = (nb >= 2 * NT) ? NT : 1;
+    // per range of blocks: the slot of each vertex of the current block (-1
+    // elsewhere, reset after the block), so a block's vertices are found without
+    // sorting its incidences; only the distinct vertices are sorted
+    std::vector<std::vector<int32_t>> slot_of_t(nt_blk);
+    parallel_for(nb, nt_blk, [&](int64_t b0, int64_t b1, int t) {
+      std::vector<int32_t> &slot_of = slot_of_t[t];
+      slot_of.assign(nf, -1);
+      std::vector<int32_t> uniq, fill;
+      std::vector<uint8_t> seen;
       for (int64_t blk = b0; blk < b1; ++blk) {
         const int64_t e0 = blk * OP_BLOCK, e1 = std::min<int64_t>(NE, e0 + OP_BLOCK);
-        pr.clear();
+        uniq.clear();
+        int64_t nent = 0;
         for (int64_t e = e0; e < e1; ++e)
           for (int v = 0; v < 8; ++v) {
             const int32_t u = E2V(e, v);
-            if (u < nf) pr.push_back({u, (uint16_t)((e - e0) * 8 + v)});
+            if (u >= nf) continue;
+            ++nent;
+            if (slot_of[u] < 0) {
+              slot_of[u] = 0;
+              uniq.push_back(u);
+            }
           }
-        // by vertex; a vertex's incidences keep their (element, local vertex) order
-        std::stable_sort(pr.begin(), pr.end(), [](const std::pair<int32_t, uint16_t> &a,
-                                                  const std::pair<int32_t, uint16_t> &b) { return a.first < b.first; });
+        std::sort(uniq.begin(), uniq.end());
+        const int32_t ns = (int32_t)uniq.size();
         BlockOut &o = bo[blk];
-        o.list_ptr.push_back(0);
-        for (size_t a = 0; a < pr.size();) {
-          size_t c = a;
-          uint8_t seen = 0;
-          const int32_t sl = (int32_t)o.verts.size();
-          while (c < pr.size() && pr[c].first == pr[a].first) {
-            const uint16_t x = pr[c].second;
-            const int v = x & 7;
-            P.lconn[(e0 + (x >> 3)) * 8 + v] = (uint16_t)sl;
-            if ((seen >> v) & 1) o.inc = 1;
-            seen |= (uint8_t)(1u << v);
-            o.lists.push_back(x);
-            ++c;
+        o.verts = uniq;
+        o.list_ptr.assign(ns + 1, 0);
+        for (int32_t sl = 0; sl < ns; ++sl) slot_of[uniq[sl]] = sl;
+        for (int64_t e = e0; e < e1; ++e)
+          for (int v = 0; v < 8; ++v) {
+            const int32_t u = E2V(e, v);
+            if (u < nf) o.list_ptr[slot_of[u] + 1]++;
           }
-          o.verts.push_back(pr[a].first);
-          o.list_ptr.push_back((int32_t)o.lists.size());
-          o.owned.push_back((int64_t)(c - a) == (int64_t)P.mult[pr[a].first] ? 1 : 0);
-          a = c;
+        for (int32_t sl = 0; sl < ns; ++sl) o.list_ptr[sl + 1] += o.list_ptr[sl];
+        // each vertex's incidences in (element, local vertex) order
+        fill.assign(o.list_ptr.begin(), o.list_ptr.end() - 1);
+        seen.assign(ns, 0);
+        o.lists.resize(nent);
+        for (int64_t e = e0; e < e1; ++e)
+          for (int v = 0; v < 8; ++v) {
+            const int32_t u = E2V(e, v);
+            if (u >= nf) continue;
+            const int32_t sl = slot_of[u];
+            o.lists[fill[sl]++] = (uint16_t)((e - e0) * 8 + v);
+            P.lconn[e * 8 + v] = (uint16_t)sl;
+            if ((seen[sl] >> v) & 1) o.inc = 1;
+            seen[sl] |= (uint8_t)(1u << v);
+          }
+        o.owned.resize(ns);
+        for (int32_t sl = 0; sl < ns; ++sl) {
+          o.owned[sl] = (int64_t)(o.list_ptr[sl + 1] - o.list_ptr[sl]) == (int64_t)P.mult[uniq[sl]] ? 1 : 0;
+          slot_of[uniq[sl]] = -1;
         }
       }
     });
-    std::vector<int64_t> shared_blocks;  // (slot global index) of shared slots
+    slot_of_t.clear();
+    // the blocks' slots and lists concatenated in block order: offsets first,
+    // then each block copies its part (in parallel)
+    std::vector<int64_t> soff(nb + 1, 0), loff(nb + 1, 0);
     for (int64_t blk = 0; blk < nb; ++blk) {
-      BlockOut &o = bo[blk];
-      const int32_t s0 = P.blk_slot_ptr.back();
-      P.blk_inc[blk] = o.inc;
-      if (o.inc) P.any_blk_inc = true;
-      for (size_t sl = 0; sl < o.verts.size(); ++sl) {
-        const int32_t u = o.verts[sl];
-        P.slot_vid.push_back(u);
-        if (P.slot_inc_ptr.empty()) P.slot_inc_ptr.push_back(0);
-        const int32_t l0 = o.list_ptr[sl], l1 = o.list_ptr[sl + 1];
-        for (int32_t k = l0; k < l1; ++k) P.slot_inc.push_back(o.lists[k]);
-        P.slot_inc_ptr.push_back((int32_t)P.slot_inc.size());
-        // the same list as one 16-byte record (0xFFFF ends it; 0xFFFE first: the
-        // list is longer than 8 and only the CSR form holds it)
-        const int len = l1 - l0;
-        for (int k = 0; k < 8; ++k)
-          P.slot_inc8.push_back(len > 8 ? (k == 0 ? 0xFFFE : 0xFFFF) : (k < len ? o.lists[l0 + k] : 0xFFFF));
-        if (o.owned[sl]) {
-          P.slot_dst.push_back(u);
-        } else {
-          P.slot_dst.push_back(-1);  // patched below
-          shared_blocks.push_back(s0 + (int64_t)sl);
-        }
-      }
-      P.blk_slot_ptr.push_back(s0 + (int32_t)o.verts.size());
-      P.max_slots = std::max<int64_t>(P.max_slots, (int64_t)o.verts.size());
-      o = BlockOut();   // release the block's lists once they are copied
+      soff[blk + 1] = soff[blk] + (int64_t)bo[blk].verts.size();
+      loff[blk + 1] = loff[blk] + (int64_t)bo[blk].lists.size();
+      P.blk_inc[blk] = bo[blk].inc;
+      if (bo[blk].inc) P.any_blk_inc = true;
+      P.max_slots = std::max<int64_t>(P.max_slots, (int64_t)bo[blk].verts.size());
     }
-    if (P.slot_inc_ptr.empty()) P.slot_inc_ptr.push_back(0);
+    const int64_t nslot = soff[nb];
+    P.blk_slot_ptr.resize(nb + 1);
+    for (int64_t blk = 0; blk <= nb; ++blk) P.blk_slot_ptr[blk] = (int32_t)soff[blk];
+    P.slot_vid.resize(nslot);
+    P.slot_dst.resize(nslot);
+    P.slot_inc.resize(loff[nb]);
+    P.slot_inc_ptr.resize(nslot + 1);
+    P.slot_inc_ptr[0] = 0;
+    P.slot_inc8.resize(8 * nslot);
+    parallel_for(nb, nt_blk, [&](int64_t b0, int64_t b1, int) {
+      for (int64_t blk = b0; blk < b1; ++blk) {
+        BlockOut &o = bo[blk];
+        const int64_t s0 = soff[blk], l0b = loff[blk];
+        std::copy(o.lists.begin(), o.lists.end(), P.slot_inc.begin() + l0b);
+        for (size_t sl = 0; sl < o.verts.size(); ++sl) {
+          const int64_t gs = s0 + (int64_t)sl;
+          const int32_t u = o.verts[sl];
+          P.slot_vid[gs] = u;
+          const int32_t l0 = o.list_ptr[sl], l1 = o.list_ptr[sl + 1];
+          P.slot_inc_ptr[gs + 1] = (int32_t)(l0b + l1);
+          // the same list as one 16-byte record (0xFFFF ends it; 0xFFFE first: the
+          // list is longer than 8 and only the CSR form holds it)
+          const int len = l1 - l0;
+          for (int k = 0; k < 8; ++k)
+            P.slot_inc8[8 * gs + k] =
+                len > 8 ? (k == 0 ? 0xFFFE : 0xFFFF) : (k < len ? o.lists[l0 + k] : (uint16_t)0xFFFF);
+          P.slot_dst[gs] = o.owned[sl] ? u : -1;   // shared slots patched below
+        }
+        o = BlockOut();   // release the block's lists once they are copied
+      }
+    });
+    std::vector<int64_t> shared_blocks;  // (slot global index) of shared slots
+    for (int64_t gs = 0; gs < nslot; ++gs)
+      if (P.slot_dst[gs] < 0) shared_blocks.push_back(gs);
     // partial ids grouped by vertex (vertices in order of first appearance, each
     // vertex's partials contiguous and in block order), so the sum over a shared
     // vertex reads one contiguous range
@@ -460,10 +511,49 @@ int build_plan(const PlanInput &in, Plan &P) {
     for (int64_t e = 0; e < NE; ++e) pstart[part_int[e] + 1]++;
     for (int p = 0; p < in.n_part; ++p) pstart[p + 1] += pstart[p];
     P.R.assign(in.n_part, {});
+    // overlap 1: the elements that join subdomain p are those of other parts that
+    // share a vertex with it; one pass over the vertices whose elements span
+    // several parts lists them as (part, element) pairs, bucketed by part
+    // (a vertex touching more than 64 subdomains sends every subdomain through the
+    // general layer loop below instead)
+    std::vector<int64_t> lay_ptr;
+    std::vector<int32_t> lay;
+    bool by_vertex = in.overlap == 1;
+    if (by_vertex) {
+      lay_ptr.assign(in.n_part + 1, 0);
+      auto visit = [&](auto &&emit) -> bool {
+        int32_t parts[64];
+        for (int64_t u = 0; u < NV; ++u) {
+          int np = 0;
+          for (int32_t k = inc_ptr[u]; k < inc_ptr[u + 1]; ++k) {
+            const int32_t q = part_int[inc[k] >> 3];
+            bool have = false;
+            for (int j = 0; j < np; ++j) have |= (parts[j] == q);
+            if (have) continue;
+            if (np == 64) return false;
+            parts[np++] = q;
+          }
+          if (np < 2) continue;
+          for (int32_t k = inc_ptr[u]; k < inc_ptr[u + 1]; ++k) {
+            const int32_t f = inc[k] >> 3, q = part_int[f];
+            for (int j = 0; j < np; ++j)
+              if (parts[j] != q) emit(parts[j], f);
+          }
+        }
+        return true;
+      };
+      by_vertex = visit([&](int32_t q, int32_t) { lay_ptr[q + 1]++; });
+      if (by_vertex) {
+        for (int32_t q = 0; q < in.n_part; ++q) lay_ptr[q + 1] += lay_ptr[q];
+        lay.resize(lay_ptr[in.n_part]);
+        std::vector<int64_t> fill(lay_ptr.begin(), lay_ptr.end() - 1);
+        visit([&](int32_t q, int32_t f) { lay[fill[q]++] = f; });
+      }
+    }
     // subdomains in parallel, each thread with its own marks
     parallel_for(in.n_part, NT, [&](int64_t p0, int64_t p1, int) {
-    std::vector<int32_t> emark(NE, -1), vmark(NV, -1);
-    std::vector<int32_t> cur, nxt;
+    std::vector<int32_t> emark(NE, -1), vmark(NV, -1), vcnt(NV, 0);
+    std::vector<int32_t> cur, nxt, touched;
     for (int32_t p = (int32_t)p0; p < (int32_t)p1; ++p) {
       cur.clear();
       for (int64_t e = pstart[p]; e < pstart[p + 1]; ++e) {
@@ -471,7 +561,14 @@ int build_plan(const PlanInput &in, Plan &P) {
         emark[e] = p;
       }
       std::vector<int32_t> all = cur;
-      for (int layer = 0; layer < in.overlap; ++layer) {
+      if (by_vertex) {
+        for (int64_t k = lay_ptr[p]; k < lay_ptr[p + 1]; ++k)
+          if (emark[lay[k]] != p) {
+            emark[lay[k]] = p;
+            all.push_back(lay[k]);
+          }
+      }
+      for (int layer = 0; !by_vertex && layer < in.overlap; ++layer) {
         nxt.clear();
         for (int32_t e : all)
           for (int v = 0; v < 8; ++v) {
@@ -486,17 +583,23 @@ int build_plan(const PlanInput &in, Plan &P) {
           }
         all.insert(all.end(), nxt.begin(), nxt.end());
       }
+      // a free vertex is in R_p when all its incidences lie in the extended
+      // subdomain: the incidences counted there equal its multiplicity
       std::vector<int32_t> &R = P.R[p];
+      touched.clear();
       for (int32_t e : all)
         for (int v = 0; v < 8; ++v) {
           int32_t u = E2V(e, v);
-          if (u >= nf || vmark[u] == p) continue;
-          vmark[u] = p;
-          bool inside = true;
-          for (int32_t k = inc_ptr[u]; k < inc_ptr[u + 1] && inside; ++k)
-            if (emark[inc[k] >> 3] != p) inside = false;
-          if (inside) R.push_back(u);
+          if (u >= nf) continue;
+          if (vmark[u] != p) {
+            vmark[u] = p;
+            vcnt[u] = 0;
+            touched.push_back(u);
+          }
+          vcnt[u]++;
         }
+      for (int32_t u : touched)
+        if (vcnt[u] == P.mult[u]) R.push_back(u);
       std::sort(R.begin(), R.end());
     }
     });
@@ -541,10 +644,15 @@ int build_plan(const PlanInput &in, Plan &P) {
   P.elem_cell.resize(NE);
   parallel_for(NE, NT, [&](int64_t e0, int64_t e1, int) {
     for (int64_t e = e0; e < e1; ++e) {
-      int32_t ev[8];
-      for (int v = 0; v < 8; ++v) ev[v] = P.user_of_vint[E2V(e, v)];
+      // the centroid from the internal-order coordinates (better locality than
+      // the user order; the same sum, corner by corner)
       double c[3];
-      centroid(in.xyz, ev, c);
+      for (int d = 0; d < 3; ++d) {
+        const double *xd = P.xyz.data() + d * NV;
+        double sum = xd[E2V(e, 0)];
+        for (int v = 1; v < 8; ++v) sum = sum + xd[E2V(e, v)];
+        c[d] = sum / 8.0;
+      }
       int32_t c3[3];
       cell_of(c, c3);
       P.elem_cell[e] = (int32_t)cell_id(c3);
@@ -566,8 +674,7 @@ int build_plan(const PlanInput &in, Plan &P) {
       EntOut &o = eo[t];
       std::vector<int32_t> cells;
       for (int64_t i = i0; i < i1; ++i) {
-        const int32_t u = P.user_of_vint[i];
-        const double x[3] = {in.xyz[3 * (int64_t)u], in.xyz[3 * (int64_t)u + 1], in.xyz[3 * (int64_t)u + 2]};
+        const double x[3] = {P.xyz[i], P.xyz[NV + i], P.xyz[2 * NV + i]};
         const size_t before = o.cell.size();
         if (in.interp == 0) {
           cells.clear();
