@@ -424,19 +424,27 @@ def kernel_bytes(info, n_elem, precision):
     A+p  : A^e (28 off-diagonal FP64 = 224 B; its rows sum to zero) + 8 u16 slots
            per element; z, p_old read,
            p and q written per free vertex
-    R_p+J^T stage 1: per packed entry index + r value + r_p write; per J entry
-           vertex id, weight, 3 local coordinates and the r value
+    R_p+J^T: the convergence test, plus the first stage of J^T (per J entry vertex
+           id, weight, 3 local coordinates and the r value) when the reduced system
+           shares the local systems' stream, or the R_p gather (per packed entry
+           index + r value + r_p write) for the inexact local solves; with stored
+           inverses the dense solves gather r_p themselves, and with the reduced
+           branch on the second stream the J^T stage runs there (no entry then)
     sum+J: per packed entry position + z_p; per free vertex cover pointer, r read,
            z written, J pointer; per J entry base corner, weight, 3 coordinates
     x,r update: x, r read and written, p, q read per free vertex."""
     es = 8 if precision == "fp64" else 4
     nf, snp, nj = info["n_free"], info["sum_np"], info["n_jent"]
-    return {
+    out = {
         "A+p": n_elem * (224 + 16) + nf * 32,
-        "R_p+J^T": snp * (4 + 8 + es) + nj * (4 + es + 3 * es + 8),
         "sum+J": snp * (4 + 8) + nf * (4 + 8 + 8 + 4) + nj * (4 + es + 3 * es),
         "x,r update": nf * 48,
     }
+    if info.get("local_iters", 0) > 0:
+        out["R_p+J^T"] = snp * (4 + 8 + es)
+    elif not info.get("reduced_stream", 0):
+        out["R_p+J^T"] = nj * (4 + es + 3 * es + 8)
+    return out
 
 
 def run_ablations(torch, coarse, mesh, b, tol, max_it=400):

@@ -441,15 +441,17 @@ int coarse_set_stream(coarse_ctx *ctx, void *stream);
  * 0xFF = all): it clears the accumulators and starts timing. enable = 0 waits for
  * the stream, stops, and writes the accumulated milliseconds and launch counts of
  * the first nphase phases into ms[] and counts[] (either may be NULL).
- * Phases: 0 operator A (with the search-direction update), 1 restriction R_p
- * gather (with the first stage of J^T in the additive mode), 2 reduced
- * restriction J^T (corner sums), 3 batched dense solves A_p^{-1} and A_r^{-1} (the
- * tiled GEMV kernel alone), 4 partial-sum combine, 5 overlap sum + J
- * prolongation (with (r, z)), 6 PCG vector update, 7 the reduced branch of the
- * additive two-level preconditioner (J^T corner sums, the dense solve of A_r and
- * its partial sums) when it runs on the context's second stream beside the local
- * dense solves (coarse_info_t.reduced_stream; phases 3 and 4 then cover the local
- * systems alone, and phase 2 is not used). */
+ * Phases: 0 operator A (with the search-direction update), 1 the convergence
+ * test of PCG, with the first stage of J^T when the reduced system shares the
+ * local systems' stream (additive mode) and the restriction gather R_p r for the
+ * inexact local solves (with stored inverses the dense solves gather r_p
+ * themselves), 2 reduced restriction J^T (corner sums), 3 batched dense solves
+ * A_p^{-1} and A_r^{-1} (the tiled GEMV kernel alone), 4 partial-sum combine,
+ * 5 overlap sum + J prolongation (with (r, z)), 6 PCG vector update, 7 the reduced
+ * branch of the additive two-level preconditioner (both stages of J^T, the dense
+ * solve of A_r and its partial sums) when it runs on the context's second stream
+ * beside the local solves (coarse_info_t.reduced_stream; phases 3 and 4 then
+ * cover the local systems alone, and phase 2 is not used). */
 #define COARSE_NPHASE 8
 int coarse_profile(coarse_ctx *ctx, int enable, double *ms, int64_t *counts, int nphase);
 

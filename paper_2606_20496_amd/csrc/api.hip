@@ -329,40 +329,43 @@ inline unsigned nblk(int64_t n, int b) { return (unsigned)std::max<int64_t>(1, (
 // The dense solves of one application: the whole-system workgroups (nwhole
 // systems, wsegs, nw wavefronts each) and the work items (segs), in one launch
 // when there are whole systems; either may be empty.
+// gin != nullptr: the local systems gather their right-hand sides r_p = R_p gin
+// themselves (through SysDev::gidx) instead of reading the packed vectors
 template <int NW>
 void launch_whole(hipStream_t s, int precision, const Seg *segs, int nseg, int nitems, const Seg *wsegs, int nwhole,
-                  int whole_lds, const int *done) {
+                  int whole_lds, const int *done, const double *gin, const PcgCheck &ck) {
   const unsigned g = (unsigned)nwhole + (nitems > 0 ? nblk(nitems, NW) : 0u);
   if (precision == COARSE_FP64)
     hipLaunchKernelGGL(k_gemv_whole_f64<NW>, dim3(g), dim3(NW * WAVE), whole_lds, s, segs, nseg, nitems, wsegs,
-                       nwhole, done);
+                       nwhole, done, gin, ck);
   else if (precision == COARSE_MIXED_F16)
     hipLaunchKernelGGL(k_gemv_whole_f16<NW>, dim3(g), dim3(NW * WAVE), whole_lds, s, segs, nseg, nitems, wsegs,
-                       nwhole, done);
+                       nwhole, done, gin, ck);
   else
     hipLaunchKernelGGL(k_gemv_whole_f32<NW>, dim3(g), dim3(NW * WAVE), whole_lds, s, segs, nseg, nitems, wsegs,
-                       nwhole, done);
+                       nwhole, done, gin, ck);
 }
 
+// ck.sc != nullptr: the launch carries the convergence test of PCG
 void launch_gemv(hipStream_t s, int precision, int nw, const Seg *segs, int nseg, int nitems, const Seg *wsegs,
-                 int nwhole, int whole_lds, const int *done) {
+                 int nwhole, int whole_lds, const int *done, const double *gin, const PcgCheck &ck = PcgCheck{}) {
   if (nwhole > 0) {
     switch (nw) {
-      case 2: launch_whole<2>(s, precision, segs, nseg, nitems, wsegs, nwhole, whole_lds, done); break;
-      case 8: launch_whole<8>(s, precision, segs, nseg, nitems, wsegs, nwhole, whole_lds, done); break;
-      case 16: launch_whole<16>(s, precision, segs, nseg, nitems, wsegs, nwhole, whole_lds, done); break;
-      default: launch_whole<4>(s, precision, segs, nseg, nitems, wsegs, nwhole, whole_lds, done); break;
+      case 2: launch_whole<2>(s, precision, segs, nseg, nitems, wsegs, nwhole, whole_lds, done, gin, ck); break;
+      case 8: launch_whole<8>(s, precision, segs, nseg, nitems, wsegs, nwhole, whole_lds, done, gin, ck); break;
+      case 16: launch_whole<16>(s, precision, segs, nseg, nitems, wsegs, nwhole, whole_lds, done, gin, ck); break;
+      default: launch_whole<4>(s, precision, segs, nseg, nitems, wsegs, nwhole, whole_lds, done, gin, ck); break;
     }
   } else if (nitems > 0) {
     // one wavefront per work item (the kernel also loops over a smaller grid, but
     // one item per wavefront measured fastest on MI355X at every size tried)
     const unsigned g = nblk(nitems, 4);
     if (precision == COARSE_FP64)
-      hipLaunchKernelGGL(k_gemv_f64, dim3(g), dim3(256), 0, s, segs, nseg, nitems, done);
+      hipLaunchKernelGGL(k_gemv_f64, dim3(g), dim3(256), 0, s, segs, nseg, nitems, done, gin, ck);
     else if (precision == COARSE_MIXED_F16)
-      hipLaunchKernelGGL(k_gemv_f16, dim3(g), dim3(256), 0, s, segs, nseg, nitems, done);
+      hipLaunchKernelGGL(k_gemv_f16, dim3(g), dim3(256), 0, s, segs, nseg, nitems, done, gin, ck);
     else
-      hipLaunchKernelGGL(k_gemv_f32, dim3(g), dim3(256), 0, s, segs, nseg, nitems, done);
+      hipLaunchKernelGGL(k_gemv_f32, dim3(g), dim3(256), 0, s, segs, nseg, nitems, done, gin, ck);
   }
 }
 
@@ -561,7 +564,7 @@ struct coarse_ctx {
   void restrict_coarse(const double *in, const int *done) {
     pbeg(2);
     hipLaunchKernelGGL(k_jt_tasks<T>, dim3(nblk(ntask, 4)), dim3(256), 0, stream, (int)ntask, done, jt_start, jc_vid,
-                       (const T *)jc_w, (const T *)jc_xi, nent, in, (T *)jt_part);
+                       (const T *)jc_w, (const T *)jc_xi, nent, in, (T *)jt_part, PcgCheck{});
     corners<T>(done);
     pend(2);
   }
@@ -584,12 +587,13 @@ struct coarse_ctx {
   }
 
   // the dense solves of a segment and the partial sums of its work items, on
-  // stream s; ph_gemv / ph_comb < 0: not timed
+  // stream s; ph_gemv / ph_comb < 0: not timed; gin != nullptr: the local
+  // systems gather r_p = R_p gin themselves
   void gemv_combine(const Seg *segs, int nitems, int nrows, int nwhole, const int *done, hipStream_t s, int ph_gemv,
-                    int ph_comb) {
+                    int ph_comb, const double *gin = nullptr, const PcgCheck &ck = PcgCheck{}) {
     if (nitems <= 0 && nwhole <= 0) return;
     if (ph_gemv >= 0) pbeg(ph_gemv, s);
-    launch_gemv(s, precision, whole_waves, segs, 1, nitems, segs, nwhole, whole_lds, done);
+    launch_gemv(s, precision, whole_waves, segs, 1, nitems, segs, nwhole, whole_lds, done, gin, ck);
     if (ph_gemv >= 0) pend(ph_gemv, s);
     if (nrows <= 0) return;
     if (ph_comb >= 0) pbeg(ph_comb, s);
@@ -601,8 +605,9 @@ struct coarse_ctx {
                          done);
     if (ph_comb >= 0) pend(ph_comb, s);
   }
-  void gemv_combine(const Seg *segs, int nitems, int nrows, int nwhole, const int *done) {
-    gemv_combine(segs, nitems, nrows, nwhole, done, stream, 3, 4);
+  void gemv_combine(const Seg *segs, int nitems, int nrows, int nwhole, const int *done,
+                    const double *gin = nullptr, const PcgCheck &ck = PcgCheck{}) {
+    gemv_combine(segs, nitems, nrows, nwhole, done, stream, 3, 4, gin, ck);
   }
 
   // one step of iterative refinement of the reduced solve just made on stream s:
@@ -621,11 +626,12 @@ struct coarse_ctx {
   }
 
   // the local solves of one application on the context's stream: the stored
-  // inverses, or local_iters steps of Jacobi-PCG per subdomain (phase 3 either way)
+  // inverses (which gather r_p = R_p in themselves), or local_iters steps of
+  // Jacobi-PCG per subdomain on the gathered packed vectors (phase 3 either way)
   template <typename T>
-  void local_part(const int *done) {
+  void local_part(const double *in, const int *done, const PcgCheck &ck = PcgCheck{}) {
     if (local_iters <= 0) {
-      gemv_combine(seg_local, items_local, rows_local, whole_local, done);
+      gemv_combine(seg_local, items_local, rows_local, whole_local, done, in, ck);
       return;
     }
     if (n_local_sys <= 0) return;
@@ -655,50 +661,71 @@ struct coarse_ctx {
     pend(5);
   }
 
-  // chk != nullptr: the convergence test of PCG runs first, from these partials
+  // chk != nullptr: the convergence test of PCG runs first, from these partials.
+  // With stored inverses the dense solves gather r_p = R_p in themselves (the
+  // packed vectors are then not written); the inexact local solves read them
+  // from the gather of the first launch.
   template <typename T>
   void precond_parts(const double *in, const double *add, bool local, bool coarse, double *out, const double *rdot,
                      double *p1, double *p2, const int *done, bool scal, int start, const double *chk) {
+    const bool gather = local && local_iters > 0;   // packed r_p needed by a separate launch
     if (local && coarse) {
-      // convergence test, R_p gather and the first stage of J^T in one launch
-      pbeg(1);
-      const int ng = pre_gather_blocks(), nt = pre_task_blocks();
-      hipLaunchKernelGGL(k_pre<T>, dim3(ng + nt), dim3(256), 0, stream, ng, coarse_vec_off, done, sub_idx, in, (T *)rp,
-                         (int)ntask, jt_start, jc_vid, (const T *)jc_w, (const T *)jc_xi, nent, (T *)jt_part,
-                         chk ? sc : nullptr, chk, nvblk, start);
-      pend(1);
       if (!reduced_aside && local_iters <= 0) {
         // a reduced system of at most WHOLE_NB_MAX tile rows joins the local
-        // systems in one dense-solve launch
+        // systems in one dense-solve launch: the convergence test and the first
+        // stage of J^T in one launch, the corner sums, then the dense solves
+        pbeg(1);
+        hipLaunchKernelGGL(k_pre<T>, dim3(std::max(pre_task_blocks(), 1)), dim3(256), 0, stream, 0, coarse_vec_off, done, sub_idx,
+                           in, (T *)rp, (int)ntask, jt_start, jc_vid, (const T *)jc_w, (const T *)jc_xi, nent,
+                           (T *)jt_part, chk ? sc : nullptr, chk, nvblk, start);
+        pend(1);
         pbeg(2);
         corners<T>(done);
         pend(2);
-        gemv_combine(seg_all, items_total, rows_total, whole_total, done);
+        gemv_combine(seg_all, items_total, rows_total, whole_total, done, in);
         refine_reduced<T>(done, stream);
         final_step<T>(add, local, coarse, out, rdot, p1, p2, done, scal, start);
         return;
       }
-      // the reduced-space branch (J^T corner sums, the dense solve of A_r and its
-      // partial sums) on the second stream, beside the local solves; the two
-      // meet before the overlap sum. Across hardware queues each of the two
-      // waits costs some microseconds, which a large reduced system (its long
-      // tile rows end the fused launch late, and its partial sums need a combine
-      // pass) repays and a small one does not. Inexact local solves have a
-      // launch of their own, so the reduced branch always runs beside them.
+      // The convergence test, the whole reduced-space branch on the second
+      // stream (both stages of J^T, the dense solve of A_r and its partial sums)
+      // beside the local solves; the two meet before the overlap sum. With
+      // stored inverses the local dense-solve launch carries the test (its
+      // workgroup 0 records it) and so does the J^T launch of the second stream
+      // (which records nothing); the inexact local solves need the gathered
+      // packed vectors, whose launch carries it instead. Across hardware queues
+      // each of the two waits costs some microseconds, which a large reduced
+      // system (its long tile rows end the fused launch late, and its partial
+      // sums need a combine pass) repays and a small one does not. Inexact local
+      // solves have a launch of their own, so the reduced branch always runs
+      // beside them.
+      const PcgCheck ck_lead{chk ? sc : nullptr, chk, (int32_t)nvblk, start, 1, 0};
+      const PcgCheck ck_aux{chk ? sc : nullptr, chk, (int32_t)nvblk, start, 0, 0};
+      if (gather) {
+        pbeg(1);
+        hipLaunchKernelGGL(k_pre<T>, dim3(pre_gather_blocks()), dim3(256), 0, stream, pre_gather_blocks(),
+                           coarse_vec_off, done, sub_idx, in, (T *)rp, 0, jt_start, jc_vid, (const T *)jc_w,
+                           (const T *)jc_xi, nent, (T *)jt_part, chk ? sc : nullptr, chk, nvblk, start);
+        pend(1);
+      }
       HIPCHK(hipEventRecord(ev_fork, stream));
       HIPCHK(hipStreamWaitEvent(aux, ev_fork, 0));
       pbeg(7, aux);
+      if (ntask > 0)
+        hipLaunchKernelGGL(k_jt_tasks<T>, dim3(nblk(ntask, 4)), dim3(256), 0, aux, (int)ntask, done, jt_start,
+                           jc_vid, (const T *)jc_w, (const T *)jc_xi, nent, in, (T *)jt_part,
+                           gather ? PcgCheck{} : ck_aux);
       corners<T>(done, aux);
       gemv_combine(seg_coarse, items_total - items_local, rows_total - rows_local, whole_total - whole_local, done, aux,
                    -1, -1);
       refine_reduced<T>(done, aux);
       pend(7, aux);
       HIPCHK(hipEventRecord(ev_join, aux));
-      local_part<T>(done);
+      local_part<T>(in, done, gather ? PcgCheck{} : ck_lead);
       HIPCHK(hipStreamWaitEvent(stream, ev_join, 0));
     } else {
       if (chk) hipLaunchKernelGGL(k_check, dim3(1), dim3(256), 0, stream, sc, chk, nvblk, start);
-      if (local) {
+      if (gather) {
         pbeg(1);
         hipLaunchKernelGGL(k_gather<T>, dim3(nblk(coarse_vec_off, VB)), dim3(VB), 0, stream, coarse_vec_off, done,
                            sub_idx, in, (T *)rp);
@@ -707,7 +734,7 @@ struct coarse_ctx {
       if (coarse) restrict_coarse<T>(in, done);
     }
     if (local && !coarse)
-      local_part<T>(done);
+      local_part<T>(in, done);
     else if (coarse && !local) {
       gemv_combine(seg_coarse, items_total - items_local, rows_total - rows_local, whole_total - whole_local, done);
       refine_reduced<T>(done, stream);
@@ -1441,7 +1468,8 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles, int wh
             c->apply_op(pv, pq, nullptr, c->zero_flag);
             hipLaunchKernelGGL(k_jt_tasks<double>, dim3(nblk(ntask, 4)), dim3(256), 0, s, (int)ntask,
                                (const int *)c->zero_flag, (const int32_t *)pjt, (const int32_t *)pjc_vid,
-                               (const double *)pjc_w, (const double *)pjc_xi, ne, (const double *)pq, ptp);
+                               (const double *)pjc_w, (const double *)pjc_xi, ne, (const double *)pq, ptp,
+                               PcgCheck{});
             hipLaunchKernelGGL(k_jt_corners<double>, dim3(nblk(nr, 4)), dim3(256), 0, s, nr,
                                (const int *)c->zero_flag, (const int32_t *)pjr_ptr, (const int32_t *)pjr_src,
                                (const double *)ptp, prr);
@@ -1475,6 +1503,7 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles, int wh
     const bool red_sys = (int64_t)k == P.n_local_sys;
     sd[k].yfull = red_sys ? c->yfull : nullptr;
     sd[k].act_bv = red_sys ? c->act_bv : nullptr;
+    sd[k].gidx = red_sys ? nullptr : (const int32_t *)c->sub_idx + S.vec_off;
   }
   c->h_msys.resize(P.sys.size());
   for (size_t k = 0; k < P.sys.size(); ++k) {
@@ -1532,13 +1561,14 @@ void setup_precision(coarse_ctx *c, const Plan &P, const int *gemv_tiles, int wh
   c->whole_local = G.whole_local;
   c->whole_total = (int32_t)G.whole.size();
   // wavefronts per whole-system workgroup: the caller's choice or the default for
-  // the tile type, halved while one wavefront copy per wave of the largest such
-  // system would not fit the 64 KiB of LDS a workgroup may use
+  // the tile type, halved while one solution copy per wave of the largest such
+  // system, plus its staged right-hand side, would not fit the 64 KiB of LDS a
+  // workgroup may use
   int nw = whole_waves_ok(c->precision, whole_waves) ? whole_waves
                                                      : (sizeof(TT) == 8 ? WHOLE_WAVES_F64 : WHOLE_WAVES_NARROW);
-  while (nw > 2 && (int64_t)nw * G.whole_nb_max * TILE * (int64_t)sizeof(T) > 65536) nw /= 2;
+  while (nw > 2 && (int64_t)(nw + 1) * G.whole_nb_max * TILE * (int64_t)sizeof(T) > 65536) nw /= 2;
   c->whole_waves = nw;
-  c->whole_lds = nw * G.whole_nb_max * TILE * (int32_t)sizeof(T);
+  c->whole_lds = (nw + 1) * G.whole_nb_max * TILE * (int32_t)sizeof(T);
   c->h_seg_all = Seg{c->items, c->rows, c->whole, c->sysdev, nullptr, 0, 0};
   c->h_seg_local = c->h_seg_all;
   c->h_seg_coarse = Seg{c->items + il, c->rows + rl, c->whole + c->whole_local, c->sysdev, nullptr, 0, 0};
@@ -1860,7 +1890,7 @@ struct coarse_batch {
     hipLaunchKernelGGL(k_pre_grp<T>, dim3(grid[G_PRE]), dim3(256), 0, main, (const IterDev *)d_iter, off + 2 * L, n);
     hipLaunchKernelGGL(k_jt_corners_grp<T>, dim3(grid[G_COR]), dim3(256), 0, main, (const IterDev *)d_iter,
                        off + 3 * L, n);
-    launch_gemv(main, precision, whole_waves, d_seg, n, n_items, d_seg + 2 * cap, n_whole, whole_lds, nullptr);
+    launch_gemv(main, precision, whole_waves, d_seg, n, n_items, d_seg + 2 * cap, n_whole, whole_lds, nullptr, nullptr);
     if (n_rows > 0)
       hipLaunchKernelGGL(k_combine<T>, dim3(nblk((int64_t)n_rows * TILE, 256)), dim3(256), 0, main,
                          (const Seg *)(d_seg + cap), n, n_rows, (const int *)nullptr);

@@ -31,6 +31,16 @@ struct Scalars {
   int32_t done, status, max_it, flexible, pad0, pad1;
 };
 
+// The convergence test of PCG carried by the first kernel of a preconditioner
+// application (sc == nullptr: none): the workgroup partials of the residual
+// norm, their count, and the start flag of pcg_check; lead != 0 lets workgroup 0
+// record the outcome (one kernel per application records it).
+struct PcgCheck {
+  Scalars *sc;
+  const double *part;
+  int32_t n, start, lead, pad;
+};
+
 // One dense system of the batched local/reduced solve, with absolute pointers.
 struct SysDev {
   const void *tiles;   // lower tiles of A_s^{-1}, TILE x TILE row-major each
@@ -40,6 +50,7 @@ struct SysDev {
   double *zp;          // solution (nb*TILE entries)
   double *yfull;       // reduced system only: solution scattered to all box vertices
   const int32_t *act_bv;   // reduced system only: active index -> box vertex
+  const int32_t *gidx;     // local systems: internal vertex of each packed entry (-1: padding)
   int32_t nb, n;
   float scale;             // FP16 tiles hold A_s^{-1} / scale (1 otherwise)
   int32_t pad;

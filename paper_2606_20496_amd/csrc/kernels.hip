@@ -555,9 +555,12 @@ __global__ __launch_bounds__(VW) void k_update_fused(int64_t nf, OpDev op, Scala
 // the tolerance;
 // otherwise of ||r_{k+1}||^2, tested against tol^2 ||b||^2 and the iteration cap.
 // Returns true when the solve is over (every workgroup reaches the same answer).
+// Only workgroup blk == 0 records the outcome in the solver state. NT: threads
+// of the calling workgroup (red holds NT / WAVE doubles).
+template <int NT = 256>
 __device__ bool pcg_check(Scalars *__restrict__ sc, const double *__restrict__ part, int n, int start, double *red,
                           int blk) {
-  const double s = block_total<256>(part, n, red);
+  const double s = block_total<NT>(part, n, red);
   const bool lead = blk == 0 && threadIdx.x == 0;
   if (start) {
     // start = 2 (initial guess by projection): the partials are those of
@@ -603,6 +606,14 @@ __global__ __launch_bounds__(256) void k_check(Scalars *__restrict__ sc, const d
   __shared__ double red[256 / WAVE];
   if (sc->done) return;
   (void)pcg_check(sc, part, n, start, red, blockIdx.x);
+}
+
+// The convergence test carried by a kernel of NT threads per workgroup: true
+// when the solve is over (the workgroup then does nothing else).
+template <int NT>
+__device__ __forceinline__ bool carried_check(const PcgCheck &ck, double *red) {
+  if (!ck.sc) return false;
+  return pcg_check<NT>(ck.sc, ck.part, ck.n, ck.start, red, ck.lead ? (int)blockIdx.x : 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -824,8 +835,10 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_jt_tasks(int ntask, const int *__restrict__ done, const int32_t *__restrict__ tstart,
                                                   const int32_t *__restrict__ vid, const T *__restrict__ w,
                                                   const T *__restrict__ xi, int64_t nent, const double *__restrict__ in,
-                                                  T *__restrict__ tpart) {
+                                                  T *__restrict__ tpart, PcgCheck ck) {
+  __shared__ double red[256 / WAVE];
   if (*done) return;
+  if (carried_check<256>(ck, red)) return;
   const int task = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (task >= ntask) return;
   jt_task<T>(task, tstart, vid, w, xi, nent, in, tpart);
@@ -875,18 +888,25 @@ __device__ __forceinline__ int find_seg(const Seg *__restrict__ segs, int nseg, 
 }
 
 // Streaming (non-temporal) 16-byte loads: the stored inverses are read once per
-// application and should not displace the small vectors from the caches.
+// application and should not displace the small vectors from the caches. They
+// are issued as global (not flat) loads: a flat load also counts against the
+// wait for LDS accesses, which would hold every LDS access of the loop until
+// the prefetched tile has arrived.
 typedef double nt_d2 __attribute__((ext_vector_type(2)));
 typedef float nt_f4 __attribute__((ext_vector_type(4)));
+template <typename V>
+__device__ __forceinline__ V ldnt_global(const V *p) {
+  return __builtin_nontemporal_load((const __attribute__((address_space(1))) V *)p);
+}
 __device__ __forceinline__ double2 ldnt(const double2 *p) {
-  const nt_d2 v = __builtin_nontemporal_load((const nt_d2 *)p);
+  const nt_d2 v = ldnt_global((const nt_d2 *)p);
   double2 o;
   o.x = v.x;
   o.y = v.y;
   return o;
 }
 __device__ __forceinline__ float4 ldnt(const float4 *p) {
-  const nt_f4 v = __builtin_nontemporal_load((const nt_f4 *)p);
+  const nt_f4 v = ldnt_global((const nt_f4 *)p);
   float4 o;
   o.x = v.x;
   o.y = v.y;
@@ -941,48 +961,101 @@ __device__ __forceinline__ void whole_finish(const SysDev &S, A *ys, double scal
   }
 }
 
+// Clears the NW solution copies and stages the right-hand side r_s in LDS after
+// them: gathered from the full vector gin through the system's packed indices
+// (r_p = R_p r, padding 0) when gin is given and the system is a local one, else
+// copied from the packed vector S.rp. Returns the wavefront's solution copy; rs
+// receives the staged right-hand side.
 template <int NW, typename A>
-__device__ __forceinline__ A *whole_begin(const SysDev &S, A *ys) {
+__device__ __forceinline__ A *whole_begin(const SysDev &S, A *ys, const double *__restrict__ gin, const A *&rs) {
   const int n = S.nb * TILE;
   for (int i = threadIdx.x; i < NW * n; i += NW * WAVE) ys[i] = A(0);
+  A *r = ys + NW * n;
+  constexpr int U = 4;   // entries per thread and step, their loads issued together
+  if (gin && S.gidx) {
+    for (int i0 = threadIdx.x; i0 < n; i0 += U * NW * WAVE) {
+      int32_t v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = (i0 + u * NW * WAVE < n) ? S.gidx[i0 + u * NW * WAVE] : -1;
+      double x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) x[u] = (v[u] >= 0) ? gin[v[u]] : 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (i0 + u * NW * WAVE < n) r[i0 + u * NW * WAVE] = (v[u] >= 0) ? (A)x[u] : A(0);
+    }
+  } else {
+    const A *__restrict__ src = (const A *)S.rp;
+    for (int i = threadIdx.x; i < n; i += NW * WAVE) r[i] = src[i];
+  }
+  rs = r;
   __syncthreads();
   return ys + (threadIdx.x >> 6) * n;
 }
 
-// FP64 tiles: lane layout of k_gemv_f64 below.
+// Entry k of a work item's right-hand side: gathered from gin through the
+// packed indices (local systems, when gin is given), else the packed vector.
+template <typename A>
+__device__ __forceinline__ A rhs_at(const SysDev &S, const double *__restrict__ gin, int k) {
+  if (gin && S.gidx) {
+    const int32_t v = S.gidx[k];
+    return v >= 0 ? (A)gin[v] : A(0);
+  }
+  return ((const A *)S.rp)[k];
+}
+
+// Tiles a wavefront walks in the row order: the sum over its rows I of I + 1.
 template <int NW>
-__device__ __forceinline__ void whole_f64(const SysDev &S, double *ys) {
-  double *y = whole_begin<NW>(S, ys);
+__device__ __forceinline__ int wave_row_tiles(int nb, int w) {
+  int T = 0;
+  for (int k = 0;; ++k) {
+    const int I = snake_row<NW>(nb, w, k);
+    if (I < 0) return T;
+    T += I + 1;
+  }
+}
+
+// FP64 tiles: lane layout of k_gemv_f64 below. Two register buffers take turns
+// (the loop body is unrolled twice): the next tile is in flight while the
+// current one is used, and the main loop issues its loads unconditionally (the
+// last tiles of the walk are handled after it), so that the compiler's count of
+// loads in flight stays exact and a tile's use waits for that tile alone.
+template <int NW>
+__device__ __forceinline__ void whole_f64(const SysDev &S, double *ys, const double *__restrict__ gin) {
+  const double *r;
+  double *y = whole_begin<NW>(S, ys, gin, r);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int grp = lane >> 4, c2 = (lane & 15) * 2;
   const int nb = S.nb;
-  const double *__restrict__ r = (const double *)S.rp;
   const double2 *__restrict__ base = (const double2 *)S.tiles;
-  int k = 0, I = snake_row<NW>(nb, w, 0), J = 0;
-  if (I >= 0) {
-    double2 v[8], nv[8];
-    const double2 *t = base + ((int64_t)I * (I + 1) / 2) * (TILE * TILE / 2);
+  const int T = wave_row_tiles<NW>(nb, w);
+  if (T > 0) {
+    auto load = [&](int ti, int tj, double2 *dst) {
+      const double2 *t = base + ((int64_t)ti * (ti + 1) / 2 + tj) * (TILE * TILE / 2);
 #pragma unroll
-    for (int m = 0; m < 8; ++m) v[m] = ldnt(t + m * 64 + lane);
+      for (int m = 0; m < 8; ++m) dst[m] = ldnt(t + m * 64 + lane);
+    };
+    // (k0, I0, J0): the tile in use; (k1, I1, J1): the next one
+    int k0 = 0, I0 = snake_row<NW>(nb, w, 0), J0 = 0, k1, I1, J1;
+    whole_next<NW>(nb, w, k0, I0, J0, k1, I1, J1);
+    // both buffers are loaded whatever T (a walk of one tile loads it twice), so
+    // that every path into the loop has issued the same loads
+    double2 va[8], vb[8];
+    load(I0, J0, va);
+    load(T > 1 ? I1 : I0, T > 1 ? J1 : J0, vb);
     double rI[8], acc[8];
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
-      rI[m] = r[I * TILE + 4 * m + grp];
+      rI[m] = r[I0 * TILE + 4 * m + grp];
       acc[m] = 0.0;
     }
-    for (;;) {
-      int nk, nI, nJ;
-      whole_next<NW>(nb, w, k, I, J, nk, nI, nJ);
-      const bool more = nI >= 0;
-      if (more) {
-        const double2 *tn = base + ((int64_t)nI * (nI + 1) / 2 + nJ) * (TILE * TILE / 2);
-#pragma unroll
-        for (int m = 0; m < 8; ++m) nv[m] = ldnt(tn + m * 64 + lane);
-      }
-      const double2 rj = *(const double2 *)(r + J * TILE + c2);
+    int t = 0;
+    // uses the tile in v, then (refill) loads into v the tile two positions ahead
+    auto step = [&](double2 *v, bool refill) {
+      const double2 rj = *(const double2 *)(r + J0 * TILE + c2);
 #pragma unroll
       for (int m = 0; m < 8; ++m) acc[m] += v[m].x * rj.x + v[m].y * rj.y;
-      if (J != I) {
+      if (J0 != I0) {
         double cx = 0.0, cy = 0.0;
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
@@ -994,11 +1067,11 @@ __device__ __forceinline__ void whole_f64(const SysDev &S, double *ys) {
         cx += __shfl_xor(cx, 32, 64);
         cy += __shfl_xor(cy, 32, 64);
         if (lane < 16) {
-          y[J * TILE + c2] += cx;
-          y[J * TILE + c2 + 1] += cy;
+          y[J0 * TILE + c2] += cx;
+          y[J0 * TILE + c2 + 1] += cy;
         }
       } else {
-        // row I complete
+        // row I0 complete
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
           double a = acc[m];
@@ -1007,20 +1080,32 @@ __device__ __forceinline__ void whole_f64(const SysDev &S, double *ys) {
           a += __shfl_xor(a, 4, 64);
           a += __shfl_xor(a, 8, 64);
           acc[m] = 0.0;
-          if ((lane & 15) == 0) y[I * TILE + 4 * m + grp] += a;
+          if ((lane & 15) == 0) y[I0 * TILE + 4 * m + grp] += a;
         }
-        if (more) {
+        if (I1 >= 0) {
 #pragma unroll
-          for (int m = 0; m < 8; ++m) rI[m] = r[nI * TILE + 4 * m + grp];
+          for (int m = 0; m < 8; ++m) rI[m] = r[I1 * TILE + 4 * m + grp];
         }
       }
-      if (!more) break;
-#pragma unroll
-      for (int m = 0; m < 8; ++m) v[m] = nv[m];
-      k = nk;
-      I = nI;
-      J = nJ;
+      int k2, I2, J2;
+      whole_next<NW>(nb, w, k1, I1, J1, k2, I2, J2);
+      if (refill) load(I2, J2, v);
+      k0 = k1;
+      I0 = I1;
+      J0 = J1;
+      k1 = k2;
+      I1 = I2;
+      J1 = J2;
+      ++t;
+    };
+    while (t + 3 < T) {
+      step(va, true);
+      step(vb, true);
     }
+    // at most three tiles left: t in va, t + 1 in vb, t + 2 loaded into va
+    if (t < T) step(va, t + 2 < T);
+    if (t < T) step(vb, false);
+    if (t < T) step(va, false);
   }
   whole_finish<NW>(S, ys, 1.0);
 }
@@ -1036,7 +1121,7 @@ __device__ __forceinline__ const Seg &seg_of(const Seg *__restrict__ segs, int n
 // holds rows 4k + l/16 (k < 8), columns 2(l%16) and 2(l%16)+1. The next tile is
 // loaded while the current one is used.
 __device__ __forceinline__ void items_f64(const Seg *__restrict__ segs, int nseg, int total, int g0,
-                                          int gstride) {
+                                          int gstride, const double *__restrict__ gin) {
   const int lane = threadIdx.x & 63;
   const int grp = lane >> 4, c2 = (lane & 15) * 2;
   for (int g = g0; g < total; g += gstride) {
@@ -1045,6 +1130,7 @@ __device__ __forceinline__ void items_f64(const Seg *__restrict__ segs, int nseg
     const GItem it = sg.items[g - sg.begin];
     const SysDev S = sg.sys[it.sys];
     const double *__restrict__ r = (const double *)S.rp;
+    const bool gr = gin && S.gidx;   // right-hand side gathered through the packed indices
     const int I = it.I;
     const int64_t rowbase = (int64_t)I * (I + 1) / 2;
     const double2 *__restrict__ t = (const double2 *)((const double *)S.tiles + (rowbase + it.j0) * (TILE * TILE));
@@ -1054,7 +1140,7 @@ __device__ __forceinline__ void items_f64(const Seg *__restrict__ segs, int nseg
     double rI[8], acc[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      rI[k] = r[I * TILE + 4 * k + grp];
+      rI[k] = gr ? rhs_at<double>(S, gin, I * TILE + 4 * k + grp) : r[I * TILE + 4 * k + grp];
       acc[k] = 0.0;
     }
     for (int J = it.j0; J < it.j1; ++J) {
@@ -1064,7 +1150,8 @@ __device__ __forceinline__ void items_f64(const Seg *__restrict__ segs, int nseg
 #pragma unroll
         for (int k = 0; k < 8; ++k) w[k] = ldnt(t + k * 64 + lane);
       }
-      const double2 rj = *(const double2 *)(r + J * TILE + c2);
+      const double2 rj = gr ? make_double2(rhs_at<double>(S, gin, J * TILE + c2), rhs_at<double>(S, gin, J * TILE + c2 + 1))
+                            : *(const double2 *)(r + J * TILE + c2);
 #pragma unroll
       for (int k = 0; k < 8; ++k) acc[k] += v[k].x * rj.x + v[k].y * rj.y;
       if (J != I) {
@@ -1109,9 +1196,12 @@ __device__ __forceinline__ void items_f64(const Seg *__restrict__ segs, int nseg
 
 // Work items only, one per wavefront.
 __global__ __launch_bounds__(256) void k_gemv_f64(const Seg *__restrict__ segs, int nseg, int total,
-                                                  const int *__restrict__ done) {
+                                                  const int *__restrict__ done, const double *__restrict__ gin,
+                                                  PcgCheck ck) {
+  __shared__ double red[256 / WAVE];
   if (done && *done) return;
-  items_f64(segs, nseg, total, blockIdx.x * 4 + (threadIdx.x >> 6), gridDim.x * 4);
+  if (carried_check<256>(ck, red)) return;
+  items_f64(segs, nseg, total, blockIdx.x * 4 + (threadIdx.x >> 6), gridDim.x * 4, gin);
 }
 
 // Workgroups [0, nwhole) solve whole systems (wsegs: begin offsets in systems),
@@ -1119,53 +1209,56 @@ __global__ __launch_bounds__(256) void k_gemv_f64(const Seg *__restrict__ segs, 
 template <int NW>
 __global__ __launch_bounds__(NW * WAVE) void k_gemv_whole_f64(const Seg *__restrict__ segs, int nseg, int total,
                                                               const Seg *__restrict__ wsegs, int nwhole,
-                                                              const int *__restrict__ done) {
+                                                              const int *__restrict__ done,
+                                                              const double *__restrict__ gin, PcgCheck ck) {
   extern __shared__ double ys_whole_d[];
+  __shared__ double red[NW];
   if (done && *done) return;
+  if (carried_check<NW * WAVE>(ck, red)) return;
   if ((int)blockIdx.x < nwhole) {
     const Seg &sg = seg_of(wsegs, nseg, blockIdx.x);
     if (sg.done && *sg.done) return;
-    whole_f64<NW>(sg.sys[sg.whole[blockIdx.x - sg.begin]], ys_whole_d);
+    whole_f64<NW>(sg.sys[sg.whole[blockIdx.x - sg.begin]], ys_whole_d, gin);
     return;
   }
-  items_f64(segs, nseg, total, (blockIdx.x - nwhole) * NW + (threadIdx.x >> 6), (gridDim.x - nwhole) * NW);
+  items_f64(segs, nseg, total, (blockIdx.x - nwhole) * NW + (threadIdx.x >> 6), (gridDim.x - nwhole) * NW, gin);
 }
 
 // FP32: 4 loads of 16 bytes per lane per tile; lane l holds rows 8m + l/8 (m < 4),
-// columns 4(l%8) .. 4(l%8)+3.
+// columns 4(l%8) .. 4(l%8)+3. Two register buffers take turns, as for FP64 tiles.
 template <int NW>
-__device__ __forceinline__ void whole_f32(const SysDev &S, float *ys) {
-  float *y = whole_begin<NW>(S, ys);
+__device__ __forceinline__ void whole_f32(const SysDev &S, float *ys, const double *__restrict__ gin) {
+  const float *r;
+  float *y = whole_begin<NW>(S, ys, gin, r);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int grp = lane >> 3, c4 = (lane & 7) * 4;
   const int nb = S.nb;
-  const float *__restrict__ r = (const float *)S.rp;
   const float4 *__restrict__ base = (const float4 *)S.tiles;
-  int k = 0, I = snake_row<NW>(nb, w, 0), J = 0;
-  if (I >= 0) {
-    float4 v[4], nv[4];
-    const float4 *t = base + ((int64_t)I * (I + 1) / 2) * (TILE * TILE / 4);
+  const int T = wave_row_tiles<NW>(nb, w);
+  if (T > 0) {
+    auto load = [&](int ti, int tj, float4 *dst) {
+      const float4 *t = base + ((int64_t)ti * (ti + 1) / 2 + tj) * (TILE * TILE / 4);
 #pragma unroll
-    for (int m = 0; m < 4; ++m) v[m] = ldnt(t + m * 64 + lane);
+      for (int m = 0; m < 4; ++m) dst[m] = ldnt(t + m * 64 + lane);
+    };
+    int k0 = 0, I0 = snake_row<NW>(nb, w, 0), J0 = 0, k1, I1, J1;
+    whole_next<NW>(nb, w, k0, I0, J0, k1, I1, J1);
+    // both buffers are loaded whatever T, as for FP64 tiles
+    float4 va[4], vb[4];
+    load(I0, J0, va);
+    load(T > 1 ? I1 : I0, T > 1 ? J1 : J0, vb);
     float rI[4], acc[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      rI[m] = r[I * TILE + 8 * m + grp];
+      rI[m] = r[I0 * TILE + 8 * m + grp];
       acc[m] = 0.0f;
     }
-    for (;;) {
-      int nk, nI, nJ;
-      whole_next<NW>(nb, w, k, I, J, nk, nI, nJ);
-      const bool more = nI >= 0;
-      if (more) {
-        const float4 *tn = base + ((int64_t)nI * (nI + 1) / 2 + nJ) * (TILE * TILE / 4);
-#pragma unroll
-        for (int m = 0; m < 4; ++m) nv[m] = ldnt(tn + m * 64 + lane);
-      }
-      const float4 rj = *(const float4 *)(r + J * TILE + c4);
+    int t = 0;
+    auto step = [&](float4 *v, bool refill) {
+      const float4 rj = *(const float4 *)(r + J0 * TILE + c4);
 #pragma unroll
       for (int m = 0; m < 4; ++m) acc[m] += v[m].x * rj.x + v[m].y * rj.y + v[m].z * rj.z + v[m].w * rj.w;
-      if (J != I) {
+      if (J0 != I0) {
         float c[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
@@ -1182,7 +1275,7 @@ __device__ __forceinline__ void whole_f32(const SysDev &S, float *ys) {
         }
         if (lane < 8) {
 #pragma unroll
-          for (int j = 0; j < 4; ++j) y[J * TILE + c4 + j] += c[j];
+          for (int j = 0; j < 4; ++j) y[J0 * TILE + c4 + j] += c[j];
         }
       } else {
 #pragma unroll
@@ -1192,27 +1285,38 @@ __device__ __forceinline__ void whole_f32(const SysDev &S, float *ys) {
           a += __shfl_xor(a, 2, 64);
           a += __shfl_xor(a, 4, 64);
           acc[m] = 0.0f;
-          if ((lane & 7) == 0) y[I * TILE + 8 * m + grp] += a;
+          if ((lane & 7) == 0) y[I0 * TILE + 8 * m + grp] += a;
         }
-        if (more) {
+        if (I1 >= 0) {
 #pragma unroll
-          for (int m = 0; m < 4; ++m) rI[m] = r[nI * TILE + 8 * m + grp];
+          for (int m = 0; m < 4; ++m) rI[m] = r[I1 * TILE + 8 * m + grp];
         }
       }
-      if (!more) break;
-#pragma unroll
-      for (int m = 0; m < 4; ++m) v[m] = nv[m];
-      k = nk;
-      I = nI;
-      J = nJ;
+      int k2, I2, J2;
+      whole_next<NW>(nb, w, k1, I1, J1, k2, I2, J2);
+      if (refill) load(I2, J2, v);
+      k0 = k1;
+      I0 = I1;
+      J0 = J1;
+      k1 = k2;
+      I1 = I2;
+      J1 = J2;
+      ++t;
+    };
+    while (t + 3 < T) {
+      step(va, true);
+      step(vb, true);
     }
+    if (t < T) step(va, t + 2 < T);
+    if (t < T) step(vb, false);
+    if (t < T) step(va, false);
   }
   whole_finish<NW>(S, ys, 1.0);
 }
 
 
 __device__ __forceinline__ void items_f32(const Seg *__restrict__ segs, int nseg, int total, int g0,
-                                          int gstride) {
+                                          int gstride, const double *__restrict__ gin) {
   const int lane = threadIdx.x & 63;
   const int grp = lane >> 3, c4 = (lane & 7) * 4;
   for (int g = g0; g < total; g += gstride) {
@@ -1221,6 +1325,7 @@ __device__ __forceinline__ void items_f32(const Seg *__restrict__ segs, int nseg
     const GItem it = sg.items[g - sg.begin];
     const SysDev S = sg.sys[it.sys];
     const float *__restrict__ r = (const float *)S.rp;
+    const bool gr = gin && S.gidx;   // right-hand side gathered through the packed indices
     const int I = it.I;
     const int64_t rowbase = (int64_t)I * (I + 1) / 2;
     const float4 *__restrict__ t = (const float4 *)((const float *)S.tiles + (rowbase + it.j0) * (TILE * TILE));
@@ -1230,7 +1335,7 @@ __device__ __forceinline__ void items_f32(const Seg *__restrict__ segs, int nseg
     float rI[4], acc[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      rI[m] = r[I * TILE + 8 * m + grp];
+      rI[m] = gr ? rhs_at<float>(S, gin, I * TILE + 8 * m + grp) : r[I * TILE + 8 * m + grp];
       acc[m] = 0.0f;
     }
     for (int J = it.j0; J < it.j1; ++J) {
@@ -1240,7 +1345,9 @@ __device__ __forceinline__ void items_f32(const Seg *__restrict__ segs, int nseg
 #pragma unroll
         for (int m = 0; m < 4; ++m) w[m] = ldnt(t + m * 64 + lane);
       }
-      const float4 rj = *(const float4 *)(r + J * TILE + c4);
+      const float4 rj = gr ? make_float4(rhs_at<float>(S, gin, J * TILE + c4), rhs_at<float>(S, gin, J * TILE + c4 + 1),
+                                         rhs_at<float>(S, gin, J * TILE + c4 + 2), rhs_at<float>(S, gin, J * TILE + c4 + 3))
+                           : *(const float4 *)(r + J * TILE + c4);
 #pragma unroll
       for (int m = 0; m < 4; ++m) acc[m] += v[m].x * rj.x + v[m].y * rj.y + v[m].z * rj.z + v[m].w * rj.w;
       if (J != I) {
@@ -1290,9 +1397,12 @@ __device__ __forceinline__ void items_f32(const Seg *__restrict__ segs, int nseg
 
 // Work items only, one per wavefront.
 __global__ __launch_bounds__(256) void k_gemv_f32(const Seg *__restrict__ segs, int nseg, int total,
-                                                  const int *__restrict__ done) {
+                                                  const int *__restrict__ done, const double *__restrict__ gin,
+                                                  PcgCheck ck) {
+  __shared__ double red[256 / WAVE];
   if (done && *done) return;
-  items_f32(segs, nseg, total, blockIdx.x * 4 + (threadIdx.x >> 6), gridDim.x * 4);
+  if (carried_check<256>(ck, red)) return;
+  items_f32(segs, nseg, total, blockIdx.x * 4 + (threadIdx.x >> 6), gridDim.x * 4, gin);
 }
 
 // Workgroups [0, nwhole) solve whole systems (wsegs: begin offsets in systems),
@@ -1300,17 +1410,20 @@ __global__ __launch_bounds__(256) void k_gemv_f32(const Seg *__restrict__ segs, 
 template <int NW>
 __global__ __launch_bounds__(NW * WAVE) void k_gemv_whole_f32(const Seg *__restrict__ segs, int nseg,
                                                                  int total, const Seg *__restrict__ wsegs,
-                                                                 int nwhole, const int *__restrict__ done) {
+                                                                 int nwhole, const int *__restrict__ done,
+                                                                 const double *__restrict__ gin, PcgCheck ck) {
   extern __shared__ float ys_whole[];
+  __shared__ double red[NW];
   if (done && *done) return;
+  if (carried_check<NW * WAVE>(ck, red)) return;
   if ((int)blockIdx.x < nwhole) {
     const Seg &sg = seg_of(wsegs, nseg, blockIdx.x);
     if (sg.done && *sg.done) return;
-    whole_f32<NW>(sg.sys[sg.whole[blockIdx.x - sg.begin]], ys_whole);
+    whole_f32<NW>(sg.sys[sg.whole[blockIdx.x - sg.begin]], ys_whole, gin);
     return;
   }
   items_f32(segs, nseg, total, (blockIdx.x - nwhole) * NW + (threadIdx.x >> 6),
-            (gridDim.x - nwhole) * NW);
+            (gridDim.x - nwhole) * NW, gin);
 }
 
 // FP16 tiles (the inverse divided by a power-of-two scale per system, so every
@@ -1337,13 +1450,19 @@ __device__ __forceinline__ float quad_sum(float v) {
 // so the transposed contribution is kept per lane down the whole strip (summed
 // across lanes once per strip) and the per-tile cross-lane work is the short row
 // sum. The waves take the strips, longest first, in the snake order.
+// A 2 KB tile is a small load per wavefront, so two tiles are kept in flight
+// while a third is used: three register buffers in a fixed rotation (the loop
+// body is unrolled three times, so no loaded register is ever copied, which
+// would wait for its load). The main loop issues its loads unconditionally (the
+// last tiles of the walk are handled after it), so that the compiler's count of
+// loads in flight stays exact and a tile's use waits for that tile alone.
 template <int NW>
-__device__ __forceinline__ void whole_f16(const SysDev &S, float *ys) {
-  float *y = whole_begin<NW>(S, ys);
+__device__ __forceinline__ void whole_f16(const SysDev &S, float *ys, const double *__restrict__ gin) {
+  const float *r;
+  float *y = whole_begin<NW>(S, ys, gin, r);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int grp = lane >> 2, c8 = (lane & 3) * 8;
   const int nb = S.nb;
-  const float *__restrict__ r = (const float *)S.rp;
   const nt_h8 *__restrict__ base = (const nt_h8 *)S.tiles;
   // the wavefront's column strips, longest first in a snake order over the waves:
   // strip J holds tiles (I, J), I = J .. nb-1
@@ -1351,86 +1470,114 @@ __device__ __forceinline__ void whole_f16(const SysDev &S, float *ys) {
     const int p = k * NW + ((k & 1) ? NW - 1 - w : w);
     return p < nb ? p : -1;
   };
-  int k = 0, J = strip(0), I = J;
-  if (J >= 0) {
-    nt_h8 v[2], nv[2];
-    auto load = [&](int ti, int tj, nt_h8 *dst) {
-      const nt_h8 *t = base + ((int64_t)ti * (ti + 1) / 2 + tj) * (TILE * TILE / 8);
-#pragma unroll
-      for (int m = 0; m < 2; ++m) dst[m] = __builtin_nontemporal_load(t + m * 64 + lane);
-    };
-    load(I, J, v);
-    float rj[8], c[8];
-    {
-      const float4 ra = *(const float4 *)(r + J * TILE + c8);
-      const float4 rb = *(const float4 *)(r + J * TILE + c8 + 4);
-      const float t8[8] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w};
-#pragma unroll
-      for (int e = 0; e < 8; ++e) rj[e] = t8[e];
-    }
-#pragma unroll
-    for (int e = 0; e < 8; ++e) c[e] = 0.0f;
-    for (;;) {
-      int nk = k, nJ = J, nI = I + 1;
-      if (nI >= nb) {
-        nk = k + 1;
-        nJ = strip(nk);
-        nI = nJ;
-      }
-      const bool more = nJ >= 0;
-      if (more) load(nI, nJ, nv);
-      float rI[2];
-#pragma unroll
-      for (int m = 0; m < 2; ++m) rI[m] = r[I * TILE + 16 * m + grp];
-      // row contribution of tile (I, J): summed over the 4 lanes of a row group
-#pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        float a = 0.0f;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) a += (float)v[m][e] * rj[e];
-        a = quad_sum(a);
-        if ((lane & 3) == 0) y[I * TILE + 16 * m + grp] += a;
-      }
-      // transposed contribution, kept per lane down the strip
-      if (I != J) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) c[e] += (float)v[0][e] * rI[0] + (float)v[1][e] * rI[1];
-      }
-      if (nJ != J) {
-        // strip J complete
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          float a = c[e];
-          a += __shfl_xor(a, 4, 64);
-          a += __shfl_xor(a, 8, 64);
-          a += __shfl_xor(a, 16, 64);
-          a += __shfl_xor(a, 32, 64);
-          c[e] = 0.0f;
-          if (lane < 4) y[J * TILE + c8 + e] += a;
-        }
-        if (more) {
-          const float4 ra = *(const float4 *)(r + nJ * TILE + c8);
-          const float4 rb = *(const float4 *)(r + nJ * TILE + c8 + 4);
-          const float t8[8] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w};
-#pragma unroll
-          for (int e = 0; e < 8; ++e) rj[e] = t8[e];
-        }
-      }
-      if (!more) break;
-#pragma unroll
-      for (int m = 0; m < 2; ++m) v[m] = nv[m];
-      k = nk;
-      J = nJ;
-      I = nI;
-    }
+  int T = 0;
+  for (int k = 0;; ++k) {
+    const int J = strip(k);
+    if (J < 0) break;
+    T += nb - J;
   }
+  if (T == 0) {
+    whole_finish<NW>(S, ys, (double)S.scale);
+    return;
+  }
+  // position after (k, I, J) in the wavefront's walk (J < 0: none)
+  auto next = [&](int &k, int &I, int &J) {
+    if (J < 0) return;
+    if (++I >= nb) {
+      J = strip(++k);
+      I = J;
+    }
+  };
+  auto load = [&](int ti, int tj, nt_h8 *dst) {
+    const nt_h8 *t = base + ((int64_t)ti * (ti + 1) / 2 + tj) * (TILE * TILE / 8);
+#pragma unroll
+    for (int m = 0; m < 2; ++m) dst[m] = ldnt_global(t + m * 64 + lane);
+  };
+  // positions of the tiles t (in use), t + 1 and t + 2 (in flight)
+  int k0 = 0, J0 = strip(0), I0 = J0;
+  int k1 = k0, I1 = I0, J1 = J0;
+  next(k1, I1, J1);
+  int k2 = k1, I2 = I1, J2 = J1;
+  next(k2, I2, J2);
+  // all three buffers are loaded whatever T (a short walk loads its first tile
+  // again), so that every path into the loop has issued the same loads
+  nt_h8 va[2], vb[2], vc[2];
+  load(I0, J0, va);
+  load(T > 1 ? I1 : I0, T > 1 ? J1 : J0, vb);
+  load(T > 2 ? I2 : I0, T > 2 ? J2 : J0, vc);
+  float rj[8], c[8];
+  auto load_rj = [&](int J) {
+    const float4 ra = *(const float4 *)(r + J * TILE + c8);
+    const float4 rb = *(const float4 *)(r + J * TILE + c8 + 4);
+    const float t8[8] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) rj[e] = t8[e];
+  };
+  load_rj(J0);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) c[e] = 0.0f;
+  int t = 0;
+  // uses the tile (I0, J0) held in v, then (refill) loads into v the tile three
+  // positions ahead, and advances
+  auto step = [&](nt_h8 *v, bool refill) {
+    float rI[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) rI[m] = r[I0 * TILE + 16 * m + grp];
+    // row contribution of tile (I0, J0): summed over the 4 lanes of a row group
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      float a = 0.0f;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) a += (float)v[m][e] * rj[e];
+      a = quad_sum(a);
+      if ((lane & 3) == 0) y[I0 * TILE + 16 * m + grp] += a;
+    }
+    // transposed contribution, kept per lane down the strip
+    if (I0 != J0) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) c[e] += (float)v[0][e] * rI[0] + (float)v[1][e] * rI[1];
+    }
+    if (J1 != J0) {
+      // strip J0 complete
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        float a = c[e];
+        a += __shfl_xor(a, 4, 64);
+        a += __shfl_xor(a, 8, 64);
+        a += __shfl_xor(a, 16, 64);
+        a += __shfl_xor(a, 32, 64);
+        c[e] = 0.0f;
+        if (lane < 4) y[J0 * TILE + c8 + e] += a;
+      }
+      if (J1 >= 0) load_rj(J1);
+    }
+    int k3 = k2, I3 = I2, J3 = J2;
+    next(k3, I3, J3);
+    if (refill) load(I3, J3, v);
+    k0 = k1, I0 = I1, J0 = J1;
+    k1 = k2, I1 = I2, J1 = J2;
+    k2 = k3, I2 = I3, J2 = J3;
+    ++t;
+  };
+  while (t + 5 < T) {
+    step(va, true);
+    step(vb, true);
+    step(vc, true);
+  }
+  // at most five tiles left: t, t + 1, t + 2 in va, vb, vc; t + 3 and t + 4
+  // loaded into va and vb by the first two steps
+  if (t < T) step(va, t + 3 < T);
+  if (t < T) step(vb, t + 3 < T);
+  if (t < T) step(vc, false);
+  if (t < T) step(va, false);
+  if (t < T) step(vb, false);
   // the tiles hold A_s^{-1} / scale
   whole_finish<NW>(S, ys, (double)S.scale);
 }
 
 
 __device__ __forceinline__ void items_f16(const Seg *__restrict__ segs, int nseg, int total, int g0,
-                                          int gstride) {
+                                          int gstride, const double *__restrict__ gin) {
   const int lane = threadIdx.x & 63;
   const int grp = lane >> 2, c8 = (lane & 3) * 8;
   for (int g = g0; g < total; g += gstride) {
@@ -1439,16 +1586,17 @@ __device__ __forceinline__ void items_f16(const Seg *__restrict__ segs, int nseg
     const GItem it = sg.items[g - sg.begin];
     const SysDev S = sg.sys[it.sys];
     const float *__restrict__ r = (const float *)S.rp;
+    const bool gr = gin && S.gidx;   // right-hand side gathered through the packed indices
     const int I = it.I;
     const int64_t rowbase = (int64_t)I * (I + 1) / 2;
     const nt_h8 *__restrict__ t = (const nt_h8 *)((const _Float16 *)S.tiles + (rowbase + it.j0) * (TILE * TILE));
     nt_h8 v[2], w[2];
 #pragma unroll
-    for (int m = 0; m < 2; ++m) v[m] = __builtin_nontemporal_load(t + m * 64 + lane);
+    for (int m = 0; m < 2; ++m) v[m] = ldnt_global(t + m * 64 + lane);
     float rI[2], acc[2];
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
-      rI[m] = r[I * TILE + 16 * m + grp];
+      rI[m] = gr ? rhs_at<float>(S, gin, I * TILE + 16 * m + grp) : r[I * TILE + 16 * m + grp];
       acc[m] = 0.0f;
     }
     for (int J = it.j0; J < it.j1; ++J) {
@@ -1456,10 +1604,19 @@ __device__ __forceinline__ void items_f16(const Seg *__restrict__ segs, int nseg
       t += TILE * TILE / 8;
       if (more) {
 #pragma unroll
-        for (int m = 0; m < 2; ++m) w[m] = __builtin_nontemporal_load(t + m * 64 + lane);
+        for (int m = 0; m < 2; ++m) w[m] = ldnt_global(t + m * 64 + lane);
       }
-      const float4 ra = *(const float4 *)(r + J * TILE + c8);
-      const float4 rb = *(const float4 *)(r + J * TILE + c8 + 4);
+      float4 ra, rb;
+      if (gr) {
+        const int k = J * TILE + c8;
+        ra = make_float4(rhs_at<float>(S, gin, k), rhs_at<float>(S, gin, k + 1), rhs_at<float>(S, gin, k + 2),
+                         rhs_at<float>(S, gin, k + 3));
+        rb = make_float4(rhs_at<float>(S, gin, k + 4), rhs_at<float>(S, gin, k + 5), rhs_at<float>(S, gin, k + 6),
+                         rhs_at<float>(S, gin, k + 7));
+      } else {
+        ra = *(const float4 *)(r + J * TILE + c8);
+        rb = *(const float4 *)(r + J * TILE + c8 + 4);
+      }
       const float rj[8] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w};
 #pragma unroll
       for (int m = 0; m < 2; ++m)
@@ -1513,9 +1670,12 @@ __device__ __forceinline__ void items_f16(const Seg *__restrict__ segs, int nseg
 
 // Work items only, one per wavefront.
 __global__ __launch_bounds__(256) void k_gemv_f16(const Seg *__restrict__ segs, int nseg, int total,
-                                                  const int *__restrict__ done) {
+                                                  const int *__restrict__ done, const double *__restrict__ gin,
+                                                  PcgCheck ck) {
+  __shared__ double red[256 / WAVE];
   if (done && *done) return;
-  items_f16(segs, nseg, total, blockIdx.x * 4 + (threadIdx.x >> 6), gridDim.x * 4);
+  if (carried_check<256>(ck, red)) return;
+  items_f16(segs, nseg, total, blockIdx.x * 4 + (threadIdx.x >> 6), gridDim.x * 4, gin);
 }
 
 // Workgroups [0, nwhole) solve whole systems (wsegs: begin offsets in systems),
@@ -1523,17 +1683,20 @@ __global__ __launch_bounds__(256) void k_gemv_f16(const Seg *__restrict__ segs, 
 template <int NW>
 __global__ __launch_bounds__(NW * WAVE) void k_gemv_whole_f16(const Seg *__restrict__ segs, int nseg,
                                                                  int total, const Seg *__restrict__ wsegs,
-                                                                 int nwhole, const int *__restrict__ done) {
+                                                                 int nwhole, const int *__restrict__ done,
+                                                                 const double *__restrict__ gin, PcgCheck ck) {
   extern __shared__ float ys_whole[];
+  __shared__ double red[NW];
   if (done && *done) return;
+  if (carried_check<NW * WAVE>(ck, red)) return;
   if ((int)blockIdx.x < nwhole) {
     const Seg &sg = seg_of(wsegs, nseg, blockIdx.x);
     if (sg.done && *sg.done) return;
-    whole_f16<NW>(sg.sys[sg.whole[blockIdx.x - sg.begin]], ys_whole);
+    whole_f16<NW>(sg.sys[sg.whole[blockIdx.x - sg.begin]], ys_whole, gin);
     return;
   }
   items_f16(segs, nseg, total, (blockIdx.x - nwhole) * NW + (threadIdx.x >> 6),
-            (gridDim.x - nwhole) * NW);
+            (gridDim.x - nwhole) * NW, gin);
 }
 
 // z_s[I*TILE + c] = sum of the row partials of tile row I + sum over I' > I of
@@ -2343,9 +2506,9 @@ __global__ __launch_bounds__(256) void k_sweep_pack(const SweepSys *__restrict__
 template __global__ void k_gather<double>(int64_t, const int *, const int32_t *, const double *, double *);
 template __global__ void k_gather<float>(int64_t, const int *, const int32_t *, const double *, float *);
 template __global__ void k_jt_tasks<double>(int, const int *, const int32_t *, const int32_t *, const double *,
-                                            const double *, int64_t, const double *, double *);
+                                            const double *, int64_t, const double *, double *, PcgCheck);
 template __global__ void k_jt_tasks<float>(int, const int *, const int32_t *, const int32_t *, const float *,
-                                           const float *, int64_t, const double *, float *);
+                                           const float *, int64_t, const double *, float *, PcgCheck);
 template __global__ void k_jt_corners<double>(int64_t, const int *, const int32_t *, const int32_t *, const double *,
                                               double *);
 template __global__ void k_jt_corners<float>(int64_t, const int *, const int32_t *, const int32_t *, const float *,
