@@ -54,6 +54,7 @@ GEMV_TRAFFIC = {
                "write_scale": 1.0, "src": "0c72c6b9fc27f9aa"},
     "annulus128": {"bytes": 9236715024, "fetch_kib": 4498571.125, "write_kib": 23424.03, "fetch_scale": 2.0,
                    "write_scale": 1.0, "src": "42f65228d1c8d5a8"},
+}
 
 
 def _gemv_source_fingerprint():
