@@ -329,8 +329,9 @@ inline unsigned nblk(int64_t n, int b) { return (unsigned)std::max<int64_t>(1, (
 // The dense solves of one application: the whole-system workgroups (nwhole
 // systems, wsegs, nw wavefronts each) and the work items (segs), in one launch
 // when there are whole systems; either may be empty.
-// gin != nullptr: the local systems gather their right-hand sides r_p = R_p gin
-// themselves (through SysDev::gidx) instead of reading the packed vectors
+// gin != nullptr: the whole-system workgroups of local systems gather their
+// right-hand sides r_p = R_p gin themselves (through SysDev::gidx) instead of
+// reading the packed vectors (work items always read the packed vectors)
 template <int NW>
 void launch_whole(hipStream_t s, int precision, const Seg *segs, int nseg, int nitems, const Seg *wsegs, int nwhole,
                   int whole_lds, const int *done, const double *gin, const PcgCheck &ck) {
@@ -360,12 +361,20 @@ void launch_gemv(hipStream_t s, int precision, int nw, const Seg *segs, int nseg
     // one wavefront per work item (the kernel also loops over a smaller grid, but
     // one item per wavefront measured fastest on MI355X at every size tried)
     const unsigned g = nblk(nitems, 4);
+    const bool chunk = nitems <= ITEM_CHUNK_MAX_ITEMS;   // few items: latency-bound
     if (precision == COARSE_FP64)
-      hipLaunchKernelGGL(k_gemv_f64, dim3(g), dim3(256), 0, s, segs, nseg, nitems, done, gin, ck);
-    else if (precision == COARSE_MIXED_F16)
-      hipLaunchKernelGGL(k_gemv_f16, dim3(g), dim3(256), 0, s, segs, nseg, nitems, done, gin, ck);
-    else
-      hipLaunchKernelGGL(k_gemv_f32, dim3(g), dim3(256), 0, s, segs, nseg, nitems, done, gin, ck);
+      hipLaunchKernelGGL(k_gemv_f64, dim3(g), dim3(256), 0, s, segs, nseg, nitems, done, ck);
+    else if (precision == COARSE_MIXED_F16) {
+      if (chunk)
+        hipLaunchKernelGGL(k_gemv_f16<ITEM_CHUNK>, dim3(g), dim3(256), 0, s, segs, nseg, nitems, done, ck);
+      else
+        hipLaunchKernelGGL(k_gemv_f16<1>, dim3(g), dim3(256), 0, s, segs, nseg, nitems, done, ck);
+    } else {
+      if (chunk)
+        hipLaunchKernelGGL(k_gemv_f32<ITEM_CHUNK>, dim3(g), dim3(256), 0, s, segs, nseg, nitems, done, ck);
+      else
+        hipLaunchKernelGGL(k_gemv_f32<1>, dim3(g), dim3(256), 0, s, segs, nseg, nitems, done, ck);
+    }
   }
 }
 
@@ -626,12 +635,13 @@ struct coarse_ctx {
   }
 
   // the local solves of one application on the context's stream: the stored
-  // inverses (which gather r_p = R_p in themselves), or local_iters steps of
-  // Jacobi-PCG per subdomain on the gathered packed vectors (phase 3 either way)
+  // inverses (gin != nullptr: they gather r_p = R_p gin themselves), or
+  // local_iters steps of Jacobi-PCG per subdomain on the gathered packed vectors
+  // (phase 3 either way)
   template <typename T>
-  void local_part(const double *in, const int *done, const PcgCheck &ck = PcgCheck{}) {
+  void local_part(const double *gin, const int *done, const PcgCheck &ck = PcgCheck{}) {
     if (local_iters <= 0) {
-      gemv_combine(seg_local, items_local, rows_local, whole_local, done, in, ck);
+      gemv_combine(seg_local, items_local, rows_local, whole_local, done, gin, ck);
       return;
     }
     if (n_local_sys <= 0) return;
@@ -662,27 +672,31 @@ struct coarse_ctx {
   }
 
   // chk != nullptr: the convergence test of PCG runs first, from these partials.
-  // With stored inverses the dense solves gather r_p = R_p in themselves (the
-  // packed vectors are then not written); the inexact local solves read them
-  // from the gather of the first launch.
+  // When every local system is solved by a whole-system workgroup from its stored
+  // inverse, the dense solves gather r_p = R_p in themselves (the packed vectors
+  // are then not written); otherwise (work items, inexact local solves) a launch
+  // of its own gathers them first.
   template <typename T>
   void precond_parts(const double *in, const double *add, bool local, bool coarse, double *out, const double *rdot,
                      double *p1, double *p2, const int *done, bool scal, int start, const double *chk) {
-    const bool gather = local && local_iters > 0;   // packed r_p needed by a separate launch
+    const bool fuse = local && local_iters <= 0 && items_local == 0;
+    const bool gather = local && !fuse;   // packed r_p written by a launch of its own
+    const double *gin = fuse ? in : nullptr;
     if (local && coarse) {
       if (!reduced_aside && local_iters <= 0) {
         // a reduced system of at most WHOLE_NB_MAX tile rows joins the local
         // systems in one dense-solve launch: the convergence test and the first
         // stage of J^T in one launch, the corner sums, then the dense solves
         pbeg(1);
-        hipLaunchKernelGGL(k_pre<T>, dim3(std::max(pre_task_blocks(), 1)), dim3(256), 0, stream, 0, coarse_vec_off, done, sub_idx,
-                           in, (T *)rp, (int)ntask, jt_start, jc_vid, (const T *)jc_w, (const T *)jc_xi, nent,
-                           (T *)jt_part, chk ? sc : nullptr, chk, nvblk, start);
+        const int ng = gather ? pre_gather_blocks() : 0;
+        hipLaunchKernelGGL(k_pre<T>, dim3(std::max(ng + pre_task_blocks(), 1)), dim3(256), 0, stream, ng,
+                           coarse_vec_off, done, sub_idx, in, (T *)rp, (int)ntask, jt_start, jc_vid, (const T *)jc_w,
+                           (const T *)jc_xi, nent, (T *)jt_part, chk ? sc : nullptr, chk, nvblk, start);
         pend(1);
         pbeg(2);
         corners<T>(done);
         pend(2);
-        gemv_combine(seg_all, items_total, rows_total, whole_total, done, in);
+        gemv_combine(seg_all, items_total, rows_total, whole_total, done, gin);
         refine_reduced<T>(done, stream);
         final_step<T>(add, local, coarse, out, rdot, p1, p2, done, scal, start);
         return;
@@ -690,10 +704,11 @@ struct coarse_ctx {
       // The convergence test, the whole reduced-space branch on the second
       // stream (both stages of J^T, the dense solve of A_r and its partial sums)
       // beside the local solves; the two meet before the overlap sum. With
-      // stored inverses the local dense-solve launch carries the test (its
-      // workgroup 0 records it) and so does the J^T launch of the second stream
-      // (which records nothing); the inexact local solves need the gathered
-      // packed vectors, whose launch carries it instead. Across hardware queues
+      // stored inverses in whole-system workgroups the local dense-solve launch
+      // carries the test (its workgroup 0 records it) and so does the J^T launch
+      // of the second stream (which records nothing); work items and the inexact
+      // local solves need the gathered packed vectors, whose launch carries it
+      // instead. Across hardware queues
       // each of the two waits costs some microseconds, which a large reduced
       // system (its long tile rows end the fused launch late, and its partial
       // sums need a combine pass) repays and a small one does not. Inexact local
@@ -721,7 +736,7 @@ struct coarse_ctx {
       refine_reduced<T>(done, aux);
       pend(7, aux);
       HIPCHK(hipEventRecord(ev_join, aux));
-      local_part<T>(in, done, gather ? PcgCheck{} : ck_lead);
+      local_part<T>(gin, done, gather ? PcgCheck{} : ck_lead);
       HIPCHK(hipStreamWaitEvent(stream, ev_join, 0));
     } else {
       if (chk) hipLaunchKernelGGL(k_check, dim3(1), dim3(256), 0, stream, sc, chk, nvblk, start);
@@ -734,7 +749,7 @@ struct coarse_ctx {
       if (coarse) restrict_coarse<T>(in, done);
     }
     if (local && !coarse)
-      local_part<T>(in, done);
+      local_part<T>(gin, done);
     else if (coarse && !local) {
       gemv_combine(seg_coarse, items_total - items_local, rows_total - rows_local, whole_total - whole_local, done);
       refine_reduced<T>(done, stream);

@@ -993,16 +993,6 @@ __device__ __forceinline__ A *whole_begin(const SysDev &S, A *ys, const double *
   return ys + (threadIdx.x >> 6) * n;
 }
 
-// Entry k of a work item's right-hand side: gathered from gin through the
-// packed indices (local systems, when gin is given), else the packed vector.
-template <typename A>
-__device__ __forceinline__ A rhs_at(const SysDev &S, const double *__restrict__ gin, int k) {
-  if (gin && S.gidx) {
-    const int32_t v = S.gidx[k];
-    return v >= 0 ? (A)gin[v] : A(0);
-  }
-  return ((const A *)S.rp)[k];
-}
 
 // Tiles a wavefront walks in the row order: the sum over its rows I of I + 1.
 template <int NW>
@@ -1121,7 +1111,7 @@ __device__ __forceinline__ const Seg &seg_of(const Seg *__restrict__ segs, int n
 // holds rows 4k + l/16 (k < 8), columns 2(l%16) and 2(l%16)+1. The next tile is
 // loaded while the current one is used.
 __device__ __forceinline__ void items_f64(const Seg *__restrict__ segs, int nseg, int total, int g0,
-                                          int gstride, const double *__restrict__ gin) {
+                                          int gstride) {
   const int lane = threadIdx.x & 63;
   const int grp = lane >> 4, c2 = (lane & 15) * 2;
   for (int g = g0; g < total; g += gstride) {
@@ -1130,7 +1120,6 @@ __device__ __forceinline__ void items_f64(const Seg *__restrict__ segs, int nseg
     const GItem it = sg.items[g - sg.begin];
     const SysDev S = sg.sys[it.sys];
     const double *__restrict__ r = (const double *)S.rp;
-    const bool gr = gin && S.gidx;   // right-hand side gathered through the packed indices
     const int I = it.I;
     const int64_t rowbase = (int64_t)I * (I + 1) / 2;
     const double2 *__restrict__ t = (const double2 *)((const double *)S.tiles + (rowbase + it.j0) * (TILE * TILE));
@@ -1140,7 +1129,7 @@ __device__ __forceinline__ void items_f64(const Seg *__restrict__ segs, int nseg
     double rI[8], acc[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      rI[k] = gr ? rhs_at<double>(S, gin, I * TILE + 4 * k + grp) : r[I * TILE + 4 * k + grp];
+      rI[k] = r[I * TILE + 4 * k + grp];
       acc[k] = 0.0;
     }
     for (int J = it.j0; J < it.j1; ++J) {
@@ -1150,8 +1139,7 @@ __device__ __forceinline__ void items_f64(const Seg *__restrict__ segs, int nseg
 #pragma unroll
         for (int k = 0; k < 8; ++k) w[k] = ldnt(t + k * 64 + lane);
       }
-      const double2 rj = gr ? make_double2(rhs_at<double>(S, gin, J * TILE + c2), rhs_at<double>(S, gin, J * TILE + c2 + 1))
-                            : *(const double2 *)(r + J * TILE + c2);
+      const double2 rj = *(const double2 *)(r + J * TILE + c2);
 #pragma unroll
       for (int k = 0; k < 8; ++k) acc[k] += v[k].x * rj.x + v[k].y * rj.y;
       if (J != I) {
@@ -1196,12 +1184,11 @@ __device__ __forceinline__ void items_f64(const Seg *__restrict__ segs, int nseg
 
 // Work items only, one per wavefront.
 __global__ __launch_bounds__(256) void k_gemv_f64(const Seg *__restrict__ segs, int nseg, int total,
-                                                  const int *__restrict__ done, const double *__restrict__ gin,
-                                                  PcgCheck ck) {
+                                                  const int *__restrict__ done, PcgCheck ck) {
   __shared__ double red[256 / WAVE];
   if (done && *done) return;
   if (carried_check<256>(ck, red)) return;
-  items_f64(segs, nseg, total, blockIdx.x * 4 + (threadIdx.x >> 6), gridDim.x * 4, gin);
+  items_f64(segs, nseg, total, blockIdx.x * 4 + (threadIdx.x >> 6), gridDim.x * 4);
 }
 
 // Workgroups [0, nwhole) solve whole systems (wsegs: begin offsets in systems),
@@ -1221,7 +1208,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_gemv_whole_f64(const Seg *__restr
     whole_f64<NW>(sg.sys[sg.whole[blockIdx.x - sg.begin]], ys_whole_d, gin);
     return;
   }
-  items_f64(segs, nseg, total, (blockIdx.x - nwhole) * NW + (threadIdx.x >> 6), (gridDim.x - nwhole) * NW, gin);
+  items_f64(segs, nseg, total, (blockIdx.x - nwhole) * NW + (threadIdx.x >> 6), (gridDim.x - nwhole) * NW);
 }
 
 // FP32: 4 loads of 16 bytes per lane per tile; lane l holds rows 8m + l/8 (m < 4),
@@ -1315,8 +1302,56 @@ __device__ __forceinline__ void whole_f32(const SysDev &S, float *ys, const doub
 }
 
 
+// Work items of FP32 (and FP16) tiles. With CH > 1 the tiles of an item and
+// their right-hand-side pieces are loaded in chunks of up to CH, all issued
+// before the first is used, so an item costs one memory round trip per chunk
+// rather than one per tile: that pays when a launch holds few items (a single
+// small mesh), whose latency nothing else hides. With CH = 1 the item's tiles
+// are streamed with the next one in flight, at twice the occupancy: that pays
+// for the many items of a lock-step batch, and in the launches that also hold
+// whole-system workgroups, whose occupancy the chunk's registers would lower.
+// Both apply each tile with the same helper (explicit fused multiply-adds), so
+// an item's result does not depend on the launch it is in.
+constexpr int ITEM_CHUNK = 4;
+// launches of at most this many work items take the chunked form (it holds
+// three wavefronts per SIMD, 3072 on the 256 compute units)
+constexpr int ITEM_CHUNK_MAX_ITEMS = 3072;
+
+// One tile (I, J) of a work item, FP32: row contribution into acc, transposed
+// contribution (J != I) to the tile's column partial.
+__device__ __forceinline__ void item_tile_f32(const float4 (&v)[4], const float4 &rj, const float (&rI)[4],
+                                              float (&acc)[4], bool offdiag, float *__restrict__ colp, int lane) {
+#pragma unroll
+  for (int m = 0; m < 4; ++m) acc[m] += fmaf(v[m].w, rj.w, fmaf(v[m].z, rj.z, fmaf(v[m].y, rj.y, v[m].x * rj.x)));
+  if (offdiag) {
+    float c[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      c[0] = fmaf(v[m].x, rI[m], c[0]);
+      c[1] = fmaf(v[m].y, rI[m], c[1]);
+      c[2] = fmaf(v[m].z, rI[m], c[2]);
+      c[3] = fmaf(v[m].w, rI[m], c[3]);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      c[j] += __shfl_xor(c[j], 8, 64);
+      c[j] += __shfl_xor(c[j], 16, 64);
+      c[j] += __shfl_xor(c[j], 32, 64);
+    }
+    if (lane < 8) {
+      float4 o;
+      o.x = c[0];
+      o.y = c[1];
+      o.z = c[2];
+      o.w = c[3];
+      *(float4 *)colp = o;
+    }
+  }
+}
+
+template <int CH>
 __device__ __forceinline__ void items_f32(const Seg *__restrict__ segs, int nseg, int total, int g0,
-                                          int gstride, const double *__restrict__ gin) {
+                                          int gstride) {
   const int lane = threadIdx.x & 63;
   const int grp = lane >> 3, c4 = (lane & 7) * 4;
   for (int g = g0; g < total; g += gstride) {
@@ -1325,58 +1360,53 @@ __device__ __forceinline__ void items_f32(const Seg *__restrict__ segs, int nseg
     const GItem it = sg.items[g - sg.begin];
     const SysDev S = sg.sys[it.sys];
     const float *__restrict__ r = (const float *)S.rp;
-    const bool gr = gin && S.gidx;   // right-hand side gathered through the packed indices
     const int I = it.I;
     const int64_t rowbase = (int64_t)I * (I + 1) / 2;
-    const float4 *__restrict__ t = (const float4 *)((const float *)S.tiles + (rowbase + it.j0) * (TILE * TILE));
-    float4 v[4], w[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) v[m] = ldnt(t + m * 64 + lane);
+    const float4 *__restrict__ t0 = (const float4 *)((const float *)S.tiles + (rowbase + it.j0) * (TILE * TILE));
     float rI[4], acc[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      rI[m] = gr ? rhs_at<float>(S, gin, I * TILE + 8 * m + grp) : r[I * TILE + 8 * m + grp];
+      rI[m] = r[I * TILE + 8 * m + grp];
       acc[m] = 0.0f;
     }
-    for (int J = it.j0; J < it.j1; ++J) {
-      const bool more = J + 1 < it.j1;
-      t += TILE * TILE / 4;
-      if (more) {
+    auto colp = [&](int J) { return (float *)S.colpart + (rowbase + J) * TILE + c4; };
+    if constexpr (CH == 1) {
+      float4 v[4], w[4];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) w[m] = ldnt(t + m * 64 + lane);
-      }
-      const float4 rj = gr ? make_float4(rhs_at<float>(S, gin, J * TILE + c4), rhs_at<float>(S, gin, J * TILE + c4 + 1),
-                                         rhs_at<float>(S, gin, J * TILE + c4 + 2), rhs_at<float>(S, gin, J * TILE + c4 + 3))
-                           : *(const float4 *)(r + J * TILE + c4);
+      for (int m = 0; m < 4; ++m) v[m] = ldnt(t0 + m * 64 + lane);
+      const float4 *t = t0;
+      for (int J = it.j0; J < it.j1; ++J) {
+        const bool more = J + 1 < it.j1;
+        t += TILE * TILE / 4;
+        if (more) {
 #pragma unroll
-      for (int m = 0; m < 4; ++m) acc[m] += v[m].x * rj.x + v[m].y * rj.y + v[m].z * rj.z + v[m].w * rj.w;
-      if (J != I) {
-        float c[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          c[0] += v[m].x * rI[m];
-          c[1] += v[m].y * rI[m];
-          c[2] += v[m].z * rI[m];
-          c[3] += v[m].w * rI[m];
+          for (int m = 0; m < 4; ++m) w[m] = ldnt(t + m * 64 + lane);
         }
+        const float4 rj = *(const float4 *)(r + J * TILE + c4);
+        item_tile_f32(v, rj, rI, acc, J != I, colp(J), lane);
+        if (more) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          c[j] += __shfl_xor(c[j], 8, 64);
-          c[j] += __shfl_xor(c[j], 16, 64);
-          c[j] += __shfl_xor(c[j], 32, 64);
-        }
-        if (lane < 8) {
-          float4 o;
-          o.x = c[0];
-          o.y = c[1];
-          o.z = c[2];
-          o.w = c[3];
-          *(float4 *)((float *)S.colpart + (rowbase + J) * TILE + c4) = o;
+          for (int m = 0; m < 4; ++m) v[m] = w[m];
         }
       }
-      if (more) {
+    } else {
+      for (int J0 = it.j0; J0 < it.j1; J0 += CH) {
+        const int cn = it.j1 - J0 < CH ? it.j1 - J0 : CH;
+        float4 v[CH][4], rjv[CH];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) v[m] = w[m];
+        for (int u = 0; u < CH; ++u) {
+          if (u < cn) {
+            const float4 *t = t0 + (int64_t)(J0 - it.j0 + u) * (TILE * TILE / 4);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) v[u][m] = ldnt(t + m * 64 + lane);
+            rjv[u] = *(const float4 *)(r + (J0 + u) * TILE + c4);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          if (u >= cn) break;
+          item_tile_f32(v[u], rjv[u], rI, acc, J0 + u != I, colp(J0 + u), lane);
+        }
       }
     }
 #pragma unroll
@@ -1395,14 +1425,14 @@ __device__ __forceinline__ void items_f32(const Seg *__restrict__ segs, int nseg
   }
 }
 
-// Work items only, one per wavefront.
+// Work items only, one per wavefront (CH: tiles loaded together, see items_f32).
+template <int CH>
 __global__ __launch_bounds__(256) void k_gemv_f32(const Seg *__restrict__ segs, int nseg, int total,
-                                                  const int *__restrict__ done, const double *__restrict__ gin,
-                                                  PcgCheck ck) {
+                                                  const int *__restrict__ done, PcgCheck ck) {
   __shared__ double red[256 / WAVE];
   if (done && *done) return;
   if (carried_check<256>(ck, red)) return;
-  items_f32(segs, nseg, total, blockIdx.x * 4 + (threadIdx.x >> 6), gridDim.x * 4, gin);
+  items_f32<CH>(segs, nseg, total, blockIdx.x * 4 + (threadIdx.x >> 6), gridDim.x * 4);
 }
 
 // Workgroups [0, nwhole) solve whole systems (wsegs: begin offsets in systems),
@@ -1422,8 +1452,8 @@ __global__ __launch_bounds__(NW * WAVE) void k_gemv_whole_f32(const Seg *__restr
     whole_f32<NW>(sg.sys[sg.whole[blockIdx.x - sg.begin]], ys_whole, gin);
     return;
   }
-  items_f32(segs, nseg, total, (blockIdx.x - nwhole) * NW + (threadIdx.x >> 6),
-            (gridDim.x - nwhole) * NW, gin);
+  items_f32<1>(segs, nseg, total, (blockIdx.x - nwhole) * NW + (threadIdx.x >> 6),
+            (gridDim.x - nwhole) * NW);
 }
 
 // FP16 tiles (the inverse divided by a power-of-two scale per system, so every
@@ -1576,8 +1606,47 @@ __device__ __forceinline__ void whole_f16(const SysDev &S, float *ys, const doub
 }
 
 
+// One tile (I, J) of a work item, FP16 storage: as item_tile_f32, the tile
+// scaled by the system's power of two.
+__device__ __forceinline__ void item_tile_f16(const nt_h8 (&v)[2], const float4 &ra, const float4 &rb,
+                                              const float (&rI)[2], float (&acc)[2], bool offdiag, float scale,
+                                              float *__restrict__ colp, int lane) {
+  const float rj[8] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w};
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[m] = fmaf((float)v[m][k], rj[k], acc[m]);
+  if (offdiag) {
+    float c[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) c[k] = fmaf((float)v[1][k], rI[1], (float)v[0][k] * rI[0]);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      c[k] += __shfl_xor(c[k], 4, 64);
+      c[k] += __shfl_xor(c[k], 8, 64);
+      c[k] += __shfl_xor(c[k], 16, 64);
+      c[k] += __shfl_xor(c[k], 32, 64);
+    }
+    if (lane < 4) {
+      float4 o0, o1;
+      o0.x = c[0] * scale;
+      o0.y = c[1] * scale;
+      o0.z = c[2] * scale;
+      o0.w = c[3] * scale;
+      o1.x = c[4] * scale;
+      o1.y = c[5] * scale;
+      o1.z = c[6] * scale;
+      o1.w = c[7] * scale;
+      *(float4 *)colp = o0;
+      *(float4 *)(colp + 4) = o1;
+    }
+  }
+}
+
+// Work items of FP16 tiles, as for FP32 (CH = 1: streamed, else in chunks).
+template <int CH>
 __device__ __forceinline__ void items_f16(const Seg *__restrict__ segs, int nseg, int total, int g0,
-                                          int gstride, const double *__restrict__ gin) {
+                                          int gstride) {
   const int lane = threadIdx.x & 63;
   const int grp = lane >> 2, c8 = (lane & 3) * 8;
   for (int g = g0; g < total; g += gstride) {
@@ -1586,71 +1655,56 @@ __device__ __forceinline__ void items_f16(const Seg *__restrict__ segs, int nseg
     const GItem it = sg.items[g - sg.begin];
     const SysDev S = sg.sys[it.sys];
     const float *__restrict__ r = (const float *)S.rp;
-    const bool gr = gin && S.gidx;   // right-hand side gathered through the packed indices
     const int I = it.I;
     const int64_t rowbase = (int64_t)I * (I + 1) / 2;
-    const nt_h8 *__restrict__ t = (const nt_h8 *)((const _Float16 *)S.tiles + (rowbase + it.j0) * (TILE * TILE));
-    nt_h8 v[2], w[2];
-#pragma unroll
-    for (int m = 0; m < 2; ++m) v[m] = ldnt_global(t + m * 64 + lane);
+    const nt_h8 *__restrict__ t0 = (const nt_h8 *)((const _Float16 *)S.tiles + (rowbase + it.j0) * (TILE * TILE));
     float rI[2], acc[2];
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
-      rI[m] = gr ? rhs_at<float>(S, gin, I * TILE + 16 * m + grp) : r[I * TILE + 16 * m + grp];
+      rI[m] = r[I * TILE + 16 * m + grp];
       acc[m] = 0.0f;
     }
-    for (int J = it.j0; J < it.j1; ++J) {
-      const bool more = J + 1 < it.j1;
-      t += TILE * TILE / 8;
-      if (more) {
+    auto colp = [&](int J) { return (float *)S.colpart + (rowbase + J) * TILE + c8; };
+    if constexpr (CH == 1) {
+      nt_h8 v[2], w[2];
 #pragma unroll
-        for (int m = 0; m < 2; ++m) w[m] = ldnt_global(t + m * 64 + lane);
-      }
-      float4 ra, rb;
-      if (gr) {
-        const int k = J * TILE + c8;
-        ra = make_float4(rhs_at<float>(S, gin, k), rhs_at<float>(S, gin, k + 1), rhs_at<float>(S, gin, k + 2),
-                         rhs_at<float>(S, gin, k + 3));
-        rb = make_float4(rhs_at<float>(S, gin, k + 4), rhs_at<float>(S, gin, k + 5), rhs_at<float>(S, gin, k + 6),
-                         rhs_at<float>(S, gin, k + 7));
-      } else {
-        ra = *(const float4 *)(r + J * TILE + c8);
-        rb = *(const float4 *)(r + J * TILE + c8 + 4);
-      }
-      const float rj[8] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w};
+      for (int m = 0; m < 2; ++m) v[m] = ldnt_global(t0 + m * 64 + lane);
+      const nt_h8 *t = t0;
+      for (int J = it.j0; J < it.j1; ++J) {
+        const bool more = J + 1 < it.j1;
+        t += TILE * TILE / 8;
+        if (more) {
 #pragma unroll
-      for (int m = 0; m < 2; ++m)
-#pragma unroll
-        for (int k = 0; k < 8; ++k) acc[m] += (float)v[m][k] * rj[k];
-      if (J != I) {
-        float c[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) c[k] = (float)v[0][k] * rI[0] + (float)v[1][k] * rI[1];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          c[k] += __shfl_xor(c[k], 4, 64);
-          c[k] += __shfl_xor(c[k], 8, 64);
-          c[k] += __shfl_xor(c[k], 16, 64);
-          c[k] += __shfl_xor(c[k], 32, 64);
+          for (int m = 0; m < 2; ++m) w[m] = ldnt_global(t + m * 64 + lane);
         }
-        if (lane < 4) {
-          float4 o0, o1;
-          o0.x = c[0] * S.scale;
-          o0.y = c[1] * S.scale;
-          o0.z = c[2] * S.scale;
-          o0.w = c[3] * S.scale;
-          o1.x = c[4] * S.scale;
-          o1.y = c[5] * S.scale;
-          o1.z = c[6] * S.scale;
-          o1.w = c[7] * S.scale;
-          float *cp = (float *)S.colpart + (rowbase + J) * TILE + c8;
-          *(float4 *)cp = o0;
-          *(float4 *)(cp + 4) = o1;
+        const float4 ra = *(const float4 *)(r + J * TILE + c8);
+        const float4 rb = *(const float4 *)(r + J * TILE + c8 + 4);
+        item_tile_f16(v, ra, rb, rI, acc, J != I, S.scale, colp(J), lane);
+        if (more) {
+#pragma unroll
+          for (int m = 0; m < 2; ++m) v[m] = w[m];
         }
       }
-      if (more) {
+    } else {
+      for (int J0 = it.j0; J0 < it.j1; J0 += CH) {
+        const int cn = it.j1 - J0 < CH ? it.j1 - J0 : CH;
+        nt_h8 v[CH][2];
+        float4 ra[CH], rb[CH];
 #pragma unroll
-        for (int m = 0; m < 2; ++m) v[m] = w[m];
+        for (int u = 0; u < CH; ++u) {
+          if (u < cn) {
+            const nt_h8 *t = t0 + (int64_t)(J0 - it.j0 + u) * (TILE * TILE / 8);
+#pragma unroll
+            for (int m = 0; m < 2; ++m) v[u][m] = ldnt_global(t + m * 64 + lane);
+            ra[u] = *(const float4 *)(r + (J0 + u) * TILE + c8);
+            rb[u] = *(const float4 *)(r + (J0 + u) * TILE + c8 + 4);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          if (u >= cn) break;
+          item_tile_f16(v[u], ra[u], rb[u], rI, acc, J0 + u != I, S.scale, colp(J0 + u), lane);
+        }
       }
     }
 #pragma unroll
@@ -1668,14 +1722,14 @@ __device__ __forceinline__ void items_f16(const Seg *__restrict__ segs, int nseg
   }
 }
 
-// Work items only, one per wavefront.
+// Work items only, one per wavefront (CH: tiles loaded together, see items_f32).
+template <int CH>
 __global__ __launch_bounds__(256) void k_gemv_f16(const Seg *__restrict__ segs, int nseg, int total,
-                                                  const int *__restrict__ done, const double *__restrict__ gin,
-                                                  PcgCheck ck) {
+                                                  const int *__restrict__ done, PcgCheck ck) {
   __shared__ double red[256 / WAVE];
   if (done && *done) return;
   if (carried_check<256>(ck, red)) return;
-  items_f16(segs, nseg, total, blockIdx.x * 4 + (threadIdx.x >> 6), gridDim.x * 4, gin);
+  items_f16<CH>(segs, nseg, total, blockIdx.x * 4 + (threadIdx.x >> 6), gridDim.x * 4);
 }
 
 // Workgroups [0, nwhole) solve whole systems (wsegs: begin offsets in systems),
@@ -1695,8 +1749,8 @@ __global__ __launch_bounds__(NW * WAVE) void k_gemv_whole_f16(const Seg *__restr
     whole_f16<NW>(sg.sys[sg.whole[blockIdx.x - sg.begin]], ys_whole, gin);
     return;
   }
-  items_f16(segs, nseg, total, (blockIdx.x - nwhole) * NW + (threadIdx.x >> 6),
-            (gridDim.x - nwhole) * NW, gin);
+  items_f16<1>(segs, nseg, total, (blockIdx.x - nwhole) * NW + (threadIdx.x >> 6),
+            (gridDim.x - nwhole) * NW);
 }
 
 // z_s[I*TILE + c] = sum of the row partials of tile row I + sum over I' > I of
