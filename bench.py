@@ -319,7 +319,8 @@ def run_serving_workload(torch, coarse, mg, tol, rates=(50.0, 2000.0), count=409
                            plan_workers=plan_workers)
         rec, wall = srv.run(reqs, progress=lambda m, r=rate: _log(f"serving {r:g} req/s: {m}"))
         summ = {k: v for k, v in serve.summarize(rec, wall).items() if k in keep}
-        summ.update(evictions=srv.evictions, estimate_ratio_max=round(srv.estimate_ratio_max, 3),
+        summ.update(evictions=srv.evictions, resolved=srv.resolved,
+                    estimate_ratio_max=round(srv.estimate_ratio_max, 3),
                     setup_per_miss_s={k: _dist(v) for k, v in srv.setup_times.items()})
         srv.close()
         res = {"batched_" + precision: summ}

@@ -124,6 +124,9 @@ class Server:
         self.precision = precision
         self.step_iters = int(step_iters)
         self.tol = tol
+        # results of the lock step whose true residual missed 10 tol and were
+        # solved again alone on their context (see _checked)
+        self.resolved = 0
         self.stream = torch.cuda.Stream()
         self.setup_stream = torch.cuda.Stream()
         self.batch = coarse.Batch(stream=self.stream, use_graph=use_graph)
@@ -372,6 +375,7 @@ class Server:
                     self.last_iters[key] = max(st["iters"] for st in sts)
                 for tag, st in finished:
                     rq, u, b, _ = live.pop(tag)
+                    st = self._checked(rq, u, b, st)
                     self.busy.discard(rq.key)
                     self.last_iters[rq.key] = st["iters"]
                     records.append(Record(rid=rq.rid, key=rq.key, t_arrive=rq.t_arrive, t_done=now(),
@@ -385,6 +389,24 @@ class Server:
                     time.sleep(0.0005)
         self.stream.synchronize()
         return records, now()
+
+    def _checked(self, rq, u, b, st):
+        """A converged lock-step result whose true residual ||b - A u|| / ||b||
+        (recomputed by the library at the end of every solve) misses 10 tol is
+        solved again alone on its context, and that result is kept. This has been
+        seen on rare cache hits of large meshes whose reduced branch runs on a
+        second stream (1 request in 1024 at 2000 req/s), with the recurrence
+        residual at the tolerance; its cause is not found, so the server does not
+        return such a result."""
+        if st["status"] != 0 or st["relres_true"] <= 10.0 * self.tol:
+            return st
+        import torch
+        S = self.cache[rq.key]
+        with torch.cuda.stream(self.stream):
+            _, st2 = S.solve(b, self.tol, out=u)
+        self.stream.synchronize()
+        self.resolved += 1
+        return st2
 
     def close(self):
         self.pool.shutdown(wait=True)
